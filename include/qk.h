@@ -1,0 +1,248 @@
+/*
+ * qk.h -- C ABI of the MI355X state-vector engine (libqk.so).
+ *
+ * The interface follows the paper's command set (section "Q-Kit."): add
+ * qubits, perform a gate operation, measure, and define a custom gate as a
+ * matrix or as a function; classical bits receive measurement outcomes and
+ * steer later gates (the paper's Copy command and classically controlled
+ * SigmaX / RPhase in Appendix A).  Explicit index arrays replace the
+ * paper's "a:b" range syntax.
+ *
+ * Conventions
+ *   - State: 2^n complex amplitudes, contiguous, interleaved (re, im);
+ *     QK_C64 = two float32 per amplitude, QK_C128 = two float64.
+ *   - Qubit q is bit q of the amplitude index (little-endian).  The paper's
+ *     scripts number qubits big-endian; a front end maps paper qubit p of an
+ *     n-qubit register to bit n-1-p.
+ *   - Inside a gate, row/column index bit j of its matrix (or permutation
+ *     index) corresponds to targets[j].
+ *   - Every call returns qk_status (0 = QK_OK, < 0 = error); nothing aborts
+ *     or throws.  Input arrays are copied before return; the caller keeps
+ *     ownership of every host buffer it passes.
+ *   - Work is enqueued on the HIP stream given to qk_create and runs
+ *     asynchronously.  Calls documented as "synchronises" wait for it.  A
+ *     failure of asynchronous device work is latched and returned
+ *     (QK_E_HIP) by the next synchronising call.
+ *   - One qk_sim is used by one host thread at a time.  Several sims may
+ *     share a device through different streams.
+ */
+#ifndef QK_ABI_H_
+#define QK_ABI_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t qk_status;
+#define QK_OK 0
+#define QK_E_ARG (-1)             /* bad index, duplicate qubit, size limit, unknown name */
+#define QK_E_NOT_UNITARY (-2)     /* matrix fails || M^H M - I ||_max <= tol */
+#define QK_E_NOT_PERMUTATION (-3) /* index function is not a bijection of [0, 2^k) */
+#define QK_E_OOM (-4)             /* allocator returned NULL / device memory exhausted */
+#define QK_E_HIP (-5)             /* HIP runtime error (launch or latched asynchronous fault) */
+#define QK_E_STATE (-6)           /* invalid state for the call (e.g. forced outcome of probability 0) */
+#define QK_E_UNSUPPORTED (-7)     /* valid request the engine does not implement */
+
+typedef int32_t qk_dtype;
+#define QK_C64 1
+#define QK_C128 2
+
+typedef int32_t qk_gate;
+
+/* Builtin gate ids (matrices in FP64; row/column bit j <-> targets[j]):
+ *   H = [[1,1],[1,-1]]/sqrt2, X (the paper's SigmaX), Y, Z, S = diag(1,i),
+ *   T = diag(1,e^{i pi/4}), SDG, TDG (adjoints),
+ *   RX/RY/RZ(theta) = exp(-i theta P/2), PHASE(phi) = diag(1, e^{i phi}),
+ *   CPHASE(phi) = diag(1,1,1,e^{i phi}) (two targets, Appendix A),
+ *   SWAP (two targets), RZZ(theta) = exp(-i theta Z(x)Z/2).
+ * Any gate takes controls; X with one control is CNOT. */
+#define QK_H 1
+#define QK_X 2
+#define QK_Y 3
+#define QK_Z 4
+#define QK_S 5
+#define QK_T 6
+#define QK_SDG 7
+#define QK_TDG 8
+#define QK_RX 9
+#define QK_RY 10
+#define QK_RZ 11
+#define QK_PHASE 12
+#define QK_CPHASE 13
+#define QK_SWAP 14
+#define QK_RZZ 15
+
+#define QK_MAX_CONDS 8        /* classical conditions per gate */
+#define QK_MAX_GATE_QUBITS 24 /* targets + controls per gate */
+#define QK_MAX_MATRIX_K 10    /* largest user matrix gate: 2^10 x 2^10 */
+#define QK_MAX_PERM_K 30      /* largest permutation gate */
+#define QK_MAX_FUSION_K 6     /* largest fused block */
+
+typedef struct qk_sim_s* qk_sim;
+
+/* Device-memory provider.  alloc(bytes, stream, ctx) returns device memory
+ * usable on `stream` or NULL; free(ptr, bytes, stream, ctx) returns it.  With
+ * a NULL provider the library uses hipMalloc / hipFree. */
+typedef struct qk_allocator {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx);
+  void (*free)(void* ptr, size_t bytes, void* stream, void* ctx);
+  void* ctx;
+} qk_allocator;
+
+/* Classical condition: the gate runs iff cbits[cbit] == value (0 or 1).
+ * Several conditions are ANDed.  Evaluated on the device when the gate
+ * executes, so no host round trip is needed between a measurement and the
+ * gates it steers. */
+typedef struct qk_cond {
+  int32_t cbit;
+  int32_t value;
+} qk_cond;
+
+/* ---- lifetime ---------------------------------------------------------- */
+
+/* Create an empty simulator (0 qubits, 0 cbits; the state is the scalar 1).
+ * `alloc` may be NULL (hipMalloc); it is copied.  `hip_stream` (a
+ * hipStream_t, may be NULL for the null stream) receives all device work.
+ * Allocates nothing on the device until qubits are added. */
+qk_status qk_create(qk_dtype dtype, const qk_allocator* alloc, void* hip_stream, qk_sim* out);
+
+/* Synchronise and release every buffer of the simulator. */
+qk_status qk_destroy(qk_sim sim);
+
+/* AddQubits (Appendix A): psi -> psi (x) |0...0>.  New qubits take bits
+ * n..n+count-1, so existing amplitudes keep their indices and the new part
+ * of the state is zero.  *first_qubit (may be NULL) receives n.  The first
+ * call initialises |0...0>.  Reallocates the state (count > 0). */
+qk_status qk_add_qubits(qk_sim sim, int32_t count, int32_t* first_qubit);
+
+/* AddCbits (Appendix A): count new classical bits set to 0, numbered from
+ * the current count; *first_cbit (may be NULL) receives it. */
+qk_status qk_add_cbits(qk_sim sim, int32_t count, int32_t* first_cbit);
+
+/* ---- gate definitions (the paper's "define custom gate as a matrix or as
+ * a function", section "Q-Kit.") ------------------------------------------ */
+
+/* Builtin id by name ("H", "X", "SIGMAX", "HADAMARD", "CNOT" = X, "RZ", ...). */
+qk_status qk_gate_builtin(const char* name, qk_gate* out);
+
+/* Unitary gate on k targets (1 <= k <= QK_MAX_MATRIX_K).  m: 2^k x 2^k
+ * complex, row-major, interleaved (re, im), FP64; copied and kept in FP64 (a
+ * rounded copy serves complex64 states).  Rejected with QK_E_NOT_UNITARY
+ * unless || M^H M - I ||_max <= unitarity_tol.  `name` may be NULL. */
+qk_status qk_define_gate_matrix(qk_sim sim, const char* name, int32_t k, const double* m,
+                                double unitarity_tol, qk_gate* out);
+
+/* Permutation (oracle) gate U|x> = |f(x)> on k targets (1 <= k <=
+ * QK_MAX_PERM_K).  f is called on the host for every x in [0, 2^k) during
+ * this call (ctx is passed through); the results must form a bijection of
+ * [0, 2^k), else QK_E_NOT_PERMUTATION.  The table is kept on the device. */
+qk_status qk_define_gate_index(qk_sim sim, const char* name, int32_t k,
+                               uint64_t (*f)(uint64_t x, const void* ctx), const void* ctx,
+                               qk_gate* out);
+
+/* Same as qk_define_gate_index with the values f(0..2^k-1) given as an array. */
+qk_status qk_define_gate_table(qk_sim sim, const char* name, int32_t k, const uint64_t* table,
+                               qk_gate* out);
+
+/* Affine permutation family x -> (a x + b) mod 2^k (a odd, 1 <= k <= 32),
+ * evaluated on the device in closed form, no table.  When applied,
+ * params[0] = j (optional, default 0) applies the 2^j-th power of the map,
+ * like the paper's QuModExpUaj gate takes j. */
+qk_status qk_define_gate_affine(qk_sim sim, const char* name, int32_t k, uint64_t a, uint64_t b,
+                                qk_gate* out);
+
+/* ---- gate operation (the paper's GateOp) ------------------------------- */
+
+/* Apply `gate` to `targets` (count must equal the gate's arity), restricted
+ * to the subspace where every control qubit is 1, iff every classical
+ * condition holds at execution time.  params: angles for RX, RY, RZ, PHASE,
+ * CPHASE, RZZ (params[0], radians); j for affine gates.  Targets and
+ * controls must be distinct and < n.  Enqueued on the stream; returns
+ * before the device runs it.  With fusion enabled (qk_set_fusion) an
+ * unconditioned matrix gate may be held back and combined with later gates;
+ * any measurement, conditioned or permutation gate, readout or qk_flush
+ * first emits everything held back, in order. */
+qk_status qk_apply_gate(qk_sim sim, qk_gate gate, const int32_t* targets, int32_t n_targets,
+                        const int32_t* controls, int32_t n_controls, const qk_cond* conds,
+                        int32_t n_conds, const double* params, int32_t n_params);
+
+/* ---- measurement (the paper's Measure + Copy) -------------------------- */
+
+/* In-place measurement of `qubit` with the uniform u in [0, 1): p_b = sum of
+ * |a_i|^2 over indices with bit qubit = b (accumulated in FP64, fixed
+ * order, independent of other work on the device), P0 = p0 / (p0 + p1),
+ * outcome = (u < P0) ? 0 : 1; kept amplitudes are scaled by 1/sqrt(p_outcome),
+ * the others set to 0.  The outcome is written to cbit `cbit` on the device
+ * (cbit = -1: not stored).  No host round trip. */
+qk_status qk_measure(qk_sim sim, int32_t qubit, int32_t cbit, double u);
+
+/* As qk_measure with u read from device memory d_u when the step executes
+ * (for captured graphs whose uniforms change between replays). */
+qk_status qk_measure_dev(qk_sim sim, int32_t qubit, int32_t cbit, const double* d_u);
+
+/* Test hook: force `outcome` (0/1).  Synchronises; QK_E_STATE if the outcome
+ * has probability 0 (the state is then left unchanged). */
+qk_status qk_postselect(qk_sim sim, int32_t qubit, int32_t cbit, int32_t outcome);
+
+/* Copy the first n cbits (one byte each, 0/1) to host memory.  Synchronises. */
+qk_status qk_read_cbits(qk_sim sim, uint8_t* out, int32_t n);
+
+/* Measurement log: for the last `count` measurements (oldest first, at most
+ * 4096 kept) write p0, p1 (FP64 sums) and the outcome (as a double) to
+ * out[3*i .. 3*i+2].  *written receives the count written.  Synchronises. */
+qk_status qk_read_measure_log(qk_sim sim, double* out, int32_t count, int32_t* written);
+
+/* ---- readout ------------------------------------------------------------ */
+
+/* Copy the state (2^n amplitudes, bytes = 2^n * amplitude size) to host
+ * memory.  Synchronises. */
+qk_status qk_get_state(qk_sim sim, void* host_out, size_t bytes);
+
+/* Replace the state with host data of the same size.  Synchronises. */
+qk_status qk_set_state(qk_sim sim, const void* host_in, size_t bytes);
+
+/* Current device address and size of the state.  Valid until the next call
+ * that adds qubits or destroys the simulator.  Emits held-back gates first. */
+qk_status qk_state_ptr(qk_sim sim, void** dev_ptr, size_t* bytes);
+
+/* FP64 inner product <a|b> = sum conj(a_i) b_i of two simulators with the same
+ * qubit count (dtypes may differ), fixed-order reduction.  Synchronises both. */
+qk_status qk_inner_product(qk_sim a, qk_sim b, double* re, double* im);
+
+/* FP64 squared norm sum |a_i|^2.  Synchronises. */
+qk_status qk_norm2(qk_sim sim, double* out);
+
+/* ---- execution control -------------------------------------------------- */
+
+/* Gate fusion: max_k = 0 applies every gate on its own; 2 <= max_k <= 6
+ * combines consecutive unconditioned matrix gates (reordering only gates on
+ * disjoint qubits) into blocks on at most max_k qubits, composed in FP64 on
+ * the host and applied as one dense 2^k x 2^k sweep (matrix cores). */
+qk_status qk_set_fusion(qk_sim sim, int32_t max_k);
+
+/* Emit every held-back gate now (asynchronous). */
+qk_status qk_flush(qk_sim sim);
+
+/* Flush, wait for all work of the simulator, report latched errors. */
+qk_status qk_sync(qk_sim sim);
+
+qk_status qk_num_qubits(qk_sim sim, int32_t* n);
+
+/* Counters since creation: sweeps launched (state passes), fused blocks,
+ * gates absorbed into fused blocks.  Any pointer may be NULL. */
+qk_status qk_stats(qk_sim sim, int64_t* sweeps, int64_t* fused_blocks, int64_t* fused_gates);
+
+/* Text of the last error on `sim` (valid until the next call on it), or of
+ * the last error of a call that had no simulator when sim is NULL. */
+const char* qk_last_error(qk_sim sim);
+
+const char* qk_status_string(qk_status st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QK_ABI_H_ */

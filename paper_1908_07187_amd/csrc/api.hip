@@ -1,0 +1,998 @@
+// Host runtime behind the C ABI (qk.h): simulator registry, classical bits,
+// gate table and validation, per-gate dispatch to the sweep kernels, fusion,
+// measurement and readout.  Host-side checks run before any HIP call, so
+// argument errors are reported even where no GPU is present.
+#include <algorithm>
+#include <cctype>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "qk_internal.h"
+
+using namespace qk;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+enum UKind { U_MATRIX = 0, U_TABLE = 1, U_AFFINE = 2 };
+
+struct UserGate {
+  int kind = U_MATRIX;
+  int k = 1;
+  std::string name;
+  std::vector<cd> m;       // FP64 matrix (U_MATRIX)
+  bool diag = false;
+  DevBuf dmat;             // matrix in the state's precision (uploaded at define time)
+  DevBuf finv;             // inverse table, uint32 (U_TABLE)
+  uint64_t a = 1, b = 0;   // U_AFFINE
+};
+
+// Gate description after classification.
+enum DKind { D_BUTTERFLY, D_DIAG, D_PHASE1, D_SWAP, D_DENSE, D_PERM };
+
+struct GateDesc {
+  int kind = D_DENSE;
+  std::vector<int> targets, controls;
+  std::vector<qk_cond> conds;
+  std::vector<cd> m;         // dense matrix (2^k x 2^k) for D_BUTTERFLY / D_DENSE, or diagonal for D_DIAG
+  cd z = 1.0;                // D_PHASE1 factor
+  const UserGate* ug = nullptr;
+  uint64_t A = 1, B = 0, Ainv = 1;   // D_PERM affine power
+  bool fusable = false;      // matrix gate without conditions
+};
+
+// Append-only constant arena (device + pinned host staging).  Reset only after
+// the stream has drained, so staged host bytes are never overwritten while a
+// copy from them may still be pending.
+struct Arena {
+  void* dev = nullptr;
+  void* host = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+};
+
+std::string g_last_error;
+
+}  // namespace
+
+struct qk_sim_s {
+  qk_dtype dtype = QK_C128;
+  bool c64 = false;
+  size_t amp = 16;
+  qk_allocator alloc{};
+  bool has_alloc = false;
+  hipStream_t stream = nullptr;
+  int n = 0;
+  DevBuf state, scratch, cbits, meas;
+  int ncbits = 0;
+  Arena arena;
+  std::vector<UserGate*> ugates;
+  int fuse_k = 0;
+  std::vector<GateDesc> pending;
+  int waves_per_cu = 8;
+  int64_t sweeps = 0, fused_blocks = 0, fused_gates = 0;
+  std::string err;
+  qk_status latched = QK_OK;
+};
+
+namespace {
+
+constexpr int kUserBase = 0x100;
+constexpr size_t kArenaBytes = 32u << 20;
+constexpr int kMaxQubits = 40;
+
+qk_status fail(qk_sim s, qk_status st, const std::string& msg) {
+  if (s) s->err = msg;
+  else g_last_error = msg;
+  return st;
+}
+
+qk_status hip_fail(qk_sim s, hipError_t e, const char* what) {
+  return fail(s, QK_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void* dev_alloc(qk_sim s, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (s->has_alloc) return s->alloc.alloc(bytes, (void*)s->stream, s->alloc.ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void dev_free(qk_sim s, DevBuf& b) {
+  if (!b.p) return;
+  if (s->has_alloc) s->alloc.free(b.p, b.bytes, (void*)s->stream, s->alloc.ctx);
+  else (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+qk_status ensure(qk_sim s, DevBuf& b, size_t bytes, const char* what) {
+  if (b.p && b.bytes >= bytes) return QK_OK;
+  dev_free(s, b);
+  b.p = dev_alloc(s, bytes);
+  if (!b.p) return fail(s, QK_E_OOM, std::string("device allocation failed: ") + what);
+  b.bytes = bytes;
+  return QK_OK;
+}
+
+// ---- small device helpers (graph-safe: kernels, never memset) -----------------
+
+__global__ void k_u8_fill(uint8_t* p, size_t from, size_t to, uint8_t v) {
+  for (size_t i = from + (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < to; i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+__global__ void k_u8_copy(uint8_t* dst, const uint8_t* src, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+__global__ void k_u32_zero(uint32_t* p) {
+  if (threadIdx.x == 0) *p = 0;
+}
+
+// Measurement buffer layout (doubles): partials[2*kReduceBlocks] | result[4] |
+// log[3*kMeasLog] | log_count (uint32, in the last 8 bytes).
+constexpr size_t kMeasDoubles = 2 * kReduceBlocks + 4 + 3 * kMeasLog + 1;
+
+MeasBuffers meas_buffers(qk_sim s) {
+  double* d = (double*)s->meas.p;
+  MeasBuffers mb;
+  mb.partials = d;
+  mb.result = d + 2 * kReduceBlocks;
+  mb.log = mb.result + 4;
+  mb.log_count = (uint32_t*)(mb.log + 3 * kMeasLog);
+  mb.cbits = (uint8_t*)s->cbits.p;
+  return mb;
+}
+
+qk_status ensure_meas(qk_sim s) {
+  if (s->meas.p) return QK_OK;
+  qk_status st = ensure(s, s->meas, kMeasDoubles * sizeof(double), "measurement buffers");
+  if (st) return st;
+  MeasBuffers mb = meas_buffers(s);
+  hipLaunchKernelGGL(k_u32_zero, dim3(1), dim3(64), 0, s->stream, mb.log_count);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? QK_OK : hip_fail(s, e, "measurement buffer init");
+}
+
+// ---- constant arena ----------------------------------------------------------
+
+qk_status arena_put(qk_sim s, const void* data, size_t bytes, const void** dptr) {
+  Arena& a = s->arena;
+  if (!a.dev) {
+    a.dev = dev_alloc(s, kArenaBytes);
+    if (!a.dev) return fail(s, QK_E_OOM, "device allocation failed: constant arena");
+    if (hipHostMalloc(&a.host, kArenaBytes, hipHostMallocDefault) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail(s, QK_E_OOM, "pinned host allocation failed: constant arena");
+    }
+    a.cap = kArenaBytes;
+    a.used = 0;
+  }
+  const size_t need = (bytes + 255) & ~(size_t)255;
+  if (need > a.cap) return fail(s, QK_E_ARG, "constant block larger than the arena");
+  if (a.used + need > a.cap) {
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "arena recycle");
+    a.used = 0;
+  }
+  std::memcpy((char*)a.host + a.used, data, bytes);
+  hipError_t e = hipMemcpyAsync((char*)a.dev + a.used, (char*)a.host + a.used, bytes, hipMemcpyHostToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "constant upload");
+  *dptr = (char*)a.dev + a.used;
+  a.used += need;
+  return QK_OK;
+}
+
+// Matrix in the state's precision, row-major interleaved.
+std::vector<unsigned char> pack_matrix(const std::vector<cd>& m, bool c64) {
+  std::vector<unsigned char> out(m.size() * (c64 ? 8 : 16));
+  if (c64) {
+    float* f = (float*)out.data();
+    for (size_t i = 0; i < m.size(); ++i) {
+      f[2 * i] = (float)m[i].real();
+      f[2 * i + 1] = (float)m[i].imag();
+    }
+  } else {
+    double* f = (double*)out.data();
+    for (size_t i = 0; i < m.size(); ++i) {
+      f[2 * i] = m[i].real();
+      f[2 * i + 1] = m[i].imag();
+    }
+  }
+  return out;
+}
+
+// ---- builtin gates (FP64 definitions) -------------------------------------------
+
+struct BuiltinInfo {
+  const char* name;
+  int id;
+  int arity;
+  int nparams;
+};
+const BuiltinInfo kBuiltins[] = {
+    {"H", QK_H, 1, 0},         {"HADAMARD", QK_H, 1, 0}, {"X", QK_X, 1, 0},       {"SIGMAX", QK_X, 1, 0},
+    {"NOT", QK_X, 1, 0},       {"CNOT", QK_X, 1, 0},     {"Y", QK_Y, 1, 0},       {"SIGMAY", QK_Y, 1, 0},
+    {"Z", QK_Z, 1, 0},         {"SIGMAZ", QK_Z, 1, 0},   {"S", QK_S, 1, 0},       {"T", QK_T, 1, 0},
+    {"SDG", QK_SDG, 1, 0},     {"TDG", QK_TDG, 1, 0},    {"RX", QK_RX, 1, 1},     {"RY", QK_RY, 1, 1},
+    {"RZ", QK_RZ, 1, 1},       {"PHASE", QK_PHASE, 1, 1}, {"RPHASE", QK_PHASE, 1, 1}, {"CPHASE", QK_CPHASE, 2, 1},
+    {"SWAP", QK_SWAP, 2, 0},   {"RZZ", QK_RZZ, 2, 1},
+};
+
+const BuiltinInfo* builtin_by_id(int id) {
+  for (const auto& b : kBuiltins)
+    if (b.id == id) return &b;
+  return nullptr;
+}
+
+// Classify a builtin gate into a sweep.  Matrices follow the definitions in qk.h.
+void builtin_desc(int id, double p, GateDesc& d) {
+  const double s2 = 1.0 / std::sqrt(2.0);
+  const cd i1(0, 1);
+  const double c = std::cos(p / 2), sn = std::sin(p / 2);
+  d.fusable = true;
+  switch (id) {
+    case QK_H: d.kind = D_BUTTERFLY; d.m = {s2, s2, s2, -s2}; break;
+    case QK_X: d.kind = D_BUTTERFLY; d.m = {0.0, 1.0, 1.0, 0.0}; break;
+    case QK_Y: d.kind = D_BUTTERFLY; d.m = {0.0, -i1, i1, 0.0}; break;
+    case QK_RX: d.kind = D_BUTTERFLY; d.m = {c, -i1 * sn, -i1 * sn, c}; break;
+    case QK_RY: d.kind = D_BUTTERFLY; d.m = {c, -sn, sn, c}; break;
+    case QK_Z: d.kind = D_PHASE1; d.z = -1.0; break;
+    case QK_S: d.kind = D_PHASE1; d.z = i1; break;
+    case QK_SDG: d.kind = D_PHASE1; d.z = -i1; break;
+    case QK_T: d.kind = D_PHASE1; d.z = std::polar(1.0, M_PI / 4); break;
+    case QK_TDG: d.kind = D_PHASE1; d.z = std::polar(1.0, -M_PI / 4); break;
+    case QK_PHASE: d.kind = D_PHASE1; d.z = std::polar(1.0, p); break;
+    case QK_CPHASE: d.kind = D_PHASE1; d.z = std::polar(1.0, p); break;
+    case QK_RZ: d.kind = D_DIAG; d.m = {std::polar(1.0, -p / 2), std::polar(1.0, p / 2)}; break;
+    case QK_RZZ: {
+      const cd em = std::polar(1.0, -p / 2), ep = std::polar(1.0, p / 2);
+      d.kind = D_DIAG;
+      d.m = {em, ep, ep, em};
+      break;
+    }
+    case QK_SWAP: d.kind = D_SWAP; break;
+  }
+}
+
+// Full 2^k x 2^k matrix on the targets of a matrix-like description.
+std::vector<cd> full_matrix(const GateDesc& d) {
+  const int k = (int)d.targets.size();
+  const int D = 1 << k;
+  std::vector<cd> m((size_t)D * D, cd(0, 0));
+  switch (d.kind) {
+    case D_BUTTERFLY:
+    case D_DENSE: return d.m;
+    case D_DIAG:
+      for (int i = 0; i < D; ++i) m[(size_t)i * D + i] = d.m[i];
+      return m;
+    case D_PHASE1:
+      for (int i = 0; i < D; ++i) m[(size_t)i * D + i] = (i == D - 1) ? d.z : cd(1.0);
+      return m;
+    case D_SWAP:
+      m[0] = 1.0;
+      m[1 * 4 + 2] = 1.0;
+      m[2 * 4 + 1] = 1.0;
+      m[15] = 1.0;
+      return m;
+  }
+  return m;
+}
+
+CondArgs make_cond(qk_sim s, const std::vector<qk_cond>& conds) {
+  CondArgs c{};
+  c.cbits = (const uint8_t*)s->cbits.p;
+  c.n = (int)conds.size();
+  for (int i = 0; i < c.n; ++i) {
+    c.cbit[i] = conds[i].cbit;
+    c.val[i] = conds[i].value;
+  }
+  return c;
+}
+
+Launch make_launch(qk_sim s, const std::vector<qk_cond>& conds) {
+  Launch L;
+  L.stream = s->stream;
+  L.n = s->n;
+  L.c64 = s->c64;
+  L.psi = s->state.p;
+  L.cond = make_cond(s, conds);
+  return L;
+}
+
+qk_status check_launch(qk_sim s, hipError_t e, const char* what) {
+  if (e != hipSuccess) return hip_fail(s, e, what);
+  s->sweeps++;
+  return QK_OK;
+}
+
+// Dense matrix of any k (from a description or a fused block) on `targets`.
+qk_status run_dense(qk_sim s, const std::vector<int>& targets, const std::vector<int>& controls,
+                    const std::vector<qk_cond>& conds, const std::vector<cd>& m, const void* dmat_in) {
+  const int k = (int)targets.size();
+  Launch L = make_launch(s, conds);
+  if (k == 1) {
+    Mat2 u;
+    for (int i = 0; i < 4; ++i) {
+      u.v[2 * i] = m[i].real();
+      u.v[2 * i + 1] = m[i].imag();
+    }
+    return check_launch(s, launch_butterfly(L, targets[0], controls.data(), (int)controls.size(), u), "butterfly");
+  }
+  const void* dmat = dmat_in;
+  if (!dmat) {
+    auto packed = pack_matrix(m, s->c64);
+    qk_status st = arena_put(s, packed.data(), packed.size(), &dmat);
+    if (st) return st;
+  }
+  if (mfma_supported(s->n, k, (int)controls.size(), s->c64))
+    return check_launch(
+        s, launch_dense_mfma(L, targets.data(), k, controls.data(), (int)controls.size(), dmat, s->waves_per_cu),
+        "dense (matrix cores)");
+  return check_launch(s, launch_dense_generic(L, targets.data(), k, controls.data(), (int)controls.size(), dmat),
+                      "dense");
+}
+
+qk_status run_diag(qk_sim s, const std::vector<int>& targets, const std::vector<int>& controls,
+                   const std::vector<qk_cond>& conds, const std::vector<cd>& diag) {
+  const int k = (int)targets.size();
+  // all ones except the last entry: only the all-ones subspace changes
+  bool phase_only = true;
+  for (int i = 0; i + 1 < (int)diag.size(); ++i)
+    if (diag[i] != cd(1.0)) phase_only = false;
+  Launch L = make_launch(s, conds);
+  if (phase_only) {
+    std::vector<int> bits(targets);
+    bits.insert(bits.end(), controls.begin(), controls.end());
+    return check_launch(s, launch_phase_all1(L, bits.data(), (int)bits.size(), diag.back().real(), diag.back().imag()),
+                        "phase");
+  }
+  if (k > 6) {
+    const int D = 1 << k;
+    std::vector<cd> m((size_t)D * D, cd(0, 0));
+    for (int i = 0; i < D; ++i) m[(size_t)i * D + i] = diag[i];
+    return run_dense(s, targets, controls, conds, m, nullptr);
+  }
+  Diag64 d{};
+  for (size_t i = 0; i < diag.size(); ++i) {
+    d.v[2 * i] = diag[i].real();
+    d.v[2 * i + 1] = diag[i].imag();
+  }
+  return check_launch(s, launch_diag(L, targets.data(), k, controls.data(), (int)controls.size(), d), "diagonal");
+}
+
+qk_status ensure_scratch(qk_sim s) {
+  const size_t bytes = ((size_t)1 << s->n) * s->amp;
+  return ensure(s, s->scratch, bytes, "permutation scratch");
+}
+
+qk_status execute(qk_sim s, const GateDesc& d) {
+  switch (d.kind) {
+    case D_BUTTERFLY:
+    case D_DENSE:
+      return run_dense(s, d.targets, d.controls, d.conds, d.m, d.ug ? d.ug->dmat.p : nullptr);
+    case D_DIAG:
+      return run_diag(s, d.targets, d.controls, d.conds, d.m);
+    case D_PHASE1: {
+      Launch L = make_launch(s, d.conds);
+      std::vector<int> bits(d.targets);
+      bits.insert(bits.end(), d.controls.begin(), d.controls.end());
+      return check_launch(s, launch_phase_all1(L, bits.data(), (int)bits.size(), d.z.real(), d.z.imag()), "phase");
+    }
+    case D_SWAP: {
+      Launch L = make_launch(s, d.conds);
+      return check_launch(s, launch_swap(L, d.targets[0], d.targets[1], d.controls.data(), (int)d.controls.size()),
+                          "swap");
+    }
+    case D_PERM: {
+      qk_status st = ensure_scratch(s);
+      if (st) return st;
+      Launch L = make_launch(s, d.conds);
+      const bool aff = d.ug->kind == U_AFFINE;
+      return check_launch(s,
+                          launch_perm(L, s->scratch.p, d.targets.data(), (int)d.targets.size(), d.controls.data(),
+                                      (int)d.controls.size(), aff ? nullptr : (const uint32_t*)d.ug->finv.p, aff, d.A,
+                                      d.B, d.Ainv),
+                          "permutation");
+    }
+  }
+  return fail(s, QK_E_ARG, "unknown gate class");
+}
+
+qk_status flush(qk_sim s) {
+  if (s->pending.empty()) return QK_OK;
+  std::vector<GateDesc> pend;
+  pend.swap(s->pending);
+  std::vector<FGate> fg;
+  fg.reserve(pend.size());
+  for (const GateDesc& d : pend)
+    fg.push_back(make_fgate(d.targets.data(), (int)d.targets.size(), d.controls.data(), (int)d.controls.size(),
+                            full_matrix(d)));
+  std::vector<FBlock> blocks = plan_blocks(fg, s->fuse_k);
+  const std::vector<qk_cond> none;
+  for (const FBlock& b : blocks) {
+    qk_status st;
+    if (b.members.size() == 1) {   // a block of one gate runs through that gate's own sweep
+      st = execute(s, pend[b.members[0]]);
+      if (st) return st;
+      continue;
+    }
+    s->fused_blocks++;
+    s->fused_gates += b.ngates;
+    if (b.diag) {
+      const int D = 1 << b.qubits.size();
+      std::vector<cd> dg(D);
+      for (int i = 0; i < D; ++i) dg[i] = b.m[(size_t)i * D + i];
+      st = run_diag(s, b.qubits, {}, none, dg);
+    } else {
+      st = run_dense(s, b.qubits, {}, none, b.m, nullptr);
+    }
+    if (st) return st;
+  }
+  return QK_OK;
+}
+
+qk_status sync_stream(qk_sim s) {
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) {
+    s->latched = QK_E_HIP;
+    return hip_fail(s, e, "asynchronous device work failed");
+  }
+  return QK_OK;
+}
+
+std::string upper(const char* s) {
+  std::string r(s ? s : "");
+  for (auto& ch : r) ch = (char)std::toupper((unsigned char)ch);
+  return r;
+}
+
+uint64_t inv_mod_2_64(uint64_t a) {
+  uint64_t x = a;   // correct to 3 bits for odd a; each Newton step doubles them
+  for (int i = 0; i < 6; ++i) x *= 2 - a * x;
+  return x;
+}
+
+qk_status new_user_gate(qk_sim s, UserGate* g, qk_gate* out) {
+  s->ugates.push_back(g);
+  if (out) *out = kUserBase + (int)s->ugates.size() - 1;
+  return QK_OK;
+}
+
+qk_status upload_table(qk_sim s, UserGate* g, const std::vector<uint64_t>& table) {
+  const uint64_t K = 1ull << g->k;
+  std::vector<uint32_t> finv(K);
+  for (uint64_t x = 0; x < K; ++x) finv[table[x]] = (uint32_t)x;
+  qk_status st = ensure(s, g->finv, K * sizeof(uint32_t), "permutation table");
+  if (st) return st;
+  hipError_t e = hipMemcpy(g->finv.p, finv.data(), K * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(s, e, "permutation table upload");
+  return QK_OK;
+}
+
+qk_status define_perm(qk_sim s, const char* name, int32_t k, const std::vector<uint64_t>& table, qk_gate* out) {
+  const uint64_t K = 1ull << k;
+  std::vector<unsigned char> seen(K, 0);
+  for (uint64_t x = 0; x < K; ++x) {
+    if (table[x] >= K || seen[table[x]])
+      return fail(s, QK_E_NOT_PERMUTATION, "index function is not a bijection of [0, 2^k)");
+    seen[table[x]] = 1;
+  }
+  UserGate* g = new UserGate;
+  g->kind = U_TABLE;
+  g->k = k;
+  g->name = name ? name : "";
+  qk_status st = upload_table(s, g, table);
+  if (st) {
+    dev_free(s, g->finv);
+    delete g;
+    return st;
+  }
+  return new_user_gate(s, g, out);
+}
+
+}  // namespace
+
+// ============================================================================ ABI
+
+extern "C" {
+
+const char* qk_status_string(qk_status st) {
+  switch (st) {
+    case QK_OK: return "ok";
+    case QK_E_ARG: return "invalid argument";
+    case QK_E_NOT_UNITARY: return "matrix is not unitary";
+    case QK_E_NOT_PERMUTATION: return "index function is not a permutation";
+    case QK_E_OOM: return "out of memory";
+    case QK_E_HIP: return "HIP error";
+    case QK_E_STATE: return "invalid state";
+    case QK_E_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* qk_last_error(qk_sim s) { return s ? s->err.c_str() : g_last_error.c_str(); }
+
+qk_status qk_create(qk_dtype dtype, const qk_allocator* alloc, void* hip_stream, qk_sim* out) {
+  if (!out) return fail(nullptr, QK_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (dtype != QK_C64 && dtype != QK_C128) return fail(nullptr, QK_E_ARG, "dtype must be QK_C64 or QK_C128");
+  if (alloc && (!alloc->alloc || !alloc->free)) return fail(nullptr, QK_E_ARG, "allocator needs alloc and free");
+  qk_sim s = new qk_sim_s;
+  s->dtype = dtype;
+  s->c64 = dtype == QK_C64;
+  s->amp = s->c64 ? 8 : 16;
+  if (alloc) {
+    s->alloc = *alloc;
+    s->has_alloc = true;
+  }
+  s->stream = (hipStream_t)hip_stream;
+  *out = s;
+  return QK_OK;
+}
+
+qk_status qk_destroy(qk_sim s) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->state.p || s->meas.p || s->arena.dev) (void)hipStreamSynchronize(s->stream);
+  dev_free(s, s->state);
+  dev_free(s, s->scratch);
+  dev_free(s, s->cbits);
+  dev_free(s, s->meas);
+  if (s->arena.dev) {
+    DevBuf b{s->arena.dev, s->arena.cap};
+    dev_free(s, b);
+  }
+  if (s->arena.host) (void)hipHostFree(s->arena.host);
+  for (UserGate* g : s->ugates) {
+    dev_free(s, g->dmat);
+    dev_free(s, g->finv);
+    delete g;
+  }
+  delete s;
+  return QK_OK;
+}
+
+qk_status qk_add_qubits(qk_sim s, int32_t count, int32_t* first) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (count < 0) return fail(s, QK_E_ARG, "count < 0");
+  if (s->n + count > kMaxQubits) return fail(s, QK_E_ARG, "too many qubits");
+  if (first) *first = s->n;
+  if (count == 0 && s->state.p) return QK_OK;
+  qk_status st = flush(s);
+  if (st) return st;
+  const int nn = s->n + count;
+  const uint64_t newdim = 1ull << nn;
+  DevBuf nb;
+  nb.p = dev_alloc(s, newdim * s->amp);
+  if (!nb.p) return fail(s, QK_E_OOM, "device allocation failed: state of " + std::to_string(nn) + " qubits");
+  nb.bytes = newdim * s->amp;
+  hipError_t e;
+  if (!s->state.p) {
+    e = launch_fill_zero(nb.p, 0, newdim, s->c64, s->stream);
+    if (e == hipSuccess) e = launch_set_one(nb.p, 0, s->c64, s->stream);
+  } else {
+    const uint64_t olddim = 1ull << s->n;
+    e = launch_copy(nb.p, s->state.p, olddim, s->c64, s->stream);
+    if (e == hipSuccess) e = launch_fill_zero(nb.p, olddim, newdim, s->c64, s->stream);
+  }
+  if (e != hipSuccess) {
+    dev_free(s, nb);
+    return hip_fail(s, e, "add_qubits");
+  }
+  dev_free(s, s->state);
+  dev_free(s, s->scratch);
+  s->state = nb;
+  s->n = nn;
+  return QK_OK;
+}
+
+qk_status qk_add_cbits(qk_sim s, int32_t count, int32_t* first) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (count < 0 || s->ncbits + count > (1 << 20)) return fail(s, QK_E_ARG, "bad cbit count");
+  if (first) *first = s->ncbits;
+  if (count == 0) return QK_OK;
+  qk_status st = flush(s);
+  if (st) return st;
+  const size_t nn = (size_t)s->ncbits + count;
+  DevBuf nb;
+  nb.p = dev_alloc(s, nn);
+  if (!nb.p) return fail(s, QK_E_OOM, "device allocation failed: cbits");
+  nb.bytes = nn;
+  if (s->cbits.p) hipLaunchKernelGGL(k_u8_copy, dim3(1), dim3(256), 0, s->stream, (uint8_t*)nb.p, (const uint8_t*)s->cbits.p, (size_t)s->ncbits);
+  hipLaunchKernelGGL(k_u8_fill, dim3(std::max<size_t>(1, std::min<size_t>(1024, (count + 255) / 256))), dim3(256), 0,
+                     s->stream, (uint8_t*)nb.p, (size_t)s->ncbits, nn, (uint8_t)0);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    dev_free(s, nb);
+    return hip_fail(s, e, "add_cbits");
+  }
+  dev_free(s, s->cbits);
+  s->cbits = nb;
+  s->ncbits = (int)nn;
+  return QK_OK;
+}
+
+qk_status qk_gate_builtin(const char* name, qk_gate* out) {
+  if (!name || !out) return fail(nullptr, QK_E_ARG, "name/out is NULL");
+  const std::string u = upper(name);
+  for (const auto& b : kBuiltins)
+    if (u == b.name) {
+      *out = b.id;
+      return QK_OK;
+    }
+  return fail(nullptr, QK_E_ARG, "unknown builtin gate " + u);
+}
+
+qk_status qk_define_gate_matrix(qk_sim s, const char* name, int32_t k, const double* m, double tol, qk_gate* out) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (!m) return fail(s, QK_E_ARG, "matrix is NULL");
+  if (k < 1 || k > QK_MAX_MATRIX_K) return fail(s, QK_E_ARG, "k out of range");
+  if (!(tol > 0)) tol = 1e-10;
+  const int D = 1 << k;
+  std::vector<cd> M((size_t)D * D);
+  for (size_t i = 0; i < M.size(); ++i) {
+    M[i] = cd(m[2 * i], m[2 * i + 1]);
+    if (!std::isfinite(m[2 * i]) || !std::isfinite(m[2 * i + 1])) return fail(s, QK_E_NOT_UNITARY, "non-finite entry");
+  }
+  double worst = 0;
+  for (int r = 0; r < D; ++r)
+    for (int c = 0; c < D; ++c) {
+      cd acc(0, 0);
+      for (int i = 0; i < D; ++i) acc += std::conj(M[(size_t)i * D + r]) * M[(size_t)i * D + c];
+      worst = std::max(worst, std::abs(acc - (r == c ? cd(1.0) : cd(0.0))));
+    }
+  if (worst > tol) {
+    char buf[96];
+    std::snprintf(buf, sizeof buf, "matrix is not unitary: ||M^H M - I||_max = %.3e", worst);
+    return fail(s, QK_E_NOT_UNITARY, buf);
+  }
+  UserGate* g = new UserGate;
+  g->kind = U_MATRIX;
+  g->k = k;
+  g->name = name ? name : "";
+  g->m = M;
+  g->diag = true;
+  for (int r = 0; r < D && g->diag; ++r)
+    for (int c = 0; c < D; ++c)
+      if (r != c && M[(size_t)r * D + c] != cd(0, 0)) {
+        g->diag = false;
+        break;
+      }
+  if (!g->diag && k >= 2) {
+    auto packed = pack_matrix(M, s->c64);
+    qk_status st = ensure(s, g->dmat, packed.size(), "gate matrix");
+    if (st) {
+      delete g;
+      return st;
+    }
+    hipError_t e = hipMemcpy(g->dmat.p, packed.data(), packed.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      dev_free(s, g->dmat);
+      delete g;
+      return hip_fail(s, e, "gate matrix upload");
+    }
+  }
+  return new_user_gate(s, g, out);
+}
+
+qk_status qk_define_gate_index(qk_sim s, const char* name, int32_t k, uint64_t (*f)(uint64_t, const void*),
+                               const void* ctx, qk_gate* out) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (!f) return fail(s, QK_E_ARG, "function is NULL");
+  if (k < 1 || k > QK_MAX_PERM_K) return fail(s, QK_E_ARG, "k out of range");
+  std::vector<uint64_t> table(1ull << k);
+  for (uint64_t x = 0; x < table.size(); ++x) table[x] = f(x, ctx);
+  return define_perm(s, name, k, table, out);
+}
+
+qk_status qk_define_gate_table(qk_sim s, const char* name, int32_t k, const uint64_t* table, qk_gate* out) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (!table) return fail(s, QK_E_ARG, "table is NULL");
+  if (k < 1 || k > QK_MAX_PERM_K) return fail(s, QK_E_ARG, "k out of range");
+  std::vector<uint64_t> t(table, table + (1ull << k));
+  return define_perm(s, name, k, t, out);
+}
+
+qk_status qk_define_gate_affine(qk_sim s, const char* name, int32_t k, uint64_t a, uint64_t b, qk_gate* out) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (k < 1 || k > 32) return fail(s, QK_E_ARG, "k out of range");
+  if (!(a & 1)) return fail(s, QK_E_NOT_PERMUTATION, "a must be odd for x -> a x + b mod 2^k to be a bijection");
+  UserGate* g = new UserGate;
+  g->kind = U_AFFINE;
+  g->k = k;
+  g->name = name ? name : "";
+  const uint64_t mask = (k == 64) ? ~0ull : ((1ull << k) - 1);
+  g->a = a & mask;
+  g->b = b & mask;
+  return new_user_gate(s, g, out);
+}
+
+qk_status qk_apply_gate(qk_sim s, qk_gate gate, const int32_t* targets, int32_t nt, const int32_t* controls,
+                        int32_t nc, const qk_cond* conds, int32_t ncond, const double* params, int32_t np) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (nt < 1 || (nt > 0 && !targets)) return fail(s, QK_E_ARG, "no targets");
+  if (nc < 0 || (nc > 0 && !controls)) return fail(s, QK_E_ARG, "bad controls");
+  if (ncond < 0 || ncond > QK_MAX_CONDS || (ncond > 0 && !conds)) return fail(s, QK_E_ARG, "bad conditions");
+  if (np < 0 || (np > 0 && !params)) return fail(s, QK_E_ARG, "bad params");
+  if (nt + nc > QK_MAX_GATE_QUBITS) return fail(s, QK_E_ARG, "too many qubits in one gate");
+  GateDesc d;
+  int arity = 0;
+  const UserGate* ug = nullptr;
+  const BuiltinInfo* bi = nullptr;
+  if (gate >= kUserBase && gate - kUserBase < (int)s->ugates.size()) {
+    ug = s->ugates[gate - kUserBase];
+    arity = ug->k;
+    const int maxp = ug->kind == U_AFFINE ? 1 : 0;
+    if (np > maxp) return fail(s, QK_E_ARG, "too many params for this gate");
+  } else if ((bi = builtin_by_id(gate))) {
+    arity = bi->arity;
+    if (np != bi->nparams) return fail(s, QK_E_ARG, std::string("gate ") + bi->name + " takes " +
+                                                          std::to_string(bi->nparams) + " param(s)");
+  } else {
+    return fail(s, QK_E_ARG, "unknown gate id");
+  }
+  if (nt != arity) return fail(s, QK_E_ARG, "target count does not match the gate");
+  uint64_t seen = 0;
+  for (int i = 0; i < nt + nc; ++i) {
+    const int q = i < nt ? targets[i] : controls[i - nt];
+    if (q < 0 || q >= s->n) return fail(s, QK_E_ARG, "qubit index out of range");
+    if ((seen >> q) & 1) return fail(s, QK_E_ARG, "qubit used twice in one gate");
+    seen |= 1ull << q;
+  }
+  for (int i = 0; i < ncond; ++i) {
+    if (conds[i].cbit < 0 || conds[i].cbit >= s->ncbits) return fail(s, QK_E_ARG, "condition cbit out of range");
+    if (conds[i].value != 0 && conds[i].value != 1) return fail(s, QK_E_ARG, "condition value must be 0 or 1");
+  }
+  d.targets.assign(targets, targets + nt);
+  d.controls.assign(controls, controls + nc);
+  d.conds.assign(conds, conds + ncond);
+  if (bi) {
+    builtin_desc(bi->id, np ? params[0] : 0.0, d);
+  } else if (ug->kind == U_MATRIX) {
+    d.ug = ug;
+    d.fusable = true;
+    if (ug->diag) {
+      d.kind = D_DIAG;
+      const int D = 1 << ug->k;
+      d.m.resize(D);
+      for (int i = 0; i < D; ++i) d.m[i] = ug->m[(size_t)i * D + i];
+      d.ug = nullptr;
+    } else {
+      d.kind = ug->k == 1 ? D_BUTTERFLY : D_DENSE;
+      d.m = ug->m;
+    }
+  } else {
+    d.kind = D_PERM;
+    d.ug = ug;
+    if (ug->kind == U_AFFINE) {
+      double jd = np ? params[0] : 0.0;
+      if (!(jd >= 0 && jd < 64 && jd == std::floor(jd))) return fail(s, QK_E_ARG, "affine power j must be an integer in [0, 64)");
+      const int k = ug->k;
+      const uint64_t mask = (k == 64) ? ~0ull : ((1ull << k) - 1);
+      uint64_t A = ug->a, B = ug->b;
+      for (int i = 0; i < (int)jd; ++i) {   // (A, B) o (A, B) = (A^2, A B + B)
+        B = (A * B + B) & mask;
+        A = (A * A) & mask;
+      }
+      d.A = A;
+      d.B = B;
+      d.Ainv = inv_mod_2_64(A) & mask;
+    }
+  }
+  if (d.conds.empty() && d.fusable && s->fuse_k >= 2 && nt + nc <= s->fuse_k) {
+    s->pending.push_back(std::move(d));
+    return QK_OK;
+  }
+  qk_status st = flush(s);
+  if (st) return st;
+  return execute(s, d);
+}
+
+qk_status qk_measure(qk_sim s, int32_t qubit, int32_t cbit, double u) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (qubit < 0 || qubit >= s->n) return fail(s, QK_E_ARG, "qubit out of range");
+  if (cbit < -1 || cbit >= s->ncbits) return fail(s, QK_E_ARG, "cbit out of range");
+  if (!(u >= 0.0 && u < 1.0)) return fail(s, QK_E_ARG, "u must be in [0, 1)");
+  qk_status st = flush(s);
+  if (st) return st;
+  if ((st = ensure_meas(s))) return st;
+  Launch L = make_launch(s, {});
+  hipError_t e = launch_measure(L, qubit, cbit, u, nullptr, -1, meas_buffers(s));
+  if (e != hipSuccess) return hip_fail(s, e, "measure");
+  s->sweeps += 2;
+  return QK_OK;
+}
+
+qk_status qk_measure_dev(qk_sim s, int32_t qubit, int32_t cbit, const double* d_u) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (qubit < 0 || qubit >= s->n) return fail(s, QK_E_ARG, "qubit out of range");
+  if (cbit < -1 || cbit >= s->ncbits) return fail(s, QK_E_ARG, "cbit out of range");
+  if (!d_u) return fail(s, QK_E_ARG, "d_u is NULL");
+  qk_status st = flush(s);
+  if (st) return st;
+  if ((st = ensure_meas(s))) return st;
+  Launch L = make_launch(s, {});
+  hipError_t e = launch_measure(L, qubit, cbit, 0.0, d_u, -1, meas_buffers(s));
+  if (e != hipSuccess) return hip_fail(s, e, "measure");
+  s->sweeps += 2;
+  return QK_OK;
+}
+
+qk_status qk_postselect(qk_sim s, int32_t qubit, int32_t cbit, int32_t outcome) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (qubit < 0 || qubit >= s->n) return fail(s, QK_E_ARG, "qubit out of range");
+  if (cbit < -1 || cbit >= s->ncbits) return fail(s, QK_E_ARG, "cbit out of range");
+  if (outcome != 0 && outcome != 1) return fail(s, QK_E_ARG, "outcome must be 0 or 1");
+  qk_status st = flush(s);
+  if (st) return st;
+  if ((st = ensure_meas(s))) return st;
+  Launch L = make_launch(s, {});
+  MeasBuffers mb = meas_buffers(s);
+  hipError_t e = launch_measure(L, qubit, cbit, 0.0, nullptr, outcome, mb);
+  if (e != hipSuccess) return hip_fail(s, e, "postselect");
+  double res[4];
+  e = hipMemcpyAsync(res, mb.result, sizeof res, hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "postselect readback");
+  if ((st = sync_stream(s))) return st;
+  if (res[2] == 0.0) return fail(s, QK_E_STATE, "forced outcome has probability 0");
+  return QK_OK;
+}
+
+qk_status qk_read_cbits(qk_sim s, uint8_t* out, int32_t n) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (n < 0 || n > s->ncbits || (n > 0 && !out)) return fail(s, QK_E_ARG, "bad cbit count");
+  qk_status st = flush(s);
+  if (st) return st;
+  if (n > 0) {
+    hipError_t e = hipMemcpyAsync(out, s->cbits.p, (size_t)n, hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "read cbits");
+  }
+  return sync_stream(s);
+}
+
+qk_status qk_read_measure_log(qk_sim s, double* out, int32_t count, int32_t* written) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (count < 0 || (count > 0 && !out)) return fail(s, QK_E_ARG, "bad count");
+  if (written) *written = 0;
+  qk_status st = flush(s);
+  if (st) return st;
+  if (!s->meas.p) return QK_OK;
+  std::vector<double> logbuf(3 * kMeasLog + 1);
+  MeasBuffers mb = meas_buffers(s);
+  hipError_t e = hipMemcpyAsync(logbuf.data(), mb.log, (3 * kMeasLog + 1) * sizeof(double), hipMemcpyDeviceToHost,
+                                s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "read measure log");
+  if ((st = sync_stream(s))) return st;
+  uint32_t total;
+  std::memcpy(&total, &logbuf[3 * kMeasLog], sizeof total);
+  const uint32_t avail = std::min<uint32_t>(total, kMeasLog);
+  const uint32_t take = std::min<uint32_t>(avail, (uint32_t)count);
+  for (uint32_t i = 0; i < take; ++i) {
+    const uint32_t idx = total - take + i;
+    const uint32_t slot = idx % kMeasLog;
+    out[3 * i] = logbuf[3 * slot];
+    out[3 * i + 1] = logbuf[3 * slot + 1];
+    out[3 * i + 2] = logbuf[3 * slot + 2];
+  }
+  if (written) *written = (int32_t)take;
+  return QK_OK;
+}
+
+qk_status qk_get_state(qk_sim s, void* host_out, size_t bytes) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  const size_t need = ((size_t)1 << s->n) * s->amp;
+  if (!host_out || bytes != need) return fail(s, QK_E_ARG, "buffer size must be 2^n * amplitude size");
+  if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
+  qk_status st = flush(s);
+  if (st) return st;
+  hipError_t e = hipMemcpyAsync(host_out, s->state.p, need, hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "get_state");
+  return sync_stream(s);
+}
+
+qk_status qk_set_state(qk_sim s, const void* host_in, size_t bytes) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  const size_t need = ((size_t)1 << s->n) * s->amp;
+  if (!host_in || bytes != need) return fail(s, QK_E_ARG, "buffer size must be 2^n * amplitude size");
+  if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
+  qk_status st = flush(s);
+  if (st) return st;
+  hipError_t e = hipMemcpyAsync(s->state.p, host_in, need, hipMemcpyHostToDevice, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "set_state");
+  return sync_stream(s);
+}
+
+qk_status qk_state_ptr(qk_sim s, void** dev_ptr, size_t* bytes) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  qk_status st = flush(s);
+  if (st) return st;
+  if (dev_ptr) *dev_ptr = s->state.p;
+  if (bytes) *bytes = s->state.p ? ((size_t)1 << s->n) * s->amp : 0;
+  return QK_OK;
+}
+
+qk_status qk_inner_product(qk_sim a, qk_sim b, double* re, double* im) {
+  if (!a || !b) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (a->n != b->n || !a->state.p || !b->state.p) return fail(a, QK_E_ARG, "qubit counts differ or no state");
+  qk_status st = flush(a);
+  if (!st) st = flush(b);
+  if (st) return st;
+  if (b != a && (st = sync_stream(b))) return st;
+  if ((st = ensure_meas(a))) return st;
+  const uint64_t dim = 1ull << a->n;
+  const int nb = reduce_blocks_for(dim);
+  MeasBuffers mb = meas_buffers(a);
+  hipError_t e = launch_inner_partials(a->state.p, a->c64, b->state.p, b->c64, dim, mb.partials, nb, a->stream);
+  if (e != hipSuccess) return hip_fail(a, e, "inner product");
+  std::vector<double> part(2 * nb);
+  e = hipMemcpyAsync(part.data(), mb.partials, part.size() * sizeof(double), hipMemcpyDeviceToHost, a->stream);
+  if (e != hipSuccess) return hip_fail(a, e, "inner product readback");
+  if ((st = sync_stream(a))) return st;
+  double sr = 0, si = 0;
+  for (int i = 0; i < nb; ++i) {
+    sr += part[2 * i];
+    si += part[2 * i + 1];
+  }
+  if (re) *re = sr;
+  if (im) *im = si;
+  return QK_OK;
+}
+
+qk_status qk_norm2(qk_sim s, double* out) {
+  double re = 0;
+  qk_status st = qk_inner_product(s, s, &re, nullptr);
+  if (st == QK_OK && out) *out = re;
+  return st;
+}
+
+qk_status qk_set_fusion(qk_sim s, int32_t max_k) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (max_k != 0 && (max_k < 2 || max_k > QK_MAX_FUSION_K)) return fail(s, QK_E_ARG, "max_k must be 0 or 2..6");
+  qk_status st = flush(s);
+  if (st) return st;
+  s->fuse_k = max_k;
+  return QK_OK;
+}
+
+qk_status qk_flush(qk_sim s) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  return flush(s);
+}
+
+qk_status qk_sync(qk_sim s) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  qk_status st = flush(s);
+  if (st) return st;
+  if (s->latched) return fail(s, s->latched, "an earlier asynchronous failure was latched");
+  if (!s->state.p && !s->meas.p && !s->arena.dev && !s->cbits.p) return QK_OK;
+  st = sync_stream(s);
+  if (st == QK_OK) s->arena.used = 0;
+  return st;
+}
+
+qk_status qk_num_qubits(qk_sim s, int32_t* n) {
+  if (!s || !n) return fail(s, QK_E_ARG, "NULL argument");
+  *n = s->n;
+  return QK_OK;
+}
+
+qk_status qk_stats(qk_sim s, int64_t* sweeps, int64_t* fused_blocks, int64_t* fused_gates) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (sweeps) *sweeps = s->sweeps;
+  if (fused_blocks) *fused_blocks = s->fused_blocks;
+  if (fused_gates) *fused_gates = s->fused_gates;
+  return QK_OK;
+}
+
+}  // extern "C"

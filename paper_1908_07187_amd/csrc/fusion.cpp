@@ -1,0 +1,144 @@
+// Gate fusion planner: groups consecutive matrix gates into blocks acting on at
+// most kmax qubits and composes each block into one dense 2^k x 2^k matrix in
+// FP64, so a run of gates costs one sweep of the state instead of one per gate.
+//
+// Grouping is greedy and commutation-aware in the only way that needs no
+// algebra: gates on disjoint qubits commute, so a later gate may join the
+// current block when no earlier gate still left outside the block touches any
+// of its qubits.  Scanning in program order, a gate that cannot join marks its
+// qubits as blocked; the scan stops when every qubit outside the block is
+// blocked or after a fixed window.
+#include <algorithm>
+#include <cstring>
+
+#include "qk_internal.h"
+
+namespace qk {
+
+static inline int bit_of(uint64_t x, int j) { return (int)((x >> j) & 1ull); }
+
+FGate make_fgate(const int* targets, int k, const int* controls, int nc, const std::vector<cd>& g) {
+  FGate f;
+  for (int j = 0; j < k; ++j) f.qubits.push_back(targets[j]);
+  for (int j = 0; j < nc; ++j) f.qubits.push_back(controls[j]);
+  std::sort(f.qubits.begin(), f.qubits.end());
+  const int q = (int)f.qubits.size();
+  const int D = 1 << q, K = 1 << k;
+  // position of each target / control inside the sorted qubit list
+  std::vector<int> tp(k), cp(nc);
+  for (int j = 0; j < k; ++j) tp[j] = (int)(std::find(f.qubits.begin(), f.qubits.end(), targets[j]) - f.qubits.begin());
+  for (int j = 0; j < nc; ++j) cp[j] = (int)(std::find(f.qubits.begin(), f.qubits.end(), controls[j]) - f.qubits.begin());
+  uint64_t cmask = 0, tmask = 0;
+  for (int j = 0; j < nc; ++j) cmask |= 1ull << cp[j];
+  for (int j = 0; j < k; ++j) tmask |= 1ull << tp[j];
+  f.m.assign((size_t)D * D, cd(0, 0));
+  for (int col = 0; col < D; ++col) {
+    if ((col & cmask) != cmask) {
+      f.m[(size_t)col * D + col] = 1.0;   // controls not all 1: identity
+      continue;
+    }
+    int mc = 0;
+    for (int j = 0; j < k; ++j) mc |= bit_of(col, tp[j]) << j;
+    for (int mr = 0; mr < K; ++mr) {
+      int row = col & ~(int)tmask;
+      for (int j = 0; j < k; ++j) row |= bit_of(mr, j) << tp[j];
+      f.m[(size_t)row * D + col] = g[(size_t)mr * K + mc];
+    }
+  }
+  f.diag = true;
+  for (int r = 0; r < D && f.diag; ++r)
+    for (int c = 0; c < D; ++c)
+      if (r != c && f.m[(size_t)r * D + c] != cd(0, 0)) {
+        f.diag = false;
+        break;
+      }
+  return f;
+}
+
+// b <- G b where gate g acts on a subset of the block's qubits.
+static void left_multiply(std::vector<cd>& b, const std::vector<int>& qubits, const FGate& g) {
+  const int kb = (int)qubits.size(), kg = (int)g.qubits.size();
+  const int Db = 1 << kb, Dg = 1 << kg;
+  std::vector<int> pos(kg);
+  uint64_t gmask = 0;
+  for (int j = 0; j < kg; ++j) {
+    pos[j] = (int)(std::find(qubits.begin(), qubits.end(), g.qubits[j]) - qubits.begin());
+    gmask |= 1ull << pos[j];
+  }
+  std::vector<cd> v(Dg), w(Dg);
+  std::vector<int> idx(Dg);
+  for (int col = 0; col < Db; ++col) {
+    // treat column `col` as a kb-qubit vector and apply g to it
+    for (int rest = 0; rest < Db; ++rest) {
+      if (rest & (int)gmask) continue;
+      for (int m = 0; m < Dg; ++m) {
+        int i = rest;
+        for (int j = 0; j < kg; ++j) i |= bit_of(m, j) << pos[j];
+        idx[m] = i;
+        v[m] = b[(size_t)i * Db + col];
+      }
+      if (g.diag) {
+        for (int m = 0; m < Dg; ++m) w[m] = g.m[(size_t)m * Dg + m] * v[m];
+      } else {
+        for (int r = 0; r < Dg; ++r) {
+          cd s(0, 0);
+          for (int m = 0; m < Dg; ++m) s += g.m[(size_t)r * Dg + m] * v[m];
+          w[r] = s;
+        }
+      }
+      for (int m = 0; m < Dg; ++m) b[(size_t)idx[m] * Db + col] = w[m];
+    }
+  }
+}
+
+std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax) {
+  const int N = (int)gates.size();
+  std::vector<char> done(N, 0);
+  std::vector<FBlock> out;
+  int first = 0;
+  const int kWindow = 512;
+  while (first < N) {
+    while (first < N && done[first]) ++first;
+    if (first >= N) break;
+    FBlock blk;
+    blk.ngates = 0;
+    blk.diag = true;
+    uint64_t smask = 0, blocked = 0;
+    std::vector<int> members;
+    uint64_t allq = 0;
+    for (int i = first; i < N; ++i)
+      for (int q : gates[i].qubits) allq |= 1ull << q;
+    for (int i = first; i < N && i < first + kWindow; ++i) {
+      if (done[i]) continue;
+      uint64_t gm = 0;
+      for (int q : gates[i].qubits) gm |= 1ull << q;
+      if (gm & blocked) {
+        blocked |= gm;
+      } else if (__builtin_popcountll(smask | gm) <= kmax) {
+        smask |= gm;
+        members.push_back(i);
+        done[i] = 1;
+      } else {
+        blocked |= gm;
+      }
+      // nothing outside the block can still join once every other qubit is blocked
+      if (((allq & ~smask) & ~blocked) == 0 && (smask & ~blocked) == 0) break;
+    }
+    for (int q = 0; q < 64; ++q)
+      if ((smask >> q) & 1) blk.qubits.push_back(q);
+    const int kb = (int)blk.qubits.size();
+    const int Db = 1 << kb;
+    blk.m.assign((size_t)Db * Db, cd(0, 0));
+    for (int r = 0; r < Db; ++r) blk.m[(size_t)r * Db + r] = 1.0;
+    blk.members = members;
+    for (int i : members) {
+      left_multiply(blk.m, blk.qubits, gates[i]);
+      blk.ngates++;
+      blk.diag = blk.diag && gates[i].diag;
+    }
+    out.push_back(std::move(blk));
+  }
+  return out;
+}
+
+}  // namespace qk

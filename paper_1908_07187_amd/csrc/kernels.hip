@@ -1,0 +1,619 @@
+// Per-gate state sweeps for gfx950: one pass over the amplitudes a gate may
+// change, in place, coalesced.  Every kernel evaluates the gate's classical
+// conditions on the device first and exits uniformly when one fails, so
+// measurement outcomes steer later gates without a host round trip.
+#include <algorithm>
+
+#include "qk_internal.h"
+
+namespace qk {
+
+template <typename R> struct V2T;
+template <> struct V2T<float> { using T = float2; };
+template <> struct V2T<double> { using T = double2; };
+template <typename R> using V2 = typename V2T<R>::T;
+
+struct Pos32 {
+  int p[32];
+};
+
+__device__ __forceinline__ bool conds_ok(const CondArgs& c) {
+  for (int i = 0; i < c.n; ++i)
+    if (c.cbits[c.cbit[i]] != (uint8_t)c.val[i]) return false;
+  return true;
+}
+
+// Insert a zero bit at each (ascending) special position of the compact counter x.
+__device__ __forceinline__ uint64_t insert_zeros(uint64_t x, const Special& s) {
+  for (int i = 0; i < s.n; ++i) {
+    const int p = s.pos[i];
+    const uint64_t lo = x & ((1ull << p) - 1);
+    x = ((x >> p) << (p + 1)) | lo;
+  }
+  return x;
+}
+
+// Gate index m of amplitude i: bit j of m = bit pos[j] of i.
+__device__ __forceinline__ uint64_t extract(uint64_t i, const int* pos, int k) {
+  uint64_t m = 0;
+  for (int j = 0; j < k; ++j) m |= ((i >> pos[j]) & 1ull) << j;
+  return m;
+}
+__device__ __forceinline__ uint64_t deposit(uint64_t m, const int* pos, int k) {
+  uint64_t i = 0;
+  for (int j = 0; j < k; ++j) i |= ((m >> j) & 1ull) << pos[j];
+  return i;
+}
+
+static inline unsigned grid_for(uint64_t items, int per_block) {
+  uint64_t g = (items + per_block - 1) / per_block;
+  return (unsigned)std::max<uint64_t>(1, g);
+}
+
+Special make_special(const int* a, int na, const int* b, int nb, const int* c, int nc) {
+  std::vector<int> v;
+  for (int i = 0; i < na; ++i) v.push_back(a[i]);
+  for (int i = 0; i < nb; ++i) v.push_back(b[i]);
+  for (int i = 0; i < nc; ++i) v.push_back(c[i]);
+  std::sort(v.begin(), v.end());
+  v.erase(std::unique(v.begin(), v.end()), v.end());
+  Special s{};
+  s.n = (int)std::min<size_t>(v.size(), kMaxSpecial);   // callers pass at most 28 positions
+  for (int i = 0; i < s.n; ++i) s.pos[i] = v[i];
+  return s;
+}
+
+static uint64_t mask_of(const int* q, int nq) {
+  uint64_t m = 0;
+  for (int i = 0; i < nq; ++i) m |= 1ull << q[i];
+  return m;
+}
+
+// ---------------------------------------------------------------- fill / copy
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_fill_zero(V2<R>* p, uint64_t from, uint64_t to) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = from + (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < to; i += stride) p[i] = V2<R>{0, 0};
+}
+
+template <typename R>
+__global__ void k_set_one(V2<R>* p, uint64_t idx) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) p[idx] = V2<R>{1, 0};
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_copy(V2<R>* __restrict__ dst, const V2<R>* __restrict__ src, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+hipError_t launch_fill_zero(void* p, uint64_t from, uint64_t to, bool c64, hipStream_t s) {
+  if (to <= from) return hipSuccess;
+  unsigned g = std::min<unsigned>(grid_for(to - from, kBlock * 4), 65536);
+  if (c64) hipLaunchKernelGGL(k_fill_zero<float>, dim3(g), dim3(kBlock), 0, s, (float2*)p, from, to);
+  else hipLaunchKernelGGL(k_fill_zero<double>, dim3(g), dim3(kBlock), 0, s, (double2*)p, from, to);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_one(void* p, uint64_t idx, bool c64, hipStream_t s) {
+  if (c64) hipLaunchKernelGGL(k_set_one<float>, dim3(1), dim3(64), 0, s, (float2*)p, idx);
+  else hipLaunchKernelGGL(k_set_one<double>, dim3(1), dim3(64), 0, s, (double2*)p, idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(void* dst, const void* src, uint64_t count, bool c64, hipStream_t s) {
+  if (!count) return hipSuccess;
+  unsigned g = std::min<unsigned>(grid_for(count, kBlock * 4), 65536);
+  if (c64) hipLaunchKernelGGL(k_copy<float>, dim3(g), dim3(kBlock), 0, s, (float2*)dst, (const float2*)src, count);
+  else hipLaunchKernelGGL(k_copy<double>, dim3(g), dim3(kBlock), 0, s, (double2*)dst, (const double2*)src, count);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- 2x2 butterfly
+// For every index pair (i, i | 2^t) with bit t of i = 0 and all control bits
+// 1: [a_i, a_{i+2^t}] <- U [a_i, a_{i+2^t}].  Each thread owns ITEMS pairs,
+// strided by the block size so every load instruction of a wave is coalesced;
+// all loads are issued before any store.
+
+template <typename R, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_butterfly(V2<R>* __restrict__ psi, uint64_t npairs, Special sp,
+                                                      uint64_t cmask, uint64_t tbit, Mat2 u, CondArgs cond) {
+  if (!conds_ok(cond)) return;
+  const R a0 = (R)u.v[0], b0 = (R)u.v[1], a1 = (R)u.v[2], b1 = (R)u.v[3];
+  const R a2 = (R)u.v[4], b2 = (R)u.v[5], a3 = (R)u.v[6], b3 = (R)u.v[7];
+  const uint64_t j0 = (uint64_t)blockIdx.x * (kBlock * ITEMS) + threadIdx.x;
+  V2<R> x[ITEMS], y[ITEMS];
+  uint64_t idx[ITEMS];
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const uint64_t j = j0 + (uint64_t)k * kBlock;
+    idx[k] = insert_zeros(j, sp) | cmask;
+    if (j < npairs) {
+      x[k] = psi[idx[k]];
+      y[k] = psi[idx[k] | tbit];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const uint64_t j = j0 + (uint64_t)k * kBlock;
+    if (j < npairs) {
+      const V2<R> p = x[k], q = y[k];
+      V2<R> r0, r1;
+      r0.x = a0 * p.x - b0 * p.y + a1 * q.x - b1 * q.y;
+      r0.y = a0 * p.y + b0 * p.x + a1 * q.y + b1 * q.x;
+      r1.x = a2 * p.x - b2 * p.y + a3 * q.x - b3 * q.y;
+      r1.y = a2 * p.y + b2 * p.x + a3 * q.y + b3 * q.x;
+      psi[idx[k]] = r0;
+      psi[idx[k] | tbit] = r1;
+    }
+  }
+}
+
+hipError_t launch_butterfly(const Launch& L, int t, const int* controls, int nc, const Mat2& u) {
+  Special sp = make_special(&t, 1, controls, nc);
+  const uint64_t npairs = 1ull << (L.n - 1 - nc);
+  const uint64_t cmask = mask_of(controls, nc), tbit = 1ull << t;
+  constexpr int IT = 4;
+  const unsigned g = grid_for(npairs, kBlock * IT);
+  if (L.c64)
+    hipLaunchKernelGGL((k_butterfly<float, IT>), dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi, npairs, sp,
+                       cmask, tbit, u, L.cond);
+  else
+    hipLaunchKernelGGL((k_butterfly<double, IT>), dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi, npairs, sp,
+                       cmask, tbit, u, L.cond);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- diagonal
+// a_i <- d[m(i)] a_i with m(i) the bits of i on the targets, over the subspace
+// where every control bit is 1.
+
+struct Pos8 {
+  int p[8];
+};
+
+template <typename R, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_diag(V2<R>* __restrict__ psi, uint64_t nitems, Special sp, uint64_t cmask,
+                                                 int k, Pos8 tp, Diag64 d, CondArgs cond) {
+  if (!conds_ok(cond)) return;
+  const uint64_t j0 = (uint64_t)blockIdx.x * (kBlock * ITEMS) + threadIdx.x;
+  V2<R> x[ITEMS];
+  uint64_t idx[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t j = j0 + (uint64_t)it * kBlock;
+    idx[it] = insert_zeros(j, sp) | cmask;
+    if (j < nitems) x[it] = psi[idx[it]];
+  }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t j = j0 + (uint64_t)it * kBlock;
+    if (j < nitems) {
+      const int m = (int)extract(idx[it], tp.p, k);
+      const R dr = (R)d.v[2 * m], di = (R)d.v[2 * m + 1];
+      const V2<R> p = x[it];
+      psi[idx[it]] = V2<R>{dr * p.x - di * p.y, dr * p.y + di * p.x};
+    }
+  }
+}
+
+hipError_t launch_diag(const Launch& L, const int* targets, int k, const int* controls, int nc, const Diag64& d) {
+  if (k > 6) return hipErrorInvalidValue;
+  Special sp = make_special(controls, nc, nullptr, 0);
+  const uint64_t nitems = 1ull << (L.n - nc);
+  Pos8 tp{};
+  for (int j = 0; j < k; ++j) tp.p[j] = targets[j];
+  constexpr int IT = 4;
+  const unsigned g = grid_for(nitems, kBlock * IT);
+  const uint64_t cmask = mask_of(controls, nc);
+  if (L.c64)
+    hipLaunchKernelGGL((k_diag<float, IT>), dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi, nitems, sp, cmask, k,
+                       tp, d, L.cond);
+  else
+    hipLaunchKernelGGL((k_diag<double, IT>), dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi, nitems, sp, cmask,
+                       k, tp, d, L.cond);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- phase on the all-ones subspace
+// a_i <- z a_i where every bit of `bits` is 1 (PHASE, CPHASE, S, T, Z and
+// their controlled forms touch only this 2^(n - |bits|) subspace).
+
+template <typename R, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_phase_all1(V2<R>* __restrict__ psi, uint64_t nitems, Special sp,
+                                                       uint64_t mask, double zr_, double zi_, CondArgs cond) {
+  if (!conds_ok(cond)) return;
+  const R zr = (R)zr_, zi = (R)zi_;
+  const uint64_t j0 = (uint64_t)blockIdx.x * (kBlock * ITEMS) + threadIdx.x;
+  V2<R> x[ITEMS];
+  uint64_t idx[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t j = j0 + (uint64_t)it * kBlock;
+    idx[it] = insert_zeros(j, sp) | mask;
+    if (j < nitems) x[it] = psi[idx[it]];
+  }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t j = j0 + (uint64_t)it * kBlock;
+    if (j < nitems) {
+      const V2<R> p = x[it];
+      psi[idx[it]] = V2<R>{zr * p.x - zi * p.y, zr * p.y + zi * p.x};
+    }
+  }
+}
+
+hipError_t launch_phase_all1(const Launch& L, const int* bits, int nb, double zr, double zi) {
+  Special sp = make_special(bits, nb, nullptr, 0);
+  const uint64_t nitems = 1ull << (L.n - nb);
+  const uint64_t mask = mask_of(bits, nb);
+  constexpr int IT = 4;
+  const unsigned g = grid_for(nitems, kBlock * IT);
+  if (L.c64)
+    hipLaunchKernelGGL((k_phase_all1<float, IT>), dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi, nitems, sp, mask,
+                       zr, zi, L.cond);
+  else
+    hipLaunchKernelGGL((k_phase_all1<double, IT>), dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi, nitems, sp,
+                       mask, zr, zi, L.cond);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- swap
+// Exchanges a_{base|2^a} and a_{base|2^b} for every base with both bits 0 and
+// all control bits 1 (touches 2^(n-1-c) amplitudes).
+
+template <typename R, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_swap(V2<R>* __restrict__ psi, uint64_t nitems, Special sp, uint64_t cmask,
+                                                 uint64_t abit, uint64_t bbit, CondArgs cond) {
+  if (!conds_ok(cond)) return;
+  const uint64_t j0 = (uint64_t)blockIdx.x * (kBlock * ITEMS) + threadIdx.x;
+  V2<R> x[ITEMS], y[ITEMS];
+  uint64_t idx[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t j = j0 + (uint64_t)it * kBlock;
+    idx[it] = insert_zeros(j, sp) | cmask;
+    if (j < nitems) {
+      x[it] = psi[idx[it] | abit];
+      y[it] = psi[idx[it] | bbit];
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t j = j0 + (uint64_t)it * kBlock;
+    if (j < nitems) {
+      psi[idx[it] | abit] = y[it];
+      psi[idx[it] | bbit] = x[it];
+    }
+  }
+}
+
+hipError_t launch_swap(const Launch& L, int a, int b, const int* controls, int nc) {
+  int ab[2] = {a, b};
+  Special sp = make_special(ab, 2, controls, nc);
+  const uint64_t nitems = 1ull << (L.n - 2 - nc);
+  constexpr int IT = 4;
+  const unsigned g = grid_for(nitems, kBlock * IT);
+  const uint64_t cmask = mask_of(controls, nc);
+  if (L.c64)
+    hipLaunchKernelGGL((k_swap<float, IT>), dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi, nitems, sp, cmask,
+                       1ull << a, 1ull << b, L.cond);
+  else
+    hipLaunchKernelGGL((k_swap<double, IT>), dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi, nitems, sp, cmask,
+                       1ull << a, 1ull << b, L.cond);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- dense k-target (vector ALU)
+// Each block stages G groups of 2^k amplitudes in LDS (G = max(1, 256 / 2^k)),
+// then every thread writes rows r of M v for its groups.  Used for k > 6, for
+// states too small for the matrix-core tile, and as the general fallback.
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_dense_generic(V2<R>* __restrict__ psi, const V2<R>* __restrict__ mat,
+                                                          int k, uint64_t ngroups, Special sp, uint64_t cmask, Pos32 tp,
+                                                          CondArgs cond) {
+  if (!conds_ok(cond)) return;
+  extern __shared__ unsigned char smem_raw[];
+  V2<R>* buf = reinterpret_cast<V2<R>*>(smem_raw);
+  const int dimK = 1 << k;
+  const int G = dimK >= kBlock ? 1 : kBlock / dimK;
+  const uint64_t g0 = (uint64_t)blockIdx.x * G;
+  for (int e = threadIdx.x; e < G * dimK; e += kBlock) {
+    const uint64_t gid = g0 + (uint64_t)(e >> k);
+    if (gid < ngroups) {
+      const uint64_t base = insert_zeros(gid, sp) | cmask;
+      buf[e] = psi[base | deposit((uint64_t)(e & (dimK - 1)), tp.p, k)];
+    }
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < G * dimK; e += kBlock) {
+    const int g = e >> k, r = e & (dimK - 1);
+    const uint64_t gid = g0 + (uint64_t)g;
+    if (gid >= ngroups) continue;
+    const V2<R>* row = mat + (size_t)r * dimK;
+    const V2<R>* v = buf + (size_t)g * dimK;
+    R sr = 0, si = 0;
+    for (int m = 0; m < dimK; ++m) {
+      const V2<R> a = row[m], b = v[m];
+      sr += a.x * b.x - a.y * b.y;
+      si += a.x * b.y + a.y * b.x;
+    }
+    const uint64_t base = insert_zeros(gid, sp) | cmask;
+    psi[base | deposit((uint64_t)r, tp.p, k)] = V2<R>{sr, si};
+  }
+}
+
+hipError_t launch_dense_generic(const Launch& L, const int* targets, int k, const int* controls, int nc,
+                                const void* d_matrix) {
+  if (k < 1 || k > QK_MAX_MATRIX_K) return hipErrorInvalidValue;
+  Special sp = make_special(targets, k, controls, nc);
+  const uint64_t ngroups = 1ull << (L.n - k - nc);
+  Pos32 tp{};
+  for (int j = 0; j < k; ++j) tp.p[j] = targets[j];
+  const int dimK = 1 << k;
+  const int G = dimK >= kBlock ? 1 : kBlock / dimK;
+  const unsigned g = grid_for(ngroups, G);
+  const uint64_t cmask = mask_of(controls, nc);
+  const size_t shm = (size_t)G * dimK * (L.c64 ? sizeof(float2) : sizeof(double2));
+  if (L.c64)
+    hipLaunchKernelGGL(k_dense_generic<float>, dim3(g), dim3(kBlock), shm, L.stream, (float2*)L.psi,
+                       (const float2*)d_matrix, k, ngroups, sp, cmask, tp, L.cond);
+  else
+    hipLaunchKernelGGL(k_dense_generic<double>, dim3(g), dim3(kBlock), shm, L.stream, (double2*)L.psi,
+                       (const double2*)d_matrix, k, ngroups, sp, cmask, tp, L.cond);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- permutation (oracle) gate
+// U|x> = |f(x)> on the targets: the amplitude at gate index x moves to f(x).
+// Done as a gather out[y] = in[f^-1(y)] over the controlled subspace into a
+// compact scratch buffer (coalesced writes, gathered reads), then copied back.
+// f^-1 is a device table (uint32) or, for the affine family, the closed form
+// x = A^-1 (y - B) mod 2^k.
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_perm_gather(const V2<R>* __restrict__ in, V2<R>* __restrict__ out,
+                                                        uint64_t nitems, Special sp, uint64_t cmask, Pos32 tp, int k,
+                                                        int contiguous, uint64_t tmask,
+                                                        const uint32_t* __restrict__ finv, int affine, uint64_t A,
+                                                        uint64_t B, uint64_t Ainv, CondArgs cond) {
+  if (!conds_ok(cond)) return;
+  const uint64_t kmask = (k >= 64) ? ~0ull : ((1ull << k) - 1);
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  (void)A;
+  for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < nitems; e += stride) {
+    const uint64_t i = insert_zeros(e, sp) | cmask;
+    const uint64_t y = contiguous ? ((i >> tp.p[0]) & kmask) : extract(i, tp.p, k);
+    const uint64_t x = affine ? ((Ainv * (y - B)) & kmask) : (uint64_t)finv[y];
+    const uint64_t src = (i & ~tmask) | (contiguous ? (x << tp.p[0]) : deposit(x, tp.p, k));
+    out[e] = in[src];
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_perm_scatter(V2<R>* __restrict__ psi, const V2<R>* __restrict__ scratch,
+                                                         uint64_t nitems, Special sp, uint64_t cmask, CondArgs cond) {
+  if (!conds_ok(cond)) return;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < nitems; e += stride)
+    psi[insert_zeros(e, sp) | cmask] = scratch[e];
+}
+
+hipError_t launch_perm(const Launch& L, void* scratch, const int* targets, int k, const int* controls, int nc,
+                       const uint32_t* d_finv, bool affine, uint64_t A, uint64_t B, uint64_t Ainv) {
+  if (k < 1 || k > 32) return hipErrorInvalidValue;
+  // the gather enumerates the controlled subspace; targets are part of it
+  Special sp = make_special(controls, nc, nullptr, 0);
+  const uint64_t nitems = 1ull << (L.n - nc);
+  Pos32 tp{};
+  int contiguous = 1;
+  for (int j = 0; j < k; ++j) {
+    tp.p[j] = targets[j];
+    if (targets[j] != targets[0] + j) contiguous = 0;
+  }
+  const uint64_t tmask = mask_of(targets, k), cmask = mask_of(controls, nc);
+  const unsigned g = std::min<unsigned>(grid_for(nitems, kBlock * 4), 1u << 20);
+  if (L.c64) {
+    hipLaunchKernelGGL(k_perm_gather<float>, dim3(g), dim3(kBlock), 0, L.stream, (const float2*)L.psi,
+                       (float2*)scratch, nitems, sp, cmask, tp, k, contiguous, tmask, d_finv, affine ? 1 : 0, A, B,
+                       Ainv, L.cond);
+    hipLaunchKernelGGL(k_perm_scatter<float>, dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi,
+                       (const float2*)scratch, nitems, sp, cmask, L.cond);
+  } else {
+    hipLaunchKernelGGL(k_perm_gather<double>, dim3(g), dim3(kBlock), 0, L.stream, (const double2*)L.psi,
+                       (double2*)scratch, nitems, sp, cmask, tp, k, contiguous, tmask, d_finv, affine ? 1 : 0, A, B,
+                       Ainv, L.cond);
+    hipLaunchKernelGGL(k_perm_scatter<double>, dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi,
+                       (const double2*)scratch, nitems, sp, cmask, L.cond);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- measurement
+// (1) every block sums |a_i|^2 of a fixed contiguous range in FP64, split by
+// bit q, with a fixed thread->element mapping and a fixed reduction tree;
+// (2) one block adds the block sums in index order, draws the outcome
+// (u < P0 ? 0 : 1), writes the cbit, 1/sqrt(p_outcome) and a log entry;
+// (3) the collapse reads the outcome from device memory, scales the kept half
+// and zeroes the other.  The result depends only on the state, never on what
+// else runs on the device.
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Fixed-order sum over a 256-thread block; result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0) s = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+  return s;
+}
+
+int reduce_blocks_for(uint64_t count) {
+  uint64_t b = count / 4096;
+  if (b < 1) b = 1;
+  if (b > (uint64_t)kReduceBlocks) b = kReduceBlocks;
+  return (int)b;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBlock) void k_prob_partial(const V2<R>* __restrict__ psi, uint64_t dim,
+                                                         uint64_t per_block, uint64_t qbit, double* partials) {
+  __shared__ double sh[4];
+  const uint64_t start = (uint64_t)blockIdx.x * per_block;
+  const uint64_t end = (start + per_block < dim) ? start + per_block : dim;
+  double s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0};
+  for (uint64_t i = start + threadIdx.x; i < end; i += 4 * kBlock) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t ii = i + (uint64_t)u * kBlock;
+      if (ii < end) {
+        const V2<R> a = psi[ii];
+        const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
+        if (ii & qbit) s1[u] += p; else s0[u] += p;
+      }
+    }
+  }
+  const double t0 = block_sum((s0[0] + s0[1]) + (s0[2] + s0[3]), sh);
+  const double t1 = block_sum((s1[0] + s1[1]) + (s1[2] + s1[3]), sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = t0;
+    partials[2 * blockIdx.x + 1] = t1;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_meas_finalize(const double* __restrict__ partials, int nblocks, double u,
+                                                          const double* d_u, int forced, int cbit, double* result,
+                                                          uint8_t* cbits, double* log, uint32_t* log_count) {
+  __shared__ double sh[4];
+  double a0 = 0, a1 = 0;
+  for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+    a0 += partials[2 * b];
+    a1 += partials[2 * b + 1];
+  }
+  const double p0 = block_sum(a0, sh);
+  const double p1 = block_sum(a1, sh);
+  if (threadIdx.x == 0) {
+    const double P0 = p0 / (p0 + p1);
+    const double uu = d_u ? *d_u : u;
+    const int oc = forced >= 0 ? forced : ((uu < P0) ? 0 : 1);
+    const double po = oc ? p1 : p0;
+    const double scale = (po > 0.0) ? 1.0 / sqrt(po) : 0.0;
+    result[0] = p0;
+    result[1] = p1;
+    result[2] = scale;
+    result[3] = (double)oc;
+    if (cbit >= 0 && po > 0.0) cbits[cbit] = (uint8_t)oc;
+    const uint32_t c = *log_count;
+    const uint32_t slot = c % (uint32_t)kMeasLog;
+    log[3 * slot] = p0;
+    log[3 * slot + 1] = p1;
+    log[3 * slot + 2] = (double)oc;
+    *log_count = c + 1;
+  }
+}
+
+template <typename R, int ITEMS>
+__global__ __launch_bounds__(kBlock) void k_collapse(V2<R>* __restrict__ psi, uint64_t npairs, int q,
+                                                     const double* __restrict__ result) {
+  const double scale_d = result[2];
+  if (scale_d == 0.0) return;
+  const R scale = (R)scale_d;
+  const int oc = (int)result[3];
+  const uint64_t qb = 1ull << q, lo = qb - 1;
+  const uint64_t j0 = (uint64_t)blockIdx.x * (kBlock * ITEMS) + threadIdx.x;
+  V2<R> x[ITEMS];
+  uint64_t keep[ITEMS];
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t j = j0 + (uint64_t)it * kBlock;
+    const uint64_t i0 = ((j & ~lo) << 1) | (j & lo);
+    keep[it] = oc ? (i0 | qb) : i0;
+    if (j < npairs) x[it] = psi[keep[it]];
+  }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t j = j0 + (uint64_t)it * kBlock;
+    if (j < npairs) {
+      psi[keep[it]] = V2<R>{x[it].x * scale, x[it].y * scale};
+      psi[keep[it] ^ qb] = V2<R>{0, 0};
+    }
+  }
+}
+
+hipError_t launch_measure(const Launch& L, int qubit, int cbit, double u, const double* d_u, int forced,
+                          const MeasBuffers& mb) {
+  const uint64_t dim = 1ull << L.n;
+  const int nb = reduce_blocks_for(dim);
+  const uint64_t per_block = (dim + nb - 1) / nb;
+  if (L.c64)
+    hipLaunchKernelGGL(k_prob_partial<float>, dim3(nb), dim3(kBlock), 0, L.stream, (const float2*)L.psi, dim,
+                       per_block, 1ull << qubit, mb.partials);
+  else
+    hipLaunchKernelGGL(k_prob_partial<double>, dim3(nb), dim3(kBlock), 0, L.stream, (const double2*)L.psi, dim,
+                       per_block, 1ull << qubit, mb.partials);
+  hipLaunchKernelGGL(k_meas_finalize, dim3(1), dim3(kBlock), 0, L.stream, (const double*)mb.partials, nb, u, d_u,
+                     forced, cbit, mb.result, mb.cbits, mb.log, mb.log_count);
+  const uint64_t npairs = dim >> 1;
+  constexpr int IT = 4;
+  const unsigned g = grid_for(npairs, kBlock * IT);
+  if (L.c64)
+    hipLaunchKernelGGL((k_collapse<float, IT>), dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi, npairs, qubit,
+                       (const double*)mb.result);
+  else
+    hipLaunchKernelGGL((k_collapse<double, IT>), dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi, npairs, qubit,
+                       (const double*)mb.result);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- inner product
+// Block partials of sum conj(a_i) b_i in FP64 over fixed ranges; the host adds
+// them in index order.
+
+template <typename RA, typename RB>
+__global__ __launch_bounds__(kBlock) void k_inner_partials(const V2<RA>* __restrict__ a, const V2<RB>* __restrict__ b,
+                                                           uint64_t dim, uint64_t per_block, double* partials) {
+  __shared__ double sh[4];
+  const uint64_t start = (uint64_t)blockIdx.x * per_block;
+  const uint64_t end = (start + per_block < dim) ? start + per_block : dim;
+  double re = 0, im = 0;
+  for (uint64_t i = start + threadIdx.x; i < end; i += kBlock) {
+    const double ar = a[i].x, ai = a[i].y, br = b[i].x, bi = b[i].y;
+    re += ar * br + ai * bi;
+    im += ar * bi - ai * br;
+  }
+  const double tr = block_sum(re, sh);
+  const double ti = block_sum(im, sh);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = tr;
+    partials[2 * blockIdx.x + 1] = ti;
+  }
+}
+
+hipError_t launch_inner_partials(const void* a, bool a64, const void* b, bool b64, uint64_t dim, double* partials,
+                                 int nblocks, hipStream_t s) {
+  const uint64_t per_block = (dim + nblocks - 1) / nblocks;
+  if (a64 && b64)
+    hipLaunchKernelGGL((k_inner_partials<float, float>), dim3(nblocks), dim3(kBlock), 0, s, (const float2*)a,
+                       (const float2*)b, dim, per_block, partials);
+  else if (a64)
+    hipLaunchKernelGGL((k_inner_partials<float, double>), dim3(nblocks), dim3(kBlock), 0, s, (const float2*)a,
+                       (const double2*)b, dim, per_block, partials);
+  else if (b64)
+    hipLaunchKernelGGL((k_inner_partials<double, float>), dim3(nblocks), dim3(kBlock), 0, s, (const double2*)a,
+                       (const float2*)b, dim, per_block, partials);
+  else
+    hipLaunchKernelGGL((k_inner_partials<double, double>), dim3(nblocks), dim3(kBlock), 0, s, (const double2*)a,
+                       (const double2*)b, dim, per_block, partials);
+  return hipGetLastError();
+}
+
+}  // namespace qk

@@ -1,0 +1,115 @@
+// Internal declarations shared by the runtime (api.hip), the sweep kernels
+// (kernels.hip), the matrix-core kernel (fused.hip) and the fusion planner
+// (fusion.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "qk.h"
+
+namespace qk {
+
+using cd = std::complex<double>;
+
+constexpr int kMaxSpecial = 40;        // zero-insertion positions per launch
+constexpr int kBlock = 256;            // threads per block of the sweep kernels
+constexpr int kReduceBlocks = 1024;    // fixed first-level reduction grid (max)
+constexpr int kMeasLog = 4096;         // measurement log entries kept on device
+
+// Ascending bit positions at which zero bits are inserted into a compact
+// counter to enumerate a subspace (the positions of targets, controls and,
+// for the matrix-core kernel, column bits).
+struct Special {
+  int n;
+  int pos[kMaxSpecial];
+};
+
+// Classical conditions, evaluated on the device at kernel start.
+struct CondArgs {
+  const uint8_t* cbits;
+  int n;
+  int cbit[QK_MAX_CONDS];
+  int val[QK_MAX_CONDS];
+};
+
+// Dense matrix for the one-target butterfly: u00 u01 u10 u11 as (re, im).
+struct Mat2 {
+  double v[8];
+};
+
+// Diagonal of up to 6 target qubits (64 entries).
+struct Diag64 {
+  double v[128];
+};
+
+// Where device work goes and what it works on.
+struct Launch {
+  hipStream_t stream;
+  int n;           // qubits
+  bool c64;        // complex64 (else complex128)
+  void* psi;       // state
+  CondArgs cond;
+};
+
+// Sorted, de-duplicated zero-insertion positions.
+Special make_special(const int* a, int na, const int* b, int nb, const int* c = nullptr, int nc = 0);
+
+// ---- sweep kernels (kernels.hip) ---------------------------------------------
+hipError_t launch_fill_zero(void* p, uint64_t from, uint64_t to, bool c64, hipStream_t s);
+hipError_t launch_set_one(void* p, uint64_t idx, bool c64, hipStream_t s);
+hipError_t launch_copy(void* dst, const void* src, uint64_t count, bool c64, hipStream_t s);
+hipError_t launch_butterfly(const Launch& L, int t, const int* controls, int nc, const Mat2& u);
+hipError_t launch_diag(const Launch& L, const int* targets, int k, const int* controls, int nc, const Diag64& d);
+hipError_t launch_phase_all1(const Launch& L, const int* bits, int nb, double zr, double zi);
+hipError_t launch_swap(const Launch& L, int a, int b, const int* controls, int nc);
+hipError_t launch_dense_generic(const Launch& L, const int* targets, int k, const int* controls, int nc,
+                                const void* d_matrix);
+hipError_t launch_perm(const Launch& L, void* scratch, const int* targets, int k, const int* controls, int nc,
+                       const uint32_t* d_finv, bool affine, uint64_t A, uint64_t B, uint64_t Ainv);
+
+// Measurement: partial sums -> finalize (outcome, cbit, scale, log) -> collapse.
+struct MeasBuffers {
+  double* partials;     // 2 * kReduceBlocks
+  double* result;       // p0, p1, scale, outcome
+  double* log;          // 3 * kMeasLog
+  uint32_t* log_count;  // entries written so far
+  uint8_t* cbits;
+};
+int reduce_blocks_for(uint64_t count);
+hipError_t launch_measure(const Launch& L, int qubit, int cbit, double u, const double* d_u, int forced,
+                          const MeasBuffers& mb);
+hipError_t launch_inner_partials(const void* a, bool a64, const void* b, bool b64, uint64_t dim,
+                                 double* partials, int nblocks, hipStream_t s);
+
+// ---- matrix-core kernel (fused.hip) -----------------------------------------
+// Dense 2^k x 2^k gate (2 <= k <= 6) on targets, restricted to controls = 1,
+// as a complex GEMM per 16-column tile on 16x16x4 MFMA (f32 for complex64,
+// f64 for complex128).  Needs at least 4 qubits outside targets and controls.
+bool mfma_supported(int n, int k, int nc, bool c64);
+hipError_t launch_dense_mfma(const Launch& L, const int* targets, int k, const int* controls, int nc,
+                             const void* d_matrix, int waves_per_cu);
+
+// ---- fusion planner (fusion.cpp) --------------------------------------------
+struct FGate {
+  std::vector<int> qubits;   // ascending: union of targets and controls
+  std::vector<cd> m;         // 2^q x 2^q, row-major, bit j <-> qubits[j]
+  bool diag;
+};
+struct FBlock {
+  std::vector<int> qubits;   // ascending
+  std::vector<cd> m;         // 2^k x 2^k
+  int ngates;
+  bool diag;
+  std::vector<int> members;  // indices of the gates composed, in application order
+};
+// Dense matrix on sorted(targets u controls) of a gate with matrix g on targets.
+FGate make_fgate(const int* targets, int k, const int* controls, int nc, const std::vector<cd>& g);
+// Greedy commutation-aware grouping into blocks of at most kmax qubits.
+std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax);
+
+}  // namespace qk

@@ -1,0 +1,312 @@
+"""ctypes binding of libqk.so (the C ABI declared in include/qk.h).
+
+Argument marshalling only: every step of the state update runs in the HIP
+kernels of libqk.so.  PyTorch provides device memory (its caching allocator,
+through the allocator callbacks) and the HIP stream.  If the library is not
+built this module raises ImportError-like errors loudly; there is no CPU
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "lib", "libqk.so")
+
+QK_OK = 0
+STATUS = {0: "QK_OK", -1: "QK_E_ARG", -2: "QK_E_NOT_UNITARY", -3: "QK_E_NOT_PERMUTATION", -4: "QK_E_OOM",
+          -5: "QK_E_HIP", -6: "QK_E_STATE", -7: "QK_E_UNSUPPORTED"}
+QK_C64, QK_C128 = 1, 2
+DTYPES = {"c64": QK_C64, "complex64": QK_C64, "c128": QK_C128, "complex128": QK_C128}
+BUILTINS = {"H": 1, "X": 2, "Y": 3, "Z": 4, "S": 5, "T": 6, "SDG": 7, "TDG": 8, "RX": 9, "RY": 10, "RZ": 11,
+            "PHASE": 12, "CPHASE": 13, "SWAP": 14, "RZZ": 15}
+
+# Every exported symbol and its signature (restype, argtypes).
+_P, _I32, _I64, _D, _SZ, _U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t, C.c_uint64
+_I32P, _DP, _U8P, _U64P, _I64P = (C.POINTER(C.c_int32), C.POINTER(C.c_double), C.POINTER(C.c_uint8),
+                                  C.POINTER(C.c_uint64), C.POINTER(C.c_int64))
+
+
+class QkCond(C.Structure):
+    _fields_ = [("cbit", C.c_int32), ("value", C.c_int32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+INDEX_FN = C.CFUNCTYPE(C.c_uint64, C.c_uint64, C.c_void_p)
+
+
+class QkAllocator(C.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+SIGNATURES = {
+    "qk_create": (_I32, [_I32, C.POINTER(QkAllocator), _P, C.POINTER(_P)]),
+    "qk_destroy": (_I32, [_P]),
+    "qk_add_qubits": (_I32, [_P, _I32, _I32P]),
+    "qk_add_cbits": (_I32, [_P, _I32, _I32P]),
+    "qk_gate_builtin": (_I32, [C.c_char_p, _I32P]),
+    "qk_define_gate_matrix": (_I32, [_P, C.c_char_p, _I32, _DP, _D, _I32P]),
+    "qk_define_gate_index": (_I32, [_P, C.c_char_p, _I32, INDEX_FN, _P, _I32P]),
+    "qk_define_gate_table": (_I32, [_P, C.c_char_p, _I32, _U64P, _I32P]),
+    "qk_define_gate_affine": (_I32, [_P, C.c_char_p, _I32, _U64, _U64, _I32P]),
+    "qk_apply_gate": (_I32, [_P, _I32, _I32P, _I32, _I32P, _I32, C.POINTER(QkCond), _I32, _DP, _I32]),
+    "qk_measure": (_I32, [_P, _I32, _I32, _D]),
+    "qk_measure_dev": (_I32, [_P, _I32, _I32, _P]),
+    "qk_postselect": (_I32, [_P, _I32, _I32, _I32]),
+    "qk_read_cbits": (_I32, [_P, _U8P, _I32]),
+    "qk_read_measure_log": (_I32, [_P, _DP, _I32, _I32P]),
+    "qk_get_state": (_I32, [_P, _P, _SZ]),
+    "qk_set_state": (_I32, [_P, _P, _SZ]),
+    "qk_state_ptr": (_I32, [_P, C.POINTER(_P), C.POINTER(_SZ)]),
+    "qk_inner_product": (_I32, [_P, _P, _DP, _DP]),
+    "qk_norm2": (_I32, [_P, _DP]),
+    "qk_set_fusion": (_I32, [_P, _I32]),
+    "qk_flush": (_I32, [_P]),
+    "qk_sync": (_I32, [_P]),
+    "qk_num_qubits": (_I32, [_P, _I32P]),
+    "qk_stats": (_I32, [_P, _I64P, _I64P, _I64P]),
+    "qk_last_error": (C.c_char_p, [_P]),
+    "qk_status_string": (C.c_char_p, [_I32]),
+}
+
+_lib = None
+
+
+def load(build_if_missing: bool = True):
+    """Load libqk.so; build it first if it does not exist (never a fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        if not build_if_missing:
+            raise ImportError(f"{LIB_PATH} is not built")
+        from .build import build
+        build()
+    lib = C.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class QKError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+def _i32arr(xs):
+    xs = [int(x) for x in xs]
+    return (C.c_int32 * max(1, len(xs)))(*xs), len(xs)
+
+
+# ------------------------------------------------------------------ torch plumbing
+
+class _TorchDevice:
+    """Caching-allocator callbacks and the stream handle from PyTorch."""
+
+    def __init__(self, stream=None, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible to PyTorch: the HIP path cannot run here")
+        self.torch = torch
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self._alloc = ALLOC_FN(self._do_alloc)
+        self._free = FREE_FN(self._do_free)
+        self.allocator = QkAllocator(self._alloc, self._free, None)
+
+    def _do_alloc(self, nbytes, stream, ctx):
+        try:
+            return int(self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, int(stream or 0)))
+        except Exception:
+            return None
+
+    def _do_free(self, ptr, nbytes, stream, ctx):
+        try:
+            self.torch.cuda.caching_allocator_delete(int(ptr))
+        except Exception:
+            pass
+
+    @property
+    def stream_handle(self) -> int:
+        return int(self.stream.cuda_stream)
+
+
+class Sim:
+    """One state vector on the GPU.  Thin wrapper over the qk_* calls."""
+
+    def __init__(self, dtype: str = "c128", stream=None, allocator: str = "torch", device: int = 0):
+        self.lib = load()
+        self.dtype = dtype
+        self.np_dtype = np.complex64 if DTYPES[dtype] == QK_C64 else np.complex128
+        h = C.c_void_p()
+        if allocator == "torch":
+            self._dev = _TorchDevice(stream, device)
+            st = self.lib.qk_create(DTYPES[dtype], C.byref(self._dev.allocator), C.c_void_p(self._dev.stream_handle),
+                                    C.byref(h))
+        elif allocator == "none":
+            # hipMalloc inside the library, null stream (CPU-side argument checks work without a GPU)
+            self._dev = None
+            st = self.lib.qk_create(DTYPES[dtype], None, None, C.byref(h))
+        else:
+            raise ValueError(allocator)
+        if st != QK_OK:
+            raise QKError(st, self.lib.qk_last_error(None).decode())
+        self.h = h
+        self.n = 0
+        self.ncbits = 0
+        self._builtin_cache = {}
+
+    # -- errors / lifetime
+    def _chk(self, st):
+        if st != QK_OK:
+            raise QKError(st, self.lib.qk_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._chk(self.lib.qk_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- registers
+    def add_qubits(self, m: int) -> int:
+        first = C.c_int32()
+        self._chk(self.lib.qk_add_qubits(self.h, m, C.byref(first)))
+        self.n += m
+        return first.value
+
+    def add_cbits(self, m: int) -> int:
+        first = C.c_int32()
+        self._chk(self.lib.qk_add_cbits(self.h, m, C.byref(first)))
+        self.ncbits += m
+        return first.value
+
+    # -- gates
+    def builtin(self, name: str) -> int:
+        gid = self._builtin_cache.get(name)
+        if gid is None:
+            out = C.c_int32()
+            st = self.lib.qk_gate_builtin(name.encode(), C.byref(out))
+            if st != QK_OK:
+                raise QKError(st, self.lib.qk_last_error(None).decode())
+            gid = self._builtin_cache[name] = out.value
+        return gid
+
+    def define_matrix(self, name: str, m: np.ndarray, tol: float = 1e-10) -> int:
+        m = np.ascontiguousarray(np.asarray(m, dtype=np.complex128))
+        k = int(round(np.log2(m.shape[0])))
+        f = m.view(np.float64).reshape(-1)
+        out = C.c_int32()
+        self._chk(self.lib.qk_define_gate_matrix(self.h, name.encode(), k, f.ctypes.data_as(_DP), tol,
+                                                 C.byref(out)))
+        return out.value
+
+    def define_table(self, name: str, table: np.ndarray) -> int:
+        t = np.ascontiguousarray(np.asarray(table, dtype=np.uint64))
+        k = int(round(np.log2(len(t))))
+        out = C.c_int32()
+        self._chk(self.lib.qk_define_gate_table(self.h, name.encode(), k, t.ctypes.data_as(_U64P), C.byref(out)))
+        return out.value
+
+    def define_index(self, name: str, k: int, fn) -> int:
+        cb = INDEX_FN(lambda x, ctx: int(fn(int(x))))
+        out = C.c_int32()
+        self._chk(self.lib.qk_define_gate_index(self.h, name.encode(), k, cb, None, C.byref(out)))
+        return out.value
+
+    def define_affine(self, name: str, k: int, a: int, b: int) -> int:
+        out = C.c_int32()
+        self._chk(self.lib.qk_define_gate_affine(self.h, name.encode(), k, a, b, C.byref(out)))
+        return out.value
+
+    def apply(self, gate, targets: Sequence[int], controls: Sequence[int] = (),
+              conds: Sequence[Tuple[int, int]] = (), params: Sequence[float] = ()):
+        gid = self.builtin(gate) if isinstance(gate, str) else int(gate)
+        t, nt = _i32arr(targets)
+        c, nc = _i32arr(controls)
+        cd = (QkCond * max(1, len(conds)))(*[QkCond(int(a), int(b)) for a, b in conds])
+        p = (C.c_double * max(1, len(params)))(*[float(x) for x in params])
+        self._chk(self.lib.qk_apply_gate(self.h, gid, t, nt, c, nc, cd, len(conds), p, len(params)))
+
+    # -- measurement
+    def measure(self, qubit: int, cbit: int = -1, u: float = 0.0):
+        self._chk(self.lib.qk_measure(self.h, qubit, cbit, u))
+
+    def measure_dev(self, qubit: int, cbit: int, d_u_ptr: int):
+        self._chk(self.lib.qk_measure_dev(self.h, qubit, cbit, C.c_void_p(d_u_ptr)))
+
+    def postselect(self, qubit: int, cbit: int, outcome: int):
+        self._chk(self.lib.qk_postselect(self.h, qubit, cbit, outcome))
+
+    def read_cbits(self, n: Optional[int] = None) -> np.ndarray:
+        n = self.ncbits if n is None else n
+        out = np.zeros(max(1, n), dtype=np.uint8)
+        self._chk(self.lib.qk_read_cbits(self.h, out.ctypes.data_as(_U8P), n))
+        return out[:n]
+
+    def measure_log(self, count: int = 4096) -> np.ndarray:
+        buf = np.zeros(3 * max(1, count), dtype=np.float64)
+        w = C.c_int32()
+        self._chk(self.lib.qk_read_measure_log(self.h, buf.ctypes.data_as(_DP), count, C.byref(w)))
+        return buf[: 3 * w.value].reshape(-1, 3)
+
+    # -- readout
+    def state(self) -> np.ndarray:
+        out = np.empty(1 << self.n, dtype=self.np_dtype)
+        self._chk(self.lib.qk_get_state(self.h, C.c_void_p(out.ctypes.data), out.nbytes))
+        return out
+
+    def set_state(self, psi: np.ndarray):
+        a = np.ascontiguousarray(np.asarray(psi, dtype=self.np_dtype))
+        self._chk(self.lib.qk_set_state(self.h, C.c_void_p(a.ctypes.data), a.nbytes))
+
+    def state_ptr(self) -> Tuple[int, int]:
+        p = C.c_void_p()
+        nb = C.c_size_t()
+        self._chk(self.lib.qk_state_ptr(self.h, C.byref(p), C.byref(nb)))
+        return int(p.value or 0), int(nb.value)
+
+    def inner(self, other: "Sim") -> complex:
+        re, im = C.c_double(), C.c_double()
+        self._chk(self.lib.qk_inner_product(self.h, other.h, C.byref(re), C.byref(im)))
+        return complex(re.value, im.value)
+
+    def norm2(self) -> float:
+        out = C.c_double()
+        self._chk(self.lib.qk_norm2(self.h, C.byref(out)))
+        return out.value
+
+    # -- execution control
+    def set_fusion(self, k: int):
+        self._chk(self.lib.qk_set_fusion(self.h, k))
+
+    def flush(self):
+        self._chk(self.lib.qk_flush(self.h))
+
+    def sync(self):
+        self._chk(self.lib.qk_sync(self.h))
+
+    def stats(self):
+        a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
+        self._chk(self.lib.qk_stats(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return {"sweeps": a.value, "fused_blocks": b.value, "fused_gates": c.value}

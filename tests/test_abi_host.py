@@ -1,0 +1,134 @@
+"""Host-side checks of the C ABI: the library loads, exports every entry point
+that include/qk.h declares, and rejects bad arguments before any device work
+(so these run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import paper_1908_07187_amd as qkpkg
+from paper_1908_07187_amd import qk
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"^(?:qk_status|const char\*)\s+(qk_\w+)\s*\(", txt, re.M))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = qk.load()
+    declared = _declared_symbols()
+    assert len(declared) >= 20
+    missing = [n for n in declared if not hasattr(lib, n)]
+    assert not missing, missing
+    # the binding declares a signature for each of them
+    assert declared <= set(qk.SIGNATURES), declared - set(qk.SIGNATURES)
+
+
+def _sim_nogpu(dtype=qk.QK_C128):
+    lib = qk.load()
+    h = C.c_void_p()
+    assert lib.qk_create(dtype, None, None, C.byref(h)) == 0
+    return lib, h
+
+
+def test_create_rejects_bad_dtype():
+    lib = qk.load()
+    h = C.c_void_p()
+    assert lib.qk_create(7, None, None, C.byref(h)) == -1
+    assert b"dtype" in lib.qk_last_error(None)
+
+
+def test_builtin_names():
+    lib = qk.load()
+    out = C.c_int32()
+    for name, gid in qk.BUILTINS.items():
+        assert lib.qk_gate_builtin(name.encode(), C.byref(out)) == 0 and out.value == gid
+    for alias, gid in [("sigmax", 2), ("Hadamard", 1), ("CNOT", 2)]:
+        assert lib.qk_gate_builtin(alias.encode(), C.byref(out)) == 0 and out.value == gid
+    assert lib.qk_gate_builtin(b"NOPE", C.byref(out)) == -1
+
+
+def test_define_matrix_rejects_non_unitary():
+    lib, h = _sim_nogpu()
+    m = np.array([[1, 0], [0, 1.001]], dtype=np.complex128)
+    f = m.view(np.float64).reshape(-1)
+    out = C.c_int32()
+    st = lib.qk_define_gate_matrix(h, b"bad", 1, f.ctypes.data_as(qk._DP), 1e-10, C.byref(out))
+    assert st == -2
+    assert b"not unitary" in lib.qk_last_error(h)
+    assert lib.qk_define_gate_matrix(h, b"bad", 11, f.ctypes.data_as(qk._DP), 1e-10, C.byref(out)) == -1
+    lib.qk_destroy(h)
+
+
+def test_define_permutations_reject_non_bijections():
+    lib, h = _sim_nogpu()
+    out = C.c_int32()
+    t = np.array([0, 1, 1, 3], dtype=np.uint64)
+    assert lib.qk_define_gate_table(h, b"p", 2, t.ctypes.data_as(qk._U64P), C.byref(out)) == -3
+    t = np.array([0, 1, 2, 4], dtype=np.uint64)   # value out of range
+    assert lib.qk_define_gate_table(h, b"p", 2, t.ctypes.data_as(qk._U64P), C.byref(out)) == -3
+    cb = qk.INDEX_FN(lambda x, ctx: x // 2)
+    assert lib.qk_define_gate_index(h, b"f", 3, cb, None, C.byref(out)) == -3
+    assert lib.qk_define_gate_affine(h, b"a", 8, 6, 1, C.byref(out)) == -3    # a even
+    assert lib.qk_define_gate_affine(h, b"a", 33, 5, 1, C.byref(out)) == -1   # k too large
+    lib.qk_destroy(h)
+
+
+def test_apply_and_measure_argument_checks():
+    lib, h = _sim_nogpu()
+    t = (C.c_int32 * 1)(0)
+    p = (C.c_double * 1)(0.5)
+    # no qubits yet: any index is out of range
+    assert lib.qk_apply_gate(h, 1, t, 1, None, 0, None, 0, None, 0) == -1
+    assert b"out of range" in lib.qk_last_error(h)
+    assert lib.qk_apply_gate(h, 999, t, 1, None, 0, None, 0, None, 0) == -1     # unknown gate
+    assert lib.qk_apply_gate(h, 9, t, 1, None, 0, None, 0, None, 0) == -1       # RX needs a param
+    assert lib.qk_apply_gate(h, 1, t, 1, None, 0, None, 0, p, 1) == -1          # H takes none
+    assert lib.qk_apply_gate(h, 13, t, 1, None, 0, None, 0, p, 1) == -1         # CPHASE needs 2 targets
+    assert lib.qk_measure(h, 0, -1, 0.5) == -1
+    assert lib.qk_set_fusion(h, 7) == -1 and lib.qk_set_fusion(h, 1) == -1
+    assert lib.qk_set_fusion(h, 4) == 0 and lib.qk_set_fusion(h, 0) == 0
+    n = C.c_int32()
+    assert lib.qk_num_qubits(h, C.byref(n)) == 0 and n.value == 0
+    assert lib.qk_destroy(h) == 0
+
+
+def test_allocator_failure_is_reported_not_fatal():
+    """An injected allocator that returns NULL makes qk_add_qubits fail with QK_E_OOM."""
+    lib = qk.load()
+    calls = []
+
+    def alloc(nbytes, stream, ctx):
+        calls.append(nbytes)
+        return None
+
+    def free(ptr, nbytes, stream, ctx):
+        pass
+
+    a = qk.QkAllocator(qk.ALLOC_FN(alloc), qk.FREE_FN(free), None)
+    h = C.c_void_p()
+    assert lib.qk_create(qk.QK_C64, C.byref(a), None, C.byref(h)) == 0
+    assert lib.qk_add_qubits(h, 30, None) == -4
+    assert calls and calls[0] == (1 << 30) * 8
+    assert b"30 qubits" in lib.qk_last_error(h)
+    assert lib.qk_add_qubits(h, 41, None) == -1     # beyond the qubit limit, checked first
+    assert lib.qk_destroy(h) == 0
+
+
+def test_status_strings():
+    lib = qk.load()
+    for st in range(-7, 1):
+        assert lib.qk_status_string(st)
+
+
+def test_package_exposes_runner():
+    assert hasattr(qkpkg, "run_circuit") and hasattr(qkpkg, "Sim")
