@@ -229,6 +229,22 @@ qk_status qk_flush(qk_sim sim);
 /* Flush, wait for all work of the simulator, report latched errors. */
 qk_status qk_sync(qk_sim sim);
 
+/* Launch-shape knobs (results never depend on them).  Keys:
+ *   "nt"          0: regular loads/stores, 1 (default): non-temporal when a
+ *                 sweep's accesses cover whole cache lines, 2: always;
+ *   "lane_bfly"   1 (default): targets below bit 6 use the cross-lane
+ *                 butterfly, 0: the strided one;
+ *   "sweep_items" amplitude pairs per thread of the strided butterfly and
+ *                 swap sweeps (1 default, 2, 4);
+ *   "diag_items"  amplitudes per thread of diagonal and phase sweeps
+ *                 (1, 2, 4; default 1 for complex128, 2 for complex64);
+ *   "lane_items"  64-amplitude segments per wave of the cross-lane
+ *                 butterfly (1, 2, 4; default 1 for complex128, 2 for complex64);
+ *   "mfma_waves"  waves per compute unit for matrix-core sweeps (4..32).
+ * QK_E_ARG for an unknown key or value. */
+qk_status qk_set_tuning(qk_sim sim, const char* key, int32_t value);
+qk_status qk_get_tuning(qk_sim sim, const char* key, int32_t* value);
+
 qk_status qk_num_qubits(qk_sim sim, int32_t* n);
 
 /* Counters since creation: sweeps launched (state passes), fused blocks,

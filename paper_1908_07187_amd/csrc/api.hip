@@ -76,7 +76,7 @@ struct qk_sim_s {
   std::vector<UserGate*> ugates;
   int fuse_k = 0;
   std::vector<GateDesc> pending;
-  int waves_per_cu = 8;
+  Tuning tune;
   int64_t sweeps = 0, fused_blocks = 0, fused_gates = 0;
   std::string err;
   qk_status latched = QK_OK;
@@ -308,6 +308,7 @@ Launch make_launch(qk_sim s, const std::vector<qk_cond>& conds) {
   L.c64 = s->c64;
   L.psi = s->state.p;
   L.cond = make_cond(s, conds);
+  L.tune = s->tune;
   return L;
 }
 
@@ -338,7 +339,7 @@ qk_status run_dense(qk_sim s, const std::vector<int>& targets, const std::vector
   }
   if (mfma_supported(s->n, k, (int)controls.size(), s->c64))
     return check_launch(
-        s, launch_dense_mfma(L, targets.data(), k, controls.data(), (int)controls.size(), dmat, s->waves_per_cu),
+        s, launch_dense_mfma(L, targets.data(), k, controls.data(), (int)controls.size(), dmat, s->tune.mfma_waves),
         "dense (matrix cores)");
   return check_launch(s, launch_dense_generic(L, targets.data(), k, controls.data(), (int)controls.size(), dmat),
                       "dense");
@@ -538,6 +539,10 @@ qk_status qk_create(qk_dtype dtype, const qk_allocator* alloc, void* hip_stream,
     s->has_alloc = true;
   }
   s->stream = (hipStream_t)hip_stream;
+  if (s->c64) {
+    s->tune.diag_items = 2;
+    s->tune.lane_items = 2;
+  }
   *out = s;
   return QK_OK;
 }
@@ -979,6 +984,45 @@ qk_status qk_sync(qk_sim s) {
   st = sync_stream(s);
   if (st == QK_OK) s->arena.used = 0;
   return st;
+}
+
+qk_status qk_set_tuning(qk_sim s, const char* key, int32_t value) {
+  if (!s || !key) return fail(s, QK_E_ARG, "NULL argument");
+  const std::string k = key;
+  if (k == "nt") {
+    if (value < 0 || value > 2) return fail(s, QK_E_ARG, "nt must be 0, 1 or 2");
+    s->tune.nt = value;
+  } else if (k == "lane_bfly") {
+    s->tune.lane_bfly = value != 0;
+  } else if (k == "sweep_items") {
+    if (value != 1 && value != 2 && value != 4) return fail(s, QK_E_ARG, "sweep_items must be 1, 2 or 4");
+    s->tune.sweep_items = value;
+  } else if (k == "diag_items") {
+    if (value != 1 && value != 2 && value != 4) return fail(s, QK_E_ARG, "diag_items must be 1, 2 or 4");
+    s->tune.diag_items = value;
+  } else if (k == "lane_items") {
+    if (value != 1 && value != 2 && value != 4) return fail(s, QK_E_ARG, "lane_items must be 1, 2 or 4");
+    s->tune.lane_items = value;
+  } else if (k == "mfma_waves") {
+    if (value < 4 || value > 32 || value % 4) return fail(s, QK_E_ARG, "mfma_waves must be 4..32, a multiple of 4");
+    s->tune.mfma_waves = value;
+  } else {
+    return fail(s, QK_E_ARG, "unknown tuning key " + k);
+  }
+  return QK_OK;
+}
+
+qk_status qk_get_tuning(qk_sim s, const char* key, int32_t* value) {
+  if (!s || !key || !value) return fail(s, QK_E_ARG, "NULL argument");
+  const std::string k = key;
+  if (k == "nt") *value = s->tune.nt;
+  else if (k == "lane_bfly") *value = s->tune.lane_bfly;
+  else if (k == "sweep_items") *value = s->tune.sweep_items;
+  else if (k == "lane_items") *value = s->tune.lane_items;
+  else if (k == "diag_items") *value = s->tune.diag_items;
+  else if (k == "mfma_waves") *value = s->tune.mfma_waves;
+  else return fail(s, QK_E_ARG, "unknown tuning key " + k);
+  return QK_OK;
 }
 
 qk_status qk_num_qubits(qk_sim s, int32_t* n) {

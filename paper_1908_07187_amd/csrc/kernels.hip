@@ -110,58 +110,205 @@ hipError_t launch_copy(void* dst, const void* src, uint64_t count, bool c64, hip
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- load / store policy
+// A gate sweep touches each byte once.  When a wave's accesses cover whole
+// cache lines, loads and stores are issued non-temporal (streaming) so the
+// sweep does not churn the caches; when the two halves of a line are read by
+// different instructions (target or control on a low bit), the regular policy
+// lets the second read hit in cache.
+
+template <typename R> struct EV;
+template <> struct EV<float> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct EV<double> { typedef double T __attribute__((ext_vector_type(2))); };
+template <typename R> using CV = typename EV<R>::T;
+
+template <bool NT, typename T>
+__device__ __forceinline__ T ld(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+// Non-temporal only when every run of consecutive amplitudes an instruction
+// touches is at least 256 bytes long: the lowest zero-inserted bit sets it.
+static bool use_nt(const Launch& L, int lowest_special) {
+  if (L.tune.nt == 0) return false;
+  if (L.tune.nt == 2) return true;
+  return lowest_special >= (L.c64 ? 5 : 4);
+}
+static int lowest(const int* a, int na, const int* b, int nb, int dflt) {
+  int m = dflt;
+  for (int i = 0; i < na; ++i) m = std::min(m, a[i]);
+  for (int i = 0; i < nb; ++i) m = std::min(m, b[i]);
+  return m;
+}
+
 // ---------------------------------------------------------------- 2x2 butterfly
 // For every index pair (i, i | 2^t) with bit t of i = 0 and all control bits
-// 1: [a_i, a_{i+2^t}] <- U [a_i, a_{i+2^t}].  Each thread owns ITEMS pairs,
-// strided by the block size so every load instruction of a wave is coalesced;
-// all loads are issued before any store.
+// 1: [a_i, a_{i+2^t}] <- U [a_i, a_{i+2^t}].
+//
+// k_butterfly: each thread owns ITEMS pairs, strided by the block size so
+// every load instruction of a wave is coalesced; all loads are issued before
+// any store.  Controls at or above bit 4 (complex128) / 5 (complex64) are
+// skipped in the enumeration (only the controlled subspace is touched);
+// lower controls would leave partial cache lines, so they are evaluated as a
+// per-pair predicate of a full sweep instead.  (The CTRL flag only separates controlled launches, e.g. CNOT,
+// into their own kernel symbol for profiling.)
 
-template <typename R, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_butterfly(V2<R>* __restrict__ psi, uint64_t npairs, Special sp,
-                                                      uint64_t cmask, uint64_t tbit, Mat2 u, CondArgs cond) {
+template <typename R, int ITEMS, bool NT, bool CTRL>
+__global__ __launch_bounds__(kBlock) void k_butterfly(CV<R>* __restrict__ psi, uint64_t npairs, Special sp,
+                                                      uint64_t cmask, uint64_t pmask, uint64_t tbit, Mat2 u,
+                                                      CondArgs cond) {
   if (!conds_ok(cond)) return;
   const R a0 = (R)u.v[0], b0 = (R)u.v[1], a1 = (R)u.v[2], b1 = (R)u.v[3];
   const R a2 = (R)u.v[4], b2 = (R)u.v[5], a3 = (R)u.v[6], b3 = (R)u.v[7];
   const uint64_t j0 = (uint64_t)blockIdx.x * (kBlock * ITEMS) + threadIdx.x;
-  V2<R> x[ITEMS], y[ITEMS];
+  CV<R> x[ITEMS], y[ITEMS];
   uint64_t idx[ITEMS];
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const uint64_t j = j0 + (uint64_t)k * kBlock;
     idx[k] = insert_zeros(j, sp) | cmask;
     if (j < npairs) {
-      x[k] = psi[idx[k]];
-      y[k] = psi[idx[k] | tbit];
+      x[k] = ld<NT>(psi + idx[k]);
+      y[k] = ld<NT>(psi + (idx[k] | tbit));
     }
   }
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     const uint64_t j = j0 + (uint64_t)k * kBlock;
     if (j < npairs) {
-      const V2<R> p = x[k], q = y[k];
-      V2<R> r0, r1;
+      const CV<R> p = x[k], q = y[k];
+      CV<R> r0, r1;
       r0.x = a0 * p.x - b0 * p.y + a1 * q.x - b1 * q.y;
       r0.y = a0 * p.y + b0 * p.x + a1 * q.y + b1 * q.x;
       r1.x = a2 * p.x - b2 * p.y + a3 * q.x - b3 * q.y;
       r1.y = a2 * p.y + b2 * p.x + a3 * q.y + b3 * q.x;
-      psi[idx[k]] = r0;
-      psi[idx[k] | tbit] = r1;
+      // controls on low bits are a predicate: pairs outside the controlled
+      // subspace are written back unchanged, so every line is written whole
+      const bool act = (idx[k] & pmask) == pmask;
+      st<NT>(psi + idx[k], act ? r0 : p);
+      st<NT>(psi + (idx[k] | tbit), act ? r1 : q);
     }
   }
 }
 
-hipError_t launch_butterfly(const Launch& L, int t, const int* controls, int nc, const Mat2& u) {
-  Special sp = make_special(&t, 1, controls, nc);
-  const uint64_t npairs = 1ull << (L.n - 1 - nc);
-  const uint64_t cmask = mask_of(controls, nc), tbit = 1ull << t;
-  constexpr int IT = 4;
+// k_butterfly_lane: target bit t < 6.  Lane l of a wave holds amplitude
+// 64 s + l of segment s, so every load and store is one fully coalesced,
+// contiguous run; the pair partner (lane l ^ 2^t) arrives by a cross-lane
+// exchange.  Controls at bits >= 6 select the segments; controls below 6
+// become a per-lane predicate on the store.
+
+template <typename R, int ITEMS, bool NT>
+__global__ __launch_bounds__(kBlock) void k_butterfly_lane(CV<R>* __restrict__ psi, uint64_t nseg, Special sp,
+                                                           uint64_t cmask_hi, uint32_t cmask_lo, int t, Mat2 u,
+                                                           CondArgs cond) {
+  if (!conds_ok(cond)) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t s0 = ((uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6)) * ITEMS;
+  if (s0 >= nseg) return;   // uniform per wave
+  const bool up = (lane >> t) & 1;
+  const bool act = ((uint32_t)lane & cmask_lo) == cmask_lo;
+  // lower lane: u00 a + u01 b; upper lane: u11 a + u10 b (b = partner)
+  const R sr = (R)(up ? u.v[6] : u.v[0]), si = (R)(up ? u.v[7] : u.v[1]);
+  const R orr = (R)(up ? u.v[4] : u.v[2]), oi = (R)(up ? u.v[5] : u.v[3]);
+  const int mask = 1 << t;
+  CV<R> a[ITEMS];
+  uint64_t addr[ITEMS];
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    addr[k] = ((insert_zeros(s0 + k, sp) << 6) | cmask_hi) + (uint64_t)lane;
+    a[k] = ld<NT>(psi + addr[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < ITEMS; ++k) {
+    const R bx = __shfl_xor(a[k].x, mask, 64);
+    const R by = __shfl_xor(a[k].y, mask, 64);
+    CV<R> r;
+    r.x = sr * a[k].x - si * a[k].y + orr * bx - oi * by;
+    r.y = sr * a[k].y + si * a[k].x + orr * by + oi * bx;
+    if (act) st<NT>(psi + addr[k], r);
+  }
+}
+
+template <typename R, int IT, bool NT, bool CTRL>
+static void launch_bfly_generic(const Launch& L, uint64_t npairs, const Special& sp, uint64_t cmask, uint64_t pmask,
+                                uint64_t tbit, const Mat2& u) {
   const unsigned g = grid_for(npairs, kBlock * IT);
-  if (L.c64)
-    hipLaunchKernelGGL((k_butterfly<float, IT>), dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi, npairs, sp,
-                       cmask, tbit, u, L.cond);
-  else
-    hipLaunchKernelGGL((k_butterfly<double, IT>), dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi, npairs, sp,
-                       cmask, tbit, u, L.cond);
+  hipLaunchKernelGGL((k_butterfly<R, IT, NT, CTRL>), dim3(g), dim3(kBlock), 0, L.stream, (CV<R>*)L.psi, npairs, sp,
+                     cmask, pmask, tbit, u, L.cond);
+}
+
+template <typename R, bool NT, bool CTRL>
+static void launch_bfly_items(const Launch& L, uint64_t npairs, const Special& sp, uint64_t cmask, uint64_t pmask,
+                              uint64_t tbit, const Mat2& u) {
+  switch (L.tune.sweep_items) {
+    case 2: launch_bfly_generic<R, 2, NT, CTRL>(L, npairs, sp, cmask, pmask, tbit, u); break;
+    case 4: launch_bfly_generic<R, 4, NT, CTRL>(L, npairs, sp, cmask, pmask, tbit, u); break;
+    default: launch_bfly_generic<R, 1, NT, CTRL>(L, npairs, sp, cmask, pmask, tbit, u); break;
+  }
+}
+
+template <typename R, int IT, bool NT>
+static void launch_lane(const Launch& L, uint64_t nseg, const Special& sp, uint64_t cmask_hi, uint32_t cmask_lo, int t,
+                        const Mat2& u) {
+  const unsigned g = grid_for(nseg / IT, kBlock / 64);
+  hipLaunchKernelGGL((k_butterfly_lane<R, IT, NT>), dim3(g), dim3(kBlock), 0, L.stream, (CV<R>*)L.psi, nseg, sp,
+                     cmask_hi, cmask_lo, t, u, L.cond);
+}
+
+template <typename R>
+static void launch_bfly_typed(const Launch& L, int t, const int* controls, int nc, const Mat2& u) {
+  if (L.tune.lane_bfly && t < 6 && L.n >= 6) {
+    std::vector<int> hi;
+    uint64_t cmask_hi = 0;
+    uint32_t cmask_lo = 0;
+    for (int i = 0; i < nc; ++i) {
+      if (controls[i] >= 6) {
+        hi.push_back(controls[i] - 6);
+        cmask_hi |= 1ull << controls[i];
+      } else {
+        cmask_lo |= 1u << controls[i];
+      }
+    }
+    Special sp = make_special(hi.data(), (int)hi.size(), nullptr, 0);
+    const uint64_t nseg = 1ull << (L.n - 6 - (int)hi.size());
+    const bool nt = L.tune.nt != 0;
+    const int it = (int)std::min<uint64_t>((uint64_t)L.tune.lane_items, nseg);
+    if (it >= 4) { if (nt) launch_lane<R, 4, true>(L, nseg, sp, cmask_hi, cmask_lo, t, u); else launch_lane<R, 4, false>(L, nseg, sp, cmask_hi, cmask_lo, t, u); }
+    else if (it == 2) { if (nt) launch_lane<R, 2, true>(L, nseg, sp, cmask_hi, cmask_lo, t, u); else launch_lane<R, 2, false>(L, nseg, sp, cmask_hi, cmask_lo, t, u); }
+    else { if (nt) launch_lane<R, 1, true>(L, nseg, sp, cmask_hi, cmask_lo, t, u); else launch_lane<R, 1, false>(L, nseg, sp, cmask_hi, cmask_lo, t, u); }
+    return;
+  }
+  // controls below the whole-line threshold become a predicate (when sweeps are non-temporal)
+  const int thr = L.c64 ? 5 : 4;
+  std::vector<int> en;
+  uint64_t pmask = 0;
+  for (int i = 0; i < nc; ++i) {
+    if (L.tune.nt != 0 && controls[i] < thr && t >= thr) pmask |= 1ull << controls[i];
+    else en.push_back(controls[i]);
+  }
+  const int ne = (int)en.size();
+  Special sp = make_special(&t, 1, en.data(), ne);
+  const uint64_t npairs = 1ull << (L.n - 1 - ne);
+  const uint64_t cmask = mask_of(en.data(), ne), tbit = 1ull << t;
+  const bool nt = use_nt(L, lowest(&t, 1, en.data(), ne, 64));
+  if (nc == 0) {
+    if (nt) launch_bfly_items<R, true, false>(L, npairs, sp, cmask, pmask, tbit, u);
+    else launch_bfly_items<R, false, false>(L, npairs, sp, cmask, pmask, tbit, u);
+  } else {
+    if (nt) launch_bfly_items<R, true, true>(L, npairs, sp, cmask, pmask, tbit, u);
+    else launch_bfly_items<R, false, true>(L, npairs, sp, cmask, pmask, tbit, u);
+  }
+}
+
+hipError_t launch_butterfly(const Launch& L, int t, const int* controls, int nc, const Mat2& u) {
+  if (L.c64) launch_bfly_typed<float>(L, t, controls, nc, u);
+  else launch_bfly_typed<double>(L, t, controls, nc, u);
   return hipGetLastError();
 }
 
@@ -173,18 +320,18 @@ struct Pos8 {
   int p[8];
 };
 
-template <typename R, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_diag(V2<R>* __restrict__ psi, uint64_t nitems, Special sp, uint64_t cmask,
+template <typename R, int ITEMS, bool NT>
+__global__ __launch_bounds__(kBlock) void k_diag(CV<R>* __restrict__ psi, uint64_t nitems, Special sp, uint64_t cmask,
                                                  int k, Pos8 tp, Diag64 d, CondArgs cond) {
   if (!conds_ok(cond)) return;
   const uint64_t j0 = (uint64_t)blockIdx.x * (kBlock * ITEMS) + threadIdx.x;
-  V2<R> x[ITEMS];
+  CV<R> x[ITEMS];
   uint64_t idx[ITEMS];
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const uint64_t j = j0 + (uint64_t)it * kBlock;
     idx[it] = insert_zeros(j, sp) | cmask;
-    if (j < nitems) x[it] = psi[idx[it]];
+    if (j < nitems) x[it] = ld<NT>(psi + idx[it]);
   }
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
@@ -192,27 +339,59 @@ __global__ __launch_bounds__(kBlock) void k_diag(V2<R>* __restrict__ psi, uint64
     if (j < nitems) {
       const int m = (int)extract(idx[it], tp.p, k);
       const R dr = (R)d.v[2 * m], di = (R)d.v[2 * m + 1];
-      const V2<R> p = x[it];
-      psi[idx[it]] = V2<R>{dr * p.x - di * p.y, dr * p.y + di * p.x};
+      const CV<R> p = x[it];
+      CV<R> r;
+      r.x = dr * p.x - di * p.y;
+      r.y = dr * p.y + di * p.x;
+      st<NT>(psi + idx[it], r);
     }
   }
 }
 
-hipError_t launch_diag(const Launch& L, const int* targets, int k, const int* controls, int nc, const Diag64& d) {
+template <typename R, bool NT>
+static void launch_diag_items(const Launch& L, unsigned items, uint64_t nitems, const Special& sp, uint64_t cmask,
+                              int k, const Pos8& tp, const Diag64& d) {
+  switch (items) {
+    case 2: hipLaunchKernelGGL((k_diag<R, 2, NT>), dim3(grid_for(nitems, kBlock * 2)), dim3(kBlock), 0, L.stream,
+                               (CV<R>*)L.psi, nitems, sp, cmask, k, tp, d, L.cond); break;
+    case 4: hipLaunchKernelGGL((k_diag<R, 4, NT>), dim3(grid_for(nitems, kBlock * 4)), dim3(kBlock), 0, L.stream,
+                               (CV<R>*)L.psi, nitems, sp, cmask, k, tp, d, L.cond); break;
+    default: hipLaunchKernelGGL((k_diag<R, 1, NT>), dim3(grid_for(nitems, kBlock)), dim3(kBlock), 0, L.stream,
+                                (CV<R>*)L.psi, nitems, sp, cmask, k, tp, d, L.cond); break;
+  }
+}
+
+hipError_t launch_diag(const Launch& L, const int* targets, int k, const int* controls, int nc, const Diag64& d_in) {
   if (k > 6) return hipErrorInvalidValue;
-  Special sp = make_special(controls, nc, nullptr, 0);
-  const uint64_t nitems = 1ull << (L.n - nc);
+  // Controls below the whole-line threshold join the diagonal (entry 1 where
+  // such a control is 0), so the sweep covers whole cache lines.
+  const int thr = L.c64 ? 5 : 4;
+  std::vector<int> tg(targets, targets + k), en, low;
+  for (int i = 0; i < nc; ++i) {
+    if (L.tune.nt != 0 && controls[i] < thr && k + (int)low.size() < 6) low.push_back(controls[i]);
+    else en.push_back(controls[i]);
+  }
+  Diag64 d = d_in;
+  if (!low.empty()) {
+    const int kk = k + (int)low.size();
+    const int lowall = (1 << low.size()) - 1;
+    for (int m = 0; m < (1 << kk); ++m) {
+      const int mt = m & ((1 << k) - 1), ml = m >> k;
+      d.v[2 * m] = ml == lowall ? d_in.v[2 * mt] : 1.0;
+      d.v[2 * m + 1] = ml == lowall ? d_in.v[2 * mt + 1] : 0.0;
+    }
+    for (int c : low) tg.push_back(c);
+  }
+  const int kk = (int)tg.size(), ne = (int)en.size();
+  Special sp = make_special(en.data(), ne, nullptr, 0);
+  const uint64_t nitems = 1ull << (L.n - ne);
   Pos8 tp{};
-  for (int j = 0; j < k; ++j) tp.p[j] = targets[j];
-  constexpr int IT = 4;
-  const unsigned g = grid_for(nitems, kBlock * IT);
-  const uint64_t cmask = mask_of(controls, nc);
-  if (L.c64)
-    hipLaunchKernelGGL((k_diag<float, IT>), dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi, nitems, sp, cmask, k,
-                       tp, d, L.cond);
-  else
-    hipLaunchKernelGGL((k_diag<double, IT>), dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi, nitems, sp, cmask,
-                       k, tp, d, L.cond);
+  for (int j = 0; j < kk; ++j) tp.p[j] = tg[j];
+  const uint64_t cmask = mask_of(en.data(), ne);
+  const bool nt = use_nt(L, lowest(en.data(), ne, nullptr, 0, 64));
+  const unsigned items = (unsigned)L.tune.diag_items;
+  if (L.c64) { if (nt) launch_diag_items<float, true>(L, items, nitems, sp, cmask, kk, tp, d); else launch_diag_items<float, false>(L, items, nitems, sp, cmask, kk, tp, d); }
+  else { if (nt) launch_diag_items<double, true>(L, items, nitems, sp, cmask, kk, tp, d); else launch_diag_items<double, false>(L, items, nitems, sp, cmask, kk, tp, d); }
   return hipGetLastError();
 }
 
@@ -220,26 +399,29 @@ hipError_t launch_diag(const Launch& L, const int* targets, int k, const int* co
 // a_i <- z a_i where every bit of `bits` is 1 (PHASE, CPHASE, S, T, Z and
 // their controlled forms touch only this 2^(n - |bits|) subspace).
 
-template <typename R, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_phase_all1(V2<R>* __restrict__ psi, uint64_t nitems, Special sp,
+template <typename R, int ITEMS, bool NT>
+__global__ __launch_bounds__(kBlock) void k_phase_all1(CV<R>* __restrict__ psi, uint64_t nitems, Special sp,
                                                        uint64_t mask, double zr_, double zi_, CondArgs cond) {
   if (!conds_ok(cond)) return;
   const R zr = (R)zr_, zi = (R)zi_;
   const uint64_t j0 = (uint64_t)blockIdx.x * (kBlock * ITEMS) + threadIdx.x;
-  V2<R> x[ITEMS];
+  CV<R> x[ITEMS];
   uint64_t idx[ITEMS];
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const uint64_t j = j0 + (uint64_t)it * kBlock;
     idx[it] = insert_zeros(j, sp) | mask;
-    if (j < nitems) x[it] = psi[idx[it]];
+    if (j < nitems) x[it] = ld<NT>(psi + idx[it]);
   }
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const uint64_t j = j0 + (uint64_t)it * kBlock;
     if (j < nitems) {
-      const V2<R> p = x[it];
-      psi[idx[it]] = V2<R>{zr * p.x - zi * p.y, zr * p.y + zi * p.x};
+      const CV<R> p = x[it];
+      CV<R> r;
+      r.x = zr * p.x - zi * p.y;
+      r.y = zr * p.y + zi * p.x;
+      st<NT>(psi + idx[it], r);
     }
   }
 }
@@ -248,14 +430,17 @@ hipError_t launch_phase_all1(const Launch& L, const int* bits, int nb, double zr
   Special sp = make_special(bits, nb, nullptr, 0);
   const uint64_t nitems = 1ull << (L.n - nb);
   const uint64_t mask = mask_of(bits, nb);
-  constexpr int IT = 4;
-  const unsigned g = grid_for(nitems, kBlock * IT);
-  if (L.c64)
-    hipLaunchKernelGGL((k_phase_all1<float, IT>), dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi, nitems, sp, mask,
-                       zr, zi, L.cond);
-  else
-    hipLaunchKernelGGL((k_phase_all1<double, IT>), dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi, nitems, sp,
-                       mask, zr, zi, L.cond);
+  const bool nt = use_nt(L, lowest(bits, nb, nullptr, 0, 64));
+  const int it = L.tune.diag_items;
+#define QK_PH(R, IT, NT)                                                                                             \
+  hipLaunchKernelGGL((k_phase_all1<R, IT, NT>), dim3(grid_for(nitems, kBlock * IT)), dim3(kBlock), 0, L.stream,   \
+                     (CV<R>*)L.psi, nitems, sp, mask, zr, zi, L.cond)
+#define QK_PH_IT(R, NT) \
+  do { if (it == 2) QK_PH(R, 2, NT); else if (it == 4) QK_PH(R, 4, NT); else QK_PH(R, 1, NT); } while (0)
+  if (L.c64) { if (nt) QK_PH_IT(float, true); else QK_PH_IT(float, false); }
+  else { if (nt) QK_PH_IT(double, true); else QK_PH_IT(double, false); }
+#undef QK_PH_IT
+#undef QK_PH
   return hipGetLastError();
 }
 
@@ -263,28 +448,28 @@ hipError_t launch_phase_all1(const Launch& L, const int* bits, int nb, double zr
 // Exchanges a_{base|2^a} and a_{base|2^b} for every base with both bits 0 and
 // all control bits 1 (touches 2^(n-1-c) amplitudes).
 
-template <typename R, int ITEMS>
-__global__ __launch_bounds__(kBlock) void k_swap(V2<R>* __restrict__ psi, uint64_t nitems, Special sp, uint64_t cmask,
+template <typename R, int ITEMS, bool NT>
+__global__ __launch_bounds__(kBlock) void k_swap(CV<R>* __restrict__ psi, uint64_t nitems, Special sp, uint64_t cmask,
                                                  uint64_t abit, uint64_t bbit, CondArgs cond) {
   if (!conds_ok(cond)) return;
   const uint64_t j0 = (uint64_t)blockIdx.x * (kBlock * ITEMS) + threadIdx.x;
-  V2<R> x[ITEMS], y[ITEMS];
+  CV<R> x[ITEMS], y[ITEMS];
   uint64_t idx[ITEMS];
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const uint64_t j = j0 + (uint64_t)it * kBlock;
     idx[it] = insert_zeros(j, sp) | cmask;
     if (j < nitems) {
-      x[it] = psi[idx[it] | abit];
-      y[it] = psi[idx[it] | bbit];
+      x[it] = ld<NT>(psi + (idx[it] | abit));
+      y[it] = ld<NT>(psi + (idx[it] | bbit));
     }
   }
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const uint64_t j = j0 + (uint64_t)it * kBlock;
     if (j < nitems) {
-      psi[idx[it] | abit] = y[it];
-      psi[idx[it] | bbit] = x[it];
+      st<NT>(psi + (idx[it] | abit), y[it]);
+      st<NT>(psi + (idx[it] | bbit), x[it]);
     }
   }
 }
@@ -293,15 +478,18 @@ hipError_t launch_swap(const Launch& L, int a, int b, const int* controls, int n
   int ab[2] = {a, b};
   Special sp = make_special(ab, 2, controls, nc);
   const uint64_t nitems = 1ull << (L.n - 2 - nc);
-  constexpr int IT = 4;
-  const unsigned g = grid_for(nitems, kBlock * IT);
   const uint64_t cmask = mask_of(controls, nc);
-  if (L.c64)
-    hipLaunchKernelGGL((k_swap<float, IT>), dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi, nitems, sp, cmask,
-                       1ull << a, 1ull << b, L.cond);
-  else
-    hipLaunchKernelGGL((k_swap<double, IT>), dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi, nitems, sp, cmask,
-                       1ull << a, 1ull << b, L.cond);
+  const bool nt = use_nt(L, lowest(ab, 2, controls, nc, 64));
+  const int it = L.tune.sweep_items;
+#define QK_SW(R, IT, NT)                                                                                           \
+  hipLaunchKernelGGL((k_swap<R, IT, NT>), dim3(grid_for(nitems, kBlock * IT)), dim3(kBlock), 0, L.stream,       \
+                     (CV<R>*)L.psi, nitems, sp, cmask, 1ull << a, 1ull << b, L.cond)
+#define QK_SW_IT(R, NT) \
+  do { if (it == 2) QK_SW(R, 2, NT); else if (it == 4) QK_SW(R, 4, NT); else QK_SW(R, 1, NT); } while (0)
+  if (L.c64) { if (nt) QK_SW_IT(float, true); else QK_SW_IT(float, false); }
+  else { if (nt) QK_SW_IT(double, true); else QK_SW_IT(double, false); }
+#undef QK_SW_IT
+#undef QK_SW
   return hipGetLastError();
 }
 

@@ -69,6 +69,8 @@ SIGNATURES = {
     "qk_flush": (_I32, [_P]),
     "qk_sync": (_I32, [_P]),
     "qk_num_qubits": (_I32, [_P, _I32P]),
+    "qk_set_tuning": (_I32, [_P, C.c_char_p, _I32]),
+    "qk_get_tuning": (_I32, [_P, C.c_char_p, _I32P]),
     "qk_stats": (_I32, [_P, _I64P, _I64P, _I64P]),
     "qk_last_error": (C.c_char_p, [_P]),
     "qk_status_string": (C.c_char_p, [_I32]),
@@ -305,6 +307,14 @@ class Sim:
 
     def sync(self):
         self._chk(self.lib.qk_sync(self.h))
+
+    def set_tuning(self, key: str, value: int):
+        self._chk(self.lib.qk_set_tuning(self.h, key.encode(), int(value)))
+
+    def get_tuning(self, key: str) -> int:
+        out = C.c_int32()
+        self._chk(self.lib.qk_get_tuning(self.h, key.encode(), C.byref(out)))
+        return out.value
 
     def stats(self):
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()

@@ -85,9 +85,12 @@ def _gate_id(sim: Sim, name: str, user_gates) -> int:
     return sim.builtin(name)
 
 
-def run_circuit(circuit, dtype: str = "c128", fusion: int = 0, sim: Optional[Sim] = None, stream=None) -> Sim:
+def run_circuit(circuit, dtype: str = "c128", fusion: int = 0, sim: Optional[Sim] = None, stream=None,
+                tuning: Optional[dict] = None) -> Sim:
     """Run ``circuit`` on a new (or the given) simulator; returns the Sim."""
     s = sim if sim is not None else Sim(dtype, stream=stream)
+    for key, val in (tuning or {}).items():
+        s.set_tuning(key, val)
     if fusion:
         s.set_fusion(fusion)
     Program(circuit).run(s)

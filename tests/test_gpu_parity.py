@@ -20,10 +20,10 @@ TOL128 = 1e-12
 TOL64 = 2e-5
 
 
-def _run_gpu(circ, dtype="c128", fusion=0):
+def _run_gpu(circ, dtype="c128", fusion=0, tuning=None):
     import paper_1908_07187_amd as qk
-    print(f"[gpu] {circ.label} dtype={dtype} fusion={fusion}", flush=True)
-    sim = qk.run_circuit(circ, dtype=dtype, fusion=fusion)
+    print(f"[gpu] {circ.label} dtype={dtype} fusion={fusion} tuning={tuning}", flush=True)
+    sim = qk.run_circuit(circ, dtype=dtype, fusion=fusion, tuning=tuning)
     st = sim.state()
     cb = sim.read_cbits()
     log = sim.measure_log()
@@ -222,3 +222,28 @@ def test_inner_product_and_norm():
     assert abs(ip - np.vdot(sa, sb)) <= 1e-12
     a.close()
     b.close()
+
+
+TUNINGS = [dict(nt=0, lane_bfly=0, sweep_items=1), dict(nt=0, lane_bfly=1, sweep_items=2, lane_items=2),
+           dict(nt=1, lane_bfly=1, sweep_items=4, lane_items=1), dict(nt=2, lane_bfly=0, sweep_items=2),
+           dict(nt=2, lane_bfly=1, sweep_items=1, mfma_waves=4), dict(nt=1, lane_bfly=0, sweep_items=4, mfma_waves=16),
+           dict(nt=1, lane_bfly=1, sweep_items=1, lane_items=4)]
+
+
+@pytest.mark.parametrize("tuning", TUNINGS, ids=[str(i) for i in range(len(TUNINGS))])
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_launch_shapes_do_not_change_results(tuning, dtype):
+    """Every launch-shape knob (load policy, lane butterfly, items per
+    thread, matrix-core waves) gives the oracle's state, on a circuit whose
+    gates hit every low and high target bit, with low and high controls."""
+    n = 13
+    c = W.random_mixed_circuit(n, 120, seed=77, max_k=3)
+    c.ops += [W.gate("H", [q]) for q in range(n)] + [W.gate("X", [q], controls=[(q + 3) % n]) for q in range(n)]
+    c.ops += [W.gate("RY", [q], controls=[(q + 1) % n, (q + 7) % n], params=(0.3 * q,)) for q in range(n)]
+    c.ops += [W.gate("RZ", [q], controls=[(q + 2) % n], params=(0.2 * q,)) for q in range(n)]
+    c.ops += [W.gate("RZZ", [q, (q + 5) % n], controls=[(q + 1) % n, (q + 9) % n], params=(0.1 * q,)) for q in range(n)]
+    ref, _, _ = oracle.run(c)
+    got, _, _ = _run_gpu(c, dtype, tuning=tuning)
+    _check(ref, got, dtype)
+    got, _, _ = _run_gpu(c, dtype, fusion=4, tuning=tuning)
+    _check(ref, got, dtype)
