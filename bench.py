@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--no-fused", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gates", type=int, default=16, help="gates of the circuit the oracle sample runs")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="run only a few strided-butterfly sweeps and a plain copy of known size (for PMC counters)")
     return ap.parse_args()
 
 
@@ -53,13 +55,30 @@ def count_updates(circ) -> int:
     return circ.amp_updates()
 
 
+# Kernel symbol each timed gate class launches (complex128, default tuning).
+K_DIAG = "qk::k_diag<double, 1, true>"
+K_BFLY = "qk::k_butterfly<double, 1, true, false>"
+K_LANE = "qk::k_butterfly_lane<double, 1, true>"
+
+
+def kernel_of(name, target, ncontrols):
+    """The sweep kernel an uncontrolled gate of this builtin runs (None: not timed)."""
+    if ncontrols:
+        return None
+    if name in ("RZ", "RZZ"):
+        return K_DIAG
+    if name in ("H", "RX", "RY"):
+        return K_LANE if target < 6 else K_BFLY
+    return None
+
+
 def run_c128_step(qk, prog, torch, timing):
-    """One pass of the circuit gate by gate; HIP events around every 2x2 butterfly."""
-    import ctypes as C
+    """One pass of the circuit gate by gate.  With ``timing`` (a dict), HIP
+    events on the simulator's stream bracket every gate whose kernel symbol is
+    known (kernel_of), collected per symbol."""
     sim = qk.Sim("c128")
     lib, h = sim.lib, sim.h
     stream = torch.cuda.current_stream()
-    circ = prog.circuit
     for it in prog.items:
         if it[0] == 0:
             sim.add_qubits(it[1])
@@ -68,18 +87,44 @@ def run_c128_step(qk, prog, torch, timing):
             raise RuntimeError("unexpected op in the benchmark circuit")
         name = it[1]
         gid = qk.BUILTINS[name]
-        dense1 = name in ("H", "RX", "RY") and it[5] == 0
-        if dense1 and timing is not None:
+        kname = kernel_of(name, it[2][0], it[5]) if timing is not None else None
+        if kname:
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
         st = lib.qk_apply_gate(h, gid, it[2], it[3], it[4], it[5], it[6], it[7], it[8], it[9])
         if st:
             sim._chk(st)
-        if dense1 and timing is not None:
+        if kname:
             e1.record(stream)
-            timing.append((e0, e1))
+            timing.setdefault(kname, []).append((e0, e1))
     return sim
+
+
+def kernels_only(qk, torch):
+    """A short program for hardware-counter runs on a 30-qubit complex128
+    state: strided-butterfly sweeps (targets 10, 17, 23, 29), diagonal sweeps
+    (RZ, RZZ), cross-lane butterflies (targets 1, 4), and one plain copy
+    kernel of known size (the 2^28-amplitude copy when a 28-qubit state grows
+    by one qubit: 4 GiB read, 4 GiB written)."""
+    s = qk.Sim("c128")
+    s.add_qubits(30)
+    for t in (10, 17, 23, 29):
+        s.apply("H", [t])
+    s.apply("RZ", [3], params=[0.3])
+    s.apply("RZZ", [5, 20], params=[0.4])
+    s.apply("H", [1])
+    s.apply("H", [4])
+    s.sync()
+    s.close()
+    c = qk.Sim("c128")
+    c.add_qubits(28)
+    c.add_qubits(1)
+    c.sync()
+    c.close()
+    torch.cuda.synchronize()
+    print(json.dumps({"kernels_only": True, "butterfly_bytes_per_launch": 2 * 16 * (1 << 30),
+                      "copy_bytes_each_way": 16 * (1 << 28)}), flush=True)
 
 
 def main():
@@ -95,6 +140,9 @@ def main():
     import paper_1908_07187_amd as qk
     import workloads as W
     qk.load(build_if_missing=True)
+    if args.kernels_only:
+        kernels_only(qk, torch)
+        return
 
     n, depth = args.qubits, args.depth
     circ = W.c2_random_rzz(n=n, depth=depth, seed=args.seed)
@@ -111,7 +159,7 @@ def main():
         s.close()
         print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
 
-    timing = []
+    timing = {}
     sims = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -125,21 +173,28 @@ def main():
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = updates * args.steps / (t1 - t0)
-    bfly_ms = [a.elapsed_time(b) for a, b in timing]
-    bfly_mean_ms = sum(bfly_ms) / len(bfly_ms)
-    bfly_bytes = 2 * 16 * (1 << n)
-    bfly_gbps = bfly_bytes / (bfly_mean_ms * 1e-3) / 1e9
-    print(f"[bench] c128 per-gate: {ms_per_step:.1f} ms/step, {value:.4e} amp-updates/s, "
-          f"butterfly {bfly_mean_ms:.3f} ms = {bfly_gbps:.0f} GB/s", file=sys.stderr, flush=True)
+    kernels = []
+    for kname, evs in timing.items():
+        ms = [a.elapsed_time(b) for a, b in evs]
+        mean = sum(ms) / len(ms)
+        kernels.append({"kernel": kname, "launches": len(ms), "mean_launch_ms": mean, "total_ms": sum(ms),
+                        "bytes_per_launch": 2 * 16 * (1 << n),
+                        "achieved_gbps": 2 * 16 * (1 << n) / (mean * 1e-3) / 1e9})
+    kernels.sort(key=lambda k: -k["total_ms"])
+    dom = kernels[0]
+    print(f"[bench] c128 per-gate: {ms_per_step:.1f} ms/step, {value:.4e} amp-updates/s; dominant kernel "
+          f"{dom['kernel']} {dom['mean_launch_ms']:.3f} ms = {dom['achieved_gbps']:.0f} GB/s", file=sys.stderr,
+          flush=True)
 
     traffic = None
-    tp = os.path.join(ROOT, "profiles", "butterfly_traffic.json")
+    tp = os.path.join(ROOT, "profiles", "sweep_traffic_30q_c128.json")
     if os.path.exists(tp):
         try:
+            from paper_1908_07187_amd.profiling import kernel_source_hash
             with open(tp) as f:
                 tj = json.load(f)
-            if tj.get("kernel_source_hash") == _kernel_hash():
-                traffic = tj.get("bytes_per_launch")
+            if tj.get("kernel_source_hash") == kernel_source_hash():
+                traffic = tj["kernels"].get(dom["kernel"], {}).get("bytes_per_launch")
         except Exception:
             traffic = None
 
@@ -161,10 +216,11 @@ def main():
                                f"CNOT on a random matching, RZZ on a second matching; complex128 gate by gate "
                                f"from |0...0>", "n_qubits": n, "depth": depth, "gates": ngates, "seed": args.seed,
                    "amp_updates_per_step": updates},
-        "roofline": {"bound": "hbm", "kernel": "k_butterfly<double,4> (2x2 gate sweep)",
-                     "achieved": bfly_gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": bfly_gbps / HBM_PEAK_GBPS, "traffic": traffic,
-                     "bytes_per_launch": bfly_bytes, "mean_launch_ms": bfly_mean_ms, "launches": len(bfly_ms)},
+        "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["achieved_gbps"],
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": dom["achieved_gbps"] / HBM_PEAK_GBPS,
+                     "traffic": traffic, "bytes_per_launch": dom["bytes_per_launch"],
+                     "mean_launch_ms": dom["mean_launch_ms"], "launches": dom["launches"]},
+        "sweep_kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in kk.items()} for kk in kernels],
     }
 
     if not args.no_fused:
@@ -177,14 +233,6 @@ def main():
         out["cpu_baseline"] = cpu_baseline(circ, args)
 
     print(json.dumps(out), flush=True)
-
-
-def _kernel_hash():
-    import hashlib
-    h = hashlib.sha256()
-    with open(os.path.join(ROOT, "paper_1908_07187_amd", "csrc", "kernels.hip"), "rb") as f:
-        h.update(f.read())
-    return h.hexdigest()[:16]
 
 
 def run_fused(qk, prog, torch, args, updates, ref_sim):
