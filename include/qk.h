@@ -257,6 +257,66 @@ const char* qk_last_error(qk_sim sim);
 
 const char* qk_status_string(qk_status st);
 
+/* ---- captured gate sequences (HIP graphs) --------------------------------
+ * A sequence of calls on one simulator can be captured once and replayed
+ * with one launch: qk_capture_begin, then any qk_reset / qk_apply_gate /
+ * qk_measure / qk_measure_dev / qk_flush calls (no readout, no qk_add_*),
+ * then qk_capture_end.  Nothing runs during capture; each qk_graph_launch
+ * replays the whole sequence on the simulator's state, cbits and stream.
+ * The graph keeps the constants it uploads; destroy graphs before their
+ * simulator. */
+typedef struct qk_graph_s* qk_graph;
+
+/* Set the state to |0...0> and every cbit to 0 (asynchronous; capturable). */
+qk_status qk_reset(qk_sim sim);
+qk_status qk_capture_begin(qk_sim sim);
+qk_status qk_capture_end(qk_sim sim, qk_graph* out);
+qk_status qk_graph_launch(qk_graph graph);
+qk_status qk_graph_destroy(qk_graph graph);
+
+/* ---- batched execution: many small circuits in one persistent launch -----
+ * Circuits on at most 13 qubits (complex128) or 14 (complex64), builtin gates
+ * and measurements only, each started from |0...0>.  qk_batch_run launches
+ * one persistent grid whose workgroups take circuits from a device queue
+ * (largest first) and keep each circuit's state in on-chip memory (LDS) for
+ * the whole circuit.  Results do not depend on which circuits share a launch. */
+#define QK_OP_GATE 1
+#define QK_OP_MEASURE 2
+
+typedef struct qk_op {
+  int32_t kind;          /* QK_OP_GATE or QK_OP_MEASURE */
+  int32_t gate;          /* builtin gate id (QK_OP_GATE) */
+  int32_t targets[2];
+  int32_t n_targets;
+  int32_t controls[4];
+  int32_t n_controls;
+  qk_cond conds[2];      /* classical conditions of a gate (ANDed) */
+  int32_t n_conds;
+  double param;          /* angle of RX, RY, RZ, PHASE, CPHASE, RZZ */
+  int32_t qubit;         /* QK_OP_MEASURE: measured qubit */
+  int32_t cbit;          /* QK_OP_MEASURE: destination cbit or -1 */
+  double u;              /* QK_OP_MEASURE: pre-drawn uniform in [0, 1) */
+} qk_op;
+
+typedef struct qk_batch_s* qk_batch;
+
+qk_status qk_batch_create(qk_dtype dtype, const qk_allocator* alloc, void* hip_stream, qk_batch* out);
+qk_status qk_batch_destroy(qk_batch batch);
+/* Validate and compile one circuit (ops copied); *job receives its index. */
+qk_status qk_batch_add(qk_batch batch, int32_t n_qubits, int32_t n_cbits, const qk_op* ops, int32_t n_ops,
+                       int32_t* job);
+/* Run every circuit added so far (asynchronous, one launch). */
+qk_status qk_batch_run(qk_batch batch);
+qk_status qk_batch_sync(qk_batch batch);
+/* Results of the last run (synchronise). */
+qk_status qk_batch_get_state(qk_batch batch, int32_t job, void* host_out, size_t bytes);
+qk_status qk_batch_read_cbits(qk_batch batch, int32_t job, uint8_t* out, int32_t n);
+qk_status qk_batch_state_ptr(qk_batch batch, int32_t job, void** dev_ptr, size_t* bytes);
+/* Forget every circuit (device buffers are kept for reuse). */
+qk_status qk_batch_clear(qk_batch batch);
+qk_status qk_batch_num_jobs(qk_batch batch, int32_t* n);
+const char* qk_batch_last_error(qk_batch batch);
+
 #ifdef __cplusplus
 }
 #endif

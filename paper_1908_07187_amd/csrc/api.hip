@@ -72,7 +72,9 @@ struct qk_sim_s {
   int n = 0;
   DevBuf state, scratch, cbits, meas;
   int ncbits = 0;
-  Arena arena;
+  std::vector<Arena> arenas;        // constant chunks in use (the last one is being filled)
+  std::vector<Arena> saved_arenas;  // chunks set aside while a capture owns `arenas`
+  bool capturing = false;
   std::vector<UserGate*> ugates;
   int fuse_k = 0;
   std::vector<GateDesc> pending;
@@ -167,25 +169,53 @@ qk_status ensure_meas(qk_sim s) {
 
 // ---- constant arena ----------------------------------------------------------
 
+qk_status arena_new_chunk(qk_sim s) {
+  Arena a;
+  a.dev = dev_alloc(s, kArenaBytes);
+  if (!a.dev) return fail(s, QK_E_OOM, "device allocation failed: constant arena");
+  if (hipHostMalloc(&a.host, kArenaBytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    DevBuf b{a.dev, kArenaBytes};
+    dev_free(s, b);
+    return fail(s, QK_E_OOM, "pinned host allocation failed: constant arena");
+  }
+  a.cap = kArenaBytes;
+  a.used = 0;
+  s->arenas.push_back(a);
+  return QK_OK;
+}
+
+void arena_free_chunk(qk_sim s, Arena& a) {
+  if (a.dev) {
+    DevBuf b{a.dev, a.cap};
+    dev_free(s, b);
+  }
+  if (a.host) (void)hipHostFree(a.host);
+  a = Arena{};
+}
+
+// Outside a capture a full arena is recycled after the stream drains (so no
+// pending copy still reads the staged bytes); inside a capture the graph will
+// replay the copies, so every staged byte must survive: a new chunk is added.
 qk_status arena_put(qk_sim s, const void* data, size_t bytes, const void** dptr) {
-  Arena& a = s->arena;
-  if (!a.dev) {
-    a.dev = dev_alloc(s, kArenaBytes);
-    if (!a.dev) return fail(s, QK_E_OOM, "device allocation failed: constant arena");
-    if (hipHostMalloc(&a.host, kArenaBytes, hipHostMallocDefault) != hipSuccess) {
-      (void)hipGetLastError();
-      return fail(s, QK_E_OOM, "pinned host allocation failed: constant arena");
-    }
-    a.cap = kArenaBytes;
-    a.used = 0;
-  }
   const size_t need = (bytes + 255) & ~(size_t)255;
-  if (need > a.cap) return fail(s, QK_E_ARG, "constant block larger than the arena");
-  if (a.used + need > a.cap) {
-    hipError_t e = hipStreamSynchronize(s->stream);
-    if (e != hipSuccess) return hip_fail(s, e, "arena recycle");
-    a.used = 0;
+  if (need > kArenaBytes) return fail(s, QK_E_ARG, "constant block larger than the arena");
+  qk_status st;
+  if (s->arenas.empty() && (st = arena_new_chunk(s))) return st;
+  if (s->arenas.back().used + need > s->arenas.back().cap) {
+    if (s->capturing) {
+      if ((st = arena_new_chunk(s))) return st;
+    } else {
+      hipError_t e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) return hip_fail(s, e, "arena recycle");
+      while (s->arenas.size() > 1) {
+        arena_free_chunk(s, s->arenas.back());
+        s->arenas.pop_back();
+      }
+      s->arenas[0].used = 0;
+    }
   }
+  Arena& a = s->arenas.back();
   std::memcpy((char*)a.host + a.used, data, bytes);
   hipError_t e = hipMemcpyAsync((char*)a.dev + a.used, (char*)a.host + a.used, bytes, hipMemcpyHostToDevice, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "constant upload");
@@ -236,33 +266,62 @@ const BuiltinInfo* builtin_by_id(int id) {
   return nullptr;
 }
 
-// Classify a builtin gate into a sweep.  Matrices follow the definitions in qk.h.
-void builtin_desc(int id, double p, GateDesc& d) {
+}  // namespace
+
+namespace qk {
+
+bool builtin_info(int id, int* arity, int* nparams) {
+  const BuiltinInfo* b = builtin_by_id(id);
+  if (!b) return false;
+  if (arity) *arity = b->arity;
+  if (nparams) *nparams = b->nparams;
+  return true;
+}
+
+// Builtin gate data in FP64, following the definitions in qk.h.
+BuiltinGate builtin_gate(int id, double p) {
   const double s2 = 1.0 / std::sqrt(2.0);
   const cd i1(0, 1);
   const double c = std::cos(p / 2), sn = std::sin(p / 2);
-  d.fusable = true;
+  BuiltinGate g;
   switch (id) {
-    case QK_H: d.kind = D_BUTTERFLY; d.m = {s2, s2, s2, -s2}; break;
-    case QK_X: d.kind = D_BUTTERFLY; d.m = {0.0, 1.0, 1.0, 0.0}; break;
-    case QK_Y: d.kind = D_BUTTERFLY; d.m = {0.0, -i1, i1, 0.0}; break;
-    case QK_RX: d.kind = D_BUTTERFLY; d.m = {c, -i1 * sn, -i1 * sn, c}; break;
-    case QK_RY: d.kind = D_BUTTERFLY; d.m = {c, -sn, sn, c}; break;
-    case QK_Z: d.kind = D_PHASE1; d.z = -1.0; break;
-    case QK_S: d.kind = D_PHASE1; d.z = i1; break;
-    case QK_SDG: d.kind = D_PHASE1; d.z = -i1; break;
-    case QK_T: d.kind = D_PHASE1; d.z = std::polar(1.0, M_PI / 4); break;
-    case QK_TDG: d.kind = D_PHASE1; d.z = std::polar(1.0, -M_PI / 4); break;
-    case QK_PHASE: d.kind = D_PHASE1; d.z = std::polar(1.0, p); break;
-    case QK_CPHASE: d.kind = D_PHASE1; d.z = std::polar(1.0, p); break;
-    case QK_RZ: d.kind = D_DIAG; d.m = {std::polar(1.0, -p / 2), std::polar(1.0, p / 2)}; break;
+    case QK_H: g.cls = BG_DENSE1; g.m = {s2, s2, s2, -s2}; break;
+    case QK_X: g.cls = BG_DENSE1; g.m = {0.0, 1.0, 1.0, 0.0}; break;
+    case QK_Y: g.cls = BG_DENSE1; g.m = {0.0, -i1, i1, 0.0}; break;
+    case QK_RX: g.cls = BG_DENSE1; g.m = {c, -i1 * sn, -i1 * sn, c}; break;
+    case QK_RY: g.cls = BG_DENSE1; g.m = {c, -sn, sn, c}; break;
+    case QK_Z: g.cls = BG_PHASE; g.z = -1.0; break;
+    case QK_S: g.cls = BG_PHASE; g.z = i1; break;
+    case QK_SDG: g.cls = BG_PHASE; g.z = -i1; break;
+    case QK_T: g.cls = BG_PHASE; g.z = std::polar(1.0, M_PI / 4); break;
+    case QK_TDG: g.cls = BG_PHASE; g.z = std::polar(1.0, -M_PI / 4); break;
+    case QK_PHASE: g.cls = BG_PHASE; g.z = std::polar(1.0, p); break;
+    case QK_CPHASE: g.cls = BG_PHASE; g.z = std::polar(1.0, p); break;
+    case QK_RZ: g.cls = BG_DIAG; g.m = {std::polar(1.0, -p / 2), std::polar(1.0, p / 2)}; break;
     case QK_RZZ: {
       const cd em = std::polar(1.0, -p / 2), ep = std::polar(1.0, p / 2);
-      d.kind = D_DIAG;
-      d.m = {em, ep, ep, em};
+      g.cls = BG_DIAG;
+      g.m = {em, ep, ep, em};
       break;
     }
-    case QK_SWAP: d.kind = D_SWAP; break;
+    case QK_SWAP: g.cls = BG_SWAP; break;
+  }
+  return g;
+}
+
+}  // namespace qk
+
+namespace {
+
+// Classify a builtin gate into a sweep.
+void builtin_desc(int id, double p, GateDesc& d) {
+  const BuiltinGate g = builtin_gate(id, p);
+  d.fusable = true;
+  switch (g.cls) {
+    case BG_DENSE1: d.kind = D_BUTTERFLY; d.m = g.m; break;
+    case BG_PHASE: d.kind = D_PHASE1; d.z = g.z; break;
+    case BG_DIAG: d.kind = D_DIAG; d.m = g.m; break;
+    case BG_SWAP: d.kind = D_SWAP; break;
   }
 }
 
@@ -483,6 +542,7 @@ qk_status upload_table(qk_sim s, UserGate* g, const std::vector<uint64_t>& table
 }
 
 qk_status define_perm(qk_sim s, const char* name, int32_t k, const std::vector<uint64_t>& table, qk_gate* out) {
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   const uint64_t K = 1ull << k;
   std::vector<unsigned char> seen(K, 0);
   for (uint64_t x = 0; x < K; ++x) {
@@ -549,16 +609,19 @@ qk_status qk_create(qk_dtype dtype, const qk_allocator* alloc, void* hip_stream,
 
 qk_status qk_destroy(qk_sim s) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
-  if (s->state.p || s->meas.p || s->arena.dev) (void)hipStreamSynchronize(s->stream);
+  if (s->capturing) {
+    hipGraph_t g = nullptr;
+    (void)hipStreamEndCapture(s->stream, &g);
+    if (g) (void)hipGraphDestroy(g);
+    s->capturing = false;
+  }
+  if (s->state.p || s->meas.p || !s->arenas.empty()) (void)hipStreamSynchronize(s->stream);
   dev_free(s, s->state);
   dev_free(s, s->scratch);
   dev_free(s, s->cbits);
   dev_free(s, s->meas);
-  if (s->arena.dev) {
-    DevBuf b{s->arena.dev, s->arena.cap};
-    dev_free(s, b);
-  }
-  if (s->arena.host) (void)hipHostFree(s->arena.host);
+  for (Arena& a : s->arenas) arena_free_chunk(s, a);
+  for (Arena& a : s->saved_arenas) arena_free_chunk(s, a);
   for (UserGate* g : s->ugates) {
     dev_free(s, g->dmat);
     dev_free(s, g->finv);
@@ -570,6 +633,7 @@ qk_status qk_destroy(qk_sim s) {
 
 qk_status qk_add_qubits(qk_sim s, int32_t count, int32_t* first) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   if (count < 0) return fail(s, QK_E_ARG, "count < 0");
   if (s->n + count > kMaxQubits) return fail(s, QK_E_ARG, "too many qubits");
   if (first) *first = s->n;
@@ -604,6 +668,7 @@ qk_status qk_add_qubits(qk_sim s, int32_t count, int32_t* first) {
 
 qk_status qk_add_cbits(qk_sim s, int32_t count, int32_t* first) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   if (count < 0 || s->ncbits + count > (1 << 20)) return fail(s, QK_E_ARG, "bad cbit count");
   if (first) *first = s->ncbits;
   if (count == 0) return QK_OK;
@@ -641,6 +706,7 @@ qk_status qk_gate_builtin(const char* name, qk_gate* out) {
 
 qk_status qk_define_gate_matrix(qk_sim s, const char* name, int32_t k, const double* m, double tol, qk_gate* out) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   if (!m) return fail(s, QK_E_ARG, "matrix is NULL");
   if (k < 1 || k > QK_MAX_MATRIX_K) return fail(s, QK_E_ARG, "k out of range");
   if (!(tol > 0)) tol = 1e-10;
@@ -836,6 +902,7 @@ qk_status qk_measure_dev(qk_sim s, int32_t qubit, int32_t cbit, const double* d_
 
 qk_status qk_postselect(qk_sim s, int32_t qubit, int32_t cbit, int32_t outcome) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   if (qubit < 0 || qubit >= s->n) return fail(s, QK_E_ARG, "qubit out of range");
   if (cbit < -1 || cbit >= s->ncbits) return fail(s, QK_E_ARG, "cbit out of range");
   if (outcome != 0 && outcome != 1) return fail(s, QK_E_ARG, "outcome must be 0 or 1");
@@ -856,6 +923,7 @@ qk_status qk_postselect(qk_sim s, int32_t qubit, int32_t cbit, int32_t outcome) 
 
 qk_status qk_read_cbits(qk_sim s, uint8_t* out, int32_t n) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   if (n < 0 || n > s->ncbits || (n > 0 && !out)) return fail(s, QK_E_ARG, "bad cbit count");
   qk_status st = flush(s);
   if (st) return st;
@@ -868,6 +936,7 @@ qk_status qk_read_cbits(qk_sim s, uint8_t* out, int32_t n) {
 
 qk_status qk_read_measure_log(qk_sim s, double* out, int32_t count, int32_t* written) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   if (count < 0 || (count > 0 && !out)) return fail(s, QK_E_ARG, "bad count");
   if (written) *written = 0;
   qk_status st = flush(s);
@@ -896,6 +965,7 @@ qk_status qk_read_measure_log(qk_sim s, double* out, int32_t count, int32_t* wri
 
 qk_status qk_get_state(qk_sim s, void* host_out, size_t bytes) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   const size_t need = ((size_t)1 << s->n) * s->amp;
   if (!host_out || bytes != need) return fail(s, QK_E_ARG, "buffer size must be 2^n * amplitude size");
   if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
@@ -908,6 +978,7 @@ qk_status qk_get_state(qk_sim s, void* host_out, size_t bytes) {
 
 qk_status qk_set_state(qk_sim s, const void* host_in, size_t bytes) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   const size_t need = ((size_t)1 << s->n) * s->amp;
   if (!host_in || bytes != need) return fail(s, QK_E_ARG, "buffer size must be 2^n * amplitude size");
   if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
@@ -930,6 +1001,7 @@ qk_status qk_state_ptr(qk_sim s, void** dev_ptr, size_t* bytes) {
 qk_status qk_inner_product(qk_sim a, qk_sim b, double* re, double* im) {
   if (!a || !b) return fail(nullptr, QK_E_ARG, "sim is NULL");
   if (a->n != b->n || !a->state.p || !b->state.p) return fail(a, QK_E_ARG, "qubit counts differ or no state");
+  if (a->capturing || b->capturing) return fail(a, QK_E_STATE, "not allowed while capturing a graph");
   qk_status st = flush(a);
   if (!st) st = flush(b);
   if (st) return st;
@@ -961,6 +1033,112 @@ qk_status qk_norm2(qk_sim s, double* out) {
   return st;
 }
 
+
+// ---------------------------------------------------------------- reset / graphs
+
+struct qk_graph_s {
+  qk_sim sim = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<Arena> arenas;   // constants the captured copies read on every replay
+};
+
+qk_status qk_reset(qk_sim s) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
+  qk_status st = flush(s);
+  if (st) return st;
+  const uint64_t dim = 1ull << s->n;
+  hipError_t e = launch_fill_zero(s->state.p, 0, dim, s->c64, s->stream);
+  if (e == hipSuccess) e = launch_set_one(s->state.p, 0, s->c64, s->stream);
+  if (e == hipSuccess && s->ncbits > 0) {
+    hipLaunchKernelGGL(k_u8_fill, dim3(std::max<size_t>(1, std::min<size_t>(1024, (s->ncbits + 255) / 256))),
+                       dim3(256), 0, s->stream, (uint8_t*)s->cbits.p, (size_t)0, (size_t)s->ncbits, (uint8_t)0);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) return hip_fail(s, e, "reset");
+  return QK_OK;
+}
+
+qk_status qk_capture_begin(qk_sim s) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->capturing) return fail(s, QK_E_STATE, "already capturing");
+  if (!s->state.p) return fail(s, QK_E_STATE, "add qubits before capturing");
+  qk_status st = flush(s);
+  if (st) return st;
+  // everything a replay touches is allocated now, outside the capture
+  if ((st = ensure_meas(s))) return st;
+  bool perms = false;
+  for (const UserGate* g : s->ugates) perms = perms || g->kind != U_MATRIX;
+  if (perms && (st = ensure_scratch(s))) return st;
+  s->saved_arenas = std::move(s->arenas);
+  s->arenas.clear();
+  if ((st = arena_new_chunk(s))) {
+    s->arenas = std::move(s->saved_arenas);
+    return st;
+  }
+  hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeRelaxed);
+  if (e != hipSuccess) {
+    for (Arena& a : s->arenas) arena_free_chunk(s, a);
+    s->arenas = std::move(s->saved_arenas);
+    return hip_fail(s, e, "begin capture");
+  }
+  s->capturing = true;
+  return QK_OK;
+}
+
+qk_status qk_capture_end(qk_sim s, qk_graph* out) {
+  if (!s || !out) return fail(s, QK_E_ARG, "NULL argument");
+  if (!s->capturing) return fail(s, QK_E_STATE, "not capturing");
+  qk_status st = flush(s);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s->stream, &g);
+  s->capturing = false;
+  std::vector<Arena> mine = std::move(s->arenas);
+  s->arenas = std::move(s->saved_arenas);
+  s->saved_arenas.clear();
+  if (st || e != hipSuccess || !g) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamSynchronize(s->stream);
+    for (Arena& a : mine) arena_free_chunk(s, a);
+    return st ? st : hip_fail(s, e, "end capture");
+  }
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    for (Arena& a : mine) arena_free_chunk(s, a);
+    return hip_fail(s, e, "instantiate graph");
+  }
+  qk_graph q = new qk_graph_s;
+  q->sim = s;
+  q->graph = g;
+  q->exec = x;
+  q->arenas = std::move(mine);
+  *out = q;
+  return QK_OK;
+}
+
+qk_status qk_graph_launch(qk_graph g) {
+  if (!g) return fail(nullptr, QK_E_ARG, "graph is NULL");
+  if (g->sim->capturing) return fail(g->sim, QK_E_STATE, "not allowed while capturing a graph");
+  qk_status st = flush(g->sim);
+  if (st) return st;
+  hipError_t e = hipGraphLaunch(g->exec, g->sim->stream);
+  if (e != hipSuccess) return hip_fail(g->sim, e, "graph launch");
+  return QK_OK;
+}
+
+qk_status qk_graph_destroy(qk_graph g) {
+  if (!g) return fail(nullptr, QK_E_ARG, "graph is NULL");
+  (void)hipStreamSynchronize(g->sim->stream);
+  if (g->exec) (void)hipGraphExecDestroy(g->exec);
+  if (g->graph) (void)hipGraphDestroy(g->graph);
+  for (Arena& a : g->arenas) arena_free_chunk(g->sim, a);
+  delete g;
+  return QK_OK;
+}
+
 qk_status qk_set_fusion(qk_sim s, int32_t max_k) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
   if (max_k != 0 && (max_k < 2 || max_k > QK_MAX_FUSION_K)) return fail(s, QK_E_ARG, "max_k must be 0 or 2..6");
@@ -977,12 +1155,14 @@ qk_status qk_flush(qk_sim s) {
 
 qk_status qk_sync(qk_sim s) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   qk_status st = flush(s);
   if (st) return st;
   if (s->latched) return fail(s, s->latched, "an earlier asynchronous failure was latched");
-  if (!s->state.p && !s->meas.p && !s->arena.dev && !s->cbits.p) return QK_OK;
+  if (!s->state.p && !s->meas.p && s->arenas.empty() && !s->cbits.p) return QK_OK;
   st = sync_stream(s);
-  if (st == QK_OK) s->arena.used = 0;
+  if (st == QK_OK)
+    for (Arena& a : s->arenas) a.used = 0;
   return st;
 }
 

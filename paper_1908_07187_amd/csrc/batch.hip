@@ -1,0 +1,558 @@
+// Batched execution: many small circuits of uneven qubit counts in one
+// persistent launch.
+//
+// Each circuit ("job") is compiled on the host into compact device op records
+// (builtin gates with their FP64 matrices, controls as a bit mask, up to two
+// classical conditions, measurements with their pre-drawn uniform).  One
+// persistent grid runs all jobs: every workgroup takes the next job from a
+// device counter (largest jobs first), builds |0...0> in LDS, applies the
+// job's ops one after another in LDS with a block barrier between ops, and
+// writes the final state and cbits to HBM.  A job's state stays in LDS for its
+// whole circuit, so a 12-qubit, 360-gate circuit costs one HBM write instead of
+// 360 sweeps and 360 launches.  Every workgroup leaves the loop once the
+// counter passes the job count.
+//
+// Measurement inside a job uses the same rule as the per-gate path (FP64
+// sums, outcome 0 iff u < P0, renormalise by 1/sqrt(p_outcome)), reduced in a
+// fixed order that depends only on the job, so a job's result does not depend
+// on which other jobs share the launch.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "qk_internal.h"
+
+using namespace qk;
+
+namespace {
+
+enum BKind { BK_U1 = 1, BK_DIAG1 = 2, BK_DIAG2 = 3, BK_PHASE = 4, BK_SWAP = 5, BK_MEAS = 6 };
+
+struct BJob {
+  uint64_t state_off;   // amplitudes
+  uint32_t op_begin, op_end;
+  int32_t n, ncbits;
+  uint32_t cbit_off;
+  int32_t pad;
+};
+
+struct BOp {
+  int32_t kind, t0, t1, ncond;
+  uint32_t cmask;
+  int32_t cb0, cv0, cb1, cv1;
+  int32_t cbit;
+  double u;
+  double m[8];
+};
+
+constexpr int kBatchThreads = 512;
+constexpr int kMaxJobCbits = 256;
+
+template <typename R> struct EVb;
+template <> struct EVb<float> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct EVb<double> { typedef double T __attribute__((ext_vector_type(2))); };
+
+__device__ __forceinline__ double bwave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kBatchThreads) void k_batch(const BJob* __restrict__ jobs, int njobs,
+                                                         const BOp* __restrict__ ops,
+                                                         typename EVb<R>::T* __restrict__ states,
+                                                         uint8_t* __restrict__ cbits, int* counter) {
+  using C = typename EVb<R>::T;
+  extern __shared__ unsigned char smem_raw[];
+  C* st = reinterpret_cast<C*>(smem_raw);
+  __shared__ uint8_t cb[kMaxJobCbits];
+  __shared__ double red[2][kBatchThreads / 64];
+  __shared__ double meas[2];
+  __shared__ int job_sh;
+  const int tid = threadIdx.x, bd = blockDim.x;
+  const int lane = tid & 63, w = tid >> 6;
+  for (;;) {
+    if (tid == 0) job_sh = atomicAdd(counter, 1);
+    __syncthreads();
+    const int j = job_sh;
+    if (j >= njobs) break;
+    const BJob jb = jobs[j];
+    const uint32_t dim = 1u << jb.n;
+    for (uint32_t i = tid; i < dim; i += bd) {
+      C z;
+      z.x = (i == 0) ? (R)1 : (R)0;
+      z.y = 0;
+      st[i] = z;
+    }
+    for (int c = tid; c < jb.ncbits; c += bd) cb[c] = 0;
+    __syncthreads();
+    for (uint32_t oi = jb.op_begin; oi < jb.op_end; ++oi) {
+      const BOp& o = ops[oi];
+      bool ok = true;
+      if (o.ncond > 0 && cb[o.cb0] != (uint8_t)o.cv0) ok = false;
+      if (o.ncond > 1 && cb[o.cb1] != (uint8_t)o.cv1) ok = false;
+      if (ok) {
+        const uint32_t cm = o.cmask;
+        switch (o.kind) {
+          case BK_U1: {
+            const R a0 = (R)o.m[0], b0 = (R)o.m[1], a1 = (R)o.m[2], b1 = (R)o.m[3];
+            const R a2 = (R)o.m[4], b2 = (R)o.m[5], a3 = (R)o.m[6], b3 = (R)o.m[7];
+            const uint32_t tb = 1u << o.t0, lo = tb - 1;
+            for (uint32_t p = tid; p < (dim >> 1); p += bd) {
+              const uint32_t i0 = ((p & ~lo) << 1) | (p & lo);
+              if ((i0 & cm) != cm) continue;
+              const C x = st[i0], y = st[i0 | tb];
+              C r0, r1;
+              r0.x = a0 * x.x - b0 * x.y + a1 * y.x - b1 * y.y;
+              r0.y = a0 * x.y + b0 * x.x + a1 * y.y + b1 * y.x;
+              r1.x = a2 * x.x - b2 * x.y + a3 * y.x - b3 * y.y;
+              r1.y = a2 * x.y + b2 * x.x + a3 * y.y + b3 * y.x;
+              st[i0] = r0;
+              st[i0 | tb] = r1;
+            }
+            break;
+          }
+          case BK_DIAG1:
+          case BK_DIAG2: {
+            for (uint32_t i = tid; i < dim; i += bd) {
+              if ((i & cm) != cm) continue;
+              int m = (i >> o.t0) & 1;
+              if (o.kind == BK_DIAG2) m |= ((i >> o.t1) & 1) << 1;
+              const R dr = (R)o.m[2 * m], di = (R)o.m[2 * m + 1];
+              const C x = st[i];
+              C r;
+              r.x = dr * x.x - di * x.y;
+              r.y = dr * x.y + di * x.x;
+              st[i] = r;
+            }
+            break;
+          }
+          case BK_PHASE: {
+            const R zr = (R)o.m[0], zi = (R)o.m[1];
+            for (uint32_t i = tid; i < dim; i += bd) {
+              if ((i & cm) != cm) continue;
+              const C x = st[i];
+              C r;
+              r.x = zr * x.x - zi * x.y;
+              r.y = zr * x.y + zi * x.x;
+              st[i] = r;
+            }
+            break;
+          }
+          case BK_SWAP: {
+            const uint32_t ab = 1u << o.t0, bb = 1u << o.t1;
+            for (uint32_t i = tid; i < dim; i += bd) {
+              if ((i & ab) && !(i & bb) && (i & cm) == cm) {
+                const uint32_t k2 = i ^ ab ^ bb;
+                const C x = st[i];
+                st[i] = st[k2];
+                st[k2] = x;
+              }
+            }
+            break;
+          }
+          case BK_MEAS: {
+            const uint32_t qb = 1u << o.t0;
+            double s0 = 0, s1 = 0;
+            for (uint32_t i = tid; i < dim; i += bd) {
+              const C x = st[i];
+              const double p = (double)x.x * (double)x.x + (double)x.y * (double)x.y;
+              if (i & qb) s1 += p; else s0 += p;
+            }
+            s0 = bwave_sum(s0);
+            s1 = bwave_sum(s1);
+            if (lane == 0) {
+              red[0][w] = s0;
+              red[1][w] = s1;
+            }
+            __syncthreads();
+            if (tid == 0) {
+              double p0 = 0, p1 = 0;
+              for (int k = 0; k < bd / 64; ++k) {
+                p0 += red[0][k];
+                p1 += red[1][k];
+              }
+              const double P0 = p0 / (p0 + p1);
+              const int oc = (o.u < P0) ? 0 : 1;
+              const double po = oc ? p1 : p0;
+              meas[0] = po > 0 ? 1.0 / sqrt(po) : 0.0;
+              meas[1] = (double)oc;
+              if (o.cbit >= 0 && po > 0) cb[o.cbit] = (uint8_t)oc;
+            }
+            __syncthreads();
+            const double sc = meas[0];
+            const uint32_t oc = (uint32_t)meas[1];
+            if (sc != 0.0) {
+              const R scale = (R)sc;
+              for (uint32_t i = tid; i < dim; i += bd) {
+                C x = st[i];
+                if (((i & qb) != 0) == (oc != 0)) {
+                  x.x *= scale;
+                  x.y *= scale;
+                } else {
+                  x.x = 0;
+                  x.y = 0;
+                }
+                st[i] = x;
+              }
+            }
+            break;
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (uint32_t i = tid; i < dim; i += bd) states[jb.state_off + i] = st[i];
+    for (int c = tid; c < jb.ncbits; c += bd) cbits[jb.cbit_off + c] = cb[c];
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_counter(int* c) {
+  if (threadIdx.x == 0) *c = 0;
+}
+
+struct HostJob {
+  int n, ncbits;
+  std::vector<BOp> ops;
+  uint64_t state_off = 0;
+  uint32_t cbit_off = 0;
+};
+
+std::string g_batch_error;
+
+}  // namespace
+
+struct qk_batch_s {
+  qk_dtype dtype = QK_C128;
+  bool c64 = false;
+  qk_allocator alloc{};
+  bool has_alloc = false;
+  hipStream_t stream = nullptr;
+  std::vector<HostJob> jobs;
+  void* d_states = nullptr;
+  size_t states_bytes = 0;
+  void* d_cbits = nullptr;
+  size_t cbits_bytes = 0;
+  void* d_ops = nullptr;
+  size_t ops_bytes = 0;
+  void* d_jobs = nullptr;
+  size_t jobs_bytes = 0;
+  int* d_counter = nullptr;
+  bool ran = false;
+  std::string err;
+};
+
+namespace {
+
+qk_status bfail(qk_batch b, qk_status st, const std::string& m) {
+  if (b) b->err = m;
+  else g_batch_error = m;
+  return st;
+}
+
+void* balloc(qk_batch b, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (b->has_alloc) return b->alloc.alloc(bytes, (void*)b->stream, b->alloc.ctx);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void bfree(qk_batch b, void*& p, size_t& bytes) {
+  if (!p) return;
+  if (b->has_alloc) b->alloc.free(p, bytes, (void*)b->stream, b->alloc.ctx);
+  else (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+qk_status bensure(qk_batch b, void*& p, size_t& cur, size_t need, const char* what) {
+  if (p && cur >= need) return QK_OK;
+  bfree(b, p, cur);
+  p = balloc(b, need);
+  if (!p) return bfail(b, QK_E_OOM, std::string("device allocation failed: ") + what);
+  cur = need;
+  return QK_OK;
+}
+
+int max_batch_qubits(bool c64) { return c64 ? 14 : 13; }
+
+}  // namespace
+
+extern "C" {
+
+qk_status qk_batch_create(qk_dtype dtype, const qk_allocator* alloc, void* hip_stream, qk_batch* out) {
+  if (!out) return bfail(nullptr, QK_E_ARG, "out is NULL");
+  *out = nullptr;
+  if (dtype != QK_C64 && dtype != QK_C128) return bfail(nullptr, QK_E_ARG, "dtype must be QK_C64 or QK_C128");
+  if (alloc && (!alloc->alloc || !alloc->free)) return bfail(nullptr, QK_E_ARG, "allocator needs alloc and free");
+  qk_batch b = new qk_batch_s;
+  b->dtype = dtype;
+  b->c64 = dtype == QK_C64;
+  if (alloc) {
+    b->alloc = *alloc;
+    b->has_alloc = true;
+  }
+  b->stream = (hipStream_t)hip_stream;
+  *out = b;
+  return QK_OK;
+}
+
+qk_status qk_batch_destroy(qk_batch b) {
+  if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
+  if (b->d_states || b->d_ops) (void)hipStreamSynchronize(b->stream);
+  bfree(b, b->d_states, b->states_bytes);
+  bfree(b, b->d_cbits, b->cbits_bytes);
+  bfree(b, b->d_ops, b->ops_bytes);
+  bfree(b, b->d_jobs, b->jobs_bytes);
+  size_t cb = sizeof(int);
+  void* c = b->d_counter;
+  bfree(b, c, cb);
+  delete b;
+  return QK_OK;
+}
+
+const char* qk_batch_last_error(qk_batch b) { return b ? b->err.c_str() : g_batch_error.c_str(); }
+
+qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, int32_t nops, int32_t* job) {
+  if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
+  if (n < 1 || n > max_batch_qubits(b->c64))
+    return bfail(b, QK_E_ARG, "qubit count outside the batched range (1.." + std::to_string(max_batch_qubits(b->c64)) + ")");
+  if (ncbits < 0 || ncbits > kMaxJobCbits) return bfail(b, QK_E_ARG, "cbit count outside 0..256");
+  if (nops < 0 || (nops > 0 && !ops)) return bfail(b, QK_E_ARG, "bad op array");
+  HostJob hj;
+  hj.n = n;
+  hj.ncbits = ncbits;
+  hj.ops.reserve(nops);
+  for (int i = 0; i < nops; ++i) {
+    const qk_op& o = ops[i];
+    BOp d{};
+    const std::string where = "op " + std::to_string(i) + ": ";
+    if (o.n_conds < 0 || o.n_conds > 2) return bfail(b, QK_E_ARG, where + "at most 2 conditions");
+    for (int c = 0; c < o.n_conds; ++c) {
+      if (o.conds[c].cbit < 0 || o.conds[c].cbit >= ncbits) return bfail(b, QK_E_ARG, where + "condition cbit out of range");
+      if (o.conds[c].value != 0 && o.conds[c].value != 1) return bfail(b, QK_E_ARG, where + "condition value must be 0 or 1");
+    }
+    d.ncond = o.n_conds;
+    d.cb0 = o.n_conds > 0 ? o.conds[0].cbit : 0;
+    d.cv0 = o.n_conds > 0 ? o.conds[0].value : 0;
+    d.cb1 = o.n_conds > 1 ? o.conds[1].cbit : 0;
+    d.cv1 = o.n_conds > 1 ? o.conds[1].value : 0;
+    if (o.kind == QK_OP_MEASURE) {
+      if (o.qubit < 0 || o.qubit >= n) return bfail(b, QK_E_ARG, where + "qubit out of range");
+      if (o.cbit < -1 || o.cbit >= ncbits) return bfail(b, QK_E_ARG, where + "cbit out of range");
+      if (!(o.u >= 0.0 && o.u < 1.0)) return bfail(b, QK_E_ARG, where + "u must be in [0, 1)");
+      if (o.n_conds) return bfail(b, QK_E_ARG, where + "measurements take no conditions");
+      d.kind = BK_MEAS;
+      d.t0 = o.qubit;
+      d.cbit = o.cbit;
+      d.u = o.u;
+    } else if (o.kind == QK_OP_GATE) {
+      int arity = 0, np = 0;
+      if (!builtin_info(o.gate, &arity, &np)) return bfail(b, QK_E_UNSUPPORTED, where + "batched circuits take builtin gates only");
+      if (o.n_targets != arity) return bfail(b, QK_E_ARG, where + "target count does not match the gate");
+      if (o.n_controls < 0 || o.n_controls > 4) return bfail(b, QK_E_ARG, where + "at most 4 controls");
+      uint32_t seen = 0;
+      for (int q = 0; q < o.n_targets + o.n_controls; ++q) {
+        const int x = q < o.n_targets ? o.targets[q] : o.controls[q - o.n_targets];
+        if (x < 0 || x >= n) return bfail(b, QK_E_ARG, where + "qubit index out of range");
+        if (seen & (1u << x)) return bfail(b, QK_E_ARG, where + "qubit used twice in one gate");
+        seen |= 1u << x;
+      }
+      uint32_t cm = 0;
+      for (int q = 0; q < o.n_controls; ++q) cm |= 1u << o.controls[q];
+      const BuiltinGate g = builtin_gate(o.gate, np ? o.param : 0.0);
+      d.t0 = o.targets[0];
+      d.t1 = arity > 1 ? o.targets[1] : 0;
+      switch (g.cls) {
+        case BG_DENSE1:
+          d.kind = BK_U1;
+          d.cmask = cm;
+          for (int e = 0; e < 4; ++e) {
+            d.m[2 * e] = g.m[e].real();
+            d.m[2 * e + 1] = g.m[e].imag();
+          }
+          break;
+        case BG_DIAG:
+          d.kind = arity == 1 ? BK_DIAG1 : BK_DIAG2;
+          d.cmask = cm;
+          for (size_t e = 0; e < g.m.size(); ++e) {
+            d.m[2 * e] = g.m[e].real();
+            d.m[2 * e + 1] = g.m[e].imag();
+          }
+          break;
+        case BG_PHASE:
+          d.kind = BK_PHASE;
+          d.cmask = cm | (1u << d.t0) | (arity > 1 ? (1u << d.t1) : 0u);
+          d.m[0] = g.z.real();
+          d.m[1] = g.z.imag();
+          break;
+        case BG_SWAP:
+          d.kind = BK_SWAP;
+          d.cmask = cm;
+          break;
+        default:
+          return bfail(b, QK_E_UNSUPPORTED, where + "gate class not supported in batches");
+      }
+    } else {
+      return bfail(b, QK_E_ARG, where + "unknown op kind");
+    }
+    hj.ops.push_back(d);
+  }
+  b->jobs.push_back(std::move(hj));
+  if (job) *job = (int32_t)b->jobs.size() - 1;
+  b->ran = false;
+  return QK_OK;
+}
+
+qk_status qk_batch_run(qk_batch b) {
+  if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
+  if (b->jobs.empty()) return QK_OK;
+  const size_t amp = b->c64 ? 8 : 16;
+  // layout: states and cbits in job order; the queue visits the largest jobs first
+  uint64_t soff = 0;
+  uint32_t coff = 0, ooff = 0;
+  int nmax = 0;
+  std::vector<BOp> all_ops;
+  std::vector<BJob> table;
+  for (auto& j : b->jobs) {
+    j.state_off = soff;
+    j.cbit_off = coff;
+    soff += 1ull << j.n;
+    coff += (uint32_t)j.ncbits;
+    nmax = std::max(nmax, j.n);
+  }
+  std::vector<int> order(b->jobs.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    const auto& a = b->jobs[x];
+    const auto& c = b->jobs[y];
+    return ((uint64_t)a.ops.size() << a.n) > ((uint64_t)c.ops.size() << c.n);
+  });
+  for (int id : order) {
+    const auto& j = b->jobs[id];
+    BJob t{};
+    t.state_off = j.state_off;
+    t.op_begin = ooff;
+    all_ops.insert(all_ops.end(), j.ops.begin(), j.ops.end());
+    ooff += (uint32_t)j.ops.size();
+    t.op_end = ooff;
+    t.n = j.n;
+    t.ncbits = j.ncbits;
+    t.cbit_off = j.cbit_off;
+    table.push_back(t);
+  }
+  qk_status st;
+  if ((st = bensure(b, b->d_states, b->states_bytes, soff * amp, "batch states"))) return st;
+  if ((st = bensure(b, b->d_cbits, b->cbits_bytes, std::max<size_t>(coff, 1), "batch cbits"))) return st;
+  if ((st = bensure(b, b->d_ops, b->ops_bytes, std::max<size_t>(all_ops.size(), 1) * sizeof(BOp), "batch ops"))) return st;
+  if ((st = bensure(b, b->d_jobs, b->jobs_bytes, table.size() * sizeof(BJob), "batch job table"))) return st;
+  if (!b->d_counter) {
+    size_t cb = 0;
+    void* c = nullptr;
+    if ((st = bensure(b, c, cb, sizeof(int), "batch counter"))) return st;
+    b->d_counter = (int*)c;
+  }
+  hipError_t e = hipSuccess;
+  if (!all_ops.empty())
+    e = hipMemcpyAsync(b->d_ops, all_ops.data(), all_ops.size() * sizeof(BOp), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->d_jobs, table.data(), table.size() * sizeof(BJob), hipMemcpyHostToDevice, b->stream);
+  if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
+  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, b->stream, b->d_counter);
+  const size_t shm = ((size_t)1 << nmax) * amp;
+  int ncu = 256, dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int per_cu = std::max<int>(1, (int)(160 * 1024 / (shm + 4096)));
+  const unsigned grid = (unsigned)std::max<size_t>(1, std::min<size_t>(table.size(), (size_t)ncu * std::min(per_cu, 4)));
+  if (b->c64) {
+    static bool set = false;
+    if (!set) {
+      (void)hipFuncSetAttribute((const void*)k_batch<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+      set = true;
+    }
+    hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBatchThreads), shm, b->stream, (const BJob*)b->d_jobs,
+                       (int)table.size(), (const BOp*)b->d_ops, (EVb<float>::T*)b->d_states, (uint8_t*)b->d_cbits,
+                       b->d_counter);
+  } else {
+    static bool set = false;
+    if (!set) {
+      (void)hipFuncSetAttribute((const void*)k_batch<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+      set = true;
+    }
+    hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBatchThreads), shm, b->stream, (const BJob*)b->d_jobs,
+                       (int)table.size(), (const BOp*)b->d_ops, (EVb<double>::T*)b->d_states, (uint8_t*)b->d_cbits,
+                       b->d_counter);
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
+  b->ran = true;
+  return QK_OK;
+}
+
+qk_status qk_batch_sync(qk_batch b) {
+  if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
+  hipError_t e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch: ") + hipGetErrorString(e));
+  return QK_OK;
+}
+
+qk_status qk_batch_get_state(qk_batch b, int32_t job, void* host_out, size_t bytes) {
+  if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
+  if (job < 0 || job >= (int)b->jobs.size()) return bfail(b, QK_E_ARG, "job index out of range");
+  if (!b->ran) return bfail(b, QK_E_STATE, "batch has not run since the job was added");
+  const size_t amp = b->c64 ? 8 : 16;
+  const auto& j = b->jobs[job];
+  const size_t need = ((size_t)1 << j.n) * amp;
+  if (!host_out || bytes != need) return bfail(b, QK_E_ARG, "buffer size must be 2^n * amplitude size");
+  hipError_t e = hipMemcpyAsync(host_out, (char*)b->d_states + j.state_off * amp, need, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch readback: ") + hipGetErrorString(e));
+  return QK_OK;
+}
+
+qk_status qk_batch_read_cbits(qk_batch b, int32_t job, uint8_t* out, int32_t n) {
+  if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
+  if (job < 0 || job >= (int)b->jobs.size()) return bfail(b, QK_E_ARG, "job index out of range");
+  if (!b->ran) return bfail(b, QK_E_STATE, "batch has not run since the job was added");
+  const auto& j = b->jobs[job];
+  if (n < 0 || n > j.ncbits || (n > 0 && !out)) return bfail(b, QK_E_ARG, "bad cbit count");
+  hipError_t e = hipSuccess;
+  if (n > 0) e = hipMemcpyAsync(out, (char*)b->d_cbits + j.cbit_off, (size_t)n, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+  if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch readback: ") + hipGetErrorString(e));
+  return QK_OK;
+}
+
+qk_status qk_batch_state_ptr(qk_batch b, int32_t job, void** dev_ptr, size_t* bytes) {
+  if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
+  if (job < 0 || job >= (int)b->jobs.size()) return bfail(b, QK_E_ARG, "job index out of range");
+  if (!b->ran) return bfail(b, QK_E_STATE, "batch has not run since the job was added");
+  const size_t amp = b->c64 ? 8 : 16;
+  const auto& j = b->jobs[job];
+  if (dev_ptr) *dev_ptr = (char*)b->d_states + j.state_off * amp;
+  if (bytes) *bytes = ((size_t)1 << j.n) * amp;
+  return QK_OK;
+}
+
+qk_status qk_batch_clear(qk_batch b) {
+  if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
+  b->jobs.clear();
+  b->ran = false;
+  return QK_OK;
+}
+
+qk_status qk_batch_num_jobs(qk_batch b, int32_t* n) {
+  if (!b || !n) return bfail(b, QK_E_ARG, "NULL argument");
+  *n = (int32_t)b->jobs.size();
+  return QK_OK;
+}
+
+}  // extern "C"

@@ -108,6 +108,19 @@ bool mfma_supported(int n, int k, int nc, bool c64);
 hipError_t launch_dense_mfma(const Launch& L, const int* targets, int k, const int* controls, int nc,
                              const void* d_matrix, int waves_per_cu);
 
+// ---- builtin gates (api.hip) --------------------------------------------------
+// Sweep class of a builtin gate and its FP64 data: BG_DENSE1 (2x2 matrix in m,
+// row-major), BG_PHASE (factor z on the all-ones subspace of targets and
+// controls), BG_DIAG (diagonal in m over the targets), BG_SWAP.
+enum BuiltinClass { BG_DENSE1 = 1, BG_PHASE = 2, BG_DIAG = 3, BG_SWAP = 4 };
+struct BuiltinGate {
+  int cls = 0;
+  std::vector<cd> m;
+  cd z = 1.0;
+};
+bool builtin_info(int id, int* arity, int* nparams);
+BuiltinGate builtin_gate(int id, double param);
+
 // ---- fusion planner (fusion.cpp) --------------------------------------------
 struct FGate {
   std::vector<int> qubits;   // ascending: union of targets and controls

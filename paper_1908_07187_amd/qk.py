@@ -44,6 +44,16 @@ class QkAllocator(C.Structure):
     _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
 
 
+QK_OP_GATE, QK_OP_MEASURE = 1, 2
+
+
+class QkOp(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("gate", C.c_int32), ("targets", C.c_int32 * 2), ("n_targets", C.c_int32),
+                ("controls", C.c_int32 * 4), ("n_controls", C.c_int32), ("conds", QkCond * 2),
+                ("n_conds", C.c_int32), ("param", C.c_double), ("qubit", C.c_int32), ("cbit", C.c_int32),
+                ("u", C.c_double)]
+
+
 SIGNATURES = {
     "qk_create": (_I32, [_I32, C.POINTER(QkAllocator), _P, C.POINTER(_P)]),
     "qk_destroy": (_I32, [_P]),
@@ -72,6 +82,22 @@ SIGNATURES = {
     "qk_set_tuning": (_I32, [_P, C.c_char_p, _I32]),
     "qk_get_tuning": (_I32, [_P, C.c_char_p, _I32P]),
     "qk_stats": (_I32, [_P, _I64P, _I64P, _I64P]),
+    "qk_reset": (_I32, [_P]),
+    "qk_capture_begin": (_I32, [_P]),
+    "qk_capture_end": (_I32, [_P, C.POINTER(_P)]),
+    "qk_graph_launch": (_I32, [_P]),
+    "qk_graph_destroy": (_I32, [_P]),
+    "qk_batch_create": (_I32, [_I32, C.POINTER(QkAllocator), _P, C.POINTER(_P)]),
+    "qk_batch_destroy": (_I32, [_P]),
+    "qk_batch_add": (_I32, [_P, _I32, _I32, C.POINTER(QkOp), _I32, _I32P]),
+    "qk_batch_run": (_I32, [_P]),
+    "qk_batch_sync": (_I32, [_P]),
+    "qk_batch_get_state": (_I32, [_P, _I32, _P, _SZ]),
+    "qk_batch_read_cbits": (_I32, [_P, _I32, _U8P, _I32]),
+    "qk_batch_state_ptr": (_I32, [_P, _I32, C.POINTER(_P), C.POINTER(_SZ)]),
+    "qk_batch_clear": (_I32, [_P]),
+    "qk_batch_num_jobs": (_I32, [_P, _I32P]),
+    "qk_batch_last_error": (C.c_char_p, [_P]),
     "qk_last_error": (C.c_char_p, [_P]),
     "qk_status_string": (C.c_char_p, [_I32]),
 }
@@ -320,3 +346,109 @@ class Sim:
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
         self._chk(self.lib.qk_stats(self.h, C.byref(a), C.byref(b), C.byref(c)))
         return {"sweeps": a.value, "fused_blocks": b.value, "fused_gates": c.value}
+
+
+# ------------------------------------------------------------------ graphs
+
+class Graph:
+    """A captured sequence of calls on one Sim, replayed with one launch."""
+
+    def __init__(self, sim: "Sim", handle):
+        self.sim = sim
+        self.h = handle
+
+    def launch(self):
+        self.sim._chk(self.sim.lib.qk_graph_launch(self.h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.sim._chk(self.sim.lib.qk_graph_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _sim_reset(self):
+    self._chk(self.lib.qk_reset(self.h))
+
+
+def _sim_capture_begin(self):
+    self._chk(self.lib.qk_capture_begin(self.h))
+
+
+def _sim_capture_end(self) -> Graph:
+    g = C.c_void_p()
+    self._chk(self.lib.qk_capture_end(self.h, C.byref(g)))
+    return Graph(self, g)
+
+
+Sim.reset = _sim_reset
+Sim.capture_begin = _sim_capture_begin
+Sim.capture_end = _sim_capture_end
+
+
+# ------------------------------------------------------------------ batches
+
+class Batch:
+    """Many small circuits (builtin gates + measurements) in one persistent launch."""
+
+    def __init__(self, dtype: str = "c128", stream=None, device: int = 0):
+        self.lib = load()
+        self.dtype = dtype
+        self.np_dtype = np.complex64 if DTYPES[dtype] == QK_C64 else np.complex128
+        self._dev = _TorchDevice(stream, device)
+        h = C.c_void_p()
+        st = self.lib.qk_batch_create(DTYPES[dtype], C.byref(self._dev.allocator),
+                                      C.c_void_p(self._dev.stream_handle), C.byref(h))
+        if st != QK_OK:
+            raise QKError(st, self.lib.qk_batch_last_error(None).decode())
+        self.h = h
+        self.jobs = []          # (n, ncbits)
+
+    def _chk(self, st):
+        if st != QK_OK:
+            raise QKError(st, self.lib.qk_batch_last_error(self.h).decode())
+
+    def add(self, n: int, ncbits: int, ops) -> int:
+        arr = (QkOp * max(1, len(ops)))(*ops)
+        job = C.c_int32()
+        self._chk(self.lib.qk_batch_add(self.h, n, ncbits, arr, len(ops), C.byref(job)))
+        self.jobs.append((n, ncbits))
+        return job.value
+
+    def run(self):
+        self._chk(self.lib.qk_batch_run(self.h))
+
+    def sync(self):
+        self._chk(self.lib.qk_batch_sync(self.h))
+
+    def state(self, job: int) -> np.ndarray:
+        n = self.jobs[job][0]
+        out = np.empty(1 << n, dtype=self.np_dtype)
+        self._chk(self.lib.qk_batch_get_state(self.h, job, C.c_void_p(out.ctypes.data), out.nbytes))
+        return out
+
+    def cbits(self, job: int) -> np.ndarray:
+        nc = self.jobs[job][1]
+        out = np.zeros(max(1, nc), dtype=np.uint8)
+        self._chk(self.lib.qk_batch_read_cbits(self.h, job, out.ctypes.data_as(_U8P), nc))
+        return out[:nc]
+
+    def clear(self):
+        self._chk(self.lib.qk_batch_clear(self.h))
+        self.jobs = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._chk(self.lib.qk_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -132,3 +132,43 @@ def test_status_strings():
 
 def test_package_exposes_runner():
     assert hasattr(qkpkg, "run_circuit") and hasattr(qkpkg, "Sim")
+
+
+def test_batch_host_validation():
+    lib = qk.load()
+    h = C.c_void_p()
+    assert lib.qk_batch_create(qk.QK_C128, None, None, C.byref(h)) == 0
+    op = qk.QkOp()
+    op.kind = qk.QK_OP_GATE
+    op.gate = 1
+    op.n_targets = 1
+    op.targets[0] = 0
+    ops = (qk.QkOp * 1)(op)
+    job = C.c_int32()
+    assert lib.qk_batch_add(h, 14, 0, ops, 1, C.byref(job)) == -1      # too many qubits for c128
+    assert lib.qk_batch_add(h, 4, 0, ops, 1, C.byref(job)) == 0 and job.value == 0
+    op.gate = 0x100                                                    # user gates are not batched
+    ops = (qk.QkOp * 1)(op)
+    assert lib.qk_batch_add(h, 4, 0, ops, 1, C.byref(job)) == -7
+    op.gate = 1
+    op.targets[0] = 4                                                  # out of range
+    ops = (qk.QkOp * 1)(op)
+    assert lib.qk_batch_add(h, 4, 0, ops, 1, C.byref(job)) == -1
+    m = qk.QkOp()
+    m.kind = qk.QK_OP_MEASURE
+    m.qubit, m.cbit, m.u = 1, 2, 0.5                                   # cbit out of range
+    assert lib.qk_batch_add(h, 4, 2, (qk.QkOp * 1)(m), 1, C.byref(job)) == -1
+    n = C.c_int32()
+    assert lib.qk_batch_num_jobs(h, C.byref(n)) == 0 and n.value == 1
+    assert lib.qk_batch_destroy(h) == 0
+
+
+def test_circuit_to_batch_records():
+    import workloads as W
+    from paper_1908_07187_amd.batch import circuit_ops
+    c = W.c0_random_layers(n=5, layers=2, seed=1)
+    c.ops += [W.add_cbits(1), W.measure(2, cbit=0, u=0.25), W.gate("X", [1], conds=[(0, 1)])]
+    ops = circuit_ops(c)
+    assert len(ops) == len([o for o in c.ops if o.kind in ("gate", "measure")])
+    assert ops[-1].n_conds == 1 and ops[-1].conds[0].cbit == 0 and ops[-1].conds[0].value == 1
+    assert ops[-2].kind == qk.QK_OP_MEASURE and ops[-2].u == 0.25

@@ -1,0 +1,166 @@
+"""Batched execution (persistent multi-circuit kernel) and captured graphs,
+against the oracle and against the per-gate path, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from workloads.circuits import rng_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _jobs(seed, count, n_range=(2, 13), depth_range=(3, 25)):
+    rng = rng_for(seed)
+    out = []
+    for _ in range(count):
+        c, _ = W.c4_job(rng, n_range=n_range, depth_range=depth_range, p_measure=0.5)
+        out.append(c)
+    return out
+
+
+def _check(ref, got, dtype):
+    d = np.max(np.abs(got.astype(np.complex128) - ref))
+    if dtype == "c128":
+        assert d <= 1e-12, d
+    else:
+        assert d <= 2e-5, d
+        f = abs(np.vdot(ref, got.astype(np.complex128))) ** 2
+        assert f >= 1 - 1e-6
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_batch_matches_oracle(dtype):
+    import paper_1908_07187_amd as qk
+    jobs = _jobs(1, 40, n_range=(2, 13 if dtype == "c128" else 14))
+    b = qk.Batch(dtype)
+    ids = [qk.add_circuit(b, c) for c in jobs]
+    print(f"[gpu-batch] {len(jobs)} jobs dtype={dtype}", flush=True)
+    b.run()
+    b.sync()
+    for c, j in zip(jobs, ids):
+        ref, rcb, recs = oracle.run(c)
+        if any(abs(r.u - r.P0) <= 1e-9 for r in recs):
+            continue
+        assert list(b.cbits(j)) == list(rcb)
+        _check(ref, b.state(j), dtype)
+    b.close()
+
+
+def test_batch_result_independent_of_company():
+    """A job's result is bit-identical alone and in a mixed batch (fixed-order reductions)."""
+    import paper_1908_07187_amd as qk
+    jobs = _jobs(2, 30)
+    mix = qk.Batch("c128")
+    ids = [qk.add_circuit(mix, c) for c in jobs]
+    mix.run()
+    for c, j in list(zip(jobs, ids))[:10]:
+        alone = qk.Batch("c128")
+        a = qk.add_circuit(alone, c)
+        alone.run()
+        assert np.array_equal(alone.state(a), mix.state(j))
+        assert np.array_equal(alone.cbits(a), mix.cbits(j))
+        alone.close()
+    mix.close()
+
+
+def test_batch_matches_per_gate_path():
+    import paper_1908_07187_amd as qk
+    jobs = _jobs(3, 12, n_range=(6, 13))
+    b = qk.Batch("c128")
+    ids = [qk.add_circuit(b, c) for c in jobs]
+    b.run()
+    for c, j in zip(jobs, ids):
+        s = qk.run_circuit(c, dtype="c128")
+        assert np.max(np.abs(s.state() - b.state(j))) <= 1e-12
+        assert list(s.read_cbits()) == list(b.cbits(j))
+        s.close()
+    b.close()
+
+
+def test_batch_rerun_and_clear():
+    import paper_1908_07187_amd as qk
+    jobs = _jobs(4, 5)
+    b = qk.Batch("c128")
+    ids = [qk.add_circuit(b, c) for c in jobs]
+    b.run()
+    first = [b.state(j) for j in ids]
+    b.run()
+    for j, f in zip(ids, first):
+        assert np.array_equal(b.state(j), f)
+    b.clear()
+    more = _jobs(5, 3)
+    ids2 = [qk.add_circuit(b, c) for c in more]
+    b.run()
+    for c, j in zip(more, ids2):
+        ref, _, _ = oracle.run(c)
+        _check(ref, b.state(j), "c128")
+    b.close()
+
+
+@pytest.mark.parametrize("fusion", [0, 4])
+def test_graph_replays_match_eager(fusion):
+    """Capture reset + a 12-qubit circuit with a measurement and a conditioned
+    gate; replay it several times with eager work and syncs in between; every
+    replay equals the eager result."""
+    import paper_1908_07187_amd as qk
+    c = W.c0_random_layers(n=12, layers=10, seed=6, rzz=True)
+    c.ops += [W.add_cbits(1), W.measure(3, cbit=0, u=0.41), W.gate("H", [8], conds=[(0, 1)]),
+              W.gate("RZ", [2], params=(0.3,))]
+    ref, rcb, _ = oracle.run(c)
+    eager = qk.run_circuit(c, dtype="c128", fusion=fusion)
+    est = eager.state()
+    s = qk.Sim("c128")
+    s.add_qubits(12)
+    s.add_cbits(1)
+    if fusion:
+        s.set_fusion(fusion)
+    prog = qk.Program(W.Circuit([op for op in c.ops if op.kind not in ("add_qubits", "add_cbits")],
+                                user_gates=c.user_gates))
+    s.capture_begin()
+    s.reset()
+    prog.run(s)
+    g = s.capture_end()
+    for rep in range(4):
+        print(f"[gpu-graph] replay {rep} fusion={fusion}", flush=True)
+        g.launch()
+        got = s.state()
+        assert np.array_equal(got, est)
+        assert list(s.read_cbits()) == list(rcb)
+        # eager work between replays
+        eager.apply("H", [rep])
+        eager.sync()
+    assert np.max(np.abs(est - ref)) <= 1e-12
+    g.close()
+    s.close()
+    eager.close()
+
+
+def test_graph_with_device_uniform_changes_between_replays():
+    import torch
+    import paper_1908_07187_amd as qk
+    n = 8
+    base = W.c0_random_layers(n=n, layers=4, seed=8)
+    s = qk.Sim("c128")
+    s.add_qubits(n)
+    s.add_cbits(1)
+    d_u = torch.zeros(1, dtype=torch.float64, device="cuda")
+    prog = qk.Program(W.Circuit([op for op in base.ops if op.kind == "gate"]))
+    s.capture_begin()
+    s.reset()
+    prog.run(s)
+    s.measure_dev(5, 0, d_u.data_ptr())
+    g = s.capture_end()
+    for u in (0.05, 0.5, 0.95):
+        d_u.fill_(u)
+        torch.cuda.synchronize()
+        g.launch()
+        c = W.Circuit(base.ops + [W.add_cbits(1), W.measure(5, cbit=0, u=u)])
+        ref, rcb, recs = oracle.run(c)
+        if abs(recs[0].u - recs[0].P0) <= 1e-9:
+            continue
+        got = s.state()
+        assert list(s.read_cbits()) == list(rcb)
+        assert np.max(np.abs(got - ref)) <= 1e-12
+    g.close()
+    s.close()

@@ -1,0 +1,125 @@
+"""Parity at the benchmark's full sizes, in the launch configuration bench.py
+times (default tuning): sampled amplitudes the oracle computed offline
+(tests/golden/), properties that hold at any size (circuit then inverse = I,
+norm), and the oracle itself where it finishes in seconds (24-qubit QFT)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _say(msg):
+    print(f"[gpu-full] {msg}", flush=True)
+
+
+def _sim_run(circ, dtype, fusion=0):
+    import paper_1908_07187_amd as qk
+    return qk.run_circuit(circ, dtype=dtype, fusion=fusion)
+
+
+def _fid(a, b):
+    ip = a.inner(b)
+    return abs(ip) ** 2 / (a.norm2() * b.norm2())
+
+
+def _samples(sim, idx):
+    import torch
+    ptr, nbytes = sim.state_ptr()
+    # read the sampled amplitudes through a zero-copy device view
+    dt = torch.complex128 if sim.dtype == "c128" else torch.complex64
+    n = nbytes // (16 if sim.dtype == "c128" else 8)
+
+    class _View:
+        __cuda_array_interface__ = {"shape": (n,), "typestr": "<c16" if sim.dtype == "c128" else "<c8",
+                                    "data": (ptr, False), "version": 3}
+    t = torch.as_tensor(_View(), device="cuda")
+    assert t.dtype == dt
+    sel = t[torch.as_tensor(idx, device="cuda")]
+    return sel.cpu().numpy().astype(np.complex128)
+
+
+def test_random26_depth40_matches_oracle_samples():
+    with open(os.path.join(GOLDEN, "random26_d40_seed0_samples.json")) as f:
+        g = json.load(f)
+    circ = W.c2_random_rzz(n=g["n"], depth=g["depth"], seed=g["seed"])
+    ref = np.array(g["re"]) + 1j * np.array(g["im"])
+    idx = np.array(g["indices"], dtype=np.int64)
+    _say("26q depth 40 c128 per gate")
+    a = _sim_run(circ, "c128")
+    got = _samples(a, idx)
+    assert np.max(np.abs(got - ref)) <= 1e-12
+    assert abs(a.norm2() - 1.0) <= 1e-12
+    _say("26q depth 40 c64 fused k=5")
+    b = _sim_run(circ, "c64", fusion=5)
+    got64 = _samples(b, idx)
+    assert np.max(np.abs(got64 - ref)) <= 2e-5
+    assert _fid(a, b) >= 1 - 1e-6
+    _say("26q depth 40 c128 fused k=5")
+    c = _sim_run(circ, "c128", fusion=5)
+    assert np.max(np.abs(_samples(c, idx) - ref)) <= 1e-12
+    for s in (a, b, c):
+        s.close()
+
+
+def test_random30_depth40_forward_then_inverse_is_identity():
+    """30 qubits, complex128, gate by gate: the circuit followed by its inverse
+    returns |0...0> with amplitude 1 (phase included)."""
+    circ = W.c2_random_rzz(n=30, depth=40, seed=0)
+    inv = W.inverse(circ)
+    full = W.Circuit(circ.ops + inv.ops, user_gates=inv.user_gates, label="random30_roundtrip")
+    _say("30q forward+inverse c128 per gate")
+    s = _sim_run(full, "c128")
+    idx = np.array([0, 1, 2, 3, 1 << 29, (1 << 30) - 1, 123456789], dtype=np.int64)
+    got = _samples(s, idx)
+    assert abs(got[0] - 1.0) <= 1e-12
+    assert np.max(np.abs(got[1:])) <= 1e-12
+    assert abs(s.norm2() - 1.0) <= 1e-12
+    s.close()
+
+
+def test_random30_c64_fused_fidelity_against_c128():
+    circ = W.c2_random_rzz(n=30, depth=40, seed=0)
+    _say("30q c128 per gate")
+    a = _sim_run(circ, "c128")
+    _say("30q c64 fused k=5")
+    b = _sim_run(circ, "c64", fusion=5)
+    f = _fid(a, b)
+    _say(f"fidelity {f!r}")
+    assert f >= 1 - 1e-6
+    assert abs(b.norm2() - 1.0) <= 1e-5
+    a.close()
+    b.close()
+
+
+def test_qft24_forward_matches_oracle_and_ifft():
+    n = 24
+    c = W.c1_qft_roundtrip(n=n, seed=1, roundtrip=False)
+    _say("oracle QFT 24q")
+    ref, _, _ = oracle.run(c, omp=True)
+    for fusion in (0, 5):
+        _say(f"GPU QFT 24q fusion={fusion}")
+        s = _sim_run(c, "c128", fusion=fusion)
+        got = s.state()
+        s.close()
+        assert np.max(np.abs(got - ref)) <= 1e-12
+    assert np.max(np.abs(got - math.sqrt(1 << n) * np.fft.ifft(c.init_state))) <= 1e-12
+
+
+@pytest.mark.parametrize("fusion", [0, 5])
+def test_qft26_roundtrip_returns_input(fusion):
+    c = W.c1_qft_roundtrip(n=26, seed=2)
+    _say(f"QFT+inverse 26q fusion={fusion}")
+    s = _sim_run(c, "c128", fusion=fusion)
+    idx = np.random.Generator(np.random.PCG64(3)).choice(1 << 26, size=4096, replace=False)
+    got = _samples(s, idx)
+    assert np.max(np.abs(got - c.init_state[idx])) <= 1e-12
+    assert abs(s.norm2() - 1.0) <= 1e-12
+    s.close()
