@@ -46,6 +46,11 @@ def parse():
     ap.add_argument("--no-fused", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gates", type=int, default=16, help="gates of the circuit the oracle sample runs")
+    ap.add_argument("--workload", default="random30", choices=["random30", "batch12", "serve", "qft26", "ipe21"],
+                    help="random30 (default): the 30-qubit depth-40 circuit; the others are the batching, "
+                         "serving, QFT and phase-estimation forms")
+    ap.add_argument("--serve-jobs", type=int, default=400)
+    ap.add_argument("--batch-circuits", type=int, default=2048)
     ap.add_argument("--kernels-only", action="store_true",
                     help="run only a few strided-butterfly sweeps and a plain copy of known size (for PMC counters)")
     return ap.parse_args()
@@ -142,6 +147,10 @@ def main():
     qk.load(build_if_missing=True)
     if args.kernels_only:
         kernels_only(qk, torch)
+        return
+    if args.workload != "random30":
+        from paper_1908_07187_amd import benchforms
+        print(json.dumps(benchforms.run(args.workload, args, qk, torch)), flush=True)
         return
 
     n, depth = args.qubits, args.depth

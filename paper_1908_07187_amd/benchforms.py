@@ -1,0 +1,217 @@
+"""Measurement of the system forms (used by ``bench.py --workload ...``).
+
+batch12  12-qubit, 20-layer random circuits (one-qubit layer + 6 CNOTs per
+         layer) in complex128: circuits/s gate by gate on one stream, as
+         replays of a captured graph, and in the persistent batch kernel.
+serve    the serving mix (qubits U{8..26}, depth U{10..60}, complex64 or
+         complex128, 30 % with a mid-circuit measurement steering a gate):
+         closed-loop capacity, then Poisson arrivals at 0.8x capacity with
+         p50/p99 latency, and fidelity of sampled jobs against the complex128
+         gate-by-gate path run alone.
+qft26    QFT + inverse QFT on a random 26-qubit complex128 state, gate by gate
+         and with fused 5-qubit blocks.
+ipe21    the 21-qubit iterative phase estimation (20 stages of controlled
+         affine permutation, cbit-steered RZ, measure-and-reset), complex128.
+"""
+from __future__ import annotations
+
+import sys
+import time
+
+import numpy as np
+
+METRIC = "amplitude-updates/s & HBM GB/s at 30 qubits; served circuits/s + p99 latency"
+
+
+def _say(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _base(args, value, unit, config, dtype, ms_per_step=None):
+    return {"metric": METRIC, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": config}
+
+
+def batch12(args, qk, torch):
+    import workloads as W
+    nc = args.batch_circuits
+    circs = [W.c0_random_layers(n=12, layers=20, seed=s) for s in range(nc)]
+    # (a) gate by gate, one simulator, eager launches
+    sim = qk.Sim("c128")
+    sim.add_qubits(12)
+    progs = [qk.Program(W.Circuit([o for o in c.ops if o.kind == "gate"])) for c in circs[:200]]
+    for p in progs[:5]:
+        sim.reset()
+        p.run(sim)
+    sim.sync()
+    t0 = time.perf_counter()
+    for p in progs:
+        sim.reset()
+        p.run(sim)
+    sim.sync()
+    eager_cps = len(progs) / (time.perf_counter() - t0)
+    sim.close()
+    _say(f"batch12 eager gate-by-gate: {eager_cps:.1f} circuits/s")
+    # (b) captured graph replays (one graph per circuit structure; replay the same circuit)
+    s2 = qk.Sim("c128", stream=torch.cuda.Stream())
+    s2.add_qubits(12)
+    s2.capture_begin()
+    s2.reset()
+    progs[0].run(s2)
+    g = s2.capture_end()
+    for _ in range(5):
+        g.launch()
+    s2.sync()
+    reps = 500
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.launch()
+    s2.sync()
+    graph_cps = reps / (time.perf_counter() - t0)
+    g.close()
+    s2.close()
+    _say(f"batch12 graph replay: {graph_cps:.1f} circuits/s")
+    # (c) persistent batch kernel, all circuits in one launch
+    b = qk.Batch("c128")
+    for c in circs:
+        qk.add_circuit(b, c)
+    for _ in range(max(1, args.warmup)):
+        b.run()
+    b.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.run()
+    b.sync()
+    dt = (time.perf_counter() - t0) / args.steps
+    batch_cps = nc / dt
+    b.close()
+    _say(f"batch12 persistent batch: {batch_cps:.1f} circuits/s ({nc} circuits per launch, {dt*1e3:.2f} ms)")
+    gates = len(circs[0].gate_ops())
+    out = _base(args, batch_cps, "circuits/s",
+                {"workload": f"{nc} random 12-qubit circuits, 20 layers ({gates} gates each), complex128, "
+                             f"one persistent launch", "n_qubits": 12, "layers": 20, "circuits": nc},
+                "f64", dt * 1e3)
+    out["forms"] = {"eager_gate_by_gate_cps": eager_cps, "graph_replay_cps": graph_cps, "persistent_batch_cps": batch_cps}
+    return out
+
+
+def serve(args, qk, torch):
+    import workloads as W
+    from .serve import Server
+    nj = args.serve_jobs
+    jobs = W.c4_job_stream(nj, seed=args.seed, rate=1.0)
+    sample = set(range(0, nj, 100))
+    # closed loop: every job at t = 0 -> capacity
+    warm = W.c4_job_stream(20, seed=args.seed + 1, rate=1.0)
+    Server(slots=8).serve(warm, realtime=False)
+    _say(f"serve: closed loop over {nj} jobs")
+    rep0 = Server(slots=8).serve(jobs, realtime=False)
+    cap = rep0.circuits_per_s
+    _say(f"serve closed-loop capacity {cap:.1f} circuits/s, wall {rep0.wall_s:.1f} s")
+    rate = 0.8 * cap
+    jobs_p = W.c4_job_stream(nj, seed=args.seed, rate=rate)
+    rep = Server(slots=8, keep_states=sample).serve(jobs_p, realtime=True)
+    _say(f"serve at {rate:.1f}/s: {rep.circuits_per_s:.1f} circuits/s p50 {rep.p50_ms:.1f} ms p99 {rep.p99_ms:.1f} ms")
+    fids = []
+    for i in sorted(sample):
+        _, circ, dt = jobs_p[i]
+        r = rep.results[i]
+        if r.state is None:
+            continue
+        ref = qk.run_circuit(circ, dtype="c128")
+        got = r.state.astype(np.complex128)
+        a = ref.state()
+        ref.close()
+        fids.append(abs(np.vdot(a, got)) ** 2 / (np.vdot(a, a).real * np.vdot(got, got).real))
+    ns = [c.n_qubits for _, c, _ in jobs_p]
+    out = _base(args, rep.circuits_per_s, "circuits/s",
+                {"workload": f"serving mix: {nj} jobs, qubits U{{8..26}}, depth U{{10..60}}, complex64/complex128 "
+                             f"50/50, 30% with a mid-circuit measurement feeding a classical control; Poisson "
+                             f"arrivals at 0.8x the closed-loop capacity", "jobs": nj, "rate_per_s": rate},
+                "f32/f64")
+    out["latency_ms"] = {"p50": rep.p50_ms, "p99": rep.p99_ms, "mean": rep.mean_ms}
+    out["closed_loop_capacity_cps"] = cap
+    out["batches"] = rep.batches
+    out["max_concurrent_streams"] = rep.max_concurrent_streams
+    out["fidelity_vs_c128_sampled"] = {"jobs": len(fids), "min": float(min(fids)) if fids else None}
+    out["mean_qubits"] = float(np.mean(ns))
+    return out
+
+
+def qft26(args, qk, torch):
+    import workloads as W
+    c = W.c1_qft_roundtrip(n=26, seed=args.seed)
+    prog = qk.Program(c)
+    upd = c.amp_updates()
+    res = {}
+    for fusion in (0, 4, 5):
+        times = []
+        for k in range(args.warmup + args.steps):
+            s = qk.Sim("c128")
+            if fusion:
+                s.set_fusion(fusion)
+            s.add_qubits(26)
+            s.set_state(c.init_state)          # the 1 GiB upload is outside the timed region
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _run_gates(prog, s)
+            s.sync()
+            if k >= args.warmup:
+                times.append(time.perf_counter() - t0)
+            st = s.stats()
+            s.close()
+        dt = sum(times) / len(times)
+        res[fusion] = {"ms": dt * 1e3, "amp_updates_per_s": upd / dt, "sweeps": st["sweeps"]}
+        _say(f"qft26 fusion={fusion}: {dt*1e3:.1f} ms, {upd/dt:.3e} amp-updates/s")
+    best = min(res, key=lambda f: res[f]["ms"])
+    out = _base(args, res[0]["amp_updates_per_s"], "amplitude-updates/s",
+                {"workload": "26-qubit QFT followed by the inverse QFT on a random complex128 state, gate by gate",
+                 "n_qubits": 26, "gates": len(c.gate_ops())}, "f64", res[0]["ms"])
+    out["fused"] = {str(k): v for k, v in res.items()}
+    out["best_fusion"] = best
+    return out
+
+
+def _run_gates(prog, sim):
+    lib, h = sim.lib, sim.h
+    from .runner import _gate_id
+    ids = {}
+    for it in prog.items:
+        if it[0] != 2:
+            continue
+        gid = ids.get(it[1])
+        if gid is None:
+            gid = ids[it[1]] = _gate_id(sim, it[1], prog.circuit.user_gates)
+        st = lib.qk_apply_gate(h, gid, it[2], it[3], it[4], it[5], it[6], it[7], it[8], it[9])
+        if st:
+            sim._chk(st)
+
+
+def ipe21(args, qk, torch):
+    import workloads as W
+    c = W.c3_ipe(m=20, seed=args.seed)
+    prog = qk.Program(c)
+    times = []
+    for k in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = qk.Sim("c128")
+        prog.run(s)
+        cb = s.read_cbits()
+        if k >= args.warmup:
+            times.append(time.perf_counter() - t0)
+        s.close()
+    dt = sum(times) / len(times)
+    ops = len([o for o in c.ops if o.kind in ("gate", "measure")])
+    _say(f"ipe21: {dt*1e3:.2f} ms per run ({ops} ops)")
+    out = _base(args, 1.0 / dt, "runs/s",
+                {"workload": "21-qubit iterative phase estimation: 20 stages of H, controlled affine permutation "
+                             "U^(2^j) on 20 target qubits, cbit-steered RZ, H, measure, conditioned reset; "
+                             "complex128", "n_qubits": 21, "ops": ops}, "f64", dt * 1e3)
+    out["cbits"] = "".join(str(int(x)) for x in cb)
+    return out
+
+
+def run(name, args, qk, torch):
+    return {"batch12": batch12, "serve": serve, "qft26": qft26, "ipe21": ipe21}[name](args, qk, torch)

@@ -1,0 +1,259 @@
+"""Continuous-batching circuit server over the C ABI.
+
+Jobs (a circuit and a dtype) arrive over time.  The loop, run on the host:
+
+* admits arrived jobs in arrival order while their state footprint
+  (2^n x 8 or 16 bytes) fits the HBM budget -- a job that can never fit is
+  refused with an error, never allowed to exhaust device memory;
+* packs admitted small jobs (<= 13 qubits complex128, <= 14 complex64) into
+  one persistent batch launch per dtype (``qk_batch_run``), up to two batch
+  launches in flight per dtype, so jobs that arrive while a batch runs go into
+  the next one;
+* gives every admitted large job its own stream slot and enqueues its whole
+  circuit there (optionally fused into matrix-core blocks); slots run
+  concurrently, so their sweeps overlap on the device;
+* polls completion events and, for each finished job, reads its cbits and a
+  digest (norm; for small jobs the whole state) back to the host, frees its
+  memory and records its latency (arrival -> result on the host).
+
+States stay resident in HBM for the whole circuit; nothing but the result
+crosses to the host.  A job's result does not depend on the other jobs in
+flight: every kernel is deterministic and every reduction runs in a fixed
+order that depends only on the job.
+"""
+from __future__ import annotations
+
+import time
+from collections import deque
+from dataclasses import dataclass, field
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import batch as _batch
+from .qk import Batch, QKError, Sim
+from .runner import Program
+
+SMALL_MAX = {"c128": 13, "c64": 14}
+AMP_BYTES = {"c128": 16, "c64": 8}
+
+
+@dataclass
+class JobResult:
+    index: int
+    n: int
+    dtype: str
+    path: str = ""                 # 'batch' | 'stream' | 'refused' | 'failed'
+    arrival: float = 0.0           # seconds since the server started
+    admitted: float = 0.0
+    done: float = 0.0
+    cbits: Optional[np.ndarray] = None
+    norm2: float = float("nan")
+    state: Optional[np.ndarray] = None
+    error: str = ""
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclass
+class ServeReport:
+    results: List[JobResult]
+    wall_s: float
+    completed: int
+    refused: int
+    failed: int
+    circuits_per_s: float
+    p50_ms: float
+    p99_ms: float
+    mean_ms: float
+    batches: int
+    max_concurrent_streams: int
+    extra: Dict = field(default_factory=dict)
+
+
+def footprint(n: int, dtype: str) -> int:
+    return (1 << n) * AMP_BYTES[dtype]
+
+
+class Server:
+    def __init__(self, hbm_budget: Optional[int] = None, slots: int = 8,
+                 fusion: Optional[Dict[str, int]] = None, keep_states: Sequence[int] = (),
+                 small_max: Optional[Dict[str, int]] = None, poll_sleep: float = 20e-6):
+        import torch
+        self.torch = torch
+        if hbm_budget is None:
+            free, total = torch.cuda.mem_get_info()
+            hbm_budget = int(0.85 * free)
+        self.budget = int(hbm_budget)
+        self.slots = slots
+        self.fusion = {"c128": 0, "c64": 5} if fusion is None else dict(fusion)
+        self.keep_states = set(keep_states)
+        self.small_max = dict(SMALL_MAX if small_max is None else small_max)
+        self.poll_sleep = poll_sleep
+
+    # ------------------------------------------------------------------
+    def serve(self, jobs: Sequence[Tuple[float, object, str]], realtime: bool = True) -> ServeReport:
+        """Run ``jobs`` = [(arrival_s, circuit, dtype)] (sorted by arrival).
+        realtime=False makes every job arrive at t = 0 (closed-loop saturation)."""
+        torch = self.torch
+        N = len(jobs)
+        res = [JobResult(i, c.n_qubits, dt) for i, (_, c, dt) in enumerate(jobs)]
+        arrivals = [a if realtime else 0.0 for a, _, _ in jobs]
+        streams = [torch.cuda.Stream() for _ in range(self.slots)]
+        free_slots = deque(range(self.slots))
+        bstreams = {dt: [torch.cuda.Stream(), torch.cuda.Stream()] for dt in ("c128", "c64")}
+        bpool = {dt: [Batch(dt, stream=s) for s in bstreams[dt]] for dt in ("c128", "c64")}
+        bfree = {dt: deque(range(2)) for dt in ("c128", "c64")}
+        pending: deque = deque()
+        inflight_stream = []   # (slot, sim, event, job index)
+        inflight_batch = []    # (dtype, pool index, event, [(job index, batch job id)])
+        used = 0
+        nxt = 0
+        finished = 0
+        nbatches = 0
+        max_conc = 0
+        t0 = time.perf_counter()
+
+        def now():
+            return time.perf_counter() - t0
+
+        while finished < N:
+            t = now()
+            while nxt < N and arrivals[nxt] <= t:
+                res[nxt].arrival = arrivals[nxt]
+                pending.append(nxt)
+                nxt += 1
+
+            # ---- completions
+            still = []
+            for slot, sim, ev, j in inflight_stream:
+                if ev.query():
+                    r = res[j]
+                    try:
+                        r.cbits = sim.read_cbits()
+                        r.norm2 = sim.norm2()
+                        if j in self.keep_states:
+                            r.state = sim.state()
+                    except QKError as e:
+                        r.path, r.error = "failed", str(e)
+                    r.done = now()
+                    sim.close()
+                    used -= footprint(r.n, r.dtype)
+                    free_slots.append(slot)
+                    finished += 1
+                else:
+                    still.append((slot, sim, ev, j))
+            inflight_stream = still
+            still = []
+            for dt, pi, ev, members in inflight_batch:
+                if ev.query():
+                    b = bpool[dt][pi]
+                    for j, bj in members:
+                        r = res[j]
+                        r.state = b.state(bj)
+                        r.cbits = b.cbits(bj)
+                        r.norm2 = float(np.vdot(r.state, r.state).real)
+                        r.done = now()
+                        used -= footprint(r.n, r.dtype)
+                        finished += 1
+                    b.clear()
+                    bfree[dt].append(pi)
+                else:
+                    still.append((dt, pi, ev, members))
+            inflight_batch = still
+
+            # ---- admission (arrival order; a job that does not fit yet waits, later small ones may pass)
+            small: Dict[str, List[int]] = {"c128": [], "c64": []}
+            keep = deque()
+            while pending:
+                j = pending.popleft()
+                _, circ, dt = jobs[j]
+                r = res[j]
+                fp = footprint(r.n, dt)
+                if fp > self.budget:
+                    r.path, r.error = "refused", f"state of {r.n} qubits ({fp} B) exceeds the HBM budget"
+                    r.done = now()
+                    finished += 1
+                    continue
+                if used + fp > self.budget:
+                    keep.append(j)
+                    continue
+                if r.n <= self.small_max[dt] and circ.init_state is None:
+                    if bfree[dt]:
+                        small[dt].append(j)
+                        used += fp
+                        r.admitted = now()
+                    else:
+                        keep.append(j)
+                    continue
+                if not free_slots:
+                    keep.append(j)
+                    continue
+                slot = free_slots.popleft()
+                used += fp
+                r.admitted = now()
+                r.path = "stream"
+                sim = None
+                try:
+                    sim = Sim(dt, stream=streams[slot])
+                    if self.fusion.get(dt, 0):
+                        sim.set_fusion(self.fusion[dt])
+                    Program(circ).run(sim)
+                    sim.flush()
+                    ev = torch.cuda.Event()
+                    ev.record(streams[slot])
+                    inflight_stream.append((slot, sim, ev, j))
+                except QKError as e:
+                    if sim is not None:
+                        sim.close()
+                    r.path, r.error = "failed", str(e)
+                    r.done = now()
+                    used -= fp
+                    free_slots.append(slot)
+                    finished += 1
+            pending = keep
+            for dt in ("c128", "c64"):
+                if not small[dt]:
+                    continue
+                pi = bfree[dt].popleft()
+                b = bpool[dt][pi]
+                members = []
+                for j in small[dt]:
+                    r = res[j]
+                    r.path = "batch"
+                    try:
+                        members.append((j, _batch.add_circuit(b, jobs[j][1])))
+                    except (QKError, ValueError) as e:
+                        r.path, r.error = "failed", str(e)
+                        r.done = now()
+                        used -= footprint(r.n, dt)
+                        finished += 1
+                if members:
+                    b.run()
+                    ev = torch.cuda.Event()
+                    ev.record(bstreams[dt][pi])
+                    inflight_batch.append((dt, pi, ev, members))
+                    nbatches += 1
+                else:
+                    bfree[dt].append(pi)
+            max_conc = max(max_conc, len(inflight_stream))
+            if finished < N and not pending and (nxt >= N or arrivals[nxt] > now()):
+                time.sleep(self.poll_sleep)
+            elif finished < N and pending and not (free_slots or any(bfree[d] for d in bfree)):
+                time.sleep(self.poll_sleep)
+
+        wall = now()
+        for dt in bpool:
+            for b in bpool[dt]:
+                b.close()
+        ok = [r for r in res if r.path in ("batch", "stream")]
+        lat = np.array([r.latency for r in ok]) * 1e3 if ok else np.array([0.0])
+        span = (max(r.done for r in ok) - min(r.arrival for r in ok)) if ok else wall
+        return ServeReport(results=res, wall_s=wall, completed=len(ok),
+                           refused=sum(r.path == "refused" for r in res),
+                           failed=sum(r.path == "failed" for r in res),
+                           circuits_per_s=len(ok) / span if span > 0 else float("nan"),
+                           p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
+                           mean_ms=float(lat.mean()), batches=nbatches, max_concurrent_streams=max_conc)

@@ -1,0 +1,60 @@
+"""The continuous-batching server: every job's result is the same alone and
+in the mix, matches the oracle, oversized jobs are refused and a failing job
+fails alone."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _stream(count, seed, n_range=(6, 20), depth_range=(4, 14), rate=300.0):
+    return W.c4_job_stream(count, seed=seed, rate=rate, n_range=n_range, depth_range=depth_range)
+
+
+def test_results_identical_alone_and_in_the_mix():
+    from paper_1908_07187_amd.serve import Server
+    jobs = _stream(24, seed=11)
+    print(f"[gpu-serve] mix of {len(jobs)} jobs", flush=True)
+    rep = Server(keep_states=range(len(jobs)), slots=4).serve(jobs)
+    assert rep.completed == len(jobs) and rep.failed == 0 and rep.refused == 0
+    assert rep.batches >= 1 and rep.max_concurrent_streams >= 2
+    for i, (_, circ, dt) in enumerate(jobs):
+        alone = Server(keep_states=[0], slots=4).serve([(0.0, circ, dt)])
+        a, m = alone.results[0], rep.results[i]
+        assert a.path == m.path
+        assert np.array_equal(a.state, m.state), (i, a.path, dt)
+        assert np.array_equal(a.cbits, m.cbits)
+
+
+def test_served_results_match_oracle():
+    from paper_1908_07187_amd.serve import Server
+    jobs = _stream(16, seed=12, n_range=(6, 18))
+    rep = Server(keep_states=range(len(jobs)), slots=3).serve(jobs)
+    for (_, circ, dt), r in zip(jobs, rep.results):
+        ref, rcb, recs = oracle.run(circ)
+        if any(abs(x.u - x.P0) <= 1e-9 for x in recs):
+            continue
+        assert list(r.cbits) == list(rcb)
+        got = r.state.astype(np.complex128)
+        d = np.max(np.abs(got - ref))
+        if dt == "c128":
+            assert d <= 1e-12
+        else:
+            f = abs(np.vdot(ref, got)) ** 2 / (np.vdot(ref, ref).real * np.vdot(got, got).real)
+            assert d <= 2e-5 and f >= 1 - 1e-6
+
+
+def test_admission_refuses_oversized_and_isolates_failure():
+    from paper_1908_07187_amd.serve import Server
+    good = _stream(6, seed=13, n_range=(6, 12))
+    big = W.c0_random_layers(n=24, layers=1, seed=1)          # 256 MiB at complex128
+    bad = W.Circuit([W.add_qubits(16), W.gate("H", [20])])    # qubit index out of range
+    jobs = [(0.0, big, "c128"), (0.0, bad, "c128")] + [(0.0, c, dt) for _, c, dt in good]
+    rep = Server(hbm_budget=64 << 20, slots=2).serve(jobs)
+    assert rep.results[0].path == "refused" and "budget" in rep.results[0].error
+    assert rep.results[1].path == "failed" and "out of range" in rep.results[1].error
+    assert all(r.path in ("batch", "stream") for r in rep.results[2:])
+    assert rep.completed == len(good)
