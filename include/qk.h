@@ -240,7 +240,11 @@ qk_status qk_sync(qk_sim sim);
  *                 (1, 2, 4; default 1 for complex128, 2 for complex64);
  *   "lane_items"  64-amplitude segments per wave of the cross-lane
  *                 butterfly (1, 2, 4; default 1 for complex128, 2 for complex64);
- *   "mfma_waves"  waves per compute unit for matrix-core sweeps (4..32).
+ *   "mfma_waves"  waves per compute unit for matrix-core sweeps (4..32);
+ *   "mfma_cols"   tile columns per wave for matrix-core sweeps (16, 32
+ *                 default, 64; capped by registers for large k);
+ *   "mfma_areg"   blocks of 5-6 qubits: 1 keeps the matrix fragments in
+ *                 registers, 0 (default) re-reads them from LDS per tile.
  * QK_E_ARG for an unknown key or value. */
 qk_status qk_set_tuning(qk_sim sim, const char* key, int32_t value);
 qk_status qk_get_tuning(qk_sim sim, const char* key, int32_t* value);
@@ -299,6 +303,18 @@ typedef struct qk_op {
 } qk_op;
 
 typedef struct qk_batch_s* qk_batch;
+
+/* Host only (no device work): the fused blocks qk_set_fusion(max_k) would
+ * form for a list of unconditioned builtin gates (op records as for
+ * batches).  *n_blocks receives the block count; for the first max_blocks
+ * blocks, block_masks[b] = the block's qubits as a bit mask, block_gates[b] =
+ * gates composed, and (if matrices != NULL) the 2^k x 2^k FP64 block matrices
+ * (row/column bit j <-> j-th lowest qubit of the mask, row-major, (re, im)
+ * interleaved) one after another in `matrices` (capacity matrices_len
+ * doubles).  Applying the blocks in order equals applying the gates in order. */
+qk_status qk_plan_fusion(int32_t n_qubits, const qk_op* ops, int32_t n_ops, int32_t max_k, int32_t* n_blocks,
+                         uint64_t* block_masks, int32_t* block_gates, int32_t max_blocks, double* matrices,
+                         size_t matrices_len);
 
 qk_status qk_batch_create(qk_dtype dtype, const qk_allocator* alloc, void* hip_stream, qk_batch* out);
 qk_status qk_batch_destroy(qk_batch batch);

@@ -1139,6 +1139,55 @@ qk_status qk_graph_destroy(qk_graph g) {
   return QK_OK;
 }
 
+
+qk_status qk_plan_fusion(int32_t n, const qk_op* ops, int32_t nops, int32_t max_k, int32_t* n_blocks,
+                         uint64_t* block_masks, int32_t* block_gates, int32_t max_blocks, double* matrices,
+                         size_t matrices_len) {
+  if (n < 1 || n > 64 || nops < 0 || (nops > 0 && !ops) || !n_blocks) return fail(nullptr, QK_E_ARG, "bad arguments");
+  if (max_k < 1 || max_k > QK_MAX_FUSION_K) return fail(nullptr, QK_E_ARG, "max_k must be 1..6");
+  std::vector<FGate> fg;
+  for (int i = 0; i < nops; ++i) {
+    const qk_op& o = ops[i];
+    int arity = 0, np = 0;
+    if (o.kind != QK_OP_GATE || o.n_conds != 0 || !builtin_info(o.gate, &arity, &np) || o.n_targets != arity ||
+        o.n_controls < 0 || o.n_controls > 4)
+      return fail(nullptr, QK_E_ARG, "op " + std::to_string(i) + ": only unconditioned builtin gates are planned");
+    uint64_t seen = 0;
+    for (int q = 0; q < o.n_targets + o.n_controls; ++q) {
+      const int x = q < o.n_targets ? o.targets[q] : o.controls[q - o.n_targets];
+      if (x < 0 || x >= n || ((seen >> x) & 1)) return fail(nullptr, QK_E_ARG, "op " + std::to_string(i) + ": bad qubit");
+      seen |= 1ull << x;
+    }
+    if (o.n_targets + o.n_controls > max_k)
+      return fail(nullptr, QK_E_ARG, "op " + std::to_string(i) + ": gate wider than max_k");
+    GateDesc d;
+    d.targets.assign(o.targets, o.targets + o.n_targets);
+    d.controls.assign(o.controls, o.controls + o.n_controls);
+    builtin_desc(o.gate, np ? o.param : 0.0, d);
+    fg.push_back(make_fgate(d.targets.data(), (int)d.targets.size(), d.controls.data(), (int)d.controls.size(),
+                            full_matrix(d)));
+  }
+  std::vector<FBlock> blocks = plan_blocks(fg, max_k);
+  *n_blocks = (int32_t)blocks.size();
+  size_t off = 0;
+  for (size_t b = 0; b < blocks.size() && (int)b < max_blocks; ++b) {
+    uint64_t m = 0;
+    for (int q : blocks[b].qubits) m |= 1ull << q;
+    if (block_masks) block_masks[b] = m;
+    if (block_gates) block_gates[b] = blocks[b].ngates;
+    if (matrices) {
+      const size_t need = blocks[b].m.size() * 2;
+      if (off + need > matrices_len) return fail(nullptr, QK_E_ARG, "matrices buffer too small");
+      for (size_t e = 0; e < blocks[b].m.size(); ++e) {
+        matrices[off + 2 * e] = blocks[b].m[e].real();
+        matrices[off + 2 * e + 1] = blocks[b].m[e].imag();
+      }
+      off += need;
+    }
+  }
+  return QK_OK;
+}
+
 qk_status qk_set_fusion(qk_sim s, int32_t max_k) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
   if (max_k != 0 && (max_k < 2 || max_k > QK_MAX_FUSION_K)) return fail(s, QK_E_ARG, "max_k must be 0 or 2..6");
@@ -1183,6 +1232,11 @@ qk_status qk_set_tuning(qk_sim s, const char* key, int32_t value) {
   } else if (k == "lane_items") {
     if (value != 1 && value != 2 && value != 4) return fail(s, QK_E_ARG, "lane_items must be 1, 2 or 4");
     s->tune.lane_items = value;
+  } else if (k == "mfma_areg") {
+    s->tune.mfma_areg = value != 0;
+  } else if (k == "mfma_cols") {
+    if (value != 16 && value != 32 && value != 64) return fail(s, QK_E_ARG, "mfma_cols must be 16, 32 or 64");
+    s->tune.mfma_cols = value;
   } else if (k == "mfma_waves") {
     if (value < 4 || value > 32 || value % 4) return fail(s, QK_E_ARG, "mfma_waves must be 4..32, a multiple of 4");
     s->tune.mfma_waves = value;
@@ -1201,6 +1255,8 @@ qk_status qk_get_tuning(qk_sim s, const char* key, int32_t* value) {
   else if (k == "lane_items") *value = s->tune.lane_items;
   else if (k == "diag_items") *value = s->tune.diag_items;
   else if (k == "mfma_waves") *value = s->tune.mfma_waves;
+  else if (k == "mfma_cols") *value = s->tune.mfma_cols;
+  else if (k == "mfma_areg") *value = s->tune.mfma_areg;
   else return fail(s, QK_E_ARG, "unknown tuning key " + k);
   return QK_OK;
 }

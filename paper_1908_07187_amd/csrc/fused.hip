@@ -1,27 +1,30 @@
 // Dense 2^K x 2^K gate (K = 2..6) on arbitrary target bits as a complex GEMM
 // on gfx950 matrix cores.
 //
-// Tile: 2^K rows (the target combinations, gate index m) x 16 columns (the
-// 16 combinations of the 4 lowest bits outside targets and controls, so a row
-// of the tile is up to 16 consecutive amplitudes).  One wave owns one tile
-// ("chunk") at a time; chunks are the remaining bits.  With the real
-// embedding Y = [[Mr, -Mi], [Mi, Mr]] [Xr; Xi] the tile update is a
-// (2^(K+1) x 2^(K+1)) x (2^(K+1) x 16) real GEMM, run as 16x16x4 MFMA steps:
+// Tile: 2^K rows (the target combinations, gate index m) x CW columns (the
+// combinations of the log2(CW) lowest bits outside targets and controls, so a
+// row of the tile is a run of CW consecutive amplitudes when those bits are
+// the lowest ones).  One wave owns one tile ("chunk") at a time; chunks are
+// the remaining bits.  With the real embedding Y = [[Mr, -Mi], [Mi, Mr]]
+// [Xr; Xi] the tile update is a (2^(K+1) x 2^(K+1)) x (2^(K+1) x CW) real
+// GEMM, run as 16x16x4 MFMA steps in CW/16 independent column groups:
 //   B operand: lane (h = lane/16, c = lane%16) loads the amplitude at tile row
-//     m = 4 ks + h, column c (one float2/double2); its real part feeds one MFMA
-//     and its imaginary part a second one, so no lane loads anything twice;
+//     m = 4 ks + h, column c + 16 g (one float2/double2); its real part feeds
+//     one MFMA and its imaginary part a second one, so nothing is loaded twice;
 //   A operand: the matching columns of the real-embedded matrix, staged once
-//     per block in LDS in per-lane fragment order (conflict-free reads);
-//   D: 16x16 accumulators per 16-row tile; the rows are arranged so that lane
-//     (h, v) holds real row 4h + v, i.e. the (re, im) pairs of two complex
-//     rows, stored straight back as float2/double2 (16 lanes = one contiguous
-//     run of 16 amplitudes).
+//     per block in LDS in per-lane fragment order (conflict-free reads); each
+//     A read serves all CW/16 column groups;
+//   D: 16x16 accumulators per 16-row tile and column group; the rows are
+//     arranged so that lane (h, v) holds real row 4h + v, i.e. the (re, im)
+//     pairs of two complex rows, stored straight back as float2/double2.
 // Complex64 states use v_mfma_f32_16x16x4f32 (FP32 products and accumulation);
 // complex128 states use v_mfma_f64_16x16x4f64.  The f32 and f64 instructions
 // place D rows differently (row 4h+v vs 4v+h for lane h, register v), which the
 // A staging absorbs by permuting the rows.
-// Each wave prefetches the next chunk's 2^K/4 loads before the current MFMAs.
+// Each wave prefetches the next chunk's loads before the current MFMAs; wider
+// tiles (CW = 32, 64) keep more bytes in flight per wave.
 #include <algorithm>
+#include <type_traits>
 
 #include "qk_internal.h"
 
@@ -32,13 +35,13 @@ typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 template <typename R> struct MF;
 template <> struct MF<float> {
-  using V = float2;
+  typedef float V __attribute__((ext_vector_type(2)));
   using Acc = floatx4;
   static constexpr bool kRowsByReg = false;   // D[i][j] at lane j + 16 (i / 4), register i % 4
   __device__ static Acc op(float a, float b, Acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
 };
 template <> struct MF<double> {
-  using V = double2;
+  typedef double V __attribute__((ext_vector_type(2)));
   using Acc = doublex4;
   static constexpr bool kRowsByReg = true;    // D[i][j] at lane j + 16 (i % 4), register i / 4
   __device__ static Acc op(double a, double b, Acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
@@ -46,7 +49,7 @@ template <> struct MF<double> {
 
 struct MfmaArgs {
   int tpos[6];   // target bit of gate index bit j
-  int lpos[4];   // column bits
+  int lpos[6];   // column bits (log2(CW) of them)
 };
 
 __device__ __forceinline__ bool conds_ok_m(const CondArgs& c) {
@@ -72,7 +75,18 @@ __device__ __forceinline__ uint64_t dep_t(uint32_t m, const MfmaArgs& a) {
   return i;
 }
 
-template <typename R, int K>
+template <bool NT, typename T>
+__device__ __forceinline__ T mld(const T* p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void mst(T* p, T v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+template <typename R, int K, int CW, bool NT, bool AREG>
 __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::V* psi, const typename MF<R>::V* __restrict__ mat,
                                                     uint64_t nchunks, Special sp, uint64_t cmask, MfmaArgs ma,
                                                     CondArgs cond) {
@@ -82,10 +96,18 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::V* psi, cons
   constexpr int RT = (2 * DIM + 15) / 16;   // 16-row tiles of the real output
   constexpr int KS = DIM / 4;               // steps of 4 complex input rows
   constexpr int NF = RT * KS * 2;           // A fragments (one value per lane each)
+  constexpr int G = CW / 16;                // column groups per wave
+  constexpr int LB = (CW == 16) ? 4 : (CW == 32 ? 5 : 6);
   extern __shared__ unsigned char smem_raw[];
   R* afrag = reinterpret_cast<R*>(smem_raw);
+  // AREG = false: the A fragments are re-read from LDS for every tile.  The
+  // offset `zoff` is reloaded from LDS per tile (it is always 0), so the
+  // compiler cannot hoist the fragment reads into registers; this keeps the
+  // register count (and so the waves per SIMD) of large blocks in check.
+  __shared__ int zero_sh;
 
   if (!conds_ok_m(cond)) return;
+  if (threadIdx.x == 0) zero_sh = 0;
 
   // Stage the real-embedded matrix in fragment order: fragment f = (rt, ks, part).
   for (int e = threadIdx.x; e < NF * 64; e += 256) {
@@ -106,43 +128,69 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::V* psi, cons
 
   const int lane = threadIdx.x & 63;
   const int h = lane >> 4, c = lane & 15;
-  uint64_t coloff = 0;
+  uint64_t lo_in[G], lo_out0[G], lo_out1[G];
+  const uint64_t din = dep_t<K>((uint32_t)h, ma);
+  const uint64_t dout0 = dep_t<K>((uint32_t)(2 * h) & (DIM - 1), ma);
+  const uint64_t dout1 = dep_t<K>((uint32_t)(2 * h + 1) & (DIM - 1), ma);
 #pragma unroll
-  for (int b = 0; b < 4; ++b) coloff |= (uint64_t)((c >> b) & 1) << ma.lpos[b];
-  // input row m = 4 ks + h = (4 ks) | h: the ks part is uniform, the h part per lane
-  const uint64_t lo_in = dep_t<K>((uint32_t)h, ma) | coloff;
-  // output rows r = 8 rt + 2 h + s
+  for (int g = 0; g < G; ++g) {
+    uint64_t coloff = 0;
+    const int col = c + 16 * g;
+#pragma unroll
+    for (int b = 0; b < LB; ++b) coloff |= (uint64_t)((col >> b) & 1) << ma.lpos[b];
+    lo_in[g] = din | coloff;
+    lo_out0[g] = dout0 | coloff;
+    lo_out1[g] = dout1 | coloff;
+  }
   const bool wr0 = (2 * h) < DIM;          // false only for K = 2, h >= 2 (padding rows)
-  const uint64_t lo_out0 = dep_t<K>((uint32_t)(2 * h) & (DIM - 1), ma) | coloff;
-  const uint64_t lo_out1 = dep_t<K>((uint32_t)(2 * h + 1) & (DIM - 1), ma) | coloff;
 
   const uint64_t wid = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const uint64_t nw = (uint64_t)gridDim.x * 4;
 
-  V xa[KS], xb[KS];
-  auto load = [&](uint64_t base, V* x) {
+  V xa[KS][G], xb[KS][G];
+  auto load = [&](uint64_t base, V (*x)[G]) {
 #pragma unroll
-    for (int ks = 0; ks < KS; ++ks) x[ks] = psi[base + dep_t<K>((uint32_t)(4 * ks), ma) + lo_in];
+    for (int ks = 0; ks < KS; ++ks) {
+      const uint64_t row = base + dep_t<K>((uint32_t)(4 * ks), ma);
+#pragma unroll
+      for (int g = 0; g < G; ++g) x[ks][g] = mld<NT>(psi + row + lo_in[g]);
+    }
   };
-  auto compute_store = [&](uint64_t base, const V* x) {
-    Acc acc[RT];
+  auto compute_store = [&](uint64_t base, V (*x)[G]) {
+    const int zoff = AREG ? 0 : *(volatile int*)&zero_sh;
+    Acc acc[RT][G];
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) acc[rt] = Acc{0, 0, 0, 0};
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int g = 0; g < G; ++g) acc[rt][g] = Acc{0, 0, 0, 0};
 #pragma unroll
     for (int ks = 0; ks < KS; ++ks) {
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
         const int f = (rt * KS + ks) * 2;
-        acc[rt] = MF<R>::op(afrag[f * 64 + lane], x[ks].x, acc[rt]);
-        acc[rt] = MF<R>::op(afrag[(f + 1) * 64 + lane], x[ks].y, acc[rt]);
+        const R a0 = afrag[f * 64 + lane + zoff];
+        const R a1 = afrag[(f + 1) * 64 + lane + zoff];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          acc[rt][g] = MF<R>::op(a0, x[ks][g].x, acc[rt][g]);
+          acc[rt][g] = MF<R>::op(a1, x[ks][g].y, acc[rt][g]);
+        }
       }
     }
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt) {
       if (wr0) {
-        const uint64_t hi = dep_t<K>((uint32_t)(8 * rt), ma);
-        psi[base + hi + lo_out0] = V{acc[rt][0], acc[rt][1]};
-        psi[base + hi + lo_out1] = V{acc[rt][2], acc[rt][3]};
+        const uint64_t hi = base + dep_t<K>((uint32_t)(8 * rt), ma);
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          V v0, v1;
+          v0.x = acc[rt][g][0];
+          v0.y = acc[rt][g][1];
+          v1.x = acc[rt][g][2];
+          v1.y = acc[rt][g][3];
+          mst<NT>(psi + hi + lo_out0[g], v0);
+          mst<NT>(psi + hi + lo_out1[g], v1);
+        }
       }
     }
   };
@@ -174,12 +222,24 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::V* psi, cons
   }
 }
 
+// Widest tile (columns per wave) that is instantiated for this block size
+// and keeps the double-buffered B registers of a lane at or below 64 VGPRs:
+// 64 columns up to k = 4; 32 up to k = 5, and at k = 6 for complex64; else 16.
+// launch_kwa dispatches exactly these widths.
+static int max_cols(int k, bool c64) {
+  if (k <= 4) return 64;
+  if (k == 5 || c64) return 32;
+  return 16;
+}
+
 bool mfma_supported(int n, int k, int nc, bool c64) {
   (void)c64;
   return k >= 2 && k <= 6 && n - k - nc >= 4;
 }
 
-template <typename R, int K>
+static int g_ncu = 0;
+
+template <typename R, int K, int CW, bool NT, bool AREG>
 static hipError_t launch_k(const Launch& L, const void* mat, uint64_t nchunks, const Special& sp, uint64_t cmask,
                            const MfmaArgs& ma, int waves_per_cu) {
   constexpr int DIM = 1 << K;
@@ -188,30 +248,69 @@ static hipError_t launch_k(const Launch& L, const void* mat, uint64_t nchunks, c
   const size_t shm = (size_t)RT * KS * 2 * 64 * sizeof(R);
   static bool attr_set = false;
   if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_dense_mfma<R, K>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)shm);
+    hipError_t e = hipFuncSetAttribute((const void*)k_dense_mfma<R, K, CW, NT, AREG>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
-  int ncu = 256;
-  {
-    int dev = 0;
-    if (hipGetDevice(&dev) == hipSuccess) {
-      int v = 0;
-      if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ncu = v;
-    }
+  if (g_ncu <= 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      g_ncu = v;
+    else
+      g_ncu = 256;
   }
   const uint64_t want = (nchunks + 3) / 4;
-  uint64_t cap = (uint64_t)ncu * std::max(1, waves_per_cu / 4);
+  const uint64_t cap = (uint64_t)g_ncu * std::max(1, waves_per_cu / 4);
   const unsigned g = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
-  hipLaunchKernelGGL((k_dense_mfma<R, K>), dim3(g), dim3(256), shm, L.stream, (typename MF<R>::V*)L.psi,
+  hipLaunchKernelGGL((k_dense_mfma<R, K, CW, NT, AREG>), dim3(g), dim3(256), shm, L.stream, (typename MF<R>::V*)L.psi,
                      (const typename MF<R>::V*)mat, nchunks, sp, cmask, ma, L.cond);
   return hipGetLastError();
+}
+
+template <typename R, int K, bool AREG>
+static hipError_t launch_kwa(const Launch& L, const void* mat, int cw, bool nt, uint64_t nchunks, const Special& sp,
+                             uint64_t cmask, const MfmaArgs& ma, int waves) {
+  if (cw == 64) {
+    if constexpr (K <= 4) {
+      return nt ? launch_k<R, K, 64, true, AREG>(L, mat, nchunks, sp, cmask, ma, waves)
+                : launch_k<R, K, 64, false, AREG>(L, mat, nchunks, sp, cmask, ma, waves);
+    }
+    return hipErrorInvalidValue;   // the host laid out chunks for a width this block size does not have
+  }
+  if (cw == 32) {
+    if constexpr (K <= 5 || std::is_same<R, float>::value) {
+      return nt ? launch_k<R, K, 32, true, AREG>(L, mat, nchunks, sp, cmask, ma, waves)
+                : launch_k<R, K, 32, false, AREG>(L, mat, nchunks, sp, cmask, ma, waves);
+    }
+    return hipErrorInvalidValue;
+  }
+  if (cw != 16) return hipErrorInvalidValue;
+  return nt ? launch_k<R, K, 16, true, AREG>(L, mat, nchunks, sp, cmask, ma, waves)
+            : launch_k<R, K, 16, false, AREG>(L, mat, nchunks, sp, cmask, ma, waves);
+}
+
+// Blocks up to k = 4 keep their (at most 16) A values in registers; larger
+// blocks choose by the "mfma_areg" knob.
+template <typename R, int K>
+static hipError_t launch_kw(const Launch& L, const void* mat, int cw, bool nt, uint64_t nchunks, const Special& sp,
+                            uint64_t cmask, const MfmaArgs& ma, int waves) {
+  if constexpr (K <= 4) {
+    return launch_kwa<R, K, true>(L, mat, cw, nt, nchunks, sp, cmask, ma, waves);
+  } else {
+    if (L.tune.mfma_areg) return launch_kwa<R, K, true>(L, mat, cw, nt, nchunks, sp, cmask, ma, waves);
+    return launch_kwa<R, K, false>(L, mat, cw, nt, nchunks, sp, cmask, ma, waves);
+  }
 }
 
 hipError_t launch_dense_mfma(const Launch& L, const int* targets, int k, const int* controls, int nc,
                              const void* d_matrix, int waves_per_cu) {
   if (!mfma_supported(L.n, k, nc, L.c64)) return hipErrorInvalidValue;
+  // tile width: the tuned one, capped by registers and by the bits available
+  int cw = std::max(16, std::min(L.tune.mfma_cols, max_cols(k, L.c64)));
+  while (cw > 16 && (1ull << (L.n - k - nc)) < (uint64_t)cw) cw >>= 1;
+  const int lb = cw == 16 ? 4 : (cw == 32 ? 5 : 6);
   MfmaArgs ma{};
   uint64_t used = 0;
   for (int j = 0; j < k; ++j) {
@@ -220,31 +319,37 @@ hipError_t launch_dense_mfma(const Launch& L, const int* targets, int k, const i
   }
   for (int j = 0; j < nc; ++j) used |= 1ull << controls[j];
   int nl = 0;
-  for (int b = 0; b < L.n && nl < 4; ++b)
+  for (int b = 0; b < L.n && nl < lb; ++b)
     if (!((used >> b) & 1)) ma.lpos[nl++] = b;
   std::vector<int> sv(targets, targets + k);
   for (int j = 0; j < nc; ++j) sv.push_back(controls[j]);
-  for (int j = 0; j < 4; ++j) sv.push_back(ma.lpos[j]);
+  for (int j = 0; j < lb; ++j) sv.push_back(ma.lpos[j]);
   Special sp = make_special(sv.data(), (int)sv.size(), nullptr, 0);
   uint64_t cmask = 0;
   for (int j = 0; j < nc; ++j) cmask |= 1ull << controls[j];
-  const uint64_t nchunks = 1ull << (L.n - k - nc - 4);
+  const uint64_t nchunks = 1ull << (L.n - k - nc - lb);
   if (waves_per_cu <= 0) waves_per_cu = 8;
+  // non-temporal when every row run of the tile is at least 256 bytes: the
+  // column bits are then the lowest ones and the run is CW amplitudes long
+  bool contiguous = true;
+  for (int j = 0; j < lb; ++j) contiguous = contiguous && ma.lpos[j] == j;
+  const size_t run = (contiguous ? (size_t)cw : 1) * (L.c64 ? 8 : 16);
+  const bool nt = L.tune.nt == 2 || (L.tune.nt == 1 && run >= 256);
   if (L.c64) {
     switch (k) {
-      case 2: return launch_k<float, 2>(L, d_matrix, nchunks, sp, cmask, ma, waves_per_cu);
-      case 3: return launch_k<float, 3>(L, d_matrix, nchunks, sp, cmask, ma, waves_per_cu);
-      case 4: return launch_k<float, 4>(L, d_matrix, nchunks, sp, cmask, ma, waves_per_cu);
-      case 5: return launch_k<float, 5>(L, d_matrix, nchunks, sp, cmask, ma, waves_per_cu);
-      case 6: return launch_k<float, 6>(L, d_matrix, nchunks, sp, cmask, ma, waves_per_cu);
+      case 2: return launch_kw<float, 2>(L, d_matrix, cw, nt, nchunks, sp, cmask, ma, waves_per_cu);
+      case 3: return launch_kw<float, 3>(L, d_matrix, cw, nt, nchunks, sp, cmask, ma, waves_per_cu);
+      case 4: return launch_kw<float, 4>(L, d_matrix, cw, nt, nchunks, sp, cmask, ma, waves_per_cu);
+      case 5: return launch_kw<float, 5>(L, d_matrix, cw, nt, nchunks, sp, cmask, ma, waves_per_cu);
+      case 6: return launch_kw<float, 6>(L, d_matrix, cw, nt, nchunks, sp, cmask, ma, waves_per_cu);
     }
   } else {
     switch (k) {
-      case 2: return launch_k<double, 2>(L, d_matrix, nchunks, sp, cmask, ma, waves_per_cu);
-      case 3: return launch_k<double, 3>(L, d_matrix, nchunks, sp, cmask, ma, waves_per_cu);
-      case 4: return launch_k<double, 4>(L, d_matrix, nchunks, sp, cmask, ma, waves_per_cu);
-      case 5: return launch_k<double, 5>(L, d_matrix, nchunks, sp, cmask, ma, waves_per_cu);
-      case 6: return launch_k<double, 6>(L, d_matrix, nchunks, sp, cmask, ma, waves_per_cu);
+      case 2: return launch_kw<double, 2>(L, d_matrix, cw, nt, nchunks, sp, cmask, ma, waves_per_cu);
+      case 3: return launch_kw<double, 3>(L, d_matrix, cw, nt, nchunks, sp, cmask, ma, waves_per_cu);
+      case 4: return launch_kw<double, 4>(L, d_matrix, cw, nt, nchunks, sp, cmask, ma, waves_per_cu);
+      case 5: return launch_kw<double, 5>(L, d_matrix, cw, nt, nchunks, sp, cmask, ma, waves_per_cu);
+      case 6: return launch_kw<double, 6>(L, d_matrix, cw, nt, nchunks, sp, cmask, ma, waves_per_cu);
     }
   }
   return hipErrorInvalidValue;

@@ -3,11 +3,8 @@
 // FP64, so a run of gates costs one sweep of the state instead of one per gate.
 //
 // Grouping is greedy and commutation-aware in the only way that needs no
-// algebra: gates on disjoint qubits commute, so a later gate may join the
-// current block when no earlier gate still left outside the block touches any
-// of its qubits.  Scanning in program order, a gate that cannot join marks its
-// qubits as blocked; the scan stops when every qubit outside the block is
-// blocked or after a fixed window.
+// algebra: gates on disjoint qubits commute, so a gate may join the current
+// block once every earlier gate on its qubits is scheduled (plan_blocks).
 #include <algorithm>
 #include <cstring>
 
@@ -91,38 +88,84 @@ static void left_multiply(std::vector<cd>& b, const std::vector<int>& qubits, co
   }
 }
 
+// Ready-frontier grouping.  A gate is ready when every earlier gate on each of
+// its qubits is already scheduled, so absorbing ready gates in any order is a
+// valid reordering (only gates on disjoint qubits are ever swapped).  A block
+// grows one ready gate at a time: gates already inside the block's qubit set
+// first, otherwise the fitting gate whose qubit set keeps the most upcoming
+// gates (within a look-ahead window) inside the block, ties to the earliest.
 std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax) {
   const int N = (int)gates.size();
+  std::vector<uint64_t> gm(N, 0);
+  int nq = 0;
+  for (int i = 0; i < N; ++i)
+    for (int q : gates[i].qubits) {
+      gm[i] |= 1ull << q;
+      nq = std::max(nq, q + 1);
+    }
+  // per-qubit program-order queues of gate indices
+  std::vector<std::vector<int>> onq(nq);
+  for (int i = 0; i < N; ++i)
+    for (int q : gates[i].qubits) onq[q].push_back(i);
+  std::vector<size_t> head(nq, 0);
   std::vector<char> done(N, 0);
+  auto ready = [&](int i) {
+    for (int q : gates[i].qubits)
+      if (onq[q][head[q]] != i) return false;
+    return true;
+  };
+  auto schedule = [&](int i) {
+    done[i] = 1;
+    for (int q : gates[i].qubits) ++head[q];
+  };
+  const int kWindow = 160;
   std::vector<FBlock> out;
-  int first = 0;
-  const int kWindow = 512;
-  while (first < N) {
+  int first = 0;   // earliest unscheduled gate
+  std::vector<int> cand;
+  while (true) {
     while (first < N && done[first]) ++first;
     if (first >= N) break;
     FBlock blk;
     blk.ngates = 0;
     blk.diag = true;
-    uint64_t smask = 0, blocked = 0;
+    uint64_t smask = 0;
     std::vector<int> members;
-    uint64_t allq = 0;
-    for (int i = first; i < N; ++i)
-      for (int q : gates[i].qubits) allq |= 1ull << q;
-    for (int i = first; i < N && i < first + kWindow; ++i) {
-      if (done[i]) continue;
-      uint64_t gm = 0;
-      for (int q : gates[i].qubits) gm |= 1ull << q;
-      if (gm & blocked) {
-        blocked |= gm;
-      } else if (__builtin_popcountll(smask | gm) <= kmax) {
-        smask |= gm;
-        members.push_back(i);
-        done[i] = 1;
-      } else {
-        blocked |= gm;
+    while (true) {
+      // ready gates: the front gate of some qubit that is ready on all its qubits
+      cand.clear();
+      for (int q = 0; q < nq; ++q) {
+        if (head[q] >= onq[q].size()) continue;
+        const int i = onq[q][head[q]];
+        if (done[i] || !ready(i)) continue;
+        if (__builtin_popcountll(smask | gm[i]) > kmax) continue;
+        if (std::find(cand.begin(), cand.end(), i) == cand.end()) cand.push_back(i);
       }
-      // nothing outside the block can still join once every other qubit is blocked
-      if (((allq & ~smask) & ~blocked) == 0 && (smask & ~blocked) == 0) break;
+      if (cand.empty()) break;
+      int pick = -1;
+      for (int i : cand)   // no growth first, earliest
+        if ((gm[i] & ~smask) == 0 && (pick < 0 || i < pick)) pick = i;
+      if (pick < 0) {
+        bool have = false;
+        long best = 0;
+        for (int i : cand) {
+          const uint64_t s2 = smask | gm[i];
+          long score = 0;
+          for (int j = first, seen = 0; j < N && seen < kWindow; ++j) {
+            if (done[j] || j == i) continue;
+            ++seen;
+            if ((gm[j] & ~s2) == 0) ++score;
+          }
+          score = score * 8 - __builtin_popcountll(gm[i] & ~smask);
+          if (!have || score > best || (score == best && i < pick)) {
+            have = true;
+            best = score;
+            pick = i;
+          }
+        }
+      }
+      smask |= gm[pick];
+      members.push_back(pick);
+      schedule(pick);
     }
     for (int q = 0; q < 64; ++q)
       if ((smask >> q) & 1) blk.qubits.push_back(q);

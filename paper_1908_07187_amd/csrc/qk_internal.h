@@ -58,6 +58,8 @@ struct Tuning {
   int diag_items = 1;    // amplitudes per thread in the diagonal and phase sweeps (1, 2 or 4)
   int lane_items = 1;    // 64-amplitude segments per wave in the cross-lane butterfly (1, 2 or 4)
   int mfma_waves = 8;    // waves per CU for the matrix-core kernel
+  int mfma_cols = 32;    // tile columns per wave for the matrix-core kernel (16, 32, 64; capped per k)
+  int mfma_areg = 0;     // blocks of 5-6 qubits: 1 keeps the A fragments in registers, 0 re-reads them from LDS
 };
 
 // Where device work goes and what it works on.

@@ -98,6 +98,7 @@ SIGNATURES = {
     "qk_batch_clear": (_I32, [_P]),
     "qk_batch_num_jobs": (_I32, [_P, _I32P]),
     "qk_batch_last_error": (C.c_char_p, [_P]),
+    "qk_plan_fusion": (_I32, [_I32, C.POINTER(QkOp), _I32, _I32, _I32P, _U64P, _I32P, _I32, _DP, _SZ]),
     "qk_last_error": (C.c_char_p, [_P]),
     "qk_status_string": (C.c_char_p, [_I32]),
 }
@@ -452,3 +453,31 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def plan_fusion(n: int, ops, max_k: int, with_matrices: bool = False):
+    """Host-only fusion plan: [(qubit list, gates composed, matrix or None)]."""
+    lib = load()
+    arr = (QkOp * max(1, len(ops)))(*ops)
+    nb = C.c_int32()
+    st = lib.qk_plan_fusion(n, arr, len(ops), max_k, C.byref(nb), None, None, 0, None, 0)
+    if st != QK_OK:
+        raise QKError(st, lib.qk_last_error(None).decode())
+    masks = (C.c_uint64 * max(1, nb.value))()
+    gates = (C.c_int32 * max(1, nb.value))()
+    cap = nb.value * (4 ** max_k) * 2 if with_matrices else 0
+    mats = np.zeros(max(1, cap), dtype=np.float64)
+    st = lib.qk_plan_fusion(n, arr, len(ops), max_k, C.byref(nb), masks, gates, nb.value,
+                            mats.ctypes.data_as(_DP) if with_matrices else None, cap)
+    if st != QK_OK:
+        raise QKError(st, lib.qk_last_error(None).decode())
+    out, off = [], 0
+    for b in range(nb.value):
+        qs = [q for q in range(64) if (masks[b] >> q) & 1]
+        m = None
+        if with_matrices:
+            d = 1 << len(qs)
+            m = mats[off: off + 2 * d * d].view(np.complex128).reshape(d, d).copy()
+            off += 2 * d * d
+        out.append((qs, gates[b], m))
+    return out

@@ -172,3 +172,38 @@ def test_circuit_to_batch_records():
     assert len(ops) == len([o for o in c.ops if o.kind in ("gate", "measure")])
     assert ops[-1].n_conds == 1 and ops[-1].conds[0].cbit == 0 and ops[-1].conds[0].value == 1
     assert ops[-2].kind == qk.QK_OP_MEASURE and ops[-2].u == 0.25
+
+
+@pytest.mark.parametrize("n,k,seed", [(4, 2, 0), (5, 3, 1), (6, 4, 2), (7, 5, 3), (7, 6, 4)])
+def test_fusion_plan_equals_circuit_unitary(n, k, seed):
+    """The planner reorders only commuting gates: the product of its block
+    matrices (composed in FP64 on the host) equals the brute-force unitary of
+    the gate sequence."""
+    import workloads as W
+    from oracle import brute
+    from paper_1908_07187_amd.batch import circuit_ops
+    c = W.c0_random_layers(n=n, layers=6, seed=seed, rzz=True)
+    extra = [W.gate("CPHASE", [0, n - 1], params=(0.7,)), W.gate("SWAP", [1, n - 2]), W.gate("S", [2]),
+             W.gate("RY", [1], controls=[0], params=(0.4,))]
+    c.ops[5:5] = extra
+    ops = circuit_ops(c)
+    blocks = qk.plan_fusion(n, ops, k, with_matrices=True)
+    assert sum(g for _, g, _ in blocks) == len(ops)
+    assert all(len(qs) <= k for qs, _, _ in blocks)
+    U = np.eye(1 << n, dtype=np.complex128)
+    for qs, _, m in blocks:
+        U = brute.embed(m, qs, [], n) @ U
+    assert np.max(np.abs(U - brute.circuit_unitary(c))) <= 1e-12
+
+
+def test_fusion_plan_quality_on_the_30_qubit_layers():
+    """Gates per 5-qubit block on the 30-qubit layered recipe (a regression
+    guard on the planner's grouping, not a correctness check)."""
+    import workloads as W
+    from paper_1908_07187_amd.batch import circuit_ops
+    c = W.c2_random_rzz(n=30, depth=8, seed=0)
+    ops = circuit_ops(c)
+    blocks = qk.plan_fusion(30, ops, 5)
+    per_block = len(ops) / len(blocks)
+    print(f"{len(ops)} gates -> {len(blocks)} blocks ({per_block:.2f} gates per block)")
+    assert per_block >= 6.0

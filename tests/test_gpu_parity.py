@@ -185,11 +185,23 @@ def test_shor_21_nx2n_single_run():
 
 @pytest.mark.parametrize("k", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_fused_blocks_match_oracle(k, dtype):
+@pytest.mark.parametrize("cols", [16, 32, 64])
+def test_fused_blocks_match_oracle(k, dtype, cols):
     c = W.c0_random_layers(n=14, layers=10, seed=k, rzz=True)
     ref, _, _ = oracle.run(c)
-    got, _, _ = _run_gpu(c, dtype, fusion=k)
-    _check(ref, got, dtype)
+    for areg in (0, 1):
+        got, _, _ = _run_gpu(c, dtype, fusion=k, tuning={"mfma_cols": cols, "mfma_areg": areg})
+        _check(ref, got, dtype)
+
+
+@pytest.mark.parametrize("n", [8, 9, 10, 11])
+def test_fused_blocks_few_column_bits(n):
+    """States with only 4..6 bits outside a 5-qubit block: the tile width falls back."""
+    c = W.c0_random_layers(n=n, layers=6, seed=n, rzz=True)
+    ref, _, _ = oracle.run(c)
+    for dtype in ("c128", "c64"):
+        got, _, _ = _run_gpu(c, dtype, fusion=5, tuning={"mfma_cols": 64})
+        _check(ref, got, dtype)
 
 
 def test_fusion_with_measurement_and_conditions():
@@ -226,8 +238,11 @@ def test_inner_product_and_norm():
 
 TUNINGS = [dict(nt=0, lane_bfly=0, sweep_items=1), dict(nt=0, lane_bfly=1, sweep_items=2, lane_items=2),
            dict(nt=1, lane_bfly=1, sweep_items=4, lane_items=1), dict(nt=2, lane_bfly=0, sweep_items=2),
-           dict(nt=2, lane_bfly=1, sweep_items=1, mfma_waves=4), dict(nt=1, lane_bfly=0, sweep_items=4, mfma_waves=16),
-           dict(nt=1, lane_bfly=1, sweep_items=1, lane_items=4)]
+           dict(nt=2, lane_bfly=1, sweep_items=1, mfma_waves=4, mfma_cols=16),
+           dict(nt=1, lane_bfly=0, sweep_items=4, mfma_waves=16, mfma_cols=64),
+           dict(nt=1, lane_bfly=1, sweep_items=1, lane_items=4, mfma_cols=32, diag_items=4),
+           dict(nt=0, mfma_cols=64, mfma_waves=12, diag_items=2, mfma_areg=1),
+           dict(nt=1, mfma_cols=16, mfma_areg=1)]
 
 
 @pytest.mark.parametrize("tuning", TUNINGS, ids=[str(i) for i in range(len(TUNINGS))])
