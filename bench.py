@@ -245,21 +245,32 @@ def main():
 
 
 def run_fused(qk, prog, torch, args, updates, ref_sim):
-    import ctypes as C
-    ks = [args.fusion_k] if args.fusion_k else [4, 5, 6]
+    """The complex64 form: fused blocks on matrix cores, configured by the
+    autotuner's cache for this qubit count (or every width 4..6 when absent)."""
+    from paper_1908_07187_amd import autotune
+    n = prog.circuit.n_qubits
+    cfg = None if args.fusion_k else autotune.lookup(n, "c64")
+    if cfg is not None and cfg.get("fusion", 0):
+        cands = [dict((k, cfg[k]) for k in ("fusion",) + autotune.SHAPE_KEYS if k in cfg)]
+    else:
+        cands = [{"fusion": k} for k in ([args.fusion_k] if args.fusion_k else [4, 5, 6])]
     best = None
-    for k in ks:
-        # one untimed pass per width (also the tuning pass), then the timed steps
-        s = qk.Sim("c64")
-        s.set_fusion(k)
+    for c in cands:
+        def make():
+            s = qk.Sim("c64")
+            for key in autotune.SHAPE_KEYS:
+                if key in c:
+                    s.set_tuning(key, c[key])
+            s.set_fusion(c["fusion"])
+            return s
+        s = make()              # one untimed pass per configuration
         prog.run(s)
         s.sync()
         s.close()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.steps):
-            s = qk.Sim("c64")
-            s.set_fusion(k)
+            s = make()
             prog.run(s)
             s.flush()
             if i + 1 < args.steps:
@@ -270,10 +281,10 @@ def run_fused(qk, prog, torch, args, updates, ref_sim):
         ip = ref_sim.inner(s)
         fid = abs(ip) ** 2 / (ref_sim.norm2() * s.norm2())
         s.close()
-        rec = {"k": k, "ms_per_step": dt * 1e3, "amp_updates_per_s": updates / dt,
+        rec = {"config": c, "autotuned": cfg is not None, "ms_per_step": dt * 1e3, "amp_updates_per_s": updates / dt,
                "speedup_vs_c128_per_gate": None, "fidelity_vs_c128": fid,
                "sweeps": stats["sweeps"], "fused_blocks": stats["fused_blocks"], "fused_gates": stats["fused_gates"]}
-        print(f"[bench] c64 fused k={k}: {dt * 1e3:.1f} ms/step, fidelity {fid:.12f}, sweeps {stats['sweeps']}",
+        print(f"[bench] c64 fused {c}: {dt * 1e3:.1f} ms/step, fidelity {fid:.12f}, sweeps {stats['sweeps']}",
               file=sys.stderr, flush=True)
         if best is None or rec["ms_per_step"] < best["ms_per_step"]:
             best = rec

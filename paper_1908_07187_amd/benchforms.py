@@ -104,14 +104,14 @@ def serve(args, qk, torch):
     sample = set(range(0, nj, 100))
     # closed loop: every job at t = 0 -> capacity
     warm = W.c4_job_stream(20, seed=args.seed + 1, rate=1.0)
-    Server(slots=8).serve(warm, realtime=False)
+    Server(slots=8, autotuned=True).serve(warm, realtime=False)
     _say(f"serve: closed loop over {nj} jobs")
-    rep0 = Server(slots=8).serve(jobs, realtime=False)
+    rep0 = Server(slots=8, autotuned=True).serve(jobs, realtime=False)
     cap = rep0.circuits_per_s
     _say(f"serve closed-loop capacity {cap:.1f} circuits/s, wall {rep0.wall_s:.1f} s")
     rate = 0.8 * cap
     jobs_p = W.c4_job_stream(nj, seed=args.seed, rate=rate)
-    rep = Server(slots=8, keep_states=sample).serve(jobs_p, realtime=True)
+    rep = Server(slots=8, keep_states=sample, autotuned=True).serve(jobs_p, realtime=True)
     _say(f"serve at {rate:.1f}/s: {rep.circuits_per_s:.1f} circuits/s p50 {rep.p50_ms:.1f} ms p99 {rep.p99_ms:.1f} ms")
     fids = []
     for i in sorted(sample):

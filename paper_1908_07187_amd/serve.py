@@ -10,8 +10,9 @@ Jobs (a circuit and a dtype) arrive over time.  The loop, run on the host:
   launches in flight per dtype, so jobs that arrive while a batch runs go into
   the next one;
 * gives every admitted large job its own stream slot and enqueues its whole
-  circuit there (optionally fused into matrix-core blocks); slots run
-  concurrently, so their sweeps overlap on the device;
+  circuit there (fused into matrix-core blocks as configured, or as the
+  autotuner chose for that qubit count and dtype); slots run concurrently,
+  so their sweeps overlap on the device;
 * polls completion events and, for each finished job, reads its cbits and a
   digest (norm; for small jobs the whole state) back to the host, frees its
   memory and records its latency (arrival -> result on the host).
@@ -30,6 +31,7 @@ from typing import Dict, List, Optional, Sequence, Tuple
 
 import numpy as np
 
+from . import autotune as _autotune
 from . import batch as _batch
 from .qk import Batch, QKError, Sim
 from .runner import Program
@@ -80,7 +82,8 @@ def footprint(n: int, dtype: str) -> int:
 class Server:
     def __init__(self, hbm_budget: Optional[int] = None, slots: int = 8,
                  fusion: Optional[Dict[str, int]] = None, keep_states: Sequence[int] = (),
-                 small_max: Optional[Dict[str, int]] = None, poll_sleep: float = 20e-6):
+                 small_max: Optional[Dict[str, int]] = None, poll_sleep: float = 20e-6,
+                 autotuned: bool = False):
         import torch
         self.torch = torch
         if hbm_budget is None:
@@ -92,6 +95,9 @@ class Server:
         self.keep_states = set(keep_states)
         self.small_max = dict(SMALL_MAX if small_max is None else small_max)
         self.poll_sleep = poll_sleep
+        # large jobs take the autotuner's fusion width and tile shape for their size
+        self.tuning_cache = _autotune.load_cache() if autotuned else None
+        self.autotuned = bool(self.tuning_cache)
 
     # ------------------------------------------------------------------
     def serve(self, jobs: Sequence[Tuple[float, object, str]], realtime: bool = True) -> ServeReport:
@@ -198,7 +204,9 @@ class Server:
                 sim = None
                 try:
                     sim = Sim(dt, stream=streams[slot])
-                    if self.fusion.get(dt, 0):
+                    if self.autotuned:
+                        _autotune.apply(sim, r.n, dt, self.tuning_cache)
+                    elif self.fusion.get(dt, 0):
                         sim.set_fusion(self.fusion[dt])
                     Program(circ).run(sim)
                     sim.flush()
