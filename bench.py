@@ -46,7 +46,7 @@ def parse():
     ap.add_argument("--no-fused", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gates", type=int, default=16, help="gates of the circuit the oracle sample runs")
-    ap.add_argument("--workload", default="random30", choices=["random30", "batch12", "serve", "qft26", "ipe21"],
+    ap.add_argument("--workload", default="random30", choices=["random30", "batch12", "serve", "qft26", "ipe21", "shor"],
                     help="random30 (default): the 30-qubit depth-40 circuit; the others are the batching, "
                          "serving, QFT and phase-estimation forms")
     ap.add_argument("--serve-jobs", type=int, default=400)
@@ -107,11 +107,13 @@ def run_c128_step(qk, prog, torch, timing):
 
 
 def kernels_only(qk, torch):
-    """A short program for hardware-counter runs on a 30-qubit complex128
-    state: strided-butterfly sweeps (targets 10, 17, 23, 29), diagonal sweeps
-    (RZ, RZZ), cross-lane butterflies (targets 1, 4), and one plain copy
-    kernel of known size (the 2^28-amplitude copy when a 28-qubit state grows
-    by one qubit: 4 GiB read, 4 GiB written)."""
+    """A short program for hardware-counter runs on 30-qubit states:
+    complex128 strided-butterfly sweeps (targets 10, 17, 23, 29), diagonal
+    sweeps (RZ, RZZ), cross-lane butterflies (targets 1, 4); dense 5- and
+    6-qubit blocks on matrix cores (complex64) and 4- and 5-qubit blocks
+    (complex128), two target sets each; and one plain copy kernel of known size
+    (the 2^28-amplitude copy when a 28-qubit state grows by one qubit: 4 GiB
+    read, 4 GiB written)."""
     s = qk.Sim("c128")
     s.add_qubits(30)
     for t in (10, 17, 23, 29):
@@ -122,6 +124,19 @@ def kernels_only(qk, torch):
     s.apply("H", [4])
     s.sync()
     s.close()
+    # matrix-core blocks: random 5- and 6-qubit unitaries on scattered targets
+    import numpy as np
+    import workloads as W
+    rng = np.random.default_rng(0)
+    for dtype, ks in (("c64", (5, 6)), ("c128", (4, 5))):
+        f = qk.Sim(dtype)
+        f.add_qubits(30)
+        for k in ks:
+            g = f.define_matrix(f"U{k}", W.random_unitary(k, rng))
+            for targets in ([3, 9, 14, 21, 27, 29][:k], [0, 7, 8, 16, 25, 28][:k]):
+                f.apply(g, targets)
+        f.sync()
+        f.close()
     c = qk.Sim("c128")
     c.add_qubits(28)
     c.add_qubits(1)

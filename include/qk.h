@@ -76,7 +76,7 @@ typedef int32_t qk_gate;
 #define QK_RZZ 15
 
 #define QK_MAX_CONDS 8        /* classical conditions per gate */
-#define QK_MAX_GATE_QUBITS 24 /* targets + controls per gate */
+#define QK_MAX_GATE_QUBITS 40 /* targets + controls per gate */
 #define QK_MAX_MATRIX_K 10    /* largest user matrix gate: 2^10 x 2^10 */
 #define QK_MAX_PERM_K 30      /* largest permutation gate */
 #define QK_MAX_FUSION_K 6     /* largest fused block */
@@ -154,12 +154,19 @@ qk_status qk_define_gate_table(qk_sim sim, const char* name, int32_t k, const ui
 qk_status qk_define_gate_affine(qk_sim sim, const char* name, int32_t k, uint64_t a, uint64_t b,
                                 qk_gate* out);
 
+/* Modular multiplication family (the paper's QuModExpUaj a= j= N=, Appendix
+ * A): y -> (a^(2^j) y) mod N for y < N, y itself for N <= y < 2^k, which
+ * keeps the map a permutation of [0, 2^k) (2 <= N <= 2^k, N < 2^32, gcd(a, N)
+ * = 1, else QK_E_NOT_PERMUTATION).  params[0] = j when applied (default 0).
+ * Evaluated on the device in closed form, no table. */
+qk_status qk_define_gate_modmul(qk_sim sim, const char* name, int32_t k, uint64_t a, uint64_t N, qk_gate* out);
+
 /* ---- gate operation (the paper's GateOp) ------------------------------- */
 
 /* Apply `gate` to `targets` (count must equal the gate's arity), restricted
  * to the subspace where every control qubit is 1, iff every classical
  * condition holds at execution time.  params: angles for RX, RY, RZ, PHASE,
- * CPHASE, RZZ (params[0], radians); j for affine gates.  Targets and
+ * CPHASE, RZZ (params[0], radians); j for affine and modular gates.  Targets and
  * controls must be distinct and < n.  Enqueued on the stream; returns
  * before the device runs it.  With fusion enabled (qk_set_fusion) an
  * unconditioned matrix gate may be held back and combined with later gates;

@@ -76,6 +76,13 @@ def gate_operator(op, user_gates, n: int) -> np.ndarray:
             m = np.asarray(g["matrix"], dtype=np.complex128)
         elif g["kind"] == "table":
             m = perm_matrix(g["table"])
+        elif g["kind"] == "modmul":
+            j = int(op.params[0]) if op.params else 0
+            t = np.arange(1 << g["k"], dtype=np.uint64)
+            mult = pow(g["a"], 1 << j, g["N"])
+            for x in range(g["N"]):
+                t[x] = (mult * x) % g["N"]
+            m = perm_matrix(t)
         else:
             j = int(op.params[0]) if op.params else 0
             m = perm_matrix(affine_power_table(g["k"], g["a"], g["b"], j))

@@ -64,3 +64,18 @@ def affine_table(k: int, a: int, b: int, power_log2: int) -> np.ndarray:
     for _ in range(int(power_log2)):
         t = t[t]
     return t
+
+
+def modmul_table(k: int, a: int, N: int, power_log2: int) -> np.ndarray:
+    """Table of y -> (a^(2^j) y) mod N for y < N, y itself for N <= y < 2^k
+    (the paper's QuModExpUaj gate; values at or above N are left in place so
+    the map is a permutation).  The multiplier a^(2^j) mod N is formed by
+    squaring j times in exact integers."""
+    m = a % N
+    for _ in range(int(power_log2)):
+        m = (m * m) % N
+    y = np.arange(1 << k, dtype=np.uint64)
+    out = y.copy()
+    lo = y < np.uint64(N)
+    out[lo] = (y[lo] * np.uint64(m)) % np.uint64(N)
+    return out

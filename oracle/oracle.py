@@ -203,6 +203,9 @@ class Oracle:
                 elif g["kind"] == "affine":
                     j = int(op.params[0]) if op.params else 0
                     self.apply_perm(gates.affine_table(g["k"], g["a"], g["b"], j), op.targets, op.controls, op.conds)
+                elif g["kind"] == "modmul":
+                    j = int(op.params[0]) if op.params else 0
+                    self.apply_perm(gates.modmul_table(g["k"], g["a"], g["N"], j), op.targets, op.controls, op.conds)
                 else:
                     raise KeyError(g["kind"])
             else:

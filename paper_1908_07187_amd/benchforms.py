@@ -213,5 +213,58 @@ def ipe21(args, qk, torch):
     return out
 
 
+def _order_from_phase(m: int, bits: int, N: int, a: int):
+    """Classical post-processing (continued fractions of m / 2^bits): the
+    smallest denominator r <= N with a^r = 1 mod N, or None."""
+    from fractions import Fraction
+    f = Fraction(m, 1 << bits).limit_denominator(N)
+    for mult in range(1, 64):
+        r = f.denominator * mult
+        if r > N:
+            break
+        if pow(a, r, N) == 1:
+            return r
+    return None
+
+
+def shor(args, qk, torch):
+    """The paper's Shor runs (Kitaev's one-control-qubit circuit) through the
+    command-script front end: N = 961307 (21 qubits, 40 stages) and N =
+    13564597 (25 qubits, 48 stages), a = 2, complex128."""
+    import workloads as W
+    from . import script
+    res = {}
+    for N in (961307, 13564597):
+        text = W.shor_nx2n_script(N, 2)
+        nC = (N * N - 1).bit_length()
+        circ = script.parse(text, seed=args.seed)
+        prog = qk.Program(circ)
+        times, outs = [], []
+        for k in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = qk.Sim("c128")
+            prog.run(s)
+            cb = s.read_cbits()
+            dt = time.perf_counter() - t0
+            s.close()
+            if k >= args.warmup:
+                times.append(dt)
+                m = sum(int(cb[e]) << e for e in range(nC))
+                outs.append({"m": m, "order": _order_from_phase(m, nC, N, 2)})
+        t = sum(times) / len(times)
+        res[str(N)] = {"qubits": circ.n_qubits, "stages": nC, "seconds_per_run": t, "runs": outs,
+                       "ops": len(circ.ops)}
+        _say(f"shor N={N}: {circ.n_qubits} qubits, {nC} stages, {t:.3f} s per run, outcomes {outs}")
+    out = _base(args, 1.0 / res["13564597"]["seconds_per_run"], "runs/s",
+                {"workload": "Shor factorisation of N = 13564597 (24-bit) with one recycled control qubit: 25 "
+                             "qubits, 48 stages of controlled modular multiplication, cbit-steered phase "
+                             "corrections, measure and reset; complex128; command-script front end",
+                 "N": 13564597, "a": 2}, "f64", res["13564597"]["seconds_per_run"] * 1e3)
+    out["runs"] = res
+    out["paper_context_seconds"] = {"961307": 139, "13564597": 1555}
+    return out
+
+
 def run(name, args, qk, torch):
-    return {"batch12": batch12, "serve": serve, "qft26": qft26, "ipe21": ipe21}[name](args, qk, torch)
+    return {"batch12": batch12, "serve": serve, "qft26": qft26, "ipe21": ipe21, "shor": shor}[name](args, qk, torch)

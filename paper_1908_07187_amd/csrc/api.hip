@@ -21,7 +21,7 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-enum UKind { U_MATRIX = 0, U_TABLE = 1, U_AFFINE = 2 };
+enum UKind { U_MATRIX = 0, U_TABLE = 1, U_AFFINE = 2, U_MODMUL = 3 };
 
 struct UserGate {
   int kind = U_MATRIX;
@@ -31,7 +31,7 @@ struct UserGate {
   bool diag = false;
   DevBuf dmat;             // matrix in the state's precision (uploaded at define time)
   DevBuf finv;             // inverse table, uint32 (U_TABLE)
-  uint64_t a = 1, b = 0;   // U_AFFINE
+  uint64_t a = 1, b = 0;   // U_AFFINE; U_MODMUL: multiplier a, modulus b
 };
 
 // Gate description after classification.
@@ -44,7 +44,7 @@ struct GateDesc {
   std::vector<cd> m;         // dense matrix (2^k x 2^k) for D_BUTTERFLY / D_DENSE, or diagonal for D_DIAG
   cd z = 1.0;                // D_PHASE1 factor
   const UserGate* ug = nullptr;
-  uint64_t A = 1, B = 0, Ainv = 1;   // D_PERM affine power
+  uint64_t A = 1, B = 0, Ainv = 1, N = 0;   // D_PERM closed forms (affine power; modular multiplier)
   bool fusable = false;      // matrix gate without conditions
 };
 
@@ -459,11 +459,11 @@ qk_status execute(qk_sim s, const GateDesc& d) {
       qk_status st = ensure_scratch(s);
       if (st) return st;
       Launch L = make_launch(s, d.conds);
-      const bool aff = d.ug->kind == U_AFFINE;
+      const int mode = d.ug->kind == U_AFFINE ? 1 : (d.ug->kind == U_MODMUL ? 2 : 0);
       return check_launch(s,
                           launch_perm(L, s->scratch.p, d.targets.data(), (int)d.targets.size(), d.controls.data(),
-                                      (int)d.controls.size(), aff ? nullptr : (const uint32_t*)d.ug->finv.p, aff, d.A,
-                                      d.B, d.Ainv),
+                                      (int)d.controls.size(), mode == 0 ? (const uint32_t*)d.ug->finv.p : nullptr,
+                                      mode, d.A, d.B, d.Ainv, d.N),
                           "permutation");
     }
   }
@@ -516,6 +516,31 @@ std::string upper(const char* s) {
   std::string r(s ? s : "");
   for (auto& ch : r) ch = (char)std::toupper((unsigned char)ch);
   return r;
+}
+
+// Inverse of a modulo N (gcd(a, N) = 1), extended Euclid in signed 64-bit.
+uint64_t inv_mod(uint64_t a, uint64_t N) {
+  int64_t t = 0, nt = 1, r = (int64_t)N, nr = (int64_t)(a % N);
+  while (nr != 0) {
+    const int64_t q = r / nr;
+    int64_t tmp = t - q * nt;
+    t = nt;
+    nt = tmp;
+    tmp = r - q * nr;
+    r = nr;
+    nr = tmp;
+  }
+  if (t < 0) t += (int64_t)N;
+  return (uint64_t)t;
+}
+
+uint64_t gcd_u64(uint64_t a, uint64_t b) {
+  while (b) {
+    const uint64_t t = a % b;
+    a = b;
+    b = t;
+  }
+  return a;
 }
 
 uint64_t inv_mod_2_64(uint64_t a) {
@@ -789,6 +814,20 @@ qk_status qk_define_gate_affine(qk_sim s, const char* name, int32_t k, uint64_t 
   return new_user_gate(s, g, out);
 }
 
+qk_status qk_define_gate_modmul(qk_sim s, const char* name, int32_t k, uint64_t a, uint64_t N, qk_gate* out) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (k < 1 || k > 32) return fail(s, QK_E_ARG, "k out of range");
+  if (N < 2 || N > (1ull << k) || N >= (1ull << 32)) return fail(s, QK_E_ARG, "N must satisfy 2 <= N <= 2^k and N < 2^32");
+  if (gcd_u64(a % N, N) != 1) return fail(s, QK_E_NOT_PERMUTATION, "a must be coprime to N for y -> a y mod N to be a bijection");
+  UserGate* g = new UserGate;
+  g->kind = U_MODMUL;
+  g->k = k;
+  g->name = name ? name : "";
+  g->a = a % N;
+  g->b = N;
+  return new_user_gate(s, g, out);
+}
+
 qk_status qk_apply_gate(qk_sim s, qk_gate gate, const int32_t* targets, int32_t nt, const int32_t* controls,
                         int32_t nc, const qk_cond* conds, int32_t ncond, const double* params, int32_t np) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
@@ -804,7 +843,7 @@ qk_status qk_apply_gate(qk_sim s, qk_gate gate, const int32_t* targets, int32_t 
   if (gate >= kUserBase && gate - kUserBase < (int)s->ugates.size()) {
     ug = s->ugates[gate - kUserBase];
     arity = ug->k;
-    const int maxp = ug->kind == U_AFFINE ? 1 : 0;
+    const int maxp = (ug->kind == U_AFFINE || ug->kind == U_MODMUL) ? 1 : 0;
     if (np > maxp) return fail(s, QK_E_ARG, "too many params for this gate");
   } else if ((bi = builtin_by_id(gate))) {
     arity = bi->arity;
@@ -859,6 +898,15 @@ qk_status qk_apply_gate(qk_sim s, qk_gate gate, const int32_t* targets, int32_t 
       d.A = A;
       d.B = B;
       d.Ainv = inv_mod_2_64(A) & mask;
+    } else if (ug->kind == U_MODMUL) {
+      double jd = np ? params[0] : 0.0;
+      if (!(jd >= 0 && jd < 64 && jd == std::floor(jd))) return fail(s, QK_E_ARG, "power j must be an integer in [0, 64)");
+      const uint64_t N = ug->b;
+      uint64_t A = ug->a % N;
+      for (int i = 0; i < (int)jd; ++i) A = (A * A) % N;   // a^(2^j) mod N; N < 2^32, no overflow
+      d.A = A;
+      d.N = N;
+      d.Ainv = inv_mod(A, N);
     }
   }
   if (d.conds.empty() && d.fusable && s->fuse_k >= 2 && nt + nc <= s->fuse_k) {

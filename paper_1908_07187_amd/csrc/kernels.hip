@@ -58,7 +58,7 @@ Special make_special(const int* a, int na, const int* b, int nb, const int* c, i
   std::sort(v.begin(), v.end());
   v.erase(std::unique(v.begin(), v.end()), v.end());
   Special s{};
-  s.n = (int)std::min<size_t>(v.size(), kMaxSpecial);   // callers pass at most 28 positions
+  s.n = (int)std::min<size_t>(v.size(), kMaxSpecial);   // callers pass at most 46 (40 gate qubits + 6 tile bits)
   for (int i = 0; i < s.n; ++i) s.pos[i] = v[i];
   return s;
 }
@@ -558,15 +558,16 @@ hipError_t launch_dense_generic(const Launch& L, const int* targets, int k, cons
 // U|x> = |f(x)> on the targets: the amplitude at gate index x moves to f(x).
 // Done as a gather out[y] = in[f^-1(y)] over the controlled subspace into a
 // compact scratch buffer (coalesced writes, gathered reads), then copied back.
-// f^-1 is a device table (uint32) or, for the affine family, the closed form
-// x = A^-1 (y - B) mod 2^k.
+// f^-1 is a device table (uint32) or a closed form: for the affine family
+// x = A^-1 (y - B) mod 2^k; for modular multiplication (y -> A y mod N for
+// y < N, y itself above) x = A^-1 y mod N for y < N.
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_perm_gather(const V2<R>* __restrict__ in, V2<R>* __restrict__ out,
                                                         uint64_t nitems, Special sp, uint64_t cmask, Pos32 tp, int k,
                                                         int contiguous, uint64_t tmask,
-                                                        const uint32_t* __restrict__ finv, int affine, uint64_t A,
-                                                        uint64_t B, uint64_t Ainv, CondArgs cond) {
+                                                        const uint32_t* __restrict__ finv, int mode, uint64_t A,
+                                                        uint64_t B, uint64_t Ainv, uint64_t N, CondArgs cond) {
   if (!conds_ok(cond)) return;
   const uint64_t kmask = (k >= 64) ? ~0ull : ((1ull << k) - 1);
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
@@ -574,7 +575,10 @@ __global__ __launch_bounds__(kBlock) void k_perm_gather(const V2<R>* __restrict_
   for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < nitems; e += stride) {
     const uint64_t i = insert_zeros(e, sp) | cmask;
     const uint64_t y = contiguous ? ((i >> tp.p[0]) & kmask) : extract(i, tp.p, k);
-    const uint64_t x = affine ? ((Ainv * (y - B)) & kmask) : (uint64_t)finv[y];
+    uint64_t x;
+    if (mode == 1) x = (Ainv * (y - B)) & kmask;
+    else if (mode == 2) x = (y < N) ? (Ainv * y) % N : y;   // A, Ainv < N < 2^32: no overflow
+    else x = (uint64_t)finv[y];
     const uint64_t src = (i & ~tmask) | (contiguous ? (x << tp.p[0]) : deposit(x, tp.p, k));
     out[e] = in[src];
   }
@@ -590,7 +594,7 @@ __global__ __launch_bounds__(kBlock) void k_perm_scatter(V2<R>* __restrict__ psi
 }
 
 hipError_t launch_perm(const Launch& L, void* scratch, const int* targets, int k, const int* controls, int nc,
-                       const uint32_t* d_finv, bool affine, uint64_t A, uint64_t B, uint64_t Ainv) {
+                       const uint32_t* d_finv, int mode, uint64_t A, uint64_t B, uint64_t Ainv, uint64_t N) {
   if (k < 1 || k > 32) return hipErrorInvalidValue;
   // the gather enumerates the controlled subspace; targets are part of it
   Special sp = make_special(controls, nc, nullptr, 0);
@@ -605,14 +609,14 @@ hipError_t launch_perm(const Launch& L, void* scratch, const int* targets, int k
   const unsigned g = std::min<unsigned>(grid_for(nitems, kBlock * 4), 1u << 20);
   if (L.c64) {
     hipLaunchKernelGGL(k_perm_gather<float>, dim3(g), dim3(kBlock), 0, L.stream, (const float2*)L.psi,
-                       (float2*)scratch, nitems, sp, cmask, tp, k, contiguous, tmask, d_finv, affine ? 1 : 0, A, B,
-                       Ainv, L.cond);
+                       (float2*)scratch, nitems, sp, cmask, tp, k, contiguous, tmask, d_finv, mode, A, B, Ainv, N,
+                       L.cond);
     hipLaunchKernelGGL(k_perm_scatter<float>, dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi,
                        (const float2*)scratch, nitems, sp, cmask, L.cond);
   } else {
     hipLaunchKernelGGL(k_perm_gather<double>, dim3(g), dim3(kBlock), 0, L.stream, (const double2*)L.psi,
-                       (double2*)scratch, nitems, sp, cmask, tp, k, contiguous, tmask, d_finv, affine ? 1 : 0, A, B,
-                       Ainv, L.cond);
+                       (double2*)scratch, nitems, sp, cmask, tp, k, contiguous, tmask, d_finv, mode, A, B, Ainv, N,
+                       L.cond);
     hipLaunchKernelGGL(k_perm_scatter<double>, dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi,
                        (const double2*)scratch, nitems, sp, cmask, L.cond);
   }

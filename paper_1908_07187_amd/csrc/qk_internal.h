@@ -16,7 +16,7 @@ namespace qk {
 
 using cd = std::complex<double>;
 
-constexpr int kMaxSpecial = 40;        // zero-insertion positions per launch
+constexpr int kMaxSpecial = 48;        // zero-insertion positions per launch (gate qubits + tile column bits)
 constexpr int kBlock = 256;            // threads per block of the sweep kernels
 constexpr int kReduceBlocks = 1024;    // fixed first-level reduction grid (max)
 constexpr int kMeasLog = 4096;         // measurement log entries kept on device
@@ -85,8 +85,10 @@ hipError_t launch_phase_all1(const Launch& L, const int* bits, int nb, double zr
 hipError_t launch_swap(const Launch& L, int a, int b, const int* controls, int nc);
 hipError_t launch_dense_generic(const Launch& L, const int* targets, int k, const int* controls, int nc,
                                 const void* d_matrix);
+// mode 0: table d_finv; 1: affine x = Ainv (y - B) mod 2^k; 2: modular
+// multiplication x = Ainv y mod N for y < N (identity above N).
 hipError_t launch_perm(const Launch& L, void* scratch, const int* targets, int k, const int* controls, int nc,
-                       const uint32_t* d_finv, bool affine, uint64_t A, uint64_t B, uint64_t Ainv);
+                       const uint32_t* d_finv, int mode, uint64_t A, uint64_t B, uint64_t Ainv, uint64_t N);
 
 // Measurement: partial sums -> finalize (outcome, cbit, scale, log) -> collapse.
 struct MeasBuffers {

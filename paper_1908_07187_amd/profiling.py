@@ -4,6 +4,7 @@ Usage (after ``rocprofv3 --pmc FETCH_SIZE`` and ``rocprofv3 --pmc WRITE_SIZE``
 runs of ``bench.py --kernels-only``):
 
     python -m paper_1908_07187_amd.profiling FETCH.csv WRITE.csv > profiles/sweep_traffic_30q_c128.json
+    python -m paper_1908_07187_amd.profiling mfma MFMA.csv
 
 FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch.  Each is scaled by
 the factor that makes the plain copy kernel of known size read back its true
@@ -66,5 +67,35 @@ def traffic(fetch_csv: str, write_csv: str) -> dict:
     return out
 
 
+def mfma(pmc_csv: str, trace_csv: str = None, simds: int = 1024) -> dict:
+    """Matrix-core use per kernel from a run with SQ_VALU_MFMA_BUSY_CYCLES,
+    GRBM_GUI_ACTIVE and SQ_INSTS_VALU_MFMA_MOPS_F32 / _F64 (512 flop per MOP):
+    utilisation = busy cycles / (active cycles x SIMDs); flops per launch."""
+    per = defaultdict(lambda: defaultdict(list))
+    dur = defaultdict(list)
+    with open(pmc_csv) as f:
+        for row in csv.DictReader(f):
+            k = short_name(row["Kernel_Name"])
+            per[k][row["Counter_Name"]].append(float(row["Counter_Value"]))
+            try:
+                dur[k].append((int(row["End_Timestamp"]) - int(row["Start_Timestamp"])) * 1e-9)
+            except (KeyError, ValueError):
+                pass
+    out = {}
+    for k, c in per.items():
+        if "SQ_VALU_MFMA_BUSY_CYCLES" not in c:
+            continue
+        busy = sum(c["SQ_VALU_MFMA_BUSY_CYCLES"]) / len(c["SQ_VALU_MFMA_BUSY_CYCLES"])
+        act = sum(c.get("GRBM_GUI_ACTIVE", [0])) / max(1, len(c.get("GRBM_GUI_ACTIVE", [0])))
+        mops = sum(c.get("SQ_INSTS_VALU_MFMA_MOPS_F32", [0]) + c.get("SQ_INSTS_VALU_MFMA_MOPS_F64", [0]))
+        n = len(c["SQ_VALU_MFMA_BUSY_CYCLES"])
+        out[k] = {"launches": n, "mfma_util": busy / (act * simds) if act else None,
+                  "flops_per_launch": mops * 512 / n}
+    return out
+
+
 if __name__ == "__main__":
-    print(json.dumps(traffic(sys.argv[1], sys.argv[2]), indent=1))
+    if sys.argv[1] == "mfma":
+        print(json.dumps(mfma(sys.argv[2]), indent=1))
+    else:
+        print(json.dumps(traffic(sys.argv[1], sys.argv[2]), indent=1))

@@ -64,6 +64,7 @@ SIGNATURES = {
     "qk_define_gate_index": (_I32, [_P, C.c_char_p, _I32, INDEX_FN, _P, _I32P]),
     "qk_define_gate_table": (_I32, [_P, C.c_char_p, _I32, _U64P, _I32P]),
     "qk_define_gate_affine": (_I32, [_P, C.c_char_p, _I32, _U64, _U64, _I32P]),
+    "qk_define_gate_modmul": (_I32, [_P, C.c_char_p, _I32, _U64, _U64, _I32P]),
     "qk_apply_gate": (_I32, [_P, _I32, _I32P, _I32, _I32P, _I32, C.POINTER(QkCond), _I32, _DP, _I32]),
     "qk_measure": (_I32, [_P, _I32, _I32, _D]),
     "qk_measure_dev": (_I32, [_P, _I32, _I32, _P]),
@@ -266,6 +267,11 @@ class Sim:
     def define_affine(self, name: str, k: int, a: int, b: int) -> int:
         out = C.c_int32()
         self._chk(self.lib.qk_define_gate_affine(self.h, name.encode(), k, a, b, C.byref(out)))
+        return out.value
+
+    def define_modmul(self, name: str, k: int, a: int, N: int) -> int:
+        out = C.c_int32()
+        self._chk(self.lib.qk_define_gate_modmul(self.h, name.encode(), k, a, N, C.byref(out)))
         return out.value
 
     def apply(self, gate, targets: Sequence[int], controls: Sequence[int] = (),

@@ -79,6 +79,8 @@ def _gate_id(sim: Sim, name: str, user_gates) -> int:
             return sim.define_table(name, g["table"])
         if g["kind"] == "affine":
             return sim.define_affine(name, g["k"], g["a"], g["b"])
+        if g["kind"] == "modmul":
+            return sim.define_modmul(name, g["k"], g["a"], g["N"])
         raise KeyError(g["kind"])
     if name in BUILTINS:
         return BUILTINS[name]

@@ -388,12 +388,14 @@ def modmul_table(N: int, a: int, j: int, nbits: int) -> np.ndarray:
 
 
 def shor_nx2n(N: int, a: int = 2, us: Optional[Sequence[float]] = None, seed: int = 0,
-              use_rz: bool = False) -> Circuit:
+              use_rz: bool = False, tables: bool = True) -> Circuit:
     """Kitaev's one-control-qubit Shor circuit (the paper's n x 2n branch).
 
     nQ = bitlen(N) + 1 qubits, nC = bitlen(N^2 - 1) cbits.  Paper qubit 0 is
     the recycled control = bit nQ-1; paper qubits 1..nQ-1 hold the work value
-    y on bits nQ-2..0.  The paper's cbit -(e+1) is cbit e here.
+    y on bits nQ-2..0.  The paper's cbit -(e+1) is cbit e here.  With
+    ``tables`` every controlled U^(2^j) is a permutation table; otherwise one
+    modular-multiplication gate family (a, N) is applied with parameter j.
     """
     nQ = N.bit_length() + 1
     nC = (N * N - 1).bit_length()
@@ -404,12 +406,17 @@ def shor_nx2n(N: int, a: int = 2, us: Optional[Sequence[float]] = None, seed: in
     ops = [add_qubits(nQ), add_cbits(nC), gate("X", [0])]
     user = {}
     rot = "RZ" if use_rz else "PHASE"
+    if not tables:
+        user["MODEXP"] = {"kind": "modmul", "k": nQ - 1, "a": a, "N": N}
     for e in range(nC):
         j = nC - e - 1
-        key = f"MODEXP_j{j}"
-        user[key] = {"kind": "table", "k": nQ - 1, "table": modmul_table(N, a, j, nQ - 1)}
         ops.append(gate("H", [ctrl]))
-        ops.append(gate(key, work, controls=[ctrl]))
+        if tables:
+            key = f"MODEXP_j{j}"
+            user[key] = {"kind": "table", "k": nQ - 1, "table": modmul_table(N, a, j, nQ - 1)}
+            ops.append(gate(key, work, controls=[ctrl]))
+        else:
+            ops.append(gate("MODEXP", work, controls=[ctrl], params=(float(j),)))
         for i in range(e):
             ops.append(gate(rot, [ctrl], conds=[(e - 1 - i, 1)], params=(-math.pi / 2 ** (i + 1),)))
         ops.append(gate("H", [ctrl]))
@@ -445,3 +452,23 @@ def shor_3nx1(N: int, a: int = 2, measure_work: bool = False, us=None, seed: int
             ops.append(measure(b, cbit=-1, u=float(us[i])))
     ops += qft_ops([nTQ - 1 - p for p in range(nCQ)])
     return Circuit(ops, user_gates=user, label=f"shor_3nx1_N{N}_a{a}")
+
+
+def shor_nx2n_script(N: int, a: int = 2) -> str:
+    """Kitaev's one-control-qubit Shor circuit as command-script text (the
+    command format of the paper's Appendix A): nQ = bitlen(N) + 1 qubits (qubit
+    0 = the recycled control, 1..nQ-1 the work register, big-endian), nC =
+    bitlen(N^2 - 1) cbits; stage e applies U^(2^(nC-1-e)), the cbit-weighted
+    phase correction, measures the control into cbit e and resets it."""
+    nQ = N.bit_length() + 1
+    nC = (N * N - 1).bit_length()
+    out = [f"#! Shor N={N} a={a}, {nQ} qubits, {nC} stages", f"AddQubits {nQ}", f"AddCbits {nC}",
+           f"GateOp SigmaX {nQ - 1}"]
+    for e in range(nC):
+        out.append("GateOp Hadamard 0")
+        out.append(f"GateOp QuModExpUaj 0:{nQ} a={a} j={nC - e - 1} N={N}")
+        if e:
+            out.append("GateOp RPhase 0," + ",".join(str(-i) for i in range(e, 0, -1)))
+        out += ["GateOp Hadamard 0", "Measure 0", f"GateOp Copy 0,-{e + 1}", f"GateOp SigmaX 0,-{e + 1}"]
+    out.append(f"Measure 1:{nQ}")
+    return "\n".join(out) + "\n"
