@@ -64,8 +64,11 @@ def _load(omp: bool):
     lib.orc_apply_perm.argtypes = [P, I, IP, C.POINTER(C.c_uint64), I, IP, I, IP, IP]
     lib.orc_measure.argtypes = [P, I, I, D, IP, DP, DP]
     lib.orc_postselect.argtypes = [P, I, I, I, DP]
+    lib.orc_marginal.argtypes = [P, I, IP, I, DP]
+    lib.orc_sample.argtypes = [P, I, IP, DP, C.c_int64, C.POINTER(C.c_uint64), DP]
     for f in ("orc_add_qubits", "orc_add_cbits", "orc_set_state", "orc_get_state", "orc_get_cbits",
-              "orc_set_cbit", "orc_apply_matrix", "orc_apply_perm", "orc_measure", "orc_postselect"):
+              "orc_set_cbit", "orc_apply_matrix", "orc_apply_perm", "orc_measure", "orc_postselect",
+              "orc_marginal", "orc_sample"):
         getattr(lib, f).restype = I
     _libs[key] = lib
     return lib
@@ -184,6 +187,31 @@ class Oracle:
             return 0.0
         self._chk(st, "postselect")
         return p.value
+
+    def marginal(self, qubits=(), normalise: bool = True) -> np.ndarray:
+        """Distribution of the listed qubits (bit j of the entry index = qubits[j]);
+        an empty list gives the distribution over all amplitude indices."""
+        qs = list(qubits)
+        out = np.empty(1 << (len(qs) if qs else self.n), dtype=np.float64)
+        st = self.lib.orc_marginal(self.h, len(qs), _iarr(qs), int(normalise),
+                                   out.ctypes.data_as(C.POINTER(C.c_double)))
+        self._chk(st, "marginal")
+        return out
+
+    def sample(self, uniforms, qubits=()):
+        """Deferred measurement: one shot per uniform.  Returns (outcomes uint64,
+        margins float64): each outcome packs bit qubits[j] of the drawn index
+        into bit j (the index itself for an empty list); the margin is the
+        draw's distance from the nearer CDF boundary, relative to the total."""
+        qs = list(qubits)
+        u = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64))
+        out = np.empty(max(1, len(u)), dtype=np.uint64)
+        margin = np.empty(max(1, len(u)), dtype=np.float64)
+        st = self.lib.orc_sample(self.h, len(qs), _iarr(qs), u.ctypes.data_as(C.POINTER(C.c_double)), len(u),
+                                 out.ctypes.data_as(C.POINTER(C.c_uint64)),
+                                 margin.ctypes.data_as(C.POINTER(C.c_double)))
+        self._chk(st, "sample")
+        return out[: len(u)], margin[: len(u)]
 
     # ------------------------------------------------------------------
     def apply_op(self, op, user_gates) -> Optional[MeasureRecord]:

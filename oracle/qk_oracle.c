@@ -21,7 +21,10 @@
  *     outcome into a classical bit is the paper's Copy command):
  *     p_b = sum of |psi_i|^2 over i with bit q = b, in index order;
  *     P0 = p0 / (p0 + p1); outcome o = (u < P0) ? 0 : 1; amplitudes with
- *     bit q = o are divided by sqrt(p_o), the others set to 0.
+ *     bit q = o are divided by sqrt(p_o), the others set to 0;
+ *   - deferred measurement (shots drawn from the final state, which is left
+ *     unchanged) and the marginal distribution of a list of qubits, from the
+ *     running sum of |psi_i|^2 in index order.
  *
  * Build: gcc -O2 -shared -fPIC (single thread), or add -fopenmp to split the
  * gate loops over host threads (same code; measurement sums stay sequential).
@@ -297,4 +300,92 @@ orc* orc_clone(const orc* o) {
     memcpy(c->psi, o->psi, o->dim * sizeof(cplx));
     if (o->ncbits) memcpy(c->cbits, o->cbits, (size_t)o->ncbits);
     return c;
+}
+
+/* ---- deferred measurement: distribution and many-shot sampling ----------
+ *
+ * The paper's circuits end either in in-place measurement or in deferred
+ * measurement of the qubits, and the state can be read out as a normalised
+ * probability distribution (section "Q-Kit.").  Deferred measurement of a
+ * list of qubits Q = (q_0..q_{m-1}) in one shot yields the bits of an index
+ * i drawn with probability |psi_i|^2 / sum_j |psi_j|^2, read at Q; the state
+ * is left as it is, so any number of shots can be drawn from it.
+ */
+
+/* Bits qubits[j] of i packed into bit j (nq = 0: i itself). */
+static uint64_t project(uint64_t i, int nq, const int* qubits) {
+    if (nq == 0) return i;
+    uint64_t r = 0;
+    for (int j = 0; j < nq; ++j) r |= ((i >> qubits[j]) & 1ull) << j;
+    return r;
+}
+
+static int check_list(const orc* o, int nq, const int* qubits) {
+    if (nq < 0 || nq > o->n || (nq > 0 && !qubits)) return ORC_E_ARG;
+    for (int j = 0; j < nq; ++j) {
+        if (qubits[j] < 0 || qubits[j] >= o->n) return ORC_E_ARG;
+        for (int l = 0; l < j; ++l)
+            if (qubits[l] == qubits[j]) return ORC_E_ARG;
+    }
+    return ORC_OK;
+}
+
+/* Marginal distribution of the listed qubits: out[m] = sum of |psi_i|^2 over
+ * the i whose projection is m, summed in index order, divided by the total
+ * (2^nq entries; not normalised when normalise == 0). */
+int orc_marginal(const orc* o, int nq, const int* qubits, int normalise, double* out) {
+    if (check_list(o, nq, qubits) || !out || o->n == 0) return ORC_E_ARG;
+    uint64_t nout = 1ull << (nq ? nq : o->n);
+    for (uint64_t m = 0; m < nout; ++m) out[m] = 0.0;
+    double total = 0.0;
+    for (uint64_t i = 0; i < o->dim; ++i) {
+        double a = creal(o->psi[i]) * creal(o->psi[i]) + cimag(o->psi[i]) * cimag(o->psi[i]);
+        out[project(i, nq, qubits)] += a;
+        total += a;
+    }
+    if (normalise) {
+        if (!(total > 0.0)) return ORC_E_STATE;
+        for (uint64_t m = 0; m < nout; ++m) out[m] /= total;
+    }
+    return ORC_OK;
+}
+
+/* S shots: for each uniform u_s in [0,1), the smallest index i whose running
+ * sum c_i = sum_{j<=i} |psi_j|^2 (index order) exceeds u_s * c_{dim-1};
+ * out[s] = projection of i onto the listed qubits.  margin (optional) gets
+ * min(u_s*T - c_{i-1}, c_i - u_s*T) / T with T = c_{dim-1} and c_{-1} = 0:
+ * how far the draw lies from the nearer boundary of the interval it fell in. */
+int orc_sample(const orc* o, int nq, const int* qubits, const double* u, int64_t S, uint64_t* out,
+               double* margin) {
+    if (check_list(o, nq, qubits) || S < 0 || (S > 0 && (!u || !out)) || o->n == 0) return ORC_E_ARG;
+    double* c = (double*)malloc(o->dim * sizeof(double));
+    if (!c) return ORC_E_OOM;
+    double run = 0.0;
+    for (uint64_t i = 0; i < o->dim; ++i) {
+        run += creal(o->psi[i]) * creal(o->psi[i]) + cimag(o->psi[i]) * cimag(o->psi[i]);
+        c[i] = run;
+    }
+    const double T = run;
+    if (!(T > 0.0)) { free(c); return ORC_E_STATE; }
+    for (int64_t s = 0; s < S; ++s) {
+        if (!(u[s] >= 0.0 && u[s] < 1.0)) { free(c); return ORC_E_ARG; }
+        const double target = u[s] * T;
+        /* bisection for the first i with c[i] > target; c is nondecreasing and
+           c[dim-1] = T > target unless the product rounded up to T */
+        uint64_t lo = 0, hi = o->dim - 1;
+        while (lo < hi) {
+            uint64_t mid = lo + (hi - lo) / 2;
+            if (c[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        /* if the draw rounded onto T, step back to the last index of nonzero weight */
+        while (lo > 0 && !(c[lo] > (lo ? c[lo - 1] : 0.0))) --lo;
+        out[s] = project(lo, nq, qubits);
+        if (margin) {
+            double below = target - (lo ? c[lo - 1] : 0.0);
+            double above = c[lo] - target;
+            margin[s] = (below < above ? below : above) / T;
+        }
+    }
+    free(c);
+    return ORC_OK;
 }
