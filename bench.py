@@ -15,6 +15,7 @@ Also reported on the same line:
   fused_c64     the same circuit in complex64 with fused k-qubit blocks on
                 matrix cores: gate throughput, sweeps, and fidelity against the
                 complex128 result of the timed steps;
+  fused_c128    the same with complex128 states and FP64 matrix cores;
   cpu_baseline  the FP64 oracle on the host cores, on the first gates of the
                 same 30-qubit circuit.
 """
@@ -248,9 +249,10 @@ def main():
     }
 
     if not args.no_fused:
-        fz = run_fused(qk, prog, torch, args, updates, sims[0])
-        fz["speedup_vs_c128_per_gate"] = ms_per_step / fz["ms_per_step"]
-        out["fused_c64"] = fz
+        for dt in ("c64", "c128"):
+            fz = run_fused(qk, prog, torch, args, updates, sims[0], dt)
+            fz["speedup_vs_c128_per_gate"] = ms_per_step / fz["ms_per_step"]
+            out[f"fused_{dt}"] = fz
     sims[0].close()
 
     if not args.no_cpu_baseline:
@@ -259,12 +261,14 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def run_fused(qk, prog, torch, args, updates, ref_sim):
-    """The complex64 form: fused blocks on matrix cores, configured by the
-    autotuner's cache for this qubit count (or every width 4..6 when absent)."""
+def run_fused(qk, prog, torch, args, updates, ref_sim, dtype="c64"):
+    """A fused form: blocks of up to k qubits composed in FP64 on the host and
+    applied on matrix cores (complex64: FP32 MFMA; complex128: FP64 MFMA),
+    configured by the autotuner's cache for this qubit count and dtype (or every
+    width 4..6 when absent)."""
     from paper_1908_07187_amd import autotune
     n = prog.circuit.n_qubits
-    cfg = None if args.fusion_k else autotune.lookup(n, "c64")
+    cfg = None if args.fusion_k else autotune.lookup(n, dtype)
     if cfg is not None and cfg.get("fusion", 0):
         cands = [dict((k, cfg[k]) for k in ("fusion",) + autotune.SHAPE_KEYS if k in cfg)]
     else:
@@ -272,7 +276,7 @@ def run_fused(qk, prog, torch, args, updates, ref_sim):
     best = None
     for c in cands:
         def make():
-            s = qk.Sim("c64")
+            s = qk.Sim(dtype)
             for key in autotune.SHAPE_KEYS:
                 if key in c:
                     s.set_tuning(key, c[key])
@@ -299,7 +303,7 @@ def run_fused(qk, prog, torch, args, updates, ref_sim):
         rec = {"config": c, "autotuned": cfg is not None, "ms_per_step": dt * 1e3, "amp_updates_per_s": updates / dt,
                "speedup_vs_c128_per_gate": None, "fidelity_vs_c128": fid,
                "sweeps": stats["sweeps"], "fused_blocks": stats["fused_blocks"], "fused_gates": stats["fused_gates"]}
-        print(f"[bench] c64 fused {c}: {dt * 1e3:.1f} ms/step, fidelity {fid:.12f}, sweeps {stats['sweeps']}",
+        print(f"[bench] {dtype} fused {c}: {dt * 1e3:.1f} ms/step, fidelity {fid:.12f}, sweeps {stats['sweeps']}",
               file=sys.stderr, flush=True)
         if best is None or rec["ms_per_step"] < best["ms_per_step"]:
             best = rec
