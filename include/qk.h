@@ -202,6 +202,45 @@ qk_status qk_read_cbits(qk_sim sim, uint8_t* out, int32_t n);
  * out[3*i .. 3*i+2].  *written receives the count written.  Synchronises. */
 qk_status qk_read_measure_log(qk_sim sim, double* out, int32_t count, int32_t* written);
 
+/* ---- deferred measurement (measuring at the end, many shots) ------------- */
+
+/* The paper's circuits measure qubits either in place or deferred to the end
+ * (section "Q-Kit."); measuring the listed qubits at the end, once per shot,
+ * draws an amplitude index i with probability |a_i|^2 / sum_j |a_j|^2 and
+ * reads its bits at those qubits.  The state is not changed.
+ *
+ * For each uniform u_s in [0, 1): i_s = the smallest index whose running sum
+ * of |a_j|^2 in index order exceeds u_s times the total (FP64 sums; an index
+ * of zero weight is never drawn, and a draw within rounding of an interval
+ * boundary may land on either side of it).  out[s] packs bit qubits[j] of
+ * i_s into bit j; n_qubits = 0 (qubits may be NULL) gives i_s itself.
+ * qubits must be distinct and < n; n_shots <= 2^32.
+ *
+ * qk_sample: uniforms and out are host arrays of n_shots entries; every
+ * uniform must lie in [0, 1) (else QK_E_ARG, nothing run); a state of zero
+ * norm gives QK_E_STATE.  Synchronises.  Costs one read sweep of the state
+ * plus one wave and about 4 KiB of reads per shot; device work space of
+ * 2^n / 128 bytes and 16 bytes per shot is allocated on first use and kept. */
+qk_status qk_sample(qk_sim sim, const int32_t* qubits, int32_t n_qubits, const double* uniforms,
+                    int64_t n_shots, uint64_t* out);
+
+/* As qk_sample with device arrays: d_uniforms (n_shots doubles, read when the
+ * step executes) and d_out (n_shots uint64).  Asynchronous, no host round
+ * trip.  Draws outside [0, 1) are clamped; a state of zero norm writes
+ * UINT64_MAX to every d_out entry.  Inside a graph capture the work space
+ * must already exist (call it once on the same qubit count first), else
+ * QK_E_STATE. */
+qk_status qk_sample_dev(qk_sim sim, const int32_t* qubits, int32_t n_qubits, const double* d_uniforms,
+                        int64_t n_shots, uint64_t* d_out);
+
+/* Normalised probability distribution of the listed qubits (the paper's
+ * probability view of the state, section "Q-Kit."): out[m] = sum of
+ * |a_i|^2 over the i whose bit qubits[j] equals bit j of m, divided by the
+ * sum of all |a_i|^2 (FP64, fixed order).  1 <= n_qubits <= min(n, 24);
+ * out is a host array of 2^n_qubits doubles.  QK_E_STATE for a state of
+ * zero norm.  Synchronises. */
+qk_status qk_probabilities(qk_sim sim, const int32_t* qubits, int32_t n_qubits, double* out);
+
 /* ---- readout ------------------------------------------------------------ */
 
 /* Copy the state (2^n amplitudes, bytes = 2^n * amplitude size) to host

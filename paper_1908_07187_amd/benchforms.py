@@ -266,5 +266,61 @@ def shor(args, qk, torch):
     return out
 
 
+def sample30(args, qk, torch):
+    """Deferred measurement at 30 qubits: 2^20 shots of all 30 qubits from an
+    entangled state (RY(theta_q) on every qubit, then a CNOT chain), for
+    complex128 and complex64 states.  HIP events on the simulator's stream time
+    the cumulative-distribution sweep alone (a call with no shots) and the
+    sweep plus the shots (uniforms and results stay on the device)."""
+    n, S = 30, 1 << 20
+    rng = np.random.default_rng(args.seed)
+    theta = rng.uniform(0.2, np.pi - 0.2, n)
+    d_u = torch.tensor(rng.random(S), dtype=torch.float64, device="cuda")
+    d_out = torch.empty(S, dtype=torch.int64, device="cuda")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for dtype in ("c128", "c64"):
+        s = qk.Sim(dtype)
+        s.add_qubits(n)
+        for q in range(n):
+            s.apply("RY", [q], params=[theta[q]])
+        for q in range(n - 1):
+            s.apply("X", [q + 1], controls=[q])
+        s.sync()
+        cdf, full = [], []
+        for k in range(args.warmup + args.steps):
+            e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            e0.record(stream)
+            s.sample_dev(d_u.data_ptr(), 0, d_out.data_ptr())
+            e1.record(stream)
+            s.sample_dev(d_u.data_ptr(), S, d_out.data_ptr())
+            e2.record(stream)
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                cdf.append(e0.elapsed_time(e1))
+                full.append(e1.elapsed_time(e2))
+        s.close()
+        amp = 16 if dtype == "c128" else 8
+        cdf_ms, full_ms = sum(cdf) / len(cdf), sum(full) / len(full)
+        # algorithmic bytes of the sweep: the state read once, 8 B written per 256 amplitudes
+        sweep_bytes = (1 << n) * amp + ((1 << n) // 256) * 8
+        res[dtype] = {"cdf_ms": cdf_ms, "shots_ms": full_ms, "draw_ms": full_ms - cdf_ms,
+                      "shots_per_s": S / (full_ms * 1e-3), "cdf_gbps": sweep_bytes / (cdf_ms * 1e-3) / 1e9,
+                      "sweep_bytes": sweep_bytes}
+        _say(f"sample30 {dtype}: sweep {cdf_ms:.3f} ms ({res[dtype]['cdf_gbps']:.0f} GB/s), "
+             f"2^20 shots incl. sweep {full_ms:.3f} ms")
+    r = res["c128"]
+    out = _base(args, r["shots_per_s"], "shots/s",
+                {"workload": "2^20 shots of all 30 qubits from an entangled 30-qubit complex128 state "
+                             "(deferred measurement: FP64 cumulative distribution sweep + one wave per shot)",
+                 "n_qubits": n, "shots": S}, "f64", r["shots_ms"])
+    out["roofline"] = {"bound": "hbm", "kernel": "qk::k_cdf_segments<double>", "achieved": r["cdf_gbps"],
+                       "peak": 8000.0, "unit": "GB/s", "frac": r["cdf_gbps"] / 8000.0, "traffic": None,
+                       "bytes_per_launch": r["sweep_bytes"], "mean_launch_ms": r["cdf_ms"]}
+    out["forms"] = res
+    return out
+
+
 def run(name, args, qk, torch):
-    return {"batch12": batch12, "serve": serve, "qft26": qft26, "ipe21": ipe21, "shor": shor}[name](args, qk, torch)
+    return {"batch12": batch12, "serve": serve, "qft26": qft26, "ipe21": ipe21, "shor": shor,
+            "sample30": sample30}[name](args, qk, torch)

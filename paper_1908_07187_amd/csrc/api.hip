@@ -71,6 +71,7 @@ struct qk_sim_s {
   hipStream_t stream = nullptr;
   int n = 0;
   DevBuf state, scratch, cbits, meas;
+  DevBuf samp, shots;               // deferred-measurement work space; host-call staging of uniforms and shots
   int ncbits = 0;
   std::vector<Arena> arenas;        // constant chunks in use (the last one is being filled)
   std::vector<Arena> saved_arenas;  // chunks set aside while a capture owns `arenas`
@@ -645,6 +646,8 @@ qk_status qk_destroy(qk_sim s) {
   dev_free(s, s->scratch);
   dev_free(s, s->cbits);
   dev_free(s, s->meas);
+  dev_free(s, s->samp);
+  dev_free(s, s->shots);
   for (Arena& a : s->arenas) arena_free_chunk(s, a);
   for (Arena& a : s->saved_arenas) arena_free_chunk(s, a);
   for (UserGate* g : s->ugates) {
@@ -1008,6 +1011,106 @@ qk_status qk_read_measure_log(qk_sim s, double* out, int32_t count, int32_t* wri
     out[3 * i + 2] = logbuf[3 * slot + 2];
   }
   if (written) *written = (int32_t)take;
+  return QK_OK;
+}
+
+// ---------------------------------------------------------------- deferred measurement
+
+static qk_status check_qubit_list(qk_sim s, const int32_t* qubits, int32_t nq, int32_t max_nq) {
+  if (nq < 0 || nq > max_nq || (nq > 0 && !qubits)) return fail(s, QK_E_ARG, "bad qubit list");
+  uint64_t seen = 0;
+  for (int j = 0; j < nq; ++j) {
+    if (qubits[j] < 0 || qubits[j] >= s->n) return fail(s, QK_E_ARG, "qubit out of range");
+    if ((seen >> qubits[j]) & 1) return fail(s, QK_E_ARG, "duplicate qubit in list");
+    seen |= 1ull << qubits[j];
+  }
+  return QK_OK;
+}
+
+static qk_status sample_common(qk_sim s, const int32_t* qubits, int32_t nq, int64_t nshots) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
+  if (nshots < 0 || nshots > ((int64_t)1 << 32)) return fail(s, QK_E_ARG, "n_shots must be in [0, 2^32]");
+  qk_status st = check_qubit_list(s, qubits, nq, s->n);
+  if (st) return st;
+  const size_t need = sample_layout(s->n).doubles * sizeof(double);
+  if (s->capturing) {
+    if (!s->samp.p || s->samp.bytes < need)
+      return fail(s, QK_E_STATE, "sampling work space missing: sample once before capturing");
+    return flush(s);
+  }
+  if ((st = flush(s))) return st;
+  return ensure(s, s->samp, need, "sampling work space");
+}
+
+qk_status qk_sample(qk_sim s, const int32_t* qubits, int32_t nq, const double* uniforms, int64_t nshots,
+                    uint64_t* out) {
+  if (s && s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
+  qk_status st = sample_common(s, qubits, nq, nshots);
+  if (st) return st;
+  if (nshots > 0 && (!uniforms || !out)) return fail(s, QK_E_ARG, "uniforms and out must be given");
+  for (int64_t i = 0; i < nshots; ++i)
+    if (!(uniforms[i] >= 0.0 && uniforms[i] < 1.0)) return fail(s, QK_E_ARG, "uniforms must lie in [0, 1)");
+  if ((st = ensure(s, s->shots, (size_t)std::max<int64_t>(nshots, 1) * 16, "shot staging"))) return st;
+  double* d_u = (double*)s->shots.p;
+  uint64_t* d_out = (uint64_t*)((char*)s->shots.p + (size_t)std::max<int64_t>(nshots, 1) * 8);
+  Launch L = make_launch(s, {});
+  hipError_t e = hipSuccess;
+  if (nshots > 0) e = hipMemcpyAsync(d_u, uniforms, (size_t)nshots * 8, hipMemcpyHostToDevice, s->stream);
+  if (e == hipSuccess) e = launch_cdf(L, (double*)s->samp.p);
+  if (e == hipSuccess) e = launch_draw(L, (const double*)s->samp.p, qubits, nq, d_u, (uint64_t)nshots, d_out);
+  if (e != hipSuccess) return hip_fail(s, e, "sample");
+  s->sweeps += 1;
+  const SampleLayout sl = sample_layout(s->n);
+  double total = 0.0;
+  e = hipMemcpyAsync(&total, (double*)s->samp.p + sl.nseg + 2 * sl.nchunk, sizeof total, hipMemcpyDeviceToHost,
+                     s->stream);
+  if (e == hipSuccess && nshots > 0)
+    e = hipMemcpyAsync(out, d_out, (size_t)nshots * 8, hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "sample readback");
+  if ((st = sync_stream(s))) return st;
+  if (!(total > 0.0)) return fail(s, QK_E_STATE, "state has zero norm");
+  return QK_OK;
+}
+
+qk_status qk_sample_dev(qk_sim s, const int32_t* qubits, int32_t nq, const double* d_u, int64_t nshots,
+                        uint64_t* d_out) {
+  qk_status st = sample_common(s, qubits, nq, nshots);
+  if (st) return st;
+  if (nshots > 0 && (!d_u || !d_out)) return fail(s, QK_E_ARG, "d_uniforms and d_out must be given");
+  Launch L = make_launch(s, {});
+  hipError_t e = launch_cdf(L, (double*)s->samp.p);
+  if (e == hipSuccess) e = launch_draw(L, (const double*)s->samp.p, qubits, nq, d_u, (uint64_t)nshots, d_out);
+  if (e != hipSuccess) return hip_fail(s, e, "sample");
+  s->sweeps += 1;
+  return QK_OK;
+}
+
+qk_status qk_probabilities(qk_sim s, const int32_t* qubits, int32_t nq, double* out) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
+  if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
+  if (nq < 1) return fail(s, QK_E_ARG, "list at least one qubit");
+  qk_status st = check_qubit_list(s, qubits, nq, std::min(s->n, 24));
+  if (st) return st;
+  if (!out) return fail(s, QK_E_ARG, "out is NULL");
+  if ((st = flush(s))) return st;
+  const MarginalLayout ml = marginal_layout(s->n, nq);
+  const size_t need = (ml.partial_doubles + ml.nrows) * sizeof(double);
+  if ((st = ensure(s, s->samp, std::max(need, sample_layout(s->n).doubles * sizeof(double)), "distribution work space")))
+    return st;
+  double* partial = (double*)s->samp.p;
+  double* d_out = partial + ml.partial_doubles;
+  Launch L = make_launch(s, {});
+  hipError_t e = launch_marginal(L, qubits, nq, partial, d_out);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, d_out, ml.nrows * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "probabilities");
+  s->sweeps += 1;
+  if ((st = sync_stream(s))) return st;
+  double total = 0.0;
+  for (uint64_t m = 0; m < ml.nrows; ++m) total += out[m];
+  if (!(total > 0.0)) return fail(s, QK_E_STATE, "state has zero norm");
+  for (uint64_t m = 0; m < ml.nrows; ++m) out[m] /= total;
   return QK_OK;
 }
 

@@ -104,6 +104,27 @@ hipError_t launch_measure(const Launch& L, int qubit, int cbit, double u, const 
 hipError_t launch_inner_partials(const void* a, bool a64, const void* b, bool b64, uint64_t dim,
                                  double* partials, int nblocks, hipStream_t s);
 
+// ---- deferred measurement (sample.hip) ---------------------------------------
+// Shots drawn from the state without collapse: launch_cdf fills `work`
+// (sample_layout(n).doubles FP64 values: segment sums, chunk sums, chunk
+// prefix with the total last); launch_draw turns device uniforms into indices
+// projected onto the listed qubits (nq = 0: the index itself).
+struct SampleLayout {
+  uint64_t nseg, nchunk, doubles;
+};
+SampleLayout sample_layout(int n);
+hipError_t launch_cdf(const Launch& L, double* work);
+hipError_t launch_draw(const Launch& L, const double* work, const int* qubits, int nq, const double* d_u,
+                       uint64_t nshots, uint64_t* d_out);
+// Marginal distribution (unnormalised) of nq >= 1 listed qubits into d_out
+// (2^nq doubles); `partial` holds marginal_layout(n, nq).partial_doubles.
+struct MarginalLayout {
+  uint64_t nrows, nslabs, partial_doubles;
+  int slab_bits;
+};
+MarginalLayout marginal_layout(int n, int nq);
+hipError_t launch_marginal(const Launch& L, const int* qubits, int nq, double* partial, double* d_out);
+
 // ---- matrix-core kernel (fused.hip) -----------------------------------------
 // Dense 2^k x 2^k gate (2 <= k <= 6) on targets, restricted to controls = 1,
 // as a complex GEMM per 16-column tile on 16x16x4 MFMA (f32 for complex64,

@@ -70,6 +70,9 @@ SIGNATURES = {
     "qk_measure_dev": (_I32, [_P, _I32, _I32, _P]),
     "qk_postselect": (_I32, [_P, _I32, _I32, _I32]),
     "qk_read_cbits": (_I32, [_P, _U8P, _I32]),
+    "qk_sample": (_I32, [_P, _I32P, _I32, _DP, _I64, _U64P]),
+    "qk_sample_dev": (_I32, [_P, _I32P, _I32, _P, _I64, _P]),
+    "qk_probabilities": (_I32, [_P, _I32P, _I32, _DP]),
     "qk_read_measure_log": (_I32, [_P, _DP, _I32, _I32P]),
     "qk_get_state": (_I32, [_P, _P, _SZ]),
     "qk_set_state": (_I32, [_P, _P, _SZ]),
@@ -292,6 +295,30 @@ class Sim:
 
     def postselect(self, qubit: int, cbit: int, outcome: int):
         self._chk(self.lib.qk_postselect(self.h, qubit, cbit, outcome))
+
+    def sample(self, uniforms, qubits=()) -> np.ndarray:
+        """Deferred measurement: one shot per uniform in [0, 1); bit j of each
+        result is bit qubits[j] of the drawn index (the index itself when
+        qubits is empty).  The state is left unchanged."""
+        qs = (C.c_int32 * max(1, len(qubits)))(*[int(q) for q in qubits])
+        u = np.ascontiguousarray(np.asarray(uniforms, dtype=np.float64).reshape(-1))
+        out = np.empty(max(1, len(u)), dtype=np.uint64)
+        self._chk(self.lib.qk_sample(self.h, qs, len(qubits), u.ctypes.data_as(_DP), len(u),
+                                     out.ctypes.data_as(_U64P)))
+        return out[: len(u)]
+
+    def sample_dev(self, d_uniforms_ptr: int, n_shots: int, d_out_ptr: int, qubits=()):
+        """As sample() with device arrays (n_shots doubles in, n_shots uint64 out); asynchronous."""
+        qs = (C.c_int32 * max(1, len(qubits)))(*[int(q) for q in qubits])
+        self._chk(self.lib.qk_sample_dev(self.h, qs, len(qubits), C.c_void_p(d_uniforms_ptr), n_shots,
+                                         C.c_void_p(d_out_ptr)))
+
+    def probabilities(self, qubits) -> np.ndarray:
+        """Normalised distribution of the listed qubits (entry m: bit j of m = qubits[j])."""
+        qs = (C.c_int32 * max(1, len(qubits)))(*[int(q) for q in qubits])
+        out = np.empty(1 << len(qubits), dtype=np.float64)
+        self._chk(self.lib.qk_probabilities(self.h, qs, len(qubits), out.ctypes.data_as(_DP)))
+        return out
 
     def read_cbits(self, n: Optional[int] = None) -> np.ndarray:
         n = self.ncbits if n is None else n

@@ -207,3 +207,18 @@ def test_fusion_plan_quality_on_the_30_qubit_layers():
     per_block = len(ops) / len(blocks)
     print(f"{len(ops)} gates -> {len(blocks)} blocks ({per_block:.2f} gates per block)")
     assert per_block >= 6.0
+
+
+def test_sampling_entry_points_reject_before_device_work():
+    lib, h = _sim_nogpu()
+    u = np.array([0.5], dtype=np.float64)
+    out = np.zeros(1, dtype=np.uint64)
+    dp = np.zeros(2, dtype=np.float64)
+    qs = (C.c_int32 * 1)(0)
+    # no qubits yet: nothing to sample or to tabulate
+    assert lib.qk_sample(h, qs, 1, u.ctypes.data_as(qk._DP), 1, out.ctypes.data_as(qk._U64P)) == -6
+    assert lib.qk_sample_dev(h, qs, 1, None, 0, None) == -6
+    assert lib.qk_probabilities(h, qs, 1, dp.ctypes.data_as(qk._DP)) == -6
+    assert lib.qk_sample(None, qs, 1, u.ctypes.data_as(qk._DP), 1, out.ctypes.data_as(qk._U64P)) == -1
+    assert lib.qk_probabilities(None, qs, 1, dp.ctypes.data_as(qk._DP)) == -1
+    lib.qk_destroy(h)
