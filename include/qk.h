@@ -109,6 +109,34 @@ typedef struct qk_cond {
  * Allocates nothing on the device until qubits are added. */
 qk_status qk_create(qk_dtype dtype, const qk_allocator* alloc, void* hip_stream, qk_sim* out);
 
+/* Create a simulator whose state is kept sparse: only its nonzero amplitudes,
+ * as entries with ascending amplitude index (the paper runs circuits whose
+ * state stays sparse -- the recycled-qubit Shor circuit, and a 39-qubit
+ * conventional Shor circuit on a 12 GB desktop -- section "Shor's
+ * Factorization with Q-Kit.").  Up to 62 qubits; at most `max_nonzeros`
+ * entries (1 .. 2^32), for which about 60 (complex64) or 76 (complex128)
+ * bytes each of device memory are allocated when qubits are first added.
+ * Gates, conditions, measurement, cbits, shots, qk_norm2, qk_reset and the
+ * measurement log work as for a dense simulator (same definitions; a gate
+ * whose result would exceed max_nonzeros fails with QK_E_OOM and leaves the
+ * state unchanged); qk_get_state / qk_set_state convert from / to a dense
+ * host vector (n <= 40).  Not available: fusion, graph capture,
+ * qk_state_ptr, qk_probabilities, inner products between two simulators.
+ * Gates with classical conditions read the cbits back, and gates that change
+ * the set of nonzero entries read entry counts back, so calls synchronise. */
+qk_status qk_create_sparse(qk_dtype dtype, const qk_allocator* alloc, void* hip_stream, int64_t max_nonzeros,
+                           qk_sim* out);
+
+/* Number of entries (nonzero amplitudes, counting those that cancel to
+ * exactly 0 only when a measurement drops them) of a sparse simulator. */
+qk_status qk_sparse_nnz(qk_sim sim, int64_t* nnz);
+
+/* Copy the entries of a sparse simulator to host memory: idx[i] ascending
+ * amplitude indices, amps[i] their amplitudes (interleaved re, im in the
+ * simulator's precision); cap = room in both arrays (QK_E_ARG if smaller than
+ * the entry count, which *nnz receives).  Synchronises. */
+qk_status qk_sparse_entries(qk_sim sim, uint64_t* idx, void* amps, int64_t cap, int64_t* nnz);
+
 /* Synchronise and release every buffer of the simulator. */
 qk_status qk_destroy(qk_sim sim);
 

@@ -19,7 +19,7 @@ OBJDIR = os.path.join(HERE, "_build")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(LIBDIR, "libqk.so")
 
-SOURCES = ["api.hip", "kernels.hip", "fused.hip", "fusion.cpp", "batch.hip", "sample.hip"]
+SOURCES = ["api.hip", "kernels.hip", "fused.hip", "fusion.cpp", "batch.hip", "sample.hip", "sparse.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -31,6 +31,7 @@ struct UserGate {
   bool diag = false;
   DevBuf dmat;             // matrix in the state's precision (uploaded at define time)
   DevBuf finv;             // inverse table, uint32 (U_TABLE)
+  DevBuf ftab;             // forward table, uint32 (U_TABLE; the sparse engine maps indices forward)
   uint64_t a = 1, b = 0;   // U_AFFINE; U_MODMUL: multiplier a, modulus b
 };
 
@@ -72,6 +73,8 @@ struct qk_sim_s {
   int n = 0;
   DevBuf state, scratch, cbits, meas;
   DevBuf samp, shots;               // deferred-measurement work space; host-call staging of uniforms and shots
+  bool sparse = false;              // state kept as sorted (index, amplitude) entries
+  SpBufs sp;
   int ncbits = 0;
   std::vector<Arena> arenas;        // constant chunks in use (the last one is being filled)
   std::vector<Arena> saved_arenas;  // chunks set aside while a capture owns `arenas`
@@ -90,6 +93,7 @@ namespace {
 constexpr int kUserBase = 0x100;
 constexpr size_t kArenaBytes = 32u << 20;
 constexpr int kMaxQubits = 40;
+constexpr int kMaxSparseQubits = 62;    // indices and the sort's sentinel bit fit 64 bits
 
 qk_status fail(qk_sim s, qk_status st, const std::string& msg) {
   if (s) s->err = msg;
@@ -564,6 +568,11 @@ qk_status upload_table(qk_sim s, UserGate* g, const std::vector<uint64_t>& table
   if (st) return st;
   hipError_t e = hipMemcpy(g->finv.p, finv.data(), K * sizeof(uint32_t), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(s, e, "permutation table upload");
+  std::vector<uint32_t> fwd(K);
+  for (uint64_t x = 0; x < K; ++x) fwd[x] = (uint32_t)table[x];
+  if ((st = ensure(s, g->ftab, K * sizeof(uint32_t), "permutation table"))) return st;
+  e = hipMemcpy(g->ftab.p, fwd.data(), K * sizeof(uint32_t), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(s, e, "permutation table upload");
   return QK_OK;
 }
 
@@ -583,10 +592,119 @@ qk_status define_perm(qk_sim s, const char* name, int32_t k, const std::vector<u
   qk_status st = upload_table(s, g, table);
   if (st) {
     dev_free(s, g->finv);
+    dev_free(s, g->ftab);
     delete g;
     return st;
   }
   return new_user_gate(s, g, out);
+}
+
+// ---- sparse state ------------------------------------------------------------
+
+struct SpArray {
+  void** p;
+  size_t bytes;
+};
+
+std::vector<SpArray> sp_arrays(qk_sim s) {
+  const size_t c = s->sp.cap;
+  return {{(void**)&s->sp.idx, c * 8}, {&s->sp.amp, c * s->amp}, {(void**)&s->sp.idx_b, c * 8},
+          {&s->sp.amp_b, c * s->amp}, {(void**)&s->sp.key, c * 8}, {(void**)&s->sp.cnt, c * 4},
+          {(void**)&s->sp.off, c * 8}, {(void**)&s->sp.scal, 16}, {&s->sp.temp, s->sp.temp_bytes}};
+}
+
+void sp_free(qk_sim s) {
+  for (SpArray& a : sp_arrays(s)) {
+    DevBuf b{*a.p, a.bytes};
+    dev_free(s, b);
+    *a.p = nullptr;
+  }
+  s->sp.nnz = 0;
+}
+
+qk_status sp_alloc(qk_sim s) {
+  s->sp.temp_bytes = std::max<size_t>(256, sp_temp_bytes(s->sp.cap, s->c64));
+  for (SpArray& a : sp_arrays(s)) {
+    *a.p = dev_alloc(s, a.bytes);
+    if (!*a.p) {
+      sp_free(s);
+      return fail(s, QK_E_OOM, "device allocation failed: sparse state of " + std::to_string(s->sp.cap) + " entries");
+    }
+  }
+  return QK_OK;
+}
+
+qk_status sp_check(qk_sim s, hipError_t e, const char* what) {
+  if (e == hipSuccess) return QK_OK;
+  if (e == hipErrorOutOfMemory)
+    return fail(s, QK_E_OOM, std::string(what) + ": the result would exceed the sparse capacity of " +
+                                 std::to_string(s->sp.cap) + " entries (state unchanged)");
+  return hip_fail(s, e, what);
+}
+
+qk_status sparse_execute(qk_sim s, const GateDesc& d) {
+  if (!d.conds.empty()) {   // the sparse engine synchronises anyway: decide on the host
+    std::vector<uint8_t> cb(s->ncbits);
+    hipError_t e = hipMemcpyAsync(cb.data(), s->cbits.p, cb.size(), hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "condition readback");
+    for (const qk_cond& c : d.conds)
+      if (cb[c.cbit] != (uint8_t)c.value) return QK_OK;
+  }
+  SpTargets t{};
+  t.k = (int)d.targets.size();
+  for (int j = 0; j < t.k; ++j) t.pos[j] = d.targets[j];
+  uint64_t cmask = 0;
+  for (int c : d.controls) cmask |= 1ull << c;
+  hipError_t e = hipSuccess;
+  s->sweeps += 1;
+  switch (d.kind) {
+    case D_BUTTERFLY:
+    case D_DENSE: {
+      const void* dmat = d.ug ? d.ug->dmat.p : nullptr;
+      if (!dmat) {
+        std::vector<unsigned char> packed = pack_matrix(d.m, s->c64);
+        qk_status st = arena_put(s, packed.data(), packed.size(), &dmat);
+        if (st) return st;
+      }
+      return sp_check(s, sp_dense_gate(s->sp, s->n, s->c64, t, cmask, dmat, s->stream), "sparse gate");
+    }
+    case D_DIAG:
+    case D_PHASE1: {
+      const int D = 1 << t.k;
+      std::vector<cd> dg(D, cd(1.0));
+      if (d.kind == D_DIAG) dg = d.m;
+      else dg[D - 1] = d.z;
+      if (t.k > 6) {   // beyond the 64-entry table: as a dense diagonal matrix
+        std::vector<cd> m((size_t)D * D, cd(0.0));
+        for (int i = 0; i < D; ++i) m[(size_t)i * D + i] = dg[i];
+        std::vector<unsigned char> packed = pack_matrix(m, s->c64);
+        const void* dmat = nullptr;
+        qk_status st = arena_put(s, packed.data(), packed.size(), &dmat);
+        if (st) return st;
+        return sp_check(s, sp_dense_gate(s->sp, s->n, s->c64, t, cmask, dmat, s->stream), "sparse gate");
+      }
+      Diag64 dd{};
+      for (int i = 0; i < D; ++i) {
+        dd.v[2 * i] = dg[i].real();
+        dd.v[2 * i + 1] = dg[i].imag();
+      }
+      e = sp_diag(s->sp, s->c64, t, cmask, dd, s->stream);
+      return sp_check(s, e, "sparse diagonal");
+    }
+    case D_SWAP:
+      return sp_check(s, sp_permute(s->sp, s->n, s->c64, t, cmask, SP_PERM_SWAP, nullptr, 0, 0, 0, s->stream),
+                      "sparse swap");
+    case D_PERM: {
+      const int mode = d.ug->kind == U_AFFINE ? SP_PERM_AFFINE
+                                                : (d.ug->kind == U_MODMUL ? SP_PERM_MODMUL : SP_PERM_TABLE);
+      return sp_check(s,
+                      sp_permute(s->sp, s->n, s->c64, t, cmask, mode, (const uint32_t*)d.ug->ftab.p, d.A, d.B, d.N,
+                                 s->stream),
+                      "sparse permutation");
+    }
+  }
+  return fail(s, QK_E_ARG, "unknown gate class");
 }
 
 }  // namespace
@@ -633,6 +751,17 @@ qk_status qk_create(qk_dtype dtype, const qk_allocator* alloc, void* hip_stream,
   return QK_OK;
 }
 
+qk_status qk_create_sparse(qk_dtype dtype, const qk_allocator* alloc, void* hip_stream, int64_t max_nonzeros,
+                           qk_sim* out) {
+  if (max_nonzeros < 1 || max_nonzeros > ((int64_t)1 << 32))
+    return fail(nullptr, QK_E_ARG, "max_nonzeros must be in [1, 2^32]");
+  qk_status st = qk_create(dtype, alloc, hip_stream, out);
+  if (st) return st;
+  (*out)->sparse = true;
+  (*out)->sp.cap = (uint64_t)max_nonzeros;
+  return QK_OK;
+}
+
 qk_status qk_destroy(qk_sim s) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
   if (s->capturing) {
@@ -641,18 +770,20 @@ qk_status qk_destroy(qk_sim s) {
     if (g) (void)hipGraphDestroy(g);
     s->capturing = false;
   }
-  if (s->state.p || s->meas.p || !s->arenas.empty()) (void)hipStreamSynchronize(s->stream);
+  if (s->state.p || s->meas.p || s->sp.idx || !s->arenas.empty()) (void)hipStreamSynchronize(s->stream);
   dev_free(s, s->state);
   dev_free(s, s->scratch);
   dev_free(s, s->cbits);
   dev_free(s, s->meas);
   dev_free(s, s->samp);
   dev_free(s, s->shots);
+  if (s->sparse) sp_free(s);
   for (Arena& a : s->arenas) arena_free_chunk(s, a);
   for (Arena& a : s->saved_arenas) arena_free_chunk(s, a);
   for (UserGate* g : s->ugates) {
     dev_free(s, g->dmat);
     dev_free(s, g->finv);
+    dev_free(s, g->ftab);
     delete g;
   }
   delete s;
@@ -663,6 +794,18 @@ qk_status qk_add_qubits(qk_sim s, int32_t count, int32_t* first) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
   if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   if (count < 0) return fail(s, QK_E_ARG, "count < 0");
+  if (s->sparse) {   // new qubits take the high bits in |0>: the entries keep their indices
+    if (s->n + count > kMaxSparseQubits) return fail(s, QK_E_ARG, "too many qubits");
+    if (first) *first = s->n;
+    if (!s->sp.idx) {
+      qk_status st = sp_alloc(s);
+      if (st) return st;
+      hipError_t e = sp_init(s->sp, s->c64, s->stream);
+      if (e != hipSuccess) return hip_fail(s, e, "add_qubits");
+    }
+    s->n += count;
+    return QK_OK;
+  }
   if (s->n + count > kMaxQubits) return fail(s, QK_E_ARG, "too many qubits");
   if (first) *first = s->n;
   if (count == 0 && s->state.p) return QK_OK;
@@ -912,6 +1055,7 @@ qk_status qk_apply_gate(qk_sim s, qk_gate gate, const int32_t* targets, int32_t 
       d.Ainv = inv_mod(A, N);
     }
   }
+  if (s->sparse) return sparse_execute(s, d);
   if (d.conds.empty() && d.fusable && s->fuse_k >= 2 && nt + nc <= s->fuse_k) {
     s->pending.push_back(std::move(d));
     return QK_OK;
@@ -929,6 +1073,10 @@ qk_status qk_measure(qk_sim s, int32_t qubit, int32_t cbit, double u) {
   qk_status st = flush(s);
   if (st) return st;
   if ((st = ensure_meas(s))) return st;
+  if (s->sparse) {
+    s->sweeps += 1;
+    return sp_check(s, sp_measure(s->sp, s->c64, qubit, cbit, u, nullptr, -1, meas_buffers(s), s->stream), "measure");
+  }
   Launch L = make_launch(s, {});
   hipError_t e = launch_measure(L, qubit, cbit, u, nullptr, -1, meas_buffers(s));
   if (e != hipSuccess) return hip_fail(s, e, "measure");
@@ -944,6 +1092,10 @@ qk_status qk_measure_dev(qk_sim s, int32_t qubit, int32_t cbit, const double* d_
   qk_status st = flush(s);
   if (st) return st;
   if ((st = ensure_meas(s))) return st;
+  if (s->sparse) {
+    s->sweeps += 1;
+    return sp_check(s, sp_measure(s->sp, s->c64, qubit, cbit, 0.0, d_u, -1, meas_buffers(s), s->stream), "measure");
+  }
   Launch L = make_launch(s, {});
   hipError_t e = launch_measure(L, qubit, cbit, 0.0, d_u, -1, meas_buffers(s));
   if (e != hipSuccess) return hip_fail(s, e, "measure");
@@ -962,7 +1114,8 @@ qk_status qk_postselect(qk_sim s, int32_t qubit, int32_t cbit, int32_t outcome) 
   if ((st = ensure_meas(s))) return st;
   Launch L = make_launch(s, {});
   MeasBuffers mb = meas_buffers(s);
-  hipError_t e = launch_measure(L, qubit, cbit, 0.0, nullptr, outcome, mb);
+  hipError_t e = s->sparse ? sp_measure(s->sp, s->c64, qubit, cbit, 0.0, nullptr, outcome, mb, s->stream)
+                           : launch_measure(L, qubit, cbit, 0.0, nullptr, outcome, mb);
   if (e != hipSuccess) return hip_fail(s, e, "postselect");
   double res[4];
   e = hipMemcpyAsync(res, mb.result, sizeof res, hipMemcpyDeviceToHost, s->stream);
@@ -1027,13 +1180,15 @@ static qk_status check_qubit_list(qk_sim s, const int32_t* qubits, int32_t nq, i
   return QK_OK;
 }
 
+static uint64_t sample_dim(qk_sim s) { return s->sparse ? s->sp.nnz : (1ull << s->n); }
+
 static qk_status sample_common(qk_sim s, const int32_t* qubits, int32_t nq, int64_t nshots) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
-  if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
+  if (!s->state.p && !s->sp.idx) return fail(s, QK_E_STATE, "no qubits");
   if (nshots < 0 || nshots > ((int64_t)1 << 32)) return fail(s, QK_E_ARG, "n_shots must be in [0, 2^32]");
   qk_status st = check_qubit_list(s, qubits, nq, s->n);
   if (st) return st;
-  const size_t need = sample_layout(s->n).doubles * sizeof(double);
+  const size_t need = (s->sparse ? sample_layout_dim(s->sp.cap) : sample_layout(s->n)).doubles * sizeof(double);
   if (s->capturing) {
     if (!s->samp.p || s->samp.bytes < need)
       return fail(s, QK_E_STATE, "sampling work space missing: sample once before capturing");
@@ -1041,6 +1196,26 @@ static qk_status sample_common(qk_sim s, const int32_t* qubits, int32_t nq, int6
   }
   if ((st = flush(s))) return st;
   return ensure(s, s->samp, need, "sampling work space");
+}
+
+// Distribution sweep and shots.  A sparse state draws positions in its entry
+// array (into `pos`, n_shots words) and maps them to indices.
+static hipError_t draw_shots(qk_sim s, const int32_t* qubits, int32_t nq, const double* d_u, uint64_t nshots,
+                             uint64_t* d_out, uint64_t* pos) {
+  double* work = (double*)s->samp.p;
+  if (!s->sparse) {
+    Launch L = make_launch(s, {});
+    hipError_t e = launch_cdf(L, work);
+    if (e == hipSuccess) e = launch_draw(L, work, qubits, nq, d_u, nshots, d_out);
+    return e;
+  }
+  hipError_t e = launch_cdf_dim(s->sp.amp, s->sp.nnz, s->c64, s->stream, work);
+  if (e == hipSuccess) e = launch_draw_dim(s->sp.amp, s->sp.nnz, s->c64, s->stream, work, d_u, nshots, pos);
+  SpTargets ql{};
+  ql.k = nq;
+  for (int j = 0; j < nq; ++j) ql.pos[j] = qubits[j];
+  if (e == hipSuccess) e = sp_project(s->sp, pos, nshots, ql, d_out, s->stream);
+  return e;
 }
 
 qk_status qk_sample(qk_sim s, const int32_t* qubits, int32_t nq, const double* uniforms, int64_t nshots,
@@ -1051,17 +1226,17 @@ qk_status qk_sample(qk_sim s, const int32_t* qubits, int32_t nq, const double* u
   if (nshots > 0 && (!uniforms || !out)) return fail(s, QK_E_ARG, "uniforms and out must be given");
   for (int64_t i = 0; i < nshots; ++i)
     if (!(uniforms[i] >= 0.0 && uniforms[i] < 1.0)) return fail(s, QK_E_ARG, "uniforms must lie in [0, 1)");
-  if ((st = ensure(s, s->shots, (size_t)std::max<int64_t>(nshots, 1) * 16, "shot staging"))) return st;
+  const size_t S1 = (size_t)std::max<int64_t>(nshots, 1);
+  if ((st = ensure(s, s->shots, S1 * (s->sparse ? 24 : 16), "shot staging"))) return st;
   double* d_u = (double*)s->shots.p;
-  uint64_t* d_out = (uint64_t*)((char*)s->shots.p + (size_t)std::max<int64_t>(nshots, 1) * 8);
-  Launch L = make_launch(s, {});
+  uint64_t* d_out = (uint64_t*)((char*)s->shots.p + S1 * 8);
+  uint64_t* pos = (uint64_t*)((char*)s->shots.p + S1 * 16);
   hipError_t e = hipSuccess;
   if (nshots > 0) e = hipMemcpyAsync(d_u, uniforms, (size_t)nshots * 8, hipMemcpyHostToDevice, s->stream);
-  if (e == hipSuccess) e = launch_cdf(L, (double*)s->samp.p);
-  if (e == hipSuccess) e = launch_draw(L, (const double*)s->samp.p, qubits, nq, d_u, (uint64_t)nshots, d_out);
+  if (e == hipSuccess) e = draw_shots(s, qubits, nq, d_u, (uint64_t)nshots, d_out, pos);
   if (e != hipSuccess) return hip_fail(s, e, "sample");
   s->sweeps += 1;
-  const SampleLayout sl = sample_layout(s->n);
+  const SampleLayout sl = sample_layout_dim(sample_dim(s));
   double total = 0.0;
   e = hipMemcpyAsync(&total, (double*)s->samp.p + sl.nseg + 2 * sl.nchunk, sizeof total, hipMemcpyDeviceToHost,
                      s->stream);
@@ -1078,9 +1253,12 @@ qk_status qk_sample_dev(qk_sim s, const int32_t* qubits, int32_t nq, const doubl
   qk_status st = sample_common(s, qubits, nq, nshots);
   if (st) return st;
   if (nshots > 0 && (!d_u || !d_out)) return fail(s, QK_E_ARG, "d_uniforms and d_out must be given");
-  Launch L = make_launch(s, {});
-  hipError_t e = launch_cdf(L, (double*)s->samp.p);
-  if (e == hipSuccess) e = launch_draw(L, (const double*)s->samp.p, qubits, nq, d_u, (uint64_t)nshots, d_out);
+  uint64_t* pos = nullptr;
+  if (s->sparse) {
+    if ((st = ensure(s, s->shots, (size_t)std::max<int64_t>(nshots, 1) * 8, "shot positions"))) return st;
+    pos = (uint64_t*)s->shots.p;
+  }
+  hipError_t e = draw_shots(s, qubits, nq, d_u, (uint64_t)nshots, d_out, pos);
   if (e != hipSuccess) return hip_fail(s, e, "sample");
   s->sweeps += 1;
   return QK_OK;
@@ -1088,6 +1266,7 @@ qk_status qk_sample_dev(qk_sim s, const int32_t* qubits, int32_t nq, const doubl
 
 qk_status qk_probabilities(qk_sim s, const int32_t* qubits, int32_t nq, double* out) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->sparse) return fail(s, QK_E_UNSUPPORTED, "probabilities of a sparse state: draw shots instead");
   if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
   if (nq < 1) return fail(s, QK_E_ARG, "list at least one qubit");
@@ -1114,9 +1293,35 @@ qk_status qk_probabilities(qk_sim s, const int32_t* qubits, int32_t nq, double* 
   return QK_OK;
 }
 
+// Copy the sparse entries to host memory (synchronises).
+static qk_status sp_read(qk_sim s, std::vector<uint64_t>& idx, std::vector<unsigned char>& amp) {
+  idx.resize(s->sp.nnz);
+  amp.resize(s->sp.nnz * s->amp);
+  hipError_t e = hipSuccess;
+  if (s->sp.nnz) {
+    e = hipMemcpyAsync(idx.data(), s->sp.idx, s->sp.nnz * 8, hipMemcpyDeviceToHost, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(amp.data(), s->sp.amp, amp.size(), hipMemcpyDeviceToHost, s->stream);
+  }
+  if (e != hipSuccess) return hip_fail(s, e, "sparse readback");
+  return sync_stream(s);
+}
+
 qk_status qk_get_state(qk_sim s, void* host_out, size_t bytes) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
   if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
+  if (s->sparse) {   // the dense vector, assembled on the host from the entries
+    if (s->n > kMaxQubits || !host_out || bytes != ((size_t)1 << s->n) * s->amp)
+      return fail(s, QK_E_ARG, "buffer size must be 2^n * amplitude size (n <= 40)");
+    if (!s->sp.idx) return fail(s, QK_E_STATE, "no qubits");
+    std::vector<uint64_t> idx;
+    std::vector<unsigned char> amp;
+    qk_status st = sp_read(s, idx, amp);
+    if (st) return st;
+    std::memset(host_out, 0, bytes);
+    for (size_t i = 0; i < idx.size(); ++i)
+      std::memcpy((char*)host_out + idx[i] * s->amp, amp.data() + i * s->amp, s->amp);
+    return QK_OK;
+  }
   const size_t need = ((size_t)1 << s->n) * s->amp;
   if (!host_out || bytes != need) return fail(s, QK_E_ARG, "buffer size must be 2^n * amplitude size");
   if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
@@ -1130,6 +1335,31 @@ qk_status qk_get_state(qk_sim s, void* host_out, size_t bytes) {
 qk_status qk_set_state(qk_sim s, const void* host_in, size_t bytes) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
   if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
+  if (s->sparse) {   // keep the nonzero amplitudes, in index order
+    if (s->n > kMaxQubits || !host_in || bytes != ((size_t)1 << s->n) * s->amp)
+      return fail(s, QK_E_ARG, "buffer size must be 2^n * amplitude size (n <= 40)");
+    if (!s->sp.idx) return fail(s, QK_E_STATE, "no qubits");
+    std::vector<uint64_t> idx;
+    std::vector<unsigned char> amp;
+    const unsigned char* src = (const unsigned char*)host_in;
+    static const unsigned char zero16[16] = {0};
+    for (uint64_t i = 0; i < (1ull << s->n); ++i) {
+      if (std::memcmp(src + i * s->amp, zero16, s->amp) == 0) continue;
+      idx.push_back(i);
+      amp.insert(amp.end(), src + i * s->amp, src + (i + 1) * s->amp);
+    }
+    if (idx.size() > s->sp.cap) return fail(s, QK_E_OOM, "state has more nonzeros than the sparse capacity");
+    qk_status st = sync_stream(s);
+    if (st) return st;
+    hipError_t e = hipSuccess;
+    if (!idx.empty()) {
+      e = hipMemcpy(s->sp.idx, idx.data(), idx.size() * 8, hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(s->sp.amp, amp.data(), amp.size(), hipMemcpyHostToDevice);
+    }
+    if (e != hipSuccess) return hip_fail(s, e, "set_state");
+    s->sp.nnz = idx.size();
+    return QK_OK;
+  }
   const size_t need = ((size_t)1 << s->n) * s->amp;
   if (!host_in || bytes != need) return fail(s, QK_E_ARG, "buffer size must be 2^n * amplitude size");
   if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
@@ -1142,6 +1372,7 @@ qk_status qk_set_state(qk_sim s, const void* host_in, size_t bytes) {
 
 qk_status qk_state_ptr(qk_sim s, void** dev_ptr, size_t* bytes) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->sparse) return fail(s, QK_E_UNSUPPORTED, "a sparse state has no dense vector");
   qk_status st = flush(s);
   if (st) return st;
   if (dev_ptr) *dev_ptr = s->state.p;
@@ -1149,8 +1380,48 @@ qk_status qk_state_ptr(qk_sim s, void** dev_ptr, size_t* bytes) {
   return QK_OK;
 }
 
+qk_status qk_sparse_nnz(qk_sim s, int64_t* nnz) {
+  if (!s || !nnz) return fail(s, QK_E_ARG, "sim or nnz is NULL");
+  if (!s->sparse) return fail(s, QK_E_UNSUPPORTED, "not a sparse simulator");
+  *nnz = (int64_t)s->sp.nnz;
+  return QK_OK;
+}
+
+qk_status qk_sparse_entries(qk_sim s, uint64_t* idx, void* amps, int64_t cap, int64_t* nnz) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (!s->sparse) return fail(s, QK_E_UNSUPPORTED, "not a sparse simulator");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
+  if (nnz) *nnz = (int64_t)s->sp.nnz;
+  if (cap < (int64_t)s->sp.nnz) return fail(s, QK_E_ARG, "cap is smaller than the number of entries");
+  if (s->sp.nnz && (!idx || !amps)) return fail(s, QK_E_ARG, "idx and amps must be given");
+  if (!s->sp.nnz) return QK_OK;   // no qubits added yet
+  hipError_t e = hipMemcpyAsync(idx, s->sp.idx, s->sp.nnz * 8, hipMemcpyDeviceToHost, s->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(amps, s->sp.amp, s->sp.nnz * s->amp, hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "sparse entries");
+  return sync_stream(s);
+}
+
 qk_status qk_inner_product(qk_sim a, qk_sim b, double* re, double* im) {
   if (!a || !b) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (a->sparse || b->sparse) {
+    if (a != b) return fail(a, QK_E_UNSUPPORTED, "inner product with a sparse state");
+    if (!a->sp.idx) return fail(a, QK_E_STATE, "no qubits");
+    qk_status st = ensure_meas(a);
+    if (st) return st;
+    const int nb = reduce_blocks_for(a->sp.nnz);
+    MeasBuffers mb = meas_buffers(a);
+    hipError_t e = sp_norm_partials(a->sp, a->c64, mb.partials, nb, a->stream);
+    std::vector<double> part(nb);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(part.data(), mb.partials, nb * sizeof(double), hipMemcpyDeviceToHost, a->stream);
+    if (e != hipSuccess) return hip_fail(a, e, "norm");
+    if ((st = sync_stream(a))) return st;
+    double sum = 0;
+    for (int i = 0; i < nb; ++i) sum += part[i];
+    if (re) *re = sum;
+    if (im) *im = 0.0;
+    return QK_OK;
+  }
   if (a->n != b->n || !a->state.p || !b->state.p) return fail(a, QK_E_ARG, "qubit counts differ or no state");
   if (a->capturing || b->capturing) return fail(a, QK_E_STATE, "not allowed while capturing a graph");
   qk_status st = flush(a);
@@ -1196,12 +1467,17 @@ struct qk_graph_s {
 
 qk_status qk_reset(qk_sim s) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
-  if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
+  if (!s->state.p && !s->sp.idx) return fail(s, QK_E_STATE, "no qubits");
   qk_status st = flush(s);
   if (st) return st;
-  const uint64_t dim = 1ull << s->n;
-  hipError_t e = launch_fill_zero(s->state.p, 0, dim, s->c64, s->stream);
-  if (e == hipSuccess) e = launch_set_one(s->state.p, 0, s->c64, s->stream);
+  hipError_t e;
+  if (s->sparse) {
+    e = sp_init(s->sp, s->c64, s->stream);
+  } else {
+    const uint64_t dim = 1ull << s->n;
+    e = launch_fill_zero(s->state.p, 0, dim, s->c64, s->stream);
+    if (e == hipSuccess) e = launch_set_one(s->state.p, 0, s->c64, s->stream);
+  }
   if (e == hipSuccess && s->ncbits > 0) {
     hipLaunchKernelGGL(k_u8_fill, dim3(std::max<size_t>(1, std::min<size_t>(1024, (s->ncbits + 255) / 256))),
                        dim3(256), 0, s->stream, (uint8_t*)s->cbits.p, (size_t)0, (size_t)s->ncbits, (uint8_t)0);
@@ -1213,6 +1489,7 @@ qk_status qk_reset(qk_sim s) {
 
 qk_status qk_capture_begin(qk_sim s) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->sparse) return fail(s, QK_E_UNSUPPORTED, "a sparse simulator cannot be captured (it reads entry counts back)");
   if (s->capturing) return fail(s, QK_E_STATE, "already capturing");
   if (!s->state.p) return fail(s, QK_E_STATE, "add qubits before capturing");
   qk_status st = flush(s);
@@ -1342,6 +1619,7 @@ qk_status qk_plan_fusion(int32_t n, const qk_op* ops, int32_t nops, int32_t max_
 qk_status qk_set_fusion(qk_sim s, int32_t max_k) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
   if (max_k != 0 && (max_k < 2 || max_k > QK_MAX_FUSION_K)) return fail(s, QK_E_ARG, "max_k must be 0 or 2..6");
+  if (s->sparse && max_k != 0) return fail(s, QK_E_UNSUPPORTED, "fusion applies to dense states only");
   qk_status st = flush(s);
   if (st) return st;
   s->fuse_k = max_k;
@@ -1359,7 +1637,7 @@ qk_status qk_sync(qk_sim s) {
   qk_status st = flush(s);
   if (st) return st;
   if (s->latched) return fail(s, s->latched, "an earlier asynchronous failure was latched");
-  if (!s->state.p && !s->meas.p && s->arenas.empty() && !s->cbits.p) return QK_OK;
+  if (!s->state.p && !s->sp.idx && !s->meas.p && s->arenas.empty() && !s->cbits.p) return QK_OK;
   st = sync_stream(s);
   if (st == QK_OK)
     for (Arena& a : s->arenas) a.used = 0;

@@ -116,6 +116,12 @@ SampleLayout sample_layout(int n);
 hipError_t launch_cdf(const Launch& L, double* work);
 hipError_t launch_draw(const Launch& L, const double* work, const int* qubits, int nq, const double* d_u,
                        uint64_t nshots, uint64_t* d_out);
+// The same over an arbitrary amplitude array of `dim` entries (the sparse
+// engine's amplitudes); draws are positions in that array (nq = 0 only).
+SampleLayout sample_layout_dim(uint64_t dim);
+hipError_t launch_cdf_dim(const void* psi, uint64_t dim, bool c64, hipStream_t s, double* work);
+hipError_t launch_draw_dim(const void* psi, uint64_t dim, bool c64, hipStream_t s, const double* work,
+                           const double* d_u, uint64_t nshots, uint64_t* d_out);
 // Marginal distribution (unnormalised) of nq >= 1 listed qubits into d_out
 // (2^nq doubles); `partial` holds marginal_layout(n, nq).partial_doubles.
 struct MarginalLayout {
@@ -124,6 +130,44 @@ struct MarginalLayout {
 };
 MarginalLayout marginal_layout(int n, int nq);
 hipError_t launch_marginal(const Launch& L, const int* qubits, int nq, double* partial, double* d_out);
+
+// ---- sparse state engine (sparse.hip) -------------------------------------------
+// The state as nnz entries with ascending indices idx[] and amplitudes amp[];
+// every array holds `cap` entries.  Operations that reorder or resize the
+// state synchronise the stream once or twice to read entry counts back.
+struct SpTargets {
+  int k;
+  int pos[64];
+};
+enum SpPermMode { SP_PERM_TABLE = 0, SP_PERM_AFFINE = 1, SP_PERM_MODMUL = 2, SP_PERM_SWAP = 3 };
+struct SpBufs {
+  uint64_t cap = 0, nnz = 0;
+  uint64_t* idx = nullptr;     // the state: ascending indices
+  void* amp = nullptr;         //            and their amplitudes
+  uint64_t* idx_b = nullptr;   // spare pair
+  void* amp_b = nullptr;
+  uint64_t* key = nullptr;     // sort keys, gate outputs
+  uint32_t* cnt = nullptr;     // per-entry counts or flags
+  uint64_t* off = nullptr;     // their exclusive scan
+  uint64_t* scal = nullptr;    // device scalars: [0] total, [1] exact-zero outputs
+  void* temp = nullptr;        // sort and scan work space
+  size_t temp_bytes = 0;
+};
+size_t sp_temp_bytes(uint64_t cap, bool c64);
+hipError_t sp_init(SpBufs& b, bool c64, hipStream_t st);
+// Dense 2^k x 2^k gate (d_mat in the state's precision, row-major) on targets
+// t, restricted to the entries whose bits in cmask are all 1.  Returns
+// hipErrorOutOfMemory (state unchanged) if the result could exceed cap.
+hipError_t sp_dense_gate(SpBufs& b, int n, bool c64, const SpTargets& t, uint64_t cmask, const void* d_mat,
+                         hipStream_t st);
+hipError_t sp_diag(SpBufs& b, bool c64, const SpTargets& t, uint64_t cmask, const Diag64& d, hipStream_t st);
+hipError_t sp_permute(SpBufs& b, int n, bool c64, const SpTargets& t, uint64_t cmask, int mode, const uint32_t* ftab,
+                      uint64_t A, uint64_t B, uint64_t N, hipStream_t st);
+hipError_t sp_measure(SpBufs& b, bool c64, int q, int cbit, double u, const double* d_u, int forced,
+                      const MeasBuffers& mb, hipStream_t st);
+hipError_t sp_norm_partials(const SpBufs& b, bool c64, double* partials, int nblocks, hipStream_t st);
+hipError_t sp_project(const SpBufs& b, const uint64_t* pos, uint64_t nshots, const SpTargets& ql, uint64_t* d_out,
+                      hipStream_t st);
 
 // ---- matrix-core kernel (fused.hip) -----------------------------------------
 // Dense 2^k x 2^k gate (2 <= k <= 6) on targets, restricted to controls = 1,

@@ -274,50 +274,61 @@ __global__ __launch_bounds__(256) void k_marginal_rows(const double* __restrict_
   }
 }
 
-SampleLayout sample_layout(int n) {
+SampleLayout sample_layout_dim(uint64_t dim) {
   SampleLayout s;
-  const uint64_t dim = 1ull << n;
   s.nseg = (dim + kSeg - 1) / kSeg;
   s.nchunk = (s.nseg + kChunkSegs - 1) / kChunkSegs;
   s.doubles = s.nseg + s.nchunk + (s.nchunk + 1);
   return s;
 }
 
-hipError_t launch_cdf(const Launch& L, double* work) {
-  const SampleLayout sl = sample_layout(L.n);
-  const uint64_t dim = 1ull << L.n;
+SampleLayout sample_layout(int n) { return sample_layout_dim(1ull << n); }
+
+hipError_t launch_cdf_dim(const void* psi, uint64_t dim, bool c64, hipStream_t st, double* work) {
+  const SampleLayout sl = sample_layout_dim(dim);
   double* seg = work;
   double* chunk = seg + sl.nseg;
   double* prefix = chunk + sl.nchunk;
   const unsigned g = blocks_for(sl.nchunk, 4);
-  if (L.c64)
-    hipLaunchKernelGGL(k_cdf_segments<float>, dim3(g), dim3(256), 0, L.stream, (const float2*)L.psi, dim, sl.nseg,
-                       sl.nchunk, seg, chunk);
+  if (c64)
+    hipLaunchKernelGGL(k_cdf_segments<float>, dim3(g), dim3(256), 0, st, (const float2*)psi, dim, sl.nseg, sl.nchunk,
+                       seg, chunk);
   else
-    hipLaunchKernelGGL(k_cdf_segments<double>, dim3(g), dim3(256), 0, L.stream, (const double2*)L.psi, dim, sl.nseg,
+    hipLaunchKernelGGL(k_cdf_segments<double>, dim3(g), dim3(256), 0, st, (const double2*)psi, dim, sl.nseg,
                        sl.nchunk, seg, chunk);
-  hipLaunchKernelGGL(k_cdf_scan, dim3(1), dim3(kScanThreads), 0, L.stream, (const double*)chunk, sl.nchunk, prefix);
+  hipLaunchKernelGGL(k_cdf_scan, dim3(1), dim3(kScanThreads), 0, st, (const double*)chunk, sl.nchunk, prefix);
   return hipGetLastError();
 }
 
-hipError_t launch_draw(const Launch& L, const double* work, const int* qubits, int nq, const double* d_u,
-                       uint64_t nshots, uint64_t* d_out) {
+static hipError_t draw(const void* psi, uint64_t dim, bool c64, hipStream_t st, const double* work, const int* qubits,
+                       int nq, const double* d_u, uint64_t nshots, uint64_t* d_out) {
   if (nshots == 0) return hipSuccess;
-  const SampleLayout sl = sample_layout(L.n);
-  const uint64_t dim = 1ull << L.n;
+  const SampleLayout sl = sample_layout_dim(dim);
   const double* seg = work;
   const double* prefix = work + sl.nseg + sl.nchunk;
   QubitList ql{};
   ql.n = nq;
   for (int j = 0; j < nq; ++j) ql.q[j] = qubits[j];
   const unsigned g = blocks_for(nshots, 4);
-  if (L.c64)
-    hipLaunchKernelGGL(k_sample<float>, dim3(g), dim3(256), 0, L.stream, (const float2*)L.psi, dim, sl.nseg, sl.nchunk,
-                       seg, prefix, d_u, nshots, ql, d_out);
+  if (c64)
+    hipLaunchKernelGGL(k_sample<float>, dim3(g), dim3(256), 0, st, (const float2*)psi, dim, sl.nseg, sl.nchunk, seg,
+                       prefix, d_u, nshots, ql, d_out);
   else
-    hipLaunchKernelGGL(k_sample<double>, dim3(g), dim3(256), 0, L.stream, (const double2*)L.psi, dim, sl.nseg,
-                       sl.nchunk, seg, prefix, d_u, nshots, ql, d_out);
+    hipLaunchKernelGGL(k_sample<double>, dim3(g), dim3(256), 0, st, (const double2*)psi, dim, sl.nseg, sl.nchunk, seg,
+                       prefix, d_u, nshots, ql, d_out);
   return hipGetLastError();
+}
+
+hipError_t launch_draw_dim(const void* psi, uint64_t dim, bool c64, hipStream_t st, const double* work,
+                           const double* d_u, uint64_t nshots, uint64_t* d_out) {
+  return draw(psi, dim, c64, st, work, nullptr, 0, d_u, nshots, d_out);
+}
+
+hipError_t launch_cdf(const Launch& L, double* work) { return launch_cdf_dim(L.psi, 1ull << L.n, L.c64, L.stream, work); }
+
+hipError_t launch_draw(const Launch& L, const double* work, const int* qubits, int nq, const double* d_u,
+                       uint64_t nshots, uint64_t* d_out) {
+  return draw(L.psi, 1ull << L.n, L.c64, L.stream, work, qubits, nq, d_u, nshots, d_out);
 }
 
 MarginalLayout marginal_layout(int n, int nq) {

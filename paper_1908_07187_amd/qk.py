@@ -56,6 +56,9 @@ class QkOp(C.Structure):
 
 SIGNATURES = {
     "qk_create": (_I32, [_I32, C.POINTER(QkAllocator), _P, C.POINTER(_P)]),
+    "qk_create_sparse": (_I32, [_I32, C.POINTER(QkAllocator), _P, _I64, C.POINTER(_P)]),
+    "qk_sparse_nnz": (_I32, [_P, _I64P]),
+    "qk_sparse_entries": (_I32, [_P, _U64P, _P, _I64, _I64P]),
     "qk_destroy": (_I32, [_P]),
     "qk_add_qubits": (_I32, [_P, _I32, _I32P]),
     "qk_add_cbits": (_I32, [_P, _I32, _I32P]),
@@ -175,23 +178,30 @@ class _TorchDevice:
 
 
 class Sim:
-    """One state vector on the GPU.  Thin wrapper over the qk_* calls."""
+    """One state on the GPU.  Thin wrapper over the qk_* calls.  With
+    ``sparse=N`` the state is kept as at most N nonzero (index, amplitude)
+    entries (qk_create_sparse) instead of a dense vector."""
 
-    def __init__(self, dtype: str = "c128", stream=None, allocator: str = "torch", device: int = 0):
+    def __init__(self, dtype: str = "c128", stream=None, allocator: str = "torch", device: int = 0,
+                 sparse: Optional[int] = None):
         self.lib = load()
         self.dtype = dtype
+        self.sparse = sparse
         self.np_dtype = np.complex64 if DTYPES[dtype] == QK_C64 else np.complex128
         h = C.c_void_p()
         if allocator == "torch":
             self._dev = _TorchDevice(stream, device)
-            st = self.lib.qk_create(DTYPES[dtype], C.byref(self._dev.allocator), C.c_void_p(self._dev.stream_handle),
-                                    C.byref(h))
+            alloc, stream_h = C.byref(self._dev.allocator), C.c_void_p(self._dev.stream_handle)
         elif allocator == "none":
             # hipMalloc inside the library, null stream (CPU-side argument checks work without a GPU)
             self._dev = None
-            st = self.lib.qk_create(DTYPES[dtype], None, None, C.byref(h))
+            alloc, stream_h = None, None
         else:
             raise ValueError(allocator)
+        if sparse is None:
+            st = self.lib.qk_create(DTYPES[dtype], alloc, stream_h, C.byref(h))
+        else:
+            st = self.lib.qk_create_sparse(DTYPES[dtype], alloc, stream_h, int(sparse), C.byref(h))
         if st != QK_OK:
             raise QKError(st, self.lib.qk_last_error(None).decode())
         self.h = h
@@ -319,6 +329,22 @@ class Sim:
         out = np.empty(1 << len(qubits), dtype=np.float64)
         self._chk(self.lib.qk_probabilities(self.h, qs, len(qubits), out.ctypes.data_as(_DP)))
         return out
+
+    def nnz(self) -> int:
+        """Entries of a sparse state."""
+        out = C.c_int64()
+        self._chk(self.lib.qk_sparse_nnz(self.h, C.byref(out)))
+        return out.value
+
+    def entries(self) -> Tuple[np.ndarray, np.ndarray]:
+        """(ascending indices uint64, amplitudes) of a sparse state."""
+        n = self.nnz()
+        idx = np.empty(max(1, n), dtype=np.uint64)
+        amp = np.empty(max(1, n), dtype=self.np_dtype)
+        got = C.c_int64()
+        self._chk(self.lib.qk_sparse_entries(self.h, idx.ctypes.data_as(_U64P), C.c_void_p(amp.ctypes.data), len(idx),
+                                             C.byref(got)))
+        return idx[: got.value], amp[: got.value]
 
     def read_cbits(self, n: Optional[int] = None) -> np.ndarray:
         n = self.ncbits if n is None else n

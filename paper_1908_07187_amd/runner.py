@@ -88,9 +88,10 @@ def _gate_id(sim: Sim, name: str, user_gates) -> int:
 
 
 def run_circuit(circuit, dtype: str = "c128", fusion: int = 0, sim: Optional[Sim] = None, stream=None,
-                tuning: Optional[dict] = None) -> Sim:
-    """Run ``circuit`` on a new (or the given) simulator; returns the Sim."""
-    s = sim if sim is not None else Sim(dtype, stream=stream)
+                tuning: Optional[dict] = None, sparse: Optional[int] = None) -> Sim:
+    """Run ``circuit`` on a new (or the given) simulator; returns the Sim.
+    ``sparse=N`` runs it on a sparse simulator of at most N entries."""
+    s = sim if sim is not None else Sim(dtype, stream=stream, sparse=sparse)
     for key, val in (tuning or {}).items():
         s.set_tuning(key, val)
     if fusion:

@@ -222,3 +222,28 @@ def test_sampling_entry_points_reject_before_device_work():
     assert lib.qk_sample(None, qs, 1, u.ctypes.data_as(qk._DP), 1, out.ctypes.data_as(qk._U64P)) == -1
     assert lib.qk_probabilities(None, qs, 1, dp.ctypes.data_as(qk._DP)) == -1
     lib.qk_destroy(h)
+
+
+def test_sparse_simulator_rejects_before_device_work():
+    lib = qk.load()
+    h = C.c_void_p()
+    assert lib.qk_create_sparse(qk.QK_C128, None, None, 0, C.byref(h)) == -1
+    assert lib.qk_create_sparse(qk.QK_C128, None, None, (1 << 32) + 1, C.byref(h)) == -1
+    assert lib.qk_create_sparse(qk.QK_C64, None, None, 1024, C.byref(h)) == 0
+    nnz = C.c_int64(-1)
+    assert lib.qk_sparse_nnz(h, C.byref(nnz)) == 0 and nnz.value == 0
+    assert lib.qk_sparse_entries(h, None, None, 0, C.byref(nnz)) == 0 and nnz.value == 0
+    # dense-only features are refused with QK_E_UNSUPPORTED
+    assert lib.qk_set_fusion(h, 5) == -7
+    assert lib.qk_set_fusion(h, 0) == 0
+    assert lib.qk_capture_begin(h) == -7
+    p, nb = C.c_void_p(), C.c_size_t()
+    assert lib.qk_state_ptr(h, C.byref(p), C.byref(nb)) == -7
+    qs = (C.c_int32 * 1)(0)
+    dp = np.zeros(2)
+    assert lib.qk_probabilities(h, qs, 1, dp.ctypes.data_as(qk._DP)) == -7
+    lib.qk_destroy(h)
+    # a dense simulator has no entries to report
+    lib2, h2 = _sim_nogpu()
+    assert lib2.qk_sparse_nnz(h2, C.byref(nnz)) == -7
+    lib2.qk_destroy(h2)

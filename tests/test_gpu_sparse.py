@@ -1,0 +1,242 @@
+"""Sparse simulator (qk_create_sparse) vs the FP64 oracle and closed forms,
+through the C ABI.
+
+The sparse engine applies the same gate definitions to a state kept as its
+nonzero amplitudes, so the dense oracle is its reference wherever a dense
+vector fits: complex128 max|d amp| <= 1e-12; complex64 <= 2e-5 with fidelity
+>= 1 - 1e-6; cbits and measurement outcomes bit-exact unless a draw lies
+within 1e-9 of P0.  Beyond dense sizes two properties pin it:
+  * relabelling -- a circuit on m qubits placed on m bit positions spread
+    over 62 qubits must give the oracle's m-qubit state at those positions
+    and nothing anywhere else;
+  * the paper's 39-qubit conventional Shor circuit (N = 8189): with the work
+    register measured before the QFT, the control register holds
+    x0 + j r (j < K) with equal amplitudes, whose QFT has the closed form
+    a_y = e^{2 pi i x0 y / M} sum_{j<K} e^{2 pi i j r y / M} / sqrt(M K).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL128 = 1e-12
+TOL64 = 2e-5
+
+
+def _run_sparse(circ, dtype, cap):
+    import paper_1908_07187_amd as qk
+    print(f"[gpu] sparse {circ.label} dtype={dtype} cap={cap}", flush=True)
+    s = qk.run_circuit(circ, dtype=dtype, sparse=cap)
+    return s
+
+
+def _fid(a, b):
+    a = a.astype(np.complex128)
+    b = b.astype(np.complex128)
+    return abs(np.vdot(a, b)) ** 2 / (np.vdot(a, a).real * np.vdot(b, b).real)
+
+
+def _check(ref, got, dtype):
+    d = np.max(np.abs(got.astype(np.complex128) - ref))
+    if dtype == "c128":
+        assert d <= TOL128, d
+    else:
+        assert d <= TOL64, d
+        assert _fid(ref, got) >= 1 - 1e-6
+
+
+def _boundary_ok(recs):
+    return all(abs(r.u - r.P0) > 1e-9 for r in recs)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,gates,seed", [(3, 40, 0), (6, 80, 1), (9, 120, 2), (12, 160, 3), (14, 120, 4)])
+def test_mixed_circuits_match_oracle(dtype, n, gates, seed):
+    c = W.random_mixed_circuit(n, gates, seed=seed, max_k=3)
+    ref, refcb, _ = oracle.run(c)
+    s = _run_sparse(c, dtype, cap=1 << n)
+    _check(ref, s.state(), dtype)
+    assert list(s.read_cbits()) == list(refcb)
+    idx, amp = s.entries()
+    assert np.all(np.diff(idx.astype(np.int64)) > 0), "entries not in ascending index order"
+    assert s.nnz() == len(idx) <= 1 << n
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("seed", [0, 1, 2, 3])
+def test_measurement_jobs_match_oracle(dtype, seed):
+    rng = np.random.default_rng(200 + seed)
+    c, _ = W.c4_job(rng, n_range=(8, 14), depth_range=(6, 14), p_measure=1.0)
+    ref, refcb, recs = oracle.run(c)
+    assert _boundary_ok(recs)
+    s = _run_sparse(c, dtype, cap=1 << c.n_qubits)
+    _check(ref, s.state(), dtype)
+    assert list(s.read_cbits()) == list(refcb)
+    log = s.measure_log()
+    assert [int(x) for x in log[:, 2]] == [r.outcome for r in recs]
+    s.close()
+
+
+@pytest.mark.parametrize("N,measure_work", [(15, False), (15, True), (21, True)])
+def test_shor_3nx1_small_matches_oracle(N, measure_work):
+    c = W.shor_3nx1(N, 2, measure_work=measure_work, seed=N, tables=False)
+    ref, _, recs = oracle.run(c)
+    assert _boundary_ok(recs)
+    s = _run_sparse(c, "c128", cap=1 << c.n_qubits)
+    _check(ref, s.state(), "c128")
+    s.close()
+
+
+def test_shor_nx2n_sparse_matches_oracle():
+    us = np.random.default_rng(9).random(64)
+    c = W.shor_nx2n(21, 2, us=us, tables=False)
+    ref, refcb, recs = oracle.run(c)
+    assert _boundary_ok(recs)
+    s = _run_sparse(c, "c128", cap=64)
+    _check(ref, s.state(), "c128")
+    assert list(s.read_cbits()) == list(refcb)
+    s.close()
+
+
+def _relabel(circ, positions, n_new):
+    """The same circuit with qubit q moved to bit positions[q] of an n_new-qubit register."""
+    ops = []
+    for op in circ.ops:
+        if op.kind == "add_qubits":
+            ops.append(W.add_qubits(n_new))
+        elif op.kind == "gate":
+            ops.append(W.gate(op.name, [positions[t] for t in op.targets], [positions[c] for c in op.controls],
+                              op.conds, op.params))
+        elif op.kind == "measure":
+            ops.append(W.measure(positions[op.qubit], op.cbit, op.u))
+        else:
+            ops.append(op)
+    return W.Circuit(ops, user_gates=circ.user_gates, label=circ.label + f"_on{n_new}")
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("m,seed", [(10, 5), (16, 6)])
+def test_relabelled_onto_62_qubits(dtype, m, seed):
+    c = W.random_mixed_circuit(m, 100, seed=seed, max_k=3)
+    ref, refcb, _ = oracle.run(c)
+    positions = sorted(np.random.default_rng(seed).choice(62, m, replace=False).tolist())
+    big = _relabel(c, positions, 62)
+    s = _run_sparse(big, dtype, cap=1 << m)
+    idx, amp = s.entries()
+    pos = np.array(positions, dtype=np.uint64)
+    outside = np.uint64(((1 << 62) - 1) ^ sum(1 << p for p in positions))
+    assert np.all((idx & outside) == 0), "weight outside the used positions"
+    compact = np.zeros(len(idx), dtype=np.int64)
+    for j, p in enumerate(pos):
+        compact |= (((idx >> p) & np.uint64(1)).astype(np.int64)) << j
+    got = np.zeros(1 << m, dtype=np.complex128)
+    got[compact] = amp
+    _check(ref, got, dtype)
+    assert list(s.read_cbits()) == list(refcb)
+    s.close()
+
+
+def test_capacity_exceeded_leaves_state_unchanged():
+    import paper_1908_07187_amd as qk
+    s = qk.Sim("c128", sparse=4)
+    s.add_qubits(5)
+    s.apply("H", [0])
+    s.apply("H", [3])
+    before = s.entries()
+    with pytest.raises(qk.QKError) as e:
+        s.apply("H", [4])
+    assert e.value.status == -4
+    after = s.entries()
+    assert np.array_equal(before[0], after[0]) and np.array_equal(before[1], after[1])
+    s.apply("RZ", [4], params=[0.3])          # diagonal gates never grow the state
+    assert s.nnz() == 4
+    s.close()
+
+
+def test_exact_zeros_are_dropped():
+    import paper_1908_07187_amd as qk
+    s = qk.Sim("c128", sparse=16)
+    s.add_qubits(3)
+    s.apply("H", [1])
+    assert s.nnz() == 2
+    s.apply("H", [1])                         # back to |000>: the |010> amplitude cancels exactly
+    idx, amp = s.entries()
+    assert idx.tolist() == [0] and abs(amp[0] - 1) < 1e-15
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_sparse_shots_match_oracle(dtype):
+    from oracle.oracle import Oracle
+    n = 14
+    c = W.random_mixed_circuit(n, 60, seed=11, max_k=2)
+    s = _run_sparse(c, dtype, cap=1 << n)
+    used = s.state()
+    o = Oracle()
+    o.add_qubits(n)
+    o.set_state(used.astype(np.complex128))
+    u = np.random.default_rng(12).random(5000)
+    for qs in ([], [13, 0, 6]):
+        got = s.sample(u, qs)
+        want, margin = o.sample(u, qs)
+        ok = margin > 1e-9
+        assert ok.mean() > 0.99
+        assert np.array_equal(got[ok], want[ok])
+    assert s.norm2() == pytest.approx(o.marginal(normalise=False).sum(), rel=1e-12)
+    s.close()
+
+
+# ------------------------------------------------------------------ 39 qubits: the paper's conventional Shor run
+
+def _closed_form_control(y, x0, r, K, M):
+    """a_y * sqrt(M K) for the control register after the QFT.  The phases are
+    reduced mod M in exact integers (r y and x0 y stay below 2^40 here), the
+    step angle to (-pi, pi], then
+    sum_{j<K} e^{i j th} = e^{i th (K-1)/2} sin(K th / 2) / sin(th / 2)."""
+    y = np.asarray(y, dtype=np.uint64)
+    Mu = np.uint64(M)
+    res = ((np.uint64(r) * y) % Mu).astype(np.int64)
+    res = np.where(res > M // 2, res - M, res)       # th in (-pi, pi]: sin(th / 2) keeps its relative precision
+    th = 2 * math.pi * res.astype(np.float64) / M
+    ph0 = 2 * math.pi * ((np.uint64(x0) * y) % Mu).astype(np.float64) / M
+    half = th / 2
+    sh = np.sin(half)
+    zero = th == 0
+    ratio = np.where(zero, float(K), np.sin(K * half) / np.where(zero, 1.0, sh))
+    return np.exp(1j * (ph0 + half * (K - 1))) * ratio
+
+
+def test_shor_3nx1_39_qubits_closed_form():
+    import paper_1908_07187_amd as qk
+    N, a = 8189, 2
+    c = W.shor_3nx1(N, a, measure_work=True, seed=39, tables=False)
+    nW, nC = N.bit_length(), (N * N - 1).bit_length()
+    assert nW + nC == 39
+    print(f"[gpu] sparse shor 3nx1 N={N} on {nW + nC} qubits", flush=True)
+    s = qk.run_circuit(c, dtype="c128", sparse=1 << nC)
+    log = s.measure_log()
+    bits = [int(x) for x in log[:, 2]]
+    # measurements ran on work bits nW-1 .. 0 in that order
+    w = sum(b << (nW - 1 - i) for i, b in enumerate(bits))
+    r = 1
+    while pow(a, r, N) != 1:
+        r += 1
+    x0 = next(x for x in range(r) if pow(a, x, N) == w)
+    M = 1 << nC
+    K = (M - x0 + r - 1) // r
+    idx, amp = s.entries()
+    assert np.all((idx & np.uint64((1 << nW) - 1)) == w), "work register not collapsed to the measured value"
+    y = idx >> np.uint64(nW)
+    want = _closed_form_control(y, x0, r, K, M) / math.sqrt(M * K)
+    err = np.max(np.abs(amp - want))
+    assert err <= TOL128, err
+    # nothing of weight is missing: the closed-form weight on the entries is the whole norm
+    assert abs(np.sum(np.abs(want) ** 2) - 1) < 1e-9
+    assert abs(np.sum(np.abs(amp) ** 2) - 1) < 1e-9
+    s.close()

@@ -427,12 +427,17 @@ def shor_nx2n(N: int, a: int = 2, us: Optional[Sequence[float]] = None, seed: in
     return Circuit(ops, user_gates=user, label=f"shor_nx2n_N{N}_a{a}")
 
 
-def shor_3nx1(N: int, a: int = 2, measure_work: bool = False, us=None, seed: int = 0) -> Circuit:
+def shor_3nx1(N: int, a: int = 2, measure_work: bool = False, us=None, seed: int = 0,
+              tables: bool = True) -> Circuit:
     """The paper's 3n x 1 Shor circuit: nCQ = bitlen(N^2-1) control qubits
     (paper qubits 0..nCQ-1 = bits nTQ-1..nWQ) in |+>, work register
     (bits 0..nWQ-1) in |1>, control qubit nCQ-1-c drives U^(2^c), then the
     QFT with reversal swaps on the control register.  Hadamards go on every
-    control qubit (the intended circuit).
+    control qubit (the intended circuit).  ``measure_work`` measures the work
+    register right after the modular exponentiation (it commutes with the QFT
+    on the control register, so the control outcomes keep their
+    distribution).  ``tables=False`` uses one modular-multiplication gate with
+    the power j as its parameter instead of 2^nWQ-entry tables.
     """
     nWQ = N.bit_length()
     nCQ = (N * N - 1).bit_length()
@@ -441,10 +446,15 @@ def shor_3nx1(N: int, a: int = 2, measure_work: bool = False, us=None, seed: int
     for p in range(nCQ):
         ops.append(gate("H", [nTQ - 1 - p]))
     user = {}
+    if not tables:
+        user["MODEXP"] = {"kind": "modmul", "k": nWQ, "a": a, "N": N}
     for c in range(nCQ):
-        key = f"MODEXP_j{c}"
-        user[key] = {"kind": "table", "k": nWQ, "table": modmul_table(N, a, c, nWQ)}
-        ops.append(gate(key, list(range(nWQ)), controls=[nWQ + c]))
+        if tables:
+            key = f"MODEXP_j{c}"
+            user[key] = {"kind": "table", "k": nWQ, "table": modmul_table(N, a, c, nWQ)}
+            ops.append(gate(key, list(range(nWQ)), controls=[nWQ + c]))
+        else:
+            ops.append(gate("MODEXP", list(range(nWQ)), controls=[nWQ + c], params=(float(c),)))
     if measure_work:
         if us is None:
             us = rng_for(seed).random(nWQ)
