@@ -48,9 +48,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gates", type=int, default=16, help="gates of the circuit the oracle sample runs")
     ap.add_argument("--workload", default="random30",
-                    choices=["random30", "batch12", "serve", "qft26", "ipe21", "shor", "sample30"],
+                    choices=["random30", "batch12", "serve", "qft26", "ipe21", "shor", "sample30", "shor39"],
                     help="random30 (default): the 30-qubit depth-40 circuit; the others are the batching, "
-                         "serving, QFT, phase-estimation, Shor and deferred-measurement forms")
+                         "serving, QFT, phase-estimation, Shor (dense and sparse) and deferred-measurement forms")
     ap.add_argument("--serve-jobs", type=int, default=400)
     ap.add_argument("--batch-circuits", type=int, default=2048)
     ap.add_argument("--kernels-only", action="store_true",

@@ -266,6 +266,49 @@ def shor(args, qk, torch):
     return out
 
 
+def shor39(args, qk, torch):
+    """The paper's 39-qubit conventional (3n x 1) Shor circuit for the 13-bit
+    N = 8189 on the sparse engine: 26 control qubits in |+>, 26 controlled
+    modular multiplications a^(2^c) on the 13-qubit work register, the work
+    register measured (it commutes with the QFT on the control register),
+    then the QFT with reversal swaps; complex128, at most 2^26 entries.
+    Each run then draws 64 shots of the control register and recovers the
+    order of a by continued fractions."""
+    import workloads as W
+    N, a = 8189, 2
+    nW, nC = N.bit_length(), (N * N - 1).bit_length()
+    circ = W.shor_3nx1(N, a, measure_work=True, seed=args.seed, tables=False)
+    prog = qk.Program(circ)
+    rng = np.random.default_rng(args.seed)
+    times, outs, peak = [], [], 0
+    for k in range(args.warmup + args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = qk.Sim("c128", sparse=1 << nC)
+        prog.run(s)
+        shots = s.sample(rng.random(64), list(range(nW, nW + nC)))
+        dt = time.perf_counter() - t0
+        nnz = s.nnz()
+        s.close()
+        if k >= args.warmup:
+            times.append(dt)
+            orders = [_order_from_phase(int(m), nC, N, a) for m in shots]
+            found = sorted({o for o in orders if o})
+            outs.append({"entries_at_end": nnz, "orders_found": found,
+                         "shots_giving_order": sum(1 for o in orders if o)})
+    t = sum(times) / len(times)
+    _say(f"shor39 N={N}: {nW + nC} qubits, {t:.3f} s per run, {outs}")
+    out = _base(args, 1.0 / t, "runs/s",
+                {"workload": "conventional Shor circuit for N = 8189 on 39 qubits (26 control, 13 work): H on the "
+                             "control register, 26 controlled modular multiplications, work register measured, "
+                             "QFT on the control register, 64 shots of the control register; complex128, sparse "
+                             "state of at most 2^26 entries", "N": N, "a": a, "qubits": nW + nC},
+                "f64", t * 1e3)
+    out["runs"] = outs
+    out["gates"] = len(circ.gate_ops())
+    return out
+
+
 def sample30(args, qk, torch):
     """Deferred measurement at 30 qubits: 2^20 shots of all 30 qubits from an
     entangled state (RY(theta_q) on every qubit, then a CNOT chain), for
@@ -323,4 +366,4 @@ def sample30(args, qk, torch):
 
 def run(name, args, qk, torch):
     return {"batch12": batch12, "serve": serve, "qft26": qft26, "ipe21": ipe21, "shor": shor,
-            "sample30": sample30}[name](args, qk, torch)
+            "sample30": sample30, "shor39": shor39}[name](args, qk, torch)

@@ -610,7 +610,7 @@ std::vector<SpArray> sp_arrays(qk_sim s) {
   const size_t c = s->sp.cap;
   return {{(void**)&s->sp.idx, c * 8}, {&s->sp.amp, c * s->amp}, {(void**)&s->sp.idx_b, c * 8},
           {&s->sp.amp_b, c * s->amp}, {(void**)&s->sp.key, c * 8}, {(void**)&s->sp.cnt, c * 4},
-          {(void**)&s->sp.off, c * 8}, {(void**)&s->sp.scal, 16}, {&s->sp.temp, s->sp.temp_bytes}};
+          {(void**)&s->sp.off, c * 8}, {(void**)&s->sp.scal, 32}, {&s->sp.temp, s->sp.temp_bytes}};
 }
 
 void sp_free(qk_sim s) {

@@ -149,7 +149,7 @@ struct SpBufs {
   uint64_t* key = nullptr;     // sort keys, gate outputs
   uint32_t* cnt = nullptr;     // per-entry counts or flags
   uint64_t* off = nullptr;     // their exclusive scan
-  uint64_t* scal = nullptr;    // device scalars: [0] total, [1] exact-zero outputs
+  uint64_t* scal = nullptr;    // device scalars: [0] total, [1] exact-zero outputs, [2] keys out of order
   void* temp = nullptr;        // sort and scan work space
   size_t temp_bytes = 0;
 };

@@ -15,11 +15,16 @@
 //                        slots come from an exclusive scan of the per-group
 //                        counts; a second radix sort by index restores the
 //                        ascending order and pushes the sentinels to the end.
+//                        Either sort is skipped when a pass over its keys
+//                        finds them already ascending (e.g. a gate on a qubit
+//                        that no entry has set yet).
 //   diagonal / phase     in place, no reordering.
 //   permutation / swap   every entry whose controls are all 1 gets its target
 //                        bits mapped forward (table, affine, modular
 //                        multiplication, bit swap); a radix sort by index
-//                        restores the order.
+//                        restores the order, unless the mapped indices are
+//                        already ascending (e.g. a map of low bits when every
+//                        run of equal high bits holds one entry).
 //   measurement          FP64 sums of |a|^2 split by the measured bit over
 //                        fixed ranges of entries (index order), outcome and
 //                        1/sqrt(p) on the device as in the dense path, then an
@@ -82,6 +87,8 @@ __device__ __forceinline__ double sp_wave_sum(double v) {
   return v;
 }
 
+}  // namespace
+
 // ---- dense k-qubit gate ----------------------------------------------------------
 
 __global__ __launch_bounds__(kSpBlock) void k_sp_keys(const uint64_t* __restrict__ idx, uint64_t nnz, Special tsorted,
@@ -90,6 +97,18 @@ __global__ __launch_bounds__(kSpBlock) void k_sp_keys(const uint64_t* __restrict
     const uint64_t x = idx[i];
     key[i] = (sp_remove(x, tsorted) << t.k) | sp_ext(x, t);
   }
+}
+
+// *unsorted = 1 when some key exceeds the next one (the sort is then needed;
+// else it is skipped).
+__global__ __launch_bounds__(kSpBlock) void k_sp_check_order(const uint64_t* __restrict__ key, uint64_t n,
+                                                             uint64_t* __restrict__ unsorted) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kSpBlock + threadIdx.x; i + 1 < n; i += (uint64_t)gridDim.x * kSpBlock)
+    if (key[i] > key[i + 1]) *unsorted = 1;
+}
+
+__global__ void k_sp_clear(uint64_t* __restrict__ p, int n) {
+  if (blockIdx.x == 0 && (int)threadIdx.x < n) p[threadIdx.x] = 0;
 }
 
 __global__ __launch_bounds__(kSpBlock) void k_sp_group_count(const uint64_t* __restrict__ skey, uint64_t nnz,
@@ -118,6 +137,7 @@ __global__ void k_sp_total(const uint32_t* __restrict__ cnt, const uint64_t* __r
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     scal[0] = nnz ? off[nnz - 1] + cnt[nnz - 1] : 0;
     scal[1] = 0;
+    scal[2] = 0;
   }
 }
 
@@ -346,6 +366,8 @@ __global__ __launch_bounds__(kSpBlock) void k_sp_init(uint64_t* idx, SpV<R>* amp
 
 // ---- orchestration -------------------------------------------------------------------------
 
+namespace {
+
 template <typename R>
 hipError_t sort_pairs(SpBufs& b, const uint64_t* kin, uint64_t* kout, const void* vin, void* vout, uint64_t n,
                       int bits, hipStream_t st) {
@@ -363,6 +385,22 @@ hipError_t scan_counts(SpBufs& b, uint64_t n, hipStream_t st) {
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_sp_total, dim3(1), dim3(64), 0, st, (const uint32_t*)b.cnt, (const uint64_t*)b.off, n, b.scal);
   return hipGetLastError();
+}
+
+// Below this many entries a sort costs about as much as the round trip that
+// would tell whether it can be skipped.
+constexpr uint64_t kCheckOrderMin = 1u << 15;
+
+hipError_t check_order(SpBufs& b, const uint64_t* key, uint64_t n, bool* unsorted, hipStream_t st) {
+  *unsorted = true;
+  if (n < kCheckOrderMin) return hipSuccess;
+  hipLaunchKernelGGL(k_sp_clear, dim3(1), dim3(64), 0, st, b.scal + 2, 1);
+  hipLaunchKernelGGL(k_sp_check_order, dim3(sp_grid(n)), dim3(kSpBlock), 0, st, key, n, b.scal + 2);
+  uint64_t flag = 1;
+  hipError_t e = hipMemcpyAsync(&flag, b.scal + 2, sizeof flag, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  *unsorted = flag != 0;
+  return e;
 }
 
 hipError_t read_scalars(SpBufs& b, uint64_t* host2, hipStream_t st) {
@@ -386,7 +424,14 @@ hipError_t dense_gate(SpBufs& b, int n, const SpTargets& t, uint64_t cmask, cons
   hipLaunchKernelGGL(k_sp_keys, dim3(sp_grid(nnz)), dim3(kSpBlock), 0, st, (const uint64_t*)b.idx, nnz, ts, t, b.key);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = sort_pairs<R>(b, b.key, b.idx_b, b.amp, b.amp_b, nnz, n, st)) != hipSuccess) return e;
+  bool unsorted;
+  if ((e = check_order(b, b.key, nnz, &unsorted, st)) != hipSuccess) return e;
+  if (unsorted) {
+    if ((e = sort_pairs<R>(b, b.key, b.idx_b, b.amp, b.amp_b, nnz, n, st)) != hipSuccess) return e;
+  } else {   // already in key order: the keys and amplitudes move over as they are
+    std::swap(b.key, b.idx_b);
+    std::swap(b.amp, b.amp_b);
+  }
   hipLaunchKernelGGL(k_sp_group_count, dim3(sp_grid(nnz)), dim3(kSpBlock), 0, st, (const uint64_t*)b.idx_b, nnz, ts,
                      t.k, cmask, b.cnt);
   if ((e = hipGetLastError()) != hipSuccess) return e;
@@ -400,11 +445,18 @@ hipError_t dense_gate(SpBufs& b, int n, const SpTargets& t, uint64_t cmask, cons
                      (const SpV<R>*)b.amp_b, nnz, ts, t, cmask, (const SpV<R>*)d_mat, (const uint64_t*)b.off, sentinel,
                      b.key, (SpV<R>*)b.amp, (unsigned long long*)(b.scal + 1));
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  // ascending index order; exact zeros (sentinel index 2^n) sort to the end
-  if ((e = sort_pairs<R>(b, b.key, b.idx, b.amp, b.amp_b, total, n + 1, st)) != hipSuccess) return e;
   if ((e = read_scalars(b, sc, st)) != hipSuccess) return e;
-  std::swap(b.amp, b.amp_b);
-  b.nnz = total - sc[1];
+  const uint64_t zeros = sc[1];
+  unsorted = true;
+  if (zeros == 0 && (e = check_order(b, b.key, total, &unsorted, st)) != hipSuccess) return e;
+  if (unsorted) {
+    // ascending index order; exact zeros (sentinel index 2^n) sort to the end
+    if ((e = sort_pairs<R>(b, b.key, b.idx, b.amp, b.amp_b, total, n + 1, st)) != hipSuccess) return e;
+    std::swap(b.amp, b.amp_b);
+  } else {
+    std::swap(b.idx, b.key);
+  }
+  b.nnz = total - zeros;
   return hipSuccess;
 }
 
@@ -416,8 +468,14 @@ hipError_t permute(SpBufs& b, int n, const SpTargets& t, uint64_t cmask, int mod
                      mode, ftab, A, B, N, b.key);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if ((e = sort_pairs<R>(b, b.key, b.idx, b.amp, b.amp_b, nnz, n, st)) != hipSuccess) return e;
-  std::swap(b.amp, b.amp_b);
+  bool unsorted;
+  if ((e = check_order(b, b.key, nnz, &unsorted, st)) != hipSuccess) return e;
+  if (unsorted) {
+    if ((e = sort_pairs<R>(b, b.key, b.idx, b.amp, b.amp_b, nnz, n, st)) != hipSuccess) return e;
+    std::swap(b.amp, b.amp_b);
+  } else {   // the mapped indices are already ascending
+    std::swap(b.idx, b.key);
+  }
   return hipSuccess;
 }
 

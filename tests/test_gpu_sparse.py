@@ -69,6 +69,24 @@ def test_mixed_circuits_match_oracle(dtype, n, gates, seed):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("n,seed", [(16, 7), (18, 8)])
+def test_large_states_match_oracle(dtype, n, seed):
+    """Enough entries (>= 2^15) that the engine checks whether keys are
+    already ascending and skips those sorts: H on every qubit first (each on
+    a fresh qubit), then a random mixed circuit."""
+    c0 = W.random_mixed_circuit(n, 60, seed=seed, max_k=2)
+    ops = c0.ops[:2] + [W.gate("H", [q]) for q in range(n)] + c0.ops[2:]
+    c = W.Circuit(ops, user_gates=c0.user_gates, label=f"hlayer_{c0.label}")
+    ref, refcb, _ = oracle.run(c)
+    s = _run_sparse(c, dtype, cap=1 << n)
+    _check(ref, s.state(), dtype)
+    assert list(s.read_cbits()) == list(refcb)
+    idx, _ = s.entries()
+    assert np.all(np.diff(idx.astype(np.int64)) > 0)
+    s.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("seed", [0, 1, 2, 3])
 def test_measurement_jobs_match_oracle(dtype, seed):
     rng = np.random.default_rng(200 + seed)
