@@ -52,6 +52,9 @@ def parse():
                     help="random30 (default): the 30-qubit depth-40 circuit; the others are the batching, "
                          "serving, QFT, phase-estimation, Shor (dense and sparse) and deferred-measurement forms")
     ap.add_argument("--serve-jobs", type=int, default=400)
+    ap.add_argument("--serve-rates", default="0.8", help="offered load as fractions of the closed-loop capacity")
+    ap.add_argument("--serve-capacity", type=float, default=0.0,
+                    help="closed-loop capacity in circuits/s (0: measure it first)")
     ap.add_argument("--batch-circuits", type=int, default=2048)
     ap.add_argument("--kernels-only", action="store_true",
                     help="run only a few strided-butterfly sweeps and a plain copy of known size (for PMC counters)")

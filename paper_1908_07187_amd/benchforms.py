@@ -97,22 +97,43 @@ def batch12(args, qk, torch):
 
 
 def serve(args, qk, torch):
+    """The serving mix: a closed-loop run (every job at t = 0) measures the
+    capacity (or --serve-capacity gives it), then Poisson streams at the listed
+    fractions of it (--serve-rates, default 0.8).  ``value`` is the throughput
+    at the first listed fraction; 1 % of its jobs are checked against the
+    complex128 per-gate path run alone."""
     import workloads as W
     from .serve import Server
     nj = args.serve_jobs
-    jobs = W.c4_job_stream(nj, seed=args.seed, rate=1.0)
-    sample = set(range(0, nj, 100))
-    # closed loop: every job at t = 0 -> capacity
+    fracs = [float(x) for x in str(args.serve_rates).split(",") if x]
+    prog = max(50, nj // 20)
     warm = W.c4_job_stream(20, seed=args.seed + 1, rate=1.0)
     Server(slots=8, autotuned=True).serve(warm, realtime=False)
-    _say(f"serve: closed loop over {nj} jobs")
-    rep0 = Server(slots=8, autotuned=True).serve(jobs, realtime=False)
-    cap = rep0.circuits_per_s
-    _say(f"serve closed-loop capacity {cap:.1f} circuits/s, wall {rep0.wall_s:.1f} s")
-    rate = 0.8 * cap
-    jobs_p = W.c4_job_stream(nj, seed=args.seed, rate=rate)
-    rep = Server(slots=8, keep_states=sample, autotuned=True).serve(jobs_p, realtime=True)
-    _say(f"serve at {rate:.1f}/s: {rep.circuits_per_s:.1f} circuits/s p50 {rep.p50_ms:.1f} ms p99 {rep.p99_ms:.1f} ms")
+    if args.serve_capacity > 0:
+        cap = args.serve_capacity
+        _say(f"serve: capacity {cap:.1f} circuits/s given")
+    else:
+        _say(f"serve: closed loop over {nj} jobs")
+        jobs = W.c4_job_stream(nj, seed=args.seed, rate=1.0)
+        rep0 = Server(slots=8, autotuned=True).serve(jobs, realtime=False, progress_every=prog)
+        cap = rep0.circuits_per_s
+        _say(f"serve closed-loop capacity {cap:.1f} circuits/s, wall {rep0.wall_s:.1f} s")
+    sample = set(range(0, nj, 100))
+    levels = {}
+    first = None
+    for fi, frac in enumerate(fracs):
+        rate = frac * cap
+        jobs_p = W.c4_job_stream(nj, seed=args.seed, rate=rate)
+        rep = Server(slots=8, keep_states=sample if fi == 0 else set(), autotuned=True).serve(
+            jobs_p, realtime=True, progress_every=prog)
+        _say(f"serve at {frac:.2f} x capacity = {rate:.1f}/s: {rep.circuits_per_s:.1f} circuits/s "
+             f"p50 {rep.p50_ms:.1f} ms p99 {rep.p99_ms:.1f} ms")
+        levels[f"{frac:.2f}"] = {"offered_per_s": rate, "circuits_per_s": rep.circuits_per_s, "p50_ms": rep.p50_ms,
+                                 "p99_ms": rep.p99_ms, "mean_ms": rep.mean_ms, "batches": rep.batches,
+                                 "max_concurrent_streams": rep.max_concurrent_streams}
+        if fi == 0:
+            first = (frac, rate, rep, jobs_p)
+    frac, rate, rep, jobs_p = first
     fids = []
     for i in sorted(sample):
         _, circ, dt = jobs_p[i]
@@ -128,10 +149,11 @@ def serve(args, qk, torch):
     out = _base(args, rep.circuits_per_s, "circuits/s",
                 {"workload": f"serving mix: {nj} jobs, qubits U{{8..26}}, depth U{{10..60}}, complex64/complex128 "
                              f"50/50, 30% with a mid-circuit measurement feeding a classical control; Poisson "
-                             f"arrivals at 0.8x the closed-loop capacity", "jobs": nj, "rate_per_s": rate},
+                             f"arrivals at {frac:.2f}x the closed-loop capacity", "jobs": nj, "rate_per_s": rate},
                 "f32/f64")
     out["latency_ms"] = {"p50": rep.p50_ms, "p99": rep.p99_ms, "mean": rep.mean_ms}
     out["closed_loop_capacity_cps"] = cap
+    out["levels"] = levels
     out["batches"] = rep.batches
     out["max_concurrent_streams"] = rep.max_concurrent_streams
     out["fidelity_vs_c128_sampled"] = {"jobs": len(fids), "min": float(min(fids)) if fids else None}

@@ -24,6 +24,7 @@ order that depends only on the job.
 """
 from __future__ import annotations
 
+import sys
 import time
 from collections import deque
 from dataclasses import dataclass, field
@@ -100,9 +101,12 @@ class Server:
         self.autotuned = bool(self.tuning_cache)
 
     # ------------------------------------------------------------------
-    def serve(self, jobs: Sequence[Tuple[float, object, str]], realtime: bool = True) -> ServeReport:
+    def serve(self, jobs: Sequence[Tuple[float, object, str]], realtime: bool = True,
+              progress_every: int = 0) -> ServeReport:
         """Run ``jobs`` = [(arrival_s, circuit, dtype)] (sorted by arrival).
-        realtime=False makes every job arrive at t = 0 (closed-loop saturation)."""
+        realtime=False makes every job arrive at t = 0 (closed-loop saturation).
+        progress_every > 0 prints a line to stderr each time that many more
+        jobs have finished."""
         torch = self.torch
         N = len(jobs)
         res = [JobResult(i, c.n_qubits, dt) for i, (_, c, dt) in enumerate(jobs)]
@@ -125,7 +129,11 @@ class Server:
         def now():
             return time.perf_counter() - t0
 
+        reported = 0
         while finished < N:
+            if progress_every and finished - reported >= progress_every:
+                reported = finished - finished % progress_every
+                print(f"[serve] {finished}/{N} jobs done at {now():.1f} s", file=sys.stderr, flush=True)
             t = now()
             while nxt < N and arrivals[nxt] <= t:
                 res[nxt].arrival = arrivals[nxt]
