@@ -41,11 +41,23 @@ class Program:
             else:
                 raise KeyError(op.kind)
 
-    def run(self, sim: Sim, set_init: bool = True) -> Sim:
+    def define_gates(self, sim: Sim) -> dict:
+        """Define every user gate of the circuit on ``sim`` (e.g. before a
+        graph capture, which allows no definitions); returns name -> gate id."""
+        return {name: _gate_id(sim, name, self.circuit.user_gates)
+                for name in dict.fromkeys(it[1] for it in self.items if it[0] == _KIND_GATE)}
+
+    def run(self, sim: Sim, set_init: bool = True, d_uniforms: Optional[int] = None,
+            ids: Optional[dict] = None) -> Sim:
+        """Issue the circuit's calls on ``sim``.  With ``d_uniforms`` (a device
+        address of one double per measurement, in circuit order) measurements
+        read their uniform from device memory when they execute
+        (qk_measure_dev), so a captured graph can be replayed with new draws."""
         lib, h = sim.lib, sim.h
-        ids = {}
+        ids = dict(ids or {})
         first_add = True
         circ = self.circuit
+        nmeas = 0
         for it in self.items:
             kind = it[0]
             if kind == _KIND_GATE:
@@ -57,7 +69,11 @@ class Program:
                 if st:
                     sim._chk(st)
             elif kind == _KIND_MEAS:
-                st = lib.qk_measure(h, it[1], it[2], it[3])
+                if d_uniforms is None:
+                    st = lib.qk_measure(h, it[1], it[2], it[3])
+                else:
+                    st = lib.qk_measure_dev(h, it[1], it[2], C.c_void_p(d_uniforms + 8 * nmeas))
+                nmeas += 1
                 if st:
                     sim._chk(st)
             elif kind == _KIND_ADDQ:

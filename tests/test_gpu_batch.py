@@ -166,3 +166,50 @@ def test_graph_with_device_uniform_changes_between_replays():
         assert np.max(np.abs(got - ref)) <= 1e-12
     g.close()
     s.close()
+
+
+def test_ipe_graph_replays_with_new_uniforms():
+    """The 21-qubit phase-estimation run captured once (reset + every op,
+    measurements reading device uniforms) and replayed with three different
+    sets of uniforms, eager work in between: each replay's cbits and state
+    equal the oracle's for those uniforms."""
+    import torch
+    import paper_1908_07187_amd as qk
+    c = W.c3_ipe(m=20, seed=4)
+    body = qk.Program(W.Circuit([o for o in c.ops if o.kind in ("gate", "measure")], user_gates=c.user_gates))
+    nmeas = sum(1 for o in c.ops if o.kind == "measure")
+    d_u = torch.zeros(nmeas, dtype=torch.float64, device="cuda")
+    s = qk.Sim("c128", stream=torch.cuda.Stream())
+    s.add_qubits(c.n_qubits)
+    s.add_cbits(c.n_cbits)
+    ids = body.define_gates(s)
+    s.capture_begin()
+    s.reset()
+    body.run(s, d_uniforms=d_u.data_ptr(), ids=ids)
+    g = s.capture_end()
+    side = qk.Sim("c128")
+    side.add_qubits(10)
+    for rep, seed in enumerate((11, 12, 13)):
+        us = np.random.default_rng(seed).random(nmeas)
+        ops, i = [], 0
+        for o in c.ops:
+            if o.kind == "measure":
+                ops.append(W.measure(o.qubit, o.cbit, float(us[i])))
+                i += 1
+            else:
+                ops.append(o)
+        ref_c = W.Circuit(ops, user_gates=c.user_gates)
+        ref, rcb, recs = oracle.run(ref_c)
+        if not all(abs(r.u - r.P0) > 1e-9 for r in recs):
+            continue
+        d_u.copy_(torch.tensor(us, dtype=torch.float64))
+        torch.cuda.synchronize()
+        print(f"[gpu-graph] ipe replay {rep}", flush=True)
+        g.launch()
+        assert list(s.read_cbits()) == list(rcb)
+        assert np.max(np.abs(s.state() - ref)) <= 1e-12
+        side.apply("H", [rep])            # eager work between replays
+        side.sync()
+    g.close()
+    s.close()
+    side.close()
