@@ -318,7 +318,10 @@ qk_status qk_sync(qk_sim sim);
  *   "mfma_cols"   tile columns per wave for matrix-core sweeps (16, 32
  *                 default, 64; capped by registers for large k);
  *   "mfma_areg"   blocks of 5-6 qubits: 1 keeps the matrix fragments in
- *                 registers, 0 (default) re-reads them from LDS per tile.
+ *                 registers, 0 (default) re-reads them from LDS per tile;
+ *   "xcd"         1 (default): the per-gate sweeps renumber their workgroups
+ *                 so that each of the 8 XCDs sweeps one contiguous range,
+ *                 0: workgroups in launch order.
  * QK_E_ARG for an unknown key or value. */
 qk_status qk_set_tuning(qk_sim sim, const char* key, int32_t value);
 qk_status qk_get_tuning(qk_sim sim, const char* key, int32_t* value);

@@ -1663,6 +1663,8 @@ qk_status qk_set_tuning(qk_sim s, const char* key, int32_t value) {
     s->tune.lane_items = value;
   } else if (k == "mfma_areg") {
     s->tune.mfma_areg = value != 0;
+  } else if (k == "xcd") {
+    s->tune.xcd = value != 0;
   } else if (k == "mfma_cols") {
     if (value != 16 && value != 32 && value != 64) return fail(s, QK_E_ARG, "mfma_cols must be 16, 32 or 64");
     s->tune.mfma_cols = value;
@@ -1686,6 +1688,7 @@ qk_status qk_get_tuning(qk_sim s, const char* key, int32_t* value) {
   else if (k == "mfma_waves") *value = s->tune.mfma_waves;
   else if (k == "mfma_cols") *value = s->tune.mfma_cols;
   else if (k == "mfma_areg") *value = s->tune.mfma_areg;
+  else if (k == "xcd") *value = s->tune.xcd;
   else return fail(s, QK_E_ARG, "unknown tuning key " + k);
   return QK_OK;
 }

@@ -60,6 +60,7 @@ struct Tuning {
   int mfma_waves = 8;    // waves per CU for the matrix-core kernel
   int mfma_cols = 32;    // tile columns per wave for the matrix-core kernel (16, 32, 64; capped per k)
   int mfma_areg = 0;     // blocks of 5-6 qubits: 1 keeps the A fragments in registers, 0 re-reads them from LDS
+  int xcd = 1;           // sweeps: 1 renumbers workgroups so each XCD sweeps a contiguous range
 };
 
 // Where device work goes and what it works on.
