@@ -75,6 +75,8 @@ struct qk_sim_s {
   DevBuf samp, shots;               // deferred-measurement work space; host-call staging of uniforms and shots
   bool sparse = false;              // state kept as sorted (index, amplitude) entries
   SpBufs sp;
+  SpDiagRun sp_run{};               // diagonal gates held back to be applied in one pass
+  std::vector<int> sp_phys;         // logical qubit -> index bit (a SWAP exchanges two entries, no data moves)
   int ncbits = 0;
   std::vector<Arena> arenas;        // constant chunks in use (the last one is being filled)
   std::vector<Arena> saved_arenas;  // chunks set aside while a capture owns `arenas`
@@ -94,6 +96,7 @@ constexpr int kUserBase = 0x100;
 constexpr size_t kArenaBytes = 32u << 20;
 constexpr int kMaxQubits = 40;
 constexpr int kMaxSparseQubits = 62;    // indices and the sort's sentinel bit fit 64 bits
+constexpr uint64_t kSpMergeMin = 1u << 12;   // entries from which one-qubit gates merge instead of sorting
 
 qk_status fail(qk_sim s, qk_status st, const std::string& msg) {
   if (s) s->err = msg;
@@ -475,7 +478,10 @@ qk_status execute(qk_sim s, const GateDesc& d) {
   return fail(s, QK_E_ARG, "unknown gate class");
 }
 
+qk_status sp_flush_run(qk_sim s);
+
 qk_status flush(qk_sim s) {
+  if (s->sparse) return sp_flush_run(s);
   if (s->pending.empty()) return QK_OK;
   std::vector<GateDesc> pend;
   pend.swap(s->pending);
@@ -642,7 +648,71 @@ qk_status sp_check(qk_sim s, hipError_t e, const char* what) {
   return hip_fail(s, e, what);
 }
 
-qk_status sparse_execute(qk_sim s, const GateDesc& d) {
+qk_status sp_flush_run(qk_sim s) {
+  if (s->sp_run.n == 0) return QK_OK;
+  hipError_t e = sp_diag_run(s->sp, s->c64, s->sp_run, s->stream);
+  s->sp_run.n = 0;
+  s->sweeps += 1;
+  return e == hipSuccess ? QK_OK : hip_fail(s, e, "sparse diagonal run");
+}
+
+int sp_bit(qk_sim s, int q) { return s->sp_phys.empty() ? q : s->sp_phys[q]; }
+
+bool sp_identity(qk_sim s) {
+  for (int q = 0; q < (int)s->sp_phys.size(); ++q)
+    if (s->sp_phys[q] != q) return false;
+  return true;
+}
+
+qk_status sp_flush_run(qk_sim s);
+
+// Put the entries back in logical index order (before a readout that returns indices).
+qk_status sp_normalize(qk_sim s) {
+  qk_status st = sp_flush_run(s);
+  if (st || sp_identity(s)) return st;
+  SpTargets phys{};
+  phys.k = s->n;
+  for (int q = 0; q < s->n; ++q) phys.pos[q] = s->sp_phys[q];
+  hipError_t e = sp_relabel(s->sp, s->n, s->c64, phys, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "sparse relabel");
+  for (int q = 0; q < s->n; ++q) s->sp_phys[q] = q;
+  s->sweeps += 1;
+  return QK_OK;
+}
+
+qk_status sparse_execute(qk_sim s, const GateDesc& dl) {
+  GateDesc d = dl;   // logical qubits -> index bits
+  for (int& q : d.targets) q = sp_bit(s, q);
+  for (int& q : d.controls) q = sp_bit(s, q);
+  if (d.kind == D_SWAP && d.controls.empty()) {   // relabel two qubits; no entry moves
+    if (!d.conds.empty()) {
+      std::vector<uint8_t> cb(s->ncbits);
+      hipError_t e = hipMemcpyAsync(cb.data(), s->cbits.p, cb.size(), hipMemcpyDeviceToHost, s->stream);
+      if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+      if (e != hipSuccess) return hip_fail(s, e, "condition readback");
+      for (const qk_cond& c : d.conds)
+        if (cb[c.cbit] != (uint8_t)c.value) return QK_OK;
+    }
+    std::swap(s->sp_phys[dl.targets[0]], s->sp_phys[dl.targets[1]]);
+    return QK_OK;
+  }
+  if ((d.kind == D_DIAG || d.kind == D_PHASE1) && d.conds.empty() && d.targets.size() <= 2) {
+    SpDiagTerm& tm = s->sp_run.t[s->sp_run.n++];
+    tm = SpDiagTerm{};
+    tm.k = (int)d.targets.size();
+    for (int j = 0; j < tm.k; ++j) tm.pos[j] = d.targets[j];
+    for (int c : d.controls) tm.cmask |= 1ull << c;
+    const int D = 1 << tm.k;
+    for (int i = 0; i < D; ++i) {
+      const cd v = d.kind == D_DIAG ? d.m[i] : (i == D - 1 ? d.z : cd(1.0));
+      tm.d[2 * i] = v.real();
+      tm.d[2 * i + 1] = v.imag();
+    }
+    if (s->sp_run.n == kSpDiagRun) return sp_flush_run(s);
+    return QK_OK;
+  }
+  qk_status fst = sp_flush_run(s);
+  if (fst) return fst;
   if (!d.conds.empty()) {   // the sparse engine synchronises anyway: decide on the host
     std::vector<uint8_t> cb(s->ncbits);
     hipError_t e = hipMemcpyAsync(cb.data(), s->cbits.p, cb.size(), hipMemcpyDeviceToHost, s->stream);
@@ -661,6 +731,15 @@ qk_status sparse_execute(qk_sim s, const GateDesc& d) {
   switch (d.kind) {
     case D_BUTTERFLY:
     case D_DENSE: {
+      // an uncontrolled one-qubit gate on many entries goes by split and merges instead of sorts
+      if (t.k == 1 && cmask == 0 && s->sp.nnz >= kSpMergeMin) {
+        Mat2 u{};
+        for (int i = 0; i < 4; ++i) {
+          u.v[2 * i] = d.m[i].real();
+          u.v[2 * i + 1] = d.m[i].imag();
+        }
+        return sp_check(s, sp_one_qubit(s->sp, s->n, s->c64, t.pos[0], u, s->stream), "sparse gate");
+      }
       const void* dmat = d.ug ? d.ug->dmat.p : nullptr;
       if (!dmat) {
         std::vector<unsigned char> packed = pack_matrix(d.m, s->c64);
@@ -698,8 +777,9 @@ qk_status sparse_execute(qk_sim s, const GateDesc& d) {
     case D_PERM: {
       const int mode = d.ug->kind == U_AFFINE ? SP_PERM_AFFINE
                                                 : (d.ug->kind == U_MODMUL ? SP_PERM_MODMUL : SP_PERM_TABLE);
+      const uint64_t B = mode == SP_PERM_MODMUL ? ~0ull / d.N : d.B;   // Barrett constant for the modulus
       return sp_check(s,
-                      sp_permute(s->sp, s->n, s->c64, t, cmask, mode, (const uint32_t*)d.ug->ftab.p, d.A, d.B, d.N,
+                      sp_permute(s->sp, s->n, s->c64, t, cmask, mode, (const uint32_t*)d.ug->ftab.p, d.A, B, d.N,
                                  s->stream),
                       "sparse permutation");
     }
@@ -803,6 +883,7 @@ qk_status qk_add_qubits(qk_sim s, int32_t count, int32_t* first) {
       hipError_t e = sp_init(s->sp, s->c64, s->stream);
       if (e != hipSuccess) return hip_fail(s, e, "add_qubits");
     }
+    for (int q = s->n; q < s->n + count; ++q) s->sp_phys.push_back(q);
     s->n += count;
     return QK_OK;
   }
@@ -1073,9 +1154,11 @@ qk_status qk_measure(qk_sim s, int32_t qubit, int32_t cbit, double u) {
   qk_status st = flush(s);
   if (st) return st;
   if ((st = ensure_meas(s))) return st;
-  if (s->sparse) {
+  if (s->sparse) {   // index-order sums: entries back in logical order first
+    if ((st = sp_normalize(s))) return st;
     s->sweeps += 1;
-    return sp_check(s, sp_measure(s->sp, s->c64, qubit, cbit, u, nullptr, -1, meas_buffers(s), s->stream), "measure");
+    return sp_check(s, sp_measure(s->sp, s->c64, sp_bit(s, qubit), cbit, u, nullptr, -1, meas_buffers(s), s->stream),
+                    "measure");
   }
   Launch L = make_launch(s, {});
   hipError_t e = launch_measure(L, qubit, cbit, u, nullptr, -1, meas_buffers(s));
@@ -1093,8 +1176,10 @@ qk_status qk_measure_dev(qk_sim s, int32_t qubit, int32_t cbit, const double* d_
   if (st) return st;
   if ((st = ensure_meas(s))) return st;
   if (s->sparse) {
+    if ((st = sp_normalize(s))) return st;
     s->sweeps += 1;
-    return sp_check(s, sp_measure(s->sp, s->c64, qubit, cbit, 0.0, d_u, -1, meas_buffers(s), s->stream), "measure");
+    return sp_check(s, sp_measure(s->sp, s->c64, sp_bit(s, qubit), cbit, 0.0, d_u, -1, meas_buffers(s), s->stream),
+                    "measure");
   }
   Launch L = make_launch(s, {});
   hipError_t e = launch_measure(L, qubit, cbit, 0.0, d_u, -1, meas_buffers(s));
@@ -1112,9 +1197,10 @@ qk_status qk_postselect(qk_sim s, int32_t qubit, int32_t cbit, int32_t outcome) 
   qk_status st = flush(s);
   if (st) return st;
   if ((st = ensure_meas(s))) return st;
+  if (s->sparse && (st = sp_normalize(s))) return st;
   Launch L = make_launch(s, {});
   MeasBuffers mb = meas_buffers(s);
-  hipError_t e = s->sparse ? sp_measure(s->sp, s->c64, qubit, cbit, 0.0, nullptr, outcome, mb, s->stream)
+  hipError_t e = s->sparse ? sp_measure(s->sp, s->c64, sp_bit(s, qubit), cbit, 0.0, nullptr, outcome, mb, s->stream)
                            : launch_measure(L, qubit, cbit, 0.0, nullptr, outcome, mb);
   if (e != hipSuccess) return hip_fail(s, e, "postselect");
   double res[4];
@@ -1195,6 +1281,7 @@ static qk_status sample_common(qk_sim s, const int32_t* qubits, int32_t nq, int6
     return flush(s);
   }
   if ((st = flush(s))) return st;
+  if (s->sparse && (st = sp_normalize(s))) return st;   // the CDF runs in logical index order
   return ensure(s, s->samp, need, "sampling work space");
 }
 
@@ -1211,9 +1298,13 @@ static hipError_t draw_shots(qk_sim s, const int32_t* qubits, int32_t nq, const 
   }
   hipError_t e = launch_cdf_dim(s->sp.amp, s->sp.nnz, s->c64, s->stream, work);
   if (e == hipSuccess) e = launch_draw_dim(s->sp.amp, s->sp.nnz, s->c64, s->stream, work, d_u, nshots, pos);
-  SpTargets ql{};
+  SpTargets ql{};   // logical qubits -> index bits (all qubits when none are listed and the map is not the identity)
   ql.k = nq;
-  for (int j = 0; j < nq; ++j) ql.pos[j] = qubits[j];
+  for (int j = 0; j < nq; ++j) ql.pos[j] = sp_bit(s, qubits[j]);
+  if (nq == 0 && !sp_identity(s)) {
+    ql.k = s->n;
+    for (int q = 0; q < s->n; ++q) ql.pos[q] = sp_bit(s, q);
+  }
   if (e == hipSuccess) e = sp_project(s->sp, pos, nshots, ql, d_out, s->stream);
   return e;
 }
@@ -1313,9 +1404,11 @@ qk_status qk_get_state(qk_sim s, void* host_out, size_t bytes) {
     if (s->n > kMaxQubits || !host_out || bytes != ((size_t)1 << s->n) * s->amp)
       return fail(s, QK_E_ARG, "buffer size must be 2^n * amplitude size (n <= 40)");
     if (!s->sp.idx) return fail(s, QK_E_STATE, "no qubits");
+    qk_status st = sp_normalize(s);
+    if (st) return st;
     std::vector<uint64_t> idx;
     std::vector<unsigned char> amp;
-    qk_status st = sp_read(s, idx, amp);
+    st = sp_read(s, idx, amp);
     if (st) return st;
     std::memset(host_out, 0, bytes);
     for (size_t i = 0; i < idx.size(); ++i)
@@ -1349,7 +1442,8 @@ qk_status qk_set_state(qk_sim s, const void* host_in, size_t bytes) {
       amp.insert(amp.end(), src + i * s->amp, src + (i + 1) * s->amp);
     }
     if (idx.size() > s->sp.cap) return fail(s, QK_E_OOM, "state has more nonzeros than the sparse capacity");
-    qk_status st = sync_stream(s);
+    qk_status st = flush(s);   // gates held back act on the state being replaced
+    if (!st) st = sync_stream(s);
     if (st) return st;
     hipError_t e = hipSuccess;
     if (!idx.empty()) {
@@ -1358,6 +1452,7 @@ qk_status qk_set_state(qk_sim s, const void* host_in, size_t bytes) {
     }
     if (e != hipSuccess) return hip_fail(s, e, "set_state");
     s->sp.nnz = idx.size();
+    for (int q = 0; q < s->n; ++q) s->sp_phys[q] = q;
     return QK_OK;
   }
   const size_t need = ((size_t)1 << s->n) * s->amp;
@@ -1393,6 +1488,8 @@ qk_status qk_sparse_entries(qk_sim s, uint64_t* idx, void* amps, int64_t cap, in
   if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
   if (nnz) *nnz = (int64_t)s->sp.nnz;
   if (cap < (int64_t)s->sp.nnz) return fail(s, QK_E_ARG, "cap is smaller than the number of entries");
+  qk_status st = sp_normalize(s);
+  if (st) return st;
   if (s->sp.nnz && (!idx || !amps)) return fail(s, QK_E_ARG, "idx and amps must be given");
   if (!s->sp.nnz) return QK_OK;   // no qubits added yet
   hipError_t e = hipMemcpyAsync(idx, s->sp.idx, s->sp.nnz * 8, hipMemcpyDeviceToHost, s->stream);
@@ -1406,7 +1503,9 @@ qk_status qk_inner_product(qk_sim a, qk_sim b, double* re, double* im) {
   if (a->sparse || b->sparse) {
     if (a != b) return fail(a, QK_E_UNSUPPORTED, "inner product with a sparse state");
     if (!a->sp.idx) return fail(a, QK_E_STATE, "no qubits");
-    qk_status st = ensure_meas(a);
+    qk_status st = flush(a);
+    if (st) return st;
+    if ((st = ensure_meas(a))) return st;
     if (st) return st;
     const int nb = reduce_blocks_for(a->sp.nnz);
     MeasBuffers mb = meas_buffers(a);
@@ -1473,6 +1572,7 @@ qk_status qk_reset(qk_sim s) {
   hipError_t e;
   if (s->sparse) {
     e = sp_init(s->sp, s->c64, s->stream);
+    for (int q = 0; q < s->n; ++q) s->sp_phys[q] = q;
   } else {
     const uint64_t dim = 1ull << s->n;
     e = launch_fill_zero(s->state.p, 0, dim, s->c64, s->stream);

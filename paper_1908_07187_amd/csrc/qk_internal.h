@@ -161,9 +161,29 @@ hipError_t sp_init(SpBufs& b, bool c64, hipStream_t st);
 // hipErrorOutOfMemory (state unchanged) if the result could exceed cap.
 hipError_t sp_dense_gate(SpBufs& b, int n, bool c64, const SpTargets& t, uint64_t cmask, const void* d_mat,
                          hipStream_t st);
+// Uncontrolled one-qubit gate u (row-major 2x2) on target t, by split and
+// merges instead of sorts (same result as sp_dense_gate).
+hipError_t sp_one_qubit(SpBufs& b, int n, bool c64, int t, const Mat2& u, hipStream_t st);
 hipError_t sp_diag(SpBufs& b, bool c64, const SpTargets& t, uint64_t cmask, const Diag64& d, hipStream_t st);
+// A run of diagonal gates of at most 2 targets, applied in order in one pass.
+struct SpDiagTerm {
+  int k;
+  int pos[2];
+  uint64_t cmask;
+  double d[8];
+};
+constexpr int kSpDiagRun = 24;
+struct SpDiagRun {
+  int n;
+  SpDiagTerm t[kSpDiagRun];
+};
+hipError_t sp_diag_run(SpBufs& b, bool c64, const SpDiagRun& run, hipStream_t st);
+// Modular multiplication (mode SP_PERM_MODMUL) takes B = floor((2^64 - 1) / N).
 hipError_t sp_permute(SpBufs& b, int n, bool c64, const SpTargets& t, uint64_t cmask, int mode, const uint32_t* ftab,
                       uint64_t A, uint64_t B, uint64_t N, hipStream_t st);
+// Renumber index bits: bit j of every new index is bit phys.pos[j] of the old
+// one (phys.k = n), then sort.
+hipError_t sp_relabel(SpBufs& b, int n, bool c64, const SpTargets& phys, hipStream_t st);
 hipError_t sp_measure(SpBufs& b, bool c64, int q, int cbit, double u, const double* d_u, int forced,
                       const MeasBuffers& mb, hipStream_t st);
 hipError_t sp_norm_partials(const SpBufs& b, bool c64, double* partials, int nblocks, hipStream_t st);

@@ -18,7 +18,8 @@
 //                        Either sort is skipped when a pass over its keys
 //                        finds them already ascending (e.g. a gate on a qubit
 //                        that no entry has set yet).
-//   diagonal / phase     in place, no reordering.
+//   diagonal / phase     in place, no reordering; a run of up to 24 diagonal
+//                        gates of at most 2 targets is one pass.
 //   permutation / swap   every entry whose controls are all 1 gets its target
 //                        bits mapped forward (table, affine, modular
 //                        multiplication, bit swap); a radix sort by index
@@ -34,6 +35,7 @@
 // output slot is written by one thread, and every floating-point sum runs in a
 // fixed order.  The host reads back only entry counts (to size the next step).
 #include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_merge.hpp>
 #include <rocprim/device/device_scan.hpp>
 
 #include <algorithm>
@@ -188,6 +190,98 @@ __global__ __launch_bounds__(kSpBlock) void k_sp_group_apply(const uint64_t* __r
   }
 }
 
+// ---- uncontrolled one-qubit gates by merging ------------------------------------
+// Entries with target bit 0 and those with bit 1 are each already in key
+// order, so a stable split and a merge replace the first sort; the outputs
+// with bit 0 and those with bit 1 are again each in index order, so a merge
+// replaces the second.
+
+__global__ __launch_bounds__(kSpBlock) void k_sp_bit_flags(const uint64_t* __restrict__ idx, uint64_t nnz, int t,
+                                                           uint32_t* __restrict__ cnt) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kSpBlock + threadIdx.x; i < nnz; i += (uint64_t)gridDim.x * kSpBlock)
+    cnt[i] = (uint32_t)((idx[i] >> t) & 1ull);
+}
+
+// Entries with the bit clear go to [0, nA) in order, those with it set to [nA, nnz).
+template <typename R>
+__global__ __launch_bounds__(kSpBlock) void k_sp_split(const uint64_t* __restrict__ key, const SpV<R>* __restrict__ amp,
+                                                       const uint32_t* __restrict__ cnt,
+                                                       const uint64_t* __restrict__ off, uint64_t nnz,
+                                                       uint64_t* __restrict__ out_key, SpV<R>* __restrict__ out_amp) {
+  const uint64_t nB = off[nnz - 1] + cnt[nnz - 1];
+  const uint64_t nA = nnz - nB;
+  for (uint64_t i = (uint64_t)blockIdx.x * kSpBlock + threadIdx.x; i < nnz; i += (uint64_t)gridDim.x * kSpBlock) {
+    const uint64_t dst = cnt[i] ? nA + off[i] : i - off[i];
+    out_key[dst] = key[i];
+    out_amp[dst] = amp[i];
+  }
+}
+
+__global__ __launch_bounds__(kSpBlock) void k_sp_head_flags(const uint64_t* __restrict__ skey, uint64_t nnz,
+                                                            uint32_t* __restrict__ cnt) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kSpBlock + threadIdx.x; i < nnz; i += (uint64_t)gridDim.x * kSpBlock)
+    cnt[i] = (i == 0 || (skey[i - 1] >> 1) != (skey[i] >> 1)) ? 1u : 0u;
+}
+
+// One thread per group (head at i, group number off[i]): w = U v, the bit-0
+// output to o0[g], the bit-1 output to o1[g].
+template <typename R>
+__global__ __launch_bounds__(kSpBlock) void k_sp_apply1(const uint64_t* __restrict__ skey,
+                                                        const SpV<R>* __restrict__ samp, uint64_t nnz, int t,
+                                                        Mat2 u, const uint64_t* __restrict__ off,
+                                                        uint64_t* __restrict__ o0_idx, SpV<R>* __restrict__ o0_amp,
+                                                        uint64_t* __restrict__ o1_idx, SpV<R>* __restrict__ o1_amp,
+                                                        unsigned long long* __restrict__ zeros) {
+  const R a0 = (R)u.v[0], b0 = (R)u.v[1], a1 = (R)u.v[2], b1 = (R)u.v[3];
+  const R a2 = (R)u.v[4], b2 = (R)u.v[5], a3 = (R)u.v[6], b3 = (R)u.v[7];
+  const uint64_t lo = (1ull << t) - 1;
+  for (uint64_t i = (uint64_t)blockIdx.x * kSpBlock + threadIdx.x; i < nnz; i += (uint64_t)gridDim.x * kSpBlock) {
+    const uint64_t pre = skey[i] >> 1;
+    if (i > 0 && (skey[i - 1] >> 1) == pre) continue;
+    SpV<R> p, q;
+    p.x = p.y = q.x = q.y = 0;
+    if (skey[i] & 1) q = samp[i];
+    else p = samp[i];
+    if (i + 1 < nnz && (skey[i + 1] >> 1) == pre) q = samp[i + 1];   // the bit-1 member follows the bit-0 one
+    SpV<R> r0, r1;
+    r0.x = a0 * p.x - b0 * p.y + a1 * q.x - b1 * q.y;
+    r0.y = a0 * p.y + b0 * p.x + a1 * q.y + b1 * q.x;
+    r1.x = a2 * p.x - b2 * p.y + a3 * q.x - b3 * q.y;
+    r1.y = a2 * p.y + b2 * p.x + a3 * q.y + b3 * q.x;
+    const uint64_t base = ((pre >> t) << (t + 1)) | (pre & lo);
+    const uint64_t g = off[i];
+    o0_idx[g] = base;
+    o0_amp[g] = r0;
+    o1_idx[g] = base | (1ull << t);
+    o1_amp[g] = r1;
+    const unsigned long long z = (r0.x == (R)0 && r0.y == (R)0 ? 1ull : 0ull) + (r1.x == (R)0 && r1.y == (R)0 ? 1ull : 0ull);
+    if (z) atomicAdd(zeros, z);
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kSpBlock) void k_sp_nonzero_flags(const SpV<R>* __restrict__ amp, uint64_t n,
+                                                               uint32_t* __restrict__ cnt) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kSpBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kSpBlock) {
+    const SpV<R> a = amp[i];
+    cnt[i] = (a.x != (R)0 || a.y != (R)0) ? 1u : 0u;
+  }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kSpBlock) void k_sp_gather_kept(const uint64_t* __restrict__ idx,
+                                                             const SpV<R>* __restrict__ amp, uint64_t n,
+                                                             const uint32_t* __restrict__ cnt,
+                                                             const uint64_t* __restrict__ off,
+                                                             uint64_t* __restrict__ out_idx,
+                                                             SpV<R>* __restrict__ out_amp) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kSpBlock + threadIdx.x; i < n; i += (uint64_t)gridDim.x * kSpBlock) {
+    if (!cnt[i]) continue;
+    out_idx[off[i]] = idx[i];
+    out_amp[off[i]] = amp[i];
+  }
+}
+
 // ---- diagonal and phase gates --------------------------------------------------------
 
 template <typename R>
@@ -206,6 +300,30 @@ __global__ __launch_bounds__(kSpBlock) void k_sp_diag(const uint64_t* __restrict
   }
 }
 
+// A run of diagonal gates in one pass: for each entry, in gate order, every
+// term whose control bits are all 1 multiplies the amplitude by its table
+// entry at the entry's target bits.
+template <typename R>
+__global__ __launch_bounds__(kSpBlock) void k_sp_diag_run(const uint64_t* __restrict__ idx, SpV<R>* __restrict__ amp,
+                                                          uint64_t nnz, SpDiagRun run) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kSpBlock + threadIdx.x; i < nnz; i += (uint64_t)gridDim.x * kSpBlock) {
+    const uint64_t x = idx[i];
+    SpV<R> a = amp[i];
+    for (int j = 0; j < run.n; ++j) {
+      const SpDiagTerm& tm = run.t[j];
+      if ((x & tm.cmask) != tm.cmask) continue;
+      int m = 0;
+      for (int b = 0; b < tm.k; ++b) m |= (int)((x >> tm.pos[b]) & 1ull) << b;
+      const R dr = (R)tm.d[2 * m], di = (R)tm.d[2 * m + 1];
+      SpV<R> r;
+      r.x = a.x * dr - a.y * di;
+      r.y = a.x * di + a.y * dr;
+      a = r;
+    }
+    amp[i] = a;
+  }
+}
+
 // ---- permutations ---------------------------------------------------------------------
 
 __global__ __launch_bounds__(kSpBlock) void k_sp_perm_keys(const uint64_t* __restrict__ idx, uint64_t nnz,
@@ -214,20 +332,42 @@ __global__ __launch_bounds__(kSpBlock) void k_sp_perm_keys(const uint64_t* __res
                                                            uint64_t N, uint64_t* __restrict__ key) {
   const uint64_t tmask = sp_dep((1ull << t.k) - 1, t);
   const uint64_t kmask = (t.k >= 64) ? ~0ull : ((1ull << t.k) - 1);
+  // targets on consecutive bits in gate order (a register): plain shifts instead of bit loops
+  bool contig = true;
+  for (int j = 1; j < t.k; ++j) contig = contig && t.pos[j] == t.pos[0] + j;
+  const int t0 = t.pos[0];
   for (uint64_t i = (uint64_t)blockIdx.x * kSpBlock + threadIdx.x; i < nnz; i += (uint64_t)gridDim.x * kSpBlock) {
     const uint64_t x = idx[i];
     if ((x & cmask) != cmask) {
       key[i] = x;
       continue;
     }
-    const uint64_t m = sp_ext(x, t);
+    const uint64_t m = contig ? ((x >> t0) & kmask) : sp_ext(x, t);
     uint64_t y;
     if (mode == SP_PERM_TABLE) y = ftab[m];
     else if (mode == SP_PERM_AFFINE) y = (A * m + B) & kmask;
-    else if (mode == SP_PERM_MODMUL) y = (m < N) ? (A * m) % N : m;
+    else if (mode == SP_PERM_MODMUL) {
+      // (A m) mod N with A, m < N < 2^32: Barrett reduction with mu = floor((2^64 - 1) / N)
+      // (the estimate q is at most 2 below the true quotient)
+      if (m < N) {
+        const uint64_t P = A * m;
+        uint64_t r = P - __umul64hi(P, B) * N;
+        while (r >= N) r -= N;
+        y = r;
+      } else {
+        y = m;
+      }
+    }
     else y = ((m & 1ull) << 1) | ((m >> 1) & 1ull);       // swap of the two targets
-    key[i] = (x & ~tmask) | sp_dep(y, t);
+    key[i] = (x & ~tmask) | (contig ? (y << t0) : sp_dep(y, t));
   }
+}
+
+// Physical index -> logical index: bit j of the result is bit phys.pos[j].
+__global__ __launch_bounds__(kSpBlock) void k_sp_relabel(const uint64_t* __restrict__ idx, uint64_t nnz, SpTargets phys,
+                                                         uint64_t* __restrict__ key) {
+  for (uint64_t i = (uint64_t)blockIdx.x * kSpBlock + threadIdx.x; i < nnz; i += (uint64_t)gridDim.x * kSpBlock)
+    key[i] = sp_ext(idx[i], phys);
 }
 
 // ---- measurement ------------------------------------------------------------------------
@@ -461,6 +601,73 @@ hipError_t dense_gate(SpBufs& b, int n, const SpTargets& t, uint64_t cmask, cons
 }
 
 template <typename R>
+hipError_t merge_pairs(SpBufs& b, const uint64_t* k1, const uint64_t* k2, uint64_t* kout, const void* v1,
+                       const void* v2, void* vout, uint64_t n1, uint64_t n2, hipStream_t st) {
+  if (n1 + n2 == 0) return hipSuccess;
+  size_t bytes = b.temp_bytes;
+  return rocprim::merge(b.temp, bytes, k1, k2, kout, (const SpV<R>*)v1, (const SpV<R>*)v2, (SpV<R>*)vout,
+                        (size_t)n1, (size_t)n2, rocprim::less<uint64_t>(), st);
+}
+
+// Uncontrolled one-qubit gate on target t by split, merge, apply, merge.
+template <typename R>
+hipError_t one_qubit(SpBufs& b, int n, int t, const Mat2& u, hipStream_t st) {
+  const uint64_t nnz = b.nnz;
+  SpTargets tt{};
+  tt.k = 1;
+  tt.pos[0] = t;
+  const Special ts = sorted_special(tt);
+  hipLaunchKernelGGL(k_sp_keys, dim3(sp_grid(nnz)), dim3(kSpBlock), 0, st, (const uint64_t*)b.idx, nnz, ts, tt, b.key);
+  hipLaunchKernelGGL(k_sp_bit_flags, dim3(sp_grid(nnz)), dim3(kSpBlock), 0, st, (const uint64_t*)b.idx, nnz, t, b.cnt);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = scan_counts(b, nnz, st)) != hipSuccess) return e;
+  hipLaunchKernelGGL((k_sp_split<R>), dim3(sp_grid(nnz)), dim3(kSpBlock), 0, st, (const uint64_t*)b.key,
+                     (const SpV<R>*)b.amp, (const uint32_t*)b.cnt, (const uint64_t*)b.off, nnz, b.idx_b,
+                     (SpV<R>*)b.amp_b);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  uint64_t sc[2];
+  if ((e = read_scalars(b, sc, st)) != hipSuccess) return e;
+  const uint64_t nB = sc[0], nA = nnz - nB;
+  // entries in key order: keys into b.key, amplitudes into b.amp
+  if ((e = merge_pairs<R>(b, b.idx_b, b.idx_b + nA, b.key, b.amp_b, (const SpV<R>*)b.amp_b + nA, b.amp, nA, nB,
+                          st)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_sp_head_flags, dim3(sp_grid(nnz)), dim3(kSpBlock), 0, st, (const uint64_t*)b.key, nnz, b.cnt);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if ((e = scan_counts(b, nnz, st)) != hipSuccess) return e;
+  if ((e = read_scalars(b, sc, st)) != hipSuccess) return e;
+  const uint64_t G = sc[0];
+  if (2 * G > b.cap) return hipErrorOutOfMemory;
+  hipLaunchKernelGGL((k_sp_apply1<R>), dim3(sp_grid(nnz)), dim3(kSpBlock), 0, st, (const uint64_t*)b.key,
+                     (const SpV<R>*)b.amp, nnz, t, u, (const uint64_t*)b.off, b.idx_b, (SpV<R>*)b.amp_b, b.idx_b + G,
+                     (SpV<R>*)b.amp_b + G, (unsigned long long*)(b.scal + 1));
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  // ascending index order again
+  if ((e = merge_pairs<R>(b, b.idx_b, b.idx_b + G, b.idx, b.amp_b, (const SpV<R>*)b.amp_b + G, b.amp, G, G, st)) !=
+      hipSuccess)
+    return e;
+  if ((e = read_scalars(b, sc, st)) != hipSuccess) return e;
+  const uint64_t zeros = sc[1];
+  b.nnz = 2 * G;
+  if (zeros) {   // drop the exact zeros, keeping the order
+    hipLaunchKernelGGL((k_sp_nonzero_flags<R>), dim3(sp_grid(b.nnz)), dim3(kSpBlock), 0, st, (const SpV<R>*)b.amp,
+                       b.nnz, b.cnt);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = scan_counts(b, b.nnz, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL((k_sp_gather_kept<R>), dim3(sp_grid(b.nnz)), dim3(kSpBlock), 0, st, (const uint64_t*)b.idx,
+                       (const SpV<R>*)b.amp, b.nnz, (const uint32_t*)b.cnt, (const uint64_t*)b.off, b.idx_b,
+                       (SpV<R>*)b.amp_b);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    std::swap(b.idx, b.idx_b);
+    std::swap(b.amp, b.amp_b);
+    b.nnz -= zeros;
+  }
+  (void)n;
+  return hipSuccess;
+}
+
+template <typename R>
 hipError_t permute(SpBufs& b, int n, const SpTargets& t, uint64_t cmask, int mode, const uint32_t* ftab, uint64_t A,
                    uint64_t B, uint64_t N, hipStream_t st) {
   const uint64_t nnz = b.nnz;
@@ -476,6 +683,17 @@ hipError_t permute(SpBufs& b, int n, const SpTargets& t, uint64_t cmask, int mod
   } else {   // the mapped indices are already ascending
     std::swap(b.idx, b.key);
   }
+  return hipSuccess;
+}
+
+template <typename R>
+hipError_t relabel(SpBufs& b, int n, const SpTargets& phys, hipStream_t st) {
+  const uint64_t nnz = b.nnz;
+  hipLaunchKernelGGL(k_sp_relabel, dim3(sp_grid(nnz)), dim3(kSpBlock), 0, st, (const uint64_t*)b.idx, nnz, phys, b.key);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if ((e = sort_pairs<R>(b, b.key, b.idx, b.amp, b.amp_b, nnz, n, st)) != hipSuccess) return e;
+  std::swap(b.amp, b.amp_b);
   return hipSuccess;
 }
 
@@ -517,7 +735,14 @@ size_t sp_temp_bytes(uint64_t cap, bool c64) {
     (void)rocprim::radix_sort_pairs(nullptr, a, kp, kp, (const double2*)nullptr, (double2*)nullptr, cap, 0u, 64u);
   (void)rocprim::exclusive_scan(nullptr, s, (const uint32_t*)nullptr, (uint64_t*)nullptr, (uint64_t)0, (size_t)cap,
                                 rocprim::plus<uint64_t>());
-  return std::max(a, s);
+  size_t m = 0;
+  if (c64)
+    (void)rocprim::merge(nullptr, m, kp, kp, kp, (const float2*)nullptr, (const float2*)nullptr, (float2*)nullptr,
+                         (size_t)cap, (size_t)cap, rocprim::less<uint64_t>());
+  else
+    (void)rocprim::merge(nullptr, m, kp, kp, kp, (const double2*)nullptr, (const double2*)nullptr, (double2*)nullptr,
+                         (size_t)cap, (size_t)cap, rocprim::less<uint64_t>());
+  return std::max(std::max(a, s), m);
 }
 
 hipError_t sp_init(SpBufs& b, bool c64, hipStream_t st) {
@@ -525,6 +750,10 @@ hipError_t sp_init(SpBufs& b, bool c64, hipStream_t st) {
   else hipLaunchKernelGGL(k_sp_init<double>, dim3(1), dim3(64), 0, st, b.idx, (double2*)b.amp);
   b.nnz = 1;
   return hipGetLastError();
+}
+
+hipError_t sp_one_qubit(SpBufs& b, int n, bool c64, int t, const Mat2& u, hipStream_t st) {
+  return c64 ? one_qubit<float>(b, n, t, u, st) : one_qubit<double>(b, n, t, u, st);
 }
 
 hipError_t sp_dense_gate(SpBufs& b, int n, bool c64, const SpTargets& t, uint64_t cmask, const void* d_mat,
@@ -543,10 +772,25 @@ hipError_t sp_diag(SpBufs& b, bool c64, const SpTargets& t, uint64_t cmask, cons
   return hipGetLastError();
 }
 
+hipError_t sp_diag_run(SpBufs& b, bool c64, const SpDiagRun& run, hipStream_t st) {
+  if (b.nnz == 0 || run.n == 0) return hipSuccess;
+  if (c64)
+    hipLaunchKernelGGL(k_sp_diag_run<float>, dim3(sp_grid(b.nnz)), dim3(kSpBlock), 0, st, (const uint64_t*)b.idx,
+                       (float2*)b.amp, b.nnz, run);
+  else
+    hipLaunchKernelGGL(k_sp_diag_run<double>, dim3(sp_grid(b.nnz)), dim3(kSpBlock), 0, st, (const uint64_t*)b.idx,
+                       (double2*)b.amp, b.nnz, run);
+  return hipGetLastError();
+}
+
 hipError_t sp_permute(SpBufs& b, int n, bool c64, const SpTargets& t, uint64_t cmask, int mode, const uint32_t* ftab,
                       uint64_t A, uint64_t B, uint64_t N, hipStream_t st) {
   return c64 ? permute<float>(b, n, t, cmask, mode, ftab, A, B, N, st)
              : permute<double>(b, n, t, cmask, mode, ftab, A, B, N, st);
+}
+
+hipError_t sp_relabel(SpBufs& b, int n, bool c64, const SpTargets& phys, hipStream_t st) {
+  return c64 ? relabel<float>(b, n, phys, st) : relabel<double>(b, n, phys, st);
 }
 
 hipError_t sp_measure(SpBufs& b, bool c64, int q, int cbit, double u, const double* d_u, int forced,

@@ -160,6 +160,48 @@ def test_relabelled_onto_62_qubits(dtype, m, seed):
     s.close()
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_swaps_relabel_without_moving_entries(dtype):
+    """Uncontrolled SWAPs only relabel qubits in the sparse engine: gates,
+    measurements, conditioned swaps, shots and readouts after many swaps
+    must still match the oracle."""
+    from oracle.oracle import Oracle
+    rng = np.random.default_rng(21)
+    n = 12
+    base = W.c0_random_layers(n=n, layers=3, seed=21)
+    ops = list(base.ops) + [W.add_cbits(1)]
+    for i in range(40):
+        a, b = [int(x) for x in rng.choice(n, 2, replace=False)]
+        ops.append(W.gate("SWAP", [a, b]))
+        if i % 7 == 3:
+            ops.append(W.gate("H", [int(rng.integers(n))]))
+            ops.append(W.gate("X", [int(rng.integers(n))], controls=[a]))
+    ops.append(W.measure(5, cbit=0, u=0.37))
+    ops.append(W.gate("SWAP", [1, 9], conds=[(0, 1)]))
+    ops.append(W.gate("SWAP", [2, 3], conds=[(0, 0)]))
+    ops.append(W.gate("RY", [4], params=(0.7,)))
+    c = W.Circuit(ops, label="swaps")
+    ref, refcb, recs = oracle.run(c)
+    assert _boundary_ok(recs)
+    s = _run_sparse(c, dtype, cap=1 << n)
+    u = rng.random(3000)
+    shots = s.sample(u, [11, 0, 7])
+    shots_all = s.sample(u)
+    _check(ref, s.state(), dtype)
+    assert list(s.read_cbits()) == list(refcb)
+    o = Oracle()
+    o.add_qubits(n)
+    o.set_state(s.state().astype(np.complex128))
+    for got, qs in ((shots, [11, 0, 7]), (shots_all, [])):
+        want, margin = o.sample(u, qs)
+        ok = margin > 1e-9
+        assert ok.mean() > 0.99
+        assert np.array_equal(got[ok], want[ok])
+    idx, _ = s.entries()
+    assert np.all(np.diff(idx.astype(np.int64)) > 0)
+    s.close()
+
+
 def test_capacity_exceeded_leaves_state_unchanged():
     import paper_1908_07187_amd as qk
     s = qk.Sim("c128", sparse=4)
