@@ -398,7 +398,9 @@ qk_status qk_batch_destroy(qk_batch batch);
 /* Validate and compile one circuit (ops copied); *job receives its index. */
 qk_status qk_batch_add(qk_batch batch, int32_t n_qubits, int32_t n_cbits, const qk_op* ops, int32_t n_ops,
                        int32_t* job);
-/* Run every circuit added so far (asynchronous, one launch). */
+/* Run every circuit added so far (asynchronous, one launch).  Running again
+ * without adding or clearing reuses the circuits already uploaded to the
+ * device (the launch only resets the job queue). */
 qk_status qk_batch_run(qk_batch batch);
 qk_status qk_batch_sync(qk_batch batch);
 /* Results of the last run (synchronise). */

@@ -77,7 +77,9 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BJob* __restrict_
   for (;;) {
     if (tid == 0) job_sh = atomicAdd(counter, 1);
     __syncthreads();
-    const int j = job_sh;
+    // the job (and so every op record) is the same for the whole workgroup:
+    // say so, so that op records come through scalar loads
+    const int j = __builtin_amdgcn_readfirstlane(job_sh);
     if (j >= njobs) break;
     const BJob jb = jobs[j];
     const uint32_t dim = 1u << jb.n;
@@ -243,6 +245,10 @@ struct qk_batch_s {
   size_t jobs_bytes = 0;
   int* d_counter = nullptr;
   bool ran = false;
+  bool uploaded = false;   // the device job table and ops match `jobs` (a rerun only relaunches)
+  size_t njobs_dev = 0;
+  size_t shm = 0;
+  unsigned grid = 0;
   std::string err;
 };
 
@@ -409,12 +415,43 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
   b->jobs.push_back(std::move(hj));
   if (job) *job = (int32_t)b->jobs.size() - 1;
   b->ran = false;
+  b->uploaded = false;
   return QK_OK;
+}
+
+static void launch_batch(qk_batch b) {
+  if (b->c64) {
+    static bool set = false;
+    if (!set) {
+      (void)hipFuncSetAttribute((const void*)k_batch<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+      set = true;
+    }
+    hipLaunchKernelGGL(k_batch<float>, dim3(b->grid), dim3(kBatchThreads), b->shm, b->stream, (const BJob*)b->d_jobs,
+                       (int)b->njobs_dev, (const BOp*)b->d_ops, (EVb<float>::T*)b->d_states, (uint8_t*)b->d_cbits,
+                       b->d_counter);
+  } else {
+    static bool set = false;
+    if (!set) {
+      (void)hipFuncSetAttribute((const void*)k_batch<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+      set = true;
+    }
+    hipLaunchKernelGGL(k_batch<double>, dim3(b->grid), dim3(kBatchThreads), b->shm, b->stream, (const BJob*)b->d_jobs,
+                       (int)b->njobs_dev, (const BOp*)b->d_ops, (EVb<double>::T*)b->d_states, (uint8_t*)b->d_cbits,
+                       b->d_counter);
+  }
 }
 
 qk_status qk_batch_run(qk_batch b) {
   if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
   if (b->jobs.empty()) return QK_OK;
+  if (b->uploaded) {   // same jobs as the last run: only the queue counter and the launch
+    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, b->stream, b->d_counter);
+    launch_batch(b);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
+    b->ran = true;
+    return QK_OK;
+  }
   const size_t amp = b->c64 ? 8 : 16;
   // layout: states and cbits in job order; the queue visits the largest jobs first
   uint64_t soff = 0;
@@ -472,28 +509,14 @@ qk_status qk_batch_run(qk_batch b) {
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const int per_cu = std::max<int>(1, (int)(160 * 1024 / (shm + 4096)));
   const unsigned grid = (unsigned)std::max<size_t>(1, std::min<size_t>(table.size(), (size_t)ncu * std::min(per_cu, 4)));
-  if (b->c64) {
-    static bool set = false;
-    if (!set) {
-      (void)hipFuncSetAttribute((const void*)k_batch<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-      set = true;
-    }
-    hipLaunchKernelGGL(k_batch<float>, dim3(grid), dim3(kBatchThreads), shm, b->stream, (const BJob*)b->d_jobs,
-                       (int)table.size(), (const BOp*)b->d_ops, (EVb<float>::T*)b->d_states, (uint8_t*)b->d_cbits,
-                       b->d_counter);
-  } else {
-    static bool set = false;
-    if (!set) {
-      (void)hipFuncSetAttribute((const void*)k_batch<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-      set = true;
-    }
-    hipLaunchKernelGGL(k_batch<double>, dim3(grid), dim3(kBatchThreads), shm, b->stream, (const BJob*)b->d_jobs,
-                       (int)table.size(), (const BOp*)b->d_ops, (EVb<double>::T*)b->d_states, (uint8_t*)b->d_cbits,
-                       b->d_counter);
-  }
+  b->shm = shm;
+  b->grid = grid;
+  b->njobs_dev = table.size();
+  launch_batch(b);
   e = hipGetLastError();
   if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
   b->ran = true;
+  b->uploaded = true;
   return QK_OK;
 }
 
@@ -546,6 +569,7 @@ qk_status qk_batch_clear(qk_batch b) {
   if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
   b->jobs.clear();
   b->ran = false;
+  b->uploaded = false;
   return QK_OK;
 }
 
