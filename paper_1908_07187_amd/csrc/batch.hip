@@ -39,17 +39,25 @@ struct BJob {
   int32_t pad;
 };
 
+// One op record, 20 dwords.  The kernel reads a record with one vector load
+// (lane w holds dword w) one op ahead of its use, so the load's latency hides
+// behind the current op and its wait does not hold up the LDS traffic.
 struct BOp {
-  int32_t kind, t0, t1, ncond;
-  uint32_t cmask;
-  int32_t cb0, cv0, cb1, cv1;
-  int32_t cbit;
-  double u;
-  double m[8];
+  uint32_t head;    // kind | t0 << 8 | t1 << 16 | ncond << 24
+  uint32_t cmask;   // control mask (BK_PHASE: the all-ones mask of targets and controls)
+  uint32_t conds;   // cb0 | cv0 << 8 | cb1 << 16 | cv1 << 24
+  int32_t cbit;     // BK_MEAS: cbit receiving the outcome, or -1
+  double m[8];      // BK_U1: 2x2 matrix row-major (re, im); BK_DIAG*: diagonal; BK_PHASE: factor; BK_MEAS: m[0] = u
 };
+static_assert(sizeof(BOp) == 80, "op record layout");
+constexpr int kOpWords = (int)(sizeof(BOp) / 4);
 
 constexpr int kBatchThreads = 512;
 constexpr int kMaxJobCbits = 256;
+// Items per thread whose LDS reads are issued together.  Two keep the
+// registers low enough for every resident workgroup's waves (complex64:
+// four 512-thread workgroups per CU; complex128: two).
+constexpr int kBU = 2;
 
 template <typename R> struct EVb;
 template <> struct EVb<float> { typedef float T __attribute__((ext_vector_type(2))); };
@@ -60,29 +68,36 @@ __device__ __forceinline__ double bwave_sum(double v) {
   return v;
 }
 
+__device__ __forceinline__ uint32_t op_word(uint32_t w, int k) { return (uint32_t)__builtin_amdgcn_readlane((int)w, k); }
+__device__ __forceinline__ double op_double(uint32_t w, int k) {
+  const uint64_t lo = op_word(w, 4 + 2 * k), hi = op_word(w, 5 + 2 * k);
+  return __longlong_as_double((long long)(lo | (hi << 32)));
+}
+__device__ __forceinline__ uint32_t ins0(uint32_t p, uint32_t q) { return ((p >> q) << (q + 1)) | (p & ((1u << q) - 1)); }
+
 template <typename R>
 __global__ __launch_bounds__(kBatchThreads) void k_batch(const BJob* __restrict__ jobs, int njobs,
-                                                         const BOp* __restrict__ ops,
+                                                         const uint32_t* __restrict__ opw,
                                                          typename EVb<R>::T* __restrict__ states,
                                                          uint8_t* __restrict__ cbits, int* counter) {
   using C = typename EVb<R>::T;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   C* st = reinterpret_cast<C*>(smem_raw);
   __shared__ uint8_t cb[kMaxJobCbits];
   __shared__ double red[2][kBatchThreads / 64];
   __shared__ double meas[2];
   __shared__ int job_sh;
-  const int tid = threadIdx.x, bd = blockDim.x;
+  const uint32_t tid = threadIdx.x, bd = blockDim.x;
   const int lane = tid & 63, w = tid >> 6;
   for (;;) {
     if (tid == 0) job_sh = atomicAdd(counter, 1);
     __syncthreads();
-    // the job (and so every op record) is the same for the whole workgroup:
-    // say so, so that op records come through scalar loads
+    // the job (and so every op record) is the same for the whole workgroup
     const int j = __builtin_amdgcn_readfirstlane(job_sh);
     if (j >= njobs) break;
     const BJob jb = jobs[j];
     const uint32_t dim = 1u << jb.n;
+    uint32_t wnext = lane < kOpWords ? opw[(size_t)jb.op_begin * kOpWords + lane] : 0u;
     for (uint32_t i = tid; i < dim; i += bd) {
       C z;
       z.x = (i == 0) ? (R)1 : (R)0;
@@ -92,77 +107,129 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BJob* __restrict_
     for (int c = tid; c < jb.ncbits; c += bd) cb[c] = 0;
     __syncthreads();
     for (uint32_t oi = jb.op_begin; oi < jb.op_end; ++oi) {
-      const BOp& o = ops[oi];
+      const uint32_t ow = wnext;
+      // the op array ends with one padding record, so this read stays in bounds
+      wnext = lane < kOpWords ? opw[(size_t)(oi + 1) * kOpWords + lane] : 0u;
+      const uint32_t head = op_word(ow, 0);
+      const int kind = head & 0xff, ncond = head >> 24;
+      const uint32_t t0 = (head >> 8) & 0xff, t1 = (head >> 16) & 0xff;
+      const uint32_t cm = op_word(ow, 1);
       bool ok = true;
-      if (o.ncond > 0 && cb[o.cb0] != (uint8_t)o.cv0) ok = false;
-      if (o.ncond > 1 && cb[o.cb1] != (uint8_t)o.cv1) ok = false;
+      if (ncond > 0) {
+        const uint32_t cw = op_word(ow, 2);
+        if (cb[cw & 0xff] != (uint8_t)((cw >> 8) & 0xff)) ok = false;
+        if (ncond > 1 && cb[(cw >> 16) & 0xff] != (uint8_t)(cw >> 24)) ok = false;
+      }
       if (ok) {
-        const uint32_t cm = o.cmask;
-        switch (o.kind) {
+        switch (kind) {
           case BK_U1: {
-            const R a0 = (R)o.m[0], b0 = (R)o.m[1], a1 = (R)o.m[2], b1 = (R)o.m[3];
-            const R a2 = (R)o.m[4], b2 = (R)o.m[5], a3 = (R)o.m[6], b3 = (R)o.m[7];
-            const uint32_t tb = 1u << o.t0, lo = tb - 1;
-            for (uint32_t p = tid; p < (dim >> 1); p += bd) {
-              const uint32_t i0 = ((p & ~lo) << 1) | (p & lo);
-              if ((i0 & cm) != cm) continue;
-              const C x = st[i0], y = st[i0 | tb];
-              C r0, r1;
-              r0.x = a0 * x.x - b0 * x.y + a1 * y.x - b1 * y.y;
-              r0.y = a0 * x.y + b0 * x.x + a1 * y.y + b1 * y.x;
-              r1.x = a2 * x.x - b2 * x.y + a3 * y.x - b3 * y.y;
-              r1.y = a2 * x.y + b2 * x.x + a3 * y.y + b3 * y.x;
-              st[i0] = r0;
-              st[i0 | tb] = r1;
+            const R a0 = (R)op_double(ow, 0), b0 = (R)op_double(ow, 1), a1 = (R)op_double(ow, 2),
+                    b1 = (R)op_double(ow, 3);
+            const R a2 = (R)op_double(ow, 4), b2 = (R)op_double(ow, 5), a3 = (R)op_double(ow, 6),
+                    b3 = (R)op_double(ow, 7);
+            const uint32_t tb = 1u << t0, half = dim >> 1;
+            for (uint32_t p0 = tid; p0 < half; p0 += kBU * bd) {
+              C x[kBU], y[kBU];
+              uint32_t ia[kBU];
+#pragma unroll
+              for (int k = 0; k < kBU; ++k) {
+                const uint32_t p = p0 + k * bd;
+                ia[k] = ins0(p, t0);
+                if (p < half) {
+                  x[k] = st[ia[k]];
+                  y[k] = st[ia[k] | tb];
+                }
+              }
+#pragma unroll
+              for (int k = 0; k < kBU; ++k) {
+                if (p0 + k * bd < half && (ia[k] & cm) == cm) {
+                  C r0, r1;
+                  r0.x = a0 * x[k].x - b0 * x[k].y + a1 * y[k].x - b1 * y[k].y;
+                  r0.y = a0 * x[k].y + b0 * x[k].x + a1 * y[k].y + b1 * y[k].x;
+                  r1.x = a2 * x[k].x - b2 * x[k].y + a3 * y[k].x - b3 * y[k].y;
+                  r1.y = a2 * x[k].y + b2 * x[k].x + a3 * y[k].y + b3 * y[k].x;
+                  st[ia[k]] = r0;
+                  st[ia[k] | tb] = r1;
+                }
+              }
             }
             break;
           }
           case BK_DIAG1:
-          case BK_DIAG2: {
-            for (uint32_t i = tid; i < dim; i += bd) {
-              if ((i & cm) != cm) continue;
-              int m = (i >> o.t0) & 1;
-              if (o.kind == BK_DIAG2) m |= ((i >> o.t1) & 1) << 1;
-              const R dr = (R)o.m[2 * m], di = (R)o.m[2 * m + 1];
-              const C x = st[i];
-              C r;
-              r.x = dr * x.x - di * x.y;
-              r.y = dr * x.y + di * x.x;
-              st[i] = r;
-            }
-            break;
-          }
+          case BK_DIAG2:
           case BK_PHASE: {
-            const R zr = (R)o.m[0], zi = (R)o.m[1];
-            for (uint32_t i = tid; i < dim; i += bd) {
-              if ((i & cm) != cm) continue;
-              const C x = st[i];
-              C r;
-              r.x = zr * x.x - zi * x.y;
-              r.y = zr * x.y + zi * x.x;
-              st[i] = r;
+            // BK_PHASE: one factor on the subspace where every bit of cm is 1.
+            // The four factors stay in named registers and are picked by
+            // selects (an indexed array would be placed in scratch memory).
+            const int nd = kind == BK_DIAG2 ? 4 : (kind == BK_DIAG1 ? 2 : 1);
+            const R d0r = (R)op_double(ow, 0), d0i = (R)op_double(ow, 1);
+            const R d1r = nd > 1 ? (R)op_double(ow, 2) : (R)0, d1i = nd > 1 ? (R)op_double(ow, 3) : (R)0;
+            const R d2r = nd > 2 ? (R)op_double(ow, 4) : (R)0, d2i = nd > 2 ? (R)op_double(ow, 5) : (R)0;
+            const R d3r = nd > 2 ? (R)op_double(ow, 6) : (R)0, d3i = nd > 2 ? (R)op_double(ow, 7) : (R)0;
+            const uint32_t s0 = kind == BK_PHASE ? 31u : t0, s1 = kind == BK_DIAG2 ? t1 : 31u;
+            for (uint32_t i0 = tid; i0 < dim; i0 += kBU * bd) {
+              C x[kBU];
+#pragma unroll
+              for (int k = 0; k < kBU; ++k)
+                if (i0 + k * bd < dim) x[k] = st[i0 + k * bd];
+#pragma unroll
+              for (int k = 0; k < kBU; ++k) {
+                const uint32_t i = i0 + k * bd;
+                if (i < dim && (i & cm) == cm) {
+                  const bool m0 = (i >> s0) & 1u, m1 = (i >> s1) & 1u;
+                  const R er = m1 ? (m0 ? d3r : d2r) : (m0 ? d1r : d0r);
+                  const R ei = m1 ? (m0 ? d3i : d2i) : (m0 ? d1i : d0i);
+                  C r;
+                  r.x = er * x[k].x - ei * x[k].y;
+                  r.y = er * x[k].y + ei * x[k].x;
+                  st[i] = r;
+                }
+              }
             }
             break;
           }
           case BK_SWAP: {
-            const uint32_t ab = 1u << o.t0, bb = 1u << o.t1;
-            for (uint32_t i = tid; i < dim; i += bd) {
-              if ((i & ab) && !(i & bb) && (i & cm) == cm) {
-                const uint32_t k2 = i ^ ab ^ bb;
-                const C x = st[i];
-                st[i] = st[k2];
-                st[k2] = x;
+            // quarter-space enumeration: bit t0 set, bit t1 clear, exchanged with the mirror
+            const uint32_t ab = 1u << t0, bb = 1u << t1, q = dim >> 2;
+            const uint32_t plo = t0 < t1 ? t0 : t1, phi = t0 < t1 ? t1 : t0;
+            for (uint32_t p0 = tid; p0 < q; p0 += kBU * bd) {
+              C x[kBU], y[kBU];
+              uint32_t ia[kBU];
+#pragma unroll
+              for (int k = 0; k < kBU; ++k) {
+                const uint32_t p = p0 + k * bd;
+                ia[k] = ins0(ins0(p, plo), phi) | ab;
+                if (p < q) {
+                  x[k] = st[ia[k]];
+                  y[k] = st[ia[k] ^ ab ^ bb];
+                }
+              }
+#pragma unroll
+              for (int k = 0; k < kBU; ++k) {
+                if (p0 + k * bd < q && (ia[k] & cm) == cm) {
+                  st[ia[k]] = y[k];
+                  st[ia[k] ^ ab ^ bb] = x[k];
+                }
               }
             }
             break;
           }
           case BK_MEAS: {
-            const uint32_t qb = 1u << o.t0;
+            const uint32_t qb = 1u << t0;
             double s0 = 0, s1 = 0;
-            for (uint32_t i = tid; i < dim; i += bd) {
-              const C x = st[i];
-              const double p = (double)x.x * (double)x.x + (double)x.y * (double)x.y;
-              if (i & qb) s1 += p; else s0 += p;
+            for (uint32_t i0 = tid; i0 < dim; i0 += kBU * bd) {
+              C x[kBU];
+#pragma unroll
+              for (int k = 0; k < kBU; ++k)
+                if (i0 + k * bd < dim) x[k] = st[i0 + k * bd];
+#pragma unroll
+              for (int k = 0; k < kBU; ++k) {
+                const uint32_t i = i0 + k * bd;
+                if (i < dim) {
+                  const double pr = (double)x[k].x * (double)x[k].x + (double)x[k].y * (double)x[k].y;
+                  if (i & qb) s1 += pr; else s0 += pr;
+                }
+              }
             }
             s0 = bwave_sum(s0);
             s1 = bwave_sum(s1);
@@ -173,32 +240,44 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BJob* __restrict_
             __syncthreads();
             if (tid == 0) {
               double p0 = 0, p1 = 0;
-              for (int k = 0; k < bd / 64; ++k) {
+              for (int k = 0; k < (int)(bd / 64); ++k) {
                 p0 += red[0][k];
                 p1 += red[1][k];
               }
+              const double u = op_double(ow, 0);
+              const int cbit = (int)op_word(ow, 3);
               const double P0 = p0 / (p0 + p1);
-              const int oc = (o.u < P0) ? 0 : 1;
+              const int oc = (u < P0) ? 0 : 1;
               const double po = oc ? p1 : p0;
               meas[0] = po > 0 ? 1.0 / sqrt(po) : 0.0;
               meas[1] = (double)oc;
-              if (o.cbit >= 0 && po > 0) cb[o.cbit] = (uint8_t)oc;
+              if (cbit >= 0 && po > 0) cb[cbit] = (uint8_t)oc;
             }
             __syncthreads();
             const double sc = meas[0];
             const uint32_t oc = (uint32_t)meas[1];
             if (sc != 0.0) {
               const R scale = (R)sc;
-              for (uint32_t i = tid; i < dim; i += bd) {
-                C x = st[i];
-                if (((i & qb) != 0) == (oc != 0)) {
-                  x.x *= scale;
-                  x.y *= scale;
-                } else {
-                  x.x = 0;
-                  x.y = 0;
+              for (uint32_t i0 = tid; i0 < dim; i0 += kBU * bd) {
+                C x[kBU];
+#pragma unroll
+                for (int k = 0; k < kBU; ++k)
+                  if (i0 + k * bd < dim) x[k] = st[i0 + k * bd];
+#pragma unroll
+                for (int k = 0; k < kBU; ++k) {
+                  const uint32_t i = i0 + k * bd;
+                  if (i < dim) {
+                    C v = x[k];
+                    if (((i & qb) != 0) == (oc != 0)) {
+                      v.x *= scale;
+                      v.y *= scale;
+                    } else {
+                      v.x = 0;
+                      v.y = 0;
+                    }
+                    st[i] = v;
+                  }
                 }
-                st[i] = x;
               }
             }
             break;
@@ -346,20 +425,19 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
       if (o.conds[c].cbit < 0 || o.conds[c].cbit >= ncbits) return bfail(b, QK_E_ARG, where + "condition cbit out of range");
       if (o.conds[c].value != 0 && o.conds[c].value != 1) return bfail(b, QK_E_ARG, where + "condition value must be 0 or 1");
     }
-    d.ncond = o.n_conds;
-    d.cb0 = o.n_conds > 0 ? o.conds[0].cbit : 0;
-    d.cv0 = o.n_conds > 0 ? o.conds[0].value : 0;
-    d.cb1 = o.n_conds > 1 ? o.conds[1].cbit : 0;
-    d.cv1 = o.n_conds > 1 ? o.conds[1].value : 0;
+    int kind = 0, t0 = 0, t1 = 0;
+    d.cbit = -1;
+    if (o.n_conds > 0) d.conds = (uint32_t)o.conds[0].cbit | ((uint32_t)o.conds[0].value << 8);
+    if (o.n_conds > 1) d.conds |= ((uint32_t)o.conds[1].cbit << 16) | ((uint32_t)o.conds[1].value << 24);
     if (o.kind == QK_OP_MEASURE) {
       if (o.qubit < 0 || o.qubit >= n) return bfail(b, QK_E_ARG, where + "qubit out of range");
       if (o.cbit < -1 || o.cbit >= ncbits) return bfail(b, QK_E_ARG, where + "cbit out of range");
       if (!(o.u >= 0.0 && o.u < 1.0)) return bfail(b, QK_E_ARG, where + "u must be in [0, 1)");
       if (o.n_conds) return bfail(b, QK_E_ARG, where + "measurements take no conditions");
-      d.kind = BK_MEAS;
-      d.t0 = o.qubit;
+      kind = BK_MEAS;
+      t0 = o.qubit;
       d.cbit = o.cbit;
-      d.u = o.u;
+      d.m[0] = o.u;
     } else if (o.kind == QK_OP_GATE) {
       int arity = 0, np = 0;
       if (!builtin_info(o.gate, &arity, &np)) return bfail(b, QK_E_UNSUPPORTED, where + "batched circuits take builtin gates only");
@@ -375,11 +453,11 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
       uint32_t cm = 0;
       for (int q = 0; q < o.n_controls; ++q) cm |= 1u << o.controls[q];
       const BuiltinGate g = builtin_gate(o.gate, np ? o.param : 0.0);
-      d.t0 = o.targets[0];
-      d.t1 = arity > 1 ? o.targets[1] : 0;
+      t0 = o.targets[0];
+      t1 = arity > 1 ? o.targets[1] : 0;
       switch (g.cls) {
         case BG_DENSE1:
-          d.kind = BK_U1;
+          kind = BK_U1;
           d.cmask = cm;
           for (int e = 0; e < 4; ++e) {
             d.m[2 * e] = g.m[e].real();
@@ -387,7 +465,7 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
           }
           break;
         case BG_DIAG:
-          d.kind = arity == 1 ? BK_DIAG1 : BK_DIAG2;
+          kind = arity == 1 ? BK_DIAG1 : BK_DIAG2;
           d.cmask = cm;
           for (size_t e = 0; e < g.m.size(); ++e) {
             d.m[2 * e] = g.m[e].real();
@@ -395,13 +473,13 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
           }
           break;
         case BG_PHASE:
-          d.kind = BK_PHASE;
-          d.cmask = cm | (1u << d.t0) | (arity > 1 ? (1u << d.t1) : 0u);
+          kind = BK_PHASE;
+          d.cmask = cm | (1u << t0) | (arity > 1 ? (1u << t1) : 0u);
           d.m[0] = g.z.real();
           d.m[1] = g.z.imag();
           break;
         case BG_SWAP:
-          d.kind = BK_SWAP;
+          kind = BK_SWAP;
           d.cmask = cm;
           break;
         default:
@@ -410,6 +488,7 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
     } else {
       return bfail(b, QK_E_ARG, where + "unknown op kind");
     }
+    d.head = (uint32_t)kind | ((uint32_t)t0 << 8) | ((uint32_t)t1 << 16) | ((uint32_t)o.n_conds << 24);
     hj.ops.push_back(d);
   }
   b->jobs.push_back(std::move(hj));
@@ -427,7 +506,7 @@ static void launch_batch(qk_batch b) {
       set = true;
     }
     hipLaunchKernelGGL(k_batch<float>, dim3(b->grid), dim3(kBatchThreads), b->shm, b->stream, (const BJob*)b->d_jobs,
-                       (int)b->njobs_dev, (const BOp*)b->d_ops, (EVb<float>::T*)b->d_states, (uint8_t*)b->d_cbits,
+                       (int)b->njobs_dev, (const uint32_t*)b->d_ops, (EVb<float>::T*)b->d_states, (uint8_t*)b->d_cbits,
                        b->d_counter);
   } else {
     static bool set = false;
@@ -436,7 +515,7 @@ static void launch_batch(qk_batch b) {
       set = true;
     }
     hipLaunchKernelGGL(k_batch<double>, dim3(b->grid), dim3(kBatchThreads), b->shm, b->stream, (const BJob*)b->d_jobs,
-                       (int)b->njobs_dev, (const BOp*)b->d_ops, (EVb<double>::T*)b->d_states, (uint8_t*)b->d_cbits,
+                       (int)b->njobs_dev, (const uint32_t*)b->d_ops, (EVb<double>::T*)b->d_states, (uint8_t*)b->d_cbits,
                        b->d_counter);
   }
 }
@@ -486,10 +565,11 @@ qk_status qk_batch_run(qk_batch b) {
     t.cbit_off = j.cbit_off;
     table.push_back(t);
   }
+  all_ops.push_back(BOp{});   // padding record: the kernel reads one record ahead
   qk_status st;
   if ((st = bensure(b, b->d_states, b->states_bytes, soff * amp, "batch states"))) return st;
   if ((st = bensure(b, b->d_cbits, b->cbits_bytes, std::max<size_t>(coff, 1), "batch cbits"))) return st;
-  if ((st = bensure(b, b->d_ops, b->ops_bytes, std::max<size_t>(all_ops.size(), 1) * sizeof(BOp), "batch ops"))) return st;
+  if ((st = bensure(b, b->d_ops, b->ops_bytes, all_ops.size() * sizeof(BOp), "batch ops"))) return st;
   if ((st = bensure(b, b->d_jobs, b->jobs_bytes, table.size() * sizeof(BJob), "batch job table"))) return st;
   if (!b->d_counter) {
     size_t cb = 0;

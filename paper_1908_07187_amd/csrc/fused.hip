@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::V* psi, cons
   constexpr int NF = RT * KS * 2;           // A fragments (one value per lane each)
   constexpr int G = CW / 16;                // column groups per wave
   constexpr int LB = (CW == 16) ? 4 : (CW == 32 ? 5 : 6);
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   R* afrag = reinterpret_cast<R*>(smem_raw);
   // AREG = false: the A fragments are re-read from LDS for every tile.  The
   // offset `zoff` is reloaded from LDS per tile (it is always 0), so the

@@ -514,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_generic(V2<R>* __restrict__ ps
                                                           int k, uint64_t ngroups, Special sp, uint64_t cmask, Pos32 tp,
                                                           CondArgs cond) {
   if (!conds_ok(cond)) return;
-  extern __shared__ unsigned char smem_raw[];
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   V2<R>* buf = reinterpret_cast<V2<R>*>(smem_raw);
   const int dimK = 1 << k;
   const int G = dimK >= kBlock ? 1 : kBlock / dimK;
