@@ -85,14 +85,34 @@ def batch12(args, qk, torch):
     b.sync()
     dt = (time.perf_counter() - t0) / args.steps
     batch_cps = nc / dt
-    b.close()
     _say(f"batch12 persistent batch: {batch_cps:.1f} circuits/s ({nc} circuits per launch, {dt*1e3:.2f} ms)")
+    # (d) the same batch with complex64 states (FP32 arithmetic), fidelity against (c)
+    b64 = qk.Batch("c64")
+    for c in circs:
+        qk.add_circuit(b64, c)
+    for _ in range(max(1, args.warmup)):
+        b64.run()
+    b64.sync()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b64.run()
+    b64.sync()
+    dt64 = (time.perf_counter() - t0) / args.steps
+    fid = []
+    for j in range(min(16, nc)):
+        a, g = b.state(j), b64.state(j).astype(np.complex128)
+        fid.append(abs(np.vdot(a, g)) ** 2 / (np.vdot(a, a).real * np.vdot(g, g).real))
+    b64.close()
+    b.close()
+    _say(f"batch12 persistent batch complex64: {nc / dt64:.1f} circuits/s ({dt64*1e3:.2f} ms), "
+         f"min fidelity vs complex128 {min(fid):.15f}")
     gates = len(circs[0].gate_ops())
     out = _base(args, batch_cps, "circuits/s",
                 {"workload": f"{nc} random 12-qubit circuits, 20 layers ({gates} gates each), complex128, "
                              f"one persistent launch", "n_qubits": 12, "layers": 20, "circuits": nc},
                 "f64", dt * 1e3)
-    out["forms"] = {"eager_gate_by_gate_cps": eager_cps, "graph_replay_cps": graph_cps, "persistent_batch_cps": batch_cps}
+    out["forms"] = {"eager_gate_by_gate_cps": eager_cps, "graph_replay_cps": graph_cps, "persistent_batch_cps": batch_cps,
+                    "persistent_batch_c64_cps": nc / dt64, "c64_min_fidelity_vs_c128": float(min(fid))}
     return out
 
 

@@ -89,7 +89,7 @@ __device__ __forceinline__ void mst(T* p, T v) {
 template <typename R, int K, int CW, bool NT, bool AREG>
 __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::V* psi, const typename MF<R>::V* __restrict__ mat,
                                                     uint64_t nchunks, Special sp, uint64_t cmask, MfmaArgs ma,
-                                                    CondArgs cond) {
+                                                    CondArgs cond, bool xcd) {
   using V = typename MF<R>::V;
   using Acc = typename MF<R>::Acc;
   constexpr int DIM = 1 << K;
@@ -101,13 +101,13 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::V* psi, cons
   extern __shared__ __align__(16) unsigned char smem_raw[];
   R* afrag = reinterpret_cast<R*>(smem_raw);
   // AREG = false: the A fragments are re-read from LDS for every tile.  The
-  // offset `zoff` is reloaded from LDS per tile (it is always 0), so the
-  // compiler cannot hoist the fragment reads into registers; this keeps the
-  // register count (and so the waves per SIMD) of large blocks in check.
-  __shared__ int zero_sh;
+  // offset `zoff` (always 0) passes through an empty asm statement per tile,
+  // so the compiler cannot hoist the fragment reads into registers; this keeps
+  // the register count (and so the waves per SIMD) of large blocks in check.
+  // (A memory read of a zero would do the same but, issued through the
+  // generic address space, it would also drain the prefetched global loads.)
 
   if (!conds_ok_m(cond)) return;
-  if (threadIdx.x == 0) zero_sh = 0;
 
   // Stage the real-embedded matrix in fragment order: fragment f = (rt, ks, part).
   for (int e = threadIdx.x; e < NF * 64; e += 256) {
@@ -144,7 +144,11 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::V* psi, cons
   }
   const bool wr0 = (2 * h) < DIM;          // false only for K = 2, h >= 2 (padding rows)
 
-  const uint64_t wid = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  // xcd: workgroups are numbered so that the ones an XCD runs (every eighth
+  // in launch order) take one contiguous range of chunks
+  uint64_t blk = blockIdx.x;
+  if (xcd && !(gridDim.x & 7)) blk = (blk & 7) * (gridDim.x >> 3) + (blk >> 3);
+  const uint64_t wid = blk * 4 + (threadIdx.x >> 6);
   const uint64_t nw = (uint64_t)gridDim.x * 4;
 
   V xa[KS][G], xb[KS][G];
@@ -157,7 +161,8 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::V* psi, cons
     }
   };
   auto compute_store = [&](uint64_t base, V (*x)[G]) {
-    const int zoff = AREG ? 0 : *(volatile int*)&zero_sh;
+    int zoff = 0;
+    if constexpr (!AREG) asm volatile("" : "+s"(zoff));
     Acc acc[RT][G];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -195,28 +200,29 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::V* psi, cons
     }
   };
 
+  // The next chunk's loads are issued unconditionally (the last chunk loads
+  // itself once more and drops the values): with the same number of loads in
+  // flight on every path, the wait before a chunk's MFMAs covers only that
+  // chunk's own loads instead of draining the prefetch as well.
   uint64_t ch = wid;
   if (ch >= nchunks) return;
   uint64_t base = insert_zeros_m(ch, sp) | cmask;
   load(base, xa);
   for (;;) {
     uint64_t nx = ch + nw;
-    uint64_t nbase = 0;
-    if (nx < nchunks) {
-      nbase = insert_zeros_m(nx, sp) | cmask;
-      load(nbase, xb);
-    }
+    bool more = nx < nchunks;
+    uint64_t nbase = more ? (insert_zeros_m(nx, sp) | cmask) : base;
+    load(nbase, xb);
     compute_store(base, xa);
-    if (nx >= nchunks) break;
+    if (!more) break;
     ch = nx;
     base = nbase;
     nx = ch + nw;
-    if (nx < nchunks) {
-      nbase = insert_zeros_m(nx, sp) | cmask;
-      load(nbase, xa);
-    }
+    more = nx < nchunks;
+    nbase = more ? (insert_zeros_m(nx, sp) | cmask) : base;
+    load(nbase, xa);
     compute_store(base, xb);
-    if (nx >= nchunks) break;
+    if (!more) break;
     ch = nx;
     base = nbase;
   }
@@ -265,7 +271,7 @@ static hipError_t launch_k(const Launch& L, const void* mat, uint64_t nchunks, c
   const uint64_t cap = (uint64_t)g_ncu * std::max(1, waves_per_cu / 4);
   const unsigned g = (unsigned)std::max<uint64_t>(1, std::min(want, cap));
   hipLaunchKernelGGL((k_dense_mfma<R, K, CW, NT, AREG>), dim3(g), dim3(256), shm, L.stream, (typename MF<R>::V*)L.psi,
-                     (const typename MF<R>::V*)mat, nchunks, sp, cmask, ma, L.cond);
+                     (const typename MF<R>::V*)mat, nchunks, sp, cmask, ma, L.cond, L.tune.xcd != 0);
   return hipGetLastError();
 }
 
@@ -292,12 +298,16 @@ static hipError_t launch_kwa(const Launch& L, const void* mat, int cw, bool nt, 
 }
 
 // Blocks up to k = 4 keep their (at most 16) A values in registers; larger
-// blocks choose by the "mfma_areg" knob.
+// blocks choose by the "mfma_areg" knob, except complex128 k = 6, whose 256
+// A values would not fit beside the tile (the registers would spill to
+// scratch memory), so it always re-reads them from LDS.
 template <typename R, int K>
 static hipError_t launch_kw(const Launch& L, const void* mat, int cw, bool nt, uint64_t nchunks, const Special& sp,
                             uint64_t cmask, const MfmaArgs& ma, int waves) {
   if constexpr (K <= 4) {
     return launch_kwa<R, K, true>(L, mat, cw, nt, nchunks, sp, cmask, ma, waves);
+  } else if constexpr (K == 6 && std::is_same<R, double>::value) {
+    return launch_kwa<R, K, false>(L, mat, cw, nt, nchunks, sp, cmask, ma, waves);
   } else {
     if (L.tune.mfma_areg) return launch_kwa<R, K, true>(L, mat, cw, nt, nchunks, sp, cmask, ma, waves);
     return launch_kwa<R, K, false>(L, mat, cw, nt, nchunks, sp, cmask, ma, waves);
