@@ -84,6 +84,7 @@ struct qk_sim_s {
   std::vector<UserGate*> ugates;
   int fuse_k = 0;
   std::vector<GateDesc> pending;
+  std::vector<GateDesc> drun;       // diagonal gates held back for one combined pass (never beside `pending`)
   Tuning tune;
   int64_t sweeps = 0, fused_blocks = 0, fused_gates = 0;
   std::string err;
@@ -480,8 +481,112 @@ qk_status execute(qk_sim s, const GateDesc& d) {
 
 qk_status sp_flush_run(qk_sim s);
 
-qk_status flush(qk_sim s) {
-  if (s->sparse) return sp_flush_run(s);
+// Diagonal runs.  A diagonal gate on at most two targets (or a phase on the
+// all-ones subspace of any qubit set) joins the run; any other operation first
+// applies the run.  The run becomes one k_diag_run pass when that pass touches
+// no more amplitudes than the gates would one by one; otherwise each gate gets
+// its own sweep, as without runs.
+
+bool phase_only_diag(const GateDesc& d) {
+  for (size_t i = 0; i + 1 < d.m.size(); ++i)
+    if (d.m[i] != cd(1.0)) return false;
+  return true;
+}
+
+bool joins_run(const GateDesc& d) {
+  if (d.kind == D_PHASE1) return true;
+  return d.kind == D_DIAG && (d.targets.size() <= 2 || phase_only_diag(d));
+}
+
+uint64_t bits_of(const std::vector<int>& a) {
+  uint64_t m = 0;
+  for (int q : a) m |= 1ull << q;
+  return m;
+}
+
+// Term of a run; the mask holds the bits that must all be 1 for it to act.
+DiagRunTerm run_term(const GateDesc& d) {
+  DiagRunTerm t{};
+  t.mask = bits_of(d.controls);
+  if (d.kind == D_PHASE1 || phase_only_diag(d)) {
+    t.mask |= bits_of(d.targets);
+    const cd z = d.kind == D_PHASE1 ? d.z : d.m.back();
+    t.k = 0;
+    t.d[0] = z.real();
+    t.d[1] = z.imag();
+    return t;
+  }
+  t.k = (int8_t)d.targets.size();
+  t.p0 = (int8_t)d.targets[0];
+  t.p1 = (int8_t)(t.k > 1 ? d.targets[1] : 0);
+  for (size_t e = 0; e < d.m.size(); ++e) {
+    t.d[2 * e] = d.m[e].real();
+    t.d[2 * e + 1] = d.m[e].imag();
+  }
+  return t;
+}
+
+qk_status execute(qk_sim s, const GateDesc& d);
+
+qk_status flush_drun(qk_sim s) {
+  if (s->drun.empty()) return QK_OK;
+  std::vector<GateDesc> run;
+  run.swap(s->drun);
+  if (run.size() > 1) {
+    // amplitudes touched: the run's pass vs the gates' own sweeps
+    uint64_t common = ~0ull;
+    double alone = 0;
+    for (const GateDesc& d : run) {
+      const DiagRunTerm t = run_term(d);
+      common &= t.mask;
+      const int fixed = t.k == 0 ? __builtin_popcountll(t.mask) : (int)d.controls.size();
+      alone += std::ldexp(1.0, s->n - fixed);
+    }
+    const int nc = __builtin_popcountll(common);
+    if (std::ldexp(1.0, s->n - nc) <= alone) {
+      DiagRunArgs a{};
+      a.cbits = (const uint8_t*)s->cbits.p;
+      a.n = (int)run.size();
+      int ncond = 0;
+      for (int i = 0; i < a.n; ++i) {
+        a.t[i] = run_term(run[i]);
+        a.t[i].c0 = (uint8_t)ncond;
+        for (const qk_cond& c : run[i].conds) {
+          a.cb[ncond] = c.cbit;
+          a.cv[ncond] = (uint8_t)c.value;
+          ++ncond;
+        }
+        a.t[i].c1 = (uint8_t)ncond;
+      }
+      std::vector<int> cpos;
+      for (int b = 0; b < 64; ++b)
+        if ((common >> b) & 1) cpos.push_back(b);
+      Launch L = make_launch(s, {});
+      s->fused_blocks++;
+      s->fused_gates += (int64_t)run.size();
+      return check_launch(s, launch_diag_run(L, a, cpos.data(), (int)cpos.size()), "diagonal run");
+    }
+  }
+  for (const GateDesc& d : run) {
+    qk_status st = execute(s, d);
+    if (st) return st;
+  }
+  return QK_OK;
+}
+
+// Appends a diagonal gate to the run (applying the run first when it is full).
+qk_status add_to_run(qk_sim s, GateDesc&& d) {
+  int ncond = 0;
+  for (const GateDesc& g : s->drun) ncond += (int)g.conds.size();
+  if ((int)s->drun.size() == kDiagRunTerms || ncond + (int)d.conds.size() > kDiagRunConds) {
+    qk_status st = flush_drun(s);
+    if (st) return st;
+  }
+  s->drun.push_back(std::move(d));
+  return QK_OK;
+}
+
+qk_status flush_pending(qk_sim s) {
   if (s->pending.empty()) return QK_OK;
   std::vector<GateDesc> pend;
   pend.swap(s->pending);
@@ -512,6 +617,14 @@ qk_status flush(qk_sim s) {
     if (st) return st;
   }
   return QK_OK;
+}
+
+// Applies every operation held back (fusion queue, diagonal run, sparse run).
+qk_status flush(qk_sim s) {
+  if (s->sparse) return sp_flush_run(s);
+  qk_status st = flush_pending(s);
+  if (st) return st;
+  return flush_drun(s);
 }
 
 qk_status sync_stream(qk_sim s) {
@@ -1138,8 +1251,15 @@ qk_status qk_apply_gate(qk_sim s, qk_gate gate, const int32_t* targets, int32_t 
   }
   if (s->sparse) return sparse_execute(s, d);
   if (d.conds.empty() && d.fusable && s->fuse_k >= 2 && nt + nc <= s->fuse_k) {
+    qk_status st = flush_drun(s);   // gates before this one in the diagonal run act first
+    if (st) return st;
     s->pending.push_back(std::move(d));
     return QK_OK;
+  }
+  if (s->tune.diag_runs && joins_run(d)) {
+    qk_status st = flush_pending(s);
+    if (st) return st;
+    return add_to_run(s, std::move(d));
   }
   qk_status st = flush(s);
   if (st) return st;
@@ -1763,6 +1883,11 @@ qk_status qk_set_tuning(qk_sim s, const char* key, int32_t value) {
     s->tune.lane_items = value;
   } else if (k == "mfma_areg") {
     s->tune.mfma_areg = value != 0;
+  } else if (k == "diag_runs") {
+    if (value != 0 && value != 1) return fail(s, QK_E_ARG, "diag_runs must be 0 or 1");
+    qk_status st = flush(s);
+    if (st) return st;
+    s->tune.diag_runs = value;
   } else if (k == "xcd") {
     s->tune.xcd = value != 0;
   } else if (k == "mfma_cols") {
@@ -1788,6 +1913,7 @@ qk_status qk_get_tuning(qk_sim s, const char* key, int32_t* value) {
   else if (k == "mfma_waves") *value = s->tune.mfma_waves;
   else if (k == "mfma_cols") *value = s->tune.mfma_cols;
   else if (k == "mfma_areg") *value = s->tune.mfma_areg;
+  else if (k == "diag_runs") *value = s->tune.diag_runs;
   else if (k == "xcd") *value = s->tune.xcd;
   else return fail(s, QK_E_ARG, "unknown tuning key " + k);
   return QK_OK;

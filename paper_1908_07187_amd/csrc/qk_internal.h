@@ -61,6 +61,7 @@ struct Tuning {
   int mfma_cols = 32;    // tile columns per wave for the matrix-core kernel (16, 32, 64; capped per k)
   int mfma_areg = 0;     // blocks of 5-6 qubits: 1 keeps the A fragments in registers, 0 re-reads them from LDS
   int xcd = 1;           // sweeps: 1 renumbers workgroups so each XCD sweeps a contiguous range
+  int diag_runs = 1;     // 1: consecutive diagonal gates are held back and applied in one pass
 };
 
 // Where device work goes and what it works on.
@@ -84,6 +85,30 @@ hipError_t launch_butterfly(const Launch& L, int t, const int* controls, int nc,
 hipError_t launch_diag(const Launch& L, const int* targets, int k, const int* controls, int nc, const Diag64& d);
 hipError_t launch_phase_all1(const Launch& L, const int* bits, int nb, double zr, double zi);
 hipError_t launch_swap(const Launch& L, int a, int b, const int* controls, int nc);
+
+// Consecutive diagonal gates applied in one pass.  Term t multiplies a_i by
+// d_t[m_t(i)] where every bit of mask_t is 1 in i and the term's classical
+// conditions hold (evaluated on the device); m_t(i) is the bit of i at p0
+// (k = 1), the bits at p0, p1 (k = 2), or 0 (k = 0: one factor on the mask
+// subspace).  The pass enumerates only the subspace where the `common` bits
+// (set in every term's mask) are 1.
+constexpr int kDiagRunTerms = 24;
+constexpr int kDiagRunConds = 32;
+struct DiagRunTerm {
+  uint64_t mask;
+  int8_t k, p0, p1;
+  uint8_t c0, c1;   // the term's conditions are entries [c0, c1) of the run's list
+  uint8_t pad[3];
+  double d[8];      // (re, im) of the factors for m = 0 .. 2^k - 1
+};
+struct DiagRunArgs {
+  const uint8_t* cbits;
+  int n;                          // terms
+  int cb[kDiagRunConds];          // condition: cbit index ...
+  uint8_t cv[kDiagRunConds];      // ... and the value it must hold
+  DiagRunTerm t[kDiagRunTerms];
+};
+hipError_t launch_diag_run(const Launch& L, const DiagRunArgs& run, const int* common, int ncommon);
 hipError_t launch_dense_generic(const Launch& L, const int* targets, int k, const int* controls, int nc,
                                 const void* d_matrix);
 // mode 0: table d_finv; 1: affine x = Ainv (y - B) mod 2^k; 2: modular
