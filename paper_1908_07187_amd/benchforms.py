@@ -187,11 +187,15 @@ def qft26(args, qk, torch):
     prog = qk.Program(c)
     upd = c.amp_updates()
     res = {}
-    for fusion in (0, 4, 5):
+    # "0": one sweep per gate; "runs": gate by gate with each CPHASE chain as one
+    # pass (diagonal runs); 4, 5: fused blocks on matrix cores
+    for fusion in (0, "runs", 4, 5):
         times = []
         for k in range(args.warmup + args.steps):
             s = qk.Sim("c128")
-            if fusion:
+            if fusion == 0:
+                s.set_tuning("diag_runs", 0)
+            elif fusion != "runs":
                 s.set_fusion(fusion)
             s.add_qubits(26)
             s.set_state(c.init_state)          # the 1 GiB upload is outside the timed region
@@ -204,7 +208,8 @@ def qft26(args, qk, torch):
             st = s.stats()
             s.close()
         dt = sum(times) / len(times)
-        res[fusion] = {"ms": dt * 1e3, "amp_updates_per_s": upd / dt, "sweeps": st["sweeps"]}
+        res[fusion] = {"ms": dt * 1e3, "amp_updates_per_s": upd / dt, "sweeps": st["sweeps"],
+                       "fused_blocks": st["fused_blocks"]}
         _say(f"qft26 fusion={fusion}: {dt*1e3:.1f} ms, {upd/dt:.3e} amp-updates/s")
     best = min(res, key=lambda f: res[f]["ms"])
     out = _base(args, res[0]["amp_updates_per_s"], "amplitude-updates/s",

@@ -493,38 +493,49 @@ bool phase_only_diag(const GateDesc& d) {
   return true;
 }
 
-bool joins_run(const GateDesc& d) {
-  if (d.kind == D_PHASE1) return true;
-  return d.kind == D_DIAG && (d.targets.size() <= 2 || phase_only_diag(d));
-}
-
 uint64_t bits_of(const std::vector<int>& a) {
   uint64_t m = 0;
   for (int q : a) m |= 1ull << q;
   return m;
 }
 
-// Term of a run; the mask holds the bits that must all be 1 for it to act.
-DiagRunTerm run_term(const GateDesc& d) {
-  DiagRunTerm t{};
-  t.mask = bits_of(d.controls);
-  if (d.kind == D_PHASE1 || phase_only_diag(d)) {
-    t.mask |= bits_of(d.targets);
-    const cd z = d.kind == D_PHASE1 ? d.z : d.m.back();
-    t.k = 0;
-    t.d[0] = z.real();
-    t.d[1] = z.imag();
-    return t;
-  }
-  t.k = (int8_t)d.targets.size();
-  t.p0 = (int8_t)d.targets[0];
-  t.p1 = (int8_t)(t.k > 1 ? d.targets[1] : 0);
-  for (size_t e = 0; e < d.m.size(); ++e) {
-    t.d[2 * e] = d.m[e].real();
-    t.d[2 * e + 1] = d.m[e].imag();
-  }
-  return t;
+// A term's qubit set (targets and controls) must fit one factor table.
+bool joins_run(const GateDesc& d) {
+  if (d.targets.size() + d.controls.size() > (size_t)kDiagRunGroupBits) return false;
+  if (d.kind == D_PHASE1) return true;
+  return d.kind == D_DIAG && (d.targets.size() <= 2 || phase_only_diag(d));
 }
+
+// Bits that must all be 1 for the term to act: the controls, and for a phase
+// on the all-ones subspace the targets as well.
+uint64_t run_mask(const GateDesc& d) {
+  uint64_t m = bits_of(d.controls);
+  if (d.kind == D_PHASE1 || phase_only_diag(d)) m |= bits_of(d.targets);
+  return m;
+}
+
+// Greedy grouping of the terms' qubit sets, in gate order: a term joins the
+// first group whose bits stay within kDiagRunGroupBits, else opens a group.
+// Returns false when a term would need more than kDiagRunGroups groups.
+bool group_terms(const std::vector<GateDesc>& run, std::vector<uint64_t>& groups, std::vector<int>& of) {
+  groups.clear();
+  of.clear();
+  for (const GateDesc& d : run) {
+    const uint64_t sq = bits_of(d.targets) | bits_of(d.controls);
+    int g = 0;
+    while (g < (int)groups.size() && __builtin_popcountll(groups[g] | sq) > kDiagRunGroupBits) ++g;
+    if (g == (int)groups.size()) {
+      if (g == kDiagRunGroups) return false;
+      groups.push_back(0);
+    }
+    groups[g] |= sq;
+    of.push_back(g);
+  }
+  return true;
+}
+
+// Rank of bit q among the set bits of u (its position in the group index).
+int local_bit(uint64_t u, int q) { return __builtin_popcountll(u & ((1ull << q) - 1)); }
 
 qk_status execute(qk_sim s, const GateDesc& d);
 
@@ -532,32 +543,62 @@ qk_status flush_drun(qk_sim s) {
   if (s->drun.empty()) return QK_OK;
   std::vector<GateDesc> run;
   run.swap(s->drun);
-  if (run.size() > 1) {
+  std::vector<uint64_t> groups;
+  std::vector<int> of;
+  if (run.size() > 1 && group_terms(run, groups, of)) {
     // amplitudes touched: the run's pass vs the gates' own sweeps
     uint64_t common = ~0ull;
     double alone = 0;
     for (const GateDesc& d : run) {
-      const DiagRunTerm t = run_term(d);
-      common &= t.mask;
-      const int fixed = t.k == 0 ? __builtin_popcountll(t.mask) : (int)d.controls.size();
-      alone += std::ldexp(1.0, s->n - fixed);
+      const uint64_t m = run_mask(d);
+      common &= m;
+      const bool phase = d.kind == D_PHASE1 || phase_only_diag(d);
+      alone += std::ldexp(1.0, s->n - (phase ? __builtin_popcountll(m) : (int)d.controls.size()));
     }
     const int nc = __builtin_popcountll(common);
     if (std::ldexp(1.0, s->n - nc) <= alone) {
       DiagRunArgs a{};
       a.cbits = (const uint8_t*)s->cbits.p;
       a.n = (int)run.size();
+      a.ng = (int)groups.size();
+      for (int g = 0; g < a.ng; ++g) {
+        int j = 0;
+        for (int q = 0; q < 64; ++q)
+          if ((groups[g] >> q) & 1) a.grp[g].pos[j++] = (int8_t)q;
+        a.grp[g].nb = (int8_t)j;
+      }
       int ncond = 0;
       for (int i = 0; i < a.n; ++i) {
-        a.t[i] = run_term(run[i]);
-        a.t[i].c0 = (uint8_t)ncond;
-        for (const qk_cond& c : run[i].conds) {
+        const GateDesc& d = run[i];
+        DiagRunTerm& t = a.t[i];
+        const uint64_t u = groups[of[i]];
+        t.g = (uint8_t)of[i];
+        const uint64_t m = run_mask(d);
+        for (int q = 0; q < 64; ++q)
+          if ((m >> q) & 1) t.lmask |= (uint8_t)(1u << local_bit(u, q));
+        if (d.kind == D_PHASE1 || phase_only_diag(d)) {
+          const cd z = d.kind == D_PHASE1 ? d.z : d.m.back();
+          t.k = 0;
+          t.d[0] = z.real();
+          t.d[1] = z.imag();
+        } else {
+          t.k = (int8_t)d.targets.size();
+          t.l0 = (int8_t)local_bit(u, d.targets[0]);
+          t.l1 = (int8_t)(t.k > 1 ? local_bit(u, d.targets[1]) : 0);
+          for (size_t e = 0; e < d.m.size(); ++e) {
+            t.d[2 * e] = d.m[e].real();
+            t.d[2 * e + 1] = d.m[e].imag();
+          }
+        }
+        t.c0 = (uint8_t)ncond;
+        for (const qk_cond& c : d.conds) {
           a.cb[ncond] = c.cbit;
           a.cv[ncond] = (uint8_t)c.value;
           ++ncond;
         }
-        a.t[i].c1 = (uint8_t)ncond;
+        t.c1 = (uint8_t)ncond;
       }
+      a.ncond = ncond;
       std::vector<int> cpos;
       for (int b = 0; b < 64; ++b)
         if ((common >> b) & 1) cpos.push_back(b);
@@ -574,11 +615,20 @@ qk_status flush_drun(qk_sim s) {
   return QK_OK;
 }
 
-// Appends a diagonal gate to the run (applying the run first when it is full).
+// Appends a diagonal gate to the run, applying the run first when the new
+// gate would exceed its terms, conditions or factor-table groups.
 qk_status add_to_run(qk_sim s, GateDesc&& d) {
   int ncond = 0;
   for (const GateDesc& g : s->drun) ncond += (int)g.conds.size();
-  if ((int)s->drun.size() == kDiagRunTerms || ncond + (int)d.conds.size() > kDiagRunConds) {
+  bool full = (int)s->drun.size() == kDiagRunTerms || ncond + (int)d.conds.size() > kDiagRunConds;
+  if (!full) {
+    std::vector<GateDesc> trial(s->drun);
+    trial.push_back(d);
+    std::vector<uint64_t> groups;
+    std::vector<int> of;
+    full = !group_terms(trial, groups, of);
+  }
+  if (full) {
     qk_status st = flush_drun(s);
     if (st) return st;
   }

@@ -456,74 +456,99 @@ hipError_t launch_phase_all1(const Launch& L, const int* bits, int nb, double zr
 }
 
 // ---------------------------------------------------------------- diagonal runs
-// Several diagonal gates in one pass: a_i <- f(i) a_i with f(i) the product,
-// in gate order, of d_t[m_t(i)] over the active terms t whose mask bits are
-// all 1 in i.  The term's activity (its classical conditions) is read from
-// the cbits once per thread; a launch with no active term exits at once.
+// Several diagonal gates in one pass.  Each workgroup first finds which terms
+// are active (lane c of every wave reads condition c, a ballot gathers the
+// failures), then tabulates every group's combined factor over the group's
+// bits in LDS (FP64 products, rounded once to the state's precision), and
+// sweeps its share of the amplitudes: a_i <- a_i * prod_g tab_g[bits of i on
+// group g].  A launch whose terms are all inactive exits at once.
 
 template <typename R, int ITEMS, bool NT>
 __global__ __launch_bounds__(kBlock) void k_diag_run(CV<R>* __restrict__ psi, uint64_t nitems, Special sp,
                                                      uint64_t common, DiagRunArgs run, bool xcd) {
+  __shared__ CV<R> tab[kDiagRunGroups * 64];
+  const int lane = threadIdx.x & 63;
+  bool bad = false;
+  if (lane < run.ncond) bad = run.cbits[run.cb[lane]] != run.cv[lane];
+  const uint64_t fail = __ballot(bad);
   uint32_t active = 0;
   for (int t = 0; t < run.n; ++t) {
-    bool ok = true;
-    for (int c = run.t[t].c0; c < run.t[t].c1; ++c)
-      if (run.cbits[run.cb[c]] != run.cv[c]) ok = false;
-    if (ok) active |= 1u << t;
+    const uint64_t cm = ((1ull << run.t[t].c1) - 1) & ~((1ull << run.t[t].c0) - 1);
+    if (!(fail & cm)) active |= 1u << t;
   }
   if (!active) return;
-  const uint64_t j0 = sweep_block(xcd) * (kBlock * ITEMS) + threadIdx.x;
-  CV<R> x[ITEMS];
-  uint64_t idx[ITEMS];
-#pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
-    const uint64_t j = j0 + (uint64_t)it * kBlock;
-    idx[it] = insert_zeros(j, sp) | common;
-    if (j < nitems) x[it] = ld<NT>(psi + idx[it]);
+  for (int e = threadIdx.x; e < run.ng * 64; e += kBlock) {
+    const int g = e >> 6, m = e & 63;
+    double fr = 1, fi = 0;
+    for (int t = 0; t < run.n; ++t) {
+      const DiagRunTerm& T = run.t[t];
+      if (T.g != g || !((active >> t) & 1u) || (m & T.lmask) != T.lmask) continue;
+      // entries picked by selects, not by an index (no scratch copy of the terms)
+      const bool b0 = T.k > 0 && ((m >> T.l0) & 1), b1 = T.k > 1 && ((m >> T.l1) & 1);
+      const double dr = b1 ? (b0 ? T.d[6] : T.d[4]) : (b0 ? T.d[2] : T.d[0]);
+      const double di = b1 ? (b0 ? T.d[7] : T.d[5]) : (b0 ? T.d[3] : T.d[1]);
+      const double nr = fr * dr - fi * di;
+      fi = fr * di + fi * dr;
+      fr = nr;
+    }
+    CV<R> v;
+    v.x = (R)fr;
+    v.y = (R)fi;
+    tab[e] = v;
   }
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * (kBlock * ITEMS);
+  for (uint64_t j0 = sweep_block(xcd) * (kBlock * ITEMS) + threadIdx.x; j0 < nitems; j0 += stride) {
+    CV<R> x[ITEMS];
+    uint64_t idx[ITEMS];
 #pragma unroll
-  for (int it = 0; it < ITEMS; ++it) {
-    const uint64_t j = j0 + (uint64_t)it * kBlock;
-    if (j < nitems) {
-      const uint64_t i = idx[it];
-      R fr = 1, fi = 0;
-      for (int t = 0; t < run.n; ++t) {
-        const DiagRunTerm& T = run.t[t];
-        if (!((active >> t) & 1u) || (i & T.mask) != T.mask) continue;
-        // the factor is picked by selects among the term's (at most four)
-        // entries, not by an index, so nothing is staged in scratch memory
-        const bool b0 = T.k > 0 && ((i >> T.p0) & 1ull), b1 = T.k > 1 && ((i >> T.p1) & 1ull);
-        const R dr = (R)(b1 ? (b0 ? T.d[6] : T.d[4]) : (b0 ? T.d[2] : T.d[0]));
-        const R di = (R)(b1 ? (b0 ? T.d[7] : T.d[5]) : (b0 ? T.d[3] : T.d[1]));
-        const R nr = fr * dr - fi * di;
-        fi = fr * di + fi * dr;
-        fr = nr;
+    for (int it = 0; it < ITEMS; ++it) {
+      const uint64_t j = j0 + (uint64_t)it * kBlock;
+      idx[it] = insert_zeros(j, sp) | common;
+      if (j < nitems) x[it] = ld<NT>(psi + idx[it]);
+    }
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const uint64_t j = j0 + (uint64_t)it * kBlock;
+      if (j < nitems) {
+        const uint64_t i = idx[it];
+        R fr = 1, fi = 0;
+        for (int g = 0; g < run.ng; ++g) {
+          int m = 0;
+          for (int b = 0; b < run.grp[g].nb; ++b) m |= (int)((i >> run.grp[g].pos[b]) & 1ull) << b;
+          const CV<R> f = tab[g * 64 + m];
+          const R nr = fr * f.x - fi * f.y;
+          fi = fr * f.y + fi * f.x;
+          fr = nr;
+        }
+        const CV<R> p = x[it];
+        CV<R> r;
+        r.x = fr * p.x - fi * p.y;
+        r.y = fr * p.y + fi * p.x;
+        st<NT>(psi + i, r);
       }
-      const CV<R> p = x[it];
-      CV<R> r;
-      r.x = fr * p.x - fi * p.y;
-      r.y = fr * p.y + fi * p.x;
-      st<NT>(psi + i, r);
     }
   }
 }
 
 hipError_t launch_diag_run(const Launch& L, const DiagRunArgs& run, const int* common, int nc) {
-  if (run.n < 1 || run.n > kDiagRunTerms) return hipErrorInvalidValue;
+  if (run.n < 1 || run.n > kDiagRunTerms || run.ng < 1 || run.ng > kDiagRunGroups || run.ncond > kDiagRunConds)
+    return hipErrorInvalidValue;
   Special sp = make_special(common, nc, nullptr, 0);
   const uint64_t nitems = 1ull << (L.n - nc);
   const uint64_t cm = mask_of(common, nc);
   const bool nt = use_nt(L, lowest(common, nc, nullptr, 0, 64));
-  const int it = L.tune.diag_items;
-#define QK_DR(R, IT, NT)                                                                                         \
-  hipLaunchKernelGGL((k_diag_run<R, IT, NT>), dim3(grid_for(nitems, kBlock * IT)), dim3(kBlock), 0, L.stream, \
-                     (CV<R>*)L.psi, nitems, sp, cm, run, L.tune.xcd != 0)
-#define QK_DR_IT(R, NT) \
-  do { if (it == 2) QK_DR(R, 2, NT); else if (it == 4) QK_DR(R, 4, NT); else QK_DR(R, 1, NT); } while (0)
-  if (L.c64) { if (nt) QK_DR_IT(float, true); else QK_DR_IT(float, false); }
-  else { if (nt) QK_DR_IT(double, true); else QK_DR_IT(double, false); }
-#undef QK_DR_IT
-#undef QK_DR
+  // a grid of at most 16 workgroups per CU, each building its tables once and
+  // sweeping a strided share of the subspace
+  constexpr int IT = 2;
+  const unsigned g = std::min<unsigned>(grid_for(nitems, kBlock * IT), 256u * 16u);
+  if (L.c64) {
+    if (nt) hipLaunchKernelGGL((k_diag_run<float, IT, true>), dim3(g), dim3(kBlock), 0, L.stream, (CV<float>*)L.psi, nitems, sp, cm, run, L.tune.xcd != 0);
+    else hipLaunchKernelGGL((k_diag_run<float, IT, false>), dim3(g), dim3(kBlock), 0, L.stream, (CV<float>*)L.psi, nitems, sp, cm, run, L.tune.xcd != 0);
+  } else {
+    if (nt) hipLaunchKernelGGL((k_diag_run<double, IT, true>), dim3(g), dim3(kBlock), 0, L.stream, (CV<double>*)L.psi, nitems, sp, cm, run, L.tune.xcd != 0);
+    else hipLaunchKernelGGL((k_diag_run<double, IT, false>), dim3(g), dim3(kBlock), 0, L.stream, (CV<double>*)L.psi, nitems, sp, cm, run, L.tune.xcd != 0);
+  }
   return hipGetLastError();
 }
 

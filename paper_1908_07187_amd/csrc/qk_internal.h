@@ -86,26 +86,41 @@ hipError_t launch_diag(const Launch& L, const int* targets, int k, const int* co
 hipError_t launch_phase_all1(const Launch& L, const int* bits, int nb, double zr, double zi);
 hipError_t launch_swap(const Launch& L, int a, int b, const int* controls, int nc);
 
-// Consecutive diagonal gates applied in one pass.  Term t multiplies a_i by
-// d_t[m_t(i)] where every bit of mask_t is 1 in i and the term's classical
-// conditions hold (evaluated on the device); m_t(i) is the bit of i at p0
-// (k = 1), the bits at p0, p1 (k = 2), or 0 (k = 0: one factor on the mask
-// subspace).  The pass enumerates only the subspace where the `common` bits
-// (set in every term's mask) are 1.
+// Consecutive diagonal gates applied in one pass.  Term t acts on amplitude i
+// when every bit of its qubit set (targets and controls, at most 6 qubits) that
+// its mask requires is 1 and its classical conditions hold (evaluated on the
+// device); it then multiplies a_i by d_t[m_t(i)], m_t(i) being the bit of i at
+// its first target (k = 1), the bits at both targets (k = 2), or 0 (k = 0: one
+// factor on the mask subspace).  The host packs the terms into groups whose
+// qubit sets together span at most 6 bits; the kernel tabulates each group's
+// combined factor over those bits (64 entries) and multiplies an amplitude by
+// one table entry per group.  The pass enumerates only the subspace where the
+// `common` bits (required by every term) are 1.
 constexpr int kDiagRunTerms = 24;
 constexpr int kDiagRunConds = 32;
+constexpr int kDiagRunGroups = 8;
+constexpr int kDiagRunGroupBits = 6;
 struct DiagRunTerm {
-  uint64_t mask;
-  int8_t k, p0, p1;
+  uint8_t g;        // group
+  uint8_t lmask;    // group-index bits that must all be 1
+  int8_t k, l0, l1; // target count (0, 1, 2) and the targets' group-index bits
   uint8_t c0, c1;   // the term's conditions are entries [c0, c1) of the run's list
-  uint8_t pad[3];
+  uint8_t pad;
   double d[8];      // (re, im) of the factors for m = 0 .. 2^k - 1
+};
+struct DiagRunGroup {
+  int8_t nb;                        // bits spanned
+  int8_t pos[kDiagRunGroupBits];    // amplitude-index bit of group-index bit j
+  int8_t pad;
 };
 struct DiagRunArgs {
   const uint8_t* cbits;
-  int n;                          // terms
-  int cb[kDiagRunConds];          // condition: cbit index ...
-  uint8_t cv[kDiagRunConds];      // ... and the value it must hold
+  int n;                            // terms
+  int ng;                           // groups
+  int ncond;                        // conditions
+  int cb[kDiagRunConds];            // condition: cbit index ...
+  uint8_t cv[kDiagRunConds];        // ... and the value it must hold
+  DiagRunGroup grp[kDiagRunGroups];
   DiagRunTerm t[kDiagRunTerms];
 };
 hipError_t launch_diag_run(const Launch& L, const DiagRunArgs& run, const int* common, int ncommon);

@@ -230,3 +230,38 @@ def test_graph_replays_runs_with_new_cbits():
         _check(ref, s.state(), "c128")
     graph.close()
     s.close()
+
+
+def test_run_group_limit_and_wide_terms():
+    """A run whose terms need more factor-table groups than one pass holds
+    (8 groups of 6 bits) is split: ten controlled RZZ sharing four controls,
+    each on its own target pair, need one group each, so they make a pass of
+    eight and a pass of two.  A phase on 6 qubits still joins a run; one on 7
+    qubits takes its own sweep."""
+    n = 16
+    rng = rng_for(13)
+    ops = [W.add_qubits(n)]
+    for q in range(n):
+        ops.append(W.gate("H", [q]))
+    for i in range(30):
+        a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+        ops.append(W.gate("RZZ", [a, b], params=(float(rng.uniform(0, 6.28)),)))
+    ops.append(W.gate("H", [0]))
+    ctl = [0, 1, 2, 3]
+    pairs = [(4, 5), (6, 7), (8, 9), (10, 11), (12, 13), (14, 15), (4, 6), (5, 7), (8, 10), (9, 11)]
+    for a, b in pairs:
+        ops.append(W.gate("RZZ", [a, b], controls=ctl, params=(float(rng.uniform(0, 6.28)),)))
+    ops.append(W.gate("H", [0]))
+    qs = [int(x) for x in rng.permutation(n)]
+    ops.append(W.gate("PHASE", [qs[0]], controls=qs[1:6], params=(0.9,)))     # 6 qubits: joins
+    ops.append(W.gate("RZ", [qs[13]], params=(0.3,)))
+    ops.append(W.gate("PHASE", [qs[6]], controls=qs[7:13], params=(1.7,)))    # 7 qubits: alone
+    ops.append(W.gate("RZ", [qs[14]], params=(0.5,)))
+    c = W.Circuit(ops, label="run_groups")
+    ref, _, _ = oracle.run(c)
+    for dtype in ("c128", "c64"):
+        got, _, stats = _run(c, dtype, 1)
+        _check(ref, got, dtype)
+        # 30 RZZ: at least one pass; the controlled RZZ: exactly two; the
+        # 6-qubit phase with the next RZ: one
+        assert stats["fused_blocks"] >= 4, stats
