@@ -115,12 +115,14 @@ def run_c128_step(qk, prog, torch, timing):
 def kernels_only(qk, torch):
     """A short program for hardware-counter runs on 30-qubit states:
     complex128 strided-butterfly sweeps (targets 10, 17, 23, 29), diagonal
-    sweeps (RZ, RZZ), cross-lane butterflies (targets 1, 4); dense 5- and
+    sweeps (RZ, RZZ), cross-lane butterflies (targets 1, 4), one diagonal-run
+    pass (fifteen RZZ); dense 5- and
     6-qubit blocks on matrix cores (complex64) and 4- and 5-qubit blocks
     (complex128), two target sets each; and one plain copy kernel of known size
     (the 2^28-amplitude copy when a 28-qubit state grows by one qubit: 4 GiB
     read, 4 GiB written)."""
     s = qk.Sim("c128")
+    s.set_tuning("diag_runs", 0)
     s.add_qubits(30)
     for t in (10, 17, 23, 29):
         s.apply("H", [t])
@@ -128,6 +130,11 @@ def kernels_only(qk, torch):
     s.apply("RZZ", [5, 20], params=[0.4])
     s.apply("H", [1])
     s.apply("H", [4])
+    s.sync()
+    # one diagonal-run pass: fifteen RZZ on a matching of the 30 qubits
+    s.set_tuning("diag_runs", 1)
+    for a in range(15):
+        s.apply("RZZ", [a, 29 - a], params=[0.1 * (a + 1)])
     s.sync()
     s.close()
     # matrix-core blocks: random 5- and 6-qubit unitaries on scattered targets

@@ -154,6 +154,8 @@ __global__ void k_u32_zero(uint32_t* p) {
 // Measurement buffer layout (doubles): partials[2*kReduceBlocks] | result[4] |
 // log[3*kMeasLog] | log_count (uint32, in the last 8 bytes).
 constexpr size_t kMeasDoubles = 2 * kReduceBlocks + 4 + 3 * kMeasLog + 1;
+// The diagonal-run tables follow, 16-byte aligned.
+constexpr size_t kRunTableOffset = ((kMeasDoubles * sizeof(double) + 15) / 16) * 16;
 
 MeasBuffers meas_buffers(qk_sim s) {
   double* d = (double*)s->meas.p;
@@ -168,7 +170,7 @@ MeasBuffers meas_buffers(qk_sim s) {
 
 qk_status ensure_meas(qk_sim s) {
   if (s->meas.p) return QK_OK;
-  qk_status st = ensure(s, s->meas, kMeasDoubles * sizeof(double), "measurement buffers");
+  qk_status st = ensure(s, s->meas, kRunTableOffset + kDiagRunTableBytes, "measurement buffers");
   if (st) return st;
   MeasBuffers mb = meas_buffers(s);
   hipLaunchKernelGGL(k_u32_zero, dim3(1), dim3(64), 0, s->stream, mb.log_count);
@@ -514,14 +516,18 @@ uint64_t run_mask(const GateDesc& d) {
   return m;
 }
 
-// Greedy grouping of the terms' qubit sets, in gate order: a term joins the
-// first group whose bits stay within kDiagRunGroupBits, else opens a group.
-// Returns false when a term would need more than kDiagRunGroups groups.
-bool group_terms(const std::vector<GateDesc>& run, std::vector<uint64_t>& groups, std::vector<int>& of) {
+// Greedy grouping of the terms' qubit sets (without the bits in `drop`, which
+// are 1 wherever the pass acts): a term joins the first group whose bits stay
+// within kDiagRunGroupBits, else opens a group.  The terms are visited in
+// `order`.  Returns false when a term would need more than kDiagRunGroups
+// groups.
+bool group_terms(const std::vector<GateDesc>& run, uint64_t drop, const std::vector<int>& order,
+                 std::vector<uint64_t>& groups, std::vector<int>& of) {
   groups.clear();
-  of.clear();
-  for (const GateDesc& d : run) {
-    const uint64_t sq = bits_of(d.targets) | bits_of(d.controls);
+  of.assign(run.size(), 0);
+  for (int i : order) {
+    const GateDesc& d = run[i];
+    const uint64_t sq = (bits_of(d.targets) | bits_of(d.controls)) & ~drop;
     int g = 0;
     while (g < (int)groups.size() && __builtin_popcountll(groups[g] | sq) > kDiagRunGroupBits) ++g;
     if (g == (int)groups.size()) {
@@ -529,9 +535,31 @@ bool group_terms(const std::vector<GateDesc>& run, std::vector<uint64_t>& groups
       groups.push_back(0);
     }
     groups[g] |= sq;
-    of.push_back(g);
+    of[i] = g;
   }
   return true;
+}
+
+std::vector<int> gate_order(size_t n) {
+  std::vector<int> o(n);
+  for (size_t i = 0; i < n; ++i) o[i] = (int)i;
+  return o;
+}
+
+// Grouping for a pass: common bits left out, terms visited by their lowest
+// remaining bit, so that terms on the low index bits (which differ between
+// the lanes of a wave) share as few groups as possible and the other groups'
+// table reads are the same for a whole wave.  Falls back to gate order, which
+// add_to_run has checked to fit.
+void group_for_pass(const std::vector<GateDesc>& run, uint64_t common, std::vector<uint64_t>& groups,
+                    std::vector<int>& of) {
+  std::vector<int> order = gate_order(run.size());
+  auto low = [&](int i) {
+    const uint64_t sq = (bits_of(run[i].targets) | bits_of(run[i].controls)) & ~common;
+    return sq ? __builtin_ctzll(sq) : 64;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return low(a) < low(b); });
+  if (!group_terms(run, common, order, groups, of)) group_terms(run, common, gate_order(run.size()), groups, of);
 }
 
 // Rank of bit q among the set bits of u (its position in the group index).
@@ -545,7 +573,7 @@ qk_status flush_drun(qk_sim s) {
   run.swap(s->drun);
   std::vector<uint64_t> groups;
   std::vector<int> of;
-  if (run.size() > 1 && group_terms(run, groups, of)) {
+  if (run.size() > 1) {
     // amplitudes touched: the run's pass vs the gates' own sweeps
     uint64_t common = ~0ull;
     double alone = 0;
@@ -557,6 +585,7 @@ qk_status flush_drun(qk_sim s) {
     }
     const int nc = __builtin_popcountll(common);
     if (std::ldexp(1.0, s->n - nc) <= alone) {
+      group_for_pass(run, common, groups, of);
       DiagRunArgs a{};
       a.cbits = (const uint8_t*)s->cbits.p;
       a.n = (int)run.size();
@@ -573,7 +602,7 @@ qk_status flush_drun(qk_sim s) {
         DiagRunTerm& t = a.t[i];
         const uint64_t u = groups[of[i]];
         t.g = (uint8_t)of[i];
-        const uint64_t m = run_mask(d);
+        const uint64_t m = run_mask(d) & ~common;   // common bits are 1 throughout the pass
         for (int q = 0; q < 64; ++q)
           if ((m >> q) & 1) t.lmask |= (uint8_t)(1u << local_bit(u, q));
         if (d.kind == D_PHASE1 || phase_only_diag(d)) {
@@ -602,10 +631,13 @@ qk_status flush_drun(qk_sim s) {
       std::vector<int> cpos;
       for (int b = 0; b < 64; ++b)
         if ((common >> b) & 1) cpos.push_back(b);
+      qk_status st = ensure_meas(s);   // the run's tables live after the measurement buffers
+      if (st) return st;
       Launch L = make_launch(s, {});
       s->fused_blocks++;
       s->fused_gates += (int64_t)run.size();
-      return check_launch(s, launch_diag_run(L, a, cpos.data(), (int)cpos.size()), "diagonal run");
+      return check_launch(s, launch_diag_run(L, a, cpos.data(), (int)cpos.size(), (char*)s->meas.p + kRunTableOffset),
+                          "diagonal run");
     }
   }
   for (const GateDesc& d : run) {
@@ -626,7 +658,7 @@ qk_status add_to_run(qk_sim s, GateDesc&& d) {
     trial.push_back(d);
     std::vector<uint64_t> groups;
     std::vector<int> of;
-    full = !group_terms(trial, groups, of);
+    full = !group_terms(trial, 0, gate_order(trial.size()), groups, of);
   }
   if (full) {
     qk_status st = flush_drun(s);

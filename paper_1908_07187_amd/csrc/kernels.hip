@@ -3,6 +3,7 @@
 // conditions on the device first and exits uniformly when one fails, so
 // measurement outcomes steer later gates without a host round trip.
 #include <algorithm>
+#include <type_traits>
 
 #include "qk_internal.h"
 
@@ -456,17 +457,19 @@ hipError_t launch_phase_all1(const Launch& L, const int* bits, int nb, double zr
 }
 
 // ---------------------------------------------------------------- diagonal runs
-// Several diagonal gates in one pass.  Each workgroup first finds which terms
-// are active (lane c of every wave reads condition c, a ballot gathers the
-// failures), then tabulates every group's combined factor over the group's
-// bits in LDS (FP64 products, rounded once to the state's precision), and
-// sweeps its share of the amplitudes: a_i <- a_i * prod_g tab_g[bits of i on
-// group g].  A launch whose terms are all inactive exits at once.
+// Several diagonal gates in one pass, in two launches.  k_diag_run_tables
+// (one workgroup) finds which terms are active (lane c of a wave reads
+// condition c, a ballot gathers the failures) and tabulates every group's
+// combined factor over the group's bits (FP64 products, rounded once to the
+// state's precision) into a small device table, with a word that says whether
+// any term is active.  k_diag_run then sweeps the subspace like the other
+// diagonal sweeps, each workgroup with its own LDS copy of the tables:
+// a_i <- a_i * prod_g tab_g[bits of i on group g].
 
-template <typename R, int ITEMS, bool NT>
-__global__ __launch_bounds__(kBlock) void k_diag_run(CV<R>* __restrict__ psi, uint64_t nitems, Special sp,
-                                                     uint64_t common, DiagRunArgs run, bool xcd) {
-  __shared__ CV<R> tab[kDiagRunGroups * 64];
+template <typename R>
+__global__ __launch_bounds__(512) void k_diag_run_tables(CV<R>* __restrict__ tab, uint32_t* __restrict__ any,
+                                                         DiagRunArgs run) {
+  constexpr int TW = 1 << kDiagRunGroupBits;
   const int lane = threadIdx.x & 63;
   bool bad = false;
   if (lane < run.ncond) bad = run.cbits[run.cb[lane]] != run.cv[lane];
@@ -476,9 +479,9 @@ __global__ __launch_bounds__(kBlock) void k_diag_run(CV<R>* __restrict__ psi, ui
     const uint64_t cm = ((1ull << run.t[t].c1) - 1) & ~((1ull << run.t[t].c0) - 1);
     if (!(fail & cm)) active |= 1u << t;
   }
-  if (!active) return;
-  for (int e = threadIdx.x; e < run.ng * 64; e += kBlock) {
-    const int g = e >> 6, m = e & 63;
+  if (threadIdx.x == 0) *any = active;
+  for (int e = threadIdx.x; e < run.ng * TW; e += blockDim.x) {
+    const int g = e / TW, m = e % TW;
     double fr = 1, fi = 0;
     for (int t = 0; t < run.n; ++t) {
       const DiagRunTerm& T = run.t[t];
@@ -496,58 +499,139 @@ __global__ __launch_bounds__(kBlock) void k_diag_run(CV<R>* __restrict__ psi, ui
     v.y = (R)fi;
     tab[e] = v;
   }
+}
+
+constexpr int kDiagRunItems = 4;   // amplitudes per thread of the run sweep
+
+struct DiagRunGroups {
+  int ng;
+  DiagRunGroup grp[kDiagRunGroups];
+  uint8_t item[kDiagRunGroups][kDiagRunItems];   // table-index bits contributed by the item offset
+};
+
+// Table index of a group for amplitude index (lo, hi words): bit b of the
+// index is bit pos[b] of the amplitude index.  The host pads unused positions
+// with bit 63, which is 0 in every amplitude index, so the loop has a fixed
+// trip count and compiles to one bit-field extract and one shift-or per bit.
+__device__ __forceinline__ uint32_t group_index(uint32_t lo, uint32_t hi, const DiagRunGroup& gr) {
+  uint32_t m = 0;
+#pragma unroll
+  for (int b = 0; b < kDiagRunGroupBits; ++b) {
+    const int p = gr.pos[b];
+    m |= (((p < 32 ? lo : hi) >> (p & 31)) & 1u) << b;
+  }
+  return m;
+}
+
+// The same on the host, for the item offsets.
+static uint32_t group_index_host(uint64_t x, const DiagRunGroup& gr) {
+  uint32_t m = 0;
+  for (int b = 0; b < gr.nb; ++b) m |= (uint32_t)((x >> gr.pos[b]) & 1ull) << b;
+  return m;
+}
+
+static uint64_t insert_zeros_host(uint64_t x, const Special& s) {
+  for (int i = 0; i < s.n; ++i) {
+    const int p = s.pos[i];
+    x = ((x >> p) << (p + 1)) | (x & ((1ull << p) - 1));
+  }
+  return x;
+}
+
+template <typename R, int ITEMS, bool NT, int NG>
+__global__ __launch_bounds__(kBlock) void k_diag_run(CV<R>* __restrict__ psi, uint64_t nitems, Special sp,
+                                                     uint64_t common, const CV<R>* __restrict__ gtab,
+                                                     const uint32_t* __restrict__ any, DiagRunGroups gs, bool xcd) {
+  constexpr int TW = 1 << kDiagRunGroupBits;
+  constexpr int CH = kBlock * ITEMS;   // amplitudes per workgroup (a power of two)
+  __shared__ CV<R> tab[kDiagRunGroups * TW];
+  if (*any == 0) return;               // every term's conditions failed
+  for (int e = threadIdx.x; e < NG * TW; e += kBlock) tab[e] = gtab[e];
   __syncthreads();
-  const uint64_t stride = (uint64_t)gridDim.x * (kBlock * ITEMS);
-  for (uint64_t j0 = sweep_block(xcd) * (kBlock * ITEMS) + threadIdx.x; j0 < nitems; j0 += stride) {
-    CV<R> x[ITEMS];
-    uint64_t idx[ITEMS];
+  // The counter j of an amplitude splits into disjoint bit fields: the
+  // workgroup base plus thread id, and the item offset (it * kBlock); zero
+  // insertion maps each field onto its own index bits.  So a group's table
+  // index is the OR of a per-thread part and a per-item part, the latter
+  // computed on the host.
+  const uint64_t base = sweep_block(xcd) * CH;
+  const uint64_t i0 = insert_zeros(base + threadIdx.x, sp) | common;
+  const uint32_t lo = (uint32_t)i0, hi = (uint32_t)(i0 >> 32);
+  uint32_t mt[NG];
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const uint64_t j = j0 + (uint64_t)it * kBlock;
-      idx[it] = insert_zeros(j, sp) | common;
-      if (j < nitems) x[it] = ld<NT>(psi + idx[it]);
-    }
+  for (int g = 0; g < NG; ++g) mt[g] = group_index(lo, hi, gs.grp[g]);
+  CV<R> x[ITEMS];
+  uint64_t idx[ITEMS];
 #pragma unroll
-    for (int it = 0; it < ITEMS; ++it) {
-      const uint64_t j = j0 + (uint64_t)it * kBlock;
-      if (j < nitems) {
-        const uint64_t i = idx[it];
-        R fr = 1, fi = 0;
-        for (int g = 0; g < run.ng; ++g) {
-          int m = 0;
-          for (int b = 0; b < run.grp[g].nb; ++b) m |= (int)((i >> run.grp[g].pos[b]) & 1ull) << b;
-          const CV<R> f = tab[g * 64 + m];
-          const R nr = fr * f.x - fi * f.y;
-          fi = fr * f.y + fi * f.x;
-          fr = nr;
-        }
-        const CV<R> p = x[it];
-        CV<R> r;
-        r.x = fr * p.x - fi * p.y;
-        r.y = fr * p.y + fi * p.x;
-        st<NT>(psi + i, r);
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t j = base + (uint64_t)it * kBlock + threadIdx.x;
+    idx[it] = insert_zeros(j, sp) | common;
+    if (j < nitems) x[it] = ld<NT>(psi + idx[it]);
+  }
+#pragma unroll
+  for (int it = 0; it < ITEMS; ++it) {
+    const uint64_t j = base + (uint64_t)it * kBlock + threadIdx.x;
+    if (j < nitems) {
+      R fr = 1, fi = 0;
+#pragma unroll
+      for (int g = 0; g < NG; ++g) {
+        const CV<R> f = tab[g * TW + (mt[g] | gs.item[g][it])];
+        const R nr = fr * f.x - fi * f.y;
+        fi = fr * f.y + fi * f.x;
+        fr = nr;
       }
+      const CV<R> p = x[it];
+      CV<R> r;
+      r.x = fr * p.x - fi * p.y;
+      r.y = fr * p.y + fi * p.x;
+      st<NT>(psi + idx[it], r);
     }
   }
 }
 
-hipError_t launch_diag_run(const Launch& L, const DiagRunArgs& run, const int* common, int nc) {
+hipError_t launch_diag_run(const Launch& L, const DiagRunArgs& run, const int* common, int nc, void* table) {
   if (run.n < 1 || run.n > kDiagRunTerms || run.ng < 1 || run.ng > kDiagRunGroups || run.ncond > kDiagRunConds)
     return hipErrorInvalidValue;
   Special sp = make_special(common, nc, nullptr, 0);
   const uint64_t nitems = 1ull << (L.n - nc);
   const uint64_t cm = mask_of(common, nc);
   const bool nt = use_nt(L, lowest(common, nc, nullptr, 0, 64));
-  // a grid of at most 16 workgroups per CU, each building its tables once and
-  // sweeping a strided share of the subspace
-  constexpr int IT = 2;
-  const unsigned g = std::min<unsigned>(grid_for(nitems, kBlock * IT), 256u * 16u);
+  DiagRunGroups gs{};
+  gs.ng = run.ng;
+  for (int g = 0; g < run.ng; ++g) {
+    gs.grp[g] = run.grp[g];
+    for (int b = run.grp[g].nb; b < kDiagRunGroupBits; ++b) gs.grp[g].pos[b] = 63;
+    for (int it = 0; it < kDiagRunItems; ++it)
+      gs.item[g][it] = (uint8_t)group_index_host(insert_zeros_host((uint64_t)it * kBlock, sp), run.grp[g]);
+  }
+  uint32_t* any = (uint32_t*)((char*)table + kDiagRunTableBytes - 16);
+  // four amplitudes per thread: the workgroup's copy of the tables into LDS
+  // (at most 8 KiB, from L2) is shared by 1024 amplitudes
+  const unsigned grid = grid_for(nitems, kBlock * kDiagRunItems);
+  auto sweep = [&](auto tag_r, auto tag_nt, auto tag_ng) {
+    using R = decltype(tag_r);
+    constexpr bool NT = decltype(tag_nt)::value;
+    constexpr int NG = decltype(tag_ng)::value;
+    hipLaunchKernelGGL((k_diag_run<R, kDiagRunItems, NT, NG>), dim3(grid), dim3(kBlock), 0, L.stream, (CV<R>*)L.psi,
+                       nitems, sp, cm, (const CV<R>*)table, any, gs, L.tune.xcd != 0);
+  };
+  auto by_groups = [&](auto tag_r, auto tag_nt) {
+    switch (run.ng) {
+      case 1: sweep(tag_r, tag_nt, std::integral_constant<int, 1>{}); break;
+      case 2: sweep(tag_r, tag_nt, std::integral_constant<int, 2>{}); break;
+      case 3: sweep(tag_r, tag_nt, std::integral_constant<int, 3>{}); break;
+      case 4: sweep(tag_r, tag_nt, std::integral_constant<int, 4>{}); break;
+      case 5: sweep(tag_r, tag_nt, std::integral_constant<int, 5>{}); break;
+      case 6: sweep(tag_r, tag_nt, std::integral_constant<int, 6>{}); break;
+      case 7: sweep(tag_r, tag_nt, std::integral_constant<int, 7>{}); break;
+      default: sweep(tag_r, tag_nt, std::integral_constant<int, 8>{}); break;
+    }
+  };
   if (L.c64) {
-    if (nt) hipLaunchKernelGGL((k_diag_run<float, IT, true>), dim3(g), dim3(kBlock), 0, L.stream, (CV<float>*)L.psi, nitems, sp, cm, run, L.tune.xcd != 0);
-    else hipLaunchKernelGGL((k_diag_run<float, IT, false>), dim3(g), dim3(kBlock), 0, L.stream, (CV<float>*)L.psi, nitems, sp, cm, run, L.tune.xcd != 0);
+    hipLaunchKernelGGL(k_diag_run_tables<float>, dim3(1), dim3(512), 0, L.stream, (CV<float>*)table, any, run);
+    if (nt) by_groups(float{}, std::true_type{}); else by_groups(float{}, std::false_type{});
   } else {
-    if (nt) hipLaunchKernelGGL((k_diag_run<double, IT, true>), dim3(g), dim3(kBlock), 0, L.stream, (CV<double>*)L.psi, nitems, sp, cm, run, L.tune.xcd != 0);
-    else hipLaunchKernelGGL((k_diag_run<double, IT, false>), dim3(g), dim3(kBlock), 0, L.stream, (CV<double>*)L.psi, nitems, sp, cm, run, L.tune.xcd != 0);
+    hipLaunchKernelGGL(k_diag_run_tables<double>, dim3(1), dim3(512), 0, L.stream, (CV<double>*)table, any, run);
+    if (nt) by_groups(double{}, std::true_type{}); else by_groups(double{}, std::false_type{});
   }
   return hipGetLastError();
 }

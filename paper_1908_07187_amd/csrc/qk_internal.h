@@ -93,7 +93,7 @@ hipError_t launch_swap(const Launch& L, int a, int b, const int* controls, int n
 // its first target (k = 1), the bits at both targets (k = 2), or 0 (k = 0: one
 // factor on the mask subspace).  The host packs the terms into groups whose
 // qubit sets together span at most 6 bits; the kernel tabulates each group's
-// combined factor over those bits (64 entries) and multiplies an amplitude by
+// combined factor over those bits (up to 64 entries) and multiplies an amplitude by
 // one table entry per group.  The pass enumerates only the subspace where the
 // `common` bits (required by every term) are 1.
 constexpr int kDiagRunTerms = 24;
@@ -123,7 +123,11 @@ struct DiagRunArgs {
   DiagRunGroup grp[kDiagRunGroups];
   DiagRunTerm t[kDiagRunTerms];
 };
-hipError_t launch_diag_run(const Launch& L, const DiagRunArgs& run, const int* common, int ncommon);
+// Device work space of a run: the group tables (complex, the state's
+// precision, 64 entries per group) and, in its last 16 bytes, the word that
+// says whether any term is active.
+constexpr size_t kDiagRunTableBytes = (size_t)kDiagRunGroups * (1 << kDiagRunGroupBits) * 16 + 16;
+hipError_t launch_diag_run(const Launch& L, const DiagRunArgs& run, const int* common, int ncommon, void* table);
 hipError_t launch_dense_generic(const Launch& L, const int* targets, int k, const int* controls, int nc,
                                 const void* d_matrix);
 // mode 0: table d_finv; 1: affine x = Ainv (y - B) mod 2^k; 2: modular
