@@ -321,7 +321,15 @@ qk_status qk_sync(qk_sim sim);
  *                 registers, 0 (default) re-reads them from LDS per tile;
  *   "xcd"         1 (default): the per-gate sweeps renumber their workgroups
  *                 so that each of the 8 XCDs sweeps one contiguous range,
- *                 0: workgroups in launch order.
+ *                 0: workgroups in launch order;
+ *   "diag_runs"   1 (default): consecutive diagonal gates (at most 6 qubits
+ *                 each, with their own controls and cbit conditions, which
+ *                 are read on the device when the pass runs) are held back
+ *                 and applied in one pass over the subspace all of them
+ *                 require, whenever that touches no more amplitudes than one
+ *                 sweep per gate; 0: one sweep per gate.  Results agree with
+ *                 one sweep per gate up to rounding (factors multiplied in
+ *                 FP64 before one multiplication of each amplitude).
  * QK_E_ARG for an unknown key or value. */
 qk_status qk_set_tuning(qk_sim sim, const char* key, int32_t value);
 qk_status qk_get_tuning(qk_sim sim, const char* key, int32_t* value);
