@@ -2,9 +2,10 @@
 // most kmax qubits and composes each block into one dense 2^k x 2^k matrix in
 // FP64, so a run of gates costs one sweep of the state instead of one per gate.
 //
-// Grouping is greedy and commutation-aware in the only way that needs no
-// algebra: gates on disjoint qubits commute, so a gate may join the current
-// block once every earlier gate on its qubits is scheduled (plan_blocks).
+// Grouping is greedy and commutation-aware in the two ways that need no
+// algebra: gates on disjoint qubits commute, and diagonal gates commute with
+// one another, so a gate may join the current block once every earlier gate
+// on its qubits that it does not commute with is scheduled (plan_blocks).
 #include <algorithm>
 #include <cstring>
 
@@ -89,11 +90,15 @@ static void left_multiply(std::vector<cd>& b, const std::vector<int>& qubits, co
 }
 
 // Ready-frontier grouping.  A gate is ready when every earlier gate on each of
-// its qubits is already scheduled, so absorbing ready gates in any order is a
-// valid reordering (only gates on disjoint qubits are ever swapped).  A block
-// grows one ready gate at a time: gates already inside the block's qubit set
-// first, otherwise the fitting gate whose qubit set keeps the most upcoming
-// gates (within a look-ahead window) inside the block, ties to the earliest.
+// its qubits that it does not commute with is already scheduled: for a
+// non-diagonal gate that is every earlier gate on its qubits, for a diagonal
+// gate (diagonal including its controls) every earlier non-diagonal gate on
+// them, since diagonal gates commute with one another.  Absorbing ready gates
+// in any order is then a valid reordering: two gates change order only when
+// they act on disjoint qubits or are both diagonal.  A block grows one ready
+// gate at a time: gates already inside the block's qubit set first, otherwise
+// the fitting gate whose qubit set keeps the most upcoming gates (within a
+// look-ahead window) inside the block, ties to the earliest.
 std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax) {
   const int N = (int)gates.size();
   std::vector<uint64_t> gm(N, 0);
@@ -103,22 +108,31 @@ std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax) {
       gm[i] |= 1ull << q;
       nq = std::max(nq, q + 1);
     }
-  // per-qubit program-order queues of gate indices
-  std::vector<std::vector<int>> onq(nq);
+  // per-qubit program-order queues: all gates, and the non-diagonal ones
+  std::vector<std::vector<int>> onq(nq), ndq(nq);
   for (int i = 0; i < N; ++i)
-    for (int q : gates[i].qubits) onq[q].push_back(i);
-  std::vector<size_t> head(nq, 0);
+    for (int q : gates[i].qubits) {
+      onq[q].push_back(i);
+      if (!gates[i].diag) ndq[q].push_back(i);
+    }
+  std::vector<size_t> head(nq, 0), nhead(nq, 0);
   std::vector<char> done(N, 0);
+  // first unscheduled gate (all / non-diagonal) on q, or N when none is left
+  auto front = [&](int q) {
+    while (head[q] < onq[q].size() && done[onq[q][head[q]]]) ++head[q];
+    return head[q] < onq[q].size() ? onq[q][head[q]] : N;
+  };
+  auto nd_front = [&](int q) {
+    while (nhead[q] < ndq[q].size() && done[ndq[q][nhead[q]]]) ++nhead[q];
+    return nhead[q] < ndq[q].size() ? ndq[q][nhead[q]] : N;
+  };
   auto ready = [&](int i) {
     for (int q : gates[i].qubits)
-      if (onq[q][head[q]] != i) return false;
+      if (gates[i].diag ? nd_front(q) < i : front(q) != i) return false;
     return true;
   };
-  auto schedule = [&](int i) {
-    done[i] = 1;
-    for (int q : gates[i].qubits) ++head[q];
-  };
   const int kWindow = 160;
+  const int kDiagScan = 8;   // diagonal gates looked at behind the first unscheduled gate of a qubit
   std::vector<FBlock> out;
   int first = 0;   // earliest unscheduled gate
   std::vector<int> cand;
@@ -131,14 +145,24 @@ std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax) {
     uint64_t smask = 0;
     std::vector<int> members;
     while (true) {
-      // ready gates: the front gate of some qubit that is ready on all its qubits
+      // ready gates: the first unscheduled gate of some qubit, and the
+      // diagonal gates right behind it on that qubit
       cand.clear();
       for (int q = 0; q < nq; ++q) {
-        if (head[q] >= onq[q].size()) continue;
-        const int i = onq[q][head[q]];
-        if (done[i] || !ready(i)) continue;
-        if (__builtin_popcountll(smask | gm[i]) > kmax) continue;
-        if (std::find(cand.begin(), cand.end(), i) == cand.end()) cand.push_back(i);
+        if (front(q) >= N) continue;
+        int seen = 0;
+        for (size_t p = head[q]; p < onq[q].size() && seen <= kDiagScan; ++p) {
+          const int i = onq[q][p];
+          if (done[i]) continue;
+          ++seen;
+          if (seen > 1 && !gates[i].diag) break;
+          if (__builtin_popcountll(smask | gm[i]) > kmax || !ready(i)) {
+            if (!gates[i].diag) break;
+            continue;
+          }
+          if (std::find(cand.begin(), cand.end(), i) == cand.end()) cand.push_back(i);
+          if (!gates[i].diag) break;
+        }
       }
       if (cand.empty()) break;
       int pick = -1;
@@ -165,7 +189,7 @@ std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax) {
       }
       smask |= gm[pick];
       members.push_back(pick);
-      schedule(pick);
+      done[pick] = 1;
     }
     for (int q = 0; q < 64; ++q)
       if ((smask >> q) & 1) blk.qubits.push_back(q);

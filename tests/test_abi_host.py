@@ -196,6 +196,46 @@ def test_fusion_plan_equals_circuit_unitary(n, k, seed):
     assert np.max(np.abs(U - brute.circuit_unitary(c))) <= 1e-12
 
 
+@pytest.mark.parametrize("n,k", [(6, 3), (7, 4), (8, 5)])
+def test_fusion_plan_reorders_diagonal_gates_soundly(n, k):
+    """Diagonal gates may pass one another in the plan (they commute); the
+    composed blocks still equal the brute-force unitary: the QFT's CPHASE
+    chains, and a layer mixing RZZ, CPHASE with controls, RZ and dense gates
+    that share qubits with them."""
+    import math
+    import workloads as W
+    from oracle import brute
+    from paper_1908_07187_amd.batch import circuit_ops
+    rng = np.random.default_rng(n)
+    ops = [W.add_qubits(n)] + W.qft_ops(list(range(n)))
+    for _ in range(3):
+        for q in range(n):
+            a, b = (int(x) for x in rng.choice(n, 2, replace=False))
+            ops.append(W.gate("RZZ", [a, b], params=(float(rng.uniform(0, 6.28)),)))
+            ops.append(W.gate("CPHASE", [q, (q + 2) % n], controls=[(q + 1) % n], params=(float(rng.uniform(0, 6.28)),)))
+            ops.append(W.gate(("RZ", "H", "T")[q % 3], [q], params=(0.3,) if q % 3 == 0 else ()))
+    c = W.Circuit(ops, label="diag_reorder")
+    cops = circuit_ops(c)
+    blocks = qk.plan_fusion(n, cops, k, with_matrices=True)
+    assert sum(g for _, g, _ in blocks) == len(cops)
+    U = np.eye(1 << n, dtype=np.complex128)
+    for qs, _, m in blocks:
+        U = brute.embed(m, qs, [], n) @ U
+    assert np.max(np.abs(U - brute.circuit_unitary(c))) <= 1e-12
+
+
+def test_fusion_plan_quality_on_the_qft():
+    """Commuting CPHASE chains gathered into blocks: a 26-qubit QFT and its
+    inverse in at most 110 five-qubit blocks (184 when only gates on disjoint
+    qubits may pass one another)."""
+    import workloads as W
+    from paper_1908_07187_amd.batch import circuit_ops
+    c = W.c1_qft_roundtrip(n=26, seed=0)
+    blocks = qk.plan_fusion(26, circuit_ops(c), 5)
+    print(f"{len(c.gate_ops())} gates -> {len(blocks)} blocks")
+    assert len(blocks) <= 110
+
+
 def test_fusion_plan_quality_on_the_30_qubit_layers():
     """Gates per 5-qubit block on the 30-qubit layered recipe (a regression
     guard on the planner's grouping, not a correctness check)."""
