@@ -1,16 +1,22 @@
 // Batched execution: many small circuits of uneven qubit counts in one
 // persistent launch.
 //
-// Each circuit ("job") is compiled on the host into compact device op records
-// (builtin gates with their FP64 matrices, controls as a bit mask, up to two
-// classical conditions, measurements with their pre-drawn uniform).  One
-// persistent grid runs all jobs: every workgroup takes the next job from a
-// device counter (largest jobs first), builds |0...0> in LDS, applies the
-// job's ops one after another in LDS with a block barrier between ops, and
-// writes the final state and cbits to HBM.  A job's state stays in LDS for its
-// whole circuit, so a 12-qubit, 360-gate circuit costs one HBM write instead of
-// 360 sweeps and 360 launches.  Every workgroup leaves the loop once the
-// counter passes the job count.
+// Each circuit ("job") is compiled on the host into compact device records:
+// builtin gates with their FP64 matrices, controls as a bit mask, up to two
+// classical conditions, measurements with their pre-drawn uniform.  One-qubit,
+// diagonal and phase gates are packed into passes: a pass names up to three
+// target qubits and carries up to eight gates whose dense targets are among
+// them (diagonal and phase gates may act on any qubits).  One persistent grid
+// runs all jobs: every workgroup takes the next job from a device counter
+// (largest jobs first), builds |0...0> in LDS and runs the job's items one
+// after another, a barrier after each.  In a pass every thread loads the 8
+// amplitudes of its group (the 2^3 combinations of the pass's targets) from
+// LDS, applies the pass's gates in registers and stores them back, so a pass
+// costs one LDS round trip whatever its gate count; swaps and measurements
+// run over the whole LDS state.  A job's state stays in LDS for its whole
+// circuit, so a 12-qubit, 360-gate circuit costs one HBM write instead of 360
+// sweeps and 360 launches.  Every workgroup leaves the loop once the counter
+// passes the job count.
 //
 // Measurement inside a job uses the same rule as the per-gate path (FP64
 // sums, outcome 0 iff u < P0, renormalise by 1/sqrt(p_outcome)), reduced in a
@@ -29,19 +35,21 @@ using namespace qk;
 
 namespace {
 
-enum BKind { BK_U1 = 1, BK_DIAG1 = 2, BK_DIAG2 = 3, BK_PHASE = 4, BK_SWAP = 5, BK_MEAS = 6 };
+enum BKind { BK_U1 = 1, BK_DIAG1 = 2, BK_DIAG2 = 3, BK_PHASE = 4, BK_SWAP = 5, BK_MEAS = 6, BK_PASS = 7 };
 
 struct BJob {
   uint64_t state_off;   // amplitudes
-  uint32_t op_begin, op_end;
+  uint32_t op_begin, op_end;   // record range of the job's items
   int32_t n, ncbits;
   uint32_t cbit_off;
   int32_t pad;
 };
 
-// One op record, 20 dwords.  The kernel reads a record with one vector load
-// (lane w holds dword w) one op ahead of its use, so the load's latency hides
-// behind the current op and its wait does not hold up the LDS traffic.
+// One record, 20 dwords.  An item is one record (swap, measurement) or a pass
+// header followed by its gate records.  BK_PASS header: head = kind | K << 8 |
+// ngates << 16, cmask = target qubits of slots 0..K-1 (8 bits each), conds =
+// the same qubits in ascending order.  A gate inside a pass names its dense
+// target by slot (head bits 8..15), other qubits by position.
 struct BOp {
   uint32_t head;    // kind | t0 << 8 | t1 << 16 | ncond << 24
   uint32_t cmask;   // control mask (BK_PHASE: the all-ones mask of targets and controls)
@@ -51,12 +59,15 @@ struct BOp {
 };
 static_assert(sizeof(BOp) == 80, "op record layout");
 constexpr int kOpWords = (int)(sizeof(BOp) / 4);
+constexpr int kPassGates = 8;                  // gates per pass at most
+constexpr int kItemWords = 3 * 64;             // dwords an item read brings in (>= (1 + kPassGates) * kOpWords)
+static_assert((1 + kPassGates) * kOpWords <= kItemWords, "an item fits one read");
+constexpr int kPadRecords = kItemWords / kOpWords + 1;   // zero records after the last job, so item reads stay in bounds
 
 constexpr int kBatchThreads = 512;
 constexpr int kMaxJobCbits = 256;
-// Items per thread whose LDS reads are issued together.  Two keep the
-// registers low enough for every resident workgroup's waves (complex64:
-// four 512-thread workgroups per CU; complex128: two).
+// Items per thread whose LDS reads are issued together in the whole-state
+// loops (swap, measurement).
 constexpr int kBU = 2;
 
 template <typename R> struct EVb;
@@ -68,15 +79,77 @@ __device__ __forceinline__ double bwave_sum(double v) {
   return v;
 }
 
-__device__ __forceinline__ uint32_t op_word(uint32_t w, int k) { return (uint32_t)__builtin_amdgcn_readlane((int)w, k); }
-__device__ __forceinline__ double op_double(uint32_t w, int k) {
-  const uint64_t lo = op_word(w, 4 + 2 * k), hi = op_word(w, 5 + 2 * k);
+// An item's records (at most kItemWords dwords) are read from global memory
+// one item ahead, lane l of every wave holding dwords l, 64 + l and 128 + l;
+// wave 0 copies them into one of two LDS buffers before the barrier that
+// ends the current item, and the next item reads its fields from there as
+// broadcast LDS loads (all lanes read the same address).
+struct ItemRegs {
+  uint32_t w0, w1, w2;
+};
+
+__device__ __forceinline__ ItemRegs load_item(const uint32_t* __restrict__ opw, uint32_t rec, int lane) {
+  const uint32_t* p = opw + (size_t)rec * kOpWords;
+  ItemRegs it;
+  it.w0 = p[lane];
+  it.w1 = p[64 + lane];
+  it.w2 = p[128 + lane];
+  return it;
+}
+
+__device__ __forceinline__ void stage_item(uint32_t* buf, const ItemRegs& it, int lane) {
+  buf[lane] = it.w0;
+  buf[64 + lane] = it.w1;
+  buf[128 + lane] = it.w2;
+}
+
+__device__ __forceinline__ double ldbl(const uint32_t* buf, int d) {
+  const uint64_t lo = buf[d], hi = buf[d + 1];
   return __longlong_as_double((long long)(lo | (hi << 32)));
 }
+
 __device__ __forceinline__ uint32_t ins0(uint32_t p, uint32_t q) { return ((p >> q) << (q + 1)) | (p & ((1u << q) - 1)); }
 
+// LDS position of amplitude i.  A pass whose targets include the lowest
+// qubits gives consecutive lanes groups 8 (or more) amplitudes apart, all in
+// the same banks; XOR-ing the next bits into the position within a 128-byte
+// row (3 bits for 16-byte amplitudes, 4 for 8-byte) spreads them, and keeps
+// contiguous runs contiguous within each row.  A bijection on [0, 2^n).
 template <typename R>
-__global__ __launch_bounds__(kBatchThreads) void k_batch(const BJob* __restrict__ jobs, int njobs,
+__device__ __forceinline__ uint32_t swz(uint32_t i) {
+  constexpr uint32_t b = sizeof(R) == 8 ? 3 : 4, m = (1u << b) - 1;
+  return i ^ ((i >> b) & m);
+}
+
+template <typename R>
+__device__ __forceinline__ typename EVb<R>::T cmul(R ar, R ai, typename EVb<R>::T x) {
+  typename EVb<R>::T r;
+  r.x = ar * x.x - ai * x.y;
+  r.y = ar * x.y + ai * x.x;
+  return r;
+}
+
+// Pair (lo, hi) of a group under a one-qubit gate: [x_lo, x_hi] <- U [x_lo, x_hi]
+// where every control bit of the pair's index is 1.
+template <typename R>
+__device__ __forceinline__ void bfly(typename EVb<R>::T& p, typename EVb<R>::T& q, bool act, const R* u) {
+  if (!act) return;
+  typename EVb<R>::T r0, r1;
+  r0.x = u[0] * p.x - u[1] * p.y + u[2] * q.x - u[3] * q.y;
+  r0.y = u[0] * p.y + u[1] * p.x + u[2] * q.y + u[3] * q.x;
+  r1.x = u[4] * p.x - u[5] * p.y + u[6] * q.x - u[7] * q.y;
+  r1.y = u[4] * p.y + u[5] * p.x + u[6] * q.y + u[7] * q.x;
+  p = r0;
+  q = r1;
+}
+
+// Waves per SIMD to keep resident: complex128, two 512-thread workgroups per
+// CU (the most the 64 KiB states of 12-qubit jobs allow in LDS); complex64,
+// four (32 KiB states).
+template <typename R> constexpr int batch_waves_per_simd() { return sizeof(R) == 8 ? 4 : 8; }
+
+template <typename R>
+__global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_batch(const BJob* __restrict__ jobs, int njobs,
                                                          const uint32_t* __restrict__ opw,
                                                          typename EVb<R>::T* __restrict__ states,
                                                          uint8_t* __restrict__ cbits, int* counter) {
@@ -87,206 +160,218 @@ __global__ __launch_bounds__(kBatchThreads) void k_batch(const BJob* __restrict_
   __shared__ double red[2][kBatchThreads / 64];
   __shared__ double meas[2];
   __shared__ int job_sh;
+  __shared__ uint32_t items[2][kItemWords];
   const uint32_t tid = threadIdx.x, bd = blockDim.x;
   const int lane = tid & 63, w = tid >> 6;
   for (;;) {
     if (tid == 0) job_sh = atomicAdd(counter, 1);
     __syncthreads();
-    // the job (and so every op record) is the same for the whole workgroup
+    // the job (and so every record) is the same for the whole workgroup
     const int j = __builtin_amdgcn_readfirstlane(job_sh);
     if (j >= njobs) break;
     const BJob jb = jobs[j];
     const uint32_t dim = 1u << jb.n;
-    uint32_t wnext = lane < kOpWords ? opw[(size_t)jb.op_begin * kOpWords + lane] : 0u;
+    if (w == 0) stage_item(items[0], load_item(opw, jb.op_begin, lane), lane);
+    int buf = 0;
     for (uint32_t i = tid; i < dim; i += bd) {
       C z;
       z.x = (i == 0) ? (R)1 : (R)0;
       z.y = 0;
-      st[i] = z;
+      st[swz<R>(i)] = z;
     }
     for (int c = tid; c < jb.ncbits; c += bd) cb[c] = 0;
     __syncthreads();
-    for (uint32_t oi = jb.op_begin; oi < jb.op_end; ++oi) {
-      const uint32_t ow = wnext;
-      // the op array ends with one padding record, so this read stays in bounds
-      wnext = lane < kOpWords ? opw[(size_t)(oi + 1) * kOpWords + lane] : 0u;
-      const uint32_t head = op_word(ow, 0);
-      const int kind = head & 0xff, ncond = head >> 24;
-      const uint32_t t0 = (head >> 8) & 0xff, t1 = (head >> 16) & 0xff;
-      const uint32_t cm = op_word(ow, 1);
-      bool ok = true;
-      if (ncond > 0) {
-        const uint32_t cw = op_word(ow, 2);
-        if (cb[cw & 0xff] != (uint8_t)((cw >> 8) & 0xff)) ok = false;
-        if (ncond > 1 && cb[(cw >> 16) & 0xff] != (uint8_t)(cw >> 24)) ok = false;
-      }
-      if (ok) {
-        switch (kind) {
-          case BK_U1: {
-            const R a0 = (R)op_double(ow, 0), b0 = (R)op_double(ow, 1), a1 = (R)op_double(ow, 2),
-                    b1 = (R)op_double(ow, 3);
-            const R a2 = (R)op_double(ow, 4), b2 = (R)op_double(ow, 5), a3 = (R)op_double(ow, 6),
-                    b3 = (R)op_double(ow, 7);
-            const uint32_t tb = 1u << t0, half = dim >> 1;
-            for (uint32_t p0 = tid; p0 < half; p0 += kBU * bd) {
-              C x[kBU], y[kBU];
-              uint32_t ia[kBU];
+    for (uint32_t rec = jb.op_begin; rec < jb.op_end;) {
+      const uint32_t* cur = items[buf];
+      const uint32_t head = __builtin_amdgcn_readfirstlane(cur[0]);
+      const int kind = head & 0xff;
+      const int ngates = kind == BK_PASS ? (int)((head >> 16) & 0xff) : 0;
+      const uint32_t next = rec + 1 + (uint32_t)ngates;
+      ItemRegs nxt{};
+      if (w == 0) nxt = load_item(opw, next, lane);   // the record array ends with padding
+      if (kind == BK_PASS) {
+        const int K = (head >> 8) & 0xff;
+        const uint32_t tw = __builtin_amdgcn_readfirstlane(cur[1]), sw = __builtin_amdgcn_readfirstlane(cur[2]);
+        const uint32_t t0 = tw & 0xff, t1 = (tw >> 8) & 0xff, t2 = (tw >> 16) & 0xff;
+        const uint32_t p0 = sw & 0xff, p1 = (sw >> 8) & 0xff, p2 = (sw >> 16) & 0xff;
+        const int G = 1 << K;
+        const uint32_t ngroups = dim >> K;
+        for (uint32_t g = tid; g < ngroups; g += bd) {
+          uint32_t base = g;
+          if (K > 0) base = ins0(base, p0);
+          if (K > 1) base = ins0(base, p1);
+          if (K > 2) base = ins0(base, p2);
+          uint32_t idx[8];
+          C x[8];
 #pragma unroll
-              for (int k = 0; k < kBU; ++k) {
-                const uint32_t p = p0 + k * bd;
-                ia[k] = ins0(p, t0);
-                if (p < half) {
-                  x[k] = st[ia[k]];
-                  y[k] = st[ia[k] | tb];
-                }
-              }
-#pragma unroll
-              for (int k = 0; k < kBU; ++k) {
-                if (p0 + k * bd < half && (ia[k] & cm) == cm) {
-                  C r0, r1;
-                  r0.x = a0 * x[k].x - b0 * x[k].y + a1 * y[k].x - b1 * y[k].y;
-                  r0.y = a0 * x[k].y + b0 * x[k].x + a1 * y[k].y + b1 * y[k].x;
-                  r1.x = a2 * x[k].x - b2 * x[k].y + a3 * y[k].x - b3 * y[k].y;
-                  r1.y = a2 * x[k].y + b2 * x[k].x + a3 * y[k].y + b3 * y[k].x;
-                  st[ia[k]] = r0;
-                  st[ia[k] | tb] = r1;
-                }
-              }
-            }
-            break;
+          for (int r = 0; r < 8; ++r) {
+            idx[r] = base | ((uint32_t)(r & 1) << t0);
+            if (K > 1) idx[r] |= (uint32_t)((r >> 1) & 1) << t1;
+            if (K > 2) idx[r] |= (uint32_t)((r >> 2) & 1) << t2;
+            if (r < G) x[r] = st[swz<R>(idx[r])];
           }
-          case BK_DIAG1:
-          case BK_DIAG2:
-          case BK_PHASE: {
-            // BK_PHASE: one factor on the subspace where every bit of cm is 1.
-            // The four factors stay in named registers and are picked by
-            // selects (an indexed array would be placed in scratch memory).
-            const int nd = kind == BK_DIAG2 ? 4 : (kind == BK_DIAG1 ? 2 : 1);
-            const R d0r = (R)op_double(ow, 0), d0i = (R)op_double(ow, 1);
-            const R d1r = nd > 1 ? (R)op_double(ow, 2) : (R)0, d1i = nd > 1 ? (R)op_double(ow, 3) : (R)0;
-            const R d2r = nd > 2 ? (R)op_double(ow, 4) : (R)0, d2i = nd > 2 ? (R)op_double(ow, 5) : (R)0;
-            const R d3r = nd > 2 ? (R)op_double(ow, 6) : (R)0, d3i = nd > 2 ? (R)op_double(ow, 7) : (R)0;
-            const uint32_t s0 = kind == BK_PHASE ? 31u : t0, s1 = kind == BK_DIAG2 ? t1 : 31u;
-            for (uint32_t i0 = tid; i0 < dim; i0 += kBU * bd) {
-              C x[kBU];
+          for (int o = 1; o <= ngates; ++o) {
+            const uint32_t* g0 = cur + o * kOpWords;
+            const uint32_t oh = __builtin_amdgcn_readfirstlane(g0[0]);
+            const int okind = oh & 0xff, ncond = oh >> 24;
+            const uint32_t a = (oh >> 8) & 0xff, b = (oh >> 16) & 0xff;
+            if (ncond > 0) {
+              const uint32_t cw = __builtin_amdgcn_readfirstlane(g0[2]);
+              if (cb[cw & 0xff] != (uint8_t)((cw >> 8) & 0xff)) continue;
+              if (ncond > 1 && cb[(cw >> 16) & 0xff] != (uint8_t)(cw >> 24)) continue;
+            }
+            const uint32_t cm = g0[1];
+            if (okind == BK_U1) {
+              R u[8];
 #pragma unroll
-              for (int k = 0; k < kBU; ++k)
-                if (i0 + k * bd < dim) x[k] = st[i0 + k * bd];
+              for (int e = 0; e < 8; ++e) u[e] = (R)ldbl(g0, 4 + 2 * e);
+              // slot a of the group index is the target; pairs differ in that bit
+              if (a == 0) {
 #pragma unroll
-              for (int k = 0; k < kBU; ++k) {
-                const uint32_t i = i0 + k * bd;
-                if (i < dim && (i & cm) == cm) {
-                  const bool m0 = (i >> s0) & 1u, m1 = (i >> s1) & 1u;
+                for (int r = 0; r < 8; r += 2)
+                  if (r + 1 < G) bfly<R>(x[r], x[r + 1], (idx[r] & cm) == cm, u);
+              } else if (a == 1) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r)
+                  if (!(r & 2) && r + 2 < G) bfly<R>(x[r], x[r + 2], (idx[r] & cm) == cm, u);
+              } else {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                  if (r + 4 < G) bfly<R>(x[r], x[r + 4], (idx[r] & cm) == cm, u);
+              }
+            } else {
+              // BK_DIAG1 / BK_DIAG2 on qubits a (, b); BK_PHASE: one factor where
+              // every bit of cm is 1.  Factors picked by selects (no indexed array).
+              const int nd = okind == BK_DIAG2 ? 4 : (okind == BK_DIAG1 ? 2 : 1);
+              const R d0r = (R)ldbl(g0, 4), d0i = (R)ldbl(g0, 6);
+              const R d1r = nd > 1 ? (R)ldbl(g0, 8) : (R)0, d1i = nd > 1 ? (R)ldbl(g0, 10) : (R)0;
+              const R d2r = nd > 2 ? (R)ldbl(g0, 12) : (R)0, d2i = nd > 2 ? (R)ldbl(g0, 14) : (R)0;
+              const R d3r = nd > 2 ? (R)ldbl(g0, 16) : (R)0, d3i = nd > 2 ? (R)ldbl(g0, 18) : (R)0;
+              const uint32_t s0 = okind == BK_PHASE ? 31u : a, s1 = okind == BK_DIAG2 ? b : 31u;
+#pragma unroll
+              for (int r = 0; r < 8; ++r) {
+                if (r < G && (idx[r] & cm) == cm) {
+                  const bool m0 = (idx[r] >> s0) & 1u, m1 = (idx[r] >> s1) & 1u;
                   const R er = m1 ? (m0 ? d3r : d2r) : (m0 ? d1r : d0r);
                   const R ei = m1 ? (m0 ? d3i : d2i) : (m0 ? d1i : d0i);
-                  C r;
-                  r.x = er * x[k].x - ei * x[k].y;
-                  r.y = er * x[k].y + ei * x[k].x;
-                  st[i] = r;
+                  x[r] = cmul<R>(er, ei, x[r]);
                 }
               }
             }
-            break;
           }
-          case BK_SWAP: {
-            // quarter-space enumeration: bit t0 set, bit t1 clear, exchanged with the mirror
-            const uint32_t ab = 1u << t0, bb = 1u << t1, q = dim >> 2;
-            const uint32_t plo = t0 < t1 ? t0 : t1, phi = t0 < t1 ? t1 : t0;
-            for (uint32_t p0 = tid; p0 < q; p0 += kBU * bd) {
-              C x[kBU], y[kBU];
-              uint32_t ia[kBU];
 #pragma unroll
-              for (int k = 0; k < kBU; ++k) {
-                const uint32_t p = p0 + k * bd;
-                ia[k] = ins0(ins0(p, plo), phi) | ab;
-                if (p < q) {
-                  x[k] = st[ia[k]];
-                  y[k] = st[ia[k] ^ ab ^ bb];
-                }
-              }
+          for (int r = 0; r < 8; ++r)
+            if (r < G) st[swz<R>(idx[r])] = x[r];
+        }
+      } else if (kind == BK_SWAP) {
+        // quarter-space enumeration: bit t0 set, bit t1 clear, exchanged with the mirror
+        const uint32_t t0 = (head >> 8) & 0xff, t1 = (head >> 16) & 0xff, cm = __builtin_amdgcn_readfirstlane(cur[1]);
+        const uint32_t ab = 1u << t0, bb = 1u << t1, q = dim >> 2;
+        const uint32_t plo = t0 < t1 ? t0 : t1, phi = t0 < t1 ? t1 : t0;
+        bool ok = true;
+        const int ncond = head >> 24;
+        if (ncond > 0) {
+          const uint32_t cw = __builtin_amdgcn_readfirstlane(cur[2]);
+          if (cb[cw & 0xff] != (uint8_t)((cw >> 8) & 0xff)) ok = false;
+          if (ncond > 1 && cb[(cw >> 16) & 0xff] != (uint8_t)(cw >> 24)) ok = false;
+        }
+        if (ok) {
+          for (uint32_t p0 = tid; p0 < q; p0 += kBU * bd) {
+            C x[kBU], y[kBU];
+            uint32_t ia[kBU];
 #pragma unroll
-              for (int k = 0; k < kBU; ++k) {
-                if (p0 + k * bd < q && (ia[k] & cm) == cm) {
-                  st[ia[k]] = y[k];
-                  st[ia[k] ^ ab ^ bb] = x[k];
-                }
+            for (int k = 0; k < kBU; ++k) {
+              const uint32_t pp = p0 + k * bd;
+              ia[k] = ins0(ins0(pp, plo), phi) | ab;
+              if (pp < q) {
+                x[k] = st[swz<R>(ia[k])];
+                y[k] = st[swz<R>(ia[k] ^ ab ^ bb)];
               }
             }
-            break;
+#pragma unroll
+            for (int k = 0; k < kBU; ++k) {
+              if (p0 + k * bd < q && (ia[k] & cm) == cm) {
+                st[swz<R>(ia[k])] = y[k];
+                st[swz<R>(ia[k] ^ ab ^ bb)] = x[k];
+              }
+            }
           }
-          case BK_MEAS: {
-            const uint32_t qb = 1u << t0;
-            double s0 = 0, s1 = 0;
-            for (uint32_t i0 = tid; i0 < dim; i0 += kBU * bd) {
-              C x[kBU];
+        }
+      } else if (kind == BK_MEAS) {
+        const uint32_t qb = 1u << ((head >> 8) & 0xff);
+        double s0 = 0, s1 = 0;
+        for (uint32_t i0 = tid; i0 < dim; i0 += kBU * bd) {
+          C x[kBU];
 #pragma unroll
-              for (int k = 0; k < kBU; ++k)
-                if (i0 + k * bd < dim) x[k] = st[i0 + k * bd];
+          for (int k = 0; k < kBU; ++k)
+            if (i0 + k * bd < dim) x[k] = st[swz<R>(i0 + k * bd)];
 #pragma unroll
-              for (int k = 0; k < kBU; ++k) {
-                const uint32_t i = i0 + k * bd;
-                if (i < dim) {
-                  const double pr = (double)x[k].x * (double)x[k].x + (double)x[k].y * (double)x[k].y;
-                  if (i & qb) s1 += pr; else s0 += pr;
+          for (int k = 0; k < kBU; ++k) {
+            const uint32_t i = i0 + k * bd;
+            if (i < dim) {
+              const double pr = (double)x[k].x * (double)x[k].x + (double)x[k].y * (double)x[k].y;
+              if (i & qb) s1 += pr; else s0 += pr;
+            }
+          }
+        }
+        s0 = bwave_sum(s0);
+        s1 = bwave_sum(s1);
+        if (lane == 0) {
+          red[0][w] = s0;
+          red[1][w] = s1;
+        }
+        __syncthreads();
+        if (tid == 0) {
+          double q0 = 0, q1 = 0;
+          for (int k = 0; k < (int)(bd / 64); ++k) {
+            q0 += red[0][k];
+            q1 += red[1][k];
+          }
+          const double u = ldbl(cur, 4);
+          const int cbit = (int)cur[3];
+          const double P0 = q0 / (q0 + q1);
+          const int oc = (u < P0) ? 0 : 1;
+          const double po = oc ? q1 : q0;
+          meas[0] = po > 0 ? 1.0 / sqrt(po) : 0.0;
+          meas[1] = (double)oc;
+          if (cbit >= 0 && po > 0) cb[cbit] = (uint8_t)oc;
+        }
+        __syncthreads();
+        const double sc = meas[0];
+        const uint32_t oc = (uint32_t)meas[1];
+        if (sc != 0.0) {
+          const R scale = (R)sc;
+          for (uint32_t i0 = tid; i0 < dim; i0 += kBU * bd) {
+            C x[kBU];
+#pragma unroll
+            for (int k = 0; k < kBU; ++k)
+              if (i0 + k * bd < dim) x[k] = st[swz<R>(i0 + k * bd)];
+#pragma unroll
+            for (int k = 0; k < kBU; ++k) {
+              const uint32_t i = i0 + k * bd;
+              if (i < dim) {
+                C v = x[k];
+                if (((i & qb) != 0) == (oc != 0)) {
+                  v.x *= scale;
+                  v.y *= scale;
+                } else {
+                  v.x = 0;
+                  v.y = 0;
                 }
+                st[swz<R>(i)] = v;
               }
             }
-            s0 = bwave_sum(s0);
-            s1 = bwave_sum(s1);
-            if (lane == 0) {
-              red[0][w] = s0;
-              red[1][w] = s1;
-            }
-            __syncthreads();
-            if (tid == 0) {
-              double p0 = 0, p1 = 0;
-              for (int k = 0; k < (int)(bd / 64); ++k) {
-                p0 += red[0][k];
-                p1 += red[1][k];
-              }
-              const double u = op_double(ow, 0);
-              const int cbit = (int)op_word(ow, 3);
-              const double P0 = p0 / (p0 + p1);
-              const int oc = (u < P0) ? 0 : 1;
-              const double po = oc ? p1 : p0;
-              meas[0] = po > 0 ? 1.0 / sqrt(po) : 0.0;
-              meas[1] = (double)oc;
-              if (cbit >= 0 && po > 0) cb[cbit] = (uint8_t)oc;
-            }
-            __syncthreads();
-            const double sc = meas[0];
-            const uint32_t oc = (uint32_t)meas[1];
-            if (sc != 0.0) {
-              const R scale = (R)sc;
-              for (uint32_t i0 = tid; i0 < dim; i0 += kBU * bd) {
-                C x[kBU];
-#pragma unroll
-                for (int k = 0; k < kBU; ++k)
-                  if (i0 + k * bd < dim) x[k] = st[i0 + k * bd];
-#pragma unroll
-                for (int k = 0; k < kBU; ++k) {
-                  const uint32_t i = i0 + k * bd;
-                  if (i < dim) {
-                    C v = x[k];
-                    if (((i & qb) != 0) == (oc != 0)) {
-                      v.x *= scale;
-                      v.y *= scale;
-                    } else {
-                      v.x = 0;
-                      v.y = 0;
-                    }
-                    st[i] = v;
-                  }
-                }
-              }
-            }
-            break;
           }
         }
       }
+      // the next item's records into the other buffer (its last readers
+      // finished before the barrier that ended the previous item)
+      if (w == 0) stage_item(items[buf ^ 1], nxt, lane);
       __syncthreads();
+      buf ^= 1;
+      rec = next;
     }
-    for (uint32_t i = tid; i < dim; i += bd) states[jb.state_off + i] = st[i];
+    for (uint32_t i = tid; i < dim; i += bd) states[jb.state_off + i] = st[swz<R>(i)];
     for (int c = tid; c < jb.ncbits; c += bd) cbits[jb.cbit_off + c] = cb[c];
     __syncthreads();
   }
@@ -296,9 +381,61 @@ __global__ void k_zero_counter(int* c) {
   if (threadIdx.x == 0) *c = 0;
 }
 
+// Packs a job's gate records into items: one-qubit, diagonal and phase gates
+// into passes over at most three target qubits (the targets of its one-qubit
+// gates, filled up with the lowest other qubits) and at most kPassGates gates;
+// swaps and measurements stay single records.  Order is kept.
+std::vector<BOp> build_items(int n, const std::vector<BOp>& ops) {
+  const int K = std::min(3, n);
+  std::vector<BOp> out, cur;
+  std::vector<int> T;
+  auto close = [&]() {
+    if (cur.empty()) return;
+    for (int q = 0; (int)T.size() < K && q < n; ++q)
+      if (std::find(T.begin(), T.end(), q) == T.end()) T.push_back(q);
+    std::vector<int> sorted(T);
+    std::sort(sorted.begin(), sorted.end());
+    BOp h{};
+    h.head = (uint32_t)BK_PASS | ((uint32_t)K << 8) | ((uint32_t)cur.size() << 16);
+    for (int i = 0; i < K; ++i) {
+      h.cmask |= (uint32_t)T[i] << (8 * i);
+      h.conds |= (uint32_t)sorted[i] << (8 * i);
+    }
+    out.push_back(h);
+    for (BOp o : cur) {
+      if ((o.head & 0xff) == BK_U1) {
+        const int t = (o.head >> 8) & 0xff;
+        const int slot = (int)(std::find(T.begin(), T.end(), t) - T.begin());
+        o.head = (o.head & ~0xff00u) | ((uint32_t)slot << 8);
+      }
+      out.push_back(o);
+    }
+    cur.clear();
+    T.clear();
+  };
+  for (const BOp& o : ops) {
+    const int kind = o.head & 0xff;
+    if (kind == BK_SWAP || kind == BK_MEAS) {
+      close();
+      out.push_back(o);
+      continue;
+    }
+    if ((int)cur.size() == kPassGates) close();
+    if (kind == BK_U1) {
+      const int t = (o.head >> 8) & 0xff;
+      const bool in = std::find(T.begin(), T.end(), t) != T.end();
+      if (!in && (int)T.size() == K) close();
+      if (!in) T.push_back(t);
+    }
+    cur.push_back(o);
+  }
+  close();
+  return out;
+}
+
 struct HostJob {
   int n, ncbits;
-  std::vector<BOp> ops;
+  std::vector<BOp> ops;   // items (passes and single records), ready to upload
   uint64_t state_off = 0;
   uint32_t cbit_off = 0;
 };
@@ -491,6 +628,7 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
     d.head = (uint32_t)kind | ((uint32_t)t0 << 8) | ((uint32_t)t1 << 16) | ((uint32_t)o.n_conds << 24);
     hj.ops.push_back(d);
   }
+  hj.ops = build_items(n, hj.ops);
   b->jobs.push_back(std::move(hj));
   if (job) *job = (int32_t)b->jobs.size() - 1;
   b->ran = false;
@@ -565,7 +703,7 @@ qk_status qk_batch_run(qk_batch b) {
     t.cbit_off = j.cbit_off;
     table.push_back(t);
   }
-  all_ops.push_back(BOp{});   // padding record: the kernel reads one record ahead
+  all_ops.resize(all_ops.size() + kPadRecords);   // padding: the kernel reads the next item before knowing its size
   qk_status st;
   if ((st = bensure(b, b->d_states, b->states_bytes, soff * amp, "batch states"))) return st;
   if ((st = bensure(b, b->d_cbits, b->cbits_bytes, std::max<size_t>(coff, 1), "batch cbits"))) return st;
