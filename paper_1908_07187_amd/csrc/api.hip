@@ -85,6 +85,8 @@ struct qk_sim_s {
   int fuse_k = 0;
   std::vector<GateDesc> pending;
   std::vector<GateDesc> drun;       // diagonal gates held back for one combined pass (never beside `pending`)
+  std::vector<uint64_t> drun_groups;  // their factor-table groups in gate order (the fit check when adding)
+  int drun_conds = 0;               // classical conditions they carry
   Tuning tune;
   int64_t sweeps = 0, fused_blocks = 0, fused_gates = 0;
   std::string err;
@@ -549,8 +551,9 @@ std::vector<int> gate_order(size_t n) {
 // Grouping for a pass: common bits left out, terms visited by their lowest
 // remaining bit, so that terms on the low index bits (which differ between
 // the lanes of a wave) share as few groups as possible and the other groups'
-// table reads are the same for a whole wave.  Falls back to gate order, which
-// add_to_run has checked to fit.
+// table reads are the same for a whole wave.  Falls back to gate order, and
+// finally to gate order with the common bits kept, which add_to_run has
+// checked to fit (a common bit in a group only leaves half its table unused).
 void group_for_pass(const std::vector<GateDesc>& run, uint64_t common, std::vector<uint64_t>& groups,
                     std::vector<int>& of) {
   std::vector<int> order = gate_order(run.size());
@@ -559,7 +562,9 @@ void group_for_pass(const std::vector<GateDesc>& run, uint64_t common, std::vect
     return sq ? __builtin_ctzll(sq) : 64;
   };
   std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return low(a) < low(b); });
-  if (!group_terms(run, common, order, groups, of)) group_terms(run, common, gate_order(run.size()), groups, of);
+  if (group_terms(run, common, order, groups, of)) return;
+  if (group_terms(run, common, gate_order(run.size()), groups, of)) return;
+  group_terms(run, 0, gate_order(run.size()), groups, of);
 }
 
 // Rank of bit q among the set bits of u (its position in the group index).
@@ -571,6 +576,8 @@ qk_status flush_drun(qk_sim s) {
   if (s->drun.empty()) return QK_OK;
   std::vector<GateDesc> run;
   run.swap(s->drun);
+  s->drun_groups.clear();
+  s->drun_conds = 0;
   std::vector<uint64_t> groups;
   std::vector<int> of;
   if (run.size() > 1) {
@@ -647,23 +654,29 @@ qk_status flush_drun(qk_sim s) {
   return QK_OK;
 }
 
+// The group a term with qubit set sq joins under the gate-order greedy rule
+// of group_terms (an index past the end: a new group), or -1 when it would
+// need more than kDiagRunGroups groups.
+int fit_group(const std::vector<uint64_t>& groups, uint64_t sq) {
+  int g = 0;
+  while (g < (int)groups.size() && __builtin_popcountll(groups[g] | sq) > kDiagRunGroupBits) ++g;
+  return g < kDiagRunGroups ? g : -1;
+}
+
 // Appends a diagonal gate to the run, applying the run first when the new
-// gate would exceed its terms, conditions or factor-table groups.
+// gate would exceed its terms, conditions or factor-table groups.  The groups
+// are kept in step with group_terms in gate order, so the check costs no copy.
 qk_status add_to_run(qk_sim s, GateDesc&& d) {
-  int ncond = 0;
-  for (const GateDesc& g : s->drun) ncond += (int)g.conds.size();
-  bool full = (int)s->drun.size() == kDiagRunTerms || ncond + (int)d.conds.size() > kDiagRunConds;
-  if (!full) {
-    std::vector<GateDesc> trial(s->drun);
-    trial.push_back(d);
-    std::vector<uint64_t> groups;
-    std::vector<int> of;
-    full = !group_terms(trial, 0, gate_order(trial.size()), groups, of);
-  }
-  if (full) {
+  const uint64_t sq = bits_of(d.targets) | bits_of(d.controls);
+  if ((int)s->drun.size() == kDiagRunTerms || s->drun_conds + (int)d.conds.size() > kDiagRunConds ||
+      fit_group(s->drun_groups, sq) < 0) {
     qk_status st = flush_drun(s);
     if (st) return st;
   }
+  const int g = fit_group(s->drun_groups, sq);   // an empty run always fits
+  if (g == (int)s->drun_groups.size()) s->drun_groups.push_back(0);
+  s->drun_groups[g] |= sq;
+  s->drun_conds += (int)d.conds.size();
   s->drun.push_back(std::move(d));
   return QK_OK;
 }
