@@ -35,7 +35,15 @@ using namespace qk;
 
 namespace {
 
-enum BKind { BK_U1 = 1, BK_DIAG1 = 2, BK_DIAG2 = 3, BK_PHASE = 4, BK_SWAP = 5, BK_MEAS = 6, BK_PASS = 7 };
+// One-qubit dense gates come in three kinds by their matrix: BK_X (the bit
+// flip: a pair exchange, no arithmetic), BK_U1R (real entries: half the
+// multiplications), BK_U1 (general complex).
+enum BKind { BK_U1 = 1, BK_DIAG1 = 2, BK_DIAG2 = 3, BK_PHASE = 4, BK_SWAP = 5, BK_MEAS = 6, BK_PASS = 7, BK_X = 8,
+             BK_U1R = 9 };
+
+__host__ __device__ constexpr bool is_one_qubit_dense(int kind) {
+  return kind == BK_U1 || kind == BK_X || kind == BK_U1R;
+}
 
 struct BJob {
   uint64_t state_off;   // amplitudes
@@ -130,18 +138,55 @@ __device__ __forceinline__ typename EVb<R>::T cmul(R ar, R ai, typename EVb<R>::
 }
 
 // Pair (lo, hi) of a group under a one-qubit gate: [x_lo, x_hi] <- U [x_lo, x_hi]
-// where every control bit of the pair's index is 1.
-template <typename R>
-__device__ __forceinline__ void bfly(typename EVb<R>::T& p, typename EVb<R>::T& q, bool act, const R* u) {
+// where every control bit of the pair's index is 1.  KIND selects the form:
+// general complex U, real U (u holds the four real entries in u[0], u[2],
+// u[4], u[6]), or the bit flip.
+// The 2x2 matrix (re, im interleaved), passed by value so that it stays in
+// registers (a pointer to a local array puts the array in scratch memory).
+template <typename R> struct U2 {
+  R v[8];
+};
+
+template <typename R, int KIND>
+__device__ __forceinline__ void bfly(typename EVb<R>::T& p, typename EVb<R>::T& q, bool act, const U2<R> m) {
+  const R* u = m.v;
   if (!act) return;
   typename EVb<R>::T r0, r1;
-  r0.x = u[0] * p.x - u[1] * p.y + u[2] * q.x - u[3] * q.y;
-  r0.y = u[0] * p.y + u[1] * p.x + u[2] * q.y + u[3] * q.x;
-  r1.x = u[4] * p.x - u[5] * p.y + u[6] * q.x - u[7] * q.y;
-  r1.y = u[4] * p.y + u[5] * p.x + u[6] * q.y + u[7] * q.x;
+  if constexpr (KIND == BK_X) {
+    r0 = q;
+    r1 = p;
+  } else if constexpr (KIND == BK_U1R) {
+    r0.x = u[0] * p.x + u[2] * q.x;
+    r0.y = u[0] * p.y + u[2] * q.y;
+    r1.x = u[4] * p.x + u[6] * q.x;
+    r1.y = u[4] * p.y + u[6] * q.y;
+  } else {
+    r0.x = u[0] * p.x - u[1] * p.y + u[2] * q.x - u[3] * q.y;
+    r0.y = u[0] * p.y + u[1] * p.x + u[2] * q.y + u[3] * q.x;
+    r1.x = u[4] * p.x - u[5] * p.y + u[6] * q.x - u[7] * q.y;
+    r1.y = u[4] * p.y + u[5] * p.x + u[6] * q.y + u[7] * q.x;
+  }
   p = r0;
   q = r1;
 }
+
+// The pairs of a group that differ in slot `a` (the gate's target), all
+// updated by bfly<R, KIND>.  Expanded in the kernel body on the kernel's own
+// register array with constant indices: passing the array to a function (by
+// reference) made the compiler keep part of it in scratch memory.
+#define QK_PASS_GATE(KIND, U)                                                            \
+  do {                                                                                   \
+    if (a == 0) {                                                                        \
+      _Pragma("unroll") for (int r = 0; r < 8; r += 2)                                   \
+        if (r + 1 < G) bfly<R, KIND>(x[r], x[r + 1], (idx[r] & cm) == cm, U);            \
+    } else if (a == 1) {                                                                 \
+      _Pragma("unroll") for (int r = 0; r < 8; ++r)                                      \
+        if (!(r & 2) && r + 2 < G) bfly<R, KIND>(x[r], x[r + 2], (idx[r] & cm) == cm, U); \
+    } else {                                                                             \
+      _Pragma("unroll") for (int r = 0; r < 4; ++r)                                      \
+        if (r + 4 < G) bfly<R, KIND>(x[r], x[r + 4], (idx[r] & cm) == cm, U);            \
+    }                                                                                    \
+  } while (0)
 
 // Waves per SIMD to keep resident: complex128, two 512-thread workgroups per
 // CU (the most the 64 KiB states of 12-qubit jobs allow in LDS); complex64,
@@ -221,24 +266,18 @@ __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_ba
               if (ncond > 1 && cb[(cw >> 16) & 0xff] != (uint8_t)(cw >> 24)) continue;
             }
             const uint32_t cm = g0[1];
-            if (okind == BK_U1) {
-              R u[8];
+            if (okind == BK_X) {
+              QK_PASS_GATE(BK_X, U2<R>{});
+            } else if (okind == BK_U1R) {
+              U2<R> u{};
 #pragma unroll
-              for (int e = 0; e < 8; ++e) u[e] = (R)ldbl(g0, 4 + 2 * e);
-              // slot a of the group index is the target; pairs differ in that bit
-              if (a == 0) {
+              for (int e = 0; e < 8; e += 2) u.v[e] = (R)ldbl(g0, 4 + 2 * e);
+              QK_PASS_GATE(BK_U1R, u);
+            } else if (okind == BK_U1) {
+              U2<R> u;
 #pragma unroll
-                for (int r = 0; r < 8; r += 2)
-                  if (r + 1 < G) bfly<R>(x[r], x[r + 1], (idx[r] & cm) == cm, u);
-              } else if (a == 1) {
-#pragma unroll
-                for (int r = 0; r < 8; ++r)
-                  if (!(r & 2) && r + 2 < G) bfly<R>(x[r], x[r + 2], (idx[r] & cm) == cm, u);
-              } else {
-#pragma unroll
-                for (int r = 0; r < 4; ++r)
-                  if (r + 4 < G) bfly<R>(x[r], x[r + 4], (idx[r] & cm) == cm, u);
-              }
+              for (int e = 0; e < 8; ++e) u.v[e] = (R)ldbl(g0, 4 + 2 * e);
+              QK_PASS_GATE(BK_U1, u);
             } else {
               // BK_DIAG1 / BK_DIAG2 on qubits a (, b); BK_PHASE: one factor where
               // every bit of cm is 1.  Factors picked by selects (no indexed array).
@@ -403,7 +442,7 @@ std::vector<BOp> build_items(int n, const std::vector<BOp>& ops) {
     }
     out.push_back(h);
     for (BOp o : cur) {
-      if ((o.head & 0xff) == BK_U1) {
+      if (is_one_qubit_dense(o.head & 0xff)) {
         const int t = (o.head >> 8) & 0xff;
         const int slot = (int)(std::find(T.begin(), T.end(), t) - T.begin());
         o.head = (o.head & ~0xff00u) | ((uint32_t)slot << 8);
@@ -421,7 +460,7 @@ std::vector<BOp> build_items(int n, const std::vector<BOp>& ops) {
       continue;
     }
     if ((int)cur.size() == kPassGates) close();
-    if (kind == BK_U1) {
+    if (is_one_qubit_dense(kind)) {
       const int t = (o.head >> 8) & 0xff;
       const bool in = std::find(T.begin(), T.end(), t) != T.end();
       if (!in && (int)T.size() == K) close();
@@ -593,14 +632,18 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
       t0 = o.targets[0];
       t1 = arity > 1 ? o.targets[1] : 0;
       switch (g.cls) {
-        case BG_DENSE1:
-          kind = BK_U1;
+        case BG_DENSE1: {
           d.cmask = cm;
+          bool real = true;
           for (int e = 0; e < 4; ++e) {
             d.m[2 * e] = g.m[e].real();
             d.m[2 * e + 1] = g.m[e].imag();
+            real = real && g.m[e].imag() == 0.0;
           }
+          const bool flip = g.m[0] == cd(0.0) && g.m[1] == cd(1.0) && g.m[2] == cd(1.0) && g.m[3] == cd(0.0);
+          kind = flip ? BK_X : (real ? BK_U1R : BK_U1);
           break;
+        }
         case BG_DIAG:
           kind = arity == 1 ? BK_DIAG1 : BK_DIAG2;
           d.cmask = cm;
