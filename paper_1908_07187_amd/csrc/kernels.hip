@@ -344,6 +344,28 @@ __global__ __launch_bounds__(kBlock) void k_diag(CV<R>* __restrict__ psi, uint64
     idx[it] = insert_zeros(j, sp) | cmask;
     if (j < nitems) x[it] = ld<NT>(psi + idx[it]);
   }
+  if (k <= 2) {
+    // at most four factors: kept in registers and picked by selects, so no
+    // amplitude waits on a per-lane load of its factor
+    const R d0r = (R)d.v[0], d0i = (R)d.v[1], d1r = (R)d.v[2], d1i = (R)d.v[3];
+    const R d2r = (R)d.v[4], d2i = (R)d.v[5], d3r = (R)d.v[6], d3i = (R)d.v[7];
+    const int p0 = tp.p[0], p1 = k > 1 ? tp.p[1] : 63;   // bit 63 of an index is 0
+#pragma unroll
+    for (int it = 0; it < ITEMS; ++it) {
+      const uint64_t j = j0 + (uint64_t)it * kBlock;
+      if (j < nitems) {
+        const bool b0 = (idx[it] >> p0) & 1ull, b1 = (idx[it] >> p1) & 1ull;
+        const R dr = b1 ? (b0 ? d3r : d2r) : (b0 ? d1r : d0r);
+        const R di = b1 ? (b0 ? d3i : d2i) : (b0 ? d1i : d0i);
+        const CV<R> p = x[it];
+        CV<R> r;
+        r.x = dr * p.x - di * p.y;
+        r.y = dr * p.y + di * p.x;
+        st<NT>(psi + idx[it], r);
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int it = 0; it < ITEMS; ++it) {
     const uint64_t j = j0 + (uint64_t)it * kBlock;
