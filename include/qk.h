@@ -308,8 +308,9 @@ qk_status qk_sync(qk_sim sim);
  *                 sweep's accesses cover whole cache lines, 2: always;
  *   "lane_bfly"   1 (default): targets below bit 6 use the cross-lane
  *                 butterfly, 0: the strided one;
- *   "sweep_items" amplitude pairs per thread of the strided butterfly and
- *                 swap sweeps (1 default, 2, 4);
+ *   "sweep_items" amplitudes per thread of the strided butterfly, amplitude
+ *                 pairs per thread of the swap sweep (1, 2, 4; default 1
+ *                 for complex128, 2 for complex64);
  *   "diag_items"  amplitudes per thread of diagonal and phase sweeps
  *                 (1, 2, 4; default 1 for complex128, 2 for complex64);
  *   "lane_items"  64-amplitude segments per wave of the cross-lane

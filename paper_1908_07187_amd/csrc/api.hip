@@ -1034,6 +1034,7 @@ qk_status qk_create(qk_dtype dtype, const qk_allocator* alloc, void* hip_stream,
   if (s->c64) {
     s->tune.diag_items = 2;
     s->tune.lane_items = 2;
+    s->tune.sweep_items = 2;
   }
   *out = s;
   return QK_OK;

@@ -49,12 +49,12 @@ struct Diag64 {
 
 // Launch-shape choices (set per simulator; the autotuner sweeps them).  The
 // defaults are the measured best on MI355X at 30 qubits for complex128; a
-// complex64 simulator starts with diag_items = 2 and lane_items = 2 (8-byte
-// amplitudes want two per thread to keep 16 bytes per load in flight).
+// complex64 simulator starts with diag_items, lane_items and sweep_items = 2
+// (8-byte amplitudes want two per thread to keep 16 bytes per load in flight).
 struct Tuning {
   int nt = 1;            // non-temporal sweeps: 0 never, 1 when accesses cover whole lines, 2 always
   int lane_bfly = 1;     // targets below bit 6 use the cross-lane butterfly
-  int sweep_items = 1;   // pairs per thread in the strided butterfly and swap (1, 2 or 4)
+  int sweep_items = 1;   // amplitudes per thread in the strided butterfly, pairs per thread in the swap (1, 2 or 4)
   int diag_items = 1;    // amplitudes per thread in the diagonal and phase sweeps (1, 2 or 4)
   int lane_items = 1;    // 64-amplitude segments per wave in the cross-lane butterfly (1, 2 or 4)
   int mfma_waves = 8;    // waves per CU for the matrix-core kernel
