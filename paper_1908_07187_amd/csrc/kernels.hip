@@ -50,15 +50,29 @@ __device__ __forceinline__ uint64_t deposit(uint64_t m, const int* pos, int k) {
 // each XCD sweeps one contiguous eighth of the launch measured 2-8 % faster
 // for in-place sweeps of a 16 GiB state; grids whose size is not a multiple of
 // 8 keep the plain order.
+// One grid dimension holds fewer than 2^32 work-items, and a one-shot sweep of
+// 32 or more qubits needs more, so a grid of more than kGridRow workgroups is
+// laid out as rows of kGridRow (a multiple of 8, so every row starts on XCD 0)
+// and the kernels read their position in launch order with flat_block().
+constexpr uint64_t kGridRow = 1ull << 22;
+
+__device__ __forceinline__ uint64_t flat_block() { return (uint64_t)blockIdx.y * gridDim.x + blockIdx.x; }
+__device__ __forceinline__ uint64_t flat_grid() { return (uint64_t)gridDim.y * gridDim.x; }
+
 __device__ __forceinline__ uint64_t sweep_block(bool xcd) {
-  const uint64_t b = blockIdx.x, g = gridDim.x;
+  const uint64_t b = flat_block(), g = flat_grid();
   if (!xcd || (g & 7)) return b;
   return (b & 7) * (g >> 3) + (b >> 3);
 }
 
-static inline unsigned grid_for(uint64_t items, int per_block) {
-  uint64_t g = (items + per_block - 1) / per_block;
-  return (unsigned)std::max<uint64_t>(1, g);
+// Workgroups for `items` work items at `per_block` per workgroup, as rows of
+// kGridRow when there are more than that.  Workgroups past the end (at most
+// kGridRow - 1 in the last row) find no item in range and exit; every kernel
+// launched this way checks its items against the count.
+static inline dim3 grid_for(uint64_t items, int per_block) {
+  const uint64_t g = std::max<uint64_t>(1, (items + per_block - 1) / per_block);
+  if (g <= kGridRow) return dim3((unsigned)g);
+  return dim3((unsigned)kGridRow, (unsigned)((g + kGridRow - 1) / kGridRow));
 }
 
 Special make_special(const int* a, int na, const int* b, int nb, const int* c, int nc) {
@@ -101,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_copy(V2<R>* __restrict__ dst, const 
 
 hipError_t launch_fill_zero(void* p, uint64_t from, uint64_t to, bool c64, hipStream_t s) {
   if (to <= from) return hipSuccess;
-  unsigned g = std::min<unsigned>(grid_for(to - from, kBlock * 4), 65536);
+  const unsigned g = (unsigned)std::min<uint64_t>((to - from + kBlock * 4 - 1) / (kBlock * 4), 65536);
   if (c64) hipLaunchKernelGGL(k_fill_zero<float>, dim3(g), dim3(kBlock), 0, s, (float2*)p, from, to);
   else hipLaunchKernelGGL(k_fill_zero<double>, dim3(g), dim3(kBlock), 0, s, (double2*)p, from, to);
   return hipGetLastError();
@@ -115,7 +129,7 @@ hipError_t launch_set_one(void* p, uint64_t idx, bool c64, hipStream_t s) {
 
 hipError_t launch_copy(void* dst, const void* src, uint64_t count, bool c64, hipStream_t s) {
   if (!count) return hipSuccess;
-  unsigned g = std::min<unsigned>(grid_for(count, kBlock * 4), 65536);
+  const unsigned g = (unsigned)std::min<uint64_t>((count + kBlock * 4 - 1) / (kBlock * 4), 65536);
   if (c64) hipLaunchKernelGGL(k_copy<float>, dim3(g), dim3(kBlock), 0, s, (float2*)dst, (const float2*)src, count);
   else hipLaunchKernelGGL(k_copy<double>, dim3(g), dim3(kBlock), 0, s, (double2*)dst, (const double2*)src, count);
   return hipGetLastError();
@@ -257,8 +271,8 @@ __global__ __launch_bounds__(kBlock) void k_butterfly_lane(CV<R>* __restrict__ p
 template <typename R, int IT, bool NT, bool CTRL>
 static void launch_bfly_generic(const Launch& L, uint64_t npairs, const Special& sp, uint64_t cmask, uint64_t pmask,
                                 uint64_t tbit, const Mat2& u) {
-  const unsigned g = grid_for(npairs, kPairsPerBlock * IT);
-  hipLaunchKernelGGL((k_butterfly<R, IT, NT, CTRL>), dim3(g), dim3(kBlock), 0, L.stream, (CV<R>*)L.psi, npairs, sp,
+  const dim3 g = grid_for(npairs, kPairsPerBlock * IT);
+  hipLaunchKernelGGL((k_butterfly<R, IT, NT, CTRL>), g, dim3(kBlock), 0, L.stream, (CV<R>*)L.psi, npairs, sp,
                      cmask, pmask, tbit, u, L.cond, L.tune.xcd != 0);
 }
 
@@ -275,8 +289,8 @@ static void launch_bfly_items(const Launch& L, uint64_t npairs, const Special& s
 template <typename R, int IT, bool NT>
 static void launch_lane(const Launch& L, uint64_t nseg, const Special& sp, uint64_t cmask_hi, uint32_t cmask_lo, int t,
                         const Mat2& u) {
-  const unsigned g = grid_for(nseg / IT, kBlock / 64);
-  hipLaunchKernelGGL((k_butterfly_lane<R, IT, NT>), dim3(g), dim3(kBlock), 0, L.stream, (CV<R>*)L.psi, nseg, sp,
+  const dim3 g = grid_for(nseg / IT, kBlock / 64);
+  hipLaunchKernelGGL((k_butterfly_lane<R, IT, NT>), g, dim3(kBlock), 0, L.stream, (CV<R>*)L.psi, nseg, sp,
                      cmask_hi, cmask_lo, t, u, L.cond, L.tune.xcd != 0);
 }
 
@@ -393,11 +407,11 @@ template <typename R, bool NT>
 static void launch_diag_items(const Launch& L, unsigned items, uint64_t nitems, const Special& sp, uint64_t cmask,
                               int k, const Pos8& tp, const Diag64& d) {
   switch (items) {
-    case 2: hipLaunchKernelGGL((k_diag<R, 2, NT>), dim3(grid_for(nitems, kBlock * 2)), dim3(kBlock), 0, L.stream,
+    case 2: hipLaunchKernelGGL((k_diag<R, 2, NT>), grid_for(nitems, kBlock * 2), dim3(kBlock), 0, L.stream,
                                (CV<R>*)L.psi, nitems, sp, cmask, k, tp, d, L.cond, L.tune.xcd != 0); break;
-    case 4: hipLaunchKernelGGL((k_diag<R, 4, NT>), dim3(grid_for(nitems, kBlock * 4)), dim3(kBlock), 0, L.stream,
+    case 4: hipLaunchKernelGGL((k_diag<R, 4, NT>), grid_for(nitems, kBlock * 4), dim3(kBlock), 0, L.stream,
                                (CV<R>*)L.psi, nitems, sp, cmask, k, tp, d, L.cond, L.tune.xcd != 0); break;
-    default: hipLaunchKernelGGL((k_diag<R, 1, NT>), dim3(grid_for(nitems, kBlock)), dim3(kBlock), 0, L.stream,
+    default: hipLaunchKernelGGL((k_diag<R, 1, NT>), grid_for(nitems, kBlock), dim3(kBlock), 0, L.stream,
                                 (CV<R>*)L.psi, nitems, sp, cmask, k, tp, d, L.cond, L.tune.xcd != 0); break;
   }
 }
@@ -475,7 +489,7 @@ hipError_t launch_phase_all1(const Launch& L, const int* bits, int nb, double zr
   const bool nt = use_nt(L, lowest(bits, nb, nullptr, 0, 64));
   const int it = L.tune.diag_items;
 #define QK_PH(R, IT, NT)                                                                                             \
-  hipLaunchKernelGGL((k_phase_all1<R, IT, NT>), dim3(grid_for(nitems, kBlock * IT)), dim3(kBlock), 0, L.stream,   \
+  hipLaunchKernelGGL((k_phase_all1<R, IT, NT>), grid_for(nitems, kBlock * IT), dim3(kBlock), 0, L.stream,   \
                      (CV<R>*)L.psi, nitems, sp, mask, zr, zi, L.cond, L.tune.xcd != 0)
 #define QK_PH_IT(R, NT) \
   do { if (it == 2) QK_PH(R, 2, NT); else if (it == 4) QK_PH(R, 4, NT); else QK_PH(R, 1, NT); } while (0)
@@ -636,12 +650,12 @@ hipError_t launch_diag_run(const Launch& L, const DiagRunArgs& run, const int* c
   uint32_t* any = (uint32_t*)((char*)table + kDiagRunTableBytes - 16);
   // four amplitudes per thread: the workgroup's copy of the tables into LDS
   // (at most 8 KiB, from L2) is shared by 1024 amplitudes
-  const unsigned grid = grid_for(nitems, kBlock * kDiagRunItems);
+  const dim3 grid = grid_for(nitems, kBlock * kDiagRunItems);
   auto sweep = [&](auto tag_r, auto tag_nt, auto tag_ng) {
     using R = decltype(tag_r);
     constexpr bool NT = decltype(tag_nt)::value;
     constexpr int NG = decltype(tag_ng)::value;
-    hipLaunchKernelGGL((k_diag_run<R, kDiagRunItems, NT, NG>), dim3(grid), dim3(kBlock), 0, L.stream, (CV<R>*)L.psi,
+    hipLaunchKernelGGL((k_diag_run<R, kDiagRunItems, NT, NG>), grid, dim3(kBlock), 0, L.stream, (CV<R>*)L.psi,
                        nitems, sp, cm, (const CV<R>*)table, any, gs, L.tune.xcd != 0);
   };
   auto by_groups = [&](auto tag_r, auto tag_nt) {
@@ -704,7 +718,7 @@ hipError_t launch_swap(const Launch& L, int a, int b, const int* controls, int n
   const bool nt = use_nt(L, lowest(ab, 2, controls, nc, 64));
   const int it = L.tune.sweep_items;
 #define QK_SW(R, IT, NT)                                                                                           \
-  hipLaunchKernelGGL((k_swap<R, IT, NT>), dim3(grid_for(nitems, kBlock * IT)), dim3(kBlock), 0, L.stream,       \
+  hipLaunchKernelGGL((k_swap<R, IT, NT>), grid_for(nitems, kBlock * IT), dim3(kBlock), 0, L.stream,       \
                      (CV<R>*)L.psi, nitems, sp, cmask, 1ull << a, 1ull << b, L.cond, L.tune.xcd != 0)
 #define QK_SW_IT(R, NT) \
   do { if (it == 2) QK_SW(R, 2, NT); else if (it == 4) QK_SW(R, 4, NT); else QK_SW(R, 1, NT); } while (0)
@@ -729,7 +743,7 @@ __global__ __launch_bounds__(kBlock) void k_dense_generic(V2<R>* __restrict__ ps
   V2<R>* buf = reinterpret_cast<V2<R>*>(smem_raw);
   const int dimK = 1 << k;
   const int G = dimK >= kBlock ? 1 : kBlock / dimK;
-  const uint64_t g0 = (uint64_t)blockIdx.x * G;
+  const uint64_t g0 = flat_block() * G;
   for (int e = threadIdx.x; e < G * dimK; e += kBlock) {
     const uint64_t gid = g0 + (uint64_t)(e >> k);
     if (gid < ngroups) {
@@ -764,14 +778,14 @@ hipError_t launch_dense_generic(const Launch& L, const int* targets, int k, cons
   for (int j = 0; j < k; ++j) tp.p[j] = targets[j];
   const int dimK = 1 << k;
   const int G = dimK >= kBlock ? 1 : kBlock / dimK;
-  const unsigned g = grid_for(ngroups, G);
+  const dim3 g = grid_for(ngroups, G);
   const uint64_t cmask = mask_of(controls, nc);
   const size_t shm = (size_t)G * dimK * (L.c64 ? sizeof(float2) : sizeof(double2));
   if (L.c64)
-    hipLaunchKernelGGL(k_dense_generic<float>, dim3(g), dim3(kBlock), shm, L.stream, (float2*)L.psi,
+    hipLaunchKernelGGL(k_dense_generic<float>, g, dim3(kBlock), shm, L.stream, (float2*)L.psi,
                        (const float2*)d_matrix, k, ngroups, sp, cmask, tp, L.cond);
   else
-    hipLaunchKernelGGL(k_dense_generic<double>, dim3(g), dim3(kBlock), shm, L.stream, (double2*)L.psi,
+    hipLaunchKernelGGL(k_dense_generic<double>, g, dim3(kBlock), shm, L.stream, (double2*)L.psi,
                        (const double2*)d_matrix, k, ngroups, sp, cmask, tp, L.cond);
   return hipGetLastError();
 }
@@ -828,7 +842,7 @@ hipError_t launch_perm(const Launch& L, void* scratch, const int* targets, int k
     if (targets[j] != targets[0] + j) contiguous = 0;
   }
   const uint64_t tmask = mask_of(targets, k), cmask = mask_of(controls, nc);
-  const unsigned g = std::min<unsigned>(grid_for(nitems, kBlock * 4), 1u << 20);
+  const unsigned g = (unsigned)std::min<uint64_t>((nitems + kBlock * 4 - 1) / (kBlock * 4), 1u << 20);
   if (L.c64) {
     hipLaunchKernelGGL(k_perm_gather<float>, dim3(g), dim3(kBlock), 0, L.stream, (const float2*)L.psi,
                        (float2*)scratch, nitems, sp, cmask, tp, k, contiguous, tmask, d_finv, mode, A, B, Ainv, N,
@@ -978,12 +992,12 @@ hipError_t launch_measure(const Launch& L, int qubit, int cbit, double u, const 
                      forced, cbit, mb.result, mb.cbits, mb.log, mb.log_count);
   const uint64_t npairs = dim >> 1;
   constexpr int IT = 4;
-  const unsigned g = grid_for(npairs, kBlock * IT);
+  const dim3 g = grid_for(npairs, kBlock * IT);
   if (L.c64)
-    hipLaunchKernelGGL((k_collapse<float, IT>), dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi, npairs, qubit,
+    hipLaunchKernelGGL((k_collapse<float, IT>), g, dim3(kBlock), 0, L.stream, (float2*)L.psi, npairs, qubit,
                        (const double*)mb.result, L.tune.xcd != 0);
   else
-    hipLaunchKernelGGL((k_collapse<double, IT>), dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi, npairs, qubit,
+    hipLaunchKernelGGL((k_collapse<double, IT>), g, dim3(kBlock), 0, L.stream, (double2*)L.psi, npairs, qubit,
                        (const double*)mb.result, L.tune.xcd != 0);
   return hipGetLastError();
 }
