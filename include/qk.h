@@ -211,11 +211,16 @@ qk_status qk_apply_gate(qk_sim sim, qk_gate gate, const int32_t* targets, int32_
  * order, independent of other work on the device), P0 = p0 / (p0 + p1),
  * outcome = (u < P0) ? 0 : 1; kept amplitudes are scaled by 1/sqrt(p_outcome),
  * the others set to 0.  The outcome is written to cbit `cbit` on the device
- * (cbit = -1: not stored).  No host round trip. */
+ * (cbit = -1: not stored).  No host round trip.  A state of zero norm (which
+ * only qk_set_state can produce) gives outcome 1 with p0 = p1 = 0: the state
+ * stays zero, the cbit is not written and the measurement log records it.
+ * QK_E_ARG if u is not in [0, 1). */
 qk_status qk_measure(qk_sim sim, int32_t qubit, int32_t cbit, double u);
 
 /* As qk_measure with u read from device memory d_u when the step executes
- * (for captured graphs whose uniforms change between replays). */
+ * (for captured graphs whose uniforms change between replays).  The host
+ * cannot check such a draw: NaN and negative values count as 0, values at or
+ * above 1 as the largest double below 1. */
 qk_status qk_measure_dev(qk_sim sim, int32_t qubit, int32_t cbit, const double* d_u);
 
 /* Test hook: force `outcome` (0/1).  Synchronises; QK_E_STATE if the outcome

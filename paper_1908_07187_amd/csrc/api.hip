@@ -1651,9 +1651,19 @@ qk_status qk_set_state(qk_sim s, const void* host_in, size_t bytes) {
     std::vector<uint64_t> idx;
     std::vector<unsigned char> amp;
     const unsigned char* src = (const unsigned char*)host_in;
-    static const unsigned char zero16[16] = {0};
     for (uint64_t i = 0; i < (1ull << s->n); ++i) {
-      if (std::memcmp(src + i * s->amp, zero16, s->amp) == 0) continue;
+      // zero by value, so -0.0 parts count as zero too
+      bool zero;
+      if (s->c64) {
+        float v[2];
+        std::memcpy(v, src + i * 8, 8);
+        zero = v[0] == 0.0f && v[1] == 0.0f;
+      } else {
+        double v[2];
+        std::memcpy(v, src + i * 16, 16);
+        zero = v[0] == 0.0 && v[1] == 0.0;
+      }
+      if (zero) continue;
       idx.push_back(i);
       amp.insert(amp.end(), src + i * s->amp, src + (i + 1) * s->amp);
     }

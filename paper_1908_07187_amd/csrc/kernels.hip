@@ -931,7 +931,7 @@ __global__ __launch_bounds__(kBlock) void k_meas_finalize(const double* __restri
   const double p1 = block_sum(a1, sh);
   if (threadIdx.x == 0) {
     const double P0 = p0 / (p0 + p1);
-    const double uu = d_u ? *d_u : u;
+    const double uu = meas_draw(d_u ? *d_u : u);
     const int oc = forced >= 0 ? forced : ((uu < P0) ? 0 : 1);
     const double po = oc ? p1 : p0;
     const double scale = (po > 0.0) ? 1.0 / sqrt(po) : 0.0;

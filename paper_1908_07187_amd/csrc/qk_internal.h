@@ -21,6 +21,16 @@ constexpr int kBlock = 256;            // threads per block of the sweep kernels
 constexpr int kReduceBlocks = 1024;    // fixed first-level reduction grid (max)
 constexpr int kMeasLog = 4096;         // measurement log entries kept on device
 
+// A measurement draw read from device memory cannot be checked by the host:
+// NaN and negative draws count as 0, draws at or above 1 as the largest
+// double below 1.  In [0, 1) the outcome u < P0 ? 0 : 1 always has positive
+// probability when the state's norm is positive.
+__device__ __forceinline__ double meas_draw(double u) {
+  if (!(u >= 0.0)) return 0.0;
+  if (!(u < 1.0)) return 0x1.fffffffffffffp-1;
+  return u;
+}
+
 // Ascending bit positions at which zero bits are inserted into a compact
 // counter to enumerate a subspace (the positions of targets, controls and,
 // for the matrix-core kernel, column bits).

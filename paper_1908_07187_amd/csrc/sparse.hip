@@ -414,7 +414,7 @@ __global__ void k_sp_meas_finalize(const double* __restrict__ partials, int nblo
     p1 += partials[2 * b + 1];
   }
   const double P0 = p0 / (p0 + p1);
-  const double uu = d_u ? *d_u : u;
+  const double uu = meas_draw(d_u ? *d_u : u);
   const int oc = forced >= 0 ? forced : ((uu < P0) ? 0 : 1);
   const double po = oc ? p1 : p0;
   const double scale = (po > 0.0) ? 1.0 / sqrt(po) : 0.0;
