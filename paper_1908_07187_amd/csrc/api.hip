@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -182,12 +183,51 @@ qk_status ensure_meas(qk_sim s) {
 
 // ---- constant arena ----------------------------------------------------------
 
+// Pinned staging chunks are pooled for the life of the process and shared by
+// every simulator: pinning and unpinning 32 MiB per simulator cost
+// milliseconds each (up to 100 ms to unpin; 5 s of host time over 2000
+// short-lived simulators in a serving loop that creates one per job).  A chunk
+// goes back to the pool only once no copy from it can be pending (its
+// simulator's stream has drained, or the capture that staged into it never
+// ran), so the next owner may overwrite it at once.
+constexpr size_t kPinnedPoolMax = 16;
+std::mutex g_pinned_mu;
+std::vector<void*> g_pinned_free;
+
+void* pinned_take() {
+  {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    if (!g_pinned_free.empty()) {
+      void* p = g_pinned_free.back();
+      g_pinned_free.pop_back();
+      return p;
+    }
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, kArenaBytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return p;
+}
+
+void pinned_give(void* p) {
+  {
+    std::lock_guard<std::mutex> lk(g_pinned_mu);
+    if (g_pinned_free.size() < kPinnedPoolMax) {
+      g_pinned_free.push_back(p);
+      return;
+    }
+  }
+  (void)hipHostFree(p);
+}
+
 qk_status arena_new_chunk(qk_sim s) {
   Arena a;
   a.dev = dev_alloc(s, kArenaBytes);
   if (!a.dev) return fail(s, QK_E_OOM, "device allocation failed: constant arena");
-  if (hipHostMalloc(&a.host, kArenaBytes, hipHostMallocDefault) != hipSuccess) {
-    (void)hipGetLastError();
+  a.host = pinned_take();
+  if (!a.host) {
     DevBuf b{a.dev, kArenaBytes};
     dev_free(s, b);
     return fail(s, QK_E_OOM, "pinned host allocation failed: constant arena");
@@ -203,7 +243,7 @@ void arena_free_chunk(qk_sim s, Arena& a) {
     DevBuf b{a.dev, a.cap};
     dev_free(s, b);
   }
-  if (a.host) (void)hipHostFree(a.host);
+  if (a.host) pinned_give(a.host);
   a = Arena{};
 }
 
