@@ -732,8 +732,27 @@ qk_status flush_pending(qk_sim s) {
                             full_matrix(d)));
   std::vector<FBlock> blocks = plan_blocks(fg, s->fuse_k);
   const std::vector<qk_cond> none;
+  // With diagonal runs on, the gates of diagonal blocks (and diagonal gates
+  // left alone) go into the run in plan order instead of a sweep each, so
+  // consecutive ones share passes; the run is applied before any other
+  // block, which keeps the plan's order.  The run may still be open when
+  // this returns.  (Regrouping a stretch of them by a bit they share, for
+  // passes over half the state, measured slower on the QFT: the stretches
+  // between dense blocks are short, so it multiplied the passes.)
+  auto all_join = [&](const FBlock& b) {
+    if (!s->tune.diag_runs) return false;
+    for (int m : b.members)
+      if (!joins_run(pend[m])) return false;
+    return true;
+  };
   for (const FBlock& b : blocks) {
     qk_status st;
+    if ((b.diag || b.members.size() == 1) && all_join(b)) {
+      for (int m : b.members)
+        if ((st = add_to_run(s, std::move(pend[m])))) return st;
+      continue;
+    }
+    if ((st = flush_drun(s))) return st;
     if (b.members.size() == 1) {   // a block of one gate runs through that gate's own sweep
       st = execute(s, pend[b.members[0]]);
       if (st) return st;
