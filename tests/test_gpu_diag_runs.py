@@ -128,6 +128,23 @@ def test_runs_under_fusion_keep_gate_order(dtype):
     assert stats["fused_blocks"] > 0
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("k", [4, 5])
+def test_fused_qft_feeds_diagonal_blocks_to_runs(dtype, k):
+    """With fusion on, the planner's diagonal-only blocks (the QFT's CPHASE
+    chains between groups of qubits) go into diagonal runs: the result is the
+    inverse FFT of the input, and the QFT takes fewer sweeps than with each
+    diagonal block swept on its own (runs off)."""
+    n = 16
+    c = W.c1_qft_roundtrip(n=n, seed=n, roundtrip=False)
+    want = math.sqrt(1 << n) * np.fft.ifft(c.init_state)
+    got_on, _, on = _run(c, dtype, 1, fusion=k)
+    got_off, _, off = _run(c, dtype, 0, fusion=k)
+    _check(want, got_on, dtype)
+    _check(want, got_off, dtype)
+    assert on["sweeps"] < off["sweeps"], (on, off)
+
+
 @pytest.mark.parametrize("n", [10, 16])
 def test_qft_with_runs_matches_ifft(n):
     """Each target's CPHASE chain shares the target bit: one half-state pass."""
