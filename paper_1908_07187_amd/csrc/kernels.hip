@@ -885,8 +885,11 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return s;
 }
 
+// Workgroups of a fixed-order reduction: one per 2048 elements, at most
+// kReduceBlocks (so at 21 qubits the pass already spreads over 1024
+// workgroups; from 2^21 elements up the count is fixed and the order with it).
 int reduce_blocks_for(uint64_t count) {
-  uint64_t b = count / 4096;
+  uint64_t b = count / 2048;
   if (b < 1) b = 1;
   if (b > (uint64_t)kReduceBlocks) b = kReduceBlocks;
   return (int)b;
@@ -991,14 +994,20 @@ hipError_t launch_measure(const Launch& L, int qubit, int cbit, double u, const 
   hipLaunchKernelGGL(k_meas_finalize, dim3(1), dim3(kBlock), 0, L.stream, (const double*)mb.partials, nb, u, d_u,
                      forced, cbit, mb.result, mb.cbits, mb.log, mb.log_count);
   const uint64_t npairs = dim >> 1;
-  constexpr int IT = 4;
-  const dim3 g = grid_for(npairs, kBlock * IT);
-  if (L.c64)
-    hipLaunchKernelGGL((k_collapse<float, IT>), g, dim3(kBlock), 0, L.stream, (float2*)L.psi, npairs, qubit,
-                       (const double*)mb.result, L.tune.xcd != 0);
-  else
-    hipLaunchKernelGGL((k_collapse<double, IT>), g, dim3(kBlock), 0, L.stream, (double2*)L.psi, npairs, qubit,
-                       (const double*)mb.result, L.tune.xcd != 0);
+  // four pairs per thread on large states; one on small ones, where the
+  // launch would otherwise have too few workgroups to cover the latency
+  auto collapse = [&](auto tag_it) {
+    constexpr int IT = decltype(tag_it)::value;
+    const dim3 g = grid_for(npairs, kBlock * IT);
+    if (L.c64)
+      hipLaunchKernelGGL((k_collapse<float, IT>), g, dim3(kBlock), 0, L.stream, (float2*)L.psi, npairs, qubit,
+                         (const double*)mb.result, L.tune.xcd != 0);
+    else
+      hipLaunchKernelGGL((k_collapse<double, IT>), g, dim3(kBlock), 0, L.stream, (double2*)L.psi, npairs, qubit,
+                         (const double*)mb.result, L.tune.xcd != 0);
+  };
+  if (npairs >= (1ull << 24)) collapse(std::integral_constant<int, 4>{});
+  else collapse(std::integral_constant<int, 1>{});
   return hipGetLastError();
 }
 
