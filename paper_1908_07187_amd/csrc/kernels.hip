@@ -238,13 +238,21 @@ __global__ __launch_bounds__(kBlock) void k_butterfly(CV<R>* __restrict__ psi, u
 
 template <typename R, int ITEMS, bool NT>
 __global__ __launch_bounds__(kBlock) void k_butterfly_lane(CV<R>* __restrict__ psi, uint64_t nseg, Special sp,
-                                                           uint64_t cmask_hi, uint32_t cmask_lo, int t, Mat2 u,
-                                                           CondArgs cond, bool xcd) {
+                                                           uint64_t cmask_hi, uint32_t cmask_lo, uint32_t cmask_fine,
+                                                           int t, Mat2 u, CondArgs cond, bool xcd) {
   if (!conds_ok(cond)) return;
   const int lane = threadIdx.x & 63;
   const uint64_t s0 = (sweep_block(xcd) * (kBlock / 64) + (threadIdx.x >> 6)) * ITEMS;
   if (s0 >= nseg) return;   // uniform per wave
   const bool up = (lane >> t) & 1;
+  // Controls below 6 are per-lane predicates.  `touch`: the lane's
+  // amplitude is read and written at all; it fails only on controls whose
+  // runs are a 64-byte sector or more, so untouched lanes leave whole sectors
+  // alone.  Controls with shorter runs (cmask_fine) would leave sectors
+  // partly written, which costs more than writing them whole: there the lane
+  // is touched and writes its own value back.
+  const uint32_t coarse = cmask_lo & ~cmask_fine;
+  const bool touch = ((uint32_t)lane & coarse) == coarse;
   const bool act = ((uint32_t)lane & cmask_lo) == cmask_lo;
   // lower lane: u00 a + u01 b; upper lane: u11 a + u10 b (b = partner)
   const R sr = (R)(up ? u.v[6] : u.v[0]), si = (R)(up ? u.v[7] : u.v[1]);
@@ -255,7 +263,10 @@ __global__ __launch_bounds__(kBlock) void k_butterfly_lane(CV<R>* __restrict__ p
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
     addr[k] = ((insert_zeros(s0 + k, sp) << 6) | cmask_hi) + (uint64_t)lane;
-    a[k] = ld<NT>(psi + addr[k]);
+    // a lane and its partner share the control bits, so the exchange below
+    // only ever reads loaded values into lanes that act
+    a[k] = CV<R>{0, 0};
+    if (touch) a[k] = ld<NT>(psi + addr[k]);
   }
 #pragma unroll
   for (int k = 0; k < ITEMS; ++k) {
@@ -264,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_butterfly_lane(CV<R>* __restrict__ p
     CV<R> r;
     r.x = sr * a[k].x - si * a[k].y + orr * bx - oi * by;
     r.y = sr * a[k].y + si * a[k].x + orr * by + oi * bx;
-    if (act) st<NT>(psi + addr[k], r);
+    if (touch) st<NT>(psi + addr[k], act ? r : a[k]);
   }
 }
 
@@ -290,8 +301,11 @@ template <typename R, int IT, bool NT>
 static void launch_lane(const Launch& L, uint64_t nseg, const Special& sp, uint64_t cmask_hi, uint32_t cmask_lo, int t,
                         const Mat2& u) {
   const dim3 g = grid_for(nseg / IT, kBlock / 64);
+  // controls whose runs are shorter than a 64-byte sector: bits 0-1 of
+  // complex128 amplitudes, 0-2 of complex64
+  const uint32_t fine = cmask_lo & (L.c64 ? 7u : 3u);
   hipLaunchKernelGGL((k_butterfly_lane<R, IT, NT>), g, dim3(kBlock), 0, L.stream, (CV<R>*)L.psi, nseg, sp,
-                     cmask_hi, cmask_lo, t, u, L.cond, L.tune.xcd != 0);
+                     cmask_hi, cmask_lo, fine, t, u, L.cond, L.tune.xcd != 0);
 }
 
 template <typename R>
@@ -318,11 +332,16 @@ static void launch_bfly_typed(const Launch& L, int t, const int* controls, int n
     return;
   }
   // controls below the whole-line threshold become a predicate (when sweeps are non-temporal)
+  // Controls below the bit whose runs are one 128-byte line (bit 3 for
+  // complex128, 4 for complex64) become a predicate of a full sweep: skipping
+  // their complement would leave lines half written.  From that bit up they
+  // are skipped in the enumeration, whole lines at a time.
   const int thr = L.c64 ? 5 : 4;
+  const int pthr = L.c64 ? 4 : 3;
   std::vector<int> en;
   uint64_t pmask = 0;
   for (int i = 0; i < nc; ++i) {
-    if (L.tune.nt != 0 && controls[i] < thr && t >= thr) pmask |= 1ull << controls[i];
+    if (L.tune.nt != 0 && controls[i] < pthr && t >= thr) pmask |= 1ull << controls[i];
     else en.push_back(controls[i]);
   }
   const int ne = (int)en.size();

@@ -50,6 +50,36 @@ def _boundary_ok(recs):
     return all(abs(r.u - r.P0) > 1e-9 for r in recs)
 
 
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_low_controls_every_pair(dtype):
+    """Controlled one-qubit gates with the control among the six lowest bits:
+    per-lane predicates in the cross-lane kernel (targets below 6), whose
+    lanes read and write whole 64-byte sectors or skip them, and predicates
+    or skipped 128-byte lines in the strided kernel (targets 6 and up).  Every
+    (target, control) pair with control < 6, after a dense random state."""
+    rng = rng_for(91)
+    n = 12
+    ops = [W.add_qubits(n)]
+    for q in range(n):
+        ops.append(W.gate("RY", [q], params=(float(rng.uniform(0.3, 2.8)),)))
+        ops.append(W.gate("RZ", [q], params=(float(rng.uniform(0.3, 2.8)),)))
+    for c in range(6):
+        for t in list(range(6)) + [6, 8, 11]:
+            if t == c:
+                continue
+            nm = ("X", "H", "RY")[(t + c) % 3]
+            par = (float(rng.uniform(0.2, 3.0)),) if nm == "RY" else ()
+            ops.append(W.gate(nm, [t], controls=[c], params=par))
+    # two low controls at once, and a low and a high one
+    ops.append(W.gate("X", [2], controls=[0, 4]))
+    ops.append(W.gate("H", [9], controls=[1, 3]))
+    ops.append(W.gate("RY", [5], controls=[3, 10], params=(0.7,)))
+    circ = W.Circuit(ops, label="low_controls")
+    ref, _, _ = oracle.run(circ)
+    got, _, _ = _run_gpu(circ, dtype)
+    _check(ref, got, dtype)
+
+
 # ------------------------------------------------------------------ random layered circuits (12 qubits)
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
