@@ -437,9 +437,11 @@ static void launch_diag_items(const Launch& L, unsigned items, uint64_t nitems, 
 
 hipError_t launch_diag(const Launch& L, const int* targets, int k, const int* controls, int nc, const Diag64& d_in) {
   if (k > 6) return hipErrorInvalidValue;
-  // Controls below the whole-line threshold join the diagonal (entry 1 where
-  // such a control is 0), so the sweep covers whole cache lines.
-  const int thr = L.c64 ? 5 : 4;
+  // Controls whose runs are shorter than a 128-byte line (below bit 3 for
+  // complex128, 4 for complex64) join the diagonal (entry 1 where such a
+  // control is 0), so the sweep covers whole lines; from that bit up they are
+  // skipped in the enumeration, whole lines at a time.
+  const int thr = L.c64 ? 4 : 3;
   std::vector<int> tg(targets, targets + k), en, low;
   for (int i = 0; i < nc; ++i) {
     if (L.tune.nt != 0 && controls[i] < thr && k + (int)low.size() < 6) low.push_back(controls[i]);
@@ -729,7 +731,81 @@ __global__ __launch_bounds__(kBlock) void k_swap(CV<R>* __restrict__ psi, uint64
   }
 }
 
+// Uncontrolled swap with a low bit a (runs of 2^a amplitudes shorter than a
+// 128-byte line): the touched half of the state would be scattered pieces of
+// lines, so instead every amplitude is read and written once, whole lines at
+// a time, and the partners meet by a cross-lane exchange.
+// k_swap_lane_hi (b >= 6): lane l of a wave holds x = a_i and y = a_{i | 2^b}
+// for i = 64 s + l in the half where bit b is 0; the amplitude for (bit a, bit
+// b) = (1, 0) comes from the partner's y, the one for (0, 1) from its x.
+template <typename R, bool NT>
+__global__ __launch_bounds__(kBlock) void k_swap_lane_hi(CV<R>* __restrict__ psi, uint64_t nseg, Special sp, int a,
+                                                         uint64_t bbit, CondArgs cond, bool xcd) {
+  if (!conds_ok(cond)) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t s0 = sweep_block(xcd) * (kBlock / 64) + (threadIdx.x >> 6);
+  if (s0 >= nseg) return;   // uniform per wave
+  const uint64_t i = (insert_zeros(s0, sp) << 6) + (uint64_t)lane;
+  const CV<R> x = ld<NT>(psi + i), y = ld<NT>(psi + (i | bbit));
+  const int m = 1 << a;
+  CV<R> px, py;
+  px.x = __shfl_xor(x.x, m, 64);
+  px.y = __shfl_xor(x.y, m, 64);
+  py.x = __shfl_xor(y.x, m, 64);
+  py.y = __shfl_xor(y.y, m, 64);
+  const bool one = (lane >> a) & 1;
+  st<NT>(psi + i, one ? py : x);
+  st<NT>(psi + (i | bbit), one ? y : px);
+}
+
+// k_swap_lane_lo (a < b < 6): every amplitude of a 64-amplitude segment comes
+// from the lane with bits a and b exchanged.
+template <typename R, bool NT>
+__global__ __launch_bounds__(kBlock) void k_swap_lane_lo(CV<R>* __restrict__ psi, uint64_t nseg, int a, int b,
+                                                         CondArgs cond, bool xcd) {
+  if (!conds_ok(cond)) return;
+  const int lane = threadIdx.x & 63;
+  const uint64_t s0 = sweep_block(xcd) * (kBlock / 64) + (threadIdx.x >> 6);
+  if (s0 >= nseg) return;   // uniform per wave
+  const uint64_t i = (s0 << 6) + (uint64_t)lane;
+  const CV<R> x = ld<NT>(psi + i);
+  const int ba = (lane >> a) & 1, bb = (lane >> b) & 1;
+  const int src = ba == bb ? lane : lane ^ ((1 << a) | (1 << b));
+  CV<R> v;
+  v.x = __shfl(x.x, src, 64);
+  v.y = __shfl(x.y, src, 64);
+  st<NT>(psi + i, v);
+}
+
 hipError_t launch_swap(const Launch& L, int a, int b, const int* controls, int nc) {
+  if (a > b) std::swap(a, b);
+  if (nc == 0 && L.n >= 6 && a < (L.c64 ? 4 : 3)) {
+    const bool nt = L.tune.nt != 0;
+    if (b >= 6) {
+      const int hb = b - 6;
+      Special sp = make_special(&hb, 1, nullptr, 0);
+      const uint64_t nseg = 1ull << (L.n - 7);
+      const dim3 g = grid_for(nseg, kBlock / 64);
+      if (L.c64) {
+        if (nt) hipLaunchKernelGGL((k_swap_lane_hi<float, true>), g, dim3(kBlock), 0, L.stream, (CV<float>*)L.psi, nseg, sp, a, 1ull << b, L.cond, L.tune.xcd != 0);
+        else hipLaunchKernelGGL((k_swap_lane_hi<float, false>), g, dim3(kBlock), 0, L.stream, (CV<float>*)L.psi, nseg, sp, a, 1ull << b, L.cond, L.tune.xcd != 0);
+      } else {
+        if (nt) hipLaunchKernelGGL((k_swap_lane_hi<double, true>), g, dim3(kBlock), 0, L.stream, (CV<double>*)L.psi, nseg, sp, a, 1ull << b, L.cond, L.tune.xcd != 0);
+        else hipLaunchKernelGGL((k_swap_lane_hi<double, false>), g, dim3(kBlock), 0, L.stream, (CV<double>*)L.psi, nseg, sp, a, 1ull << b, L.cond, L.tune.xcd != 0);
+      }
+    } else {
+      const uint64_t nseg = 1ull << (L.n - 6);
+      const dim3 g = grid_for(nseg, kBlock / 64);
+      if (L.c64) {
+        if (nt) hipLaunchKernelGGL((k_swap_lane_lo<float, true>), g, dim3(kBlock), 0, L.stream, (CV<float>*)L.psi, nseg, a, b, L.cond, L.tune.xcd != 0);
+        else hipLaunchKernelGGL((k_swap_lane_lo<float, false>), g, dim3(kBlock), 0, L.stream, (CV<float>*)L.psi, nseg, a, b, L.cond, L.tune.xcd != 0);
+      } else {
+        if (nt) hipLaunchKernelGGL((k_swap_lane_lo<double, true>), g, dim3(kBlock), 0, L.stream, (CV<double>*)L.psi, nseg, a, b, L.cond, L.tune.xcd != 0);
+        else hipLaunchKernelGGL((k_swap_lane_lo<double, false>), g, dim3(kBlock), 0, L.stream, (CV<double>*)L.psi, nseg, a, b, L.cond, L.tune.xcd != 0);
+      }
+    }
+    return hipGetLastError();
+  }
   int ab[2] = {a, b};
   Special sp = make_special(ab, 2, controls, nc);
   const uint64_t nitems = 1ull << (L.n - 2 - nc);

@@ -51,6 +51,37 @@ def _boundary_ok(recs):
 
 
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_swaps_with_a_low_bit(dtype):
+    """Swaps whose lower bit has runs shorter than a 128-byte line go through
+    whole-line sweeps with a cross-lane exchange (partner inside the
+    64-amplitude segment, or in the other half of a high bit); every such
+    pair, a controlled one (the general kernel), and cbit-conditioned ones
+    whose condition holds or fails."""
+    rng = rng_for(93)
+    n = 11
+    ops = [W.add_qubits(n), W.add_cbits(1)]
+    for q in range(n):
+        ops.append(W.gate("RY", [q], params=(float(rng.uniform(0.3, 2.8)),)))
+        ops.append(W.gate("RZ", [q], params=(float(rng.uniform(0.3, 2.8)),)))
+    for a in range(4):
+        for b in list(range(a + 1, 6)) + [6, 9, n - 1]:
+            ops.append(W.gate("SWAP", [b, a] if (a + b) % 2 else [a, b]))
+            ops.append(W.gate("RX", [a], params=(float(rng.uniform(0.3, 2.8)),)))
+    ops.append(W.gate("SWAP", [1, 8], controls=[4]))
+    ops.append(W.gate("X", [10]))
+    ops.append(W.measure(10, cbit=0, u=0.5))          # cbit 0 <- 1
+    ops.append(W.gate("SWAP", [0, 7], conds=[(0, 1)]))
+    ops.append(W.gate("SWAP", [2, 3], conds=[(0, 1)]))
+    ops.append(W.gate("SWAP", [1, 9], conds=[(0, 0)]))  # skipped
+    ops.append(W.gate("SWAP", [0, 5], conds=[(0, 0)]))  # skipped
+    circ = W.Circuit(ops, label="low_swaps")
+    ref, rcb, _ = oracle.run(circ)
+    got, cb, _ = _run_gpu(circ, dtype)
+    assert list(cb) == list(rcb)
+    _check(ref, got, dtype)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
 def test_low_controls_every_pair(dtype):
     """Controlled one-qubit gates with the control among the six lowest bits:
     per-lane predicates in the cross-lane kernel (targets below 6), whose
