@@ -199,7 +199,14 @@ qk_status qk_define_gate_modmul(qk_sim sim, const char* name, int32_t k, uint64_
  * before the device runs it.  With fusion enabled (qk_set_fusion) an
  * unconditioned matrix gate may be held back and combined with later gates;
  * any measurement, conditioned or permutation gate, readout or qk_flush
- * first emits everything held back, in order. */
+ * first emits everything held back, in order.  On a dense state an
+ * uncontrolled, unconditioned SWAP moves no data: the simulator exchanges the
+ * two qubits' index bits in its qubit map, which every later gate and
+ * measurement goes through.  qk_get_state, qk_set_state, qk_state_ptr,
+ * qk_probabilities, sampling, inner products of two simulators, graph
+ * capture and graph launch first put the state back in logical qubit order
+ * (one physical swap per misplaced qubit); qk_norm2 and measurements do not
+ * need to (the "swap_relabel" tuning key turns this off). */
 qk_status qk_apply_gate(qk_sim sim, qk_gate gate, const int32_t* targets, int32_t n_targets,
                         const int32_t* controls, int32_t n_controls, const qk_cond* conds,
                         int32_t n_conds, const double* params, int32_t n_params);
@@ -283,7 +290,8 @@ qk_status qk_get_state(qk_sim sim, void* host_out, size_t bytes);
 /* Replace the state with host data of the same size.  Synchronises. */
 qk_status qk_set_state(qk_sim sim, const void* host_in, size_t bytes);
 
-/* Current device address and size of the state.  Valid until the next call
+/* Current device address and size of the state, in logical qubit order
+ * (relabelled qubits are put back first).  Valid until the next call
  * that adds qubits or destroys the simulator.  Emits held-back gates first. */
 qk_status qk_state_ptr(qk_sim sim, void** dev_ptr, size_t* bytes);
 
@@ -328,6 +336,9 @@ qk_status qk_sync(qk_sim sim);
  *   "xcd"         1 (default): the per-gate sweeps renumber their workgroups
  *                 so that each of the 8 XCDs sweeps one contiguous range,
  *                 0: workgroups in launch order;
+ *   "swap_relabel" 1 (default): an uncontrolled, unconditioned SWAP on a
+ *                 dense state relabels the two qubits instead of moving data
+ *                 (see qk_apply_gate); 0: every SWAP is a sweep;
  *   "diag_runs"   1 (default): consecutive diagonal gates (at most 6 qubits
  *                 each, with their own controls and cbit conditions, which
  *                 are read on the device when the pass runs) are held back

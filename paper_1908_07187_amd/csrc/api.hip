@@ -78,6 +78,7 @@ struct qk_sim_s {
   SpBufs sp;
   SpDiagRun sp_run{};               // diagonal gates held back to be applied in one pass
   std::vector<int> sp_phys;         // logical qubit -> index bit (a SWAP exchanges two entries, no data moves)
+  std::vector<int> dphys;           // the same for a dense state (identity until an uncontrolled SWAP relabels)
   int ncbits = 0;
   std::vector<Arena> arenas;        // constant chunks in use (the last one is being filled)
   std::vector<Arena> saved_arenas;  // chunks set aside while a capture owns `arenas`
@@ -411,6 +412,15 @@ CondArgs make_cond(qk_sim s, const std::vector<qk_cond>& conds) {
     c.val[i] = conds[i].value;
   }
   return c;
+}
+
+// Dense states: index bit of a logical qubit, and whether the layout is the
+// logical one.
+int dbit(qk_sim s, int q) { return q < (int)s->dphys.size() ? s->dphys[q] : q; }
+bool dense_identity(qk_sim s) {
+  for (int q = 0; q < (int)s->dphys.size(); ++q)
+    if (s->dphys[q] != q) return false;
+  return true;
 }
 
 Launch make_launch(qk_sim s, const std::vector<qk_cond>& conds) {
@@ -779,6 +789,26 @@ qk_status flush(qk_sim s) {
   qk_status st = flush_pending(s);
   if (st) return st;
   return flush_drun(s);
+}
+
+// Puts a relabelled dense state back in logical qubit order (held-back gates
+// first, as they act on the current layout): one physical swap per logical
+// qubit that is not at its own bit.
+qk_status restore_layout(qk_sim s) {
+  if (s->sparse || dense_identity(s)) return QK_OK;
+  qk_status st = flush(s);
+  if (st) return st;
+  Launch L = make_launch(s, {});
+  for (int q = 0; q < s->n; ++q) {
+    const int p = s->dphys[q];
+    if (p == q) continue;
+    int r = 0;   // the logical qubit now at bit q
+    while (s->dphys[r] != q) ++r;
+    if ((st = check_launch(s, launch_swap(L, p, q, nullptr, 0), "layout restore"))) return st;
+    s->dphys[q] = q;
+    s->dphys[r] = p;
+  }
+  return QK_OK;
 }
 
 qk_status sync_stream(qk_sim s) {
@@ -1182,6 +1212,7 @@ qk_status qk_add_qubits(qk_sim s, int32_t count, int32_t* first) {
   dev_free(s, s->state);
   dev_free(s, s->scratch);
   s->state = nb;
+  for (int q = s->n; q < nn; ++q) s->dphys.push_back(q);   // new qubits take the new high bits
   s->n = nn;
   return QK_OK;
 }
@@ -1359,9 +1390,19 @@ qk_status qk_apply_gate(qk_sim s, qk_gate gate, const int32_t* targets, int32_t 
     if (conds[i].cbit < 0 || conds[i].cbit >= s->ncbits) return fail(s, QK_E_ARG, "condition cbit out of range");
     if (conds[i].value != 0 && conds[i].value != 1) return fail(s, QK_E_ARG, "condition value must be 0 or 1");
   }
+  if (!s->sparse && bi && bi->id == QK_SWAP && nc == 0 && ncond == 0 && !s->capturing && s->tune.swap_relabel) {
+    // no data moves: later gates, measurements and readouts see the two
+    // qubits at each other's bits
+    std::swap(s->dphys[targets[0]], s->dphys[targets[1]]);
+    return QK_OK;
+  }
   d.targets.assign(targets, targets + nt);
   d.controls.assign(controls, controls + nc);
   d.conds.assign(conds, conds + ncond);
+  if (!s->sparse) {
+    for (int& q : d.targets) q = dbit(s, q);
+    for (int& q : d.controls) q = dbit(s, q);
+  }
   if (bi) {
     builtin_desc(bi->id, np ? params[0] : 0.0, d);
   } else if (ug->kind == U_MATRIX) {
@@ -1436,7 +1477,7 @@ qk_status qk_measure(qk_sim s, int32_t qubit, int32_t cbit, double u) {
                     "measure");
   }
   Launch L = make_launch(s, {});
-  hipError_t e = launch_measure(L, qubit, cbit, u, nullptr, -1, meas_buffers(s));
+  hipError_t e = launch_measure(L, dbit(s, qubit), cbit, u, nullptr, -1, meas_buffers(s));
   if (e != hipSuccess) return hip_fail(s, e, "measure");
   s->sweeps += 2;
   return QK_OK;
@@ -1457,7 +1498,7 @@ qk_status qk_measure_dev(qk_sim s, int32_t qubit, int32_t cbit, const double* d_
                     "measure");
   }
   Launch L = make_launch(s, {});
-  hipError_t e = launch_measure(L, qubit, cbit, 0.0, d_u, -1, meas_buffers(s));
+  hipError_t e = launch_measure(L, dbit(s, qubit), cbit, 0.0, d_u, -1, meas_buffers(s));
   if (e != hipSuccess) return hip_fail(s, e, "measure");
   s->sweeps += 2;
   return QK_OK;
@@ -1476,7 +1517,7 @@ qk_status qk_postselect(qk_sim s, int32_t qubit, int32_t cbit, int32_t outcome) 
   Launch L = make_launch(s, {});
   MeasBuffers mb = meas_buffers(s);
   hipError_t e = s->sparse ? sp_measure(s->sp, s->c64, sp_bit(s, qubit), cbit, 0.0, nullptr, outcome, mb, s->stream)
-                           : launch_measure(L, qubit, cbit, 0.0, nullptr, outcome, mb);
+                           : launch_measure(L, dbit(s, qubit), cbit, 0.0, nullptr, outcome, mb);
   if (e != hipSuccess) return hip_fail(s, e, "postselect");
   double res[4];
   e = hipMemcpyAsync(res, mb.result, sizeof res, hipMemcpyDeviceToHost, s->stream);
@@ -1557,6 +1598,7 @@ static qk_status sample_common(qk_sim s, const int32_t* qubits, int32_t nq, int6
   }
   if ((st = flush(s))) return st;
   if (s->sparse && (st = sp_normalize(s))) return st;   // the CDF runs in logical index order
+  if ((st = restore_layout(s))) return st;
   return ensure(s, s->samp, need, "sampling work space");
 }
 
@@ -1640,6 +1682,7 @@ qk_status qk_probabilities(qk_sim s, const int32_t* qubits, int32_t nq, double* 
   if (st) return st;
   if (!out) return fail(s, QK_E_ARG, "out is NULL");
   if ((st = flush(s))) return st;
+  if ((st = restore_layout(s))) return st;
   const MarginalLayout ml = marginal_layout(s->n, nq);
   const size_t need = (ml.partial_doubles + ml.nrows) * sizeof(double);
   if ((st = ensure(s, s->samp, std::max(need, sample_layout(s->n).doubles * sizeof(double)), "distribution work space")))
@@ -1694,6 +1737,7 @@ qk_status qk_get_state(qk_sim s, void* host_out, size_t bytes) {
   if (!host_out || bytes != need) return fail(s, QK_E_ARG, "buffer size must be 2^n * amplitude size");
   if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
   qk_status st = flush(s);
+  if (!st) st = restore_layout(s);
   if (st) return st;
   hipError_t e = hipMemcpyAsync(host_out, s->state.p, need, hipMemcpyDeviceToHost, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "get_state");
@@ -1745,6 +1789,7 @@ qk_status qk_set_state(qk_sim s, const void* host_in, size_t bytes) {
   if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
   qk_status st = flush(s);
   if (st) return st;
+  for (int q = 0; q < s->n; ++q) s->dphys[q] = q;   // the new data is in logical order
   hipError_t e = hipMemcpyAsync(s->state.p, host_in, need, hipMemcpyHostToDevice, s->stream);
   if (e != hipSuccess) return hip_fail(s, e, "set_state");
   return sync_stream(s);
@@ -1754,6 +1799,7 @@ qk_status qk_state_ptr(qk_sim s, void** dev_ptr, size_t* bytes) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
   if (s->sparse) return fail(s, QK_E_UNSUPPORTED, "a sparse state has no dense vector");
   qk_status st = flush(s);
+  if (!st) st = restore_layout(s);
   if (st) return st;
   if (dev_ptr) *dev_ptr = s->state.p;
   if (bytes) *bytes = s->state.p ? ((size_t)1 << s->n) * s->amp : 0;
@@ -1810,6 +1856,9 @@ qk_status qk_inner_product(qk_sim a, qk_sim b, double* re, double* im) {
   if (a->capturing || b->capturing) return fail(a, QK_E_STATE, "not allowed while capturing a graph");
   qk_status st = flush(a);
   if (!st) st = flush(b);
+  // two states are compared index by index in logical order (a norm needs no order)
+  if (!st && b != a) st = restore_layout(a);
+  if (!st && b != a) st = restore_layout(b);
   if (st) return st;
   if (b != a && (st = sync_stream(b))) return st;
   if ((st = ensure_meas(a))) return st;
@@ -1862,6 +1911,7 @@ qk_status qk_reset(qk_sim s) {
     const uint64_t dim = 1ull << s->n;
     e = launch_fill_zero(s->state.p, 0, dim, s->c64, s->stream);
     if (e == hipSuccess) e = launch_set_one(s->state.p, 0, s->c64, s->stream);
+    for (int q = 0; q < s->n; ++q) s->dphys[q] = q;
   }
   if (e == hipSuccess && s->ncbits > 0) {
     hipLaunchKernelGGL(k_u8_fill, dim3(std::max<size_t>(1, std::min<size_t>(1024, (s->ncbits + 255) / 256))),
@@ -1879,6 +1929,8 @@ qk_status qk_capture_begin(qk_sim s) {
   if (!s->state.p) return fail(s, QK_E_STATE, "add qubits before capturing");
   qk_status st = flush(s);
   if (st) return st;
+  // a replay starts from the logical layout (swaps inside a capture move data)
+  if ((st = restore_layout(s))) return st;
   // everything a replay touches is allocated now, outside the capture
   if ((st = ensure_meas(s))) return st;
   bool perms = false;
@@ -1936,6 +1988,7 @@ qk_status qk_graph_launch(qk_graph g) {
   if (!g) return fail(nullptr, QK_E_ARG, "graph is NULL");
   if (g->sim->capturing) return fail(g->sim, QK_E_STATE, "not allowed while capturing a graph");
   qk_status st = flush(g->sim);
+  if (!st) st = restore_layout(g->sim);   // the graph was recorded in the logical layout
   if (st) return st;
   hipError_t e = hipGraphLaunch(g->exec, g->sim->stream);
   if (e != hipSuccess) return hip_fail(g->sim, e, "graph launch");
@@ -2053,6 +2106,9 @@ qk_status qk_set_tuning(qk_sim s, const char* key, int32_t value) {
     qk_status st = flush(s);
     if (st) return st;
     s->tune.diag_runs = value;
+  } else if (k == "swap_relabel") {
+    if (value != 0 && value != 1) return fail(s, QK_E_ARG, "swap_relabel must be 0 or 1");
+    s->tune.swap_relabel = value;   // qubits already relabelled stay so (every gate goes through the map)
   } else if (k == "xcd") {
     s->tune.xcd = value != 0;
   } else if (k == "mfma_cols") {
@@ -2079,6 +2135,7 @@ qk_status qk_get_tuning(qk_sim s, const char* key, int32_t* value) {
   else if (k == "mfma_cols") *value = s->tune.mfma_cols;
   else if (k == "mfma_areg") *value = s->tune.mfma_areg;
   else if (k == "diag_runs") *value = s->tune.diag_runs;
+  else if (k == "swap_relabel") *value = s->tune.swap_relabel;
   else if (k == "xcd") *value = s->tune.xcd;
   else return fail(s, QK_E_ARG, "unknown tuning key " + k);
   return QK_OK;

@@ -72,6 +72,7 @@ struct Tuning {
   int mfma_areg = 0;     // blocks of 5-6 qubits: 1 keeps the A fragments in registers, 0 re-reads them from LDS
   int xcd = 1;           // sweeps: 1 renumbers workgroups so each XCD sweeps a contiguous range
   int diag_runs = 1;     // 1: consecutive diagonal gates are held back and applied in one pass
+  int swap_relabel = 1;  // 1: an uncontrolled SWAP on a dense state relabels the two qubits instead of moving data
 };
 
 // Where device work goes and what it works on.

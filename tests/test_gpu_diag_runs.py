@@ -47,6 +47,17 @@ def _run(circ, dtype, runs, fusion=0):
     return st, cb, stats
 
 
+def _run_tuned(circ, dtype, tuning, fusion=0):
+    import paper_1908_07187_amd as qk
+    print(f"[gpu-diag-runs] {circ.label} dtype={dtype} tuning={tuning} fusion={fusion}", flush=True)
+    sim = qk.run_circuit(circ, dtype=dtype, fusion=fusion, tuning=tuning)
+    sim.flush()
+    stats = sim.stats()
+    st, cb = sim.state(), sim.read_cbits()
+    sim.close()
+    return st, cb, stats
+
+
 def diag_heavy_circuit(n, n_ops, seed, p_dense=0.12, p_meas=0.04):
     """Mostly diagonal gates (one- and two-qubit, 0-2 controls, diagonal user
     matrices of 1-3 qubits), some under cbit conditions, broken up now and
@@ -152,8 +163,13 @@ def test_qft_with_runs_matches_ifft(n):
     got, _, stats = _run(c, "c128", 1)
     assert np.max(np.abs(got - math.sqrt(1 << n) * np.fft.ifft(c.init_state))) <= TOL128
     # H per qubit, one pass per CPHASE chain of two or more gates, one sweep
-    # for the single CPHASE of the second-to-last qubit, the reversal swaps
-    assert stats["sweeps"] == n + (n - 2) + 1 + n // 2
+    # for the single CPHASE of the second-to-last qubit; the reversal swaps
+    # only relabel qubits (counted before the readout puts the state back in
+    # logical order), and are sweeps of their own with relabelling off
+    assert stats["sweeps"] == n + (n - 2) + 1
+    got_off, _, stats_off = _run_tuned(c, "c128", {"diag_runs": 1, "swap_relabel": 0})
+    assert np.max(np.abs(got_off - math.sqrt(1 << n) * np.fft.ifft(c.init_state))) <= TOL128
+    assert stats_off["sweeps"] == n + (n - 2) + 1 + n // 2
 
 
 @pytest.mark.parametrize("m,seed", [(8, 0), (12, 3), (16, 5)])
