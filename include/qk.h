@@ -317,8 +317,10 @@ qk_status qk_flush(qk_sim sim);
 qk_status qk_sync(qk_sim sim);
 
 /* Launch-shape knobs (results never depend on them).  Keys:
- *   "nt"          0: regular loads/stores, 1 (default): non-temporal when a
- *                 sweep's accesses cover whole cache lines, 2: always;
+ *   "nt"          0: regular loads/stores, 1 (default): non-temporal when
+ *                 the state is larger than 256 MiB (smaller states stay in
+ *                 the Infinity Cache between sweeps) and a sweep's accesses
+ *                 cover whole cache lines, 2: always;
  *   "lane_bfly"   1 (default): targets below bit 6 use the cross-lane
  *                 butterfly, 0: the strided one;
  *   "sweep_items" amplitudes per thread of the strided butterfly, amplitude

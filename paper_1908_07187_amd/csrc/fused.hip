@@ -344,7 +344,7 @@ hipError_t launch_dense_mfma(const Launch& L, const int* targets, int k, const i
   bool contiguous = true;
   for (int j = 0; j < lb; ++j) contiguous = contiguous && ma.lpos[j] == j;
   const size_t run = (contiguous ? (size_t)cw : 1) * (L.c64 ? 8 : 16);
-  const bool nt = L.tune.nt == 2 || (L.tune.nt == 1 && run >= 256);
+  const bool nt = L.tune.nt == 2 || (L.tune.nt == 1 && run >= 256 && state_streams(L));
   if (L.c64) {
     switch (k) {
       case 2: return launch_kw<float, 2>(L, d_matrix, cw, nt, nchunks, sp, cmask, ma, waves_per_cu);

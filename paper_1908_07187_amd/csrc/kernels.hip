@@ -158,11 +158,13 @@ __device__ __forceinline__ void st(T* p, T v) {
   else *p = v;
 }
 
-// Non-temporal only when every run of consecutive amplitudes an instruction
-// touches is at least 256 bytes long: the lowest zero-inserted bit sets it.
+// Non-temporal only for a state larger than the Infinity Cache, and when
+// every run of consecutive amplitudes an instruction touches is at least 256
+// bytes long (the lowest zero-inserted bit sets it).
 static bool use_nt(const Launch& L, int lowest_special) {
   if (L.tune.nt == 0) return false;
   if (L.tune.nt == 2) return true;
+  if (!state_streams(L)) return false;
   return lowest_special >= (L.c64 ? 5 : 4);
 }
 static int lowest(const int* a, int na, const int* b, int nb, int dflt) {
@@ -324,7 +326,7 @@ static void launch_bfly_typed(const Launch& L, int t, const int* controls, int n
     }
     Special sp = make_special(hi.data(), (int)hi.size(), nullptr, 0);
     const uint64_t nseg = 1ull << (L.n - 6 - (int)hi.size());
-    const bool nt = L.tune.nt != 0;
+    const bool nt = L.tune.nt == 2 || (L.tune.nt == 1 && state_streams(L));
     const int it = (int)std::min<uint64_t>((uint64_t)L.tune.lane_items, nseg);
     if (it >= 4) { if (nt) launch_lane<R, 4, true>(L, nseg, sp, cmask_hi, cmask_lo, t, u); else launch_lane<R, 4, false>(L, nseg, sp, cmask_hi, cmask_lo, t, u); }
     else if (it == 2) { if (nt) launch_lane<R, 2, true>(L, nseg, sp, cmask_hi, cmask_lo, t, u); else launch_lane<R, 2, false>(L, nseg, sp, cmask_hi, cmask_lo, t, u); }
@@ -780,7 +782,7 @@ __global__ __launch_bounds__(kBlock) void k_swap_lane_lo(CV<R>* __restrict__ psi
 hipError_t launch_swap(const Launch& L, int a, int b, const int* controls, int nc) {
   if (a > b) std::swap(a, b);
   if (nc == 0 && L.n >= 6 && a < (L.c64 ? 4 : 3)) {
-    const bool nt = L.tune.nt != 0;
+    const bool nt = L.tune.nt == 2 || (L.tune.nt == 1 && state_streams(L));
     if (b >= 6) {
       const int hb = b - 6;
       Special sp = make_special(&hb, 1, nullptr, 0);
