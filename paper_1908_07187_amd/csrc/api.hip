@@ -755,30 +755,60 @@ qk_status flush_pending(qk_sim s) {
       if (!joins_run(pend[m])) return false;
     return true;
   };
-  for (const FBlock& b : blocks) {
-    qk_status st;
-    if ((b.diag || b.members.size() == 1) && all_join(b)) {
-      for (int m : b.members)
-        if ((st = add_to_run(s, std::move(pend[m])))) return st;
-      continue;
+  // The matrices of consecutive dense blocks go up in one copy per segment
+  // (at most kUploadBatch bytes) instead of one copy per block; a segment's
+  // blocks are launched before the next segment is staged, so recycling the
+  // constant arena (after a stream sync) never overwrites a matrix that a
+  // launched block has yet to read.
+  constexpr size_t kUploadBatch = kArenaBytes / 4;
+  auto dense = [&](const FBlock& b) { return b.members.size() > 1 && !b.diag && b.qubits.size() > 1; };
+  std::vector<const void*> dmat(blocks.size(), nullptr);
+  size_t i = 0;
+  while (i < blocks.size()) {
+    std::vector<unsigned char> stage;
+    std::vector<std::pair<size_t, size_t>> at;   // (block, offset in stage)
+    size_t j = i;
+    for (; j < blocks.size(); ++j) {
+      if (!dense(blocks[j])) continue;
+      std::vector<unsigned char> packed = pack_matrix(blocks[j].m, s->c64);
+      const size_t o = (stage.size() + 255) & ~(size_t)255;
+      if (!stage.empty() && o + packed.size() > kUploadBatch) break;
+      stage.resize(o + packed.size());
+      std::memcpy(stage.data() + o, packed.data(), packed.size());
+      at.emplace_back(j, o);
     }
-    if ((st = flush_drun(s))) return st;
-    if (b.members.size() == 1) {   // a block of one gate runs through that gate's own sweep
-      st = execute(s, pend[b.members[0]]);
+    if (!stage.empty()) {
+      const void* base = nullptr;
+      qk_status st = arena_put(s, stage.data(), stage.size(), &base);
       if (st) return st;
-      continue;
+      for (const auto& bo : at) dmat[bo.first] = (const char*)base + bo.second;
     }
-    s->fused_blocks++;
-    s->fused_gates += b.ngates;
-    if (b.diag) {
-      const int D = 1 << b.qubits.size();
-      std::vector<cd> dg(D);
-      for (int i = 0; i < D; ++i) dg[i] = b.m[(size_t)i * D + i];
-      st = run_diag(s, b.qubits, {}, none, dg);
-    } else {
-      st = run_dense(s, b.qubits, {}, none, b.m, nullptr);
+    for (; i < j; ++i) {
+      const FBlock& b = blocks[i];
+      qk_status st;
+      if ((b.diag || b.members.size() == 1) && all_join(b)) {
+        for (int m : b.members)
+          if ((st = add_to_run(s, std::move(pend[m])))) return st;
+        continue;
+      }
+      if ((st = flush_drun(s))) return st;
+      if (b.members.size() == 1) {   // a block of one gate runs through that gate's own sweep
+        st = execute(s, pend[b.members[0]]);
+        if (st) return st;
+        continue;
+      }
+      s->fused_blocks++;
+      s->fused_gates += b.ngates;
+      if (b.diag) {
+        const int D = 1 << b.qubits.size();
+        std::vector<cd> dg(D);
+        for (int e = 0; e < D; ++e) dg[e] = b.m[(size_t)e * D + e];
+        st = run_diag(s, b.qubits, {}, none, dg);
+      } else {
+        st = run_dense(s, b.qubits, {}, none, b.m, dmat[i]);
+      }
+      if (st) return st;
     }
-    if (st) return st;
   }
   return QK_OK;
 }
