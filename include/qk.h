@@ -292,7 +292,10 @@ qk_status qk_set_state(qk_sim sim, const void* host_in, size_t bytes);
 
 /* Current device address and size of the state, in logical qubit order
  * (relabelled qubits are put back first).  Valid until the next call
- * that adds qubits or destroys the simulator.  Emits held-back gates first. */
+ * that adds qubits or destroys the simulator.  Emits held-back gates first.
+ * Later gates update the state in place, but a later uncontrolled SWAP may
+ * only relabel qubits: call qk_state_ptr again before reading through the
+ * pointer (or set the "swap_relabel" tuning key to 0). */
 qk_status qk_state_ptr(qk_sim sim, void** dev_ptr, size_t* bytes);
 
 /* FP64 inner product <a|b> = sum conj(a_i) b_i of two simulators with the same
