@@ -163,7 +163,7 @@ def kernels_only(qk, torch):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on exactly one GPU (the state-vector path is single-device); "
+        print("bench.py: this implementation runs on exactly one GPU (the state-vector path is single-device); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     import torch
