@@ -255,6 +255,24 @@ def test_fused_blocks_match_oracle(k, dtype, cols):
         _check(ref, got, dtype)
 
 
+def test_fused_block_uploads_span_segments_and_arena_recycling():
+    """Block matrices go up in segments of up to 8 MiB, each segment's blocks
+    launched before the next is staged; with more than 32 MiB of matrices
+    (over 512 complex128 6-qubit blocks of 64 KiB) the constant arena is also
+    recycled in between.  Against the oracle."""
+    import paper_1908_07187_amd as qk
+    c = W.c0_random_layers(n=12, layers=260, seed=17, rzz=True)   # 712 dense blocks, 45.6 MiB of matrices
+    ref, _, _ = oracle.run(c)
+    print("[gpu] long circuit, 6-qubit blocks, complex128", flush=True)
+    sim = qk.run_circuit(c, dtype="c128", fusion=6)
+    sim.flush()
+    st = sim.stats()
+    got = sim.state()
+    sim.close()
+    assert st["fused_blocks"] > 512, st
+    _check(ref, got, "c128")
+
+
 @pytest.mark.parametrize("n", [8, 9, 10, 11])
 def test_fused_blocks_few_column_bits(n):
     """States with only 4..6 bits outside a 5-qubit block: the tile width falls back."""
