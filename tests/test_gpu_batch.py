@@ -99,6 +99,30 @@ def test_batch_rerun_and_clear():
     b.close()
 
 
+def test_graph_of_a_long_fused_circuit():
+    """A captured circuit whose block matrices (712 complex128 6-qubit blocks,
+    45.6 MiB) need several arena chunks: the capture adds chunks instead of
+    recycling, and every replay equals the oracle."""
+    import torch
+    import paper_1908_07187_amd as qk
+    c = W.c0_random_layers(n=12, layers=260, seed=17, rzz=True)
+    ref, _, _ = oracle.run(c)
+    s = qk.Sim("c128", stream=torch.cuda.Stream())     # capture needs a non-default stream
+    s.add_qubits(12)
+    s.set_fusion(6)
+    prog = qk.Program(W.Circuit([op for op in c.ops if op.kind not in ("add_qubits", "add_cbits")],
+                                user_gates=c.user_gates))
+    s.capture_begin()
+    s.reset()
+    prog.run(s)
+    g = s.capture_end()
+    for rep in range(3):
+        print(f"[gpu-graph] long fused circuit replay {rep}", flush=True)
+        g.launch()
+        assert np.max(np.abs(s.state() - ref)) <= 1e-12
+    g.close()
+    s.close()
+
 @pytest.mark.parametrize("fusion", [0, 4])
 def test_graph_replays_match_eager(fusion):
     """Capture reset + a 12-qubit circuit with a measurement and a conditioned
