@@ -48,7 +48,7 @@ typedef struct orc {
     unsigned char* cbits;
 } orc;
 
-enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_OOM = -4, ORC_E_STATE = -6 };
+enum { ORC_OK = 0, ORC_E_ARG = -1, ORC_E_NOT_PERM = -3, ORC_E_OOM = -4, ORC_E_STATE = -6 };
 
 int orc_threads(void) {
 #ifdef _OPENMP
@@ -219,8 +219,18 @@ int orc_apply_perm(orc* o, int k, const int* targets, const uint64_t* table,
     if (st) return st;
     if ((st = check_conds(o, ncond, cond_cbits))) return st;
     const uint64_t K = 1ull << k;
-    for (uint64_t m = 0; m < K; ++m)
-        if (table[m] >= K) return ORC_E_ARG;
+    /* the table must be a bijection of [0, 2^k): every value in range, none twice */
+    unsigned char* seen = (unsigned char*)calloc((size_t)((K + 7) / 8), 1);
+    if (!seen) return ORC_E_OOM;
+    for (uint64_t m = 0; m < K; ++m) {
+        const uint64_t y = table[m];
+        if (y >= K || (seen[y >> 3] >> (y & 7)) & 1) {
+            free(seen);
+            return ORC_E_NOT_PERM;
+        }
+        seen[y >> 3] |= (unsigned char)(1u << (y & 7));
+    }
+    free(seen);
     if (!conditions_hold(o, ncond, cond_cbits, cond_vals)) return ORC_OK;
     uint64_t tmask = 0, cmask = 0;
     for (int j = 0; j < k; ++j) tmask |= 1ull << targets[j];

@@ -89,6 +89,84 @@ def test_affine_power_table_matches_repeated_application():
             assert np.array_equal(gates.affine_table(k, a, b, j), brute.affine_power_table(k, a, b, j))
 
 
+def _modmul_exact(k, a, N, j):
+    """y -> (a^(2^j) y) mod N below N, y itself from N up (reading R8), with
+    the power a^(2^j) formed as an exact integer before any reduction."""
+    mult = a ** (2 ** j)
+    return [(mult * y) % N if y < N else y for y in range(1 << k)]
+
+
+@pytest.mark.parametrize("k,a,N", [(4, 2, 15), (5, 5, 21), (5, 2, 21), (6, 3, 64), (6, 5, 33), (7, 3, 91),
+                                   (7, 7, 128), (10, 10, 1001), (10, 3, 1024), (3, 1, 2), (8, 17, 200)])
+def test_modmul_table_matches_exact_integers(k, a, N):
+    """The oracle's modular-multiplication table (the paper's QuModExpUaj
+    a= j= N=, Appendix A) against exact integer arithmetic, for powers j up to
+    10, N below and equal to 2^k; the values at and above N must stay where
+    they are and the table must be a bijection of [0, 2^k)."""
+    for j in range(11):
+        t = gates.modmul_table(k, a, N, j)
+        assert t.dtype == np.uint64 and t.shape == (1 << k,)
+        assert [int(v) for v in t] == _modmul_exact(k, a, N, j), (k, a, N, j)
+        assert np.array_equal(np.sort(t), np.arange(1 << k, dtype=np.uint64))
+
+
+def test_modmul_table_has_the_order_of_a():
+    """Applying the j = 0 map r times, r = the multiplicative order of a mod N,
+    gives the identity, and no smaller count does (2 mod 15: r = 4; 2 mod 21:
+    r = 6; 3 mod 91: r = 6; r found by iterating a^r mod N)."""
+    for k, a, N in [(4, 2, 15), (5, 2, 21), (7, 3, 91)]:
+        r = next(r for r in range(1, N) if pow(a, r, N) == 1)
+        t = gates.modmul_table(k, a, N, 0)
+        cur = np.arange(1 << k, dtype=np.uint64)
+        for step in range(1, r + 1):
+            cur = t[cur]
+            assert np.array_equal(cur, np.arange(1 << k, dtype=np.uint64)) == (step == r)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_modmul_gates_match_kronecker_brute_force(seed):
+    """Circuits of controlled modular multiplications (j = 0..4, N <= 2^k) on
+    a random state, oracle against the brute force, whose modmul operator is
+    built from Python's modular pow, not from the oracle's table."""
+    rng = W.circuits.rng_for(4000 + seed)
+    n = 7
+    ops = [W.add_qubits(n)]
+    user = {}
+    for g in range(12):
+        k = int(rng.integers(2, 5))
+        N = int(rng.integers(2, (1 << k) + 1))
+        a = int(rng.integers(1, N))
+        while math.gcd(a, N) != 1:
+            a = int(rng.integers(1, N))
+        qs = [int(x) for x in rng.permutation(n)]
+        user[f"M{g}"] = {"kind": "modmul", "k": k, "a": a, "N": N}
+        ncont = int(rng.integers(0, 3))
+        ops.append(W.gate(f"M{g}", qs[:k], controls=qs[k:k + ncont], params=(float(rng.integers(0, 5)),)))
+        ops.append(W.gate("RY", [qs[-1]], params=(float(rng.uniform(0, 6)),)))
+    c = W.Circuit(ops, user_gates=user)
+    c.init_state = W.random_state(n, W.circuits.rng_for(77 + seed))
+    st, _, _ = oracle.run(c)
+    assert np.max(np.abs(st - brute.final_state(c))) <= 1e-12
+
+
+def test_random_mixed_circuits_carry_every_permutation_family():
+    kinds = set()
+    for seed in range(8):
+        c = W.random_mixed_circuit(6, 60, seed=seed)
+        kinds |= {g["kind"] for g in c.user_gates.values()}
+    assert kinds == {"matrix", "table", "affine", "modmul"}
+
+
+def test_oracle_rejects_a_table_that_is_not_a_bijection():
+    o = Oracle()
+    o.add_qubits(3)
+    with pytest.raises(oracle.oracle.OracleError):
+        o.apply_perm(np.array([0, 0, 2, 3], dtype=np.uint64), [0, 1])      # 1 missing, 0 twice
+    with pytest.raises(oracle.oracle.OracleError):
+        o.apply_perm(np.array([0, 1, 2, 4], dtype=np.uint64), [0, 1])      # value out of range
+    o.apply_perm(np.array([3, 2, 1, 0], dtype=np.uint64), [0, 1])          # a bijection is accepted
+
+
 # --------------------------------------------------------------- closed forms
 
 @pytest.mark.parametrize("n", [1, 2, 3, 5, 8])
@@ -163,7 +241,6 @@ def test_circuit_then_inverse_is_identity(seed):
 def test_mixed_circuit_then_inverse_is_identity():
     c = W.random_mixed_circuit(7, 60, seed=21, with_perms=True, with_conds=False)
     c.user_gates = {k: v for k, v in c.user_gates.items()}
-    c.ops = [op for op in c.ops if not (op.kind == "gate" and c.user_gates.get(op.name, {}).get("kind") == "affine")]
     inv = W.inverse(c)
     full = W.Circuit(c.ops + inv.ops, user_gates=inv.user_gates)
     st, _, _ = oracle.run(full)

@@ -294,8 +294,9 @@ def random_mixed_circuit(n: int, n_gates: int, seed: int = 0, max_k: int = 3,
                          with_perms: bool = True, with_conds: bool = True) -> Circuit:
     """Random circuit over every gate class, for brute-force and parity checks:
     builtins with 0..2 controls, multi-target user unitaries (k <= max_k),
-    permutation tables, affine permutations with a power, and gates with
-    cbit conditions that hold (value 0, cbits start at 0) or fail (value 1).
+    permutation tables, affine permutations and modular multiplications with
+    a power, and gates with cbit conditions that hold (value 0, cbits start
+    at 0) or fail (value 1).
     """
     rng = rng_for(seed)
     ops = [add_qubits(n), add_cbits(2)]
@@ -327,7 +328,7 @@ def random_mixed_circuit(n: int, n_gates: int, seed: int = 0, max_k: int = 3,
             user[key] = {"kind": "table", "k": k, "table": rng.permutation(1 << k).astype(np.uint64)}
             ncont = int(rng.integers(0, min(1, n - k) + 1)) if rng.random() < 0.4 else 0
             ops.append(gate(key, qs[:k], controls=qs[k:k + ncont]))
-        else:
+        elif kind < 0.965 or n < 2:
             k = int(rng.integers(1, min(max_k + 1, n) + 1))
             key = f"A{gi}"
             a = int(rng.integers(0, 1 << max(k - 1, 0))) * 2 + 1
@@ -335,6 +336,17 @@ def random_mixed_circuit(n: int, n_gates: int, seed: int = 0, max_k: int = 3,
             user[key] = {"kind": "affine", "k": k, "a": a, "b": b}
             ncont = int(rng.integers(0, min(1, n - k) + 1)) if rng.random() < 0.4 else 0
             ops.append(gate(key, qs[:k], controls=qs[k:k + ncont], params=(float(rng.integers(0, 4)),)))
+        else:
+            # modular multiplication y -> a^(2^j) y mod N on k >= 2 targets, N anywhere in [2, 2^k]
+            k = int(rng.integers(2, min(max_k + 1, n) + 1))
+            key = f"M{gi}"
+            N = int(rng.integers(2, (1 << k) + 1))
+            a = int(rng.integers(1, N))
+            while math.gcd(a, N) != 1:
+                a = int(rng.integers(1, N))
+            user[key] = {"kind": "modmul", "k": k, "a": a, "N": N}
+            ncont = int(rng.integers(0, min(1, n - k) + 1)) if rng.random() < 0.4 else 0
+            ops.append(gate(key, qs[:k], controls=qs[k:k + ncont], params=(float(rng.integers(0, 5)),)))
         if with_conds and rng.random() < 0.15:
             last = ops[-1]
             ops[-1] = gate(last.name, last.targets, last.controls,
@@ -366,8 +378,14 @@ def inverse(circ: Circuit) -> Circuit:
                 user[key] = {"kind": "matrix", "k": g["k"], "matrix": np.conj(g["matrix"]).T.copy()}
             elif g["kind"] == "table":
                 user[key] = {"kind": "table", "k": g["k"], "table": np.argsort(g["table"]).astype(np.uint64)}
+            elif g["kind"] == "modmul":
+                # (a^(2^j))^-1 = (a^-1)^(2^j) mod N: the same family with the inverse multiplier
+                user[key] = {"kind": "modmul", "k": g["k"], "a": pow(g["a"], -1, g["N"]), "N": g["N"]}
             else:
-                raise ValueError("inverse of an affine gate is not generated")
+                # f(x) = a x + b mod 2^k has inverse a^-1 x - a^-1 b, and (f^-1)^(2^j) = (f^(2^j))^-1
+                mod = 1 << g["k"]
+                ainv = pow(g["a"], -1, mod)
+                user[key] = {"kind": "affine", "k": g["k"], "a": ainv, "b": (-ainv * g["b"]) % mod}
             nm = key
         ops.append(gate(nm, op.targets, op.controls, op.conds, prm))
     return Circuit(ops, user_gates=user, label=circ.label + "_inv")
@@ -462,23 +480,3 @@ def shor_3nx1(N: int, a: int = 2, measure_work: bool = False, us=None, seed: int
             ops.append(measure(b, cbit=-1, u=float(us[i])))
     ops += qft_ops([nTQ - 1 - p for p in range(nCQ)])
     return Circuit(ops, user_gates=user, label=f"shor_3nx1_N{N}_a{a}")
-
-
-def shor_nx2n_script(N: int, a: int = 2) -> str:
-    """Kitaev's one-control-qubit Shor circuit as command-script text (the
-    command format of the paper's Appendix A): nQ = bitlen(N) + 1 qubits (qubit
-    0 = the recycled control, 1..nQ-1 the work register, big-endian), nC =
-    bitlen(N^2 - 1) cbits; stage e applies U^(2^(nC-1-e)), the cbit-weighted
-    phase correction, measures the control into cbit e and resets it."""
-    nQ = N.bit_length() + 1
-    nC = (N * N - 1).bit_length()
-    out = [f"#! Shor N={N} a={a}, {nQ} qubits, {nC} stages", f"AddQubits {nQ}", f"AddCbits {nC}",
-           f"GateOp SigmaX {nQ - 1}"]
-    for e in range(nC):
-        out.append("GateOp Hadamard 0")
-        out.append(f"GateOp QuModExpUaj 0:{nQ} a={a} j={nC - e - 1} N={N}")
-        if e:
-            out.append("GateOp RPhase 0," + ",".join(str(-i) for i in range(e, 0, -1)))
-        out += ["GateOp Hadamard 0", "Measure 0", f"GateOp Copy 0,-{e + 1}", f"GateOp SigmaX 0,-{e + 1}"]
-    out.append(f"Measure 1:{nQ}")
-    return "\n".join(out) + "\n"
