@@ -315,7 +315,7 @@ def shor(args, qk, torch):
     from . import script
     res = {}
     for N in (961307, 13564597):
-        text = W.shor_nx2n_script(N, 2)
+        text = script.dump(W.shor_nx2n(N, 2, tables=False))
         nC = (N * N - 1).bit_length()
         circ = script.parse(text, seed=args.seed)
         prog = qk.Program(circ)
@@ -444,6 +444,102 @@ def sample30(args, qk, torch):
     return out
 
 
+def kernels30(args, qk, torch):
+    """Per-call timing of the path's sweep classes on 30-qubit states, each
+    against its algorithmic bytes (read + write of every amplitude the call may
+    change; permutation tables add 4 B per amplitude; the measurement reads
+    the state once, then reads the kept half and writes the whole state).
+    HIP events on the simulator's stream bracket each call; every case runs
+    ``args.steps`` times after ``args.warmup`` untimed calls."""
+    import workloads as W
+    n = 30
+    stream = torch.cuda.current_stream()
+    rng = np.random.default_rng(args.seed)
+    reps = max(1, args.steps)
+    rows = []
+
+    def timed(label, dtype, alg_bytes, call, **extra):
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            call()
+            e1.record(stream)
+            ms.append((e0, e1))
+        torch.cuda.synchronize()
+        t = [a.elapsed_time(b) for a, b in ms]
+        mean = sum(t) / len(t)
+        gbps = alg_bytes / (mean * 1e-3) / 1e9
+        row = {"case": label, "dtype": dtype, "mean_ms": mean, "min_ms": min(t), "max_ms": max(t),
+               "alg_bytes": alg_bytes, "gbps": gbps, "frac_of_8tbps": gbps / 8000.0}
+        row.update(extra)
+        rows.append(row)
+        _say(f"kernels30 {dtype} {label}: {mean:.3f} ms ({min(t):.3f}-{max(t):.3f}), {gbps:.0f} GB/s "
+             f"= {gbps / 8000.0:.3f} of 8 TB/s")
+
+    for dtype in ("c128", "c64"):
+        amp = 16 if dtype == "c128" else 8
+        full = (1 << n) * 2 * amp
+        s = qk.Sim(dtype)
+        s.set_tuning("diag_runs", 0)
+        s.add_qubits(n)
+        s.add_cbits(2)
+        for q in range(n):
+            s.apply("H", [q])
+        s.sync()
+        # controlled sweeps (CNOT / Toffoli): 2^(n-c) amplitudes
+        for c, t in ((0, 1), (1, 0), (2, 20), (3, 20), (6, 20), (20, 3), (20, 0), (25, 29)):
+            timed(f"CNOT c{c} t{t}", dtype, full >> 1, lambda c=c, t=t: s.apply("X", [t], controls=[c]))
+        timed("Toffoli c0,c1 t20", dtype, full >> 2, lambda: s.apply("X", [20], controls=[0, 1]))
+        timed("Toffoli c12,c29 t3", dtype, full >> 2, lambda: s.apply("X", [3], controls=[12, 29]))
+        # permutation gates: 20-bit table, affine and modular maps, un- and controlled
+        tab = rng.permutation(1 << 20).astype(np.uint64)
+        gt = s.define_table("T20", tab)
+        ga = s.define_affine("A20", 20, int(rng.integers(0, 1 << 19)) * 2 + 1, int(rng.integers(0, 1 << 20)))
+        gm = s.define_modmul("M20", 20, 7, 1000003)
+        timed("perm table k20 t0..19", dtype, (1 << n) * (2 * amp + 4), lambda: s.apply(gt, list(range(20))))
+        timed("perm table k20 t10..29", dtype, (1 << n) * (2 * amp + 4), lambda: s.apply(gt, list(range(10, 30))))
+        timed("perm affine k20 t0..19 c29", dtype, (1 << (n - 1)) * 2 * amp,
+              lambda: s.apply(ga, list(range(20)), controls=[29], params=[3.0]))
+        timed("perm modmul k20 t0..19 c29", dtype, (1 << (n - 1)) * 2 * amp,
+              lambda: s.apply(gm, list(range(20)), controls=[29], params=[5.0]))
+        timed("perm modmul k20 t0..19", dtype, (1 << n) * 2 * amp,
+              lambda: s.apply(gm, list(range(20)), params=[5.0]))
+        # measurement: prob sweep (read 2^n) + collapse (read 2^(n-1), write 2^n); postselect keeps the state nonzero
+        meas_bytes = (1 << n) * amp + (1 << (n - 1)) * amp + (1 << n) * amp
+        for q in (0, 5, 29):
+            def m(q=q):
+                s.apply("H", [q])
+                s.measure(q, 0, 0.5)
+            timed(f"H + measure q{q}", dtype, meas_bytes + full, m)
+        s.close()
+        # fused matrix-core blocks, k = 5 (and 4, 6 for complex64)
+        f = qk.Sim(dtype)
+        f.add_qubits(n)
+        f.sync()
+        for k in ((4, 5, 6) if dtype == "c64" else (4, 5)):
+            g = f.define_matrix(f"U{k}", W.random_unitary(k, rng))
+            for targets in ([3, 9, 14, 21, 27, 29], [0, 7, 8, 16, 25, 28], [0, 1, 2, 3, 4, 5], [24, 25, 26, 27, 28, 29],
+                            [5, 6, 7, 8, 9, 10], [1, 3, 5, 7, 9, 11]):
+                tg = targets[:k]
+                timed(f"dense k{k} {tg}", dtype, full, lambda g=g, tg=tg: f.apply(g, tg), k=k,
+                      tflops=(8 << k) * (1 << n))
+        f.close()
+    for r in rows:
+        if "tflops" in r:
+            r["tflops"] = r["tflops"] / (r["mean_ms"] * 1e-3) / 1e12
+    worst = min(rows, key=lambda r: r["frac_of_8tbps"])
+    out = _base(args, worst["gbps"], "GB/s",
+                {"workload": "per-call timing of the sweep classes on 30-qubit states (controlled gates, "
+                             "permutation gates, measurement, dense blocks), complex128 and complex64",
+                 "n_qubits": n}, "f64")
+    out["cases"] = rows
+    return out
+
+
 def run(name, args, qk, torch):
     return {"batch12": batch12, "serve": serve, "qft26": qft26, "ipe21": ipe21, "shor": shor,
-            "sample30": sample30, "shor39": shor39}[name](args, qk, torch)
+            "sample30": sample30, "shor39": shor39, "kernels30": kernels30}[name](args, qk, torch)

@@ -34,8 +34,9 @@ Gates (names are case-insensitive):
 Measure measures the listed qubits one after another, each with the next
 pre-drawn uniform.
 
-``parse(text, uniforms)`` returns a ``workloads.Circuit``; ``run(text, ...)``
-parses and executes it through the C ABI.
+``parse(text, uniforms)`` returns a ``workloads.Circuit``; ``dump(circuit)``
+writes a circuit back as such text; ``run(text, ...)`` parses and executes it
+through the C ABI.
 """
 from __future__ import annotations
 
@@ -211,6 +212,130 @@ def parse(text: str, uniforms: Optional[Sequence[float]] = None, seed: int = 0) 
             raise ScriptError(f"unknown command {cmd!r}")
         i += 1
     return W.Circuit(ops, user_gates=user, label="script")
+
+
+# ---------------------------------------------------------------- writer
+
+_NAME_OF = {"X": "SigmaX", "Y": "SigmaY", "Z": "SigmaZ", "H": "Hadamard", "S": "S", "T": "T", "SDG": "Sdg",
+            "TDG": "Tdg"}
+_ROT_OF = {"RX": "RX theta", "RY": "RY theta", "RZ": "RZ theta", "PHASE": "Phase phi"}
+
+
+def _num(x: float) -> str:
+    """Shortest text that reads back as the same double."""
+    return repr(float(x))
+
+
+def _listing(vals: Sequence[int]) -> str:
+    """Comma-separated values; ascending runs of non-negative numbers of
+    length >= 3 as exclusive ranges a:b."""
+    out, i = [], 0
+    vals = list(vals)
+    while i < len(vals):
+        j = i
+        while j + 1 < len(vals) and vals[i] >= 0 and vals[j + 1] == vals[j] + 1:
+            j += 1
+        if j - i >= 2:
+            out.append(f"{vals[i]}:{vals[j] + 1}")
+        else:
+            out.extend(str(v) for v in vals[i:j + 1])
+        i = j + 1
+    return ",".join(out)
+
+
+def uniforms_of(circuit) -> List[float]:
+    """The measurement uniforms of a circuit in op order (what ``parse`` takes)."""
+    return [float(op.u) for op in circuit.ops if op.kind == "measure"]
+
+
+def dump(circuit) -> str:
+    """Write a circuit as command-script text that ``parse`` reads back into
+    the same operations (with ``uniforms_of(circuit)`` as its uniforms).
+
+    Only what the command format can say is accepted: gates with no classical
+    condition other than "cbit = 1"; one-qubit builtins, rotations and PHASE
+    without controls; CNOT (X with one control); CPHASE and SWAP without
+    controls; modular multiplications with exactly one control (QuModExpUaj,
+    work register listed from its most significant bit); measurements, with
+    a Copy line when the outcome goes to a cbit.  Runs of PHASE gates on one
+    qubit whose angles are -pi/2, -pi/4, ... each steered by one cbit are
+    written as one RPhase command.  Anything else raises ScriptError.
+    """
+    nq = sum(op.count for op in circuit.ops if op.kind == "add_qubits")
+    ops = list(circuit.ops)
+
+    def p(b: int) -> int:
+        return nq - 1 - int(b)
+
+    def cond_list(op) -> List[int]:
+        if any(v != 1 for _, v in op.conds):
+            raise ScriptError(f"a condition on cbit = 0 has no command form: {op}")
+        return [-(c + 1) for c, _ in op.conds]
+
+    def rphase_weight(op, i: int) -> bool:
+        return (op.kind == "gate" and op.name == "PHASE" and len(op.targets) == 1 and not op.controls
+                and len(op.conds) == 1 and op.conds[0][1] == 1 and op.params[0] == -math.pi / 2 ** (i + 1))
+
+    lines = [f"#! {circuit.label}" if getattr(circuit, "label", "") else "#! circuit"]
+    i = 0
+    while i < len(ops):
+        op = ops[i]
+        if op.kind == "add_qubits":
+            lines.append(f"AddQubits {op.count}")
+        elif op.kind == "add_cbits":
+            lines.append(f"AddCbits {op.count}")
+        elif op.kind == "measure":
+            if op.cbit >= 0:
+                lines.append(f"Measure {p(op.qubit)}")
+                lines.append(f"GateOp Copy {p(op.qubit)},-{op.cbit + 1}")
+            else:
+                qs = [p(op.qubit)]
+                while i + 1 < len(ops) and ops[i + 1].kind == "measure" and ops[i + 1].cbit < 0:
+                    i += 1
+                    qs.append(p(ops[i].qubit))
+                lines.append(f"Measure {_listing(qs)}")
+        elif op.kind == "gate":
+            name = op.name
+            user = circuit.user_gates.get(name)
+            if user is not None:
+                if user["kind"] != "modmul" or len(op.controls) != 1:
+                    raise ScriptError(f"only singly controlled modular multiplications have a command form: {op}")
+                j = op.params[0] if op.params else 0.0
+                if j != int(j):
+                    raise ScriptError(f"QuModExpUaj takes an integer power: {op}")
+                regs = [p(op.controls[0])] + [p(t) for t in reversed(op.targets)]
+                lines.append(f"GateOp QuModExpUaj {_listing(regs + cond_list(op))} a={user['a']} j={int(j)} "
+                             f"N={user['N']}")
+            elif rphase_weight(op, 0):
+                cb = [op.conds[0][0]]
+                while i + 1 < len(ops) and rphase_weight(ops[i + 1], len(cb)) and ops[i + 1].targets == op.targets:
+                    i += 1
+                    cb.append(ops[i].conds[0][0])
+                lines.append(f"GateOp RPhase {p(op.targets[0])}," + ",".join(str(-(c + 1)) for c in cb))
+            elif name in _NAME_OF and not op.controls and len(op.targets) == 1:
+                qs = [p(op.targets[0])]
+                while (i + 1 < len(ops) and ops[i + 1].kind == "gate" and ops[i + 1].name == name
+                       and not ops[i + 1].controls and ops[i + 1].conds == op.conds and len(ops[i + 1].targets) == 1):
+                    i += 1
+                    qs.append(p(ops[i].targets[0]))
+                lines.append(f"GateOp {_NAME_OF[name]} {_listing(qs + cond_list(op))}")
+            elif name in _ROT_OF and not op.controls and len(op.targets) == 1:
+                cmd, key = _ROT_OF[name].split()
+                lines.append(f"GateOp {cmd} {_listing([p(op.targets[0])] + cond_list(op))} {key}={_num(op.params[0])}")
+            elif name == "X" and len(op.controls) == 1 and len(op.targets) == 1:
+                lines.append(f"GateOp CNOT {_listing([p(op.controls[0]), p(op.targets[0])] + cond_list(op))}")
+            elif name == "CPHASE" and not op.controls:
+                lines.append(f"GateOp CPHASE {p(op.targets[0])},{p(op.targets[1])}"
+                             + "".join(f",{c}" for c in cond_list(op)) + f" phi={_num(op.params[0])}")
+            elif name == "SWAP" and not op.controls:
+                lines.append(f"GateOp SWAP {p(op.targets[0])},{p(op.targets[1])}"
+                             + "".join(f",{c}" for c in cond_list(op)))
+            else:
+                raise ScriptError(f"no command form for {op}")
+        else:
+            raise ScriptError(f"unknown op kind {op.kind!r}")
+        i += 1
+    return "\n".join(lines) + "\n"
 
 
 def run(text: str, dtype: str = "c128", uniforms: Optional[Sequence[float]] = None, fusion: int = 0,

@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 @pytest.mark.parametrize("N,a", [(15, 2), (21, 2), (21, 5), (33, 7), (91, 3)])
 def test_shor_scripts_match_oracle(N, a):
     from paper_1908_07187_amd import script
-    text = W.shor_nx2n_script(N, a)
+    text = script.dump(W.shor_nx2n(N, a, tables=False))
     us = np.random.Generator(np.random.PCG64(N + a)).random(256)
     sim, circ = script.run(text, uniforms=us)
     got, cb = sim.state(), sim.read_cbits()
