@@ -150,8 +150,8 @@ qk_status qk_add_qubits(qk_sim sim, int32_t count, int32_t* first_qubit);
  * the current count; *first_cbit (may be NULL) receives it. */
 qk_status qk_add_cbits(qk_sim sim, int32_t count, int32_t* first_cbit);
 
-/* ---- gate definitions (the paper's "define custom gate as a matrix or as
- * a function", section "Q-Kit.") ------------------------------------------ */
+/* ---- gate definitions: custom gates given by a matrix or by an index
+ * function, as the paper's engine allows (section "Q-Kit.") --------------- */
 
 /* Builtin id by name ("H", "X", "SIGMAX", "HADAMARD", "CNOT" = X, "RZ", ...). */
 qk_status qk_gate_builtin(const char* name, qk_gate* out);
@@ -202,7 +202,10 @@ qk_status qk_define_gate_modmul(qk_sim sim, const char* name, int32_t k, uint64_
  * first emits everything held back, in order.  On a dense state an
  * uncontrolled, unconditioned SWAP moves no data: the simulator exchanges the
  * two qubits' index bits in its qubit map, which every later gate and
- * measurement goes through.  qk_get_state, qk_set_state, qk_state_ptr,
+ * measurement goes through.  An uncontrolled permutation gate (outside a
+ * graph capture) gathers the permuted state into the simulator's second
+ * state-sized buffer, which then holds the state: the two buffers trade
+ * places and no copy back is made.  qk_get_state, qk_set_state, qk_state_ptr,
  * qk_probabilities, sampling, inner products of two simulators, graph
  * capture and graph launch first put the state back in logical qubit order
  * (one physical swap per misplaced qubit); qk_norm2 and measurements do not
@@ -292,10 +295,12 @@ qk_status qk_set_state(qk_sim sim, const void* host_in, size_t bytes);
 
 /* Current device address and size of the state, in logical qubit order
  * (relabelled qubits are put back first).  Valid until the next call
- * that adds qubits or destroys the simulator.  Emits held-back gates first.
- * Later gates update the state in place, but a later uncontrolled SWAP may
- * only relabel qubits: call qk_state_ptr again before reading through the
- * pointer (or set the "swap_relabel" tuning key to 0). */
+ * that adds qubits, applies an uncontrolled permutation gate (which leaves
+ * the state in the simulator's other buffer) or destroys the simulator.
+ * Emits held-back gates first.  Other gates update the state in place, but a
+ * later uncontrolled SWAP may only relabel qubits: call qk_state_ptr again
+ * before reading through the pointer (or set the "swap_relabel" tuning key
+ * to 0). */
 qk_status qk_state_ptr(qk_sim sim, void** dev_ptr, size_t* bytes);
 
 /* FP64 inner product <a|b> = sum conj(a_i) b_i of two simulators with the same
@@ -374,8 +379,11 @@ const char* qk_status_string(qk_status st);
  * qk_measure / qk_measure_dev / qk_flush calls (no readout, no qk_add_*),
  * then qk_capture_end.  Nothing runs during capture; each qk_graph_launch
  * replays the whole sequence on the simulator's state, cbits and stream.
- * The graph keeps the constants it uploads; destroy graphs before their
- * simulator. */
+ * Permutation gates inside a capture keep the state in its buffer; if an
+ * uncontrolled permutation gate applied after the capture moved the state to
+ * the other buffer, qk_graph_launch first copies it back (QK_E_STATE if
+ * qubits were added since the capture).  The graph keeps the constants it
+ * uploads; destroy graphs before their simulator. */
 typedef struct qk_graph_s* qk_graph;
 
 /* Set the state to |0...0> and every cbit to 0 (asynchronous; capturable). */

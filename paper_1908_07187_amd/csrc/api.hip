@@ -523,11 +523,17 @@ qk_status execute(qk_sim s, const GateDesc& d) {
       if (st) return st;
       Launch L = make_launch(s, d.conds);
       const int mode = d.ug->kind == U_AFFINE ? 1 : (d.ug->kind == U_MODMUL ? 2 : 0);
-      return check_launch(s,
-                          launch_perm(L, s->scratch.p, d.targets.data(), (int)d.targets.size(), d.controls.data(),
-                                      (int)d.controls.size(), mode == 0 ? (const uint32_t*)d.ug->finv.p : nullptr,
-                                      mode, d.A, d.B, d.Ainv, d.N),
-                          "permutation");
+      // without controls the gather writes the whole result into the second
+      // buffer, which becomes the state (inside a capture the pointers the
+      // graph records must stay put, so the state is gathered and copied back)
+      const bool oop = d.controls.empty() && !s->capturing;
+      st = check_launch(s,
+                        launch_perm(L, s->scratch.p, d.targets.data(), (int)d.targets.size(), d.controls.data(),
+                                    (int)d.controls.size(), mode == 0 ? (const uint32_t*)d.ug->finv.p : nullptr,
+                                    mode, d.A, d.B, d.Ainv, d.N, oop),
+                        "permutation");
+      if (!st && oop) std::swap(s->state, s->scratch);
+      return st;
     }
   }
   return fail(s, QK_E_ARG, "unknown gate class");
@@ -1925,6 +1931,7 @@ struct qk_graph_s {
   qk_sim sim = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  void* state = nullptr;       // the state buffer the graph's kernels address
   std::vector<Arena> arenas;   // constants the captured copies read on every replay
 };
 
@@ -2009,6 +2016,7 @@ qk_status qk_capture_end(qk_sim s, qk_graph* out) {
   q->sim = s;
   q->graph = g;
   q->exec = x;
+  q->state = s->state.p;
   q->arenas = std::move(mine);
   *out = q;
   return QK_OK;
@@ -2017,10 +2025,19 @@ qk_status qk_capture_end(qk_sim s, qk_graph* out) {
 qk_status qk_graph_launch(qk_graph g) {
   if (!g) return fail(nullptr, QK_E_ARG, "graph is NULL");
   if (g->sim->capturing) return fail(g->sim, QK_E_STATE, "not allowed while capturing a graph");
-  qk_status st = flush(g->sim);
-  if (!st) st = restore_layout(g->sim);   // the graph was recorded in the logical layout
+  qk_sim s = g->sim;
+  qk_status st = flush(s);
+  if (!st) st = restore_layout(s);   // the graph was recorded in the logical layout
   if (st) return st;
-  hipError_t e = hipGraphLaunch(g->exec, g->sim->stream);
+  if (s->state.p != g->state) {
+    // an uncontrolled permutation gate since the capture left the state in the
+    // other buffer: copy it back to the one the graph's kernels address
+    if (s->scratch.p != g->state) return fail(s, QK_E_STATE, "the state was reallocated since the capture");
+    hipError_t e = launch_copy(s->scratch.p, s->state.p, 1ull << s->n, s->c64, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "graph launch: state copy");
+    std::swap(s->state, s->scratch);
+  }
+  hipError_t e = hipGraphLaunch(g->exec, s->stream);
   if (e != hipSuccess) return hip_fail(g->sim, e, "graph launch");
   return QK_OK;
 }

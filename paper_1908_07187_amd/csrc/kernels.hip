@@ -889,30 +889,48 @@ hipError_t launch_dense_generic(const Launch& L, const int* targets, int k, cons
 
 // ---------------------------------------------------------------- permutation (oracle) gate
 // U|x> = |f(x)> on the targets: the amplitude at gate index x moves to f(x).
-// Done as a gather out[y] = in[f^-1(y)] over the controlled subspace into a
-// compact scratch buffer (coalesced writes, gathered reads), then copied back.
+// Done as a gather out[y] = in[f^-1(y)] (coalesced writes, gathered reads).
+// Without controls the gather writes the whole permuted state into the second
+// state buffer, which then becomes the state (one read and one write of every
+// amplitude); when its classical condition fails it copies the state instead,
+// so the second buffer always holds the result.  With controls it gathers the
+// controlled subspace into a compact scratch buffer and copies that back.
 // f^-1 is a device table (uint32) or a closed form: for the affine family
 // x = A^-1 (y - B) mod 2^k; for modular multiplication (y -> A y mod N for
-// y < N, y itself above) x = A^-1 y mod N for y < N.
+// y < N, y itself above) x = A^-1 y mod N for y < N, reduced by Barrett's
+// method with mu = floor((2^64 - 1) / N): for p = A^-1 y < N^2 < 2^64 the
+// quotient estimate hi64(p mu) is floor(p / N) or one less, so one
+// conditional subtraction finishes the reduction.
+
+__device__ __forceinline__ uint64_t mod_barrett(uint64_t p, uint64_t N, uint64_t mu) {
+  const uint64_t q = __umul64hi(p, mu);
+  uint64_t r = p - q * N;
+  if (r >= N) r -= N;
+  return r;
+}
 
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_perm_gather(const V2<R>* __restrict__ in, V2<R>* __restrict__ out,
                                                         uint64_t nitems, Special sp, uint64_t cmask, Pos32 tp, int k,
                                                         int contiguous, uint64_t tmask,
-                                                        const uint32_t* __restrict__ finv, int mode, uint64_t A,
-                                                        uint64_t B, uint64_t Ainv, uint64_t N, CondArgs cond) {
-  if (!conds_ok(cond)) return;
+                                                        const uint32_t* __restrict__ finv, int mode, uint64_t B,
+                                                        uint64_t Ainv, uint64_t N, uint64_t mu, int whole,
+                                                        CondArgs cond) {
+  const bool run = conds_ok(cond);
+  if (!run && !whole) return;
   const uint64_t kmask = (k >= 64) ? ~0ull : ((1ull << k) - 1);
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  (void)A;
   for (uint64_t e = (uint64_t)blockIdx.x * kBlock + threadIdx.x; e < nitems; e += stride) {
     const uint64_t i = insert_zeros(e, sp) | cmask;
-    const uint64_t y = contiguous ? ((i >> tp.p[0]) & kmask) : extract(i, tp.p, k);
-    uint64_t x;
-    if (mode == 1) x = (Ainv * (y - B)) & kmask;
-    else if (mode == 2) x = (y < N) ? (Ainv * y) % N : y;   // A, Ainv < N < 2^32: no overflow
-    else x = (uint64_t)finv[y];
-    const uint64_t src = (i & ~tmask) | (contiguous ? (x << tp.p[0]) : deposit(x, tp.p, k));
+    uint64_t src = i;
+    if (run) {
+      const uint64_t y = contiguous ? ((i >> tp.p[0]) & kmask) : extract(i, tp.p, k);
+      uint64_t x;
+      if (mode == 1) x = (Ainv * (y - B)) & kmask;
+      else if (mode == 2) x = (y < N) ? mod_barrett(Ainv * y, N, mu) : y;   // Ainv, y < N < 2^32
+      else x = (uint64_t)finv[y];
+      src = (i & ~tmask) | (contiguous ? (x << tp.p[0]) : deposit(x, tp.p, k));
+    }
     out[e] = in[src];
   }
 }
@@ -927,8 +945,12 @@ __global__ __launch_bounds__(kBlock) void k_perm_scatter(V2<R>* __restrict__ psi
 }
 
 hipError_t launch_perm(const Launch& L, void* scratch, const int* targets, int k, const int* controls, int nc,
-                       const uint32_t* d_finv, int mode, uint64_t A, uint64_t B, uint64_t Ainv, uint64_t N) {
+                       const uint32_t* d_finv, int mode, uint64_t A, uint64_t B, uint64_t Ainv, uint64_t N,
+                       bool out_of_place) {
+  (void)A;
   if (k < 1 || k > 32) return hipErrorInvalidValue;
+  if (out_of_place && nc != 0) return hipErrorInvalidValue;
+  if (mode == 2 && (N < 2 || N > 0xffffffffull)) return hipErrorInvalidValue;
   // the gather enumerates the controlled subspace; targets are part of it
   Special sp = make_special(controls, nc, nullptr, 0);
   const uint64_t nitems = 1ull << (L.n - nc);
@@ -939,19 +961,23 @@ hipError_t launch_perm(const Launch& L, void* scratch, const int* targets, int k
     if (targets[j] != targets[0] + j) contiguous = 0;
   }
   const uint64_t tmask = mask_of(targets, k), cmask = mask_of(controls, nc);
+  const uint64_t mu = (mode == 2) ? ~0ull / N : 0;
+  const int whole = out_of_place ? 1 : 0;
   const unsigned g = (unsigned)std::min<uint64_t>((nitems + kBlock * 4 - 1) / (kBlock * 4), 1u << 20);
   if (L.c64) {
     hipLaunchKernelGGL(k_perm_gather<float>, dim3(g), dim3(kBlock), 0, L.stream, (const float2*)L.psi,
-                       (float2*)scratch, nitems, sp, cmask, tp, k, contiguous, tmask, d_finv, mode, A, B, Ainv, N,
-                       L.cond);
-    hipLaunchKernelGGL(k_perm_scatter<float>, dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi,
-                       (const float2*)scratch, nitems, sp, cmask, L.cond);
+                       (float2*)scratch, nitems, sp, cmask, tp, k, contiguous, tmask, d_finv, mode, B, Ainv, N, mu,
+                       whole, L.cond);
+    if (!out_of_place)
+      hipLaunchKernelGGL(k_perm_scatter<float>, dim3(g), dim3(kBlock), 0, L.stream, (float2*)L.psi,
+                         (const float2*)scratch, nitems, sp, cmask, L.cond);
   } else {
     hipLaunchKernelGGL(k_perm_gather<double>, dim3(g), dim3(kBlock), 0, L.stream, (const double2*)L.psi,
-                       (double2*)scratch, nitems, sp, cmask, tp, k, contiguous, tmask, d_finv, mode, A, B, Ainv, N,
-                       L.cond);
-    hipLaunchKernelGGL(k_perm_scatter<double>, dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi,
-                       (const double2*)scratch, nitems, sp, cmask, L.cond);
+                       (double2*)scratch, nitems, sp, cmask, tp, k, contiguous, tmask, d_finv, mode, B, Ainv, N, mu,
+                       whole, L.cond);
+    if (!out_of_place)
+      hipLaunchKernelGGL(k_perm_scatter<double>, dim3(g), dim3(kBlock), 0, L.stream, (double2*)L.psi,
+                         (const double2*)scratch, nitems, sp, cmask, L.cond);
   }
   return hipGetLastError();
 }

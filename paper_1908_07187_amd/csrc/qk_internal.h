@@ -152,9 +152,13 @@ hipError_t launch_diag_run(const Launch& L, const DiagRunArgs& run, const int* c
 hipError_t launch_dense_generic(const Launch& L, const int* targets, int k, const int* controls, int nc,
                                 const void* d_matrix);
 // mode 0: table d_finv; 1: affine x = Ainv (y - B) mod 2^k; 2: modular
-// multiplication x = Ainv y mod N for y < N (identity above N).
+// multiplication x = Ainv y mod N for y < N (identity above N, N < 2^32).
+// out_of_place (no controls only): the permuted state is written to `scratch`
+// (a whole second state buffer), which the caller then takes as the state;
+// otherwise the controlled subspace goes through `scratch` and back.
 hipError_t launch_perm(const Launch& L, void* scratch, const int* targets, int k, const int* controls, int nc,
-                       const uint32_t* d_finv, int mode, uint64_t A, uint64_t B, uint64_t Ainv, uint64_t N);
+                       const uint32_t* d_finv, int mode, uint64_t A, uint64_t B, uint64_t Ainv, uint64_t N,
+                       bool out_of_place);
 
 // Measurement: partial sums -> finalize (outcome, cbit, scale, log) -> collapse.
 struct MeasBuffers {
