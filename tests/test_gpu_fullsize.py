@@ -69,6 +69,120 @@ def test_random26_depth40_matches_oracle_samples():
         s.close()
 
 
+def _bench_sim(dtype, fused):
+    """A simulator in the configuration bench.py times: complex128 strictly
+    gate by gate (diagonal runs off), or fused blocks with the autotuned
+    shape for 30-qubit states."""
+    import paper_1908_07187_amd as qk
+    from paper_1908_07187_amd import autotune
+    s = qk.Sim(dtype)
+    if not fused:
+        s.set_tuning("diag_runs", 0)
+        return s
+    cfg = autotune.lookup(30, dtype) or {"fusion": 5}
+    for key in autotune.SHAPE_KEYS:
+        if key in cfg:
+            s.set_tuning(key, cfg[key])
+    s.set_fusion(cfg.get("fusion", 5) or 5)
+    return s
+
+
+def _chunks(sim, rows=1 << 24):
+    """(lo, hi, amplitudes lo..hi-1 as complex128) through a zero-copy device view."""
+    import torch
+    ptr, nbytes = sim.state_ptr()
+    n = nbytes // (16 if sim.dtype == "c128" else 8)
+
+    class _View:
+        __cuda_array_interface__ = {"shape": (n,), "typestr": "<c16" if sim.dtype == "c128" else "<c8",
+                                    "data": (ptr, False), "version": 3}
+    t = torch.as_tensor(_View(), device="cuda")
+    for lo in range(0, n, rows):
+        hi = min(n, lo + rows)
+        yield lo, hi, t[lo:hi].cpu().numpy().astype(np.complex128)
+
+
+def _c64_norm_bound(n_sweeps):
+    """|<psi|psi> - 1| after n_sweeps complex64 sweeps from a unit-norm state:
+    each sweep rounds every amplitude it writes with relative error at most
+    about 2 u (u = 2^-24, one complex multiply-add), so the squared norm moves
+    by at most 4 u per sweep to first order; the bound adds these worst cases."""
+    return 4.0 * 2.0 ** -24 * max(1, n_sweeps)
+
+
+@pytest.fixture(scope="module")
+def oracle26():
+    circ = W.c2_random_rzz(n=26, depth=40, seed=0)
+    _say("oracle 26q depth 40 (whole state, host threads)")
+    ref, _, _ = oracle.run(circ, omp=True)
+    return circ, ref
+
+
+@pytest.mark.parametrize("dtype,fused", [("c128", False), ("c64", True), ("c128", True)])
+def test_random26_depth40_whole_state_matches_oracle(oracle26, dtype, fused):
+    """The 26-qubit depth-40 circuit (seed 0), every one of its 2^26
+    amplitudes against the oracle: complex128 gate by gate, complex64 and
+    complex128 with fused blocks.  Fidelity for complex64 on FP64-normalised
+    states (the complex64 acceptance rule)."""
+    circ, ref = oracle26
+    _say(f"26q depth 40 {dtype} fused={fused}")
+    s = _bench_sim(dtype, fused)
+    qk_prog(circ).run(s)
+    got = s.state().astype(np.complex128)
+    sweeps = s.stats()["sweeps"]
+    s.close()
+    d = float(np.max(np.abs(got - ref)))
+    _say(f"  max|d| = {d:.3e}, sweeps {sweeps}")
+    if dtype == "c128":
+        assert d <= 1e-12
+    else:
+        assert d <= 2e-5
+        f = abs(np.vdot(ref, got)) ** 2 / (np.vdot(ref, ref).real * np.vdot(got, got).real)
+        drift = abs(np.vdot(got, got).real - 1.0)
+        _say(f"  fidelity {f!r}, |norm^2 - 1| = {drift:.3e} (bound {_c64_norm_bound(sweeps):.3e})")
+        assert f >= 1 - 1e-6
+        assert drift <= _c64_norm_bound(sweeps)
+
+
+def qk_prog(circ):
+    import paper_1908_07187_amd as qk
+    return qk.Program(circ)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_random30_split_depth40_whole_state_matches_oracle_product(dtype):
+    """30 qubits, depth 40, the layer recipe with two-qubit gates kept inside
+    the even and the odd qubits: every gate still sweeps the whole 30-qubit
+    state (bench configuration: complex128 gate by gate, complex64 fused),
+    and the exact result is the product of two 15-qubit oracle states, so all
+    2^30 amplitudes are compared.  Unlike circuit-then-inverse, this sees a
+    kernel that applies a wrong but invertible map (such as U transposed)."""
+    from oracle.product import ProductState
+    n = 30
+    circ = W.c2_split_layers(n=n, depth=40, seed=0, groups=2)
+    parts = [oracle.run(W.restrict(circ, list(range(g, n, 2))))[0] for g in range(2)]
+    ps = ProductState(parts, n)
+    _say(f"30q split depth 40 {dtype}")
+    s = _bench_sim(dtype, fused=(dtype == "c64"))
+    qk_prog(circ).run(s)
+    sweeps = s.stats()["sweeps"]
+    worst, dot, nrm = 0.0, 0.0 + 0.0j, 0.0
+    for lo, hi, got in _chunks(s):
+        ref = ps.chunk(lo, hi)
+        worst = max(worst, float(np.max(np.abs(got - ref))))
+        dot += np.vdot(ref, got)
+        nrm += np.vdot(got, got).real
+    s.close()
+    _say(f"  max|d| = {worst:.3e}, sweeps {sweeps}")
+    if dtype == "c128":
+        assert worst <= 1e-12
+    else:
+        f = abs(dot) ** 2 / nrm          # the product state has unit norm
+        _say(f"  fidelity {f!r}, |norm^2 - 1| = {abs(nrm - 1):.3e}")
+        assert worst <= 2e-5 and f >= 1 - 1e-6
+        assert abs(nrm - 1.0) <= _c64_norm_bound(sweeps)
+
+
 def test_random30_depth40_forward_then_inverse_is_identity():
     """30 qubits, complex128, gate by gate: the circuit followed by its inverse
     returns |0...0> with amplitude 1 (phase included)."""

@@ -430,3 +430,29 @@ def test_paper_order_of_two_mod_24_bit_number():
         x = (x * a) % N
         r += 1
     assert r == fact["order"] and r % fact["divisor_estimate"] == 0
+
+
+# --------------------------------------------------------------- product states (split circuits)
+
+@pytest.mark.parametrize("n,groups,depth", [(12, 2, 6), (12, 3, 5), (18, 2, 4), (17, 2, 3)])
+def test_split_circuit_state_is_the_product_of_its_groups(n, groups, depth):
+    """A circuit whose two-qubit gates stay inside the groups q mod G: the
+    oracle's full state equals the product of the groups' states, each from
+    the oracle on the group alone (this pins the product evaluator used at
+    sizes the oracle cannot run whole)."""
+    from oracle.product import ProductState
+    c = W.c2_split_layers(n=n, depth=depth, seed=n + groups, groups=groups)
+    full, _, _ = oracle.run(c)
+    parts = [oracle.run(W.restrict(c, list(range(g, n, groups))))[0] for g in range(groups)]
+    ps = ProductState(parts, n)
+    assert np.max(np.abs(ps.chunk(0, 1 << n) - full)) <= 1e-13
+    lo = (1 << n) // 3
+    assert np.max(np.abs(ps.chunk(lo, lo + 777) - full[lo:lo + 777])) <= 1e-13
+    # every gate of the split circuit is kept by exactly one group
+    assert sum(len(W.restrict(c, list(range(g, n, groups))).gate_ops()) for g in range(groups)) == len(c.gate_ops())
+
+
+def test_restrict_refuses_a_coupling_gate():
+    c = W.c2_random_rzz(n=6, depth=2, seed=0)
+    with pytest.raises(ValueError):
+        W.restrict(c, [0, 2, 4])

@@ -174,6 +174,50 @@ def c2_random_rzz(n: int = 30, depth: int = 40, seed: int = 0) -> Circuit:
     return c0_random_layers(n=n, layers=depth, seed=seed, rzz=True)
 
 
+def c2_split_layers(n: int = 30, depth: int = 40, seed: int = 0, groups: int = 2) -> Circuit:
+    """The 30-qubit layer recipe with its two-qubit gates kept inside fixed
+    qubit groups (qubit q in group q mod ``groups``): per layer the one-qubit
+    layer on every qubit, then per group a CNOT matching and an RZZ matching
+    of that group's qubits.  No gate couples two groups, so the final state is
+    the product of the groups' states (each group a circuit of n/groups
+    qubits), while every gate still sweeps the whole n-qubit state and
+    two-qubit gates pair bits far apart (q and q + groups * j)."""
+    rng = rng_for(seed)
+    ops = [add_qubits(n)]
+    members = [[q for q in range(n) if q % groups == g] for g in range(groups)]
+    for _ in range(depth):
+        _one_qubit_layer(ops, n, rng)
+        for mem in members:
+            for c, t in _matching(len(mem), rng):
+                ops.append(gate("X", [mem[t]], controls=[mem[c]]))
+        for mem in members:
+            pairs = _matching(len(mem), rng)
+            thetas = rng.uniform(0.0, 2.0 * math.pi, len(pairs))
+            for (a, b), th in zip(pairs, thetas):
+                ops.append(gate("RZZ", [mem[a], mem[b]], params=(float(th),)))
+    return Circuit(ops, label=f"split_layers_n{n}_d{depth}_g{groups}", seed=seed)
+
+
+def restrict(circ: Circuit, qubits: Sequence[int]) -> Circuit:
+    """The gates of a gate-only circuit that act inside ``qubits`` (every other
+    gate must act outside them), on a register of len(qubits) qubits with
+    qubits[j] renumbered j."""
+    pos = {q: j for j, q in enumerate(qubits)}
+    ops = [add_qubits(len(qubits))]
+    for op in circ.ops:
+        if op.kind != "gate":
+            continue
+        qs = list(op.targets) + list(op.controls)
+        inside = [q in pos for q in qs]
+        if not any(inside):
+            continue
+        if not all(inside):
+            raise ValueError(f"gate {op} couples the group to other qubits")
+        ops.append(gate(op.name, [pos[q] for q in op.targets], controls=[pos[q] for q in op.controls],
+                        conds=op.conds, params=op.params))
+    return Circuit(ops, user_gates=circ.user_gates, label=f"{circ.label}_part", seed=circ.seed)
+
+
 def qft_ops(bits: Sequence[int], inverse: bool = False) -> List[Op]:
     """The paper's QFT script (Appendix A, 3n x 1 branch): for each qubit c in
     order, Hadamard on c then CPHASE(d, c) with phi = pi / 2^(i+1) for the
