@@ -233,6 +233,25 @@ qk_status qk_measure(qk_sim sim, int32_t qubit, int32_t cbit, double u);
  * above 1 as the largest double below 1. */
 qk_status qk_measure_dev(qk_sim sim, int32_t qubit, int32_t cbit, const double* d_u);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the
+ * measurement of qk_measure_dev on a caller's state, with no simulator and no
+ * allocation.  d_state: 2^n_qubits amplitudes of `dtype` in device memory
+ * (qubit q = bit q of the index), collapsed and renormalised in place exactly
+ * as qk_measure_dev does (same kernels, same fixed-order FP64 sums); d_u: the
+ * uniform in device memory, read when the step executes (clamped into [0, 1));
+ * d_cbit (may be NULL): receives the outcome (0/1) unless its probability is
+ * 0; d_result (may be NULL): receives p0, p1 and the outcome as 3 doubles.
+ * Enqueued on hip_stream (NULL: the null stream of the current device);
+ * asynchronous.  The partial sums and the result live in a fixed device array
+ * of the library (16,448 bytes per GPU, kept until the process ends) instead
+ * of allocated memory, so calls that overlap on one GPU race: order them on
+ * one stream.  1 <= n_qubits <= QK_NOALLOC_MAX_QUBITS, else QK_E_ARG; errors
+ * are reported by qk_last_error(NULL). */
+#define QK_NOALLOC_MAX_QUBITS 40
+qk_status qk_measure_noalloc(qk_dtype dtype, void* d_state, int32_t n_qubits, int32_t qubit, const double* d_u,
+                             uint8_t* d_cbit, double* d_result, void* hip_stream);
+
 /* Test hook: force `outcome` (0/1).  Synchronises; QK_E_STATE if the outcome
  * has probability 0 (the state is then left unchanged). */
 qk_status qk_postselect(qk_sim sim, int32_t qubit, int32_t cbit, int32_t outcome);

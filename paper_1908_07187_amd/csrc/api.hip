@@ -1540,6 +1540,23 @@ qk_status qk_measure_dev(qk_sim s, int32_t qubit, int32_t cbit, const double* d_
   return QK_OK;
 }
 
+qk_status qk_measure_noalloc(qk_dtype dtype, void* d_state, int32_t n_qubits, int32_t qubit, const double* d_u,
+                             uint8_t* d_cbit, double* d_result, void* hip_stream) {
+  if (dtype != QK_C64 && dtype != QK_C128) return fail(nullptr, QK_E_ARG, "unknown dtype");
+  if (!d_state || !d_u) return fail(nullptr, QK_E_ARG, "d_state or d_u is NULL");
+  if (n_qubits < 1 || n_qubits > QK_NOALLOC_MAX_QUBITS)
+    return fail(nullptr, QK_E_ARG, "n_qubits must be 1.." + std::to_string(QK_NOALLOC_MAX_QUBITS) +
+                                       " (the fixed scratch covers one reduction grid of states up to that size)");
+  if (qubit < 0 || qubit >= n_qubits) return fail(nullptr, QK_E_ARG, "qubit out of range");
+  hipStream_t stream = (hipStream_t)hip_stream;
+  int device = -1;
+  hipError_t e = stream ? hipStreamGetDevice(stream, &device) : hipGetDevice(&device);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "measure_noalloc: device of the stream");
+  e = launch_measure_noalloc(device, stream, d_state, n_qubits, dtype == QK_C64, qubit, d_u, d_cbit, d_result);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "measure_noalloc");
+  return QK_OK;
+}
+
 qk_status qk_postselect(qk_sim s, int32_t qubit, int32_t cbit, int32_t outcome) {
   if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
   if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");

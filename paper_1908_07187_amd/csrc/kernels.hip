@@ -3,6 +3,7 @@
 // conditions on the device first and exits uniformly when one fails, so
 // measurement outcomes steer later gates without a host round trip.
 #include <algorithm>
+#include <mutex>
 #include <type_traits>
 
 #include "qk_internal.h"
@@ -1046,7 +1047,8 @@ __global__ __launch_bounds__(kBlock) void k_prob_partial(const V2<R>* __restrict
 
 __global__ __launch_bounds__(kBlock) void k_meas_finalize(const double* __restrict__ partials, int nblocks, double u,
                                                           const double* d_u, int forced, int cbit, double* result,
-                                                          uint8_t* cbits, double* log, uint32_t* log_count) {
+                                                          uint8_t* cbits, double* log, uint32_t* log_count,
+                                                          double* out) {
   __shared__ double sh[4];
   double a0 = 0, a1 = 0;
   for (int b = threadIdx.x; b < nblocks; b += kBlock) {
@@ -1066,12 +1068,19 @@ __global__ __launch_bounds__(kBlock) void k_meas_finalize(const double* __restri
     result[2] = scale;
     result[3] = (double)oc;
     if (cbit >= 0 && po > 0.0) cbits[cbit] = (uint8_t)oc;
-    const uint32_t c = *log_count;
-    const uint32_t slot = c % (uint32_t)kMeasLog;
-    log[3 * slot] = p0;
-    log[3 * slot + 1] = p1;
-    log[3 * slot + 2] = (double)oc;
-    *log_count = c + 1;
+    if (log) {
+      const uint32_t c = *log_count;
+      const uint32_t slot = c % (uint32_t)kMeasLog;
+      log[3 * slot] = p0;
+      log[3 * slot + 1] = p1;
+      log[3 * slot + 2] = (double)oc;
+      *log_count = c + 1;
+    }
+    if (out) {
+      out[0] = p0;
+      out[1] = p1;
+      out[2] = (double)oc;
+    }
   }
 }
 
@@ -1115,7 +1124,7 @@ hipError_t launch_measure(const Launch& L, int qubit, int cbit, double u, const 
     hipLaunchKernelGGL(k_prob_partial<double>, dim3(nb), dim3(kBlock), 0, L.stream, (const double2*)L.psi, dim,
                        per_block, 1ull << qubit, mb.partials);
   hipLaunchKernelGGL(k_meas_finalize, dim3(1), dim3(kBlock), 0, L.stream, (const double*)mb.partials, nb, u, d_u,
-                     forced, cbit, mb.result, mb.cbits, mb.log, mb.log_count);
+                     forced, cbit, mb.result, mb.cbits, mb.log, mb.log_count, mb.out);
   const uint64_t npairs = dim >> 1;
   // four pairs per thread on large states; one on small ones, where the
   // launch would otherwise have too few workgroups to cover the latency
@@ -1132,6 +1141,56 @@ hipError_t launch_measure(const Launch& L, int qubit, int cbit, double u, const 
   if (npairs >= (1ull << 24)) collapse(std::integral_constant<int, 4>{});
   else collapse(std::integral_constant<int, 1>{});
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- allocation-free measurement
+// The measurement kernels need a scratch buffer for the partial sums of the
+// reduction grid and the 4-double result.  For callers that cannot allocate,
+// it is this file-scope device array (one copy per GPU, held until the process
+// ends).  Host code never passes the array's name to a kernel: its device
+// address is looked up once per device and kept.
+
+constexpr size_t kNoAllocDoubles = 2 * kReduceBlocks + 8;   // 16,448 bytes
+static __device__ __align__(256) double scratch[kNoAllocDoubles];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[kMaxDevices] = {};
+
+static hipError_t noalloc_scratch(int device, double** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    int prev = -1;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return e;
+    if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != device) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = (double*)p;
+  }
+  *out = g_scratch_ptr[device];
+  return hipSuccess;
+}
+
+hipError_t launch_measure_noalloc(int device, hipStream_t stream, void* psi, int n, bool c64, int qubit,
+                                  const double* d_u, uint8_t* d_cbit, double* d_out) {
+  double* sc = nullptr;
+  hipError_t e = noalloc_scratch(device, &sc);
+  if (e != hipSuccess) return e;
+  MeasBuffers mb;
+  mb.partials = sc;                       // 2 * kReduceBlocks doubles, every slot rewritten by each call
+  mb.result = sc + 2 * kReduceBlocks;     // p0, p1, scale, outcome
+  mb.cbits = d_cbit;
+  mb.out = d_out;
+  Launch L{};
+  L.stream = stream;
+  L.n = n;
+  L.c64 = c64;
+  L.psi = psi;
+  return launch_measure(L, qubit, d_cbit ? 0 : -1, 0.0, d_u, -1, mb);
 }
 
 // ---------------------------------------------------------------- inner product

@@ -162,15 +162,21 @@ hipError_t launch_perm(const Launch& L, void* scratch, const int* targets, int k
 
 // Measurement: partial sums -> finalize (outcome, cbit, scale, log) -> collapse.
 struct MeasBuffers {
-  double* partials;     // 2 * kReduceBlocks
-  double* result;       // p0, p1, scale, outcome
-  double* log;          // 3 * kMeasLog
-  uint32_t* log_count;  // entries written so far
-  uint8_t* cbits;
+  double* partials = nullptr;     // 2 * kReduceBlocks
+  double* result = nullptr;       // p0, p1, scale, outcome
+  double* log = nullptr;          // 3 * kMeasLog (nullptr: no log)
+  uint32_t* log_count = nullptr;  // entries written so far
+  uint8_t* cbits = nullptr;
+  double* out = nullptr;          // if set: p0, p1, outcome
 };
 int reduce_blocks_for(uint64_t count);
 hipError_t launch_measure(const Launch& L, int qubit, int cbit, double u, const double* d_u, int forced,
                           const MeasBuffers& mb);
+// The same measurement with its scratch in a file-scope device array (no
+// allocation); the outcome goes to d_cbit[0] and p0, p1, outcome to d_out
+// (either may be NULL).  Calls that overlap on one device share the array.
+hipError_t launch_measure_noalloc(int device, hipStream_t stream, void* psi, int n, bool c64, int qubit,
+                                  const double* d_u, uint8_t* d_cbit, double* d_out);
 hipError_t launch_inner_partials(const void* a, bool a64, const void* b, bool b64, uint64_t dim,
                                  double* partials, int nblocks, hipStream_t s);
 

@@ -106,6 +106,7 @@ SIGNATURES = {
     "qk_batch_num_jobs": (_I32, [_P, _I32P]),
     "qk_batch_last_error": (C.c_char_p, [_P]),
     "qk_plan_fusion": (_I32, [_I32, C.POINTER(QkOp), _I32, _I32, _I32P, _U64P, _I32P, _I32, _DP, _SZ]),
+    "qk_measure_noalloc": (_I32, [_I32, _P, _I32, _I32, _P, _P, _P, _P]),
     "qk_last_error": (C.c_char_p, [_P]),
     "qk_status_string": (C.c_char_p, [_I32]),
 }
@@ -406,6 +407,16 @@ class Sim:
         a, b, c = C.c_int64(), C.c_int64(), C.c_int64()
         self._chk(self.lib.qk_stats(self.h, C.byref(a), C.byref(b), C.byref(c)))
         return {"sweeps": a.value, "fused_blocks": b.value, "fused_gates": c.value}
+
+
+def measure_noalloc(dtype: str, d_state: int, n_qubits: int, qubit: int, d_u: int, d_cbit: int = 0,
+                    d_result: int = 0, stream: int = 0):
+    """qk_measure_noalloc on device addresses (plain integers; 0 = NULL)."""
+    lib = load()
+    st = lib.qk_measure_noalloc(DTYPES[dtype], C.c_void_p(d_state), int(n_qubits), int(qubit), C.c_void_p(d_u),
+                                C.c_void_p(d_cbit or None), C.c_void_p(d_result or None), C.c_void_p(stream or None))
+    if st != QK_OK:
+        raise QKError(st, lib.qk_last_error(None).decode())
 
 
 # ------------------------------------------------------------------ graphs

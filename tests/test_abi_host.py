@@ -287,3 +287,18 @@ def test_sparse_simulator_rejects_before_device_work():
     lib2, h2 = _sim_nogpu()
     assert lib2.qk_sparse_nnz(h2, C.byref(nnz)) == -7
     lib2.qk_destroy(h2)
+
+
+def test_noalloc_measure_rejects_before_device_work():
+    """qk_measure_noalloc checks its sizes and pointers before it looks up its
+    device array or launches anything (so this runs without a GPU; the
+    addresses below are never dereferenced)."""
+    lib = qk.load()
+    fake = C.c_void_p(0x1000)
+    cases = [(qk.QK_C128, None, 4, 0, fake), (qk.QK_C128, fake, 4, 0, None), (7, fake, 4, 0, fake),
+             (qk.QK_C128, fake, 41, 0, fake), (qk.QK_C64, fake, 0, 0, fake), (qk.QK_C128, fake, 4, 4, fake),
+             (qk.QK_C128, fake, 4, -1, fake)]
+    for dt, st, n, q, du in cases:
+        assert lib.qk_measure_noalloc(dt, st, n, q, du, None, None, None) == -1, (dt, n, q)
+    assert lib.qk_measure_noalloc(qk.QK_C128, fake, 41, 0, fake, None, None, None) == -1
+    assert b"n_qubits" in lib.qk_last_error(None)
