@@ -1019,26 +1019,60 @@ int reduce_blocks_for(uint64_t count) {
   return (int)b;
 }
 
+// Each block sums a fixed contiguous range with 16-byte loads (one complex128
+// or two complex64 amplitudes), eight loads in flight per thread, and a
+// fixed thread -> element mapping and reduction tree.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_prob_partial(const V2<R>* __restrict__ psi, uint64_t dim,
                                                          uint64_t per_block, uint64_t qbit, double* partials) {
+  constexpr int VEC = 16 / (int)sizeof(V2<R>);   // amplitudes per load
+  constexpr int U = 8;                            // loads in flight per thread
+  using L = typename std::conditional<VEC == 1, double2, float4>::type;
   __shared__ double sh[4];
-  const uint64_t start = (uint64_t)blockIdx.x * per_block;
-  const uint64_t end = (start + per_block < dim) ? start + per_block : dim;
-  double s0[4] = {0, 0, 0, 0}, s1[4] = {0, 0, 0, 0};
-  for (uint64_t i = start + threadIdx.x; i < end; i += 4 * kBlock) {
+  const L* p = reinterpret_cast<const L*>(psi);
+  const uint64_t start = (uint64_t)blockIdx.x * per_block / VEC;
+  const uint64_t end = ((uint64_t)blockIdx.x * per_block + per_block < dim ? (uint64_t)blockIdx.x * per_block + per_block
+                                                                            : dim) / VEC;
+  double s0[U], s1[U];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < U; ++u) s0[u] = s1[u] = 0.0;
+  for (uint64_t i = start + threadIdx.x; i < end; i += (uint64_t)U * kBlock) {
+    L a[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t ii = i + (uint64_t)u * kBlock;
+      if (ii < end) a[u] = p[ii];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
       const uint64_t ii = i + (uint64_t)u * kBlock;
       if (ii < end) {
-        const V2<R> a = psi[ii];
-        const double p = (double)a.x * (double)a.x + (double)a.y * (double)a.y;
-        if (ii & qbit) s1[u] += p; else s0[u] += p;
+        if constexpr (VEC == 1) {
+          const double w = a[u].x * a[u].x + a[u].y * a[u].y;
+          if (ii & qbit) s1[u] += w; else s0[u] += w;
+        } else {
+          const double w0 = (double)a[u].x * (double)a[u].x + (double)a[u].y * (double)a[u].y;
+          const double w1 = (double)a[u].z * (double)a[u].z + (double)a[u].w * (double)a[u].w;
+          if (qbit == 1) {
+            s0[u] += w0;
+            s1[u] += w1;
+          } else if ((2 * ii) & qbit) {
+            s1[u] += w0 + w1;
+          } else {
+            s0[u] += w0 + w1;
+          }
+        }
       }
     }
   }
-  const double t0 = block_sum((s0[0] + s0[1]) + (s0[2] + s0[3]), sh);
-  const double t1 = block_sum((s1[0] + s1[1]) + (s1[2] + s1[3]), sh);
+  double t0 = 0, t1 = 0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    t0 += s0[u];
+    t1 += s1[u];
+  }
+  t0 = block_sum(t0, sh);
+  t1 = block_sum(t1, sh);
   if (threadIdx.x == 0) {
     partials[2 * blockIdx.x] = t0;
     partials[2 * blockIdx.x + 1] = t1;
