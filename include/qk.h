@@ -362,6 +362,11 @@ qk_status qk_sync(qk_sim sim);
  *                 default, 64; capped by registers for large k);
  *   "mfma_areg"   blocks of 5-6 qubits: 1 keeps the matrix fragments in
  *                 registers, 0 (default) re-reads them from LDS per tile;
+ *   "mfma_lds"    blocks of 4-5 qubits: 1 stages each workgroup's tile
+ *                 (2^k rows x 1 KiB) through LDS so that global memory is read
+ *                 and written in address order, 0: each wave loads its own
+ *                 register tile;
+ *   "lds_wg"      workgroups per compute unit of the LDS-staged kernel (1..4);
  *   "xcd"         1 (default): the per-gate sweeps renumber their workgroups
  *                 so that each of the 8 XCDs sweeps one contiguous range,
  *                 0: workgroups in launch order;
@@ -437,6 +442,16 @@ typedef struct qk_op {
 } qk_op;
 
 typedef struct qk_batch_s* qk_batch;
+
+/* A whole op list on one simulator in one call (for hosts that submit a
+ * circuit per request, such as a serving loop): each QK_OP_GATE record is
+ * qk_apply_gate(gate, targets, controls, conds, params) with the gate's own
+ * parameter count (builtins; j for affine and modular families, from
+ * `param`), each QK_OP_MEASURE record is qk_measure(qubit, cbit, u).  Gate
+ * ids may be builtins or gates defined on `sim`.  Stops at the first failing
+ * record: its status is returned, qk_last_error names the record, and
+ * *n_done (may be NULL) receives the number of records applied. */
+qk_status qk_apply_ops(qk_sim sim, const qk_op* ops, int32_t n_ops, int32_t* n_done);
 
 /* Host only (no device work): the fused blocks qk_set_fusion(max_k) would
  * form for a list of unconditioned builtin gates (op records as for

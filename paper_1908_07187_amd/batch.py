@@ -38,6 +38,12 @@ def circuit_ops(circuit) -> List[QkOp]:
     return out
 
 
+def op_array(circuit):
+    """circuit_ops as one ctypes array (what qk_batch_add and qk_apply_ops take)."""
+    ops = circuit_ops(circuit)
+    return (QkOp * max(1, len(ops)))(*ops), len(ops)
+
+
 def add_circuit(batch, circuit) -> int:
     if circuit.init_state is not None:
         raise ValueError("batched circuits start from |0...0>")

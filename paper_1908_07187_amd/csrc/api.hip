@@ -459,6 +459,10 @@ qk_status run_dense(qk_sim s, const std::vector<int>& targets, const std::vector
     qk_status st = arena_put(s, packed.data(), packed.size(), &dmat);
     if (st) return st;
   }
+  if (s->tune.mfma_lds && mfma_lds_supported(s->n, k, controls.data(), (int)controls.size(), s->c64))
+    return check_launch(
+        s, launch_dense_lds(L, targets.data(), k, controls.data(), (int)controls.size(), dmat, s->tune.lds_wg),
+        "dense (matrix cores, LDS tiles)");
   if (mfma_supported(s->n, k, (int)controls.size(), s->c64))
     return check_launch(
         s, launch_dense_mfma(L, targets.data(), k, controls.data(), (int)controls.size(), dmat, s->tune.mfma_waves),
@@ -1540,6 +1544,42 @@ qk_status qk_measure_dev(qk_sim s, int32_t qubit, int32_t cbit, const double* d_
   return QK_OK;
 }
 
+qk_status qk_apply_ops(qk_sim s, const qk_op* ops, int32_t n_ops, int32_t* n_done) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (n_done) *n_done = 0;
+  if (n_ops < 0 || (n_ops > 0 && !ops)) return fail(s, QK_E_ARG, "bad op list");
+  for (int32_t i = 0; i < n_ops; ++i) {
+    const qk_op& o = ops[i];
+    qk_status st;
+    if (o.kind == QK_OP_GATE) {
+      if (o.n_targets < 1 || o.n_targets > 2 || o.n_controls < 0 || o.n_controls > 4 || o.n_conds < 0 ||
+          o.n_conds > 2) {
+        st = fail(s, QK_E_ARG, "counts exceed the record's arrays");
+      } else {
+        // builtins take their own parameter count; permutation families take j
+        int np = 0;
+        if (const BuiltinInfo* bi = builtin_by_id(o.gate)) np = bi->nparams;
+        else if (o.gate >= kUserBase && o.gate - kUserBase < (int)s->ugates.size()) {
+          const int kind = s->ugates[o.gate - kUserBase]->kind;
+          np = (kind == U_AFFINE || kind == U_MODMUL) ? 1 : 0;
+        }
+        st = qk_apply_gate(s, o.gate, o.targets, o.n_targets, o.controls, o.n_controls, o.conds, o.n_conds,
+                           &o.param, np);
+      }
+    } else if (o.kind == QK_OP_MEASURE) {
+      st = qk_measure(s, o.qubit, o.cbit, o.u);
+    } else {
+      st = fail(s, QK_E_ARG, "unknown op kind");
+    }
+    if (st) {
+      s->err = "op " + std::to_string(i) + ": " + s->err;
+      return st;
+    }
+    if (n_done) *n_done = i + 1;
+  }
+  return QK_OK;
+}
+
 qk_status qk_measure_noalloc(qk_dtype dtype, void* d_state, int32_t n_qubits, int32_t qubit, const double* d_u,
                              uint8_t* d_cbit, double* d_result, void* hip_stream) {
   if (dtype != QK_C64 && dtype != QK_C128) return fail(nullptr, QK_E_ARG, "unknown dtype");
@@ -2165,6 +2205,12 @@ qk_status qk_set_tuning(qk_sim s, const char* key, int32_t value) {
     s->tune.lane_items = value;
   } else if (k == "mfma_areg") {
     s->tune.mfma_areg = value != 0;
+  } else if (k == "mfma_lds") {
+    if (value != 0 && value != 1) return fail(s, QK_E_ARG, "mfma_lds must be 0 or 1");
+    s->tune.mfma_lds = value;
+  } else if (k == "lds_wg") {
+    if (value < 1 || value > 4) return fail(s, QK_E_ARG, "lds_wg must be 1..4");
+    s->tune.lds_wg = value;
   } else if (k == "diag_runs") {
     if (value != 0 && value != 1) return fail(s, QK_E_ARG, "diag_runs must be 0 or 1");
     qk_status st = flush(s);
@@ -2198,6 +2244,8 @@ qk_status qk_get_tuning(qk_sim s, const char* key, int32_t* value) {
   else if (k == "mfma_waves") *value = s->tune.mfma_waves;
   else if (k == "mfma_cols") *value = s->tune.mfma_cols;
   else if (k == "mfma_areg") *value = s->tune.mfma_areg;
+  else if (k == "mfma_lds") *value = s->tune.mfma_lds;
+  else if (k == "lds_wg") *value = s->tune.lds_wg;
   else if (k == "diag_runs") *value = s->tune.diag_runs;
   else if (k == "swap_relabel") *value = s->tune.swap_relabel;
   else if (k == "xcd") *value = s->tune.xcd;

@@ -228,6 +228,289 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::V* psi, cons
   }
 }
 
+// ---------------------------------------------------------------- LDS-staged tiles
+// The same GEMM with the tile staged through LDS by the whole workgroup, so
+// that global memory is read and written in address order: every wave-wide
+// access is 64 consecutive 16-byte pieces (1 KiB).  Tile = 2^K rows (gate
+// index m) x CW = 2^LB columns (the LB lowest bits outside targets and
+// controls); since the column bits are the lowest free bits, the tile's
+// amplitudes form runs of at least CW consecutive amplitudes.  The tile-local
+// address index j has one bit per bit of U = targets + column bits (ascending);
+// both its global offset and its LDS position (row m, column c) are sums of
+// per-bit weights, so a thread's part and each step's part are added.
+//   load:    global (address order) -> registers, prefetched one tile ahead;
+//   stage:   registers -> LDS X[m][c] (row stride CW + 1);
+//   compute: wave w takes column groups [w*GW, (w+1)*GW); MFMA as above, the
+//            B operand from LDS, results written over the wave's own columns;
+//   store:   LDS -> global in address order.
+static int g_ncu = 0;
+
+struct LdsTileArgs {
+  int tpos[6];         // target bit of gate index bit j
+  int nu;              // bits of the tile index (K + LB)
+  uint32_t lw[13];     // LDS offset (in amplitudes) of tile-index bit b
+  uint64_t gw[13];     // global offset (in amplitudes) of tile-index bit b
+};
+
+template <typename R, int K, int LB, bool NT>
+__global__ __launch_bounds__(256) void k_dense_lds(typename MF<R>::V* psi, const typename MF<R>::V* __restrict__ mat,
+                                                   uint64_t ntiles, Special sp, uint64_t cmask, LdsTileArgs ta,
+                                                   CondArgs cond, bool xcd) {
+  using V = typename MF<R>::V;
+  using Acc = typename MF<R>::Acc;
+  constexpr int DIM = 1 << K;
+  constexpr int CW = 1 << LB;
+  constexpr int S = CW + 1;                   // LDS row stride (amplitudes)
+  constexpr int RT = (2 * DIM + 15) / 16;
+  constexpr int KS = DIM / 4;
+  constexpr int NF = RT * KS * 2;
+  constexpr int GW = CW / 64;                 // 16-column groups per wave
+  constexpr int VEC = 16 / (int)sizeof(V);    // amplitudes per 16-byte access (1 or 2)
+  constexpr int E = DIM * CW;                 // amplitudes per tile
+  constexpr int NA = E / (256 * VEC);         // accesses per thread per tile
+  static_assert(GW >= 1 && NA >= 1, "tile too small for a 256-thread workgroup");
+  using Q = typename std::conditional<VEC == 1, V, floatx4>::type;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  R* afrag = reinterpret_cast<R*>(smem_raw);
+  V* X = reinterpret_cast<V*>(smem_raw + (size_t)NF * 64 * sizeof(R));
+
+  if (!conds_ok_m(cond)) return;
+
+  for (int e = threadIdx.x; e < NF * 64; e += 256) {
+    const int l = e & 63, f = e >> 6;
+    const int part = f & 1, ks = (f >> 1) % KS, rt = (f >> 1) / KS;
+    const int i = l & 15, kk = l >> 4;
+    const int rho = 16 * rt + (MF<R>::kRowsByReg ? (4 * (i & 3) + (i >> 2)) : i);
+    const int r = rho >> 1, m = 4 * ks + kk;
+    R val = 0;
+    if (r < DIM) {
+      const V z = mat[r * DIM + m];
+      if ((rho & 1) == 0) val = part == 0 ? z.x : -z.y;
+      else val = part == 0 ? z.y : z.x;
+    }
+    afrag[e] = val;
+  }
+
+  // this thread's part of the tile index: bits of VEC * threadIdx.x; the
+  // remaining bits come from the access number a (j = VEC * (tid + 256 a) + v)
+  uint32_t lofs_t = 0;
+  uint64_t gofs_t = 0;
+  {
+    const uint32_t jt = (uint32_t)(VEC * threadIdx.x);
+    for (int b = 0; b < ta.nu; ++b)
+      if ((jt >> b) & 1u) {
+        lofs_t += ta.lw[b];
+        gofs_t += ta.gw[b];
+      }
+  }
+  uint32_t lofs_a[NA];
+  uint64_t gofs_a[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) {
+    const uint32_t ja = (uint32_t)(VEC * 256 * a);
+    uint32_t lo = 0;
+    uint64_t go = 0;
+    for (int b = 0; b < ta.nu; ++b)
+      if ((ja >> b) & 1u) {
+        lo += ta.lw[b];
+        go += ta.gw[b];
+      }
+    lofs_a[a] = lo + lofs_t;
+    gofs_a[a] = go + gofs_t;
+  }
+  const uint32_t lw0 = ta.lw[0];   // LDS offset of the second amplitude of a pair (VEC = 2)
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int h = lane >> 4, c = lane & 15;
+
+  uint64_t blk = blockIdx.x;
+  if (xcd && !(gridDim.x & 7)) blk = (blk & 7) * (gridDim.x >> 3) + (blk >> 3);
+  const uint64_t nwg = gridDim.x;
+
+  Q rg[NA];
+  auto gload = [&](uint64_t base) {
+#pragma unroll
+    for (int a = 0; a < NA; ++a) rg[a] = mld<NT>(reinterpret_cast<const Q*>(psi + base + gofs_a[a]));
+  };
+  uint64_t t = blk;
+  if (t >= ntiles) return;
+  uint64_t base = insert_zeros_m(t, sp) | cmask;
+  gload(base);
+  __syncthreads();   // A fragments staged
+  for (;;) {
+    // registers -> LDS
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      if constexpr (VEC == 1) {
+        X[lofs_a[a]] = rg[a];
+      } else {
+        V v0, v1;
+        v0.x = rg[a].x;
+        v0.y = rg[a].y;
+        v1.x = rg[a].z;
+        v1.y = rg[a].w;
+        X[lofs_a[a]] = v0;
+        X[lofs_a[a] + lw0] = v1;
+      }
+    }
+    __syncthreads();
+    const uint64_t tn = t + nwg;
+    const bool more = tn < ntiles;
+    const uint64_t nbase = more ? (insert_zeros_m(tn, sp) | cmask) : base;
+    if (more) gload(nbase);
+    // compute this wave's columns
+    Acc acc[RT][GW];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+      for (int g = 0; g < GW; ++g) acc[rt][g] = Acc{0, 0, 0, 0};
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+      V xb[GW];
+#pragma unroll
+      for (int g = 0; g < GW; ++g) xb[g] = X[(4 * ks + h) * S + 16 * (wv * GW + g) + c];
+#pragma unroll
+      for (int rt = 0; rt < RT; ++rt) {
+        const int f = (rt * KS + ks) * 2;
+        const R a0 = afrag[f * 64 + lane];
+        const R a1 = afrag[(f + 1) * 64 + lane];
+#pragma unroll
+        for (int g = 0; g < GW; ++g) {
+          acc[rt][g] = MF<R>::op(a0, xb[g].x, acc[rt][g]);
+          acc[rt][g] = MF<R>::op(a1, xb[g].y, acc[rt][g]);
+        }
+      }
+    }
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt) {
+      const int r0 = 8 * rt + 2 * h;
+      if (r0 < DIM) {
+#pragma unroll
+        for (int g = 0; g < GW; ++g) {
+          const int col = 16 * (wv * GW + g) + c;
+          V v0, v1;
+          v0.x = acc[rt][g][0];
+          v0.y = acc[rt][g][1];
+          v1.x = acc[rt][g][2];
+          v1.y = acc[rt][g][3];
+          X[r0 * S + col] = v0;
+          X[(r0 + 1) * S + col] = v1;
+        }
+      }
+    }
+    __syncthreads();
+    // LDS -> global, address order
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      Q q;
+      if constexpr (VEC == 1) {
+        q = X[lofs_a[a]];
+      } else {
+        const V v0 = X[lofs_a[a]], v1 = X[lofs_a[a] + lw0];
+        q = floatx4{v0.x, v0.y, v1.x, v1.y};
+      }
+      mst<NT>(reinterpret_cast<Q*>(psi + base + gofs_a[a]), q);
+    }
+    if (!more) break;
+    __syncthreads();   // every store has read X before the next tile overwrites it
+    t = tn;
+    base = nbase;
+  }
+}
+
+template <typename R, int K, int LB, bool NT>
+static hipError_t launch_lds_k(const Launch& L, const void* mat, uint64_t ntiles, const Special& sp, uint64_t cmask,
+                               const LdsTileArgs& ta, int wg_per_cu) {
+  constexpr int DIM = 1 << K;
+  constexpr int RT = (2 * DIM + 15) / 16;
+  constexpr int KS = DIM / 4;
+  constexpr size_t shm = (size_t)RT * KS * 2 * 64 * sizeof(R) + (size_t)DIM * ((1 << LB) + 1) * 2 * sizeof(R);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_dense_lds<R, K, LB, NT>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  if (g_ncu <= 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      g_ncu = v;
+    else
+      g_ncu = 256;
+  }
+  const uint64_t cap = (uint64_t)g_ncu * (uint64_t)std::max(1, wg_per_cu);
+  const unsigned g = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(ntiles, cap));
+  hipLaunchKernelGGL((k_dense_lds<R, K, LB, NT>), dim3(g), dim3(256), shm, L.stream, (typename MF<R>::V*)L.psi,
+                     (const typename MF<R>::V*)mat, ntiles, sp, cmask, ta, L.cond, L.tune.xcd != 0);
+  return hipGetLastError();
+}
+
+// Tile widths of the LDS-staged kernel: 64 columns (complex128) and 128
+// (complex64), so that a tile is 2^K x 1 KiB.
+static int lds_lb(bool c64) { return c64 ? 7 : 6; }
+
+// Blocks of 4 or 5 qubits whose tile starts at bit 0 (no control on bit 0),
+// with enough free bits for a tile row.
+bool mfma_lds_supported(int n, int k, const int* controls, int nc, bool c64) {
+  for (int j = 0; j < nc; ++j)
+    if (controls[j] == 0) return false;
+  return (k == 4 || k == 5) && n - k - nc >= lds_lb(c64);
+}
+
+hipError_t launch_dense_lds(const Launch& L, const int* targets, int k, const int* controls, int nc,
+                            const void* d_matrix, int wg_per_cu) {
+  if (!mfma_lds_supported(L.n, k, controls, nc, L.c64)) return hipErrorInvalidValue;
+  const int lb = lds_lb(L.c64);
+  const int CW = 1 << lb;
+  uint64_t used = 0;
+  for (int j = 0; j < k; ++j) used |= 1ull << targets[j];
+  for (int j = 0; j < nc; ++j) used |= 1ull << controls[j];
+  int lpos[8];
+  int nl = 0;
+  for (int b = 0; b < L.n && nl < lb; ++b)
+    if (!((used >> b) & 1)) lpos[nl++] = b;
+  // tile index bits: targets and column bits in ascending bit order
+  std::vector<int> ubits(targets, targets + k);
+  for (int j = 0; j < lb; ++j) ubits.push_back(lpos[j]);
+  std::sort(ubits.begin(), ubits.end());
+  LdsTileArgs ta{};
+  ta.nu = (int)ubits.size();
+  for (int j = 0; j < k; ++j) ta.tpos[j] = targets[j];
+  for (int b = 0; b < ta.nu; ++b) {
+    const int bit = ubits[b];
+    ta.gw[b] = 1ull << bit;
+    uint32_t w = 0;
+    for (int j = 0; j < k; ++j)
+      if (targets[j] == bit) w = (uint32_t)(1u << j) * (uint32_t)(CW + 1);   // row m bit j
+    for (int j = 0; j < lb; ++j)
+      if (lpos[j] == bit) w = 1u << j;                                        // column bit j
+    ta.lw[b] = w;
+  }
+  // runs of the tile start at bit 0 (a 16-byte access covers two complex64 amplitudes)
+  if (ubits[0] != 0) return hipErrorInvalidValue;
+  std::vector<int> sv(targets, targets + k);
+  for (int j = 0; j < nc; ++j) sv.push_back(controls[j]);
+  for (int j = 0; j < lb; ++j) sv.push_back(lpos[j]);
+  Special sp = make_special(sv.data(), (int)sv.size(), nullptr, 0);
+  uint64_t cmask = 0;
+  for (int j = 0; j < nc; ++j) cmask |= 1ull << controls[j];
+  const uint64_t ntiles = 1ull << (L.n - k - nc - lb);
+  if (wg_per_cu <= 0) wg_per_cu = 2;
+  const bool nt = L.tune.nt == 2 || (L.tune.nt == 1 && state_streams(L));
+  if (L.c64) {
+    if (k == 4) return nt ? launch_lds_k<float, 4, 7, true>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu)
+                          : launch_lds_k<float, 4, 7, false>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu);
+    return nt ? launch_lds_k<float, 5, 7, true>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu)
+              : launch_lds_k<float, 5, 7, false>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu);
+  }
+  if (k == 4) return nt ? launch_lds_k<double, 4, 6, true>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu)
+                        : launch_lds_k<double, 4, 6, false>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu);
+  return nt ? launch_lds_k<double, 5, 6, true>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu)
+            : launch_lds_k<double, 5, 6, false>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu);
+}
+
 // Widest tile (columns per wave) that is instantiated for this block size
 // and keeps the double-buffered B registers of a lane at or below 64 VGPRs:
 // 64 columns up to k = 4; 32 up to k = 5, and at k = 6 for complex64; else 16.
@@ -242,8 +525,6 @@ bool mfma_supported(int n, int k, int nc, bool c64) {
   (void)c64;
   return k >= 2 && k <= 6 && n - k - nc >= 4;
 }
-
-static int g_ncu = 0;
 
 template <typename R, int K, int CW, bool NT, bool AREG>
 static hipError_t launch_k(const Launch& L, const void* mat, uint64_t nchunks, const Special& sp, uint64_t cmask,

@@ -73,6 +73,8 @@ struct Tuning {
   int xcd = 1;           // sweeps: 1 renumbers workgroups so each XCD sweeps a contiguous range
   int diag_runs = 1;     // 1: consecutive diagonal gates are held back and applied in one pass
   int swap_relabel = 1;  // 1: an uncontrolled SWAP on a dense state relabels the two qubits instead of moving data
+  int mfma_lds = 0;      // 1: blocks of 4-5 qubits use the LDS-staged matrix-core kernel
+  int lds_wg = 2;        // workgroups per CU of the LDS-staged kernel
 };
 
 // Where device work goes and what it works on.
@@ -270,6 +272,11 @@ hipError_t sp_project(const SpBufs& b, const uint64_t* pos, uint64_t nshots, con
 // as a complex GEMM per 16-column tile on 16x16x4 MFMA (f32 for complex64,
 // f64 for complex128).  Needs at least 4 qubits outside targets and controls.
 bool mfma_supported(int n, int k, int nc, bool c64);
+// The same GEMM with workgroup tiles staged through LDS (global memory in
+// address order, 1 KiB per wave access); blocks of 4 or 5 qubits.
+bool mfma_lds_supported(int n, int k, const int* controls, int nc, bool c64);
+hipError_t launch_dense_lds(const Launch& L, const int* targets, int k, const int* controls, int nc,
+                            const void* d_matrix, int wg_per_cu);
 hipError_t launch_dense_mfma(const Launch& L, const int* targets, int k, const int* controls, int nc,
                              const void* d_matrix, int waves_per_cu);
 

@@ -107,6 +107,7 @@ SIGNATURES = {
     "qk_batch_last_error": (C.c_char_p, [_P]),
     "qk_plan_fusion": (_I32, [_I32, C.POINTER(QkOp), _I32, _I32, _I32P, _U64P, _I32P, _I32, _DP, _SZ]),
     "qk_measure_noalloc": (_I32, [_I32, _P, _I32, _I32, _P, _P, _P, _P]),
+    "qk_apply_ops": (_I32, [_P, C.POINTER(QkOp), _I32, _I32P]),
     "qk_last_error": (C.c_char_p, [_P]),
     "qk_status_string": (C.c_char_p, [_I32]),
 }
@@ -297,6 +298,11 @@ class Sim:
         p = (C.c_double * max(1, len(params)))(*[float(x) for x in params])
         self._chk(self.lib.qk_apply_gate(self.h, gid, t, nt, c, nc, cd, len(conds), p, len(params)))
 
+    def apply_ops(self, ops, count: Optional[int] = None) -> None:
+        """A ctypes array of QkOp records (batch.op_array) in one call."""
+        done = C.c_int32()
+        self._chk(self.lib.qk_apply_ops(self.h, ops, len(ops) if count is None else count, C.byref(done)))
+
     # -- measurement
     def measure(self, qubit: int, cbit: int = -1, u: float = 0.0):
         self._chk(self.lib.qk_measure(self.h, qubit, cbit, u))
@@ -484,10 +490,14 @@ class Batch:
         if st != QK_OK:
             raise QKError(st, self.lib.qk_batch_last_error(self.h).decode())
 
-    def add(self, n: int, ncbits: int, ops) -> int:
-        arr = (QkOp * max(1, len(ops)))(*ops)
+    def add(self, n: int, ncbits: int, ops, count: Optional[int] = None) -> int:
+        """ops: a list of QkOp, or a ctypes QkOp array with its record count."""
+        if count is None:
+            arr, count = (QkOp * max(1, len(ops)))(*ops), len(ops)
+        else:
+            arr = ops
         job = C.c_int32()
-        self._chk(self.lib.qk_batch_add(self.h, n, ncbits, arr, len(ops), C.byref(job)))
+        self._chk(self.lib.qk_batch_add(self.h, n, ncbits, arr, count, C.byref(job)))
         self.jobs.append((n, ncbits))
         return job.value
 

@@ -2,9 +2,14 @@
 
 Jobs (a circuit and a dtype) arrive over time.  The loop, run on the host:
 
-* admits arrived jobs in arrival order while their state footprint
-  (2^n x 8 or 16 bytes) fits the HBM budget -- a job that can never fit is
-  refused with an error, never allowed to exhaust device memory;
+* admits arrived jobs in arrival order while their device footprint fits
+  the HBM budget (``footprint``: the state of 2^n x 8 or 16 bytes; on a
+  stream slot also the simulator's fixed buffers and, for circuits with
+  permutation gates, a second state-sized buffer) -- a job that can never fit
+  is refused with an error, never allowed to exhaust device memory;
+* takes each request as qk_op records prepared before it arrives (the form a
+  client would submit), so a job on a stream slot is enqueued with one C call
+  (qk_apply_ops) instead of one call per operation;
 * packs admitted small jobs (<= 13 qubits complex128, <= 14 complex64) into
   one persistent batch launch per dtype (``qk_batch_run``), up to two batch
   launches in flight per dtype, so jobs that arrive while a batch runs go into
@@ -77,8 +82,23 @@ class ServeReport:
     extra: Dict = field(default_factory=dict)
 
 
-def footprint(n: int, dtype: str) -> int:
-    return (1 << n) * AMP_BYTES[dtype]
+# Device memory a simulator holds beside its state: the constant arena chunk
+# of fused block matrices (32 MiB, allocated on first use) and the
+# measurement buffers, cbits and diagonal-run tables (under 1 MiB).
+SIM_OVERHEAD = (32 << 20) + (1 << 20)
+PERM_KINDS = ("table", "affine", "modmul")
+
+
+def footprint(n: int, dtype: str, circuit=None, batched: bool = False) -> int:
+    """Device bytes a job holds while admitted.  A batched job holds its state
+    inside the batch buffers; a job on its own stream slot holds its state,
+    a second state-sized buffer if it applies permutation gates (they gather
+    into it), and the simulator's fixed buffers."""
+    state = (1 << n) * AMP_BYTES[dtype]
+    if batched:
+        return state
+    perms = circuit is not None and any(g.get("kind") in PERM_KINDS for g in circuit.user_gates.values())
+    return state * (2 if perms else 1) + SIM_OVERHEAD
 
 
 class Server:
@@ -122,10 +142,23 @@ class Server:
         finally:
             gc.unfreeze()
 
+    @staticmethod
+    def _records(circ):
+        """A request as the loop receives it: qk_op records (one C call per job)
+        when the circuit has builtin gates only and starts from |0...0>, else
+        None (the circuit is then issued op by op)."""
+        if circ.init_state is not None or circ.user_gates:
+            return None
+        try:
+            return _batch.op_array(circ)
+        except ValueError:
+            return None
+
     def _serve(self, jobs, realtime, progress_every) -> ServeReport:
         torch = self.torch
         N = len(jobs)
         res = [JobResult(i, c.n_qubits, dt) for i, (_, c, dt) in enumerate(jobs)]
+        recs = [self._records(c) for _, c, _ in jobs]
         arrivals = [a if realtime else 0.0 for a, _, _ in jobs]
         streams = [torch.cuda.Stream() for _ in range(self.slots)]
         free_slots = deque(range(self.slots))
@@ -140,6 +173,7 @@ class Server:
         finished = 0
         nbatches = 0
         max_conc = 0
+        slept = 0.0            # host time spent waiting (nothing to admit or no room)
         t0 = time.perf_counter()
 
         def now():
@@ -170,7 +204,7 @@ class Server:
                         r.path, r.error = "failed", str(e)
                     r.done = now()
                     sim.close()
-                    used -= footprint(r.n, r.dtype)
+                    used -= footprint(r.n, r.dtype, jobs[j][1])
                     free_slots.append(slot)
                     finished += 1
                 else:
@@ -186,7 +220,7 @@ class Server:
                         r.cbits = b.cbits(bj)
                         r.norm2 = float(np.vdot(r.state, r.state).real)
                         r.done = now()
-                        used -= footprint(r.n, r.dtype)
+                        used -= footprint(r.n, r.dtype, batched=True)
                         finished += 1
                     b.clear()
                     bfree[dt].append(pi)
@@ -201,7 +235,8 @@ class Server:
                 j = pending.popleft()
                 _, circ, dt = jobs[j]
                 r = res[j]
-                fp = footprint(r.n, dt)
+                small_job = r.n <= self.small_max[dt] and recs[j] is not None
+                fp = footprint(r.n, dt, circ, batched=small_job)
                 if fp > self.budget:
                     r.path, r.error = "refused", f"state of {r.n} qubits ({fp} B) exceeds the HBM budget"
                     r.done = now()
@@ -210,7 +245,7 @@ class Server:
                 if used + fp > self.budget:
                     keep.append(j)
                     continue
-                if r.n <= self.small_max[dt] and circ.init_state is None:
+                if small_job:
                     if bfree[dt]:
                         small[dt].append(j)
                         used += fp
@@ -232,7 +267,13 @@ class Server:
                         _autotune.apply(sim, r.n, dt, self.tuning_cache)
                     elif self.fusion.get(dt, 0):
                         sim.set_fusion(self.fusion[dt])
-                    Program(circ).run(sim)
+                    if recs[j] is not None:
+                        sim.add_qubits(r.n)
+                        if circ.n_cbits:
+                            sim.add_cbits(circ.n_cbits)
+                        sim.apply_ops(*recs[j])
+                    else:
+                        Program(circ).run(sim)
                     sim.flush()
                     ev = torch.cuda.Event()
                     ev.record(streams[slot])
@@ -256,11 +297,12 @@ class Server:
                     r = res[j]
                     r.path = "batch"
                     try:
-                        members.append((j, _batch.add_circuit(b, jobs[j][1])))
+                        circ = jobs[j][1]
+                        members.append((j, b.add(circ.n_qubits, circ.n_cbits, recs[j][0], recs[j][1])))
                     except (QKError, ValueError) as e:
                         r.path, r.error = "failed", str(e)
                         r.done = now()
-                        used -= footprint(r.n, dt)
+                        used -= footprint(r.n, dt, batched=True)
                         finished += 1
                 if members:
                     b.run()
@@ -271,10 +313,12 @@ class Server:
                 else:
                     bfree[dt].append(pi)
             max_conc = max(max_conc, len(inflight_stream))
-            if finished < N and not pending and (nxt >= N or arrivals[nxt] > now()):
+            idle = ((finished < N and not pending and (nxt >= N or arrivals[nxt] > now()))
+                    or (finished < N and pending and not (free_slots or any(bfree[d] for d in bfree))))
+            if idle:
+                ts = time.perf_counter()
                 time.sleep(self.poll_sleep)
-            elif finished < N and pending and not (free_slots or any(bfree[d] for d in bfree)):
-                time.sleep(self.poll_sleep)
+                slept += time.perf_counter() - ts
 
         wall = now()
         for dt in bpool:
@@ -288,4 +332,5 @@ class Server:
                            failed=sum(r.path == "failed" for r in res),
                            circuits_per_s=len(ok) / span if span > 0 else float("nan"),
                            p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
-                           mean_ms=float(lat.mean()), batches=nbatches, max_concurrent_streams=max_conc)
+                           mean_ms=float(lat.mean()), batches=nbatches, max_concurrent_streams=max_conc,
+                           extra={"host_wait_s": slept, "host_busy_frac": 1.0 - slept / wall if wall > 0 else None})

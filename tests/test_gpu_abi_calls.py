@@ -240,3 +240,52 @@ def test_uncontrolled_permutations_trade_buffers_and_graphs_still_replay(dtype):
     _close(o.state(), s.state(), dtype)
     graph.close()
     s.close()
+
+
+# ---------------------------------------------------------------- op lists in one call
+
+@pytest.mark.parametrize("seed", range(3))
+def test_apply_ops_equals_one_call_per_op(seed):
+    """qk_apply_ops on a serving job's records gives the state and cbits of
+    the same ops issued one call at a time, bit for bit (and the oracle's)."""
+    import paper_1908_07187_amd as qk
+    from paper_1908_07187_amd import batch
+    rng = rng_for(950 + seed)
+    c, dtype = W.c4_job(rng, n_range=(10, 16), depth_range=(5, 12), p_measure=1.0)
+    arr, count = batch.op_array(c)
+    print(f"[gpu-ops] seed={seed} n={c.n_qubits} dtype={dtype} ops={count}", flush=True)
+    a = qk.Sim(dtype)
+    a.add_qubits(c.n_qubits)
+    a.add_cbits(c.n_cbits)
+    a.apply_ops(arr, count)
+    b = qk.run_circuit(c, dtype=dtype)
+    assert np.array_equal(a.state(), b.state())
+    assert list(a.read_cbits()) == list(b.read_cbits())
+    ref, rcb, recs = oracle.run(c)
+    if all(abs(r.u - r.P0) > 1e-9 for r in recs):
+        _close(ref, a.state(), dtype)
+        assert list(a.read_cbits()) == list(rcb)
+    a.close()
+    b.close()
+
+
+def test_apply_ops_stops_at_the_first_bad_record():
+    import ctypes as C
+    import paper_1908_07187_amd as qk
+    from paper_1908_07187_amd import batch
+    c = W.c0_random_layers(n=6, layers=2, seed=3)
+    arr, count = batch.op_array(c)
+    arr[5].targets[0] = 9                     # qubit out of range
+    s = qk.Sim("c128")
+    s.add_qubits(6)
+    done = C.c_int32(-1)
+    st = s.lib.qk_apply_ops(s.h, arr, count, C.byref(done))
+    assert st == -1 and done.value == 5
+    assert s.lib.qk_last_error(s.h).decode().startswith("op 5:")
+    # the five records before it were applied: the same as running them alone
+    t = qk.Sim("c128")
+    t.add_qubits(6)
+    t.apply_ops(arr, 5)
+    assert np.array_equal(s.state(), t.state())
+    s.close()
+    t.close()

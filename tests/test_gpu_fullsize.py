@@ -165,6 +165,7 @@ def test_random30_split_depth40_whole_state_matches_oracle_product(dtype):
     _say(f"30q split depth 40 {dtype}")
     s = _bench_sim(dtype, fused=(dtype == "c64"))
     qk_prog(circ).run(s)
+    s.flush()
     sweeps = s.stats()["sweeps"]
     worst, dot, nrm = 0.0, 0.0 + 0.0j, 0.0
     for lo, hi, got in _chunks(s):

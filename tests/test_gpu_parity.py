@@ -321,7 +321,8 @@ TUNINGS = [dict(nt=0, lane_bfly=0, sweep_items=1), dict(nt=0, lane_bfly=1, sweep
            dict(nt=1, lane_bfly=0, sweep_items=4, mfma_waves=16, mfma_cols=64),
            dict(nt=1, lane_bfly=1, sweep_items=1, lane_items=4, mfma_cols=32, diag_items=4),
            dict(nt=0, mfma_cols=64, mfma_waves=12, diag_items=2, mfma_areg=1),
-           dict(nt=1, mfma_cols=16, mfma_areg=1)]
+           dict(nt=1, mfma_cols=16, mfma_areg=1), dict(nt=1, mfma_lds=1, lds_wg=2),
+           dict(nt=0, mfma_lds=1, lds_wg=3, xcd=0)]
 
 
 @pytest.mark.parametrize("tuning", TUNINGS, ids=[str(i) for i in range(len(TUNINGS))])
