@@ -8,16 +8,23 @@ RZZ on a second matching (2400 gates), complex128, applied gate by gate from
 (2^n per dense or RZ-like gate, 2^(n-1) per CNOT) per second.
 
 Also reported on the same line:
-  roofline      the dominant kernel (the 2x2 butterfly sweep): algorithmic
-                bytes per launch (2^n * 16 B read + written) over its mean
-                launch time, timed with HIP events on the simulator's stream
-                during the timed steps, against the 8 TB/s HBM peak;
+  roofline      the kernel with the most total time among the timed gate
+                classes (one-qubit butterflies on low and strided targets, RZ
+                and RZZ diagonal sweeps): algorithmic bytes per launch (2^n x
+                16 B read + written) over its mean launch time, timed with HIP
+                events on the simulator's stream during the timed steps,
+                against the 8 TB/s HBM peak; every timed class is listed under
+                sweep_kernels;
   fused_c64     the same circuit in complex64 with fused k-qubit blocks on
                 matrix cores: gate throughput, sweeps, and fidelity against the
                 complex128 result of the timed steps;
   fused_c128    the same with complex128 states and FP64 matrix cores;
-  cpu_baseline  the FP64 oracle on the host cores, on the first gates of the
-                same 30-qubit circuit.
+  serving       a short run of the serving form (jobs of 8-26 qubits, Poisson
+                arrivals at 0.8x the closed-loop capacity): circuits/s,
+                p50/p99 latency, fidelity of sampled jobs;
+  batch12       12-qubit circuits in one persistent launch: circuits/s;
+  cpu_baseline  the FP64 oracle on the host cores (all threads, and one
+                thread), on the first gates of the same 30-qubit circuit.
 """
 from __future__ import annotations
 
@@ -56,6 +63,7 @@ def parse():
     ap.add_argument("--serve-capacity", type=float, default=0.0,
                     help="closed-loop capacity in circuits/s (0: measure it first)")
     ap.add_argument("--batch-circuits", type=int, default=2048)
+    ap.add_argument("--no-forms", action="store_true", help="leave out the serving and batch12 sub-records")
     ap.add_argument("--kernels-only", action="store_true",
                     help="run only a few strided-butterfly sweeps and a plain copy of known size (for PMC counters)")
     return ap.parse_args()
@@ -270,10 +278,53 @@ def main():
         out["diag_runs_c128"] = dr
     sims[0].close()
 
+    if not args.no_forms:
+        out["serving"] = serving_record(qk, torch, args)
+        out["batch12"] = batch_record(qk, torch, args)
+
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(circ, args)
 
     print(json.dumps(out), flush=True)
+
+
+def serving_record(qk, torch, args):
+    """The serving form, short: a closed-loop run over 200 jobs gives the
+    capacity, then 400 jobs arrive as a Poisson stream at 0.8x it."""
+    from paper_1908_07187_amd import benchforms
+    a = argparse.Namespace(**vars(args))
+    a.serve_jobs, a.serve_rates, a.serve_capacity = 400, "0.8", 0.0
+    r = benchforms.serve(a, qk, torch)
+    return {"circuits_per_s": r["value"], "p50_ms": r["latency_ms"]["p50"], "p99_ms": r["latency_ms"]["p99"],
+            "offered_per_s": r["config"]["rate_per_s"], "closed_loop_capacity_cps": r["closed_loop_capacity_cps"],
+            "jobs": r["config"]["jobs"], "fidelity_vs_c128_sampled": r["fidelity_vs_c128_sampled"],
+            "host_busy_frac": r.get("host_busy_frac"), "workload": r["config"]["workload"]}
+
+
+def batch_record(qk, torch, args):
+    """2048 random 12-qubit circuits (20 layers) in one persistent launch."""
+    import workloads as W
+    circs = [W.c0_random_layers(n=12, layers=20, seed=s) for s in range(2048)]
+    out = {}
+    for dtype in ("c128", "c64"):
+        b = qk.Batch(dtype)
+        for c in circs:
+            qk.add_circuit(b, c)
+        b.run()
+        b.sync()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            b.run()
+        b.sync()
+        dt = (time.perf_counter() - t0) / 5
+        b.close()
+        out[f"{dtype}_circuits_per_s"] = len(circs) / dt
+        out[f"{dtype}_ms_per_launch"] = dt * 1e3
+    out["workload"] = "2048 random 12-qubit circuits, 20 layers (360 gates each), one persistent launch"
+    print(f"[bench] batch12: {out['c128_circuits_per_s']:.0f} (c128) / {out['c64_circuits_per_s']:.0f} (c64) "
+          f"circuits/s", file=sys.stderr, flush=True)
+    return out
 
 
 def run_fused(qk, prog, torch, args, updates, ref_sim, dtype="c64"):
@@ -346,26 +397,48 @@ def run_diag_runs(qk, prog, torch, updates, ref_sim):
             "sweeps": stats["sweeps"], "diag_runs": stats["fused_blocks"], "gates_in_runs": stats["fused_gates"]}
 
 
-def cpu_baseline(circ, args):
-    """The oracle as it stands, on the first gates of the same circuit (OpenMP over host cores)."""
-    import oracle
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def _oracle_rate(circ, gates, omp):
     from oracle.oracle import Oracle
-    gates = circ.gate_ops()[: args.cpu_gates]
-    o = Oracle(omp=True)
-    n = circ.n_qubits
-    o.add_qubits(n)
+    o = Oracle(omp=omp)
+    o.add_qubits(circ.n_qubits)
     t0 = time.perf_counter()
     for op in gates:
         o.apply_op(op, circ.user_gates)
     dt = time.perf_counter() - t0
-    sub = type(circ)([circ.ops[0]] + gates)
-    upd = sub.amp_updates()
-    threads = o.threads
+    upd = type(circ)([circ.ops[0]] + gates).amp_updates()
+    threads = o.threads if omp else 1
     del o
+    return upd, dt, threads
+
+
+def cpu_baseline(circ, args):
+    """The oracle as it stands, on the first gates of the same circuit: the
+    OpenMP build over the host's threads (``value``), and the single-thread
+    build on the first two gates."""
+    n = circ.n_qubits
+    gates = circ.gate_ops()[: args.cpu_gates]
+    upd, dt, threads = _oracle_rate(circ, gates, omp=True)
+    upd1, dt1, _ = _oracle_rate(circ, gates[:2], omp=False)
+    print(f"[bench] oracle: {upd / dt:.3e} updates/s on {threads} threads, {upd1 / dt1:.3e} on one",
+          file=sys.stderr, flush=True)
     return {"value": upd / dt, "unit": "amplitude-updates/s", "cores": threads,
-            "kind": "oracle", "seconds": dt,
+            "kind": "oracle", "seconds": dt, "cpu_model": _cpu_model(), "nproc": os.cpu_count(),
             "sample": f"first {len(gates)} gates of the same {n}-qubit circuit (FP64 C oracle, OpenMP), "
-                      f"{upd:.3e} amplitude updates"}
+                      f"{upd:.3e} amplitude updates",
+            "single_thread": {"value": upd1 / dt1, "seconds": dt1,
+                              "sample": f"first 2 gates of the same circuit, single-thread build, "
+                                        f"{upd1:.3e} amplitude updates"}}
 
 
 if __name__ == "__main__":

@@ -3,9 +3,10 @@
 For a (qubit count, dtype) pair it times a short slice (a few layers) of the
 layered random recipe -- one-qubit layer, CNOT matching, RZZ matching -- on
 the device, first over the fusion width k in {0 (gate by gate), 3, 4, 5, 6}
-with the default tile, then over the tile shape (columns per wave, A
-fragments in registers or LDS, waves per compute unit) for the two best
-widths.  The fastest configuration is stored in a JSON cache keyed by
+with the default tile, then over the tile shape (columns per wave up to the
+widest the block size has, A fragments in registers or LDS, waves per
+compute unit; or, for 4- and 5-qubit blocks, workgroup tiles staged through
+LDS) for the two best widths.  The fastest configuration is stored in a JSON cache keyed by
 device, dtype and qubit count; ``apply`` configures a simulator from it
 (nearest tuned qubit count).
 
@@ -23,7 +24,27 @@ from typing import Dict, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning", "mi355x.json")
-SHAPE_KEYS = ("mfma_cols", "mfma_areg", "mfma_waves")
+SHAPE_KEYS = ("mfma_cols", "mfma_areg", "mfma_waves", "mfma_lds", "lds_wg")
+
+
+def max_cols(k: int, dtype: str) -> int:
+    """Widest register tile the matrix-core kernel has for a k-qubit block:
+    64 columns up to k = 4, 32 at k = 5 (and at k = 6 for complex64), else 16
+    (wider ones would not fit the double-buffered tile in registers)."""
+    if k <= 4:
+        return 64
+    if k == 5 or dtype == "c64":
+        return 32
+    return 16
+
+
+def effective(cfg: Dict, dtype: str) -> Dict:
+    """The configuration as it runs: the tile width capped for the block size."""
+    out = dict(cfg)
+    k = out.get("fusion", 0)
+    if k and "mfma_cols" in out:
+        out["mfma_cols"] = min(out["mfma_cols"], max_cols(k, dtype))
+    return out
 
 
 def _device_name() -> str:
@@ -83,10 +104,14 @@ def tune(n: int, dtype: str, layers: int = 3, seed: int = 0, verbose: bool = Tru
         k = base["fusion"]
         if k == 0:
             continue
+        cands = []
         for cols, areg, waves in itertools.product((16, 32, 64), (0, 1), (8, 16)):
-            if areg == 1 and k < 5:
+            if (areg == 1 and k < 5) or cols > max_cols(k, dtype):
                 continue
-            cfg = {"fusion": k, "mfma_cols": cols, "mfma_areg": areg, "mfma_waves": waves}
+            cands.append({"fusion": k, "mfma_lds": 0, "mfma_cols": cols, "mfma_areg": areg, "mfma_waves": waves})
+        if k in (4, 5):   # the LDS-staged tiles
+            cands += [{"fusion": k, "mfma_lds": 1, "lds_wg": wg} for wg in (2, 3)]
+        for cfg in cands:
             t = _time_config(qk, prog, n, dtype, cfg)
             if verbose:
                 print(f"[autotune] n={n} {dtype} {cfg}: {t * 1e3:.1f} ms", file=sys.stderr, flush=True)
@@ -117,7 +142,7 @@ def lookup(n: int, dtype: str, cache: Optional[Dict] = None, device: Optional[st
         nn = int(nn[1:])
         if best is None or abs(nn - n) < abs(best[0] - n):
             best = (nn, cfg)
-    return None if best is None else best[1]
+    return None if best is None else effective(best[1], dtype)
 
 
 def apply(sim, n: int, dtype: str, cache: Optional[Dict] = None) -> Optional[Dict]:

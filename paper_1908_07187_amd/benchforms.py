@@ -172,6 +172,7 @@ def serve(args, qk, torch):
                              f"arrivals at {frac:.2f}x the closed-loop capacity", "jobs": nj, "rate_per_s": rate},
                 "f32/f64")
     out["latency_ms"] = {"p50": rep.p50_ms, "p99": rep.p99_ms, "mean": rep.mean_ms}
+    out["host_busy_frac"] = rep.extra.get("host_busy_frac")
     out["closed_loop_capacity_cps"] = cap
     out["levels"] = levels
     out["batches"] = rep.batches
@@ -516,17 +517,20 @@ def kernels30(args, qk, torch):
                 s.measure(q, 0, 0.5)
             timed(f"H + measure q{q}", dtype, meas_bytes + full, m)
         s.close()
-        # fused matrix-core blocks, k = 5 (and 4, 6 for complex64)
+        # fused matrix-core blocks, k = 4, 5 (and 6 for complex64); k = 4, 5 also
+        # with the LDS-staged kernel (tuning key mfma_lds)
         f = qk.Sim(dtype)
         f.add_qubits(n)
         f.sync()
         for k in ((4, 5, 6) if dtype == "c64" else (4, 5)):
             g = f.define_matrix(f"U{k}", W.random_unitary(k, rng))
-            for targets in ([3, 9, 14, 21, 27, 29], [0, 7, 8, 16, 25, 28], [0, 1, 2, 3, 4, 5], [24, 25, 26, 27, 28, 29],
-                            [5, 6, 7, 8, 9, 10], [1, 3, 5, 7, 9, 11]):
-                tg = targets[:k]
-                timed(f"dense k{k} {tg}", dtype, full, lambda g=g, tg=tg: f.apply(g, tg), k=k,
-                      tflops=(8 << k) * (1 << n))
+            for lds in ((0, 1) if k in (4, 5) else (0,)):
+                f.set_tuning("mfma_lds", lds)
+                for targets in ([3, 9, 14, 21, 27, 29], [0, 7, 8, 16, 25, 28], [0, 1, 2, 3, 4, 5],
+                                [24, 25, 26, 27, 28, 29], [5, 6, 7, 8, 9, 10], [1, 3, 5, 7, 9, 11]):
+                    tg = targets[:k]
+                    timed(f"dense k{k} {tg} lds={lds}", dtype, full, lambda g=g, tg=tg: f.apply(g, tg), k=k,
+                          tflops=(8 << k) * (1 << n), lds=lds)
         f.close()
     for r in rows:
         if "tflops" in r:
