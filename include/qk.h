@@ -365,8 +365,11 @@ qk_status qk_sync(qk_sim sim);
  *   "mfma_lds"    blocks of 4-5 qubits: 1 stages each workgroup's tile
  *                 (2^k rows x 1 KiB) through LDS so that global memory is read
  *                 and written in address order, 0: each wave loads its own
- *                 register tile;
- *   "lds_wg"      workgroups per compute unit of the LDS-staged kernel (1..4);
+ *                 register tile, 2 (default): LDS tiles for 4-qubit blocks
+ *                 and for complex64 5-qubit blocks with three or more targets
+ *                 below bit 5, register tiles otherwise;
+ *   "lds_wg"      workgroups per compute unit of the LDS-staged kernel (1..8,
+ *                 default 2);
  *   "xcd"         1 (default): the per-gate sweeps renumber their workgroups
  *                 so that each of the 8 XCDs sweeps one contiguous range,
  *                 0: workgroups in launch order;

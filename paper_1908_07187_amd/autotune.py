@@ -109,8 +109,8 @@ def tune(n: int, dtype: str, layers: int = 3, seed: int = 0, verbose: bool = Tru
             if (areg == 1 and k < 5) or cols > max_cols(k, dtype):
                 continue
             cands.append({"fusion": k, "mfma_lds": 0, "mfma_cols": cols, "mfma_areg": areg, "mfma_waves": waves})
-        if k in (4, 5):   # the LDS-staged tiles
-            cands += [{"fusion": k, "mfma_lds": 1, "lds_wg": wg} for wg in (2, 3)]
+        if k in (4, 5):   # the LDS-staged tiles, everywhere or by the per-block rule
+            cands += [{"fusion": k, "mfma_lds": lds, "lds_wg": wg} for lds, wg in ((1, 2), (1, 3), (2, 2))]
         for cfg in cands:
             t = _time_config(qk, prog, n, dtype, cfg)
             if verbose:

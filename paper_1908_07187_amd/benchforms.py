@@ -126,6 +126,7 @@ def serve(args, qk, torch):
     from .serve import Server
     nj = args.serve_jobs
     fracs = [float(x) for x in str(args.serve_rates).split(",") if x]
+    spans = {}     # phase -> (start, end) on the monotonic clock in ns (the kernel trace's clock)
     prog = max(50, nj // 20)
     warm = W.c4_job_stream(20, seed=args.seed + 1, rate=1.0)
     Server(slots=8, autotuned=True).serve(warm, realtime=False)
@@ -135,7 +136,9 @@ def serve(args, qk, torch):
     else:
         _say(f"serve: closed loop over {nj} jobs")
         jobs = W.c4_job_stream(nj, seed=args.seed, rate=1.0)
+        c0 = time.perf_counter_ns()
         rep0 = Server(slots=8, autotuned=True).serve(jobs, realtime=False, progress_every=prog)
+        spans["closed_loop"] = (c0, time.perf_counter_ns())
         cap = rep0.circuits_per_s
         _say(f"serve closed-loop capacity {cap:.1f} circuits/s, wall {rep0.wall_s:.1f} s")
     sample = set(range(0, nj, 100))
@@ -144,8 +147,10 @@ def serve(args, qk, torch):
     for fi, frac in enumerate(fracs):
         rate = frac * cap
         jobs_p = W.c4_job_stream(nj, seed=args.seed, rate=rate)
+        c0 = time.perf_counter_ns()
         rep = Server(slots=8, keep_states=sample if fi == 0 else set(), autotuned=True).serve(
             jobs_p, realtime=True, progress_every=prog)
+        spans[f"{frac:.2f}"] = (c0, time.perf_counter_ns())
         _say(f"serve at {frac:.2f} x capacity = {rate:.1f}/s: {rep.circuits_per_s:.1f} circuits/s "
              f"p50 {rep.p50_ms:.1f} ms p99 {rep.p99_ms:.1f} ms")
         levels[f"{frac:.2f}"] = {"offered_per_s": rate, "circuits_per_s": rep.circuits_per_s, "p50_ms": rep.p50_ms,
@@ -173,6 +178,7 @@ def serve(args, qk, torch):
                 "f32/f64")
     out["latency_ms"] = {"p50": rep.p50_ms, "p99": rep.p99_ms, "mean": rep.mean_ms}
     out["host_busy_frac"] = rep.extra.get("host_busy_frac")
+    out["clock_spans_ns"] = spans
     out["closed_loop_capacity_cps"] = cap
     out["levels"] = levels
     out["batches"] = rep.batches
@@ -524,13 +530,18 @@ def kernels30(args, qk, torch):
         f.sync()
         for k in ((4, 5, 6) if dtype == "c64" else (4, 5)):
             g = f.define_matrix(f"U{k}", W.random_unitary(k, rng))
-            for lds in ((0, 1) if k in (4, 5) else (0,)):
-                f.set_tuning("mfma_lds", lds)
+            shapes = [{"mfma_lds": 0}]
+            if k in (4, 5):
+                shapes += [{"mfma_lds": 1, "lds_wg": 2}, {"mfma_lds": 1, "lds_wg": 3}, {"mfma_lds": 2, "lds_wg": 2}]
+            for shape in shapes:
+                for key, val in shape.items():
+                    f.set_tuning(key, val)
+                tag = " ".join(f"{key}={val}" for key, val in shape.items())
                 for targets in ([3, 9, 14, 21, 27, 29], [0, 7, 8, 16, 25, 28], [0, 1, 2, 3, 4, 5],
                                 [24, 25, 26, 27, 28, 29], [5, 6, 7, 8, 9, 10], [1, 3, 5, 7, 9, 11]):
                     tg = targets[:k]
-                    timed(f"dense k{k} {tg} lds={lds}", dtype, full, lambda g=g, tg=tg: f.apply(g, tg), k=k,
-                          tflops=(8 << k) * (1 << n), lds=lds)
+                    timed(f"dense k{k} {tg} {tag}", dtype, full, lambda g=g, tg=tg: f.apply(g, tg), k=k,
+                          tflops=(8 << k) * (1 << n), shape=dict(shape))
         f.close()
     for r in rows:
         if "tflops" in r:

@@ -459,7 +459,8 @@ qk_status run_dense(qk_sim s, const std::vector<int>& targets, const std::vector
     qk_status st = arena_put(s, packed.data(), packed.size(), &dmat);
     if (st) return st;
   }
-  if (s->tune.mfma_lds && mfma_lds_supported(s->n, k, controls.data(), (int)controls.size(), s->c64))
+  const bool lds = s->tune.mfma_lds == 1 || (s->tune.mfma_lds == 2 && mfma_lds_auto(k, targets.data(), s->c64));
+  if (lds && mfma_lds_supported(s->n, k, controls.data(), (int)controls.size(), s->c64))
     return check_launch(
         s, launch_dense_lds(L, targets.data(), k, controls.data(), (int)controls.size(), dmat, s->tune.lds_wg),
         "dense (matrix cores, LDS tiles)");
@@ -2206,11 +2207,12 @@ qk_status qk_set_tuning(qk_sim s, const char* key, int32_t value) {
   } else if (k == "mfma_areg") {
     s->tune.mfma_areg = value != 0;
   } else if (k == "mfma_lds") {
-    if (value != 0 && value != 1) return fail(s, QK_E_ARG, "mfma_lds must be 0 or 1");
+    if (value < 0 || value > 2) return fail(s, QK_E_ARG, "mfma_lds must be 0, 1 or 2");
     s->tune.mfma_lds = value;
   } else if (k == "lds_wg") {
-    if (value < 1 || value > 4) return fail(s, QK_E_ARG, "lds_wg must be 1..4");
+    if (value < 1 || value > 8) return fail(s, QK_E_ARG, "lds_wg must be 1..8");
     s->tune.lds_wg = value;
+
   } else if (k == "diag_runs") {
     if (value != 0 && value != 1) return fail(s, QK_E_ARG, "diag_runs must be 0 or 1");
     qk_status st = flush(s);

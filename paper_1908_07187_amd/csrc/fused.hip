@@ -231,26 +231,47 @@ __global__ __launch_bounds__(256) void k_dense_mfma(typename MF<R>::V* psi, cons
 // ---------------------------------------------------------------- LDS-staged tiles
 // The same GEMM with the tile staged through LDS by the whole workgroup, so
 // that global memory is read and written in address order: every wave-wide
-// access is 64 consecutive 16-byte pieces (1 KiB).  Tile = 2^K rows (gate
-// index m) x CW = 2^LB columns (the LB lowest bits outside targets and
-// controls); since the column bits are the lowest free bits, the tile's
-// amplitudes form runs of at least CW consecutive amplitudes.  The tile-local
-// address index j has one bit per bit of U = targets + column bits (ascending);
-// both its global offset and its LDS position (row m, column c) are sums of
-// per-bit weights, so a thread's part and each step's part are added.
+// access is 64 consecutive 16-byte pieces (1 KiB).
+// Tile = 2^K rows (gate index m) x CW = 2^LB columns (the LB lowest bits
+// outside targets and controls); since the column bits are the lowest free
+// bits, the tile's amplitudes form runs of at least CW consecutive
+// amplitudes.  The tile-local address index j has one bit per bit of U =
+// targets + column bits (ascending); both its global offset and its LDS
+// position (row m, column c) are sums of per-bit weights, so a thread's part
+// and each access's part are added.
 //   load:    global (address order) -> registers, prefetched one tile ahead;
 //   stage:   registers -> LDS X[m][c] (row stride CW + 1);
-//   compute: wave w takes column groups [w*GW, (w+1)*GW); MFMA as above, the
-//            B operand from LDS, results written over the wave's own columns;
-//   store:   LDS -> global in address order.
+//   compute: wave w takes column groups [w*GW, (w+1)*GW); MFMA as above with
+//            the B operand from LDS and the A operand from the complex matrix
+//            kept in LDS (row stride DIM + 1): one 16-byte read gives both
+//            real-embedding values a lane needs for an MFMA pair;
+//   store:   results written over the wave's own columns of X, then
+//            LDS -> global in address order.
+// Stand-alone variants of this kernel at 30 qubits showed its time is set by
+// the memory side: with the MFMAs removed it runs 4-12 % faster than the full
+// kernel, yet 15-50 % slower than a plain in-place sweep of the same state
+// (more so when the tile's rows lie far apart in memory); with the global
+// accesses removed, 5-qubit blocks still take 90-97 % of a plain sweep's
+// time.  Storing straight from the accumulators (runs of 16 columns per row)
+// was slower than the address-order stores, and more workgroups per compute
+// unit or a second tile of prefetch did not help.
 static int g_ncu = 0;
 
 struct LdsTileArgs {
   int tpos[6];         // target bit of gate index bit j
+  int lpos[8];         // column bit b
   int nu;              // bits of the tile index (K + LB)
   uint32_t lw[13];     // LDS offset (in amplitudes) of tile-index bit b
   uint64_t gw[13];     // global offset (in amplitudes) of tile-index bit b
 };
+
+template <int K>
+__device__ __forceinline__ uint64_t lds_dep_rows(uint32_t m, const LdsTileArgs& a) {
+  uint64_t i = 0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) i |= (uint64_t)((m >> j) & 1u) << a.tpos[j];
+  return i;
+}
 
 template <typename R, int K, int LB, bool NT>
 __global__ __launch_bounds__(256) void k_dense_lds(typename MF<R>::V* psi, const typename MF<R>::V* __restrict__ mat,
@@ -260,36 +281,33 @@ __global__ __launch_bounds__(256) void k_dense_lds(typename MF<R>::V* psi, const
   using Acc = typename MF<R>::Acc;
   constexpr int DIM = 1 << K;
   constexpr int CW = 1 << LB;
-  constexpr int S = CW + 1;                   // LDS row stride (amplitudes)
+  constexpr int S = CW + 1;                   // LDS row stride of the tile (amplitudes)
+  constexpr int SA = DIM + 1;                 // LDS row stride of the matrix
   constexpr int RT = (2 * DIM + 15) / 16;
   constexpr int KS = DIM / 4;
-  constexpr int NF = RT * KS * 2;
   constexpr int GW = CW / 64;                 // 16-column groups per wave
   constexpr int VEC = 16 / (int)sizeof(V);    // amplitudes per 16-byte access (1 or 2)
   constexpr int E = DIM * CW;                 // amplitudes per tile
   constexpr int NA = E / (256 * VEC);         // accesses per thread per tile
-  static_assert(GW >= 1 && NA >= 1, "tile too small for a 256-thread workgroup");
+  static_assert(K >= 3 && GW >= 1 && NA >= 1, "tile too small for a 256-thread workgroup");
   using Q = typename std::conditional<VEC == 1, V, floatx4>::type;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  R* afrag = reinterpret_cast<R*>(smem_raw);
-  V* X = reinterpret_cast<V*>(smem_raw + (size_t)NF * 64 * sizeof(R));
+  V* Am = reinterpret_cast<V*>(smem_raw);
+  V* X = Am + DIM * SA;
 
   if (!conds_ok_m(cond)) return;
 
-  for (int e = threadIdx.x; e < NF * 64; e += 256) {
-    const int l = e & 63, f = e >> 6;
-    const int part = f & 1, ks = (f >> 1) % KS, rt = (f >> 1) / KS;
-    const int i = l & 15, kk = l >> 4;
-    const int rho = 16 * rt + (MF<R>::kRowsByReg ? (4 * (i & 3) + (i >> 2)) : i);
-    const int r = rho >> 1, m = 4 * ks + kk;
-    R val = 0;
-    if (r < DIM) {
-      const V z = mat[r * DIM + m];
-      if ((rho & 1) == 0) val = part == 0 ? z.x : -z.y;
-      else val = part == 0 ? z.y : z.x;
-    }
-    afrag[e] = val;
-  }
+  for (int e = threadIdx.x; e < DIM * DIM; e += 256) Am[(e / DIM) * SA + (e % DIM)] = mat[e];
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int h = lane >> 4, c = lane & 15;
+  // A operand of lane (i = lane % 16, kk = lane / 16) for 16-row tile rt and
+  // step ks: real-embedding row rho = 16 rt + p(i) (p orders D rows the way
+  // the instruction returns them), complex row rho / 2 = 8 rt + p(i) / 2,
+  // column 4 ks + kk; an even rho takes (Re, -Im), an odd one (Im, Re)
+  const int pi_ = MF<R>::kRowsByReg ? (4 * (c & 3) + (c >> 2)) : c;
+  const bool odd = pi_ & 1;
+  const int arow = (pi_ >> 1) * SA + h;
 
   // this thread's part of the tile index: bits of VEC * threadIdx.x; the
   // remaining bits come from the access number a (j = VEC * (tid + 256 a) + v)
@@ -319,10 +337,6 @@ __global__ __launch_bounds__(256) void k_dense_lds(typename MF<R>::V* psi, const
     gofs_a[a] = go + gofs_t;
   }
   const uint32_t lw0 = ta.lw[0];   // LDS offset of the second amplitude of a pair (VEC = 2)
-
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int h = lane >> 4, c = lane & 15;
-
   uint64_t blk = blockIdx.x;
   if (xcd && !(gridDim.x & 7)) blk = (blk & 7) * (gridDim.x >> 3) + (blk >> 3);
   const uint64_t nwg = gridDim.x;
@@ -336,7 +350,6 @@ __global__ __launch_bounds__(256) void k_dense_lds(typename MF<R>::V* psi, const
   if (t >= ntiles) return;
   uint64_t base = insert_zeros_m(t, sp) | cmask;
   gload(base);
-  __syncthreads();   // A fragments staged
   for (;;) {
     // registers -> LDS
 #pragma unroll
@@ -353,7 +366,7 @@ __global__ __launch_bounds__(256) void k_dense_lds(typename MF<R>::V* psi, const
         X[lofs_a[a] + lw0] = v1;
       }
     }
-    __syncthreads();
+    __syncthreads();   // (first pass: the matrix is staged too)
     const uint64_t tn = t + nwg;
     const bool more = tn < ntiles;
     const uint64_t nbase = more ? (insert_zeros_m(tn, sp) | cmask) : base;
@@ -371,9 +384,9 @@ __global__ __launch_bounds__(256) void k_dense_lds(typename MF<R>::V* psi, const
       for (int g = 0; g < GW; ++g) xb[g] = X[(4 * ks + h) * S + 16 * (wv * GW + g) + c];
 #pragma unroll
       for (int rt = 0; rt < RT; ++rt) {
-        const int f = (rt * KS + ks) * 2;
-        const R a0 = afrag[f * 64 + lane];
-        const R a1 = afrag[(f + 1) * 64 + lane];
+        const V z = Am[arow + 8 * rt * SA + 4 * ks];
+        const R a0 = odd ? z.y : z.x;
+        const R a1 = odd ? z.x : -z.y;
 #pragma unroll
         for (int g = 0; g < GW; ++g) {
           acc[rt][g] = MF<R>::op(a0, xb[g].x, acc[rt][g]);
@@ -381,38 +394,40 @@ __global__ __launch_bounds__(256) void k_dense_lds(typename MF<R>::V* psi, const
         }
       }
     }
+    {
 #pragma unroll
-    for (int rt = 0; rt < RT; ++rt) {
-      const int r0 = 8 * rt + 2 * h;
-      if (r0 < DIM) {
+      for (int rt = 0; rt < RT; ++rt) {
+        const int r0 = 8 * rt + 2 * h;
+        if (r0 < DIM) {
 #pragma unroll
-        for (int g = 0; g < GW; ++g) {
-          const int col = 16 * (wv * GW + g) + c;
-          V v0, v1;
-          v0.x = acc[rt][g][0];
-          v0.y = acc[rt][g][1];
-          v1.x = acc[rt][g][2];
-          v1.y = acc[rt][g][3];
-          X[r0 * S + col] = v0;
-          X[(r0 + 1) * S + col] = v1;
+          for (int g = 0; g < GW; ++g) {
+            const int col = 16 * (wv * GW + g) + c;
+            V v0, v1;
+            v0.x = acc[rt][g][0];
+            v0.y = acc[rt][g][1];
+            v1.x = acc[rt][g][2];
+            v1.y = acc[rt][g][3];
+            X[r0 * S + col] = v0;
+            X[(r0 + 1) * S + col] = v1;
+          }
         }
       }
-    }
-    __syncthreads();
-    // LDS -> global, address order
+      __syncthreads();
+      // LDS -> global, address order
 #pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      Q q;
-      if constexpr (VEC == 1) {
-        q = X[lofs_a[a]];
-      } else {
-        const V v0 = X[lofs_a[a]], v1 = X[lofs_a[a] + lw0];
-        q = floatx4{v0.x, v0.y, v1.x, v1.y};
+      for (int a = 0; a < NA; ++a) {
+        Q q;
+        if constexpr (VEC == 1) {
+          q = X[lofs_a[a]];
+        } else {
+          const V v0 = X[lofs_a[a]], v1 = X[lofs_a[a] + lw0];
+          q = floatx4{v0.x, v0.y, v1.x, v1.y};
+        }
+        mst<NT>(reinterpret_cast<Q*>(psi + base + gofs_a[a]), q);
       }
-      mst<NT>(reinterpret_cast<Q*>(psi + base + gofs_a[a]), q);
+      if (!more) break;
+      __syncthreads();   // every store has read X before the next tile overwrites it
     }
-    if (!more) break;
-    __syncthreads();   // every store has read X before the next tile overwrites it
     t = tn;
     base = nbase;
   }
@@ -422,9 +437,7 @@ template <typename R, int K, int LB, bool NT>
 static hipError_t launch_lds_k(const Launch& L, const void* mat, uint64_t ntiles, const Special& sp, uint64_t cmask,
                                const LdsTileArgs& ta, int wg_per_cu) {
   constexpr int DIM = 1 << K;
-  constexpr int RT = (2 * DIM + 15) / 16;
-  constexpr int KS = DIM / 4;
-  constexpr size_t shm = (size_t)RT * KS * 2 * 64 * sizeof(R) + (size_t)DIM * ((1 << LB) + 1) * 2 * sizeof(R);
+  constexpr size_t shm = ((size_t)DIM * (DIM + 1) + (size_t)DIM * ((1 << LB) + 1)) * 2 * sizeof(R);
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute((const void*)k_dense_lds<R, K, LB, NT>,
@@ -447,6 +460,13 @@ static hipError_t launch_lds_k(const Launch& L, const void* mat, uint64_t ntiles
   return hipGetLastError();
 }
 
+template <typename R, int K, int LB>
+static hipError_t launch_lds_kn(const Launch& L, const void* mat, uint64_t ntiles, const Special& sp, uint64_t cmask,
+                                const LdsTileArgs& ta, int wg_per_cu, bool nt) {
+  return nt ? launch_lds_k<R, K, LB, true>(L, mat, ntiles, sp, cmask, ta, wg_per_cu)
+            : launch_lds_k<R, K, LB, false>(L, mat, ntiles, sp, cmask, ta, wg_per_cu);
+}
+
 // Tile widths of the LDS-staged kernel: 64 columns (complex128) and 128
 // (complex64), so that a tile is 2^K x 1 KiB.
 static int lds_lb(bool c64) { return c64 ? 7 : 6; }
@@ -459,6 +479,19 @@ bool mfma_lds_supported(int n, int k, const int* controls, int nc, bool c64) {
   return (k == 4 || k == 5) && n - k - nc >= lds_lb(c64);
 }
 
+// The automatic choice (tuning value 2), from 30-qubit timings of both
+// kernels over low, scattered and high target sets: 4-qubit blocks gain
+// 2-33 % from LDS tiles (most where targets sit on the lowest bits, whose
+// register tiles then load short pieces); 5-qubit blocks gain only for
+// complex64 blocks with three or more targets below bit 5 (4.4 -> 3.5 ms on
+// bits 0-4) and are otherwise 0-10 % slower, so they keep register tiles.
+bool mfma_lds_auto(int k, const int* targets, bool c64) {
+  if (k == 4) return true;
+  int low = 0;
+  for (int j = 0; j < k; ++j) low += targets[j] < 5;
+  return k == 5 && c64 && low >= 3;
+}
+
 hipError_t launch_dense_lds(const Launch& L, const int* targets, int k, const int* controls, int nc,
                             const void* d_matrix, int wg_per_cu) {
   if (!mfma_lds_supported(L.n, k, controls, nc, L.c64)) return hipErrorInvalidValue;
@@ -467,15 +500,14 @@ hipError_t launch_dense_lds(const Launch& L, const int* targets, int k, const in
   uint64_t used = 0;
   for (int j = 0; j < k; ++j) used |= 1ull << targets[j];
   for (int j = 0; j < nc; ++j) used |= 1ull << controls[j];
-  int lpos[8];
+  LdsTileArgs ta{};
   int nl = 0;
   for (int b = 0; b < L.n && nl < lb; ++b)
-    if (!((used >> b) & 1)) lpos[nl++] = b;
+    if (!((used >> b) & 1)) ta.lpos[nl++] = b;
   // tile index bits: targets and column bits in ascending bit order
   std::vector<int> ubits(targets, targets + k);
-  for (int j = 0; j < lb; ++j) ubits.push_back(lpos[j]);
+  for (int j = 0; j < lb; ++j) ubits.push_back(ta.lpos[j]);
   std::sort(ubits.begin(), ubits.end());
-  LdsTileArgs ta{};
   ta.nu = (int)ubits.size();
   for (int j = 0; j < k; ++j) ta.tpos[j] = targets[j];
   for (int b = 0; b < ta.nu; ++b) {
@@ -485,14 +517,14 @@ hipError_t launch_dense_lds(const Launch& L, const int* targets, int k, const in
     for (int j = 0; j < k; ++j)
       if (targets[j] == bit) w = (uint32_t)(1u << j) * (uint32_t)(CW + 1);   // row m bit j
     for (int j = 0; j < lb; ++j)
-      if (lpos[j] == bit) w = 1u << j;                                        // column bit j
+      if (ta.lpos[j] == bit) w = 1u << j;                                     // column bit j
     ta.lw[b] = w;
   }
   // runs of the tile start at bit 0 (a 16-byte access covers two complex64 amplitudes)
   if (ubits[0] != 0) return hipErrorInvalidValue;
   std::vector<int> sv(targets, targets + k);
   for (int j = 0; j < nc; ++j) sv.push_back(controls[j]);
-  for (int j = 0; j < lb; ++j) sv.push_back(lpos[j]);
+  for (int j = 0; j < lb; ++j) sv.push_back(ta.lpos[j]);
   Special sp = make_special(sv.data(), (int)sv.size(), nullptr, 0);
   uint64_t cmask = 0;
   for (int j = 0; j < nc; ++j) cmask |= 1ull << controls[j];
@@ -500,15 +532,11 @@ hipError_t launch_dense_lds(const Launch& L, const int* targets, int k, const in
   if (wg_per_cu <= 0) wg_per_cu = 2;
   const bool nt = L.tune.nt == 2 || (L.tune.nt == 1 && state_streams(L));
   if (L.c64) {
-    if (k == 4) return nt ? launch_lds_k<float, 4, 7, true>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu)
-                          : launch_lds_k<float, 4, 7, false>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu);
-    return nt ? launch_lds_k<float, 5, 7, true>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu)
-              : launch_lds_k<float, 5, 7, false>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu);
+    if (k == 4) return launch_lds_kn<float, 4, 7>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu, nt);
+    return launch_lds_kn<float, 5, 7>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu, nt);
   }
-  if (k == 4) return nt ? launch_lds_k<double, 4, 6, true>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu)
-                        : launch_lds_k<double, 4, 6, false>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu);
-  return nt ? launch_lds_k<double, 5, 6, true>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu)
-            : launch_lds_k<double, 5, 6, false>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu);
+  if (k == 4) return launch_lds_kn<double, 4, 6>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu, nt);
+  return launch_lds_kn<double, 5, 6>(L, d_matrix, ntiles, sp, cmask, ta, wg_per_cu, nt);
 }
 
 // Widest tile (columns per wave) that is instantiated for this block size

@@ -73,7 +73,7 @@ struct Tuning {
   int xcd = 1;           // sweeps: 1 renumbers workgroups so each XCD sweeps a contiguous range
   int diag_runs = 1;     // 1: consecutive diagonal gates are held back and applied in one pass
   int swap_relabel = 1;  // 1: an uncontrolled SWAP on a dense state relabels the two qubits instead of moving data
-  int mfma_lds = 0;      // 1: blocks of 4-5 qubits use the LDS-staged matrix-core kernel
+  int mfma_lds = 2;      // blocks of 4-5 qubits: 0 register tiles, 1 LDS-staged tiles, 2 chosen per block
   int lds_wg = 2;        // workgroups per CU of the LDS-staged kernel
 };
 
@@ -275,6 +275,7 @@ bool mfma_supported(int n, int k, int nc, bool c64);
 // The same GEMM with workgroup tiles staged through LDS (global memory in
 // address order, 1 KiB per wave access); blocks of 4 or 5 qubits.
 bool mfma_lds_supported(int n, int k, const int* controls, int nc, bool c64);
+bool mfma_lds_auto(int k, const int* targets, bool c64);
 hipError_t launch_dense_lds(const Launch& L, const int* targets, int k, const int* controls, int nc,
                             const void* d_matrix, int wg_per_cu);
 hipError_t launch_dense_mfma(const Launch& L, const int* targets, int k, const int* controls, int nc,

@@ -5,6 +5,8 @@ runs of ``bench.py --kernels-only``):
 
     python -m paper_1908_07187_amd.profiling FETCH.csv WRITE.csv > profiles/sweep_traffic_30q_c128.json
     python -m paper_1908_07187_amd.profiling mfma MFMA.csv
+    python -m paper_1908_07187_amd.profiling busy KERNEL_TRACE.csv [FROM_S TO_S]
+    python -m paper_1908_07187_amd.profiling stats KERNEL_STATS.csv [TOP]
 
 FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch.  Each is scaled by
 the factor that makes the plain copy kernel of known size read back its true
@@ -94,8 +96,68 @@ def mfma(pmc_csv: str, trace_csv: str = None, simds: int = 1024) -> dict:
     return out
 
 
+def busy(trace_csv: str, t_from: float = None, t_to: float = None) -> dict:
+    """GPU-busy fraction from a rocprofv3 kernel trace: the time covered by at
+    least one running kernel (the union of the dispatch intervals, so kernels
+    that overlap on several streams count once) over the span from the first
+    kernel start to the last kernel end, or over [t_from, t_to]: seconds from
+    the first start, or, when above 1e15, absolute monotonic-clock
+    nanoseconds (the trace's clock, which time.perf_counter_ns reads)."""
+    iv = []
+    with open(trace_csv) as f:
+        for row in csv.DictReader(f):
+            iv.append((int(row["Start_Timestamp"]), int(row["End_Timestamp"])))
+    if not iv:
+        return {"kernels": 0}
+    iv.sort()
+    t0 = iv[0][0]
+
+    def at(v, dflt):
+        if v is None:
+            return dflt
+        return int(v) if v > 1e15 else t0 + int(v * 1e9)
+    lo = at(t_from, t0)
+    hi = at(t_to, max(e for _, e in iv))
+    covered, cur_s, cur_e = 0, None, None
+    for a, b in iv:
+        a, b = max(a, lo), min(b, hi)
+        if b <= a:
+            continue
+        if cur_e is None or a > cur_e:
+            if cur_e is not None:
+                covered += cur_e - cur_s
+            cur_s, cur_e = a, b
+        else:
+            cur_e = max(cur_e, b)
+    if cur_e is not None:
+        covered += cur_e - cur_s
+    return {"kernels": len(iv), "span_s": (hi - lo) * 1e-9, "busy_s": covered * 1e-9,
+            "busy_frac": covered / (hi - lo) if hi > lo else None}
+
+
+def stats_table(stats_csv: str, top: int = 30) -> str:
+    """A rocprofv3 --stats kernel summary as a markdown table (calls, total,
+    average, min, max in ms, share of kernel time)."""
+    rows = []
+    with open(stats_csv) as f:
+        for row in csv.DictReader(f):
+            rows.append(row)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| Kernel | Calls | Total ms | Average ms | Min ms | Max ms | % |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['TotalDurationNs']) * 1e-6:.1f} | "
+                   f"{float(r['AverageNs']) * 1e-6:.4f} | {float(r['MinNs']) * 1e-6:.4f} | "
+                   f"{float(r['MaxNs']) * 1e-6:.4f} | {float(r['Percentage']):.2f} |")
+    return "\n".join(out)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "mfma":
         print(json.dumps(mfma(sys.argv[2]), indent=1))
+    elif sys.argv[1] == "stats":
+        print(stats_table(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 30))
+    elif sys.argv[1] == "busy":
+        rest = [float(x) for x in sys.argv[3:5]]
+        print(json.dumps(busy(sys.argv[2], *rest), indent=1))
     else:
         print(json.dumps(traffic(sys.argv[1], sys.argv[2]), indent=1))

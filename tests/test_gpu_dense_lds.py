@@ -65,8 +65,8 @@ def test_lds_dense_blocks_match_oracle(dtype, k, extra):
     c.init_state = W.random_state(n, rng)
     ref, _, _ = oracle.run(c)
     print(f"[gpu-lds] dtype={dtype} k={k} n={n} sets={sets}", flush=True)
-    for wg in (2, 3):
-        got, _ = _run(c, dtype, {"mfma_lds": 1, "lds_wg": wg})
+    for lds, wg in ((1, 2), (1, 3), (1, 6), (2, 2)):
+        got, _ = _run(c, dtype, {"mfma_lds": lds, "lds_wg": wg})
         _check(ref, got, dtype)
 
 

@@ -102,12 +102,13 @@ def _chunks(sim, rows=1 << 24):
         yield lo, hi, t[lo:hi].cpu().numpy().astype(np.complex128)
 
 
-def _c64_norm_bound(n_sweeps):
-    """|<psi|psi> - 1| after n_sweeps complex64 sweeps from a unit-norm state:
-    each sweep rounds every amplitude it writes with relative error at most
-    about 2 u (u = 2^-24, one complex multiply-add), so the squared norm moves
-    by at most 4 u per sweep to first order; the bound adds these worst cases."""
-    return 4.0 * 2.0 ** -24 * max(1, n_sweeps)
+def _c64_norm_bound(n_sweeps, k=5):
+    """|<psi|psi> - 1| after n_sweeps complex64 sweeps of blocks of at most k
+    qubits from a unit-norm state: a sweep forms each amplitude it writes as a
+    sum of 2^k complex products, rounded with relative error at most
+    (2^k + 1) u (u = 2^-24), so the squared norm moves by at most
+    2 (2^k + 1) u per sweep to first order; the bound adds these worst cases."""
+    return 2.0 * (2 ** k + 1) * 2.0 ** -24 * max(1, n_sweeps)
 
 
 @pytest.fixture(scope="module")
