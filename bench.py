@@ -55,7 +55,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gates", type=int, default=16, help="gates of the circuit the oracle sample runs")
     ap.add_argument("--workload", default="random30",
-                    choices=["random30", "batch12", "serve", "qft26", "ipe21", "shor", "sample30", "shor39", "kernels30"],
+                    choices=["random30", "batch12", "serve", "qft26", "ipe21", "shor", "sample30", "shor39", "kernels30",
+                             "cpu_oracle"],
                     help="random30 (default): the 30-qubit depth-40 circuit; the others are the batching, "
                          "serving, QFT, phase-estimation, Shor (dense and sparse) and deferred-measurement forms")
     ap.add_argument("--serve-jobs", type=int, default=400)
@@ -124,11 +125,13 @@ def kernels_only(qk, torch):
     """A short program for hardware-counter runs on 30-qubit states:
     complex128 strided-butterfly sweeps (targets 10, 17, 23, 29), diagonal
     sweeps (RZ, RZZ), cross-lane butterflies (targets 1, 4), one diagonal-run
-    pass (fifteen RZZ); dense 5- and
-    6-qubit blocks on matrix cores (complex64) and 4- and 5-qubit blocks
-    (complex128), two target sets each; and one plain copy kernel of known size
-    (the 2^28-amplitude copy when a 28-qubit state grows by one qubit: 4 GiB
-    read, 4 GiB written)."""
+    pass (fifteen RZZ); dense 5- and 6-qubit blocks on matrix cores (complex64)
+    and 4- and 5-qubit blocks (complex128), two target sets each; permutation
+    gates (a 20-bit table on bits 10-29 and on bits 0-19, controlled affine and
+    modular maps), two measurements, CNOTs with low and high controls
+    (complex128); LDS-staged 4-qubit blocks (both precisions); and one plain
+    copy kernel of known size (the 2^28-amplitude copy when a 28-qubit state
+    grows by one qubit: 4 GiB read, 4 GiB written)."""
     s = qk.Sim("c128")
     s.set_tuning("diag_runs", 0)
     s.add_qubits(30)
@@ -156,6 +159,39 @@ def kernels_only(qk, torch):
             g = f.define_matrix(f"U{k}", W.random_unitary(k, rng))
             for targets in ([3, 9, 14, 21, 27, 29][:k], [0, 7, 8, 16, 25, 28][:k]):
                 f.apply(g, targets)
+        f.sync()
+        f.close()
+    # permutation gates (uncontrolled 20-bit table on high and low targets,
+    # controlled affine and modular maps), measurement, and controlled sweeps
+    # with low and high controls, complex128
+    p = qk.Sim("c128")
+    p.set_tuning("diag_runs", 0)
+    p.add_qubits(30)
+    p.add_cbits(1)
+    for t in range(30):
+        p.apply("H", [t])
+    gt = p.define_table("T20", rng.permutation(1 << 20).astype(np.uint64))
+    ga = p.define_affine("A20", 20, 2 * 12345 + 1, 777)
+    gm = p.define_modmul("M20", 20, 7, 1000003)
+    p.apply(gt, list(range(10, 30)))
+    p.apply(gt, list(range(20)))
+    p.apply(ga, list(range(20)), controls=[29], params=[3.0])
+    p.apply(gm, list(range(20)), controls=[29], params=[5.0])
+    p.measure(29, 0, 0.5)
+    p.apply("H", [29])
+    p.measure(5, 0, 0.5)
+    for ctl, tgt in ((0, 1), (3, 20), (20, 3), (25, 29)):
+        p.apply("X", [tgt], controls=[ctl])
+    p.sync()
+    p.close()
+    # LDS-staged 4-qubit blocks, complex128 and complex64
+    for dtype in ("c128", "c64"):
+        f = qk.Sim(dtype)
+        f.set_tuning("mfma_lds", 1)
+        f.add_qubits(30)
+        g = f.define_matrix("U4", W.random_unitary(4, rng))
+        f.apply(g, [5, 6, 7, 8])
+        f.apply(g, [0, 7, 8, 16])
         f.sync()
         f.close()
     c = qk.Sim("c128")

@@ -555,6 +555,61 @@ def kernels30(args, qk, torch):
     return out
 
 
+def cpu_oracle(args, qk, torch):
+    """The CPU baseline plan: the FP64 oracle (as it stands) on the host's
+    cores, single thread and OpenMP over all threads, on the configs it
+    finishes in bounded time: the 12-qubit layered circuit, the 24-qubit QFT
+    and the 26-qubit QFT round trip, the 21-qubit phase estimation, and the
+    30-qubit layered circuit at 26 qubits (OpenMP only; its single-thread rate
+    is taken on the first 120 gates).  Rates use the same amplitude-update
+    counting as the GPU.  No GPU work."""
+    import os
+    import oracle
+    import workloads as W
+
+    def cpu_model():
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        return line.split(":", 1)[1].strip()
+        except OSError:
+            return None
+
+    cases = [("12-qubit layered circuit, 20 layers", W.c0_random_layers(n=12, layers=20, seed=0), (False, True)),
+             ("24-qubit QFT of a random state", W.c1_qft_roundtrip(n=24, seed=1, roundtrip=False), (False, True)),
+             ("26-qubit QFT + inverse QFT", W.c1_qft_roundtrip(n=26, seed=2), (False, True)),
+             ("21-qubit iterative phase estimation", W.c3_ipe(m=20, seed=0), (False, True)),
+             ("26-qubit layered circuit, depth 40 (+RZZ)", W.c2_random_rzz(n=26, depth=40, seed=0), (True,))]
+    rows = []
+    for label, circ, modes in cases:
+        for omp in modes:
+            t0 = time.perf_counter()
+            oracle.run(circ, omp=omp)
+            dt = time.perf_counter() - t0
+            upd = circ.amp_updates()
+            rows.append({"case": label, "threads": "all" if omp else 1, "seconds": dt, "amp_updates": upd,
+                         "amp_updates_per_s": upd / dt})
+            _say(f"oracle {label} ({'OpenMP' if omp else '1 thread'}): {dt:.2f} s, {upd / dt:.3e} updates/s")
+    # single thread on the first 120 gates of the 26-qubit layered circuit
+    circ = W.c2_random_rzz(n=26, depth=40, seed=0)
+    sub = W.Circuit([circ.ops[0]] + circ.gate_ops()[:120])
+    t0 = time.perf_counter()
+    oracle.run(sub, omp=False)
+    dt = time.perf_counter() - t0
+    rows.append({"case": "26-qubit layered circuit, first 120 gates", "threads": 1, "seconds": dt,
+                 "amp_updates": sub.amp_updates(), "amp_updates_per_s": sub.amp_updates() / dt})
+    from oracle.oracle import Oracle
+    threads = Oracle(omp=True).threads
+    out = _base(args, rows[-2]["amp_updates_per_s"], "amplitude-updates/s",
+                {"workload": "FP64 CPU oracle on the host cores (single thread and OpenMP) over the 12-, 21-, 24-, "
+                             "26-qubit configurations", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+                 "omp_threads": threads}, "f64")
+    out["cases"] = rows
+    return out
+
+
 def run(name, args, qk, torch):
     return {"batch12": batch12, "serve": serve, "qft26": qft26, "ipe21": ipe21, "shor": shor,
-            "sample30": sample30, "shor39": shor39, "kernels30": kernels30}[name](args, qk, torch)
+            "sample30": sample30, "shor39": shor39, "kernels30": kernels30,
+            "cpu_oracle": cpu_oracle}[name](args, qk, torch)
