@@ -5,7 +5,7 @@ runs of ``bench.py --kernels-only``):
 
     python -m paper_1908_07187_amd.profiling FETCH.csv WRITE.csv > profiles/sweep_traffic_30q_c128.json
     python -m paper_1908_07187_amd.profiling mfma MFMA.csv
-    python -m paper_1908_07187_amd.profiling busy KERNEL_TRACE.csv [FROM_S TO_S]
+    python -m paper_1908_07187_amd.profiling busy KERNEL_TRACE.csv [FROM TO [ns]]
     python -m paper_1908_07187_amd.profiling stats KERNEL_STATS.csv [TOP]
 
 FETCH_SIZE and WRITE_SIZE are reported in KiB per dispatch.  Each is scaled by
@@ -96,13 +96,13 @@ def mfma(pmc_csv: str, trace_csv: str = None, simds: int = 1024) -> dict:
     return out
 
 
-def busy(trace_csv: str, t_from: float = None, t_to: float = None) -> dict:
+def busy(trace_csv: str, t_from: float = None, t_to: float = None, absolute_ns: bool = False) -> dict:
     """GPU-busy fraction from a rocprofv3 kernel trace: the time covered by at
     least one running kernel (the union of the dispatch intervals, so kernels
     that overlap on several streams count once) over the span from the first
     kernel start to the last kernel end, or over [t_from, t_to]: seconds from
-    the first start, or, when above 1e15, absolute monotonic-clock
-    nanoseconds (the trace's clock, which time.perf_counter_ns reads)."""
+    the first start, or with absolute_ns, timestamps of the trace's own clock
+    in nanoseconds (on Linux the monotonic clock time.perf_counter_ns reads)."""
     iv = []
     with open(trace_csv) as f:
         for row in csv.DictReader(f):
@@ -115,7 +115,7 @@ def busy(trace_csv: str, t_from: float = None, t_to: float = None) -> dict:
     def at(v, dflt):
         if v is None:
             return dflt
-        return int(v) if v > 1e15 else t0 + int(v * 1e9)
+        return int(v) if absolute_ns else t0 + int(v * 1e9)
     lo = at(t_from, t0)
     hi = at(t_to, max(e for _, e in iv))
     covered, cur_s, cur_e = 0, None, None
@@ -158,6 +158,6 @@ if __name__ == "__main__":
         print(stats_table(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 30))
     elif sys.argv[1] == "busy":
         rest = [float(x) for x in sys.argv[3:5]]
-        print(json.dumps(busy(sys.argv[2], *rest), indent=1))
+        print(json.dumps(busy(sys.argv[2], *rest, absolute_ns="ns" in sys.argv[5:]), indent=1))
     else:
         print(json.dumps(traffic(sys.argv[1], sys.argv[2]), indent=1))
