@@ -420,12 +420,16 @@ qk_status qk_capture_end(qk_sim sim, qk_graph* out);
 qk_status qk_graph_launch(qk_graph graph);
 qk_status qk_graph_destroy(qk_graph graph);
 
-/* ---- batched execution: many small circuits in one persistent launch -----
- * Circuits on at most 13 qubits (complex128) or 14 (complex64), builtin gates
- * and measurements only, each started from |0...0>.  qk_batch_run launches
- * one persistent grid whose workgroups take circuits from a device queue
- * (largest first) and keep each circuit's state in on-chip memory (LDS) for
- * the whole circuit.  Results do not depend on which circuits share a launch. */
+/* ---- batched execution: many circuits in one persistent launch -----------
+ * Circuits on 1..24 qubits, builtin gates and measurements only, each started
+ * from |0...0>.  qk_batch_run launches one persistent grid whose workgroups
+ * take circuits from a device queue (largest first), one circuit per
+ * workgroup.  A circuit on at most 13 qubits (complex128) or 14 (complex64)
+ * keeps its state in on-chip memory (LDS) for the whole circuit; a larger one
+ * keeps it in the batch's device buffer and runs by stages: gate groups on at
+ * most 12 (complex128) or 13 (complex64) qubits, each applied chunk by chunk
+ * through LDS (one read and one write of the state per stage).  Results do
+ * not depend on which circuits share a launch. */
 #define QK_OP_GATE 1
 #define QK_OP_MEASURE 2
 

@@ -128,8 +128,9 @@ def serve(args, qk, torch):
     fracs = [float(x) for x in str(args.serve_rates).split(",") if x]
     spans = {}     # phase -> (start, end) on the monotonic clock in ns (the kernel trace's clock)
     prog = max(50, nj // 20)
+    mid = {"c128": args.serve_mid_max, "c64": args.serve_mid_max} if args.serve_mid_max > 0 else None
     warm = W.c4_job_stream(20, seed=args.seed + 1, rate=1.0)
-    Server(slots=8, autotuned=True).serve(warm, realtime=False)
+    Server(slots=8, autotuned=True, mid_max=mid).serve(warm, realtime=False)
     if args.serve_capacity > 0:
         cap = args.serve_capacity
         _say(f"serve: capacity {cap:.1f} circuits/s given")
@@ -137,7 +138,7 @@ def serve(args, qk, torch):
         _say(f"serve: closed loop over {nj} jobs")
         jobs = W.c4_job_stream(nj, seed=args.seed, rate=1.0)
         c0 = time.perf_counter_ns()
-        rep0 = Server(slots=8, autotuned=True).serve(jobs, realtime=False, progress_every=prog)
+        rep0 = Server(slots=8, autotuned=True, mid_max=mid).serve(jobs, realtime=False, progress_every=prog)
         spans["closed_loop"] = (c0, time.perf_counter_ns())
         cap = rep0.circuits_per_s
         _say(f"serve closed-loop capacity {cap:.1f} circuits/s, wall {rep0.wall_s:.1f} s")
@@ -148,7 +149,7 @@ def serve(args, qk, torch):
         rate = frac * cap
         jobs_p = W.c4_job_stream(nj, seed=args.seed, rate=rate)
         c0 = time.perf_counter_ns()
-        rep = Server(slots=8, keep_states=sample if fi == 0 else set(), autotuned=True).serve(
+        rep = Server(slots=8, keep_states=sample if fi == 0 else set(), autotuned=True, mid_max=mid).serve(
             jobs_p, realtime=True, progress_every=prog)
         spans[f"{frac:.2f}"] = (c0, time.perf_counter_ns())
         _say(f"serve at {frac:.2f} x capacity = {rate:.1f}/s: {rep.circuits_per_s:.1f} circuits/s "
@@ -185,6 +186,7 @@ def serve(args, qk, torch):
     out["max_concurrent_streams"] = rep.max_concurrent_streams
     out["fidelity_vs_c128_sampled"] = {"jobs": len(fids), "min": float(min(fids)) if fids else None}
     out["mean_qubits"] = float(np.mean(ns))
+    out["mid_batched_max_qubits"] = args.serve_mid_max if mid else None
     return out
 
 
@@ -555,6 +557,70 @@ def kernels30(args, qk, torch):
     return out
 
 
+def batch_mid(args, qk, torch):
+    """Mid-size batching: serving-mix circuits of 15..20 qubits (layered, CNOT
+    matchings, a measurement and a conditioned gate in 30 %), uneven sizes,
+    all in one persistent launch with their states in HBM, run by stages
+    through LDS; against the same circuits one after another on the per-gate
+    path (one simulator per circuit, op records in one call).  Both dtypes;
+    the batched states are compared with the per-gate ones."""
+    import workloads as W
+    from workloads.circuits import rng_for
+    from .batch import op_array
+    nc = args.mid_circuits
+    rng = rng_for(11)
+    circs = [W.c4_job(rng, n_range=(15, 20))[0] for _ in range(nc)]
+    upd = sum(c.amp_updates() for c in circs)
+    recs = [op_array(c) for c in circs]
+    out = {}
+    for dt in ("c128", "c64"):
+        # (a) per-gate path, one circuit after another
+        k = min(nc, args.mid_stream)
+        ref = []
+        for rep in range(2):   # the first pass warms allocations and code
+            t0 = time.perf_counter()
+            for i in range(k):
+                s = qk.Sim(dt)
+                s.add_qubits(circs[i].n_qubits)
+                if circs[i].n_cbits:
+                    s.add_cbits(circs[i].n_cbits)
+                s.apply_ops(*recs[i])
+                s.sync()
+                if rep == 1 and i < 16:
+                    ref.append((s.state(), list(s.read_cbits())))
+                s.close()
+            stream_dt = time.perf_counter() - t0
+        stream_cps = k / stream_dt
+        # (b) one persistent launch
+        b = qk.Batch(dt)
+        ids = [b.add(c.n_qubits, c.n_cbits, *r) for c, r in zip(circs, recs)]
+        for _ in range(max(1, args.warmup)):
+            b.run()
+        b.sync()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            b.run()
+        b.sync()
+        bdt = (time.perf_counter() - t0) / args.steps
+        dmax = 0.0
+        cb_ok = True
+        for i, (st, cbv) in enumerate(ref):
+            got = b.state(ids[i]).astype(np.complex128)
+            dmax = max(dmax, float(np.max(np.abs(got - st.astype(np.complex128)))))
+            cb_ok = cb_ok and list(b.cbits(ids[i])) == cbv
+        b.close()
+        out[dt] = {"batch_circuits_per_s": nc / bdt, "batch_ms": bdt * 1e3, "batch_amp_updates_per_s": upd / bdt,
+                   "per_gate_circuits_per_s": stream_cps, "per_gate_sample": k, "speedup": (nc / bdt) / stream_cps,
+                   "max_abs_diff_vs_per_gate": dmax, "cbits_equal": cb_ok}
+        _say(f"batch_mid {dt}: batch {nc / bdt:.1f} circuits/s ({bdt * 1e3:.1f} ms for {nc}), per-gate path "
+             f"{stream_cps:.1f} circuits/s, max|d| {dmax:.2e}, cbits equal {cb_ok}")
+    res = _base(args, out["c128"]["batch_circuits_per_s"], "circuits/s",
+                {"workload": f"{nc} serving-mix circuits of 15..20 qubits (depth 10..60) in one persistent launch",
+                 "qubits": [15, 20]}, "c128")
+    res["forms"] = out
+    return res
+
+
 def cpu_oracle(args, qk, torch):
     """The CPU baseline plan: the FP64 oracle (as it stands) on the host's
     cores, single thread and OpenMP over all threads, each case bounded to
@@ -610,4 +676,4 @@ def cpu_oracle(args, qk, torch):
 def run(name, args, qk, torch):
     return {"batch12": batch12, "serve": serve, "qft26": qft26, "ipe21": ipe21, "shor": shor,
             "sample30": sample30, "shor39": shor39, "kernels30": kernels30,
-            "cpu_oracle": cpu_oracle}[name](args, qk, torch)
+            "cpu_oracle": cpu_oracle, "batch_mid": batch_mid}[name](args, qk, torch)

@@ -18,6 +18,17 @@
 // sweeps and 360 launches.  Every workgroup leaves the loop once the counter
 // passes the job count.
 //
+// Jobs too large for LDS (above 13 qubits complex128, 14 complex64; up to
+// 24) run in the same launch with their state in global memory.  The host
+// splits such a job into stages: runs of gates, reordered only where they
+// commute, whose qubits fit one LDS chunk (12 qubits complex128, 13
+// complex64), and measurements between them.  For a stage the workgroup
+// gathers each chunk (the amplitudes that share the values of the qubits
+// outside the stage) into LDS, runs the stage's items on it exactly as for
+// a small job, and scatters it back, so a stage costs one read and one write
+// of the state whatever its gate count; a measurement runs over the state in
+// global memory.
+//
 // Measurement inside a job uses the same rule as the per-gate path (FP64
 // sums, outcome 0 iff u < P0, renormalise by 1/sqrt(p_outcome)), reduced in a
 // fixed order that depends only on the job, so a job's result does not depend
@@ -39,7 +50,7 @@ namespace {
 // flip: a pair exchange, no arithmetic), BK_U1R (real entries: half the
 // multiplications), BK_U1 (general complex).
 enum BKind { BK_U1 = 1, BK_DIAG1 = 2, BK_DIAG2 = 3, BK_PHASE = 4, BK_SWAP = 5, BK_MEAS = 6, BK_PASS = 7, BK_X = 8,
-             BK_U1R = 9 };
+             BK_U1R = 9, BK_STAGE = 10 };
 
 __host__ __device__ constexpr bool is_one_qubit_dense(int kind) {
   return kind == BK_U1 || kind == BK_X || kind == BK_U1R;
@@ -50,7 +61,7 @@ struct BJob {
   uint32_t op_begin, op_end;   // record range of the job's items
   int32_t n, ncbits;
   uint32_t cbit_off;
-  int32_t pad;
+  int32_t staged;   // state in global memory, run by stages (n above what LDS holds)
 };
 
 // One record, 20 dwords.  An item is one record (swap, measurement) or a pass
@@ -193,12 +204,239 @@ __device__ __forceinline__ void bfly(typename EVb<R>::T& p, typename EVb<R>::T& 
 // four (32 KiB states).
 template <typename R> constexpr int batch_waves_per_simd() { return sizeof(R) == 8 ? 4 : 8; }
 
+// Staged (mid-size) jobs: qubits of the LDS chunk a stage works on, and the
+// amplitudes each thread moves per chunk.
+template <typename R> constexpr int stage_qubits() { return sizeof(R) == 8 ? 12 : 13; }
+template <typename R> constexpr int stage_per_thread() { return (1 << stage_qubits<R>()) / kBatchThreads; }
+static_assert(stage_per_thread<double>() % 8 == 0 && stage_per_thread<float>() % 8 == 0, "chunk moves go 8 at a time");
+static_assert(kBatchThreads == 512, "a staged chunk maps the thread to the stage's lowest 9 qubits");
+
+// Measurement of qubit mask qb over a state of dim amplitudes (in LDS, read
+// through the swizzle, or the job's state in global memory): FP64 sums of
+// |x|^2 by outcome in a fixed order (thread-strided, then wave, then the
+// waves in order), outcome 0 iff u < P0, the outcome's half scaled by
+// 1/sqrt(p), the other half zeroed; cbit (>= 0) receives the outcome.  A
+// zero-probability outcome leaves the state and the cbit as they are.
+template <typename R, bool LDS>
+__device__ __forceinline__ void meas_run(typename EVb<R>::T* st, uint32_t dim, uint32_t qb, double u, int cbit,
+                                         uint8_t* cb, double (*red)[kBatchThreads / 64], double* meas) {
+  using C = typename EVb<R>::T;
+  const uint32_t tid = threadIdx.x, bd = blockDim.x;
+  const int lane = tid & 63, w = tid >> 6;
+  auto at = [](uint32_t i) { return LDS ? swz<R>(i) : i; };
+  double s0 = 0, s1 = 0;
+  for (uint32_t i0 = tid; i0 < dim; i0 += kBU * bd) {
+    C x[kBU];
+#pragma unroll
+    for (int k = 0; k < kBU; ++k)
+      if (i0 + k * bd < dim) x[k] = st[at(i0 + k * bd)];
+#pragma unroll
+    for (int k = 0; k < kBU; ++k) {
+      const uint32_t i = i0 + k * bd;
+      if (i < dim) {
+        const double pr = (double)x[k].x * (double)x[k].x + (double)x[k].y * (double)x[k].y;
+        if (i & qb) s1 += pr; else s0 += pr;
+      }
+    }
+  }
+  s0 = bwave_sum(s0);
+  s1 = bwave_sum(s1);
+  if (lane == 0) {
+    red[0][w] = s0;
+    red[1][w] = s1;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double q0 = 0, q1 = 0;
+    for (int k = 0; k < (int)(bd / 64); ++k) {
+      q0 += red[0][k];
+      q1 += red[1][k];
+    }
+    const double P0 = q0 / (q0 + q1);
+    const int oc = (u < P0) ? 0 : 1;
+    const double po = oc ? q1 : q0;
+    meas[0] = po > 0 ? 1.0 / sqrt(po) : 0.0;
+    meas[1] = (double)oc;
+    if (cbit >= 0 && po > 0) cb[cbit] = (uint8_t)oc;
+  }
+  __syncthreads();
+  const double sc = meas[0];
+  const uint32_t oc = (uint32_t)meas[1];
+  if (sc != 0.0) {
+    const R scale = (R)sc;
+    for (uint32_t i0 = tid; i0 < dim; i0 += kBU * bd) {
+      C x[kBU];
+#pragma unroll
+      for (int k = 0; k < kBU; ++k)
+        if (i0 + k * bd < dim) x[k] = st[at(i0 + k * bd)];
+#pragma unroll
+      for (int k = 0; k < kBU; ++k) {
+        const uint32_t i = i0 + k * bd;
+        if (i < dim) {
+          C v = x[k];
+          if (((i & qb) != 0) == (oc != 0)) {
+            v.x *= scale;
+            v.y *= scale;
+          } else {
+            v.x = 0;
+            v.y = 0;
+          }
+          st[at(i)] = v;
+        }
+      }
+    }
+  }
+}
+
+// Runs items [rec, end) over a state of dim amplitudes in LDS.  The first
+// item's records must already sit in items[0], staged before a barrier; every
+// item ends with a barrier.
+template <typename R>
+__device__ __forceinline__ void run_items(typename EVb<R>::T* st, uint32_t dim, uint32_t rec, uint32_t end,
+                                          const uint32_t* __restrict__ opw, uint8_t* cb,
+                                          uint32_t (*items)[kItemWords], double (*red)[kBatchThreads / 64],
+                                          double* meas) {
+  using C = typename EVb<R>::T;
+  const uint32_t tid = threadIdx.x, bd = blockDim.x;
+  const int lane = tid & 63, w = tid >> 6;
+  int buf = 0;
+  while (rec < end) {
+    const uint32_t* cur = items[buf];
+    const uint32_t head = __builtin_amdgcn_readfirstlane(cur[0]);
+    const int kind = head & 0xff;
+    const int ngates = kind == BK_PASS ? (int)((head >> 16) & 0xff) : 0;
+    const uint32_t next = rec + 1 + (uint32_t)ngates;
+    ItemRegs nxt{};
+    if (w == 0) nxt = load_item(opw, next, lane);   // the record array ends with padding
+    if (kind == BK_PASS) {
+      const int K = (head >> 8) & 0xff;
+      const uint32_t tw = __builtin_amdgcn_readfirstlane(cur[1]), sw = __builtin_amdgcn_readfirstlane(cur[2]);
+      const uint32_t t0 = tw & 0xff, t1 = (tw >> 8) & 0xff, t2 = (tw >> 16) & 0xff;
+      const uint32_t p0 = sw & 0xff, p1 = (sw >> 8) & 0xff, p2 = (sw >> 16) & 0xff;
+      const int G = 1 << K;
+      const uint32_t ngroups = dim >> K;
+      for (uint32_t g = tid; g < ngroups; g += bd) {
+        uint32_t base = g;
+        if (K > 0) base = ins0(base, p0);
+        if (K > 1) base = ins0(base, p1);
+        if (K > 2) base = ins0(base, p2);
+        uint32_t idx[8];
+        C x[8];
+#pragma unroll
+        for (int r = 0; r < 8; ++r) {
+          idx[r] = base | ((uint32_t)(r & 1) << t0);
+          if (K > 1) idx[r] |= (uint32_t)((r >> 1) & 1) << t1;
+          if (K > 2) idx[r] |= (uint32_t)((r >> 2) & 1) << t2;
+          if (r < G) x[r] = st[swz<R>(idx[r])];
+        }
+        for (int o = 1; o <= ngates; ++o) {
+          const uint32_t* g0 = cur + o * kOpWords;
+          const uint32_t oh = __builtin_amdgcn_readfirstlane(g0[0]);
+          const int okind = oh & 0xff, ncond = oh >> 24;
+          const uint32_t a = (oh >> 8) & 0xff, b = (oh >> 16) & 0xff;
+          if (ncond > 0) {
+            const uint32_t cw = __builtin_amdgcn_readfirstlane(g0[2]);
+            if (cb[cw & 0xff] != (uint8_t)((cw >> 8) & 0xff)) continue;
+            if (ncond > 1 && cb[(cw >> 16) & 0xff] != (uint8_t)(cw >> 24)) continue;
+          }
+          const uint32_t cm = g0[1];
+          if (okind == BK_X) {
+            QK_PASS_GATE(BK_X, U2<R>{});
+          } else if (okind == BK_U1R) {
+            U2<R> u{};
+#pragma unroll
+            for (int e = 0; e < 8; e += 2) u.v[e] = (R)ldbl(g0, 4 + 2 * e);
+            QK_PASS_GATE(BK_U1R, u);
+          } else if (okind == BK_U1) {
+            U2<R> u;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) u.v[e] = (R)ldbl(g0, 4 + 2 * e);
+            QK_PASS_GATE(BK_U1, u);
+          } else {
+            // BK_DIAG1 / BK_DIAG2 on qubits a (, b); BK_PHASE: one factor where
+            // every bit of cm is 1.  Factors picked by selects (no indexed array).
+            const int nd = okind == BK_DIAG2 ? 4 : (okind == BK_DIAG1 ? 2 : 1);
+            const R d0r = (R)ldbl(g0, 4), d0i = (R)ldbl(g0, 6);
+            const R d1r = nd > 1 ? (R)ldbl(g0, 8) : (R)0, d1i = nd > 1 ? (R)ldbl(g0, 10) : (R)0;
+            const R d2r = nd > 2 ? (R)ldbl(g0, 12) : (R)0, d2i = nd > 2 ? (R)ldbl(g0, 14) : (R)0;
+            const R d3r = nd > 2 ? (R)ldbl(g0, 16) : (R)0, d3i = nd > 2 ? (R)ldbl(g0, 18) : (R)0;
+            const uint32_t s0 = okind == BK_PHASE ? 31u : a, s1 = okind == BK_DIAG2 ? b : 31u;
+#pragma unroll
+            for (int r = 0; r < 8; ++r) {
+              if (r < G && (idx[r] & cm) == cm) {
+                const bool m0 = (idx[r] >> s0) & 1u, m1 = (idx[r] >> s1) & 1u;
+                const R er = m1 ? (m0 ? d3r : d2r) : (m0 ? d1r : d0r);
+                const R ei = m1 ? (m0 ? d3i : d2i) : (m0 ? d1i : d0i);
+                x[r] = cmul<R>(er, ei, x[r]);
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < 8; ++r)
+          if (r < G) st[swz<R>(idx[r])] = x[r];
+      }
+    } else if (kind == BK_SWAP) {
+      // quarter-space enumeration: bit t0 set, bit t1 clear, exchanged with the mirror
+      const uint32_t t0 = (head >> 8) & 0xff, t1 = (head >> 16) & 0xff, cm = __builtin_amdgcn_readfirstlane(cur[1]);
+      const uint32_t ab = 1u << t0, bb = 1u << t1, q = dim >> 2;
+      const uint32_t plo = t0 < t1 ? t0 : t1, phi = t0 < t1 ? t1 : t0;
+      bool ok = true;
+      const int ncond = head >> 24;
+      if (ncond > 0) {
+        const uint32_t cw = __builtin_amdgcn_readfirstlane(cur[2]);
+        if (cb[cw & 0xff] != (uint8_t)((cw >> 8) & 0xff)) ok = false;
+        if (ncond > 1 && cb[(cw >> 16) & 0xff] != (uint8_t)(cw >> 24)) ok = false;
+      }
+      if (ok) {
+        for (uint32_t p0 = tid; p0 < q; p0 += kBU * bd) {
+          C x[kBU], y[kBU];
+          uint32_t ia[kBU];
+#pragma unroll
+          for (int k = 0; k < kBU; ++k) {
+            const uint32_t pp = p0 + k * bd;
+            ia[k] = ins0(ins0(pp, plo), phi) | ab;
+            if (pp < q) {
+              x[k] = st[swz<R>(ia[k])];
+              y[k] = st[swz<R>(ia[k] ^ ab ^ bb)];
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < kBU; ++k) {
+            if (p0 + k * bd < q && (ia[k] & cm) == cm) {
+              st[swz<R>(ia[k])] = y[k];
+              st[swz<R>(ia[k] ^ ab ^ bb)] = x[k];
+            }
+          }
+        }
+      }
+    } else if (kind == BK_MEAS) {
+      meas_run<R, true>(st, dim, 1u << ((head >> 8) & 0xff), ldbl(cur, 4), (int)cur[3], cb, red, meas);
+    }
+    // the next item's records into the other buffer (its last readers
+    // finished before the barrier that ended the previous item)
+    if (w == 0) stage_item(items[buf ^ 1], nxt, lane);
+    __syncthreads();
+    buf ^= 1;
+    rec = next;
+  }
+}
+
+// Bits of v deposited, lowest first, at the set bits of mask.
+__device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask) {
+  uint32_t out = 0;
+  for (uint32_t m = mask; m; m &= m - 1, v >>= 1)
+    if (v & 1u) out |= m & (~m + 1u);
+  return out;
+}
+
 template <typename R>
 __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_batch(const BJob* __restrict__ jobs, int njobs,
                                                          const uint32_t* __restrict__ opw,
                                                          typename EVb<R>::T* __restrict__ states,
                                                          uint8_t* __restrict__ cbits, int* counter) {
   using C = typename EVb<R>::T;
+  constexpr int LQ = stage_qubits<R>(), PT = stage_per_thread<R>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* st = reinterpret_cast<C*>(smem_raw);
   __shared__ uint8_t cb[kMaxJobCbits];
@@ -216,201 +454,102 @@ __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_ba
     if (j >= njobs) break;
     const BJob jb = jobs[j];
     const uint32_t dim = 1u << jb.n;
-    if (w == 0) stage_item(items[0], load_item(opw, jb.op_begin, lane), lane);
-    int buf = 0;
-    for (uint32_t i = tid; i < dim; i += bd) {
-      C z;
-      z.x = (i == 0) ? (R)1 : (R)0;
-      z.y = 0;
-      st[swz<R>(i)] = z;
-    }
+    const bool staged = jb.staged != 0;
+    C* gst = states + jb.state_off;
     for (int c = tid; c < jb.ncbits; c += bd) cb[c] = 0;
-    __syncthreads();
-    for (uint32_t rec = jb.op_begin; rec < jb.op_end;) {
-      const uint32_t* cur = items[buf];
-      const uint32_t head = __builtin_amdgcn_readfirstlane(cur[0]);
-      const int kind = head & 0xff;
-      const int ngates = kind == BK_PASS ? (int)((head >> 16) & 0xff) : 0;
-      const uint32_t next = rec + 1 + (uint32_t)ngates;
-      ItemRegs nxt{};
-      if (w == 0) nxt = load_item(opw, next, lane);   // the record array ends with padding
-      if (kind == BK_PASS) {
-        const int K = (head >> 8) & 0xff;
-        const uint32_t tw = __builtin_amdgcn_readfirstlane(cur[1]), sw = __builtin_amdgcn_readfirstlane(cur[2]);
-        const uint32_t t0 = tw & 0xff, t1 = (tw >> 8) & 0xff, t2 = (tw >> 16) & 0xff;
-        const uint32_t p0 = sw & 0xff, p1 = (sw >> 8) & 0xff, p2 = (sw >> 16) & 0xff;
-        const int G = 1 << K;
-        const uint32_t ngroups = dim >> K;
-        for (uint32_t g = tid; g < ngroups; g += bd) {
-          uint32_t base = g;
-          if (K > 0) base = ins0(base, p0);
-          if (K > 1) base = ins0(base, p1);
-          if (K > 2) base = ins0(base, p2);
-          uint32_t idx[8];
-          C x[8];
-#pragma unroll
-          for (int r = 0; r < 8; ++r) {
-            idx[r] = base | ((uint32_t)(r & 1) << t0);
-            if (K > 1) idx[r] |= (uint32_t)((r >> 1) & 1) << t1;
-            if (K > 2) idx[r] |= (uint32_t)((r >> 2) & 1) << t2;
-            if (r < G) x[r] = st[swz<R>(idx[r])];
-          }
-          for (int o = 1; o <= ngates; ++o) {
-            const uint32_t* g0 = cur + o * kOpWords;
-            const uint32_t oh = __builtin_amdgcn_readfirstlane(g0[0]);
-            const int okind = oh & 0xff, ncond = oh >> 24;
-            const uint32_t a = (oh >> 8) & 0xff, b = (oh >> 16) & 0xff;
-            if (ncond > 0) {
-              const uint32_t cw = __builtin_amdgcn_readfirstlane(g0[2]);
-              if (cb[cw & 0xff] != (uint8_t)((cw >> 8) & 0xff)) continue;
-              if (ncond > 1 && cb[(cw >> 16) & 0xff] != (uint8_t)(cw >> 24)) continue;
-            }
-            const uint32_t cm = g0[1];
-            if (okind == BK_X) {
-              QK_PASS_GATE(BK_X, U2<R>{});
-            } else if (okind == BK_U1R) {
-              U2<R> u{};
-#pragma unroll
-              for (int e = 0; e < 8; e += 2) u.v[e] = (R)ldbl(g0, 4 + 2 * e);
-              QK_PASS_GATE(BK_U1R, u);
-            } else if (okind == BK_U1) {
-              U2<R> u;
-#pragma unroll
-              for (int e = 0; e < 8; ++e) u.v[e] = (R)ldbl(g0, 4 + 2 * e);
-              QK_PASS_GATE(BK_U1, u);
-            } else {
-              // BK_DIAG1 / BK_DIAG2 on qubits a (, b); BK_PHASE: one factor where
-              // every bit of cm is 1.  Factors picked by selects (no indexed array).
-              const int nd = okind == BK_DIAG2 ? 4 : (okind == BK_DIAG1 ? 2 : 1);
-              const R d0r = (R)ldbl(g0, 4), d0i = (R)ldbl(g0, 6);
-              const R d1r = nd > 1 ? (R)ldbl(g0, 8) : (R)0, d1i = nd > 1 ? (R)ldbl(g0, 10) : (R)0;
-              const R d2r = nd > 2 ? (R)ldbl(g0, 12) : (R)0, d2i = nd > 2 ? (R)ldbl(g0, 14) : (R)0;
-              const R d3r = nd > 2 ? (R)ldbl(g0, 16) : (R)0, d3i = nd > 2 ? (R)ldbl(g0, 18) : (R)0;
-              const uint32_t s0 = okind == BK_PHASE ? 31u : a, s1 = okind == BK_DIAG2 ? b : 31u;
-#pragma unroll
-              for (int r = 0; r < 8; ++r) {
-                if (r < G && (idx[r] & cm) == cm) {
-                  const bool m0 = (idx[r] >> s0) & 1u, m1 = (idx[r] >> s1) & 1u;
-                  const R er = m1 ? (m0 ? d3r : d2r) : (m0 ? d1r : d0r);
-                  const R ei = m1 ? (m0 ? d3i : d2i) : (m0 ? d1i : d0i);
-                  x[r] = cmul<R>(er, ei, x[r]);
-                }
-              }
-            }
-          }
-#pragma unroll
-          for (int r = 0; r < 8; ++r)
-            if (r < G) st[swz<R>(idx[r])] = x[r];
-        }
-      } else if (kind == BK_SWAP) {
-        // quarter-space enumeration: bit t0 set, bit t1 clear, exchanged with the mirror
-        const uint32_t t0 = (head >> 8) & 0xff, t1 = (head >> 16) & 0xff, cm = __builtin_amdgcn_readfirstlane(cur[1]);
-        const uint32_t ab = 1u << t0, bb = 1u << t1, q = dim >> 2;
-        const uint32_t plo = t0 < t1 ? t0 : t1, phi = t0 < t1 ? t1 : t0;
-        bool ok = true;
-        const int ncond = head >> 24;
-        if (ncond > 0) {
-          const uint32_t cw = __builtin_amdgcn_readfirstlane(cur[2]);
-          if (cb[cw & 0xff] != (uint8_t)((cw >> 8) & 0xff)) ok = false;
-          if (ncond > 1 && cb[(cw >> 16) & 0xff] != (uint8_t)(cw >> 24)) ok = false;
-        }
-        if (ok) {
-          for (uint32_t p0 = tid; p0 < q; p0 += kBU * bd) {
-            C x[kBU], y[kBU];
-            uint32_t ia[kBU];
-#pragma unroll
-            for (int k = 0; k < kBU; ++k) {
-              const uint32_t pp = p0 + k * bd;
-              ia[k] = ins0(ins0(pp, plo), phi) | ab;
-              if (pp < q) {
-                x[k] = st[swz<R>(ia[k])];
-                y[k] = st[swz<R>(ia[k] ^ ab ^ bb)];
-              }
-            }
-#pragma unroll
-            for (int k = 0; k < kBU; ++k) {
-              if (p0 + k * bd < q && (ia[k] & cm) == cm) {
-                st[swz<R>(ia[k])] = y[k];
-                st[swz<R>(ia[k] ^ ab ^ bb)] = x[k];
-              }
-            }
-          }
-        }
-      } else if (kind == BK_MEAS) {
-        const uint32_t qb = 1u << ((head >> 8) & 0xff);
-        double s0 = 0, s1 = 0;
-        for (uint32_t i0 = tid; i0 < dim; i0 += kBU * bd) {
-          C x[kBU];
-#pragma unroll
-          for (int k = 0; k < kBU; ++k)
-            if (i0 + k * bd < dim) x[k] = st[swz<R>(i0 + k * bd)];
-#pragma unroll
-          for (int k = 0; k < kBU; ++k) {
-            const uint32_t i = i0 + k * bd;
-            if (i < dim) {
-              const double pr = (double)x[k].x * (double)x[k].x + (double)x[k].y * (double)x[k].y;
-              if (i & qb) s1 += pr; else s0 += pr;
-            }
-          }
-        }
-        s0 = bwave_sum(s0);
-        s1 = bwave_sum(s1);
-        if (lane == 0) {
-          red[0][w] = s0;
-          red[1][w] = s1;
-        }
-        __syncthreads();
-        if (tid == 0) {
-          double q0 = 0, q1 = 0;
-          for (int k = 0; k < (int)(bd / 64); ++k) {
-            q0 += red[0][k];
-            q1 += red[1][k];
-          }
-          const double u = ldbl(cur, 4);
-          const int cbit = (int)cur[3];
-          const double P0 = q0 / (q0 + q1);
-          const int oc = (u < P0) ? 0 : 1;
-          const double po = oc ? q1 : q0;
-          meas[0] = po > 0 ? 1.0 / sqrt(po) : 0.0;
-          meas[1] = (double)oc;
-          if (cbit >= 0 && po > 0) cb[cbit] = (uint8_t)oc;
-        }
-        __syncthreads();
-        const double sc = meas[0];
-        const uint32_t oc = (uint32_t)meas[1];
-        if (sc != 0.0) {
-          const R scale = (R)sc;
-          for (uint32_t i0 = tid; i0 < dim; i0 += kBU * bd) {
-            C x[kBU];
-#pragma unroll
-            for (int k = 0; k < kBU; ++k)
-              if (i0 + k * bd < dim) x[k] = st[swz<R>(i0 + k * bd)];
-#pragma unroll
-            for (int k = 0; k < kBU; ++k) {
-              const uint32_t i = i0 + k * bd;
-              if (i < dim) {
-                C v = x[k];
-                if (((i & qb) != 0) == (oc != 0)) {
-                  v.x *= scale;
-                  v.y *= scale;
-                } else {
-                  v.x = 0;
-                  v.y = 0;
-                }
-                st[swz<R>(i)] = v;
-              }
-            }
-          }
-        }
+    if (staged) {
+      for (uint32_t i = tid; i < dim; i += bd) {
+        C z;
+        z.x = (i == 0) ? (R)1 : (R)0;
+        z.y = 0;
+        gst[i] = z;
       }
-      // the next item's records into the other buffer (its last readers
-      // finished before the barrier that ended the previous item)
-      if (w == 0) stage_item(items[buf ^ 1], nxt, lane);
-      __syncthreads();
-      buf ^= 1;
-      rec = next;
     }
-    for (uint32_t i = tid; i < dim; i += bd) states[jb.state_off + i] = st[swz<R>(i)];
+    __syncthreads();
+    // A job in LDS is one unit: its items over the whole state, from |0...0>
+    // in LDS, written out at the end.  A staged job is a list of stages and
+    // measurements; a stage's items run on every LDS chunk of its qubits.
+    uint32_t rec = jb.op_begin;
+    bool first = true;
+    while (rec < jb.op_end || (first && !staged)) {
+      first = false;
+      uint32_t it_begin = rec, it_end = jb.op_end, nchunks = 1, ldim = dim, cmask = 0, shigh = 0, base = 0;
+      if (staged) {
+        const uint32_t* h = opw + (size_t)rec * kOpWords;
+        const uint32_t head = __builtin_amdgcn_readfirstlane(h[0]);
+        if ((head & 0xff) == BK_MEAS) {
+          // readfirstlane returns a signed int: widen through uint32_t
+          const uint64_t ulo = (uint32_t)__builtin_amdgcn_readfirstlane(h[4]);
+          const uint64_t uhi = (uint32_t)__builtin_amdgcn_readfirstlane(h[5]);
+          const double u = __longlong_as_double((long long)(ulo | (uhi << 32)));
+          meas_run<R, false>(gst, dim, 1u << ((head >> 8) & 0xff), u, (int)__builtin_amdgcn_readfirstlane(h[3]), cb, red,
+                             meas);
+          __syncthreads();
+          ++rec;
+          continue;
+        }
+        // BK_STAGE: cmask word = records in the stage, bytes of m = the global
+        // qubit of each local bit, ascending
+        it_begin = rec + 1;
+        it_end = it_begin + __builtin_amdgcn_readfirstlane(h[1]);
+        uint32_t smask = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const uint32_t wq = __builtin_amdgcn_readfirstlane(h[4 + q]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (4 * q + e < LQ) smask |= 1u << ((wq >> (8 * e)) & 0xff);
+        }
+        ldim = 1u << LQ;
+        nchunks = dim >> LQ;
+        cmask = (dim - 1) & ~smask;
+        // local index tid + k * 512: its low 9 bits (the thread) land on the
+        // lowest 9 qubits of the stage, k on the others (the same for every
+        // thread); the chunk number on the qubits outside the stage
+        uint32_t slow = 0;
+        shigh = smask;
+        for (int e = 0; e < 9; ++e) {
+          slow |= shigh & (~shigh + 1u);
+          shigh &= shigh - 1;
+        }
+        base = deposit(tid, slow);
+      }
+      for (uint32_t ch = 0; ch < nchunks; ++ch) {
+        if (w == 0) stage_item(items[0], load_item(opw, it_begin, lane), lane);
+        if (staged) {
+          const uint32_t cpart = deposit(ch, cmask);
+#pragma unroll 1
+          for (int k0 = 0; k0 < PT; k0 += 8) {   // 8 loads in flight per thread
+            C x[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) x[k] = gst[base | deposit((uint32_t)(k0 + k), shigh) | cpart];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) st[swz<R>(tid + (uint32_t)(k0 + k) * bd)] = x[k];
+          }
+        } else {
+          for (uint32_t i = tid; i < dim; i += bd) {
+            C z;
+            z.x = (i == 0) ? (R)1 : (R)0;
+            z.y = 0;
+            st[swz<R>(i)] = z;
+          }
+        }
+        __syncthreads();
+        run_items<R>(st, ldim, it_begin, it_end, opw, cb, items, red, meas);
+        if (staged) {
+          const uint32_t cpart = deposit(ch, cmask);
+#pragma unroll 1
+          for (int k0 = 0; k0 < PT; k0 += 8)
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+              gst[base | deposit((uint32_t)(k0 + k), shigh) | cpart] = st[swz<R>(tid + (uint32_t)(k0 + k) * bd)];
+        } else {
+          for (uint32_t i = tid; i < dim; i += bd) gst[i] = st[swz<R>(i)];
+        }
+        __syncthreads();
+      }
+      rec = it_end;
+    }
     for (int c = tid; c < jb.ncbits; c += bd) cbits[jb.cbit_off + c] = cb[c];
     __syncthreads();
   }
@@ -472,9 +611,132 @@ std::vector<BOp> build_items(int n, const std::vector<BOp>& ops) {
   return out;
 }
 
+// Qubits an op record touches (targets and controls) as a bit mask.
+uint32_t op_mask(const BOp& o) {
+  const int kind = o.head & 0xff;
+  const uint32_t t0 = (o.head >> 8) & 0xff, t1 = (o.head >> 16) & 0xff;
+  if (kind == BK_PHASE) return o.cmask;   // already holds targets and controls
+  if (kind == BK_DIAG2 || kind == BK_SWAP) return o.cmask | (1u << t0) | (1u << t1);
+  return o.cmask | (1u << t0);
+}
+
+bool op_diag(const BOp& o) {
+  const int kind = o.head & 0xff;
+  return kind == BK_DIAG1 || kind == BK_DIAG2 || kind == BK_PHASE;
+}
+
+// The record with its qubits renumbered through loc (global -> local).
+BOp to_local(BOp o, const std::vector<int>& loc) {
+  const int kind = o.head & 0xff;
+  const uint32_t t0 = (o.head >> 8) & 0xff, t1 = (o.head >> 16) & 0xff;
+  const bool two = kind == BK_DIAG2 || kind == BK_SWAP;
+  uint32_t cm = 0;
+  for (uint32_t m = o.cmask; m; m &= m - 1) cm |= 1u << loc[__builtin_ctz(m)];
+  const uint32_t l0 = kind == BK_PHASE ? 0u : (uint32_t)loc[t0], l1 = two ? (uint32_t)loc[t1] : 0u;
+  o.head = (o.head & 0xff0000ffu) | (l0 << 8) | (l1 << 16);
+  o.cmask = cm;
+  return o;
+}
+
+// Stages of a job whose state stays in global memory (n above what LDS
+// holds).  Measurements split the list; between them, gates are grouped into
+// stages of at most L qubits by a ready frontier (a gate is ready once every
+// earlier gate on its qubits is scheduled, except that diagonal gates pass
+// one another, since they commute; gates on disjoint qubits commute too, so
+// any order of ready gates is valid).  A stage grows by the ready gate that
+// adds the fewest new qubits (the earliest among equals) while the union
+// stays within L qubits, then takes the lowest unused qubits up to L.  Each
+// stage becomes a BK_STAGE header (record count, the L qubits ascending)
+// followed by its items over local qubits 0..L-1.
+std::vector<BOp> plan_stages(int n, int L, const std::vector<BOp>& ops) {
+  std::vector<BOp> out;
+  const int kScan = 8;   // diagonal gates looked at behind the first unscheduled gate of a qubit
+  size_t i0 = 0;
+  while (i0 < ops.size()) {
+    if ((ops[i0].head & 0xff) == BK_MEAS) {
+      out.push_back(ops[i0++]);
+      continue;
+    }
+    size_t i1 = i0;
+    while (i1 < ops.size() && (ops[i1].head & 0xff) != BK_MEAS) ++i1;
+    const int N = (int)(i1 - i0);
+    std::vector<uint32_t> gm(N);
+    std::vector<char> dg(N), done(N, 0);
+    std::vector<std::vector<int>> onq(n);
+    for (int i = 0; i < N; ++i) {
+      gm[i] = op_mask(ops[i0 + i]);
+      dg[i] = op_diag(ops[i0 + i]);
+      for (uint32_t m = gm[i]; m; m &= m - 1) onq[__builtin_ctz(m)].push_back(i);
+    }
+    std::vector<size_t> head(n, 0);
+    auto ready = [&](int i) {
+      for (uint32_t m = gm[i]; m; m &= m - 1) {
+        const int q = __builtin_ctz(m);
+        for (size_t p = head[q]; p < onq[q].size(); ++p) {
+          const int j = onq[q][p];
+          if (j == i) break;
+          if (done[j] || (dg[i] && dg[j])) continue;
+          return false;
+        }
+      }
+      return true;
+    };
+    int left = N;
+    while (left > 0) {
+      uint32_t S = 0;
+      std::vector<int> members;
+      for (;;) {
+        int best = -1, best_new = 64;
+        for (int q = 0; q < n; ++q) {
+          while (head[q] < onq[q].size() && done[onq[q][head[q]]]) ++head[q];
+          int seen = 0;
+          for (size_t p = head[q]; p < onq[q].size() && seen <= kScan; ++p) {
+            const int j = onq[q][p];
+            if (done[j]) continue;
+            ++seen;
+            if (seen > 1 && !dg[j]) break;
+            const int nw = __builtin_popcount(gm[j] & ~S);
+            if (__builtin_popcount(S | gm[j]) <= L && (nw < best_new || (nw == best_new && j < best)) && ready(j)) {
+              best = j;
+              best_new = nw;
+            }
+            if (!dg[j]) break;
+          }
+        }
+        if (best < 0) break;
+        S |= gm[best];
+        done[best] = 1;
+        members.push_back(best);
+        --left;
+      }
+      for (int q = 0; q < n && __builtin_popcount(S) < L; ++q) S |= 1u << q;
+      std::vector<int> loc(n, -1);
+      std::vector<uint8_t> qs;
+      for (int q = 0; q < n; ++q)
+        if ((S >> q) & 1) {
+          loc[q] = (int)qs.size();
+          qs.push_back((uint8_t)q);
+        }
+      std::vector<BOp> local;
+      local.reserve(members.size());
+      for (int i : members) local.push_back(to_local(ops[i0 + i], loc));
+      std::vector<BOp> items = build_items(L, local);
+      BOp h{};
+      h.head = (uint32_t)BK_STAGE | ((uint32_t)L << 8);
+      h.cmask = (uint32_t)items.size();
+      std::memcpy(h.m, qs.data(), qs.size());
+      out.push_back(h);
+      out.insert(out.end(), items.begin(), items.end());
+    }
+    i0 = i1;
+  }
+  return out;
+}
+
 struct HostJob {
   int n, ncbits;
-  std::vector<BOp> ops;   // items (passes and single records), ready to upload
+  bool staged = false;    // state in global memory, run by stages
+  std::vector<BOp> ops;   // items (passes and single records), or stages and measurements, ready to upload
   uint64_t state_off = 0;
   uint32_t cbit_off = 0;
 };
@@ -543,7 +805,11 @@ qk_status bensure(qk_batch b, void*& p, size_t& cur, size_t need, const char* wh
   return QK_OK;
 }
 
-int max_batch_qubits(bool c64) { return c64 ? 14 : 13; }
+// Jobs up to these sizes keep their whole state in LDS; larger ones, up to
+// kMaxStagedQubits, keep it in global memory and run by stages of
+// stage_qubits() qubits through LDS.
+int max_lds_qubits(bool c64) { return c64 ? 14 : 13; }
+constexpr int kMaxStagedQubits = 24;
 
 }  // namespace
 
@@ -584,8 +850,8 @@ const char* qk_batch_last_error(qk_batch b) { return b ? b->err.c_str() : g_batc
 
 qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, int32_t nops, int32_t* job) {
   if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
-  if (n < 1 || n > max_batch_qubits(b->c64))
-    return bfail(b, QK_E_ARG, "qubit count outside the batched range (1.." + std::to_string(max_batch_qubits(b->c64)) + ")");
+  if (n < 1 || n > kMaxStagedQubits)
+    return bfail(b, QK_E_ARG, "qubit count outside the batched range (1.." + std::to_string(kMaxStagedQubits) + ")");
   if (ncbits < 0 || ncbits > kMaxJobCbits) return bfail(b, QK_E_ARG, "cbit count outside 0..256");
   if (nops < 0 || (nops > 0 && !ops)) return bfail(b, QK_E_ARG, "bad op array");
   HostJob hj;
@@ -671,7 +937,9 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
     d.head = (uint32_t)kind | ((uint32_t)t0 << 8) | ((uint32_t)t1 << 16) | ((uint32_t)o.n_conds << 24);
     hj.ops.push_back(d);
   }
-  hj.ops = build_items(n, hj.ops);
+  hj.staged = n > max_lds_qubits(b->c64);
+  hj.ops = hj.staged ? plan_stages(n, b->c64 ? stage_qubits<float>() : stage_qubits<double>(), hj.ops)
+                     : build_items(n, hj.ops);
   b->jobs.push_back(std::move(hj));
   if (job) *job = (int32_t)b->jobs.size() - 1;
   b->ran = false;
@@ -716,7 +984,8 @@ qk_status qk_batch_run(qk_batch b) {
   // layout: states and cbits in job order; the queue visits the largest jobs first
   uint64_t soff = 0;
   uint32_t coff = 0, ooff = 0;
-  int nmax = 0;
+  int nmax = 0;   // largest job kept in LDS, or the stage chunk when larger
+  const int lq = b->c64 ? stage_qubits<float>() : stage_qubits<double>();
   std::vector<BOp> all_ops;
   std::vector<BJob> table;
   for (auto& j : b->jobs) {
@@ -724,7 +993,7 @@ qk_status qk_batch_run(qk_batch b) {
     j.cbit_off = coff;
     soff += 1ull << j.n;
     coff += (uint32_t)j.ncbits;
-    nmax = std::max(nmax, j.n);
+    nmax = std::max(nmax, j.staged ? lq : j.n);
   }
   std::vector<int> order(b->jobs.size());
   std::iota(order.begin(), order.end(), 0);
@@ -744,6 +1013,7 @@ qk_status qk_batch_run(qk_batch b) {
     t.n = j.n;
     t.ncbits = j.ncbits;
     t.cbit_off = j.cbit_off;
+    t.staged = j.staged ? 1 : 0;
     table.push_back(t);
   }
   all_ops.resize(all_ops.size() + kPadRecords);   // padding: the kernel reads the next item before knowing its size

@@ -14,13 +14,19 @@ Jobs (a circuit and a dtype) arrive over time.  The loop, run on the host:
   one persistent batch launch per dtype (``qk_batch_run``), up to two batch
   launches in flight per dtype, so jobs that arrive while a batch runs go into
   the next one;
+* optionally (``mid_max``) packs mid-size jobs, above that and up to mid_max
+  qubits, into batch launches of their own (the batch kernel runs them by
+  stages through LDS, one workgroup per job), kept apart from the small jobs'
+  batches so a long mid-size batch never holds back small results;
 * gives every admitted large job its own stream slot and enqueues its whole
   circuit there (fused into matrix-core blocks as configured, or as the
   autotuner chose for that qubit count and dtype); slots run concurrently,
   so their sweeps overlap on the device;
 * polls completion events and, for each finished job, reads its cbits and a
   digest (norm; for small jobs the whole state) back to the host, frees its
-  memory and records its latency (arrival -> result on the host).
+  memory and records its latency (arrival -> result on the host).  A
+  mid-size batched job's state is read back only when asked for
+  (``keep_states``), and so is its norm.
 
 States stay resident in HBM for the whole circuit; nothing but the result
 crosses to the host.  A job's result does not depend on the other jobs in
@@ -105,7 +111,7 @@ class Server:
     def __init__(self, hbm_budget: Optional[int] = None, slots: int = 8,
                  fusion: Optional[Dict[str, int]] = None, keep_states: Sequence[int] = (),
                  small_max: Optional[Dict[str, int]] = None, poll_sleep: float = 20e-6,
-                 autotuned: bool = False):
+                 autotuned: bool = False, mid_max: Optional[Dict[str, int]] = None):
         import torch
         self.torch = torch
         if hbm_budget is None:
@@ -116,6 +122,7 @@ class Server:
         self.fusion = {"c128": 0, "c64": 5} if fusion is None else dict(fusion)
         self.keep_states = set(keep_states)
         self.small_max = dict(SMALL_MAX if small_max is None else small_max)
+        self.mid_max = dict(self.small_max if mid_max is None else mid_max)
         self.poll_sleep = poll_sleep
         # large jobs take the autotuner's fusion width and tile shape for their size
         self.tuning_cache = _autotune.load_cache() if autotuned else None
@@ -162,9 +169,11 @@ class Server:
         arrivals = [a if realtime else 0.0 for a, _, _ in jobs]
         streams = [torch.cuda.Stream() for _ in range(self.slots)]
         free_slots = deque(range(self.slots))
-        bstreams = {dt: [torch.cuda.Stream(), torch.cuda.Stream()] for dt in ("c128", "c64")}
-        bpool = {dt: [Batch(dt, stream=s) for s in bstreams[dt]] for dt in ("c128", "c64")}
-        bfree = {dt: deque(range(2)) for dt in ("c128", "c64")}
+        # batch pools: small jobs ("c128", "c64") and mid-size jobs ("mid-c128", "mid-c64")
+        pools = ("c128", "c64", "mid-c128", "mid-c64")
+        bstreams = {p: [torch.cuda.Stream(), torch.cuda.Stream()] for p in pools}
+        bpool = {p: [Batch(p.split("-")[-1], stream=s) for s in bstreams[p]] for p in pools}
+        bfree = {p: deque(range(2)) for p in pools}
         pending: deque = deque()
         inflight_stream = []   # (slot, sim, event, job index)
         inflight_batch = []    # (dtype, pool index, event, [(job index, batch job id)])
@@ -216,9 +225,10 @@ class Server:
                     b = bpool[dt][pi]
                     for j, bj in members:
                         r = res[j]
-                        r.state = b.state(bj)
+                        if r.n <= self.small_max[r.dtype] or j in self.keep_states:
+                            r.state = b.state(bj)
+                            r.norm2 = float(np.vdot(r.state, r.state).real)
                         r.cbits = b.cbits(bj)
-                        r.norm2 = float(np.vdot(r.state, r.state).real)
                         r.done = now()
                         used -= footprint(r.n, r.dtype, batched=True)
                         finished += 1
@@ -229,13 +239,14 @@ class Server:
             inflight_batch = still
 
             # ---- admission (arrival order; a job that does not fit yet waits, later small ones may pass)
-            small: Dict[str, List[int]] = {"c128": [], "c64": []}
+            small: Dict[str, List[int]] = {p: [] for p in pools}
             keep = deque()
             while pending:
                 j = pending.popleft()
                 _, circ, dt = jobs[j]
                 r = res[j]
-                small_job = r.n <= self.small_max[dt] and recs[j] is not None
+                small_job = r.n <= self.mid_max[dt] and recs[j] is not None
+                pool = dt if r.n <= self.small_max[dt] else "mid-" + dt
                 fp = footprint(r.n, dt, circ, batched=small_job)
                 if fp > self.budget:
                     r.path, r.error = "refused", f"state of {r.n} qubits ({fp} B) exceeds the HBM budget"
@@ -246,8 +257,8 @@ class Server:
                     keep.append(j)
                     continue
                 if small_job:
-                    if bfree[dt]:
-                        small[dt].append(j)
+                    if bfree[pool]:
+                        small[pool].append(j)
                         used += fp
                         r.admitted = now()
                     else:
@@ -287,7 +298,7 @@ class Server:
                     free_slots.append(slot)
                     finished += 1
             pending = keep
-            for dt in ("c128", "c64"):
+            for dt in pools:
                 if not small[dt]:
                     continue
                 pi = bfree[dt].popleft()
@@ -302,7 +313,7 @@ class Server:
                     except (QKError, ValueError) as e:
                         r.path, r.error = "failed", str(e)
                         r.done = now()
-                        used -= footprint(r.n, dt, batched=True)
+                        used -= footprint(r.n, r.dtype, batched=True)
                         finished += 1
                 if members:
                     b.run()

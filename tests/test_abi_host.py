@@ -145,7 +145,8 @@ def test_batch_host_validation():
     op.targets[0] = 0
     ops = (qk.QkOp * 1)(op)
     job = C.c_int32()
-    assert lib.qk_batch_add(h, 14, 0, ops, 1, C.byref(job)) == -1      # too many qubits for c128
+    assert lib.qk_batch_add(h, 25, 0, ops, 1, C.byref(job)) == -1      # above the batched range
+    assert lib.qk_batch_add(h, 0, 0, ops, 1, C.byref(job)) == -1
     assert lib.qk_batch_add(h, 4, 0, ops, 1, C.byref(job)) == 0 and job.value == 0
     op.gate = 0x100                                                    # user gates are not batched
     ops = (qk.QkOp * 1)(op)
@@ -160,6 +161,11 @@ def test_batch_host_validation():
     assert lib.qk_batch_add(h, 4, 2, (qk.QkOp * 1)(m), 1, C.byref(job)) == -1
     n = C.c_int32()
     assert lib.qk_batch_num_jobs(h, C.byref(n)) == 0 and n.value == 1
+    # jobs above what LDS holds are staged (host planning only, no device work)
+    op.targets[0] = 23
+    ops = (qk.QkOp * 1)(op)
+    assert lib.qk_batch_add(h, 24, 0, ops, 1, C.byref(job)) == 0 and job.value == 1
+    assert lib.qk_batch_add(h, 14, 0, ops, 1, C.byref(job)) == -1      # qubit 23 out of range
     assert lib.qk_batch_destroy(h) == 0
 
 

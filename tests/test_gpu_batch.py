@@ -110,12 +110,12 @@ def test_batch_rerun_and_clear():
 
 
 def test_graph_of_a_long_fused_circuit():
-    """A captured circuit whose block matrices (712 complex128 6-qubit blocks,
-    45.6 MiB) need several arena chunks: the capture adds chunks instead of
+    """A captured circuit whose block matrices (720 complex128 6-qubit blocks
+    among 791, 45 MiB) need several arena chunks: the capture adds chunks instead of
     recycling, and every replay equals the oracle."""
     import torch
     import paper_1908_07187_amd as qk
-    c = W.c0_random_layers(n=12, layers=260, seed=17, rzz=True)
+    c = W.c0_random_layers(n=12, layers=400, seed=17, rzz=True)
     ref, _, _ = oracle.run(c)
     s = qk.Sim("c128", stream=torch.cuda.Stream())     # capture needs a non-default stream
     s.add_qubits(12)
@@ -247,3 +247,103 @@ def test_ipe_graph_replays_with_new_uniforms():
     g.close()
     s.close()
     side.close()
+
+
+# ---- jobs above what LDS holds: state in global memory, run by stages
+
+def _staged_job(seed, n, n_gates):
+    """Random builtin circuit over every batched gate kind: one-qubit gates
+    (bit flip, real, complex), diagonal one- and two-qubit gates, phases and
+    swaps, with up to three controls, cbit conditions and measurements, so
+    that stages meet commuting diagonal runs, blocked qubits and measurement
+    boundaries."""
+    rng = rng_for(seed)
+    ops = [W.add_qubits(n), W.add_cbits(2)] + [W.gate("H", [q]) for q in range(n)]   # every qubit in play
+    one = ["H", "X", "Y", "Z", "S", "T", "SDG", "TDG", "RX", "RY", "RZ", "PHASE"]
+    two = ["CPHASE", "SWAP", "RZZ"]
+    for _ in range(n_gates):
+        r = rng.random()
+        qs = [int(x) for x in rng.permutation(n)]
+        if r < 0.04:
+            ops.append(W.measure(qs[0], cbit=int(rng.integers(2)), u=float(rng.random())))
+            continue
+        ncont = int(rng.integers(0, 4)) if rng.random() < 0.35 else 0
+        conds = [(int(rng.integers(2)), int(rng.integers(2)))] if rng.random() < 0.1 else []
+        if r < 0.7:
+            nm = one[int(rng.integers(len(one)))]
+            prm = (float(rng.uniform(0, 2 * np.pi)),) if nm in ("RX", "RY", "RZ", "PHASE") else ()
+            ops.append(W.gate(nm, [qs[0]], controls=qs[1:1 + ncont], conds=conds, params=prm))
+        else:
+            nm = two[int(rng.integers(len(two)))]
+            prm = (float(rng.uniform(0, 2 * np.pi)),) if nm != "SWAP" else ()
+            ops.append(W.gate(nm, qs[:2], controls=qs[2:2 + min(ncont, 2)], conds=conds, params=prm))
+    return W.Circuit(ops, label=f"staged_n{n}_seed{seed}")
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_staged_jobs_match_oracle(dtype):
+    """Jobs of 14..20 qubits (complex128) and 15..20 (complex64), uneven
+    sizes in one launch together with LDS-resident jobs, against the oracle;
+    cbits bit-exact."""
+    import paper_1908_07187_amd as qk
+    lo = 14 if dtype == "c128" else 15
+    jobs = [_staged_job(100 + i, n, 60 + 15 * i) for i, n in enumerate([lo, lo, 16, 17, 18, 20, lo + 1, 19])]
+    jobs += _jobs(7, 6, n_range=(3, 12))
+    b = qk.Batch(dtype)
+    ids = [qk.add_circuit(b, c) for c in jobs]
+    print(f"[gpu-batch] staged: {len(jobs)} jobs dtype={dtype} n={[c.n_qubits for c in jobs]}", flush=True)
+    b.run()
+    b.sync()
+    checked = 0
+    for c, j in zip(jobs, ids):
+        ref, rcb, recs = oracle.run(c)
+        if any(abs(r.u - r.P0) <= 1e-9 for r in recs):
+            continue
+        assert list(b.cbits(j)) == list(rcb), c.label
+        _check(ref, b.state(j), dtype, circ=c)
+        checked += 1
+    assert checked >= len(jobs) - 3
+    b.close()
+
+
+def test_staged_job_alone_equals_in_mix():
+    """A staged job's result is bit-identical alone and among other jobs."""
+    import paper_1908_07187_amd as qk
+    big = [_staged_job(200 + i, n, 80) for i, n in enumerate([14, 17, 19])]
+    mix = qk.Batch("c128")
+    small = [qk.add_circuit(mix, c) for c in _jobs(8, 20, n_range=(4, 13))]
+    ids = [qk.add_circuit(mix, c) for c in big]
+    mix.run()
+    assert len(small) == 20
+    for c, j in zip(big, ids):
+        alone = qk.Batch("c128")
+        a = qk.add_circuit(alone, c)
+        alone.run()
+        assert np.array_equal(alone.state(a), mix.state(j))
+        assert np.array_equal(alone.cbits(a), mix.cbits(j))
+        alone.close()
+    mix.close()
+
+
+def test_staged_edge_cases():
+    """No gates (the state stays |0...0>), measurements only, the 24-qubit
+    limit, and a layered circuit whose every layer crosses the stage width;
+    sizes outside 1..24 are refused."""
+    import paper_1908_07187_amd as qk
+    jobs = [W.Circuit([W.add_qubits(15)]),
+            W.Circuit([W.add_qubits(16), W.add_cbits(2), W.measure(3, cbit=0, u=0.3), W.measure(15, cbit=1, u=0.7)]),
+            W.Circuit([W.add_qubits(24)] + [W.gate("H", [q]) for q in (0, 5, 12, 23)]
+                      + [W.gate("X", [23], controls=[0]), W.gate("RZZ", [5, 20], params=(0.7,)),
+                         W.gate("SWAP", [1, 22])]),
+            W.c0_random_layers(n=16, layers=6, seed=9, rzz=True)]
+    b = qk.Batch("c128")
+    ids = [qk.add_circuit(b, c) for c in jobs]
+    b.run()
+    for c, j in zip(jobs, ids):
+        print(f"[gpu-batch] staged edge case n={c.n_qubits} ops={len(c.ops)}", flush=True)
+        ref, rcb, _ = oracle.run(c)
+        _check(ref, b.state(j), "c128")
+        assert list(b.cbits(j)) == list(rcb)
+    with pytest.raises(qk.QKError):
+        qk.add_circuit(b, W.Circuit([W.add_qubits(25)]))
+    b.close()

@@ -276,7 +276,7 @@ def test_fused_block_uploads_span_segments_and_arena_recycling():
     (over 512 complex128 6-qubit blocks of 64 KiB) the constant arena is also
     recycled in between.  Against the oracle."""
     import paper_1908_07187_amd as qk
-    c = W.c0_random_layers(n=12, layers=260, seed=17, rzz=True)   # 712 dense blocks, 45.6 MiB of matrices
+    c = W.c0_random_layers(n=12, layers=400, seed=17, rzz=True)   # 791 blocks, 720 of 6 qubits: 45 MiB of matrices
     ref, _, _ = oracle.run(c)
     print("[gpu] long circuit, 6-qubit blocks, complex128", flush=True)
     sim = qk.run_circuit(c, dtype="c128", fusion=6)
