@@ -61,7 +61,8 @@ struct BJob {
   uint32_t op_begin, op_end;   // record range of the job's items
   int32_t n, ncbits;
   uint32_t cbit_off;
-  int32_t staged;   // state in global memory, run by stages (n above what LDS holds)
+  uint32_t st_begin, nst;   // staged jobs: their stages in the launch's stage table
+  int32_t pad;
 };
 
 // One record, 20 dwords.  An item is one record (swap, measurement) or a pass
@@ -430,11 +431,35 @@ __device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask) {
   return out;
 }
 
+// Scheduling state of a batch launch.  Staged jobs: per job a 64-bit word
+// (current stage << 32 | chunks claimed in it), the chunks completed in the
+// current stage and a finished flag.  sched[0]: every staged job below it has
+// finished (a scan hint); sched[1]: small jobs taken; sched[2]: set when a
+// workgroup found no work for stall_ticks of the wall clock, 10 s (the host
+// reports it).
+struct BStage {
+  uint32_t rec;       // record of the stage header or measurement
+  uint32_t nchunks;   // chunks of the stage (1 for a measurement)
+};
+struct JobCtl {
+  unsigned long long word;
+  unsigned int done;
+  unsigned int finished;
+};
+constexpr uint32_t kScanWindow = 128;                   // staged jobs a workgroup looks at for a free chunk
+
+__device__ __forceinline__ unsigned ld_acq(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long ld_acq64(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename R>
-__global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_batch(const BJob* __restrict__ jobs, int njobs,
-                                                         const uint32_t* __restrict__ opw,
-                                                         typename EVb<R>::T* __restrict__ states,
-                                                         uint8_t* __restrict__ cbits, int* counter) {
+__global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_batch(
+    const BJob* __restrict__ jobs, int njobs, int nstaged, const BStage* __restrict__ stages, JobCtl* ctl,
+    unsigned* sched, const uint32_t* __restrict__ opw, typename EVb<R>::T* __restrict__ states,
+    uint8_t* __restrict__ cbits, unsigned long long stall_ticks) {
   using C = typename EVb<R>::T;
   constexpr int LQ = stage_qubits<R>(), PT = stage_per_thread<R>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -442,121 +467,225 @@ __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_ba
   __shared__ uint8_t cb[kMaxJobCbits];
   __shared__ double red[2][kBatchThreads / 64];
   __shared__ double meas[2];
-  __shared__ int job_sh;
+  __shared__ int task[5];
   __shared__ uint32_t items[2][kItemWords];
   const uint32_t tid = threadIdx.x, bd = blockDim.x;
   const int lane = tid & 63, w = tid >> 6;
+  unsigned long long idle_since = 0;
   for (;;) {
-    if (tid == 0) job_sh = atomicAdd(counter, 1);
+    // ---- find work (wave 0): a free chunk of a staged job, oldest first,
+    // 64 jobs looked at per load round; else the next small job; else wait
+    // for the stages in flight, or leave once every staged job has finished
+    if (w == 0) {
+      int job = -1, stage = 0, chunk = 0, count = 1, status = 0;   // status 0: work, 1: wait, 2: leave
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane(ld_acq(&sched[0]));
+      for (uint32_t b0 = lo; job < 0 && b0 < (uint32_t)nstaged && b0 < lo + kScanWindow; b0 += 64) {
+        const uint32_t j = b0 + lane;
+        bool fin = true, avail = false;
+        if (j < (uint32_t)nstaged) {
+          fin = ld_acq(&ctl[j].finished) != 0;
+          if (!fin) {
+            const BJob& jb = jobs[j];
+            const unsigned long long wd = ld_acq64(&ctl[j].word);
+            const uint32_t s0 = (uint32_t)(wd >> 32);
+            avail = s0 < jb.nst && (uint32_t)wd < stages[jb.st_begin + s0].nchunks;
+          }
+        }
+        const unsigned long long fm = __ballot(fin);
+        if (b0 == lo && (fm & 1ull)) {   // a finished prefix: move the hint past it
+          const uint32_t np = ~fm == 0 ? 64u : (uint32_t)__builtin_ctzll(~fm);
+          if (lane == 0) atomicMax(&sched[0], b0 + np);
+        }
+        unsigned long long av = __ballot(avail);
+        while (av) {
+          const int l = __builtin_ctzll(av);
+          int got = 0, s2 = 0, c2 = 0, cnt = 0;
+          if (lane == l) {
+            // a run of chunks per claim: fewer claims and fences on large stages
+            const BJob& jb = jobs[j];
+            const uint32_t nck = stages[jb.st_begin + (uint32_t)(ld_acq64(&ctl[j].word) >> 32) % jb.nst].nchunks;
+            const uint32_t want = min(16u, max(1u, nck >> 4));
+            const unsigned long long old = atomicAdd(&ctl[j].word, (unsigned long long)want);
+            s2 = (int)(old >> 32);
+            c2 = (int)(uint32_t)old;
+            if ((uint32_t)s2 < jb.nst) {
+              const uint32_t n2 = stages[jb.st_begin + s2].nchunks;
+              got = (uint32_t)c2 < n2;
+              cnt = got ? (int)min(want, n2 - (uint32_t)c2) : 0;
+            }
+          }
+          if (__ballot(got)) {
+            job = (int)(b0 + l);
+            stage = __shfl(s2, l, 64);
+            chunk = __shfl(c2, l, 64);
+            count = __shfl(cnt, l, 64);
+            break;
+          }
+          av &= av - 1;
+        }
+      }
+      if (job >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // pairs with the release that opened the stage
+      if (lane == 0) {
+        if (job < 0 && ld_acq(&sched[1]) < (unsigned)(njobs - nstaged)) {
+          const unsigned q = atomicAdd(&sched[1], 1u);
+          if (q < (unsigned)(njobs - nstaged)) job = nstaged + (int)q;
+        }
+        if (job < 0) {
+          if (ld_acq(&sched[0]) >= (unsigned)nstaged) {
+            status = 2;
+          } else {
+            const unsigned long long t = wall_clock64();
+            if (idle_since == 0) idle_since = t;
+            if (t - idle_since > stall_ticks) {
+              atomicOr(&sched[2], 1u);
+              status = 2;
+            } else {
+              status = 1;
+            }
+          }
+        } else {
+          idle_since = 0;
+        }
+        task[0] = job;
+        task[1] = stage;
+        task[2] = chunk;
+        task[3] = status;
+        task[4] = count;
+      }
+    }
     __syncthreads();
-    // the job (and so every record) is the same for the whole workgroup
-    const int j = __builtin_amdgcn_readfirstlane(job_sh);
-    if (j >= njobs) break;
-    const BJob jb = jobs[j];
+    const int job = __builtin_amdgcn_readfirstlane(task[0]);
+    const uint32_t stage = (uint32_t)__builtin_amdgcn_readfirstlane(task[1]);
+    const uint32_t chunk = (uint32_t)__builtin_amdgcn_readfirstlane(task[2]);
+    const int status = __builtin_amdgcn_readfirstlane(task[3]);
+    const uint32_t count = (uint32_t)__builtin_amdgcn_readfirstlane(task[4]);
+    __syncthreads();   // task[] is rewritten by the next search
+    if (status == 2) break;
+    if (status == 1) {
+      __builtin_amdgcn_s_sleep(8);
+      continue;
+    }
+    const BJob jb = jobs[job];
     const uint32_t dim = 1u << jb.n;
-    const bool staged = jb.staged != 0;
     C* gst = states + jb.state_off;
-    for (int c = tid; c < jb.ncbits; c += bd) cb[c] = 0;
-    if (staged) {
+    if (job >= nstaged) {
+      // ---- a small job: |0...0> in LDS, every item, written out once
+      for (int c = tid; c < jb.ncbits; c += bd) cb[c] = 0;
+      if (w == 0) stage_item(items[0], load_item(opw, jb.op_begin, lane), lane);
       for (uint32_t i = tid; i < dim; i += bd) {
         C z;
         z.x = (i == 0) ? (R)1 : (R)0;
         z.y = 0;
-        gst[i] = z;
+        st[swz<R>(i)] = z;
       }
+      __syncthreads();
+      run_items<R>(st, dim, jb.op_begin, jb.op_end, opw, cb, items, red, meas);
+      for (uint32_t i = tid; i < dim; i += bd) gst[i] = st[swz<R>(i)];
+      for (int c = tid; c < jb.ncbits; c += bd) cbits[jb.cbit_off + c] = cb[c];
+      __syncthreads();
+      continue;
     }
+    // ---- a run of chunks of a stage (or a measurement) of a staged job.
+    // Wave 0 acquired after its claim (the invalidation covers this compute
+    // unit's caches), and the barrier above orders every wave after it, so
+    // every chunk of the earlier stages, written by any workgroup, is visible.
+    const BStage bs = stages[jb.st_begin + stage];
+    for (int c = tid; c < jb.ncbits; c += bd) cb[c] = cbits[jb.cbit_off + c];
     __syncthreads();
-    // A job in LDS is one unit: its items over the whole state, from |0...0>
-    // in LDS, written out at the end.  A staged job is a list of stages and
-    // measurements; a stage's items run on every LDS chunk of its qubits.
-    uint32_t rec = jb.op_begin;
-    bool first = true;
-    while (rec < jb.op_end || (first && !staged)) {
-      first = false;
-      uint32_t it_begin = rec, it_end = jb.op_end, nchunks = 1, ldim = dim, cmask = 0, shigh = 0, base = 0;
-      if (staged) {
-        const uint32_t* h = opw + (size_t)rec * kOpWords;
-        const uint32_t head = __builtin_amdgcn_readfirstlane(h[0]);
-        if ((head & 0xff) == BK_MEAS) {
-          // readfirstlane returns a signed int: widen through uint32_t
-          const uint64_t ulo = (uint32_t)__builtin_amdgcn_readfirstlane(h[4]);
-          const uint64_t uhi = (uint32_t)__builtin_amdgcn_readfirstlane(h[5]);
-          const double u = __longlong_as_double((long long)(ulo | (uhi << 32)));
-          meas_run<R, false>(gst, dim, 1u << ((head >> 8) & 0xff), u, (int)__builtin_amdgcn_readfirstlane(h[3]), cb, red,
-                             meas);
-          __syncthreads();
-          ++rec;
-          continue;
-        }
-        // BK_STAGE: cmask word = records in the stage, bytes of m = the global
-        // qubit of each local bit, ascending
-        it_begin = rec + 1;
-        it_end = it_begin + __builtin_amdgcn_readfirstlane(h[1]);
-        uint32_t smask = 0;
+    const uint32_t* h = opw + (size_t)bs.rec * kOpWords;
+    const uint32_t head = __builtin_amdgcn_readfirstlane(h[0]);
+    if ((head & 0xff) == BK_MEAS) {
+      // readfirstlane returns a signed int: widen through uint32_t
+      const uint64_t ulo = (uint32_t)__builtin_amdgcn_readfirstlane(h[4]);
+      const uint64_t uhi = (uint32_t)__builtin_amdgcn_readfirstlane(h[5]);
+      const double u = __longlong_as_double((long long)(ulo | (uhi << 32)));
+      const int cbit = (int)__builtin_amdgcn_readfirstlane(h[3]);
+      meas_run<R, false>(gst, dim, 1u << ((head >> 8) & 0xff), u, cbit, cb, red, meas);
+      if (tid == 0 && cbit >= 0) cbits[jb.cbit_off + cbit] = cb[cbit];
+    } else {
+      // BK_STAGE: cmask word = records in the stage, bytes of m = the global
+      // qubit of each local bit, ascending.  Local index tid + k * 512: its
+      // low 9 bits (the thread) land on the lowest 9 qubits of the stage, k
+      // on the others (the same for every thread); the chunk number on the
+      // qubits outside the stage.
+      const uint32_t it_begin = bs.rec + 1, it_end = it_begin + (uint32_t)__builtin_amdgcn_readfirstlane(h[1]);
+      uint32_t smask = 0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const uint32_t wq = __builtin_amdgcn_readfirstlane(h[4 + q]);
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t wq = (uint32_t)__builtin_amdgcn_readfirstlane(h[4 + q]);
 #pragma unroll
-          for (int e = 0; e < 4; ++e)
-            if (4 * q + e < LQ) smask |= 1u << ((wq >> (8 * e)) & 0xff);
-        }
-        ldim = 1u << LQ;
-        nchunks = dim >> LQ;
-        cmask = (dim - 1) & ~smask;
-        // local index tid + k * 512: its low 9 bits (the thread) land on the
-        // lowest 9 qubits of the stage, k on the others (the same for every
-        // thread); the chunk number on the qubits outside the stage
-        uint32_t slow = 0;
-        shigh = smask;
-        for (int e = 0; e < 9; ++e) {
-          slow |= shigh & (~shigh + 1u);
-          shigh &= shigh - 1;
-        }
-        base = deposit(tid, slow);
+        for (int e = 0; e < 4; ++e)
+          if (4 * q + e < LQ) smask |= 1u << ((wq >> (8 * e)) & 0xff);
       }
-      for (uint32_t ch = 0; ch < nchunks; ++ch) {
+      const uint32_t cmask = (dim - 1) & ~smask;
+      uint32_t slow = 0, shigh = smask;
+      for (int e = 0; e < 9; ++e) {
+        slow |= shigh & (~shigh + 1u);
+        shigh &= shigh - 1;
+      }
+      const uint32_t base = deposit(tid, slow);
+#pragma unroll 1
+      for (uint32_t ch = chunk; ch < chunk + count; ++ch) {
+        const uint32_t cpart = deposit(ch, cmask);
         if (w == 0) stage_item(items[0], load_item(opw, it_begin, lane), lane);
-        if (staged) {
-          const uint32_t cpart = deposit(ch, cmask);
 #pragma unroll 1
-          for (int k0 = 0; k0 < PT; k0 += 8) {   // 8 loads in flight per thread
-            C x[8];
+        for (int k0 = 0; k0 < PT; k0 += 8) {   // 8 loads in flight per thread
+          C x[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) x[k] = gst[base | deposit((uint32_t)(k0 + k), shigh) | cpart];
+          for (int k = 0; k < 8; ++k) {
+            const uint32_t g = base | deposit((uint32_t)(k0 + k), shigh) | cpart;
+            if (stage == 0) {   // the first stage starts from |0...0>
+              x[k].x = g == 0 ? (R)1 : (R)0;
+              x[k].y = 0;
+            } else {
+              x[k] = gst[g];
+            }
+          }
 #pragma unroll
-            for (int k = 0; k < 8; ++k) st[swz<R>(tid + (uint32_t)(k0 + k) * bd)] = x[k];
-          }
-        } else {
-          for (uint32_t i = tid; i < dim; i += bd) {
-            C z;
-            z.x = (i == 0) ? (R)1 : (R)0;
-            z.y = 0;
-            st[swz<R>(i)] = z;
-          }
+          for (int k = 0; k < 8; ++k) st[swz<R>(tid + (uint32_t)(k0 + k) * bd)] = x[k];
         }
         __syncthreads();
-        run_items<R>(st, ldim, it_begin, it_end, opw, cb, items, red, meas);
-        if (staged) {
-          const uint32_t cpart = deposit(ch, cmask);
+        run_items<R>(st, 1u << LQ, it_begin, it_end, opw, cb, items, red, meas);
 #pragma unroll 1
-          for (int k0 = 0; k0 < PT; k0 += 8)
+        for (int k0 = 0; k0 < PT; k0 += 8)
 #pragma unroll
-            for (int k = 0; k < 8; ++k)
-              gst[base | deposit((uint32_t)(k0 + k), shigh) | cpart] = st[swz<R>(tid + (uint32_t)(k0 + k) * bd)];
-        } else {
-          for (uint32_t i = tid; i < dim; i += bd) gst[i] = st[swz<R>(i)];
-        }
-        __syncthreads();
+          for (int k = 0; k < 8; ++k)
+            gst[base | deposit((uint32_t)(k0 + k), shigh) | cpart] = st[swz<R>(tid + (uint32_t)(k0 + k) * bd)];
+        __syncthreads();   // the next chunk's gather overwrites LDS
       }
-      rec = it_end;
     }
-    for (int c = tid; c < jb.ncbits; c += bd) cbits[jb.cbit_off + c] = cb[c];
+    // Release: every wave's stores have completed (waitcnt) before the
+    // barrier, then one agent-scope release (the write-back of this XCD's
+    // L2) before the chunks count as done; the workgroup that completes a
+    // stage opens the next one.
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
+    if (tid == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");   // the whole workgroup's stores, through the barrier
+      const unsigned d = atomicAdd(&ctl[job].done, count) + count;
+      if (d == bs.nchunks) {
+        atomicExch(&ctl[job].done, 0u);
+        __threadfence();
+        if (stage + 1 == jb.nst) atomicExch(&ctl[job].finished, 1u);
+        __threadfence();
+        atomicExch(&ctl[job].word, (unsigned long long)(stage + 1) << 32);
+      }
+    }
   }
 }
 
-__global__ void k_zero_counter(int* c) {
-  if (threadIdx.x == 0) *c = 0;
+// Clears a launch's scheduling state and every cbit (a staged job's cbits
+// are read by each of its chunks).  A kernel rather than a memset so that a
+// captured batch launch replays correctly.
+__global__ void k_batch_reset(JobCtl* ctl, int nctl, unsigned* sched, uint8_t* cbits, uint32_t ncbits) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x, stride = gridDim.x * blockDim.x;
+  for (uint32_t k = i; k < (uint32_t)nctl; k += stride) {
+    ctl[k].word = 0;
+    ctl[k].done = 0;
+    ctl[k].finished = 0;
+  }
+  for (uint32_t k = i; k < ncbits; k += stride) cbits[k] = 0;
+  if (i < 4) sched[i] = 0;
 }
 
 // Packs a job's gate records into items: one-qubit, diagonal and phase gates
@@ -651,6 +780,16 @@ BOp to_local(BOp o, const std::vector<int>& loc) {
 std::vector<BOp> plan_stages(int n, int L, const std::vector<BOp>& ops) {
   std::vector<BOp> out;
   const int kScan = 8;   // diagonal gates looked at behind the first unscheduled gate of a qubit
+  // the first stage writes |0...0> (its chunks start from it instead of
+  // reading the state): when the list is empty or starts with a measurement,
+  // an empty stage on the lowest L qubits comes first
+  if (ops.empty() || (ops[0].head & 0xff) == BK_MEAS) {
+    BOp h{};
+    h.head = (uint32_t)BK_STAGE | ((uint32_t)L << 8);
+    uint8_t* q = reinterpret_cast<uint8_t*>(h.m);
+    for (int j = 0; j < L; ++j) q[j] = (uint8_t)j;
+    out.push_back(h);
+  }
   size_t i0 = 0;
   while (i0 < ops.size()) {
     if ((ops[i0].head & 0xff) == BK_MEAS) {
@@ -760,7 +899,14 @@ struct qk_batch_s {
   size_t ops_bytes = 0;
   void* d_jobs = nullptr;
   size_t jobs_bytes = 0;
-  int* d_counter = nullptr;
+  void* d_stages = nullptr;   // stage table of the staged jobs
+  size_t stages_bytes = 0;
+  void* d_ctl = nullptr;      // per staged job scheduling state
+  size_t ctl_bytes = 0;
+  void* d_sched = nullptr;    // scan hint, small-job counter, stall flag
+  size_t sched_bytes = 0;
+  size_t nstaged = 0;
+  size_t ncbits_total = 0;
   bool ran = false;
   bool uploaded = false;   // the device job table and ops match `jobs` (a rerun only relaunches)
   size_t njobs_dev = 0;
@@ -839,9 +985,9 @@ qk_status qk_batch_destroy(qk_batch b) {
   bfree(b, b->d_cbits, b->cbits_bytes);
   bfree(b, b->d_ops, b->ops_bytes);
   bfree(b, b->d_jobs, b->jobs_bytes);
-  size_t cb = sizeof(int);
-  void* c = b->d_counter;
-  bfree(b, c, cb);
+  bfree(b, b->d_stages, b->stages_bytes);
+  bfree(b, b->d_ctl, b->ctl_bytes);
+  bfree(b, b->d_sched, b->sched_bytes);
   delete b;
   return QK_OK;
 }
@@ -947,33 +1093,42 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
   return QK_OK;
 }
 
-static void launch_batch(qk_batch b) {
-  if (b->c64) {
-    static bool set = false;
-    if (!set) {
-      (void)hipFuncSetAttribute((const void*)k_batch<float>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-      set = true;
-    }
-    hipLaunchKernelGGL(k_batch<float>, dim3(b->grid), dim3(kBatchThreads), b->shm, b->stream, (const BJob*)b->d_jobs,
-                       (int)b->njobs_dev, (const uint32_t*)b->d_ops, (EVb<float>::T*)b->d_states, (uint8_t*)b->d_cbits,
-                       b->d_counter);
-  } else {
-    static bool set = false;
-    if (!set) {
-      (void)hipFuncSetAttribute((const void*)k_batch<double>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-      set = true;
-    }
-    hipLaunchKernelGGL(k_batch<double>, dim3(b->grid), dim3(kBatchThreads), b->shm, b->stream, (const BJob*)b->d_jobs,
-                       (int)b->njobs_dev, (const uint32_t*)b->d_ops, (EVb<double>::T*)b->d_states, (uint8_t*)b->d_cbits,
-                       b->d_counter);
+}  // extern "C"
+
+template <typename R>
+static void launch_batch_t(qk_batch b) {
+  static bool set = false;
+  if (!set) {
+    (void)hipFuncSetAttribute((const void*)k_batch<R>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+    set = true;
   }
+  hipLaunchKernelGGL(k_batch_reset, dim3(64), dim3(256), 0, b->stream, (JobCtl*)b->d_ctl, (int)b->nstaged,
+                     (unsigned*)b->d_sched, (uint8_t*)b->d_cbits, (uint32_t)b->ncbits_total);
+  static unsigned long long stall = 0;   // 10 s of the device wall clock
+  if (!stall) {
+    int khz = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz <= 0)
+      khz = 100000;
+    stall = 10000ull * (unsigned long long)khz;
+  }
+  hipLaunchKernelGGL(k_batch<R>, dim3(b->grid), dim3(kBatchThreads), b->shm, b->stream, (const BJob*)b->d_jobs,
+                     (int)b->njobs_dev, (int)b->nstaged, (const BStage*)b->d_stages, (JobCtl*)b->d_ctl,
+                     (unsigned*)b->d_sched, (const uint32_t*)b->d_ops, (typename EVb<R>::T*)b->d_states,
+                     (uint8_t*)b->d_cbits, stall);
 }
+
+static void launch_batch(qk_batch b) {
+  if (b->c64) launch_batch_t<float>(b);
+  else launch_batch_t<double>(b);
+}
+
+extern "C" {
 
 qk_status qk_batch_run(qk_batch b) {
   if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
   if (b->jobs.empty()) return QK_OK;
-  if (b->uploaded) {   // same jobs as the last run: only the queue counter and the launch
-    hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, b->stream, b->d_counter);
+  if (b->uploaded) {   // same jobs as the last run: only the scheduling state is reset
     launch_batch(b);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
@@ -981,13 +1136,12 @@ qk_status qk_batch_run(qk_batch b) {
     return QK_OK;
   }
   const size_t amp = b->c64 ? 8 : 16;
-  // layout: states and cbits in job order; the queue visits the largest jobs first
+  const int lq = b->c64 ? stage_qubits<float>() : stage_qubits<double>();
+  // layout: states and cbits in job order; the device table lists the staged
+  // jobs first, then the small ones, each part largest first
   uint64_t soff = 0;
   uint32_t coff = 0, ooff = 0;
   int nmax = 0;   // largest job kept in LDS, or the stage chunk when larger
-  const int lq = b->c64 ? stage_qubits<float>() : stage_qubits<double>();
-  std::vector<BOp> all_ops;
-  std::vector<BJob> table;
   for (auto& j : b->jobs) {
     j.state_off = soff;
     j.cbit_off = coff;
@@ -1000,20 +1154,39 @@ qk_status qk_batch_run(qk_batch b) {
   std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
     const auto& a = b->jobs[x];
     const auto& c = b->jobs[y];
+    if (a.staged != c.staged) return a.staged;
     return ((uint64_t)a.ops.size() << a.n) > ((uint64_t)c.ops.size() << c.n);
   });
+  std::vector<BOp> all_ops;
+  std::vector<BJob> table;
+  std::vector<BStage> stab;
+  size_t nstaged = 0;
   for (int id : order) {
     const auto& j = b->jobs[id];
     BJob t{};
     t.state_off = j.state_off;
     t.op_begin = ooff;
     all_ops.insert(all_ops.end(), j.ops.begin(), j.ops.end());
-    ooff += (uint32_t)j.ops.size();
-    t.op_end = ooff;
+    t.op_end = ooff + (uint32_t)j.ops.size();
     t.n = j.n;
     t.ncbits = j.ncbits;
     t.cbit_off = j.cbit_off;
-    t.staged = j.staged ? 1 : 0;
+    if (j.staged) {
+      ++nstaged;
+      t.st_begin = (uint32_t)stab.size();
+      for (uint32_t r = 0; r < (uint32_t)j.ops.size();) {
+        const BOp& o = j.ops[r];
+        if ((o.head & 0xff) == BK_MEAS) {
+          stab.push_back({ooff + r, 1u});
+          ++r;
+        } else {
+          stab.push_back({ooff + r, 1u << (j.n - lq)});
+          r += 1 + o.cmask;
+        }
+      }
+      t.nst = (uint32_t)stab.size() - t.st_begin;
+    }
+    ooff = t.op_end;
     table.push_back(t);
   }
   all_ops.resize(all_ops.size() + kPadRecords);   // padding: the kernel reads the next item before knowing its size
@@ -1022,27 +1195,29 @@ qk_status qk_batch_run(qk_batch b) {
   if ((st = bensure(b, b->d_cbits, b->cbits_bytes, std::max<size_t>(coff, 1), "batch cbits"))) return st;
   if ((st = bensure(b, b->d_ops, b->ops_bytes, all_ops.size() * sizeof(BOp), "batch ops"))) return st;
   if ((st = bensure(b, b->d_jobs, b->jobs_bytes, table.size() * sizeof(BJob), "batch job table"))) return st;
-  if (!b->d_counter) {
-    size_t cb = 0;
-    void* c = nullptr;
-    if ((st = bensure(b, c, cb, sizeof(int), "batch counter"))) return st;
-    b->d_counter = (int*)c;
-  }
-  hipError_t e = hipSuccess;
-  if (!all_ops.empty())
-    e = hipMemcpyAsync(b->d_ops, all_ops.data(), all_ops.size() * sizeof(BOp), hipMemcpyHostToDevice, b->stream);
+  if ((st = bensure(b, b->d_stages, b->stages_bytes, std::max<size_t>(stab.size(), 1) * sizeof(BStage), "batch stages")))
+    return st;
+  if ((st = bensure(b, b->d_ctl, b->ctl_bytes, std::max<size_t>(nstaged, 1) * sizeof(JobCtl), "batch scheduling")))
+    return st;
+  if ((st = bensure(b, b->d_sched, b->sched_bytes, 4 * sizeof(unsigned), "batch scheduling"))) return st;
+  hipError_t e = hipMemcpyAsync(b->d_ops, all_ops.data(), all_ops.size() * sizeof(BOp), hipMemcpyHostToDevice, b->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(b->d_jobs, table.data(), table.size() * sizeof(BJob), hipMemcpyHostToDevice, b->stream);
+  if (e == hipSuccess && !stab.empty())
+    e = hipMemcpyAsync(b->d_stages, stab.data(), stab.size() * sizeof(BStage), hipMemcpyHostToDevice, b->stream);
   if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
-  hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(64), 0, b->stream, b->d_counter);
   const size_t shm = ((size_t)1 << nmax) * amp;
   int ncu = 256, dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  const int per_cu = std::max<int>(1, (int)(160 * 1024 / (shm + 4096)));
-  const unsigned grid = (unsigned)std::max<size_t>(1, std::min<size_t>(table.size(), (size_t)ncu * std::min(per_cu, 4)));
+  const int per_cu = std::max<int>(1, std::min(4, (int)(160 * 1024 / (shm + 4096))));
+  // staged jobs spread their chunks over every workgroup that fits; small
+  // jobs need at most one workgroup each
+  const size_t want = nstaged ? (size_t)ncu * per_cu : std::min<size_t>(table.size(), (size_t)ncu * per_cu);
   b->shm = shm;
-  b->grid = grid;
+  b->grid = (unsigned)std::max<size_t>(1, want);
   b->njobs_dev = table.size();
+  b->nstaged = nstaged;
+  b->ncbits_total = coff;
   launch_batch(b);
   e = hipGetLastError();
   if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
@@ -1055,6 +1230,12 @@ qk_status qk_batch_sync(qk_batch b) {
   if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
   hipError_t e = hipStreamSynchronize(b->stream);
   if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch: ") + hipGetErrorString(e));
+  if (b->ran && b->nstaged && b->d_sched) {
+    unsigned flags[4] = {0, 0, 0, 0};
+    e = hipMemcpy(flags, b->d_sched, sizeof(flags), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch: ") + hipGetErrorString(e));
+    if (flags[2]) return bfail(b, QK_E_HIP, "batch: a workgroup found no work for 10 s while stages were open (scheduler stall)");
+  }
   return QK_OK;
 }
 
