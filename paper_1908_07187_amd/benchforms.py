@@ -186,6 +186,17 @@ def serve(args, qk, torch):
     out["max_concurrent_streams"] = rep.max_concurrent_streams
     out["fidelity_vs_c128_sampled"] = {"jobs": len(fids), "min": float(min(fids)) if fids else None}
     out["mean_qubits"] = float(np.mean(ns))
+    # latency by job size (arrival -> result), and the share spent before admission
+    by = {}
+    for lo_, hi_ in ((1, 14), (15, 20), (21, 23), (24, 26)):
+        sel = [r for r in rep.results if r.path in ("batch", "stream") and lo_ <= r.n <= hi_]
+        if sel:
+            lat = np.array([r.latency for r in sel]) * 1e3
+            wait = np.array([r.admitted - r.arrival for r in sel]) * 1e3
+            by[f"{lo_}-{hi_}"] = {"jobs": len(sel), "p50_ms": float(np.percentile(lat, 50)),
+                                   "p99_ms": float(np.percentile(lat, 99)),
+                                   "mean_wait_before_admission_ms": float(wait.mean())}
+    out["latency_by_qubits"] = by
     out["mid_batched_max_qubits"] = args.serve_mid_max if mid else None
     return out
 
@@ -609,7 +620,35 @@ def batch_mid(args, qk, torch):
             dmax = max(dmax, float(np.max(np.abs(got - st.astype(np.complex128)))))
             cb_ok = cb_ok and list(b.cbits(ids[i])) == cbv
         b.close()
+        # (c) one circuit alone: the largest, as a batch of one and on the per-gate path
+        big = max(range(nc), key=lambda i: (circs[i].n_qubits, len(circs[i].ops)))
+        b1 = qk.Batch(dt)
+        b1.add(circs[big].n_qubits, circs[big].n_cbits, *recs[big])
+        b1.run()
+        b1.sync()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            b1.run()
+        b1.sync()
+        lone_batch = (time.perf_counter() - t0) / 5
+        b1.close()
+        s = qk.Sim(dt)
+        s.add_qubits(circs[big].n_qubits)
+        s.add_cbits(max(1, circs[big].n_cbits))
+        s.apply_ops(*recs[big])
+        s.sync()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            s.reset()
+            s.apply_ops(*recs[big])
+        s.sync()
+        lone_pg = (time.perf_counter() - t0) / 5
+        s.close()
+        _say(f"batch_mid {dt}: largest circuit alone ({circs[big].n_qubits} qubits, {len(circs[big].ops)} ops): "
+             f"batch {lone_batch * 1e3:.2f} ms, per-gate path {lone_pg * 1e3:.2f} ms")
         out[dt] = {"batch_circuits_per_s": nc / bdt, "batch_ms": bdt * 1e3, "batch_amp_updates_per_s": upd / bdt,
+                   "largest_alone": {"qubits": circs[big].n_qubits, "ops": len(circs[big].ops),
+                                     "batch_ms": lone_batch * 1e3, "per_gate_ms": lone_pg * 1e3},
                    "per_gate_circuits_per_s": stream_cps, "per_gate_sample": k, "speedup": (nc / bdt) / stream_cps,
                    "max_abs_diff_vs_per_gate": dmax, "cbits_equal": cb_ok}
         _say(f"batch_mid {dt}: batch {nc / bdt:.1f} circuits/s ({bdt * 1e3:.1f} ms for {nc}), per-gate path "

@@ -459,7 +459,7 @@ template <typename R>
 __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_batch(
     const BJob* __restrict__ jobs, int njobs, int nstaged, const BStage* __restrict__ stages, JobCtl* ctl,
     unsigned* sched, const uint32_t* __restrict__ opw, typename EVb<R>::T* __restrict__ states,
-    uint8_t* __restrict__ cbits, unsigned long long stall_ticks) {
+    uint8_t* __restrict__ cbits, unsigned long long stall_ticks, uint32_t run_max) {
   using C = typename EVb<R>::T;
   constexpr int LQ = stage_qubits<R>(), PT = stage_per_thread<R>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -504,7 +504,7 @@ __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_ba
             // a run of chunks per claim: fewer claims and fences on large stages
             const BJob& jb = jobs[j];
             const uint32_t nck = stages[jb.st_begin + (uint32_t)(ld_acq64(&ctl[j].word) >> 32) % jb.nst].nchunks;
-            const uint32_t want = min(16u, max(1u, nck >> 4));
+            const uint32_t want = min(run_max, max(1u, nck >> 4));
             const unsigned long long old = atomicAdd(&ctl[j].word, (unsigned long long)want);
             s2 = (int)(old >> 32);
             c2 = (int)(uint32_t)old;
@@ -907,6 +907,7 @@ struct qk_batch_s {
   size_t sched_bytes = 0;
   size_t nstaged = 0;
   size_t ncbits_total = 0;
+  uint32_t run_max = 1;       // longest run of chunks one claim takes
   bool ran = false;
   bool uploaded = false;   // the device job table and ops match `jobs` (a rerun only relaunches)
   size_t njobs_dev = 0;
@@ -1115,7 +1116,7 @@ static void launch_batch_t(qk_batch b) {
   hipLaunchKernelGGL(k_batch<R>, dim3(b->grid), dim3(kBatchThreads), b->shm, b->stream, (const BJob*)b->d_jobs,
                      (int)b->njobs_dev, (int)b->nstaged, (const BStage*)b->d_stages, (JobCtl*)b->d_ctl,
                      (unsigned*)b->d_sched, (const uint32_t*)b->d_ops, (typename EVb<R>::T*)b->d_states,
-                     (uint8_t*)b->d_cbits, stall);
+                     (uint8_t*)b->d_cbits, stall, b->run_max);
 }
 
 static void launch_batch(qk_batch b) {
@@ -1218,6 +1219,13 @@ qk_status qk_batch_run(qk_batch b) {
   b->njobs_dev = table.size();
   b->nstaged = nstaged;
   b->ncbits_total = coff;
+  // Runs of chunks per claim amortise the claim's fences when the staged
+  // work is plentiful (about two claims per workgroup per round of stages),
+  // and shrink to single chunks when a few jobs must spread over the grid.
+  uint64_t chunks = 0;
+  for (const BJob& t : table)
+    if (t.nst) chunks += 1ull << (t.n - lq);
+  b->run_max = (uint32_t)std::min<uint64_t>(16, std::max<uint64_t>(1, chunks / (2ull * b->grid)));
   launch_batch(b);
   e = hipGetLastError();
   if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch launch: ") + hipGetErrorString(e));
