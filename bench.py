@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--fusion-k", type=int, default=0, help="fused block width for the complex64 form (0 = tuned)")
     ap.add_argument("--no-fused", action="store_true")
+    ap.add_argument("--no-stages", action="store_true", help="leave out the LDS-tile (stages) forms")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-gates", type=int, default=16, help="gates of the circuit the oracle sample runs")
     ap.add_argument("--workload", default="random30",
@@ -316,6 +317,11 @@ def main():
         dr = run_diag_runs(qk, prog, torch, updates, sims[0])
         dr["speedup_vs_c128_per_gate"] = ms_per_step / dr["ms_per_step"]
         out["diag_runs_c128"] = dr
+    if not args.no_stages:
+        for dt in ("c128", "c64"):
+            sg = run_stages(qk, prog, torch, updates, sims[0], dt)
+            sg["speedup_vs_c128_per_gate"] = ms_per_step / sg["ms_per_step"]
+            out[f"stages_{dt}"] = sg
     sims[0].close()
 
     if not args.no_forms:
@@ -435,6 +441,33 @@ def run_diag_runs(qk, prog, torch, updates, ref_sim):
           file=sys.stderr, flush=True)
     return {"ms_per_step": dt * 1e3, "amp_updates_per_s": updates / dt, "fidelity_vs_c128": fid,
             "sweeps": stats["sweeps"], "diag_runs": stats["fused_blocks"], "gates_in_runs": stats["fused_gates"]}
+
+
+def run_stages(qk, prog, torch, updates, ref_sim, dtype):
+    """The LDS-tile mode: every gate applied on its own, in FP64 (complex128)
+    or FP32 (complex64) exactly as the per-gate sweeps do, but the gates are
+    grouped into stages of 12 / 13 qubits, each stage one pass over the state
+    through LDS chunks; one untimed and one timed pass."""
+    dt = 0.0
+    for rep in range(2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s = qk.Sim(dtype)
+        s.set_tuning("stages", 1)
+        prog.run(s)
+        s.flush()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if rep == 0:
+            s.close()
+    stats = s.stats()
+    ip = ref_sim.inner(s)
+    fid = abs(ip) ** 2 / (ref_sim.norm2() * s.norm2())
+    s.close()
+    print(f"[bench] {dtype} stages: {dt * 1e3:.1f} ms/step, {updates / dt:.4e} amp-updates/s, stages {stats['sweeps']}, "
+          f"fidelity {fid:.15f}", file=sys.stderr, flush=True)
+    return {"ms_per_step": dt * 1e3, "amp_updates_per_s": updates / dt, "stages": stats["sweeps"],
+            "fidelity_vs_c128": fid}
 
 
 def _cpu_model():

@@ -383,7 +383,20 @@ qk_status qk_sync(qk_sim sim);
  *                 require, whenever that touches no more amplitudes than one
  *                 sweep per gate; 0: one sweep per gate.  Results agree with
  *                 one sweep per gate up to rounding (factors multiplied in
- *                 FP64 before one multiplication of each amplitude).
+ *                 FP64 before one multiplication of each amplitude);
+ *   "stages"      0 (default), 1: the LDS-tile mode.  Builtin gates (at
+ *                 most 4 controls, conditions on cbits below 256) on a dense
+ *                 state of 12 (complex128) / 13 (complex64) to 31 qubits are
+ *                 held back; at the next other operation they are grouped
+ *                 into stages of 12 / 13 qubits (gates pass one another only
+ *                 on disjoint qubits or when both are diagonal) and each
+ *                 stage is one pass over the state: every chunk of it (the
+ *                 amplitudes that agree on the other qubits) is gathered
+ *                 into LDS, every gate of the stage is applied there one at
+ *                 a time (no matrices composed; results agree with the
+ *                 per-gate sweeps up to rounding), and it is written back.
+ *                 Each stage counts as one sweep in qk_stats.  Setting
+ *                 the key applies whatever is held back first.
  * QK_E_ARG for an unknown key or value. */
 qk_status qk_set_tuning(qk_sim sim, const char* key, int32_t value);
 qk_status qk_get_tuning(qk_sim sim, const char* key, int32_t* value);

@@ -86,6 +86,8 @@ struct qk_sim_s {
   std::vector<UserGate*> ugates;
   int fuse_k = 0;
   std::vector<GateDesc> pending;
+  std::vector<qk_op> stage_q;       // builtin gates held back for the LDS-tile mode (physical qubits; never beside
+                                    // `pending` or `drun`)
   std::vector<GateDesc> drun;       // diagonal gates held back for one combined pass (never beside `pending`)
   std::vector<uint64_t> drun_groups;  // their factor-table groups in gate order (the fit check when adding)
   int drun_conds = 0;               // classical conditions they carry
@@ -102,6 +104,7 @@ constexpr size_t kArenaBytes = 32u << 20;
 constexpr int kMaxQubits = 40;
 constexpr int kMaxSparseQubits = 62;    // indices and the sort's sentinel bit fit 64 bits
 constexpr uint64_t kSpMergeMin = 1u << 12;   // entries from which one-qubit gates merge instead of sorting
+constexpr size_t kStageQueueMax = 8192;      // held-back gates of the LDS-tile mode (about 0.7 MB of records)
 
 qk_status fail(qk_sim s, qk_status st, const std::string& msg) {
   if (s) s->err = msg;
@@ -824,10 +827,51 @@ qk_status flush_pending(qk_sim s) {
   return QK_OK;
 }
 
-// Applies every operation held back (fusion queue, diagonal run, sparse run).
+// The LDS-tile mode: the held-back builtin gates are grouped into stages of
+// stage_chunk_qubits() qubits (gates pass one another only where they
+// commute), their records go up through the constant arena, and each stage
+// is one launch over every chunk of the state: a chunk (the amplitudes that
+// agree on the qubits outside the stage) is gathered into LDS, every gate of
+// the stage is applied there, and it is written back, so a stage costs one
+// read and one write of the state whatever its gate count.
+qk_status flush_stage(qk_sim s) {
+  if (s->stage_q.empty()) return QK_OK;
+  std::vector<qk_op> q;
+  q.swap(s->stage_q);
+  std::vector<unsigned char> recs;
+  std::vector<uint32_t> heads;
+  std::string err;
+  qk_status st = stage_plan(s->c64, s->n, s->ncbits, q, recs, heads, err);
+  if (st) return fail(s, st, "staged gates: " + err);
+  const void* dev = nullptr;
+  if ((st = arena_put(s, recs.data(), recs.size(), &dev))) return st;
+  for (uint32_t h : heads) {
+    launch_stage(s->c64, s->state.p, s->n, dev, h, (const uint8_t*)s->cbits.p, s->ncbits, s->stream);
+    s->sweeps++;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(s, e, "stage launch");
+  return QK_OK;
+}
+
+// Gates the LDS-tile mode holds back: builtins on a dense state of
+// stage_chunk_qubits() to 31 qubits, at most 4 controls, conditions on cbits
+// below 256, outside graph capture.
+bool stageable(qk_sim s, int nc, const qk_cond* conds, int ncond) {
+  if (!s->tune.stages || s->sparse || s->capturing) return false;
+  if (s->n < stage_chunk_qubits(s->c64) || s->n > 31 || nc > 4) return false;
+  for (int i = 0; i < ncond; ++i)
+    if (conds[i].cbit >= 256) return false;
+  return true;
+}
+
+// Applies every operation held back (stage queue, fusion queue, diagonal run,
+// sparse run).
 qk_status flush(qk_sim s) {
   if (s->sparse) return sp_flush_run(s);
-  qk_status st = flush_pending(s);
+  qk_status st = flush_stage(s);
+  if (st) return st;
+  st = flush_pending(s);
   if (st) return st;
   return flush_drun(s);
 }
@@ -1485,6 +1529,28 @@ qk_status qk_apply_gate(qk_sim s, qk_gate gate, const int32_t* targets, int32_t 
       d.N = N;
       d.Ainv = inv_mod(A, N);
     }
+  }
+  if (bi && stageable(s, nc, conds, ncond)) {
+    qk_status st = flush_pending(s);
+    if (!st) st = flush_drun(s);
+    if (st) return st;
+    qk_op o{};
+    o.kind = QK_OP_GATE;
+    o.gate = bi->id;
+    o.n_targets = nt;
+    for (int i = 0; i < nt; ++i) o.targets[i] = d.targets[i];
+    o.n_controls = nc;
+    for (int i = 0; i < nc; ++i) o.controls[i] = d.controls[i];
+    o.n_conds = ncond;
+    for (int i = 0; i < ncond; ++i) o.conds[i] = conds[i];
+    o.param = np ? params[0] : 0.0;
+    s->stage_q.push_back(o);
+    if (s->stage_q.size() >= kStageQueueMax) return flush_stage(s);
+    return QK_OK;
+  }
+  if (!s->stage_q.empty()) {
+    qk_status st = flush_stage(s);
+    if (st) return st;
   }
   if (s->sparse) return sparse_execute(s, d);
   if (d.conds.empty() && d.fusable && s->fuse_k >= 2 && nt + nc <= s->fuse_k) {
@@ -2213,6 +2279,11 @@ qk_status qk_set_tuning(qk_sim s, const char* key, int32_t value) {
     if (value < 1 || value > 8) return fail(s, QK_E_ARG, "lds_wg must be 1..8");
     s->tune.lds_wg = value;
 
+  } else if (k == "stages") {
+    if (value != 0 && value != 1) return fail(s, QK_E_ARG, "stages must be 0 or 1");
+    qk_status st = flush(s);
+    if (st) return st;
+    s->tune.stages = value;
   } else if (k == "diag_runs") {
     if (value != 0 && value != 1) return fail(s, QK_E_ARG, "diag_runs must be 0 or 1");
     qk_status st = flush(s);
@@ -2249,6 +2320,7 @@ qk_status qk_get_tuning(qk_sim s, const char* key, int32_t* value) {
   else if (k == "mfma_lds") *value = s->tune.mfma_lds;
   else if (k == "lds_wg") *value = s->tune.lds_wg;
   else if (k == "diag_runs") *value = s->tune.diag_runs;
+  else if (k == "stages") *value = s->tune.stages;
   else if (k == "swap_relabel") *value = s->tune.swap_relabel;
   else if (k == "xcd") *value = s->tune.xcd;
   else return fail(s, QK_E_ARG, "unknown tuning key " + k);

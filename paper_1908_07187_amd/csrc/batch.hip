@@ -209,6 +209,10 @@ template <typename R> constexpr int batch_waves_per_simd() { return sizeof(R) ==
 // amplitudes each thread moves per chunk.
 template <typename R> constexpr int stage_qubits() { return sizeof(R) == 8 ? 12 : 13; }
 template <typename R> constexpr int stage_per_thread() { return (1 << stage_qubits<R>()) / kBatchThreads; }
+// Records of a stage kept in LDS beside its chunk by the stage kernel (12 KiB:
+// 153 records; two workgroups of 64 + 12 KiB and their static arrays fit a
+// compute unit).
+constexpr uint32_t kStageLdsWords = 3072;
 static_assert(stage_per_thread<double>() % 8 == 0 && stage_per_thread<float>() % 8 == 0, "chunk moves go 8 at a time");
 static_assert(kBatchThreads == 512, "a staged chunk maps the thread to the stage's lowest 9 qubits");
 
@@ -292,23 +296,31 @@ __device__ __forceinline__ void meas_run(typename EVb<R>::T* st, uint32_t dim, u
 // Runs items [rec, end) over a state of dim amplitudes in LDS.  The first
 // item's records must already sit in items[0], staged before a barrier; every
 // item ends with a barrier.
-template <typename R>
+// Where run_items reads the records: a double-buffered LDS copy of each
+// item staged one item ahead (REC_STAGED), a copy of the whole range in LDS
+// (REC_LDS), or global memory at a uniform address, which the compiler turns
+// into scalar loads (REC_SCALAR).
+enum { REC_STAGED = 0, REC_LDS = 1, REC_SCALAR = 2 };
+
+template <typename R, int RM = REC_STAGED>
 __device__ __forceinline__ void run_items(typename EVb<R>::T* st, uint32_t dim, uint32_t rec, uint32_t end,
                                           const uint32_t* __restrict__ opw, uint8_t* cb,
                                           uint32_t (*items)[kItemWords], double (*red)[kBatchThreads / 64],
-                                          double* meas) {
+                                          double* meas, const uint32_t* lrec = nullptr, uint32_t lbase = 0) {
   using C = typename EVb<R>::T;
+  constexpr bool LREC = RM != REC_STAGED;
   const uint32_t tid = threadIdx.x, bd = blockDim.x;
   const int lane = tid & 63, w = tid >> 6;
   int buf = 0;
   while (rec < end) {
-    const uint32_t* cur = items[buf];
+    const uint32_t* cur = RM == REC_SCALAR ? opw + (size_t)rec * kOpWords
+                        : (RM == REC_LDS ? lrec + (size_t)(rec - lbase) * kOpWords : items[buf]);
     const uint32_t head = __builtin_amdgcn_readfirstlane(cur[0]);
     const int kind = head & 0xff;
     const int ngates = kind == BK_PASS ? (int)((head >> 16) & 0xff) : 0;
     const uint32_t next = rec + 1 + (uint32_t)ngates;
     ItemRegs nxt{};
-    if (w == 0) nxt = load_item(opw, next, lane);   // the record array ends with padding
+    if (!LREC && w == 0) nxt = load_item(opw, next, lane);   // the record array ends with padding
     if (kind == BK_PASS) {
       const int K = (head >> 8) & 0xff;
       const uint32_t tw = __builtin_amdgcn_readfirstlane(cur[1]), sw = __builtin_amdgcn_readfirstlane(cur[2]);
@@ -416,7 +428,7 @@ __device__ __forceinline__ void run_items(typename EVb<R>::T* st, uint32_t dim, 
     }
     // the next item's records into the other buffer (its last readers
     // finished before the barrier that ended the previous item)
-    if (w == 0) stage_item(items[buf ^ 1], nxt, lane);
+    if (!LREC && w == 0) stage_item(items[buf ^ 1], nxt, lane);
     __syncthreads();
     buf ^= 1;
     rec = next;
@@ -429,6 +441,79 @@ __device__ __forceinline__ uint32_t deposit(uint32_t v, uint32_t mask) {
   for (uint32_t m = mask; m; m &= m - 1, v >>= 1)
     if (v & 1u) out |= m & (~m + 1u);
   return out;
+}
+
+// The chunk layout of a stage whose header record is h (record index rec):
+// its item range, the qubits outside it (cmask: where the chunk number goes),
+// and this thread's part of the local index.  Local index tid + k * 512: its
+// low 9 bits (the thread) land on the stage's lowest 9 qubits, k on the
+// others (the same for every thread).
+struct ChunkMap {
+  uint32_t it_begin, it_end, cmask, shigh, base;
+};
+
+template <int LQ>
+__device__ __forceinline__ ChunkMap chunk_map(const uint32_t* h, uint32_t rec, uint32_t dim, uint32_t tid) {
+  ChunkMap m;
+  m.it_begin = rec + 1;
+  m.it_end = m.it_begin + (uint32_t)__builtin_amdgcn_readfirstlane(h[1]);
+  uint32_t smask = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t wq = (uint32_t)__builtin_amdgcn_readfirstlane(h[4 + q]);
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (4 * q + e < LQ) smask |= 1u << ((wq >> (8 * e)) & 0xff);
+  }
+  m.cmask = (dim - 1) & ~smask;
+  uint32_t slow = 0, shigh = smask;
+  for (int e = 0; e < 9; ++e) {
+    slow |= shigh & (~shigh + 1u);
+    shigh &= shigh - 1;
+  }
+  m.shigh = shigh;
+  m.base = deposit(tid, slow);
+  return m;
+}
+
+// One chunk of a stage: gathered from the state into LDS (or, with zero,
+// made |0...0>'s slice), the stage's items run on it, scattered back.
+// Starts after and ends with a barrier.
+template <typename R, int RM = REC_STAGED>
+__device__ __forceinline__ void stage_chunk(typename EVb<R>::T* st, typename EVb<R>::T* gst, const ChunkMap& cm,
+                                            uint32_t ch, bool zero, const uint32_t* __restrict__ opw, uint8_t* cb,
+                                            uint32_t (*items)[kItemWords], double (*red)[kBatchThreads / 64],
+                                            double* meas, const uint32_t* lrec = nullptr) {
+  using C = typename EVb<R>::T;
+  constexpr int LQ = stage_qubits<R>(), PT = stage_per_thread<R>();
+  const uint32_t tid = threadIdx.x, bd = blockDim.x;
+  const int lane = tid & 63, w = tid >> 6;
+  const uint32_t cpart = deposit(ch, cm.cmask);
+  if (RM == REC_STAGED && w == 0) stage_item(items[0], load_item(opw, cm.it_begin, lane), lane);
+#pragma unroll 1
+  for (int k0 = 0; k0 < PT; k0 += 8) {   // 8 loads in flight per thread
+    C x[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t g = cm.base | deposit((uint32_t)(k0 + k), cm.shigh) | cpart;
+      if (zero) {
+        x[k].x = g == 0 ? (R)1 : (R)0;
+        x[k].y = 0;
+      } else {
+        x[k] = gst[g];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) st[swz<R>(tid + (uint32_t)(k0 + k) * bd)] = x[k];
+  }
+  __syncthreads();
+  run_items<R, RM>(st, 1u << LQ, cm.it_begin, cm.it_end, opw, cb, items, red, meas, lrec, cm.it_begin);
+#pragma unroll 1
+  for (int k0 = 0; k0 < PT; k0 += 8)
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      gst[cm.base | deposit((uint32_t)(k0 + k), cm.shigh) | cpart] = st[swz<R>(tid + (uint32_t)(k0 + k) * bd)];
+  __syncthreads();   // the next chunk's gather overwrites LDS
 }
 
 // Scheduling state of a batch launch.  Staged jobs: per job a 64-bit word
@@ -455,13 +540,19 @@ __device__ __forceinline__ unsigned long long ld_acq64(const unsigned long long*
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Where the small jobs' records come from.
+// Staged one item ahead: reading the records as scalar loads from global
+// memory instead measured 8-11 % slower (2048 12-qubit circuits) and 6 %
+// slower on mid-size staged jobs.
+constexpr int RM_SMALL = REC_STAGED;
+
 template <typename R>
 __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_batch(
     const BJob* __restrict__ jobs, int njobs, int nstaged, const BStage* __restrict__ stages, JobCtl* ctl,
     unsigned* sched, const uint32_t* __restrict__ opw, typename EVb<R>::T* __restrict__ states,
     uint8_t* __restrict__ cbits, unsigned long long stall_ticks, uint32_t run_max) {
   using C = typename EVb<R>::T;
-  constexpr int LQ = stage_qubits<R>(), PT = stage_per_thread<R>();
+  constexpr int LQ = stage_qubits<R>();
   extern __shared__ __align__(16) unsigned char smem_raw[];
   C* st = reinterpret_cast<C*>(smem_raw);
   __shared__ uint8_t cb[kMaxJobCbits];
@@ -571,7 +662,7 @@ __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_ba
     if (job >= nstaged) {
       // ---- a small job: |0...0> in LDS, every item, written out once
       for (int c = tid; c < jb.ncbits; c += bd) cb[c] = 0;
-      if (w == 0) stage_item(items[0], load_item(opw, jb.op_begin, lane), lane);
+      if (RM_SMALL == REC_STAGED && w == 0) stage_item(items[0], load_item(opw, jb.op_begin, lane), lane);
       for (uint32_t i = tid; i < dim; i += bd) {
         C z;
         z.x = (i == 0) ? (R)1 : (R)0;
@@ -579,7 +670,7 @@ __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_ba
         st[swz<R>(i)] = z;
       }
       __syncthreads();
-      run_items<R>(st, dim, jb.op_begin, jb.op_end, opw, cb, items, red, meas);
+      run_items<R, RM_SMALL>(st, dim, jb.op_begin, jb.op_end, opw, cb, items, red, meas);
       for (uint32_t i = tid; i < dim; i += bd) gst[i] = st[swz<R>(i)];
       for (int c = tid; c < jb.ncbits; c += bd) cbits[jb.cbit_off + c] = cb[c];
       __syncthreads();
@@ -604,55 +695,11 @@ __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_ba
       if (tid == 0 && cbit >= 0) cbits[jb.cbit_off + cbit] = cb[cbit];
     } else {
       // BK_STAGE: cmask word = records in the stage, bytes of m = the global
-      // qubit of each local bit, ascending.  Local index tid + k * 512: its
-      // low 9 bits (the thread) land on the lowest 9 qubits of the stage, k
-      // on the others (the same for every thread); the chunk number on the
-      // qubits outside the stage.
-      const uint32_t it_begin = bs.rec + 1, it_end = it_begin + (uint32_t)__builtin_amdgcn_readfirstlane(h[1]);
-      uint32_t smask = 0;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const uint32_t wq = (uint32_t)__builtin_amdgcn_readfirstlane(h[4 + q]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (4 * q + e < LQ) smask |= 1u << ((wq >> (8 * e)) & 0xff);
-      }
-      const uint32_t cmask = (dim - 1) & ~smask;
-      uint32_t slow = 0, shigh = smask;
-      for (int e = 0; e < 9; ++e) {
-        slow |= shigh & (~shigh + 1u);
-        shigh &= shigh - 1;
-      }
-      const uint32_t base = deposit(tid, slow);
+      // qubit of each local bit, ascending; the first stage starts from |0...0>
+      const ChunkMap cm = chunk_map<LQ>(h, bs.rec, dim, tid);
 #pragma unroll 1
-      for (uint32_t ch = chunk; ch < chunk + count; ++ch) {
-        const uint32_t cpart = deposit(ch, cmask);
-        if (w == 0) stage_item(items[0], load_item(opw, it_begin, lane), lane);
-#pragma unroll 1
-        for (int k0 = 0; k0 < PT; k0 += 8) {   // 8 loads in flight per thread
-          C x[8];
-#pragma unroll
-          for (int k = 0; k < 8; ++k) {
-            const uint32_t g = base | deposit((uint32_t)(k0 + k), shigh) | cpart;
-            if (stage == 0) {   // the first stage starts from |0...0>
-              x[k].x = g == 0 ? (R)1 : (R)0;
-              x[k].y = 0;
-            } else {
-              x[k] = gst[g];
-            }
-          }
-#pragma unroll
-          for (int k = 0; k < 8; ++k) st[swz<R>(tid + (uint32_t)(k0 + k) * bd)] = x[k];
-        }
-        __syncthreads();
-        run_items<R>(st, 1u << LQ, it_begin, it_end, opw, cb, items, red, meas);
-#pragma unroll 1
-        for (int k0 = 0; k0 < PT; k0 += 8)
-#pragma unroll
-          for (int k = 0; k < 8; ++k)
-            gst[base | deposit((uint32_t)(k0 + k), shigh) | cpart] = st[swz<R>(tid + (uint32_t)(k0 + k) * bd)];
-        __syncthreads();   // the next chunk's gather overwrites LDS
-      }
+      for (uint32_t ch = chunk; ch < chunk + count; ++ch)
+        stage_chunk<R>(st, gst, cm, ch, stage == 0, opw, cb, items, red, meas);
     }
     // Release: every wave's stores have completed (waitcnt) before the
     // barrier, then one agent-scope release (the write-back of this XCD's
@@ -686,6 +733,40 @@ __global__ void k_batch_reset(JobCtl* ctl, int nctl, unsigned* sched, uint8_t* c
   }
   for (uint32_t k = i; k < ncbits; k += stride) cbits[k] = 0;
   if (i < 4) sched[i] = 0;
+}
+
+// One stage of a simulator's held-back gates (the LDS-tile mode): every
+// chunk of the state, a chunk per workgroup at a time.  The stage's header
+// is record hrec of opw; the gates' cbit conditions read cbits.
+template <typename R>
+__global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_stage(
+    typename EVb<R>::T* __restrict__ psi, int n, const uint32_t* __restrict__ opw, uint32_t hrec,
+    const uint8_t* __restrict__ cbits, int ncbits) {
+  constexpr int LQ = stage_qubits<R>();
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  typename EVb<R>::T* st = reinterpret_cast<typename EVb<R>::T*>(smem_raw);
+  __shared__ uint8_t cb[kMaxJobCbits];
+  __shared__ double red[2][kBatchThreads / 64];
+  __shared__ double meas[2];
+  __shared__ uint32_t items[2][kItemWords];
+  const uint32_t tid = threadIdx.x, dim = 1u << n;
+  for (int c = tid; c < ncbits && c < kMaxJobCbits; c += blockDim.x) cb[c] = cbits[c];
+  const ChunkMap cm = chunk_map<LQ>(opw + (size_t)hrec * kOpWords, hrec, dim, tid);
+  const uint32_t nchunks = dim >> LQ;
+  const uint32_t nwords = (cm.it_end - cm.it_begin) * kOpWords;
+  if (nwords <= kStageLdsWords) {
+    // the stage's records once into LDS beside the chunk, for all of this
+    // workgroup's chunks (2 % faster than staging each item per chunk;
+    // scalar loads from global memory were 8 % slower)
+    uint32_t* lrec = reinterpret_cast<uint32_t*>(smem_raw + (sizeof(typename EVb<R>::T) << LQ));
+    for (uint32_t i = tid; i < nwords; i += blockDim.x) lrec[i] = opw[(size_t)cm.it_begin * kOpWords + i];
+    __syncthreads();
+    for (uint32_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x)
+      stage_chunk<R, REC_LDS>(st, psi, cm, ch, false, opw, cb, items, red, meas, lrec);
+  } else {
+    for (uint32_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x)
+      stage_chunk<R>(st, psi, cm, ch, false, opw, cb, items, red, meas);
+  }
 }
 
 // Packs a job's gate records into items: one-qubit, diagonal and phase gates
@@ -872,6 +953,91 @@ std::vector<BOp> plan_stages(int n, int L, const std::vector<BOp>& ops) {
   return out;
 }
 
+qk_status cfail(std::string& err, qk_status st, const std::string& m) {
+  err = m;
+  return st;
+}
+
+// One op record compiled to a device record (qubits as given, n of them;
+// cbit indices below ncbits).  Errors name the problem in err.
+qk_status compile_op(const qk_op& o, int n, int ncbits, BOp& d, std::string& err) {
+  d = BOp{};
+  if (o.n_conds < 0 || o.n_conds > 2) return cfail(err, QK_E_ARG, "at most 2 conditions");
+  for (int c = 0; c < o.n_conds; ++c) {
+    if (o.conds[c].cbit < 0 || o.conds[c].cbit >= ncbits) return cfail(err, QK_E_ARG, "condition cbit out of range");
+    if (o.conds[c].value != 0 && o.conds[c].value != 1) return cfail(err, QK_E_ARG, "condition value must be 0 or 1");
+  }
+  int kind = 0, t0 = 0, t1 = 0;
+  d.cbit = -1;
+  if (o.n_conds > 0) d.conds = (uint32_t)o.conds[0].cbit | ((uint32_t)o.conds[0].value << 8);
+  if (o.n_conds > 1) d.conds |= ((uint32_t)o.conds[1].cbit << 16) | ((uint32_t)o.conds[1].value << 24);
+  if (o.kind == QK_OP_MEASURE) {
+    if (o.qubit < 0 || o.qubit >= n) return cfail(err, QK_E_ARG, "qubit out of range");
+    if (o.cbit < -1 || o.cbit >= ncbits) return cfail(err, QK_E_ARG, "cbit out of range");
+    if (!(o.u >= 0.0 && o.u < 1.0)) return cfail(err, QK_E_ARG, "u must be in [0, 1)");
+    if (o.n_conds) return cfail(err, QK_E_ARG, "measurements take no conditions");
+    kind = BK_MEAS;
+    t0 = o.qubit;
+    d.cbit = o.cbit;
+    d.m[0] = o.u;
+  } else if (o.kind == QK_OP_GATE) {
+    int arity = 0, np = 0;
+    if (!builtin_info(o.gate, &arity, &np)) return cfail(err, QK_E_UNSUPPORTED, "batched circuits take builtin gates only");
+    if (o.n_targets != arity) return cfail(err, QK_E_ARG, "target count does not match the gate");
+    if (o.n_controls < 0 || o.n_controls > 4) return cfail(err, QK_E_ARG, "at most 4 controls");
+    uint32_t seen = 0;
+    for (int q = 0; q < o.n_targets + o.n_controls; ++q) {
+      const int x = q < o.n_targets ? o.targets[q] : o.controls[q - o.n_targets];
+      if (x < 0 || x >= n) return cfail(err, QK_E_ARG, "qubit index out of range");
+      if (seen & (1u << x)) return cfail(err, QK_E_ARG, "qubit used twice in one gate");
+      seen |= 1u << x;
+    }
+    uint32_t cm = 0;
+    for (int q = 0; q < o.n_controls; ++q) cm |= 1u << o.controls[q];
+    const BuiltinGate g = builtin_gate(o.gate, np ? o.param : 0.0);
+    t0 = o.targets[0];
+    t1 = arity > 1 ? o.targets[1] : 0;
+    switch (g.cls) {
+      case BG_DENSE1: {
+        d.cmask = cm;
+        bool real = true;
+        for (int e = 0; e < 4; ++e) {
+          d.m[2 * e] = g.m[e].real();
+          d.m[2 * e + 1] = g.m[e].imag();
+          real = real && g.m[e].imag() == 0.0;
+        }
+        const bool flip = g.m[0] == cd(0.0) && g.m[1] == cd(1.0) && g.m[2] == cd(1.0) && g.m[3] == cd(0.0);
+        kind = flip ? BK_X : (real ? BK_U1R : BK_U1);
+        break;
+      }
+      case BG_DIAG:
+        kind = arity == 1 ? BK_DIAG1 : BK_DIAG2;
+        d.cmask = cm;
+        for (size_t e = 0; e < g.m.size(); ++e) {
+          d.m[2 * e] = g.m[e].real();
+          d.m[2 * e + 1] = g.m[e].imag();
+        }
+        break;
+      case BG_PHASE:
+        kind = BK_PHASE;
+        d.cmask = cm | (1u << t0) | (arity > 1 ? (1u << t1) : 0u);
+        d.m[0] = g.z.real();
+        d.m[1] = g.z.imag();
+        break;
+      case BG_SWAP:
+        kind = BK_SWAP;
+        d.cmask = cm;
+        break;
+      default:
+        return cfail(err, QK_E_UNSUPPORTED, "gate class not supported in batches");
+    }
+  } else {
+    return cfail(err, QK_E_ARG, "unknown op kind");
+  }
+  d.head = (uint32_t)kind | ((uint32_t)t0 << 8) | ((uint32_t)t1 << 16) | ((uint32_t)o.n_conds << 24);
+  return QK_OK;
+}
+
 struct HostJob {
   int n, ncbits;
   bool staged = false;    // state in global memory, run by stages
@@ -1006,82 +1172,10 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
   hj.ncbits = ncbits;
   hj.ops.reserve(nops);
   for (int i = 0; i < nops; ++i) {
-    const qk_op& o = ops[i];
-    BOp d{};
-    const std::string where = "op " + std::to_string(i) + ": ";
-    if (o.n_conds < 0 || o.n_conds > 2) return bfail(b, QK_E_ARG, where + "at most 2 conditions");
-    for (int c = 0; c < o.n_conds; ++c) {
-      if (o.conds[c].cbit < 0 || o.conds[c].cbit >= ncbits) return bfail(b, QK_E_ARG, where + "condition cbit out of range");
-      if (o.conds[c].value != 0 && o.conds[c].value != 1) return bfail(b, QK_E_ARG, where + "condition value must be 0 or 1");
-    }
-    int kind = 0, t0 = 0, t1 = 0;
-    d.cbit = -1;
-    if (o.n_conds > 0) d.conds = (uint32_t)o.conds[0].cbit | ((uint32_t)o.conds[0].value << 8);
-    if (o.n_conds > 1) d.conds |= ((uint32_t)o.conds[1].cbit << 16) | ((uint32_t)o.conds[1].value << 24);
-    if (o.kind == QK_OP_MEASURE) {
-      if (o.qubit < 0 || o.qubit >= n) return bfail(b, QK_E_ARG, where + "qubit out of range");
-      if (o.cbit < -1 || o.cbit >= ncbits) return bfail(b, QK_E_ARG, where + "cbit out of range");
-      if (!(o.u >= 0.0 && o.u < 1.0)) return bfail(b, QK_E_ARG, where + "u must be in [0, 1)");
-      if (o.n_conds) return bfail(b, QK_E_ARG, where + "measurements take no conditions");
-      kind = BK_MEAS;
-      t0 = o.qubit;
-      d.cbit = o.cbit;
-      d.m[0] = o.u;
-    } else if (o.kind == QK_OP_GATE) {
-      int arity = 0, np = 0;
-      if (!builtin_info(o.gate, &arity, &np)) return bfail(b, QK_E_UNSUPPORTED, where + "batched circuits take builtin gates only");
-      if (o.n_targets != arity) return bfail(b, QK_E_ARG, where + "target count does not match the gate");
-      if (o.n_controls < 0 || o.n_controls > 4) return bfail(b, QK_E_ARG, where + "at most 4 controls");
-      uint32_t seen = 0;
-      for (int q = 0; q < o.n_targets + o.n_controls; ++q) {
-        const int x = q < o.n_targets ? o.targets[q] : o.controls[q - o.n_targets];
-        if (x < 0 || x >= n) return bfail(b, QK_E_ARG, where + "qubit index out of range");
-        if (seen & (1u << x)) return bfail(b, QK_E_ARG, where + "qubit used twice in one gate");
-        seen |= 1u << x;
-      }
-      uint32_t cm = 0;
-      for (int q = 0; q < o.n_controls; ++q) cm |= 1u << o.controls[q];
-      const BuiltinGate g = builtin_gate(o.gate, np ? o.param : 0.0);
-      t0 = o.targets[0];
-      t1 = arity > 1 ? o.targets[1] : 0;
-      switch (g.cls) {
-        case BG_DENSE1: {
-          d.cmask = cm;
-          bool real = true;
-          for (int e = 0; e < 4; ++e) {
-            d.m[2 * e] = g.m[e].real();
-            d.m[2 * e + 1] = g.m[e].imag();
-            real = real && g.m[e].imag() == 0.0;
-          }
-          const bool flip = g.m[0] == cd(0.0) && g.m[1] == cd(1.0) && g.m[2] == cd(1.0) && g.m[3] == cd(0.0);
-          kind = flip ? BK_X : (real ? BK_U1R : BK_U1);
-          break;
-        }
-        case BG_DIAG:
-          kind = arity == 1 ? BK_DIAG1 : BK_DIAG2;
-          d.cmask = cm;
-          for (size_t e = 0; e < g.m.size(); ++e) {
-            d.m[2 * e] = g.m[e].real();
-            d.m[2 * e + 1] = g.m[e].imag();
-          }
-          break;
-        case BG_PHASE:
-          kind = BK_PHASE;
-          d.cmask = cm | (1u << t0) | (arity > 1 ? (1u << t1) : 0u);
-          d.m[0] = g.z.real();
-          d.m[1] = g.z.imag();
-          break;
-        case BG_SWAP:
-          kind = BK_SWAP;
-          d.cmask = cm;
-          break;
-        default:
-          return bfail(b, QK_E_UNSUPPORTED, where + "gate class not supported in batches");
-      }
-    } else {
-      return bfail(b, QK_E_ARG, where + "unknown op kind");
-    }
-    d.head = (uint32_t)kind | ((uint32_t)t0 << 8) | ((uint32_t)t1 << 16) | ((uint32_t)o.n_conds << 24);
+    BOp d;
+    std::string err;
+    const qk_status st = compile_op(ops[i], n, ncbits, d, err);
+    if (st) return bfail(b, st, "op " + std::to_string(i) + ": " + err);
     hj.ops.push_back(d);
   }
   hj.staged = n > max_lds_qubits(b->c64);
@@ -1300,3 +1394,60 @@ qk_status qk_batch_num_jobs(qk_batch b, int32_t* n) {
 }
 
 }  // extern "C"
+
+// ---- the simulator's LDS-tile mode ---------------------------------------------
+
+namespace qk {
+
+int stage_chunk_qubits(bool c64) { return c64 ? stage_qubits<float>() : stage_qubits<double>(); }
+
+qk_status stage_plan(bool c64, int n, int ncbits, const std::vector<qk_op>& ops, std::vector<unsigned char>& recs,
+                     std::vector<uint32_t>& headers, std::string& err) {
+  std::vector<BOp> bops;
+  bops.reserve(ops.size());
+  for (size_t i = 0; i < ops.size(); ++i) {
+    BOp d;
+    const qk_status st = compile_op(ops[i], n, std::min(ncbits, kMaxJobCbits), d, err);
+    if (st) {
+      err = "op " + std::to_string(i) + ": " + err;
+      return st;
+    }
+    if ((d.head & 0xff) == BK_MEAS) {
+      err = "measurements are not staged";
+      return QK_E_ARG;
+    }
+    bops.push_back(d);
+  }
+  std::vector<BOp> planned = plan_stages(n, stage_chunk_qubits(c64), bops);
+  headers.clear();
+  for (uint32_t r = 0; r < (uint32_t)planned.size(); r += 1 + planned[r].cmask) headers.push_back(r);
+  planned.resize(planned.size() + kPadRecords);   // the item prefetch reads past a stage's last record
+  recs.resize(planned.size() * sizeof(BOp));
+  std::memcpy(recs.data(), planned.data(), recs.size());
+  return QK_OK;
+}
+
+template <typename R>
+static void launch_stage_t(void* psi, int n, const void* d_recs, uint32_t hrec, const uint8_t* d_cbits, int ncbits,
+                           hipStream_t stream) {
+  static int ncu = 0;
+  if (!ncu) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      ncu = 256;
+    (void)hipFuncSetAttribute((const void*)k_stage<R>, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
+  }
+  const size_t shm = (sizeof(typename EVb<R>::T) << stage_qubits<R>()) + kStageLdsWords * 4;   // 64 + 12 KiB
+  const uint32_t nchunks = 1u << (n - stage_qubits<R>());
+  const unsigned grid = (unsigned)std::min<uint32_t>(nchunks, (uint32_t)ncu * 2);   // two 64 KiB chunks per CU
+  hipLaunchKernelGGL(k_stage<R>, dim3(grid), dim3(kBatchThreads), shm, stream, (typename EVb<R>::T*)psi, n,
+                     (const uint32_t*)d_recs, hrec, d_cbits, ncbits);
+}
+
+void launch_stage(bool c64, void* psi, int n, const void* d_recs, uint32_t hrec, const uint8_t* d_cbits, int ncbits,
+                  hipStream_t stream) {
+  if (c64) launch_stage_t<float>(psi, n, d_recs, hrec, d_cbits, ncbits, stream);
+  else launch_stage_t<double>(psi, n, d_recs, hrec, d_cbits, ncbits, stream);
+}
+
+}  // namespace qk

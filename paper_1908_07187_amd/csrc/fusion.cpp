@@ -53,38 +53,62 @@ FGate make_fgate(const int* targets, int k, const int* controls, int nc, const s
   return f;
 }
 
-// b <- G b where gate g acts on a subset of the block's qubits.
+// b <- G b where gate g acts on a subset of the block's qubits.  The rows
+// of b that differ only in the gate's bits form groups of 2^kg; each group's
+// rows are replaced by G times them, a whole row (every column) at a time,
+// in plain real arithmetic; a diagonal gate scales rows.
 static void left_multiply(std::vector<cd>& b, const std::vector<int>& qubits, const FGate& g) {
   const int kb = (int)qubits.size(), kg = (int)g.qubits.size();
   const int Db = 1 << kb, Dg = 1 << kg;
-  std::vector<int> pos(kg);
-  uint64_t gmask = 0;
-  for (int j = 0; j < kg; ++j) {
-    pos[j] = (int)(std::find(qubits.begin(), qubits.end(), g.qubits[j]) - qubits.begin());
-    gmask |= 1ull << pos[j];
+  int off[64];   // row offset of each combination of the gate's bits
+  uint32_t gmask = 0;
+  {
+    int pos[6];
+    for (int j = 0; j < kg; ++j) {
+      pos[j] = (int)(std::find(qubits.begin(), qubits.end(), g.qubits[j]) - qubits.begin());
+      gmask |= 1u << pos[j];
+    }
+    for (int m = 0; m < Dg; ++m) {
+      off[m] = 0;
+      for (int j = 0; j < kg; ++j) off[m] |= bit_of(m, j) << pos[j];
+    }
   }
-  std::vector<cd> v(Dg), w(Dg);
-  std::vector<int> idx(Dg);
-  for (int col = 0; col < Db; ++col) {
-    // treat column `col` as a kb-qubit vector and apply g to it
-    for (int rest = 0; rest < Db; ++rest) {
-      if (rest & (int)gmask) continue;
+  double* B = reinterpret_cast<double*>(b.data());   // (re, im) pairs, row-major
+  const double* G = reinterpret_cast<const double*>(g.m.data());
+  const size_t row = 2 * (size_t)Db;                    // doubles per row
+  if (g.diag) {
+    for (int r = 0; r < Db; ++r) {
+      if (r & gmask) continue;
       for (int m = 0; m < Dg; ++m) {
-        int i = rest;
-        for (int j = 0; j < kg; ++j) i |= bit_of(m, j) << pos[j];
-        idx[m] = i;
-        v[m] = b[(size_t)i * Db + col];
-      }
-      if (g.diag) {
-        for (int m = 0; m < Dg; ++m) w[m] = g.m[(size_t)m * Dg + m] * v[m];
-      } else {
-        for (int r = 0; r < Dg; ++r) {
-          cd s(0, 0);
-          for (int m = 0; m < Dg; ++m) s += g.m[(size_t)r * Dg + m] * v[m];
-          w[r] = s;
+        const double zr = G[2 * ((size_t)m * Dg + m)], zi = G[2 * ((size_t)m * Dg + m) + 1];
+        if (zr == 1.0 && zi == 0.0) continue;
+        double* x = B + (size_t)(r | off[m]) * row;
+        for (int c = 0; c < Db; ++c) {
+          const double xr = x[2 * c], xi = x[2 * c + 1];
+          x[2 * c] = zr * xr - zi * xi;
+          x[2 * c + 1] = zr * xi + zi * xr;
         }
       }
-      for (int m = 0; m < Dg; ++m) b[(size_t)idx[m] * Db + col] = w[m];
+    }
+    return;
+  }
+  std::vector<double> tmp((size_t)Dg * row);
+  for (int r = 0; r < Db; ++r) {
+    if (r & gmask) continue;
+    for (int m = 0; m < Dg; ++m) std::memcpy(&tmp[(size_t)m * row], B + (size_t)(r | off[m]) * row, row * sizeof(double));
+    for (int m = 0; m < Dg; ++m) {
+      double* y = B + (size_t)(r | off[m]) * row;
+      for (int c = 0; c < 2 * Db; ++c) y[c] = 0.0;
+      for (int j = 0; j < Dg; ++j) {
+        const double ar = G[2 * ((size_t)m * Dg + j)], ai = G[2 * ((size_t)m * Dg + j) + 1];
+        if (ar == 0.0 && ai == 0.0) continue;
+        const double* x = &tmp[(size_t)j * row];
+        for (int c = 0; c < Db; ++c) {
+          const double xr = x[2 * c], xi = x[2 * c + 1];
+          y[2 * c] += ar * xr - ai * xi;
+          y[2 * c + 1] += ar * xi + ai * xr;
+        }
+      }
     }
   }
 }

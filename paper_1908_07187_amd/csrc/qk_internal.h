@@ -75,6 +75,7 @@ struct Tuning {
   int swap_relabel = 1;  // 1: an uncontrolled SWAP on a dense state relabels the two qubits instead of moving data
   int mfma_lds = 2;      // blocks of 4-5 qubits: 0 register tiles, 1 LDS-staged tiles, 2 chosen per block
   int lds_wg = 2;        // workgroups per CU of the LDS-staged kernel
+  int stages = 0;        // 1: runs of builtin gates are held back and applied by stages through LDS chunks
 };
 
 // Where device work goes and what it works on.
@@ -311,5 +312,17 @@ struct FBlock {
 FGate make_fgate(const int* targets, int k, const int* controls, int nc, const std::vector<cd>& g);
 // Greedy commutation-aware grouping into blocks of at most kmax qubits.
 std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax);
+
+// ---- the LDS-tile mode (batch.hip) ---------------------------------------------
+// Held-back builtin gates (op records on physical qubits, n of them, cbit
+// conditions below 256) compiled and grouped into stages of
+// stage_chunk_qubits() qubits; recs is the device record image, headers the
+// record index of each stage's header, in order.  launch_stage applies one
+// stage to every chunk of the state (n from stage_chunk_qubits() to 31).
+int stage_chunk_qubits(bool c64);
+qk_status stage_plan(bool c64, int n, int ncbits, const std::vector<qk_op>& ops, std::vector<unsigned char>& recs,
+                     std::vector<uint32_t>& headers, std::string& err);
+void launch_stage(bool c64, void* psi, int n, const void* d_recs, uint32_t hrec, const uint8_t* d_cbits, int ncbits,
+                  hipStream_t stream);
 
 }  // namespace qk

@@ -71,11 +71,14 @@ def test_random26_depth40_matches_oracle_samples():
 
 def _bench_sim(dtype, fused):
     """A simulator in the configuration bench.py times: complex128 strictly
-    gate by gate (diagonal runs off), or fused blocks with the autotuned
-    shape for 30-qubit states."""
+    gate by gate (diagonal runs off), fused blocks with the autotuned shape
+    for 30-qubit states, or (fused="stages") the LDS-tile mode."""
     import paper_1908_07187_amd as qk
     from paper_1908_07187_amd import autotune
     s = qk.Sim(dtype)
+    if fused == "stages":
+        s.set_tuning("stages", 1)
+        return s
     if not fused:
         s.set_tuning("diag_runs", 0)
         return s
@@ -119,12 +122,15 @@ def oracle26():
     return circ, ref
 
 
-@pytest.mark.parametrize("dtype,fused", [("c128", False), ("c64", True), ("c128", True)])
+@pytest.mark.parametrize("dtype,fused", [("c128", False), ("c64", True), ("c128", True), ("c128", "stages"),
+                                         ("c64", "stages")])
 def test_random26_depth40_whole_state_matches_oracle(oracle26, dtype, fused):
     """The 26-qubit depth-40 circuit (seed 0), every one of its 2^26
     amplitudes against the oracle: complex128 gate by gate, complex64 and
-    complex128 with fused blocks.  Fidelity for complex64 on FP64-normalised
-    states (the complex64 acceptance rule)."""
+    complex128 with fused blocks, both in the LDS-tile mode.  Fidelity for
+    complex64 on FP64-normalised states (the complex64 acceptance rule); its
+    norm drift bound counts a staged gate (at most two targets) like a
+    2-qubit block."""
     circ, ref = oracle26
     _say(f"26q depth 40 {dtype} fused={fused}")
     s = _bench_sim(dtype, fused)
@@ -140,9 +146,10 @@ def test_random26_depth40_whole_state_matches_oracle(oracle26, dtype, fused):
         assert d <= 2e-5
         f = abs(np.vdot(ref, got)) ** 2 / (np.vdot(ref, ref).real * np.vdot(got, got).real)
         drift = abs(np.vdot(got, got).real - 1.0)
-        _say(f"  fidelity {f!r}, |norm^2 - 1| = {drift:.3e} (bound {_c64_norm_bound(sweeps):.3e})")
+        bound = _c64_norm_bound(len(circ.gate_ops()), k=2) if fused == "stages" else _c64_norm_bound(sweeps)
+        _say(f"  fidelity {f!r}, |norm^2 - 1| = {drift:.3e} (bound {bound:.3e})")
         assert f >= 1 - 1e-6
-        assert drift <= _c64_norm_bound(sweeps)
+        assert drift <= bound
 
 
 def qk_prog(circ):
@@ -150,8 +157,8 @@ def qk_prog(circ):
     return qk.Program(circ)
 
 
-@pytest.mark.parametrize("dtype", ["c128", "c64"])
-def test_random30_split_depth40_whole_state_matches_oracle_product(dtype):
+@pytest.mark.parametrize("dtype,mode", [("c128", "bench"), ("c64", "bench"), ("c128", "stages")])
+def test_random30_split_depth40_whole_state_matches_oracle_product(dtype, mode):
     """30 qubits, depth 40, the layer recipe with two-qubit gates kept inside
     the even and the odd qubits: every gate still sweeps the whole 30-qubit
     state (bench configuration: complex128 gate by gate, complex64 fused),
@@ -164,7 +171,7 @@ def test_random30_split_depth40_whole_state_matches_oracle_product(dtype):
     parts = [oracle.run(W.restrict(circ, list(range(g, n, 2))))[0] for g in range(2)]
     ps = ProductState(parts, n)
     _say(f"30q split depth 40 {dtype}")
-    s = _bench_sim(dtype, fused=(dtype == "c64"))
+    s = _bench_sim(dtype, fused="stages" if mode == "stages" else (dtype == "c64"))
     qk_prog(circ).run(s)
     s.flush()
     sweeps = s.stats()["sweeps"]
