@@ -57,13 +57,15 @@ def parse():
     ap.add_argument("--cpu-gates", type=int, default=16, help="gates of the circuit the oracle sample runs")
     ap.add_argument("--workload", default="random30",
                     choices=["random30", "batch12", "batch_mid", "serve", "qft26", "ipe21", "shor", "sample30", "shor39",
-                             "kernels30", "cpu_oracle"],
+                             "kernels30", "cpu_oracle", "stages30"],
                     help="random30 (default): the 30-qubit depth-40 circuit; the others are the batching, "
                          "serving, QFT, phase-estimation, Shor (dense and sparse) and deferred-measurement forms")
     ap.add_argument("--serve-jobs", type=int, default=400)
     ap.add_argument("--serve-rates", default="0.8", help="offered load as fractions of the closed-loop capacity")
     ap.add_argument("--serve-mid-max", type=int, default=0,
                     help="batch serving jobs up to this many qubits by stages (0: only jobs that fit LDS)")
+    ap.add_argument("--serve-stages", action="store_true",
+                    help="serving: run stream-slot jobs in the LDS-tile mode instead of autotuned fusion")
     ap.add_argument("--serve-capacity", type=float, default=0.0,
                     help="closed-loop capacity in circuits/s (0: measure it first)")
     ap.add_argument("--batch-circuits", type=int, default=2048)

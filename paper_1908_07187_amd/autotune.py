@@ -2,8 +2,9 @@
 
 For a (qubit count, dtype) pair it times a short slice (a few layers) of the
 layered random recipe -- one-qubit layer, CNOT matching, RZZ matching -- on
-the device, first over the fusion width k in {0 (gate by gate), 3, 4, 5, 6}
-with the default tile, then over the tile shape (columns per wave up to the
+the device (wall time of enqueueing and running, so host planning counts),
+first over the fusion width k in {0 (gate by gate), 3, 4, 5, 6} with the
+default tile and the LDS-tile mode (``stages``), then over the tile shape (columns per wave up to the
 widest the block size has, A fragments in registers or LDS, waves per
 compute unit; or, for 4- and 5-qubit blocks, workgroup tiles staged through
 LDS) for the two best widths.  The fastest configuration is stored in a JSON cache keyed by
@@ -24,7 +25,7 @@ from typing import Dict, Optional
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CACHE = os.path.join(HERE, "tuning", "mi355x.json")
-SHAPE_KEYS = ("mfma_cols", "mfma_areg", "mfma_waves", "mfma_lds", "lds_wg")
+SHAPE_KEYS = ("mfma_cols", "mfma_areg", "mfma_waves", "mfma_lds", "lds_wg", "stages")
 
 
 def max_cols(k: int, dtype: str) -> int:
@@ -98,11 +99,17 @@ def tune(n: int, dtype: str, layers: int = 3, seed: int = 0, verbose: bool = Tru
         if verbose:
             print(f"[autotune] n={n} {dtype} fusion={k}: {t * 1e3:.1f} ms ({ngates} gates)", file=sys.stderr,
                   flush=True)
+    per_gate = results[0][1]
+    if n >= (13 if dtype == "c64" else 12):   # the LDS-tile mode takes states of at least one chunk
+        t = _time_config(qk, prog, n, dtype, {"fusion": 0, "stages": 1})
+        results.append(({"fusion": 0, "stages": 1}, t))
+        if verbose:
+            print(f"[autotune] n={n} {dtype} stages: {t * 1e3:.1f} ms", file=sys.stderr, flush=True)
     results.sort(key=lambda r: r[1])
     best_cfg, best_t = results[0]
     for base, _ in results[:2]:
         k = base["fusion"]
-        if k == 0:
+        if k == 0 or base.get("stages"):
             continue
         cands = []
         for cols, areg, waves in itertools.product((16, 32, 64), (0, 1), (8, 16)):
@@ -119,7 +126,7 @@ def tune(n: int, dtype: str, layers: int = 3, seed: int = 0, verbose: bool = Tru
                 best_cfg, best_t = cfg, t
     out = dict(best_cfg)
     out.update({"ms_per_gate": best_t * 1e3 / ngates, "gates": ngates, "layers": layers,
-                "per_gate_ms_per_gate": dict((r[0]["fusion"], r[1]) for r in results)[0] * 1e3 / ngates})
+                "per_gate_ms_per_gate": per_gate * 1e3 / ngates})
     return out
 
 

@@ -130,7 +130,8 @@ def serve(args, qk, torch):
     prog = max(50, nj // 20)
     mid = {"c128": args.serve_mid_max, "c64": args.serve_mid_max} if args.serve_mid_max > 0 else None
     warm = W.c4_job_stream(20, seed=args.seed + 1, rate=1.0)
-    Server(slots=8, autotuned=True, mid_max=mid).serve(warm, realtime=False)
+    sg = bool(args.serve_stages)
+    Server(slots=8, autotuned=True, mid_max=mid, stages=sg).serve(warm, realtime=False)
     if args.serve_capacity > 0:
         cap = args.serve_capacity
         _say(f"serve: capacity {cap:.1f} circuits/s given")
@@ -138,7 +139,7 @@ def serve(args, qk, torch):
         _say(f"serve: closed loop over {nj} jobs")
         jobs = W.c4_job_stream(nj, seed=args.seed, rate=1.0)
         c0 = time.perf_counter_ns()
-        rep0 = Server(slots=8, autotuned=True, mid_max=mid).serve(jobs, realtime=False, progress_every=prog)
+        rep0 = Server(slots=8, autotuned=True, mid_max=mid, stages=sg).serve(jobs, realtime=False, progress_every=prog)
         spans["closed_loop"] = (c0, time.perf_counter_ns())
         cap = rep0.circuits_per_s
         _say(f"serve closed-loop capacity {cap:.1f} circuits/s, wall {rep0.wall_s:.1f} s")
@@ -149,7 +150,7 @@ def serve(args, qk, torch):
         rate = frac * cap
         jobs_p = W.c4_job_stream(nj, seed=args.seed, rate=rate)
         c0 = time.perf_counter_ns()
-        rep = Server(slots=8, keep_states=sample if fi == 0 else set(), autotuned=True, mid_max=mid).serve(
+        rep = Server(slots=8, keep_states=sample if fi == 0 else set(), autotuned=True, mid_max=mid, stages=sg).serve(
             jobs_p, realtime=True, progress_every=prog)
         spans[f"{frac:.2f}"] = (c0, time.perf_counter_ns())
         _say(f"serve at {frac:.2f} x capacity = {rate:.1f}/s: {rep.circuits_per_s:.1f} circuits/s "
@@ -198,6 +199,7 @@ def serve(args, qk, torch):
                                    "mean_wait_before_admission_ms": float(wait.mean())}
     out["latency_by_qubits"] = by
     out["mid_batched_max_qubits"] = args.serve_mid_max if mid else None
+    out["stream_jobs"] = "stages" if sg else "autotuned fusion"
     return out
 
 
@@ -660,6 +662,37 @@ def batch_mid(args, qk, torch):
     return res
 
 
+def stages30(args, qk, torch):
+    """The 30-qubit depth-40 circuit in the LDS-tile mode only (complex128
+    and complex64, one untimed and one timed pass each): a short program for
+    profiling the stage kernel."""
+    import workloads as W
+    circ = W.c2_random_rzz(n=args.qubits, depth=args.depth, seed=args.seed)
+    prog = qk.Program(circ)
+    upd = circ.amp_updates()
+    res = {}
+    for dt in ("c128", "c64"):
+        dtm = 0.0
+        for rep in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s = qk.Sim(dt)
+            s.set_tuning("stages", 1)
+            prog.run(s)
+            s.flush()
+            torch.cuda.synchronize()
+            dtm = time.perf_counter() - t0
+            st = s.stats()
+            s.close()
+        res[dt] = {"ms_per_step": dtm * 1e3, "amp_updates_per_s": upd / dtm, "stages": st["sweeps"]}
+        _say(f"stages30 {dt}: {dtm * 1e3:.1f} ms, {upd / dtm:.4e} amp-updates/s, {st['sweeps']} stages")
+    out = _base(args, res["c128"]["amp_updates_per_s"], "amplitude-updates/s",
+                {"workload": f"{args.qubits}-qubit depth-{args.depth} layered circuit in the LDS-tile mode"}, "f64",
+                res["c128"]["ms_per_step"])
+    out["forms"] = res
+    return out
+
+
 def cpu_oracle(args, qk, torch):
     """The CPU baseline plan: the FP64 oracle (as it stands) on the host's
     cores, single thread and OpenMP over all threads, each case bounded to
@@ -715,4 +748,4 @@ def cpu_oracle(args, qk, torch):
 def run(name, args, qk, torch):
     return {"batch12": batch12, "serve": serve, "qft26": qft26, "ipe21": ipe21, "shor": shor,
             "sample30": sample30, "shor39": shor39, "kernels30": kernels30,
-            "cpu_oracle": cpu_oracle, "batch_mid": batch_mid}[name](args, qk, torch)
+            "cpu_oracle": cpu_oracle, "batch_mid": batch_mid, "stages30": stages30}[name](args, qk, torch)

@@ -20,8 +20,9 @@ Jobs (a circuit and a dtype) arrive over time.  The loop, run on the host:
   batches so a long mid-size batch never holds back small results;
 * gives every admitted large job its own stream slot and enqueues its whole
   circuit there (fused into matrix-core blocks as configured, or as the
-  autotuner chose for that qubit count and dtype); slots run concurrently,
-  so their sweeps overlap on the device;
+  autotuner chose for that qubit count and dtype, or with ``stages`` in the
+  LDS-tile mode); slots run concurrently, so their sweeps overlap on the
+  device;
 * polls completion events and, for each finished job, reads its cbits and a
   digest (norm; for small jobs the whole state) back to the host, frees its
   memory and records its latency (arrival -> result on the host).  A
@@ -111,7 +112,7 @@ class Server:
     def __init__(self, hbm_budget: Optional[int] = None, slots: int = 8,
                  fusion: Optional[Dict[str, int]] = None, keep_states: Sequence[int] = (),
                  small_max: Optional[Dict[str, int]] = None, poll_sleep: float = 20e-6,
-                 autotuned: bool = False, mid_max: Optional[Dict[str, int]] = None):
+                 autotuned: bool = False, mid_max: Optional[Dict[str, int]] = None, stages: bool = False):
         import torch
         self.torch = torch
         if hbm_budget is None:
@@ -123,6 +124,9 @@ class Server:
         self.keep_states = set(keep_states)
         self.small_max = dict(SMALL_MAX if small_max is None else small_max)
         self.mid_max = dict(self.small_max if mid_max is None else mid_max)
+        # stream-slot jobs in the LDS-tile mode (gates grouped into stages, no
+        # block matrices to compose) instead of fused blocks
+        self.stages = stages
         self.poll_sleep = poll_sleep
         # large jobs take the autotuner's fusion width and tile shape for their size
         self.tuning_cache = _autotune.load_cache() if autotuned else None
@@ -274,7 +278,9 @@ class Server:
                 sim = None
                 try:
                     sim = Sim(dt, stream=streams[slot])
-                    if self.autotuned:
+                    if self.stages:
+                        sim.set_tuning("stages", 1)
+                    elif self.autotuned:
                         _autotune.apply(sim, r.n, dt, self.tuning_cache)
                     elif self.fusion.get(dt, 0):
                         sim.set_fusion(self.fusion[dt])

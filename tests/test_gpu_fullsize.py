@@ -84,7 +84,7 @@ def _bench_sim(dtype, fused):
         return s
     cfg = autotune.lookup(30, dtype) or {"fusion": 5}
     for key in autotune.SHAPE_KEYS:
-        if key in cfg:
+        if key in cfg and key != "stages":
             s.set_tuning(key, cfg[key])
     s.set_fusion(cfg.get("fusion", 5) or 5)
     return s
