@@ -53,11 +53,13 @@ FGate make_fgate(const int* targets, int k, const int* controls, int nc, const s
   return f;
 }
 
-// b <- G b where gate g acts on a subset of the block's qubits.  The rows
-// of b that differ only in the gate's bits form groups of 2^kg; each group's
-// rows are replaced by G times them, a whole row (every column) at a time,
-// in plain real arithmetic; a diagonal gate scales rows.
-static void left_multiply(std::vector<cd>& b, const std::vector<int>& qubits, const FGate& g) {
+// b <- G b where gate g acts on a subset of the block's qubits; b is kept as
+// separate real and imaginary parts (row-major, Db x Db each) so that the
+// row updates below run over contiguous doubles.  The rows of b that differ
+// only in the gate's bits form groups of 2^kg; each group's rows are replaced
+// by G times them, a whole row at a time; a diagonal gate scales rows.
+static void left_multiply(std::vector<double>& bre, std::vector<double>& bim, std::vector<double>& tre,
+                          std::vector<double>& tim, const std::vector<int>& qubits, const FGate& g) {
   const int kb = (int)qubits.size(), kg = (int)g.qubits.size();
   const int Db = 1 << kb, Dg = 1 << kg;
   int off[64];   // row offset of each combination of the gate's bits
@@ -73,42 +75,57 @@ static void left_multiply(std::vector<cd>& b, const std::vector<int>& qubits, co
       for (int j = 0; j < kg; ++j) off[m] |= bit_of(m, j) << pos[j];
     }
   }
-  double* B = reinterpret_cast<double*>(b.data());   // (re, im) pairs, row-major
-  const double* G = reinterpret_cast<const double*>(g.m.data());
-  const size_t row = 2 * (size_t)Db;                    // doubles per row
   if (g.diag) {
     for (int r = 0; r < Db; ++r) {
       if (r & gmask) continue;
       for (int m = 0; m < Dg; ++m) {
-        const double zr = G[2 * ((size_t)m * Dg + m)], zi = G[2 * ((size_t)m * Dg + m) + 1];
+        const cd z = g.m[(size_t)m * Dg + m];
+        const double zr = z.real(), zi = z.imag();
         if (zr == 1.0 && zi == 0.0) continue;
-        double* x = B + (size_t)(r | off[m]) * row;
+        double* xr = &bre[(size_t)(r | off[m]) * Db];
+        double* xi = &bim[(size_t)(r | off[m]) * Db];
         for (int c = 0; c < Db; ++c) {
-          const double xr = x[2 * c], xi = x[2 * c + 1];
-          x[2 * c] = zr * xr - zi * xi;
-          x[2 * c + 1] = zr * xi + zi * xr;
+          const double a = xr[c], b = xi[c];
+          xr[c] = zr * a - zi * b;
+          xi[c] = zr * b + zi * a;
         }
       }
     }
     return;
   }
-  std::vector<double> tmp((size_t)Dg * row);
+  tre.resize((size_t)Dg * Db);
+  tim.resize((size_t)Dg * Db);
   for (int r = 0; r < Db; ++r) {
     if (r & gmask) continue;
-    for (int m = 0; m < Dg; ++m) std::memcpy(&tmp[(size_t)m * row], B + (size_t)(r | off[m]) * row, row * sizeof(double));
     for (int m = 0; m < Dg; ++m) {
-      double* y = B + (size_t)(r | off[m]) * row;
-      for (int c = 0; c < 2 * Db; ++c) y[c] = 0.0;
+      std::memcpy(&tre[(size_t)m * Db], &bre[(size_t)(r | off[m]) * Db], Db * sizeof(double));
+      std::memcpy(&tim[(size_t)m * Db], &bim[(size_t)(r | off[m]) * Db], Db * sizeof(double));
+    }
+    for (int m = 0; m < Dg; ++m) {
+      double* yr = &bre[(size_t)(r | off[m]) * Db];
+      double* yi = &bim[(size_t)(r | off[m]) * Db];
+      bool first = true;
       for (int j = 0; j < Dg; ++j) {
-        const double ar = G[2 * ((size_t)m * Dg + j)], ai = G[2 * ((size_t)m * Dg + j) + 1];
+        const cd a = g.m[(size_t)m * Dg + j];
+        const double ar = a.real(), ai = a.imag();
         if (ar == 0.0 && ai == 0.0) continue;
-        const double* x = &tmp[(size_t)j * row];
-        for (int c = 0; c < Db; ++c) {
-          const double xr = x[2 * c], xi = x[2 * c + 1];
-          y[2 * c] += ar * xr - ai * xi;
-          y[2 * c + 1] += ar * xi + ai * xr;
+        const double* xr = &tre[(size_t)j * Db];
+        const double* xi = &tim[(size_t)j * Db];
+        if (first) {
+          for (int c = 0; c < Db; ++c) {
+            yr[c] = ar * xr[c] - ai * xi[c];
+            yi[c] = ar * xi[c] + ai * xr[c];
+          }
+          first = false;
+        } else {
+          for (int c = 0; c < Db; ++c) {
+            yr[c] += ar * xr[c] - ai * xi[c];
+            yi[c] += ar * xi[c] + ai * xr[c];
+          }
         }
       }
+      if (first)
+        for (int c = 0; c < Db; ++c) yr[c] = yi[c] = 0.0;
     }
   }
 }
@@ -197,6 +214,7 @@ std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax) {
     return (long)marked.size();
   };
   std::vector<FBlock> out;
+  std::vector<double> bre, bim, tre, tim;   // block matrix being composed (real, imaginary) and row scratch
   int first = 0;   // earliest unscheduled gate
   std::vector<int> cand;
   while (true) {
@@ -251,14 +269,17 @@ std::vector<FBlock> plan_blocks(const std::vector<FGate>& gates, int kmax) {
       if ((smask >> q) & 1) blk.qubits.push_back(q);
     const int kb = (int)blk.qubits.size();
     const int Db = 1 << kb;
-    blk.m.assign((size_t)Db * Db, cd(0, 0));
-    for (int r = 0; r < Db; ++r) blk.m[(size_t)r * Db + r] = 1.0;
+    bre.assign((size_t)Db * Db, 0.0);
+    bim.assign((size_t)Db * Db, 0.0);
+    for (int r = 0; r < Db; ++r) bre[(size_t)r * Db + r] = 1.0;
     blk.members = members;
     for (int i : members) {
-      left_multiply(blk.m, blk.qubits, gates[i]);
+      left_multiply(bre, bim, tre, tim, blk.qubits, gates[i]);
       blk.ngates++;
       blk.diag = blk.diag && gates[i].diag;
     }
+    blk.m.resize((size_t)Db * Db);
+    for (size_t e = 0; e < blk.m.size(); ++e) blk.m[e] = cd(bre[e], bim[e]);
     out.push_back(std::move(blk));
   }
   return out;
