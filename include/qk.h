@@ -328,6 +328,18 @@ qk_status qk_inner_product(qk_sim a, qk_sim b, double* re, double* im);
 
 /* FP64 squared norm sum |a_i|^2.  Synchronises. */
 qk_status qk_norm2(qk_sim sim, double* out);
+/* Asynchronous readouts for hosts that must not wait on the device (a
+ * serving loop): both only enqueue work on the simulator's stream and
+ * return.  qk_norm2_async enqueues the norm's fixed-order partial sums
+ * (*count receives their number nb) and their copy into host_partials as
+ * (re, im) pairs (capacity >= 2 nb doubles, at most 2048); the sum of the
+ * nb real parts taken in order equals qk_norm2 exactly.  qk_read_cbits_async
+ * enqueues the copy of the first n cbits.  The host buffers (pinned memory
+ * keeps the copies asynchronous) must stay valid, and hold the results only
+ * after the stream has reached this point (an event recorded after the call
+ * has completed).  Dense states only for the norm. */
+qk_status qk_norm2_async(qk_sim sim, double* host_partials, int32_t capacity, int32_t* count);
+qk_status qk_read_cbits_async(qk_sim sim, uint8_t* host_out, int32_t n);
 
 /* ---- execution control -------------------------------------------------- */
 
@@ -499,6 +511,19 @@ qk_status qk_batch_sync(qk_batch batch);
 qk_status qk_batch_get_state(qk_batch batch, int32_t job, void* host_out, size_t bytes);
 qk_status qk_batch_read_cbits(qk_batch batch, int32_t job, uint8_t* out, int32_t n);
 qk_status qk_batch_state_ptr(qk_batch batch, int32_t job, void** dev_ptr, size_t* bytes);
+/* Where job `job` lives in the batch's buffers (host only, any time after
+ * the job was added): byte offset and size of its state, offset of its
+ * cbits (one byte each); the same layout as qk_batch_read_async's copies. */
+qk_status qk_batch_layout(qk_batch batch, int32_t job, size_t* state_offset, size_t* state_bytes,
+                          size_t* cbit_offset);
+/* Enqueue (after the last qk_batch_run, on the batch's stream; no wait) the
+ * copy of every job's final state and cbits into host buffers of at least
+ * the batch's total sizes (pinned memory keeps it asynchronous).  For hosts
+ * that must not wait on the device, such as a serving loop: the results are
+ * there once the stream has reached this point (an event recorded after the
+ * call has completed).  QK_E_STATE before a run. */
+qk_status qk_batch_read_async(qk_batch batch, void* host_states, size_t state_bytes, uint8_t* host_cbits,
+                              size_t cbit_bytes);
 /* Forget every circuit (device buffers are kept for reuse). */
 qk_status qk_batch_clear(qk_batch batch);
 qk_status qk_batch_num_jobs(qk_batch batch, int32_t* n);

@@ -131,7 +131,8 @@ def serve(args, qk, torch):
     mid = {"c128": args.serve_mid_max, "c64": args.serve_mid_max} if args.serve_mid_max > 0 else None
     warm = W.c4_job_stream(20, seed=args.seed + 1, rate=1.0)
     sg = bool(args.serve_stages)
-    Server(slots=8, autotuned=True, mid_max=mid, stages=sg).serve(warm, realtime=False)
+    Server(slots=args.serve_slots, autotuned=True, mid_max=mid, stages=sg).serve(warm, realtime=False)
+    rep0 = None
     if args.serve_capacity > 0:
         cap = args.serve_capacity
         _say(f"serve: capacity {cap:.1f} circuits/s given")
@@ -139,7 +140,8 @@ def serve(args, qk, torch):
         _say(f"serve: closed loop over {nj} jobs")
         jobs = W.c4_job_stream(nj, seed=args.seed, rate=1.0)
         c0 = time.perf_counter_ns()
-        rep0 = Server(slots=8, autotuned=True, mid_max=mid, stages=sg).serve(jobs, realtime=False, progress_every=prog)
+        rep0 = Server(slots=args.serve_slots, autotuned=True, mid_max=mid, stages=sg).serve(jobs, realtime=False,
+                                                                                         progress_every=prog)
         spans["closed_loop"] = (c0, time.perf_counter_ns())
         cap = rep0.circuits_per_s
         _say(f"serve closed-loop capacity {cap:.1f} circuits/s, wall {rep0.wall_s:.1f} s")
@@ -150,7 +152,8 @@ def serve(args, qk, torch):
         rate = frac * cap
         jobs_p = W.c4_job_stream(nj, seed=args.seed, rate=rate)
         c0 = time.perf_counter_ns()
-        rep = Server(slots=8, keep_states=sample if fi == 0 else set(), autotuned=True, mid_max=mid, stages=sg).serve(
+        rep = Server(slots=args.serve_slots, keep_states=sample if fi == 0 else set(), autotuned=True, mid_max=mid,
+                     stages=sg).serve(
             jobs_p, realtime=True, progress_every=prog)
         spans[f"{frac:.2f}"] = (c0, time.perf_counter_ns())
         _say(f"serve at {frac:.2f} x capacity = {rate:.1f}/s: {rep.circuits_per_s:.1f} circuits/s "
@@ -180,6 +183,9 @@ def serve(args, qk, torch):
                 "f32/f64")
     out["latency_ms"] = {"p50": rep.p50_ms, "p99": rep.p99_ms, "mean": rep.mean_ms}
     out["host_busy_frac"] = rep.extra.get("host_busy_frac")
+    out["host_s"] = rep.extra.get("host_s")
+    out["closed_loop_host_s"] = rep0.extra.get("host_s") if rep0 is not None else None
+    out["closed_loop_host_busy_frac"] = rep0.extra.get("host_busy_frac") if rep0 is not None else None
     out["clock_spans_ns"] = spans
     out["closed_loop_capacity_cps"] = cap
     out["levels"] = levels
@@ -200,6 +206,7 @@ def serve(args, qk, torch):
     out["latency_by_qubits"] = by
     out["mid_batched_max_qubits"] = args.serve_mid_max if mid else None
     out["stream_jobs"] = "stages" if sg else "autotuned fusion"
+    out["stream_slots"] = args.serve_slots
     return out
 
 

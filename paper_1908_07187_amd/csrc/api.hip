@@ -1233,7 +1233,14 @@ qk_status qk_destroy(qk_sim s) {
     if (g) (void)hipGraphDestroy(g);
     s->capturing = false;
   }
-  if (s->state.p || s->meas.p || s->sp.idx || !s->arenas.empty()) (void)hipStreamSynchronize(s->stream);
+  if (s->state.p || s->meas.p || s->sp.idx || !s->arenas.empty()) {
+    // Synchronise only when work is still pending: on a stream that has
+    // finished, hipStreamSynchronize still waited behind other streams' work
+    // sharing its hardware queue (about 5 ms per simulator in a serving loop
+    // that destroys one per job).
+    if (hipStreamQuery(s->stream) != hipSuccess) (void)hipStreamSynchronize(s->stream);
+    (void)hipGetLastError();
+  }
   dev_free(s, s->state);
   dev_free(s, s->scratch);
   dev_free(s, s->cbits);
@@ -2038,6 +2045,40 @@ qk_status qk_inner_product(qk_sim a, qk_sim b, double* re, double* im) {
   }
   if (re) *re = sr;
   if (im) *im = si;
+  return QK_OK;
+}
+
+qk_status qk_norm2_async(qk_sim s, double* host_partials, int32_t capacity, int32_t* count) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (!count || (capacity > 0 && !host_partials)) return fail(s, QK_E_ARG, "NULL argument");
+  if (s->sparse) return fail(s, QK_E_UNSUPPORTED, "asynchronous norm of a sparse state");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
+  if (!s->state.p) return fail(s, QK_E_STATE, "no qubits");
+  qk_status st = flush(s);
+  if (st) return st;
+  if ((st = ensure_meas(s))) return st;
+  const uint64_t dim = 1ull << s->n;
+  const int nb = reduce_blocks_for(dim);
+  if (capacity < 2 * nb) return fail(s, QK_E_ARG, "capacity below 2 x " + std::to_string(nb) + " partial sums");
+  MeasBuffers mb = meas_buffers(s);
+  hipError_t e = launch_inner_partials(s->state.p, s->c64, s->state.p, s->c64, dim, mb.partials, nb, s->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(host_partials, mb.partials, 2 * (size_t)nb * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+  if (e != hipSuccess) return hip_fail(s, e, "asynchronous norm");
+  *count = nb;
+  return QK_OK;
+}
+
+qk_status qk_read_cbits_async(qk_sim s, uint8_t* host_out, int32_t n) {
+  if (!s) return fail(nullptr, QK_E_ARG, "sim is NULL");
+  if (s->capturing) return fail(s, QK_E_STATE, "not allowed while capturing a graph");
+  if (n < 0 || n > s->ncbits || (n > 0 && !host_out)) return fail(s, QK_E_ARG, "bad cbit count");
+  qk_status st = flush(s);
+  if (st) return st;
+  if (n > 0) {
+    hipError_t e = hipMemcpyAsync(host_out, s->cbits.p, (size_t)n, hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(s, e, "asynchronous cbit read");
+  }
   return QK_OK;
 }
 

@@ -1379,6 +1379,39 @@ qk_status qk_batch_state_ptr(qk_batch b, int32_t job, void** dev_ptr, size_t* by
   return QK_OK;
 }
 
+qk_status qk_batch_layout(qk_batch b, int32_t job, size_t* state_offset, size_t* state_bytes, size_t* cbit_offset) {
+  if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
+  if (job < 0 || job >= (int)b->jobs.size()) return bfail(b, QK_E_ARG, "job index out of range");
+  uint64_t soff = 0, coff = 0;   // the layout qk_batch_run uses: states and cbits in job order
+  for (int32_t i = 0; i < job; ++i) {
+    soff += 1ull << b->jobs[i].n;
+    coff += (uint64_t)b->jobs[i].ncbits;
+  }
+  const size_t amp = b->c64 ? 8 : 16;
+  if (state_offset) *state_offset = soff * amp;
+  if (state_bytes) *state_bytes = ((size_t)1 << b->jobs[job].n) * amp;
+  if (cbit_offset) *cbit_offset = coff;
+  return QK_OK;
+}
+
+qk_status qk_batch_read_async(qk_batch b, void* host_states, size_t state_bytes, uint8_t* host_cbits,
+                              size_t cbit_bytes) {
+  if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
+  if (!b->ran || !b->uploaded) return bfail(b, QK_E_STATE, "batch has not run since the last job was added");
+  uint64_t samps = 0, cbytes = 0;
+  for (const auto& j : b->jobs) {
+    samps += 1ull << j.n;
+    cbytes += (uint64_t)j.ncbits;
+  }
+  const size_t need = samps * (b->c64 ? 8 : 16);
+  if (!host_states || state_bytes < need) return bfail(b, QK_E_ARG, "state buffer smaller than the batch's states");
+  if (cbytes && (!host_cbits || cbit_bytes < cbytes)) return bfail(b, QK_E_ARG, "cbit buffer smaller than the batch's cbits");
+  hipError_t e = hipMemcpyAsync(host_states, b->d_states, need, hipMemcpyDeviceToHost, b->stream);
+  if (e == hipSuccess && cbytes) e = hipMemcpyAsync(host_cbits, b->d_cbits, cbytes, hipMemcpyDeviceToHost, b->stream);
+  if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch asynchronous read: ") + hipGetErrorString(e));
+  return QK_OK;
+}
+
 qk_status qk_batch_clear(qk_batch b) {
   if (!b) return bfail(nullptr, QK_E_ARG, "batch is NULL");
   b->jobs.clear();

@@ -82,6 +82,8 @@ SIGNATURES = {
     "qk_state_ptr": (_I32, [_P, C.POINTER(_P), C.POINTER(_SZ)]),
     "qk_inner_product": (_I32, [_P, _P, _DP, _DP]),
     "qk_norm2": (_I32, [_P, _DP]),
+    "qk_norm2_async": (_I32, [_P, C.c_void_p, _I32, _I32P]),
+    "qk_read_cbits_async": (_I32, [_P, C.c_void_p, _I32]),
     "qk_set_fusion": (_I32, [_P, _I32]),
     "qk_flush": (_I32, [_P]),
     "qk_sync": (_I32, [_P]),
@@ -101,6 +103,8 @@ SIGNATURES = {
     "qk_batch_sync": (_I32, [_P]),
     "qk_batch_get_state": (_I32, [_P, _I32, _P, _SZ]),
     "qk_batch_read_cbits": (_I32, [_P, _I32, _U8P, _I32]),
+    "qk_batch_layout": (_I32, [_P, _I32, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "qk_batch_read_async": (_I32, [_P, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t]),
     "qk_batch_state_ptr": (_I32, [_P, _I32, C.POINTER(_P), C.POINTER(_SZ)]),
     "qk_batch_clear": (_I32, [_P]),
     "qk_batch_num_jobs": (_I32, [_P, _I32P]),
@@ -391,6 +395,20 @@ class Sim:
         self._chk(self.lib.qk_norm2(self.h, C.byref(out)))
         return out.value
 
+    def norm2_async(self, host_ptr: int, capacity: int) -> int:
+        """Enqueue the norm's partial sums and their copy to host memory at
+        host_ptr (capacity doubles); returns their number nb.  After the
+        stream reaches this point, norm2 = sum of the nb real parts in order
+        (``norm2_from_partials``)."""
+        count = C.c_int32()
+        self._chk(self.lib.qk_norm2_async(self.h, C.c_void_p(host_ptr), int(capacity), C.byref(count)))
+        return count.value
+
+    def read_cbits_async(self, host_ptr: int, n: Optional[int] = None):
+        """Enqueue the copy of the first n cbits (all by default) to host_ptr."""
+        n = self.ncbits if n is None else n
+        self._chk(self.lib.qk_read_cbits_async(self.h, C.c_void_p(host_ptr), int(n)))
+
     # -- execution control
     def set_fusion(self, k: int):
         self._chk(self.lib.qk_set_fusion(self.h, k))
@@ -519,6 +537,25 @@ class Batch:
         self._chk(self.lib.qk_batch_read_cbits(self.h, job, out.ctypes.data_as(_U8P), nc))
         return out[:nc]
 
+    def layout(self, job: int) -> Tuple[int, int, int]:
+        """(state byte offset, state bytes, cbit offset) of a job in the batch's buffers."""
+        so, sb, co = C.c_size_t(), C.c_size_t(), C.c_size_t()
+        self._chk(self.lib.qk_batch_layout(self.h, job, C.byref(so), C.byref(sb), C.byref(co)))
+        return so.value, sb.value, co.value
+
+    def sizes(self) -> Tuple[int, int]:
+        """Total bytes of the batch's states and cbits."""
+        if not self.jobs:
+            return 0, 0
+        so, sb, co = self.layout(len(self.jobs) - 1)
+        return so + sb, co + self.jobs[-1][1]
+
+    def read_async(self, host_states_ptr: int, state_bytes: int, host_cbits_ptr: int, cbit_bytes: int):
+        """Enqueue the copy of every job's final state and cbits into host
+        memory (see qk_batch_read_async); read it after the stream gets there."""
+        self._chk(self.lib.qk_batch_read_async(self.h, C.c_void_p(host_states_ptr), int(state_bytes),
+                                               C.c_void_p(host_cbits_ptr), int(cbit_bytes)))
+
     def clear(self):
         self._chk(self.lib.qk_batch_clear(self.h))
         self.jobs = []
@@ -561,3 +598,12 @@ def plan_fusion(n: int, ops, max_k: int, with_matrices: bool = False):
             off += 2 * d * d
         out.append((qs, gates[b], m))
     return out
+
+
+def norm2_from_partials(parts, nb: int) -> float:
+    """The norm from qk_norm2_async's copy: the nb real parts added in order
+    (the same order, so the same value, as qk_norm2)."""
+    total = 0.0
+    for i in range(nb):
+        total += float(parts[2 * i])
+    return total

@@ -2,11 +2,16 @@
 
 Jobs (a circuit and a dtype) arrive over time.  The loop, run on the host:
 
-* admits arrived jobs in arrival order while their device footprint fits
-  the HBM budget (``footprint``: the state of 2^n x 8 or 16 bytes; on a
-  stream slot also the simulator's fixed buffers and, for circuits with
-  permutation gates, a second state-sized buffer) -- a job that can never fit
-  is refused with an error, never allowed to exhaust device memory;
+* queues each arrived job by its route (a batch pool by dtype and size, or
+  a stream slot of its own; worked out once per job) and admits each queue in
+  arrival order while the head's device footprint fits the HBM budget
+  (``footprint``: the state of 2^n x 8 or 16 bytes; on a stream slot also
+  the simulator's fixed buffers and, for circuits with permutation gates, a
+  second state-sized buffer) -- a job that can never fit is refused with an
+  error, never allowed to exhaust device memory; a head that does not fit
+  yet waits, and other queues may pass it (scanning one arrival-ordered list
+  of every waiting job on each turn of the loop made the closed loop
+  quadratic in the queue length);
 * takes each request as qk_op records prepared before it arrives (the form a
   client would submit), so a job on a stream slot is enqueued with one C call
   (qk_apply_ops) instead of one call per operation;
@@ -23,9 +28,15 @@ Jobs (a circuit and a dtype) arrive over time.  The loop, run on the host:
   autotuner chose for that qubit count and dtype, or with ``stages`` in the
   LDS-tile mode); slots run concurrently, so their sweeps overlap on the
   device;
-* polls completion events and, for each finished job, reads its cbits and a
-  digest (norm; for small jobs the whole state) back to the host, frees its
-  memory and records its latency (arrival -> result on the host).  A
+* polls completion events and, for each finished job, takes its cbits and a
+  digest (norm; for small jobs the whole state) on the host, frees its memory
+  and records its latency (arrival -> result on the host).  A stream-slot job
+  enqueues its digest right after its circuit (qk_norm2_async,
+  qk_read_cbits_async into pinned host memory), and a batch the copy of all
+  its states and cbits right after its launch (qk_batch_read_async), so
+  reading a result never waits on the device: copies enqueued only once a
+  job had finished queued behind other streams' sweeps (about 5 ms per small
+  job).  A
   mid-size batched job's state is read back only when asked for
   (``keep_states``), and so is its norm.
 
@@ -47,7 +58,7 @@ import numpy as np
 
 from . import autotune as _autotune
 from . import batch as _batch
-from .qk import Batch, QKError, Sim
+from .qk import Batch, QKError, Sim, norm2_from_partials
 from .runner import Program
 
 SMALL_MAX = {"c128": 13, "c64": 14}
@@ -173,13 +184,28 @@ class Server:
         arrivals = [a if realtime else 0.0 for a, _, _ in jobs]
         streams = [torch.cuda.Stream() for _ in range(self.slots)]
         free_slots = deque(range(self.slots))
+        # per slot, pinned host memory the job's digest (norm partial sums and
+        # cbits) is copied into right after its circuit, so that a finished
+        # job is read without waiting on the device
+        norm_host = [torch.empty(2048, dtype=torch.float64, pin_memory=True) for _ in range(self.slots)]
+        cbit_host = [torch.empty(256, dtype=torch.uint8, pin_memory=True) for _ in range(self.slots)]
         # batch pools: small jobs ("c128", "c64") and mid-size jobs ("mid-c128", "mid-c64")
         pools = ("c128", "c64", "mid-c128", "mid-c64")
         bstreams = {p: [torch.cuda.Stream(), torch.cuda.Stream()] for p in pools}
         bpool = {p: [Batch(p.split("-")[-1], stream=s) for s in bstreams[p]] for p in pools}
         bfree = {p: deque(range(2)) for p in pools}
-        pending: deque = deque()
-        inflight_stream = []   # (slot, sim, event, job index)
+        # per batch, pinned host memory its results (every state and cbit) are
+        # copied into right after its launch (grown on demand)
+        bhost = {p: [[None, None], [None, None]] for p in pools}
+        # each job's route, worked out once: its queue (a batch pool, or
+        # "stream" for a slot of its own) and its device footprint
+        route = []
+        for j, (_, circ, dt) in enumerate(jobs):
+            batched = res[j].n <= self.mid_max[dt] and recs[j] is not None
+            q = (dt if res[j].n <= self.small_max[dt] else "mid-" + dt) if batched else "stream"
+            route.append((q, footprint(res[j].n, dt, circ, batched=batched)))
+        waiting = {q: deque() for q in pools + ("stream",)}   # arrived, not yet admitted, in arrival order
+        inflight_stream = []   # (slot, sim, event, job index, norm partial sums)
         inflight_batch = []    # (dtype, pool index, event, [(job index, batch job id)])
         used = 0
         nxt = 0
@@ -187,6 +213,8 @@ class Server:
         nbatches = 0
         max_conc = 0
         slept = 0.0            # host time spent waiting (nothing to admit or no room)
+        spent = {"stream_enqueue": 0.0, "batch_enqueue": 0.0, "stream_results": 0.0, "batch_results": 0.0,
+                 "event_query": 0.0, "stream_close": 0.0}
         t0 = time.perf_counter()
 
         def now():
@@ -197,85 +225,102 @@ class Server:
             if progress_every and finished - reported >= progress_every:
                 reported = finished - finished % progress_every
                 print(f"[serve] {finished}/{N} jobs done at {now():.1f} s", file=sys.stderr, flush=True)
+            progress = False
             t = now()
             while nxt < N and arrivals[nxt] <= t:
-                res[nxt].arrival = arrivals[nxt]
-                pending.append(nxt)
+                r = res[nxt]
+                r.arrival = arrivals[nxt]
+                q, fp = route[nxt]
+                if fp > self.budget:
+                    r.path, r.error = "refused", f"state of {r.n} qubits ({fp} B) exceeds the HBM budget"
+                    r.done = now()
+                    finished += 1
+                else:
+                    waiting[q].append(nxt)
                 nxt += 1
+                progress = True
 
             # ---- completions
             still = []
-            for slot, sim, ev, j in inflight_stream:
-                if ev.query():
+            tq = time.perf_counter()
+            for slot, sim, ev, j, nb in inflight_stream:
+                tq2 = time.perf_counter()
+                done = ev.query()
+                spent["event_query"] += time.perf_counter() - tq2
+                if done:
                     r = res[j]
                     try:
-                        r.cbits = sim.read_cbits()
-                        r.norm2 = sim.norm2()
+                        nc = jobs[j][1].n_cbits
+                        if nc <= 256:
+                            r.cbits = cbit_host[slot][:nc].numpy().copy()
+                        else:
+                            r.cbits = sim.read_cbits()
+                        r.norm2 = norm2_from_partials(norm_host[slot].numpy(), nb)
                         if j in self.keep_states:
                             r.state = sim.state()
                     except QKError as e:
                         r.path, r.error = "failed", str(e)
                     r.done = now()
+                    tq2 = time.perf_counter()
                     sim.close()
-                    used -= footprint(r.n, r.dtype, jobs[j][1])
+                    spent["stream_close"] += time.perf_counter() - tq2
+                    used -= route[j][1]
                     free_slots.append(slot)
                     finished += 1
+                    progress = True
                 else:
-                    still.append((slot, sim, ev, j))
+                    still.append((slot, sim, ev, j, nb))
             inflight_stream = still
+            spent["stream_results"] += time.perf_counter() - tq
             still = []
+            tq = time.perf_counter()
             for dt, pi, ev, members in inflight_batch:
                 if ev.query():
                     b = bpool[dt][pi]
+                    hs, hc = bhost[dt][pi]
                     for j, bj in members:
                         r = res[j]
+                        so, sb, co = b.layout(bj)
                         if r.n <= self.small_max[r.dtype] or j in self.keep_states:
-                            r.state = b.state(bj)
+                            r.state = hs[so:so + sb].numpy().view(b.np_dtype).copy()
                             r.norm2 = float(np.vdot(r.state, r.state).real)
-                        r.cbits = b.cbits(bj)
+                        r.cbits = hc[co:co + jobs[j][1].n_cbits].numpy().copy()
                         r.done = now()
-                        used -= footprint(r.n, r.dtype, batched=True)
+                        used -= route[j][1]
                         finished += 1
                     b.clear()
+                    progress = True
                     bfree[dt].append(pi)
                 else:
                     still.append((dt, pi, ev, members))
             inflight_batch = still
+            spent["batch_results"] += time.perf_counter() - tq
 
-            # ---- admission (arrival order; a job that does not fit yet waits, later small ones may pass)
+            # ---- admission: each queue in arrival order; a job whose footprint
+            # does not fit yet waits at the head of its queue (jobs of other
+            # queues may pass it).  Batch pools take every waiting job that
+            # fits when one of their batches is free.
             small: Dict[str, List[int]] = {p: [] for p in pools}
-            keep = deque()
-            while pending:
-                j = pending.popleft()
+            for p in pools:
+                wq = waiting[p]
+                while bfree[p] and wq and used + route[wq[0]][1] <= self.budget:
+                    j = wq.popleft()
+                    small[p].append(j)
+                    used += route[j][1]
+                    res[j].admitted = now()
+            wq = waiting["stream"]
+            while free_slots and wq and used + route[wq[0]][1] <= self.budget:
+                j = wq.popleft()
                 _, circ, dt = jobs[j]
                 r = res[j]
-                small_job = r.n <= self.mid_max[dt] and recs[j] is not None
-                pool = dt if r.n <= self.small_max[dt] else "mid-" + dt
-                fp = footprint(r.n, dt, circ, batched=small_job)
-                if fp > self.budget:
-                    r.path, r.error = "refused", f"state of {r.n} qubits ({fp} B) exceeds the HBM budget"
-                    r.done = now()
-                    finished += 1
-                    continue
-                if used + fp > self.budget:
-                    keep.append(j)
-                    continue
-                if small_job:
-                    if bfree[pool]:
-                        small[pool].append(j)
-                        used += fp
-                        r.admitted = now()
-                    else:
-                        keep.append(j)
-                    continue
-                if not free_slots:
-                    keep.append(j)
-                    continue
+                fp = route[j][1]
                 slot = free_slots.popleft()
                 used += fp
                 r.admitted = now()
                 r.path = "stream"
+                progress = True
                 sim = None
+                tq = time.perf_counter()
                 try:
                     sim = Sim(dt, stream=streams[slot])
                     if self.stages:
@@ -291,10 +336,13 @@ class Server:
                         sim.apply_ops(*recs[j])
                     else:
                         Program(circ).run(sim)
-                    sim.flush()
+                    nb = sim.norm2_async(norm_host[slot].data_ptr(), 2048)
+                    if 0 < circ.n_cbits <= 256:
+                        sim.read_cbits_async(cbit_host[slot].data_ptr(), circ.n_cbits)
                     ev = torch.cuda.Event()
                     ev.record(streams[slot])
-                    inflight_stream.append((slot, sim, ev, j))
+                    inflight_stream.append((slot, sim, ev, j, nb))
+                    spent["stream_enqueue"] += time.perf_counter() - tq
                 except QKError as e:
                     if sim is not None:
                         sim.close()
@@ -303,7 +351,7 @@ class Server:
                     used -= fp
                     free_slots.append(slot)
                     finished += 1
-            pending = keep
+            tq = time.perf_counter()
             for dt in pools:
                 if not small[dt]:
                     continue
@@ -319,20 +367,29 @@ class Server:
                     except (QKError, ValueError) as e:
                         r.path, r.error = "failed", str(e)
                         r.done = now()
-                        used -= footprint(r.n, r.dtype, batched=True)
+                        used -= route[j][1]
                         finished += 1
                 if members:
                     b.run()
+                    nbytes, ncb = b.sizes()
+                    hs, hc = bhost[dt][pi]
+                    if hs is None or hs.numel() < nbytes:
+                        hs = torch.empty(max(nbytes, 1 << 20), dtype=torch.uint8, pin_memory=True)
+                    if hc is None or hc.numel() < max(ncb, 1):
+                        hc = torch.empty(max(ncb, 4096), dtype=torch.uint8, pin_memory=True)
+                    bhost[dt][pi] = [hs, hc]
+                    b.read_async(hs.data_ptr(), hs.numel(), hc.data_ptr(), hc.numel())
                     ev = torch.cuda.Event()
                     ev.record(bstreams[dt][pi])
                     inflight_batch.append((dt, pi, ev, members))
                     nbatches += 1
+                    progress = True
                 else:
                     bfree[dt].append(pi)
+            spent["batch_enqueue"] += time.perf_counter() - tq
             max_conc = max(max_conc, len(inflight_stream))
-            idle = ((finished < N and not pending and (nxt >= N or arrivals[nxt] > now()))
-                    or (finished < N and pending and not (free_slots or any(bfree[d] for d in bfree))))
-            if idle:
+            # nothing arrived, finished or started: wait a little before polling again
+            if not progress and finished < N:
                 ts = time.perf_counter()
                 time.sleep(self.poll_sleep)
                 slept += time.perf_counter() - ts
@@ -350,4 +407,5 @@ class Server:
                            circuits_per_s=len(ok) / span if span > 0 else float("nan"),
                            p50_ms=float(np.percentile(lat, 50)), p99_ms=float(np.percentile(lat, 99)),
                            mean_ms=float(lat.mean()), batches=nbatches, max_concurrent_streams=max_conc,
-                           extra={"host_wait_s": slept, "host_busy_frac": 1.0 - slept / wall if wall > 0 else None})
+                           extra={"host_wait_s": slept, "host_busy_frac": 1.0 - slept / wall if wall > 0 else None,
+                                  "host_s": spent})

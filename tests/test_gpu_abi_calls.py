@@ -289,3 +289,27 @@ def test_apply_ops_stops_at_the_first_bad_record():
     assert np.array_equal(s.state(), t.state())
     s.close()
     t.close()
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_async_norm_and_cbits_equal_the_synchronous_reads(dtype):
+    """qk_norm2_async + the in-order sum of its partials equals qk_norm2
+    exactly, and qk_read_cbits_async equals qk_read_cbits, after a stream
+    synchronisation; nothing else waits."""
+    import torch
+    import paper_1908_07187_amd as qk
+    from paper_1908_07187_amd.qk import norm2_from_partials
+    c = W.c0_random_layers(n=18, layers=6, seed=21, rzz=True)
+    c.ops += [W.add_cbits(3), W.measure(4, cbit=0, u=0.3), W.measure(11, cbit=2, u=0.8)]
+    s = qk.run_circuit(c, dtype=dtype)
+    parts = torch.empty(2048, dtype=torch.float64, pin_memory=True)
+    bits = torch.empty(8, dtype=torch.uint8, pin_memory=True)
+    nb = s.norm2_async(parts.data_ptr(), 2048)
+    s.read_cbits_async(bits.data_ptr(), 3)
+    s.sync()
+    assert 0 < nb <= 1024
+    assert norm2_from_partials(parts.numpy(), nb) == s.norm2()
+    assert list(bits.numpy()[:3]) == list(s.read_cbits())
+    with pytest.raises(qk.QKError):
+        s.norm2_async(parts.data_ptr(), 2 * nb - 1)
+    s.close()

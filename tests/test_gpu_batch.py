@@ -347,3 +347,31 @@ def test_staged_edge_cases():
     with pytest.raises(qk.QKError):
         qk.add_circuit(b, W.Circuit([W.add_qubits(25)]))
     b.close()
+
+
+def test_batch_asynchronous_read_equals_the_synchronous_reads():
+    """qk_batch_read_async copies every job's state and cbits, at the offsets
+    qk_batch_layout gives, equal to qk_batch_get_state / qk_batch_read_cbits;
+    refused before a run and into buffers that are too small."""
+    import torch
+    import paper_1908_07187_amd as qk
+    jobs = _jobs(12, 10, n_range=(3, 12)) + [_staged_job(400, 15, 60)]
+    b = qk.Batch("c128")
+    ids = [qk.add_circuit(b, c) for c in jobs]
+    nbytes, ncb = b.sizes()
+    hs = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    hc = torch.empty(max(ncb, 1), dtype=torch.uint8, pin_memory=True)
+    with pytest.raises(qk.QKError):
+        b.read_async(hs.data_ptr(), nbytes, hc.data_ptr(), hc.numel())
+    b.run()
+    with pytest.raises(qk.QKError):
+        b.read_async(hs.data_ptr(), nbytes - 16, hc.data_ptr(), hc.numel())
+    b.read_async(hs.data_ptr(), nbytes, hc.data_ptr(), hc.numel())
+    b.sync()
+    for c, j in zip(jobs, ids):
+        so, sb, co = b.layout(j)
+        assert sb == (1 << c.n_qubits) * 16
+        got = hs[so:so + sb].numpy().view(np.complex128)
+        assert np.array_equal(got, b.state(j))
+        assert list(hc[co:co + c.n_cbits].numpy()) == list(b.cbits(j))
+    b.close()
