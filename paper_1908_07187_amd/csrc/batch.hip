@@ -367,20 +367,17 @@ __device__ __forceinline__ void run_items(typename EVb<R>::T* st, uint32_t dim, 
             QK_PASS_GATE(BK_U1, u);
           } else {
             // BK_DIAG1 / BK_DIAG2 on qubits a (, b); BK_PHASE: one factor where
-            // every bit of cm is 1.  Factors picked by selects (no indexed array).
-            const int nd = okind == BK_DIAG2 ? 4 : (okind == BK_DIAG1 ? 2 : 1);
-            const R d0r = (R)ldbl(g0, 4), d0i = (R)ldbl(g0, 6);
-            const R d1r = nd > 1 ? (R)ldbl(g0, 8) : (R)0, d1i = nd > 1 ? (R)ldbl(g0, 10) : (R)0;
-            const R d2r = nd > 2 ? (R)ldbl(g0, 12) : (R)0, d2i = nd > 2 ? (R)ldbl(g0, 14) : (R)0;
-            const R d3r = nd > 2 ? (R)ldbl(g0, 16) : (R)0, d3i = nd > 2 ? (R)ldbl(g0, 18) : (R)0;
+            // every bit of cm is 1.  Each amplitude reads its factor k = 2 m1 +
+            // m0 (two doubles at dwords 4 + 4k of the record, in LDS) with one
+            // 16-byte read: choosing among four factors by selects cost about
+            // twelve vector instructions per amplitude.
             const uint32_t s0 = okind == BK_PHASE ? 31u : a, s1 = okind == BK_DIAG2 ? b : 31u;
 #pragma unroll
             for (int r = 0; r < 8; ++r) {
               if (r < G && (idx[r] & cm) == cm) {
-                const bool m0 = (idx[r] >> s0) & 1u, m1 = (idx[r] >> s1) & 1u;
-                const R er = m1 ? (m0 ? d3r : d2r) : (m0 ? d1r : d0r);
-                const R ei = m1 ? (m0 ? d3i : d2i) : (m0 ? d1i : d0i);
-                x[r] = cmul<R>(er, ei, x[r]);
+                const uint32_t k = ((idx[r] >> s0) & 1u) | (((idx[r] >> s1) & 1u) << 1);
+                const typename EVb<double>::T f = *reinterpret_cast<const typename EVb<double>::T*>(g0 + 4 + 4 * k);
+                x[r] = cmul<R>((R)f.x, (R)f.y, x[r]);
               }
             }
           }
@@ -559,7 +556,7 @@ __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_ba
   __shared__ double red[2][kBatchThreads / 64];
   __shared__ double meas[2];
   __shared__ int task[5];
-  __shared__ uint32_t items[2][kItemWords];
+  __shared__ __align__(16) uint32_t items[2][kItemWords];
   const uint32_t tid = threadIdx.x, bd = blockDim.x;
   const int lane = tid & 63, w = tid >> 6;
   unsigned long long idle_since = 0;
@@ -748,7 +745,7 @@ __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_st
   __shared__ uint8_t cb[kMaxJobCbits];
   __shared__ double red[2][kBatchThreads / 64];
   __shared__ double meas[2];
-  __shared__ uint32_t items[2][kItemWords];
+  __shared__ __align__(16) uint32_t items[2][kItemWords];
   const uint32_t tid = threadIdx.x, dim = 1u << n;
   for (int c = tid; c < ncbits && c < kMaxJobCbits; c += blockDim.x) cb[c] = cbits[c];
   const ChunkMap cm = chunk_map<LQ>(opw + (size_t)hrec * kOpWords, hrec, dim, tid);
