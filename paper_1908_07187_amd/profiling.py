@@ -36,7 +36,11 @@ def kernel_source_hash() -> str:
 
 
 def short_name(name: str) -> str:
-    nm = name.split("(")[0]
+    """A kernel's name without its return type and parameter list (the
+    batch kernels live in an anonymous namespace, whose '(anonymous
+    namespace)::' prefix is dropped first)."""
+    nm = name.replace("(anonymous namespace)::", "")
+    nm = nm.split("(")[0]
     return nm[5:] if nm.startswith("void ") else nm
 
 
