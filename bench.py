@@ -64,7 +64,7 @@ def parse():
     ap.add_argument("--serve-rates", default="0.8", help="offered load as fractions of the closed-loop capacity")
     ap.add_argument("--serve-mid-max", type=int, default=0,
                     help="batch serving jobs up to this many qubits by stages (0: only jobs that fit LDS)")
-    ap.add_argument("--serve-slots", type=int, default=8, help="serving: stream slots for jobs above the batch size")
+    ap.add_argument("--serve-slots", type=int, default=4, help="serving: stream slots for jobs above the batch size")
     ap.add_argument("--serve-stages", action="store_true",
                     help="serving: run stream-slot jobs in the LDS-tile mode instead of autotuned fusion")
     ap.add_argument("--serve-capacity", type=float, default=0.0,

@@ -120,7 +120,7 @@ def footprint(n: int, dtype: str, circuit=None, batched: bool = False) -> int:
 
 
 class Server:
-    def __init__(self, hbm_budget: Optional[int] = None, slots: int = 8,
+    def __init__(self, hbm_budget: Optional[int] = None, slots: int = 4,
                  fusion: Optional[Dict[str, int]] = None, keep_states: Sequence[int] = (),
                  small_max: Optional[Dict[str, int]] = None, poll_sleep: float = 20e-6,
                  autotuned: bool = False, mid_max: Optional[Dict[str, int]] = None, stages: bool = False):
