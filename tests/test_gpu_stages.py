@@ -117,3 +117,30 @@ def test_stage_mode_small_states_and_toggling():
     qk.Program(W.Circuit(gates[half:])).run(s)
     _check(ref, s.state(), "c128")
     s.close()
+
+
+def test_stage_mode_31_qubits_circuit_then_inverse():
+    """The largest state the mode takes (31 qubits, complex64, 16 GiB): a
+    layered circuit and its inverse return |0...0> (amplitude 0 equal to 1,
+    phase included, within the complex64 rounding of ~2 x 130 gates)."""
+    import torch
+    import paper_1908_07187_amd as qk
+    from workloads.circuits import inverse
+    c = W.c2_random_rzz(n=31, depth=2, seed=5)
+    inv = inverse(c)
+    s = qk.Sim("c64")
+    s.set_tuning("stages", 1)
+    qk.Program(c).run(s)
+    qk.Program(W.Circuit([op for op in inv.ops if op.kind == "gate"])).run(s)
+    s.flush()
+    st = s.stats()
+    ptr, nbytes = s.state_ptr()
+
+    class _View:
+        __cuda_array_interface__ = {"shape": (nbytes // 8,), "typestr": "<c8", "data": (ptr, False), "version": 3}
+    t = torch.as_tensor(_View(), device="cuda")
+    a0 = complex(t[0].item())
+    print(f"[gpu-stages] 31 qubits: amplitude 0 = {a0}, stages {st['sweeps']}", flush=True)
+    assert abs(a0 - 1.0) <= 1e-4
+    assert st["sweeps"] < len(c.gate_ops())
+    s.close()
