@@ -1,5 +1,5 @@
-// Batched execution: many small circuits of uneven qubit counts in one
-// persistent launch.
+// Batched execution: many circuits of uneven qubit counts in one persistent
+// launch, and the stage kernel of the simulator's LDS-tile mode.
 //
 // Each circuit ("job") is compiled on the host into compact device records:
 // builtin gates with their FP64 matrices, controls as a bit mask, up to two
@@ -22,12 +22,19 @@
 // 24) run in the same launch with their state in global memory.  The host
 // splits such a job into stages: runs of gates, reordered only where they
 // commute, whose qubits fit one LDS chunk (12 qubits complex128, 13
-// complex64), and measurements between them.  For a stage the workgroup
-// gathers each chunk (the amplitudes that share the values of the qubits
-// outside the stage) into LDS, runs the stage's items on it exactly as for
-// a small job, and scatters it back, so a stage costs one read and one write
-// of the state whatever its gate count; a measurement runs over the state in
-// global memory.
+// complex64), and measurements between them.  A stage's chunks (the
+// amplitudes that share the values of the qubits outside the stage) are
+// independent, so any free workgroup claims a run of them: it gathers each
+// into LDS, runs the stage's items on it exactly as for a small job, and
+// scatters it back; the workgroup that completes a stage's last chunk opens
+// the next stage.  A stage costs one read and one write of the state
+// whatever its gate count; a measurement runs over the state in global
+// memory on one workgroup.  Workgroups take staged chunks first and small
+// jobs when no chunk is free, and leave once every staged job has finished
+// and the small-job counter has passed the job count.
+//
+// The simulator's LDS-tile mode (k_stage) runs one stage of a single state
+// per launch with the same chunk code.
 //
 // Measurement inside a job uses the same rule as the per-gate path (FP64
 // sums, outcome 0 iff u < P0, renormalise by 1/sqrt(p_outcome)), reduced in a
