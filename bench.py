@@ -415,9 +415,13 @@ def run_fused(qk, prog, torch, args, updates, ref_sim, dtype="c64"):
         ip = ref_sim.inner(s)
         fid = abs(ip) ** 2 / (ref_sim.norm2() * s.norm2())
         s.close()
+        # every sweep (block, diagonal run or lone gate) reads and writes the whole state
+        state_bytes = (1 << n) * (8 if dtype == "c64" else 16)
+        gbps = stats["sweeps"] * 2 * state_bytes / dt / 1e9
         rec = {"config": c, "autotuned": cfg is not None, "ms_per_step": dt * 1e3, "amp_updates_per_s": updates / dt,
                "speedup_vs_c128_per_gate": None, "fidelity_vs_c128": fid,
-               "sweeps": stats["sweeps"], "fused_blocks": stats["fused_blocks"], "fused_gates": stats["fused_gates"]}
+               "sweeps": stats["sweeps"], "fused_blocks": stats["fused_blocks"], "fused_gates": stats["fused_gates"],
+               "hbm_gbps_algorithmic": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS}
         print(f"[bench] {dtype} fused {c}: {dt * 1e3:.1f} ms/step, fidelity {fid:.12f}, sweeps {stats['sweeps']}",
               file=sys.stderr, flush=True)
         if best is None or rec["ms_per_step"] < best["ms_per_step"]:
@@ -469,8 +473,11 @@ def run_stages(qk, prog, torch, updates, ref_sim, dtype):
     s.close()
     print(f"[bench] {dtype} stages: {dt * 1e3:.1f} ms/step, {updates / dt:.4e} amp-updates/s, stages {stats['sweeps']}, "
           f"fidelity {fid:.15f}", file=sys.stderr, flush=True)
+    # a stage reads and writes the whole state once; the stage kernel is bound by vector instructions
+    state_bytes = (1 << prog.circuit.n_qubits) * (8 if dtype == "c64" else 16)
+    gbps = stats["sweeps"] * 2 * state_bytes / dt / 1e9
     return {"ms_per_step": dt * 1e3, "amp_updates_per_s": updates / dt, "stages": stats["sweeps"],
-            "fidelity_vs_c128": fid}
+            "fidelity_vs_c128": fid, "hbm_gbps_algorithmic": gbps, "hbm_frac": gbps / HBM_PEAK_GBPS}
 
 
 def _cpu_model():
