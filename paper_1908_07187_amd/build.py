@@ -30,12 +30,19 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-result",
 ]
 
+# Per-source flags.  batch.hip: the pass interpreter keeps a group's eight
+# amplitudes in a register array indexed by unrolled constants; the AMDGPU
+# promotion of such arrays to one vector register tuple made every
+# conditional update of one amplitude copy the whole tuple (16 64-bit moves
+# per gate), so that promotion is off and the array splits into scalars.
+EXTRA = {"batch.hip": ["-mllvm", "-disable-promote-alloca-to-vector"]}
+
 
 def _compile(src: str, verbose: bool) -> str:
     path = os.path.join(CSRC, src)
     obj = os.path.join(OBJDIR, os.path.splitext(src)[0] + ".o")
     lang = ["-x", "hip"] if src.endswith(".hip") else []
-    cmd = [HIPCC, *FLAGS, *lang, "-c", path, "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), *lang, "-c", path, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

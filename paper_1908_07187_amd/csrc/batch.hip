@@ -4,9 +4,9 @@
 // Each circuit ("job") is compiled on the host into compact device records:
 // builtin gates with their FP64 matrices, controls as a bit mask, up to two
 // classical conditions, measurements with their pre-drawn uniform.  One-qubit,
-// diagonal and phase gates are packed into passes: a pass names up to three
-// target qubits and carries up to eight gates whose dense targets are among
-// them (diagonal and phase gates may act on any qubits).  One persistent grid
+// diagonal and phase gates are packed into passes: a pass names three target
+// qubits and carries up to eight gates whose dense targets are among them
+// (diagonal and phase gates may act on any qubits).  One persistent grid
 // runs all jobs: every workgroup takes the next job from a device counter
 // (largest jobs first), builds |0...0> in LDS and runs the job's items one
 // after another, a barrier after each.  In a pass every thread loads the 8
@@ -76,7 +76,10 @@ struct BJob {
 // header followed by its gate records.  BK_PASS header: head = kind | K << 8 |
 // ngates << 16, cmask = target qubits of slots 0..K-1 (8 bits each), conds =
 // the same qubits in ascending order.  A gate inside a pass names its dense
-// target by slot (head bits 8..15), other qubits by position.
+// target by slot (head bits 8..15), other qubits by position; its cmask
+// keeps only the controls off the pass's targets, and cbit holds the member
+// bits the others need (bits 16..18) and, for a diagonal gate, each
+// member's factor bits from pass targets (2 bits per member, bits 0..15).
 struct BOp {
   uint32_t head;    // kind | t0 << 8 | t1 << 16 | ncond << 24
   uint32_t cmask;   // control mask (BK_PHASE: the all-ones mask of targets and controls)
@@ -87,6 +90,7 @@ struct BOp {
 static_assert(sizeof(BOp) == 80, "op record layout");
 constexpr int kOpWords = (int)(sizeof(BOp) / 4);
 constexpr int kPassGates = 8;                  // gates per pass at most
+constexpr int kPassSlots = 3;                  // target qubits of every pass (8 amplitudes per group)
 constexpr int kItemWords = 3 * 64;             // dwords an item read brings in (>= (1 + kPassGates) * kOpWords)
 static_assert((1 + kPassGates) * kOpWords <= kItemWords, "an item fits one read");
 constexpr int kPadRecords = kItemWords / kOpWords + 1;   // zero records after the last job, so item reads stay in bounds
@@ -189,22 +193,40 @@ __device__ __forceinline__ void bfly(typename EVb<R>::T& p, typename EVb<R>::T& 
   q = r1;
 }
 
-// The pairs of a group that differ in slot `a` (the gate's target), all
-// updated by bfly<R, KIND>.  Expanded in the kernel body on the kernel's own
-// register array with constant indices: passing the array to a function (by
+// The pairs of a group that differ in slot `a` (the gate's target), updated
+// by bfly<R, KIND> when the pair's member number has the bits of rmask set
+// (its controls among the pass's targets: a uniform test) and ACT holds (the
+// lane's controls outside them).  Expanded in the kernel body on the kernel's own register
+// array with constant indices: passing the array to a function (by
 // reference) made the compiler keep part of it in scratch memory.
-#define QK_PASS_GATE(KIND, U)                                                            \
-  do {                                                                                   \
-    if (a == 0) {                                                                        \
-      _Pragma("unroll") for (int r = 0; r < 8; r += 2)                                   \
-        if (r + 1 < G) bfly<R, KIND>(x[r], x[r + 1], (idx[r] & cm) == cm, U);            \
-    } else if (a == 1) {                                                                 \
-      _Pragma("unroll") for (int r = 0; r < 8; ++r)                                      \
-        if (!(r & 2) && r + 2 < G) bfly<R, KIND>(x[r], x[r + 2], (idx[r] & cm) == cm, U); \
-    } else {                                                                             \
-      _Pragma("unroll") for (int r = 0; r < 4; ++r)                                      \
-        if (r + 4 < G) bfly<R, KIND>(x[r], x[r + 4], (idx[r] & cm) == cm, U);            \
-    }                                                                                    \
+#define QK_PASS_GATE(KIND, U, ACT, RMASK)                                               \
+  do {                                                                                  \
+    if (a == 0) {                                                                       \
+      _Pragma("unroll") for (int r = 0; r < 8; r += 2)                                  \
+        if ((r & (RMASK)) == (RMASK)) bfly<R, KIND>(x[r], x[r + 1], ACT, U);              \
+    } else if (a == 1) {                                                                \
+      _Pragma("unroll") for (int r = 0; r < 8; ++r)                                     \
+        if (!(r & 2) && (r & (RMASK)) == (RMASK))                                        \
+          bfly<R, KIND>(x[r], x[r + 2], ACT, U);                                        \
+    } else {                                                                            \
+      _Pragma("unroll") for (int r = 0; r < 4; ++r)                                     \
+        if ((r & (RMASK)) == (RMASK)) bfly<R, KIND>(x[r], x[r + 4], ACT, U);              \
+    }                                                                                   \
+  } while (0)
+
+// A diagonal or phase gate on every member of the group: member r takes
+// factor k = kb | (its bits at the gate's qubits among the pass's targets),
+// a 16-byte read at the lane's record address fb plus a uniform offset.
+#define QK_PASS_DIAG(ACT, RMASK)                                                        \
+  do {                                                                                  \
+    _Pragma("unroll") for (int r = 0; r < 8; ++r) {                                     \
+      if ((r & (RMASK)) == (RMASK)) {                                                  \
+        const uint32_t kr = (aux >> (2 * r)) & 3u;                                     \
+        const typename EVb<double>::T f = *reinterpret_cast<const typename EVb<double>::T*>(fb + 4 * kr); \
+        const C p = cmul<R>((R)f.x, (R)f.y, x[r]);                                      \
+        x[r] = (ACT) ? p : x[r];                                                        \
+      }                                                                                 \
+    }                                                                                   \
   } while (0)
 
 // Waves per SIMD to keep resident: complex128, two 512-thread workgroups per
@@ -220,6 +242,10 @@ template <typename R> constexpr int stage_per_thread() { return (1 << stage_qubi
 // 153 records; two workgroups of 64 + 12 KiB and their static arrays fit a
 // compute unit).
 constexpr uint32_t kStageLdsWords = 3072;
+// The stage kernel's residency: two workgroups per CU (the LDS they hold
+// allows no more), so four waves per SIMD and 128 registers per lane for
+// either amplitude type.
+constexpr int kStageWavesPerSimd = 4;
 static_assert(stage_per_thread<double>() % 8 == 0 && stage_per_thread<float>() % 8 == 0, "chunk moves go 8 at a time");
 static_assert(kBatchThreads == 512, "a staged chunk maps the thread to the stage's lowest 9 qubits");
 
@@ -329,17 +355,17 @@ __device__ __forceinline__ void run_items(typename EVb<R>::T* st, uint32_t dim, 
     ItemRegs nxt{};
     if (!LREC && w == 0) nxt = load_item(opw, next, lane);   // the record array ends with padding
     if (kind == BK_PASS) {
-      const int K = (head >> 8) & 0xff;
+      // every pass has three slots (the host fills them with qubits above
+      // the job's own for jobs of one or two qubits, whose groups then run
+      // into the padding of an LDS state of at least 8 amplitudes), so the
+      // member tests below are compile-time constants
+      constexpr int K = kPassSlots, G = 1 << K;
       const uint32_t tw = __builtin_amdgcn_readfirstlane(cur[1]), sw = __builtin_amdgcn_readfirstlane(cur[2]);
       const uint32_t t0 = tw & 0xff, t1 = (tw >> 8) & 0xff, t2 = (tw >> 16) & 0xff;
       const uint32_t p0 = sw & 0xff, p1 = (sw >> 8) & 0xff, p2 = (sw >> 16) & 0xff;
-      const int G = 1 << K;
-      const uint32_t ngroups = dim >> K;
+      const uint32_t ngroups = dim >= (uint32_t)G ? dim >> K : 1u;
       for (uint32_t g = tid; g < ngroups; g += bd) {
-        uint32_t base = g;
-        if (K > 0) base = ins0(base, p0);
-        if (K > 1) base = ins0(base, p1);
-        if (K > 2) base = ins0(base, p2);
+        const uint32_t base = ins0(ins0(ins0(g, p0), p1), p2);
         uint32_t idx[8];
         C x[8];
 #pragma unroll
@@ -356,37 +382,44 @@ __device__ __forceinline__ void run_items(typename EVb<R>::T* st, uint32_t dim, 
           const uint32_t a = (oh >> 8) & 0xff, b = (oh >> 16) & 0xff;
           if (ncond > 0) {
             const uint32_t cw = __builtin_amdgcn_readfirstlane(g0[2]);
-            if (cb[cw & 0xff] != (uint8_t)((cw >> 8) & 0xff)) continue;
-            if (ncond > 1 && cb[(cw >> 16) & 0xff] != (uint8_t)(cw >> 24)) continue;
+            if ((uint32_t)__builtin_amdgcn_readfirstlane(cb[cw & 0xff]) != ((cw >> 8) & 0xff)) continue;
+            if (ncond > 1 && (uint32_t)__builtin_amdgcn_readfirstlane(cb[(cw >> 16) & 0xff]) != (cw >> 24)) continue;
           }
-          const uint32_t cm = g0[1];
+          // the host split the controls into those on the pass's targets
+          // (rmask: the member bits they need, a uniform test per member)
+          // and the rest (cout: the same for the whole group, one test per
+          // lane); with neither, no tests at all
+          const uint32_t cout = __builtin_amdgcn_readfirstlane(g0[1]);
+          const uint32_t aux = __builtin_amdgcn_readfirstlane(g0[3]);
+          const int rmask = (int)((aux >> 16) & 7u);
+          const bool plain = cout == 0u && rmask == 0;
+          const bool gact = (base & cout) == cout;
           if (okind == BK_X) {
-            QK_PASS_GATE(BK_X, U2<R>{});
+            if (plain) QK_PASS_GATE(BK_X, U2<R>{}, true, 0);
+            else QK_PASS_GATE(BK_X, U2<R>{}, gact, rmask);
           } else if (okind == BK_U1R) {
             U2<R> u{};
 #pragma unroll
             for (int e = 0; e < 8; e += 2) u.v[e] = (R)ldbl(g0, 4 + 2 * e);
-            QK_PASS_GATE(BK_U1R, u);
+            if (plain) QK_PASS_GATE(BK_U1R, u, true, 0);
+            else QK_PASS_GATE(BK_U1R, u, gact, rmask);
           } else if (okind == BK_U1) {
             U2<R> u;
 #pragma unroll
             for (int e = 0; e < 8; ++e) u.v[e] = (R)ldbl(g0, 4 + 2 * e);
-            QK_PASS_GATE(BK_U1, u);
+            if (plain) QK_PASS_GATE(BK_U1, u, true, 0);
+            else QK_PASS_GATE(BK_U1, u, gact, rmask);
           } else {
             // BK_DIAG1 / BK_DIAG2 on qubits a (, b); BK_PHASE: one factor where
-            // every bit of cm is 1.  Each amplitude reads its factor k = 2 m1 +
-            // m0 (two doubles at dwords 4 + 4k of the record, in LDS) with one
-            // 16-byte read: choosing among four factors by selects cost about
-            // twelve vector instructions per amplitude.
+            // every control bit is 1.  Factor k = 2 m1 + m0 (two doubles at
+            // dwords 4 + 4k of the record, in LDS): the bits of the lane's
+            // group base give kb (zero at pass targets), the member's bits
+            // at pass targets the rest (2 bits per member in aux).
             const uint32_t s0 = okind == BK_PHASE ? 31u : a, s1 = okind == BK_DIAG2 ? b : 31u;
-#pragma unroll
-            for (int r = 0; r < 8; ++r) {
-              if (r < G && (idx[r] & cm) == cm) {
-                const uint32_t k = ((idx[r] >> s0) & 1u) | (((idx[r] >> s1) & 1u) << 1);
-                const typename EVb<double>::T f = *reinterpret_cast<const typename EVb<double>::T*>(g0 + 4 + 4 * k);
-                x[r] = cmul<R>((R)f.x, (R)f.y, x[r]);
-              }
-            }
+            const uint32_t kb = ((base >> s0) & 1u) | (((base >> s1) & 1u) << 1);
+            const uint32_t* fb = g0 + 4 + 4 * kb;
+            if (plain) QK_PASS_DIAG(true, 0);
+            else QK_PASS_DIAG(gact, rmask);
           }
         }
 #pragma unroll
@@ -739,11 +772,22 @@ __global__ void k_batch_reset(JobCtl* ctl, int nctl, unsigned* sched, uint8_t* c
   if (i < 4) sched[i] = 0;
 }
 
+// The chunk that the i-th position of the stage kernel's chunk loop takes:
+// i with its low 3 bits rotated to the top.  Workgroups go to the 8 XCDs in
+// turn (workgroup b to XCD b mod 8) and the grid is a multiple of 8, so XCD
+// x takes the chunks [x R, (x + 1) R), R = nchunks / 8, and the workgroups
+// of one XCD hold consecutive chunks at any time: chunks that differ only
+// in the lowest qubits outside the stage share cache lines when the stage
+// leaves out some of qubits 0..2, and then meet in that XCD's L2.
+__device__ __forceinline__ uint32_t xcd_chunk(uint32_t i, uint32_t nchunks) {
+  return nchunks >= 8 ? ((i & 7u) * (nchunks >> 3)) | (i >> 3) : i;
+}
+
 // One stage of a simulator's held-back gates (the LDS-tile mode): every
 // chunk of the state, a chunk per workgroup at a time.  The stage's header
 // is record hrec of opw; the gates' cbit conditions read cbits.
 template <typename R>
-__global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_stage(
+__global__ __launch_bounds__(kBatchThreads, kStageWavesPerSimd) void k_stage(
     typename EVb<R>::T* __restrict__ psi, int n, const uint32_t* __restrict__ opw, uint32_t hrec,
     const uint8_t* __restrict__ cbits, int ncbits) {
   constexpr int LQ = stage_qubits<R>();
@@ -765,25 +809,27 @@ __global__ __launch_bounds__(kBatchThreads, batch_waves_per_simd<R>()) void k_st
     uint32_t* lrec = reinterpret_cast<uint32_t*>(smem_raw + (sizeof(typename EVb<R>::T) << LQ));
     for (uint32_t i = tid; i < nwords; i += blockDim.x) lrec[i] = opw[(size_t)cm.it_begin * kOpWords + i];
     __syncthreads();
-    for (uint32_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x)
-      stage_chunk<R, REC_LDS>(st, psi, cm, ch, false, opw, cb, items, red, meas, lrec);
+    for (uint32_t i = blockIdx.x; i < nchunks; i += gridDim.x)
+      stage_chunk<R, REC_LDS>(st, psi, cm, xcd_chunk(i, nchunks), false, opw, cb, items, red, meas, lrec);
   } else {
-    for (uint32_t ch = blockIdx.x; ch < nchunks; ch += gridDim.x)
-      stage_chunk<R>(st, psi, cm, ch, false, opw, cb, items, red, meas);
+    for (uint32_t i = blockIdx.x; i < nchunks; i += gridDim.x)
+      stage_chunk<R>(st, psi, cm, xcd_chunk(i, nchunks), false, opw, cb, items, red, meas);
   }
 }
 
 // Packs a job's gate records into items: one-qubit, diagonal and phase gates
-// into passes over at most three target qubits (the targets of its one-qubit
-// gates, filled up with the lowest other qubits) and at most kPassGates gates;
-// swaps and measurements stay single records.  Order is kept.
-std::vector<BOp> build_items(int n, const std::vector<BOp>& ops) {
-  const int K = std::min(3, n);
+// into passes over three target qubits (the targets of its one-qubit gates,
+// filled up with the lowest other qubits) and at most kPassGates gates; swaps
+// and measurements stay single records.  Order is kept.
+std::vector<BOp> build_items(const std::vector<BOp>& ops) {
+  const int K = kPassSlots;
   std::vector<BOp> out, cur;
   std::vector<int> T;
   auto close = [&]() {
     if (cur.empty()) return;
-    for (int q = 0; (int)T.size() < K && q < n; ++q)
+    // below three qubits the remaining slots take qubits n, n + 1, ...: no
+    // gate names them, and their amplitudes lie in the LDS state's padding
+    for (int q = 0; (int)T.size() < K; ++q)
       if (std::find(T.begin(), T.end(), q) == T.end()) T.push_back(q);
     std::vector<int> sorted(T);
     std::sort(sorted.begin(), sorted.end());
@@ -794,12 +840,31 @@ std::vector<BOp> build_items(int n, const std::vector<BOp>& ops) {
       h.conds |= (uint32_t)sorted[i] << (8 * i);
     }
     out.push_back(h);
+    auto slot_of = [&](int q) { return (int)(std::find(T.begin(), T.end(), q) - T.begin()); };   // K: none
+    uint32_t smask = 0;
+    for (int i = 0; i < K; ++i) smask |= 1u << T[i];
     for (BOp o : cur) {
-      if (is_one_qubit_dense(o.head & 0xff)) {
-        const int t = (o.head >> 8) & 0xff;
-        const int slot = (int)(std::find(T.begin(), T.end(), t) - T.begin());
+      const int okind = o.head & 0xff;
+      if (is_one_qubit_dense(okind)) {
+        const int slot = slot_of((o.head >> 8) & 0xff);
         o.head = (o.head & ~0xff00u) | ((uint32_t)slot << 8);
       }
+      // a pass member's controls: those on pass targets as the member bits
+      // they need (rmask), the others kept as a mask (cmask); a diagonal or
+      // phase gate also gets, for each member r, its factor bits from pass
+      // targets (2 bits per member), so the kernel does no slot lookups
+      uint32_t rmask = 0, ktab = 0;
+      for (int i = 0; i < K; ++i)
+        if ((o.cmask >> T[i]) & 1u) rmask |= 1u << i;
+      if (okind == BK_DIAG1 || okind == BK_DIAG2) {
+        const int j0 = slot_of((o.head >> 8) & 0xff), j1 = okind == BK_DIAG2 ? slot_of((o.head >> 16) & 0xff) : K;
+        for (int r = 0; r < (1 << K); ++r) {
+          const uint32_t kr = (j0 < K ? (uint32_t)(r >> j0) & 1u : 0u) | (j1 < K ? ((uint32_t)(r >> j1) & 1u) << 1 : 0u);
+          ktab |= kr << (2 * r);
+        }
+      }
+      o.cmask &= ~smask;
+      o.cbit = (int32_t)(ktab | (rmask << 16));
       out.push_back(o);
     }
     cur.clear();
@@ -944,7 +1009,7 @@ std::vector<BOp> plan_stages(int n, int L, const std::vector<BOp>& ops) {
       std::vector<BOp> local;
       local.reserve(members.size());
       for (int i : members) local.push_back(to_local(ops[i0 + i], loc));
-      std::vector<BOp> items = build_items(L, local);
+      std::vector<BOp> items = build_items(local);
       BOp h{};
       h.head = (uint32_t)BK_STAGE | ((uint32_t)L << 8);
       h.cmask = (uint32_t)items.size();
@@ -1184,7 +1249,7 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
   }
   hj.staged = n > max_lds_qubits(b->c64);
   hj.ops = hj.staged ? plan_stages(n, b->c64 ? stage_qubits<float>() : stage_qubits<double>(), hj.ops)
-                     : build_items(n, hj.ops);
+                     : build_items(hj.ops);
   b->jobs.push_back(std::move(hj));
   if (job) *job = (int32_t)b->jobs.size() - 1;
   b->ran = false;
@@ -1305,7 +1370,7 @@ qk_status qk_batch_run(qk_batch b) {
   if (e == hipSuccess && !stab.empty())
     e = hipMemcpyAsync(b->d_stages, stab.data(), stab.size() * sizeof(BStage), hipMemcpyHostToDevice, b->stream);
   if (e != hipSuccess) return bfail(b, QK_E_HIP, std::string("batch upload: ") + hipGetErrorString(e));
-  const size_t shm = ((size_t)1 << nmax) * amp;
+  const size_t shm = ((size_t)1 << std::max(nmax, kPassSlots)) * amp;   // a pass group's 8 amplitudes at least
   int ncu = 256, dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
   const int per_cu = std::max<int>(1, std::min(4, (int)(160 * 1024 / (shm + 4096))));
