@@ -75,7 +75,8 @@ struct BJob {
 // One record, 20 dwords.  An item is one record (swap, measurement) or a pass
 // header followed by its gate records.  BK_PASS header: head = kind | K << 8 |
 // ngates << 16, cmask = target qubits of slots 0..K-1 (8 bits each), conds =
-// the same qubits in ascending order.  A gate inside a pass names its dense
+// the same qubits in ascending order, dwords 4..11 = the LDS byte offset of
+// each of the 8 group members relative to the group base.  A gate inside a pass names its dense
 // target by slot (head bits 8..15), other qubits by position; its cmask
 // keeps only the controls off the pass's targets, and cbit holds the member
 // bits the others need (bits 16..18) and, for a diagonal gate, each
@@ -360,21 +361,22 @@ __device__ __forceinline__ void run_items(typename EVb<R>::T* st, uint32_t dim, 
       // into the padding of an LDS state of at least 8 amplitudes), so the
       // member tests below are compile-time constants
       constexpr int K = kPassSlots, G = 1 << K;
-      const uint32_t tw = __builtin_amdgcn_readfirstlane(cur[1]), sw = __builtin_amdgcn_readfirstlane(cur[2]);
-      const uint32_t t0 = tw & 0xff, t1 = (tw >> 8) & 0xff, t2 = (tw >> 16) & 0xff;
+      const uint32_t sw = __builtin_amdgcn_readfirstlane(cur[2]);
       const uint32_t p0 = sw & 0xff, p1 = (sw >> 8) & 0xff, p2 = (sw >> 16) & 0xff;
+      // member r of a group sits at LDS byte offset swz(base) * sizeof(C) ^
+      // off[r]: the swizzle is linear over XOR and the group base has zeros
+      // at the pass's targets, so the host gives each member's part once
+      uint32_t off[G];
+#pragma unroll
+      for (int r = 0; r < G; ++r) off[r] = __builtin_amdgcn_readfirstlane(cur[4 + r]);
+      unsigned char* const sp = reinterpret_cast<unsigned char*>(st);
       const uint32_t ngroups = dim >= (uint32_t)G ? dim >> K : 1u;
       for (uint32_t g = tid; g < ngroups; g += bd) {
         const uint32_t base = ins0(ins0(ins0(g, p0), p1), p2);
-        uint32_t idx[8];
+        const uint32_t sb = swz<R>(base) * (uint32_t)sizeof(C);
         C x[8];
 #pragma unroll
-        for (int r = 0; r < 8; ++r) {
-          idx[r] = base | ((uint32_t)(r & 1) << t0);
-          if (K > 1) idx[r] |= (uint32_t)((r >> 1) & 1) << t1;
-          if (K > 2) idx[r] |= (uint32_t)((r >> 2) & 1) << t2;
-          if (r < G) x[r] = st[swz<R>(idx[r])];
-        }
+        for (int r = 0; r < 8; ++r) x[r] = *reinterpret_cast<const C*>(sp + (sb ^ off[r]));
         for (int o = 1; o <= ngates; ++o) {
           const uint32_t* g0 = cur + o * kOpWords;
           const uint32_t oh = __builtin_amdgcn_readfirstlane(g0[0]);
@@ -423,8 +425,7 @@ __device__ __forceinline__ void run_items(typename EVb<R>::T* st, uint32_t dim, 
           }
         }
 #pragma unroll
-        for (int r = 0; r < 8; ++r)
-          if (r < G) st[swz<R>(idx[r])] = x[r];
+        for (int r = 0; r < 8; ++r) *reinterpret_cast<C*>(sp + (sb ^ off[r])) = x[r];
       }
     } else if (kind == BK_SWAP) {
       // quarter-space enumeration: bit t0 set, bit t1 clear, exchanged with the mirror
@@ -821,7 +822,13 @@ __global__ __launch_bounds__(kBatchThreads, kStageWavesPerSimd) void k_stage(
 // into passes over three target qubits (the targets of its one-qubit gates,
 // filled up with the lowest other qubits) and at most kPassGates gates; swaps
 // and measurements stay single records.  Order is kept.
-std::vector<BOp> build_items(const std::vector<BOp>& ops) {
+// The LDS swizzle of the pass kernel (swz), for the host.
+uint32_t swz_host(uint32_t i, bool c64) {
+  const uint32_t b = c64 ? 4 : 3, m = (1u << b) - 1;
+  return i ^ ((i >> b) & m);
+}
+
+std::vector<BOp> build_items(const std::vector<BOp>& ops, bool c64) {
   const int K = kPassSlots;
   std::vector<BOp> out, cur;
   std::vector<int> T;
@@ -838,6 +845,13 @@ std::vector<BOp> build_items(const std::vector<BOp>& ops) {
     for (int i = 0; i < K; ++i) {
       h.cmask |= (uint32_t)T[i] << (8 * i);
       h.conds |= (uint32_t)sorted[i] << (8 * i);
+    }
+    // dwords 4..11: member r's LDS byte offset within a group
+    uint32_t* hw = reinterpret_cast<uint32_t*>(h.m);
+    for (int r = 0; r < (1 << K); ++r) {
+      uint32_t rb = 0;
+      for (int i = 0; i < K; ++i) rb |= (uint32_t)((r >> i) & 1) << T[i];
+      hw[r] = swz_host(rb, c64) * (c64 ? 8u : 16u);
     }
     out.push_back(h);
     auto slot_of = [&](int q) { return (int)(std::find(T.begin(), T.end(), q) - T.begin()); };   // K: none
@@ -927,7 +941,7 @@ BOp to_local(BOp o, const std::vector<int>& loc) {
 // stays within L qubits, then takes the lowest unused qubits up to L.  Each
 // stage becomes a BK_STAGE header (record count, the L qubits ascending)
 // followed by its items over local qubits 0..L-1.
-std::vector<BOp> plan_stages(int n, int L, const std::vector<BOp>& ops) {
+std::vector<BOp> plan_stages(int n, int L, const std::vector<BOp>& ops, bool c64) {
   std::vector<BOp> out;
   const int kScan = 8;   // diagonal gates looked at behind the first unscheduled gate of a qubit
   // the first stage writes |0...0> (its chunks start from it instead of
@@ -1009,7 +1023,7 @@ std::vector<BOp> plan_stages(int n, int L, const std::vector<BOp>& ops) {
       std::vector<BOp> local;
       local.reserve(members.size());
       for (int i : members) local.push_back(to_local(ops[i0 + i], loc));
-      std::vector<BOp> items = build_items(local);
+      std::vector<BOp> items = build_items(local, c64);
       BOp h{};
       h.head = (uint32_t)BK_STAGE | ((uint32_t)L << 8);
       h.cmask = (uint32_t)items.size();
@@ -1248,8 +1262,8 @@ qk_status qk_batch_add(qk_batch b, int32_t n, int32_t ncbits, const qk_op* ops, 
     hj.ops.push_back(d);
   }
   hj.staged = n > max_lds_qubits(b->c64);
-  hj.ops = hj.staged ? plan_stages(n, b->c64 ? stage_qubits<float>() : stage_qubits<double>(), hj.ops)
-                     : build_items(hj.ops);
+  hj.ops = hj.staged ? plan_stages(n, b->c64 ? stage_qubits<float>() : stage_qubits<double>(), hj.ops, b->c64)
+                     : build_items(hj.ops, b->c64);
   b->jobs.push_back(std::move(hj));
   if (job) *job = (int32_t)b->jobs.size() - 1;
   b->ran = false;
@@ -1520,7 +1534,7 @@ qk_status stage_plan(bool c64, int n, int ncbits, const std::vector<qk_op>& ops,
     }
     bops.push_back(d);
   }
-  std::vector<BOp> planned = plan_stages(n, stage_chunk_qubits(c64), bops);
+  std::vector<BOp> planned = plan_stages(n, stage_chunk_qubits(c64), bops, c64);
   headers.clear();
   for (uint32_t r = 0; r < (uint32_t)planned.size(); r += 1 + planned[r].cmask) headers.push_back(r);
   planned.resize(planned.size() + kPadRecords);   // the item prefetch reads past a stage's last record
