@@ -34,7 +34,8 @@ FLAGS = [
 # amplitudes in a register array indexed by unrolled constants; the AMDGPU
 # promotion of such arrays to one vector register tuple made every
 # conditional update of one amplitude copy the whole tuple (16 64-bit moves
-# per gate), so that promotion is off and the array splits into scalars.
+# per gate), so that promotion is off there and the array splits into
+# scalars.  (The sweep kernels compiled the same way ran no faster.)
 EXTRA = {"batch.hip": ["-mllvm", "-disable-promote-alloca-to-vector"]}
 
 
