@@ -379,13 +379,13 @@ def batch_record(qk, torch, args):
 def run_fused(qk, prog, torch, args, updates, ref_sim, dtype="c64"):
     """A fused form: blocks of up to k qubits composed in FP64 on the host and
     applied on matrix cores (complex64: FP32 MFMA; complex128: FP64 MFMA),
-    configured by the autotuner's cache for this qubit count and dtype (or every
-    width 4..6 when absent)."""
+    configured by the autotuner's cache for this qubit count and dtype (its
+    fastest fused configuration; every width 4..6 when there is none)."""
     from paper_1908_07187_amd import autotune
     n = prog.circuit.n_qubits
-    cfg = None if args.fusion_k else autotune.lookup(n, dtype)
-    if cfg is not None and cfg.get("fusion", 0):
-        cands = [dict((k, cfg[k]) for k in ("fusion",) + autotune.SHAPE_KEYS if k in cfg)]
+    cfg = None if args.fusion_k else autotune.fused_config(autotune.lookup(n, dtype))
+    if cfg is not None:
+        cands = [dict((k, cfg[k]) for k in ("fusion",) + autotune.SHAPE_KEYS if k in cfg and k != "stages")]
     else:
         cands = [{"fusion": k} for k in ([args.fusion_k] if args.fusion_k else [4, 5, 6])]
     best = None

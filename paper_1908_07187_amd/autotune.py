@@ -7,9 +7,9 @@ first over the fusion width k in {0 (gate by gate), 3, 4, 5, 6} with the
 default tile and the LDS-tile mode (``stages``), then over the tile shape (columns per wave up to the
 widest the block size has, A fragments in registers or LDS, waves per
 compute unit; or, for 4- and 5-qubit blocks, workgroup tiles staged through
-LDS) for the two best widths.  The fastest configuration is stored in a JSON cache keyed by
-device, dtype and qubit count; ``apply`` configures a simulator from it
-(nearest tuned qubit count).
+LDS) for the two best fused widths.  The fastest configuration is stored in a JSON cache keyed by
+device, dtype and qubit count, with the fastest fused one beside it (``fused``) when gate by gate or
+the LDS-tile mode won; ``apply`` configures a simulator from it (nearest tuned qubit count).
 
     python -m paper_1908_07187_amd.autotune --qubits 30 26 22 --dtypes c64 c128
 """
@@ -40,12 +40,26 @@ def max_cols(k: int, dtype: str) -> int:
 
 
 def effective(cfg: Dict, dtype: str) -> Dict:
-    """The configuration as it runs: the tile width capped for the block size."""
+    """The configuration as it runs: the tile width capped for the block size
+    (also in the fastest fused configuration kept beside a non-fused winner)."""
     out = dict(cfg)
     k = out.get("fusion", 0)
     if k and "mfma_cols" in out:
         out["mfma_cols"] = min(out["mfma_cols"], max_cols(k, dtype))
+    if isinstance(out.get("fused"), dict):
+        out["fused"] = effective(out["fused"], dtype)
     return out
+
+
+def fused_config(cfg: Optional[Dict]) -> Optional[Dict]:
+    """The fused configuration of a cache entry: the entry itself when a
+    fused width won, else the fastest fused one kept beside it (or None)."""
+    if cfg is None:
+        return None
+    if cfg.get("fusion", 0):
+        return cfg
+    f = cfg.get("fused")
+    return f if isinstance(f, dict) and f.get("fusion", 0) else None
 
 
 def _device_name() -> str:
@@ -107,10 +121,10 @@ def tune(n: int, dtype: str, layers: int = 3, seed: int = 0, verbose: bool = Tru
             print(f"[autotune] n={n} {dtype} stages: {t * 1e3:.1f} ms", file=sys.stderr, flush=True)
     results.sort(key=lambda r: r[1])
     best_cfg, best_t = results[0]
-    for base, _ in results[:2]:
+    fused = [r for r in results if r[0]["fusion"]]
+    best_fused, best_fused_t = fused[0]
+    for base, _ in fused[:2]:
         k = base["fusion"]
-        if k == 0 or base.get("stages"):
-            continue
         cands = []
         for cols, areg, waves in itertools.product((16, 32, 64), (0, 1), (8, 16)):
             if (areg == 1 and k < 5) or cols > max_cols(k, dtype):
@@ -122,11 +136,15 @@ def tune(n: int, dtype: str, layers: int = 3, seed: int = 0, verbose: bool = Tru
             t = _time_config(qk, prog, n, dtype, cfg)
             if verbose:
                 print(f"[autotune] n={n} {dtype} {cfg}: {t * 1e3:.1f} ms", file=sys.stderr, flush=True)
+            if t < best_fused_t:
+                best_fused, best_fused_t = cfg, t
             if t < best_t:
                 best_cfg, best_t = cfg, t
     out = dict(best_cfg)
     out.update({"ms_per_gate": best_t * 1e3 / ngates, "gates": ngates, "layers": layers,
                 "per_gate_ms_per_gate": per_gate * 1e3 / ngates})
+    if not best_cfg.get("fusion", 0):   # the fastest fused configuration as well, for fused runs
+        out["fused"] = dict(best_fused, ms_per_gate=best_fused_t * 1e3 / ngates)
     return out
 
 

@@ -82,7 +82,7 @@ def _bench_sim(dtype, fused):
     if not fused:
         s.set_tuning("diag_runs", 0)
         return s
-    cfg = autotune.lookup(30, dtype) or {"fusion": 5}
+    cfg = autotune.fused_config(autotune.lookup(30, dtype)) or {"fusion": 5}
     for key in autotune.SHAPE_KEYS:
         if key in cfg and key != "stages":
             s.set_tuning(key, cfg[key])
