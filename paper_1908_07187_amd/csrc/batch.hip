@@ -102,6 +102,8 @@ constexpr int kMaxJobCbits = 256;
 // loops (swap, measurement).
 constexpr int kBU = 2;
 
+typedef uint32_t QkU4 __attribute__((ext_vector_type(4)));
+
 template <typename R> struct EVb;
 template <> struct EVb<float> { typedef float T __attribute__((ext_vector_type(2))); };
 template <> struct EVb<double> { typedef double T __attribute__((ext_vector_type(2))); };
@@ -377,13 +379,27 @@ __device__ __forceinline__ void run_items(typename EVb<R>::T* st, uint32_t dim, 
         C x[8];
 #pragma unroll
         for (int r = 0; r < 8; ++r) x[r] = *reinterpret_cast<const C*>(sp + (sb ^ off[r]));
+        // complex128: a gate's first four dwords (head, cmask, conds, aux)
+        // are read one gate ahead, so their LDS latency overlaps the previous
+        // gate's work (complex64, whose kernel keeps twice the waves within
+        // half the registers, was slower so)
+        constexpr bool kAhead = sizeof(R) == 8;
+        QkU4 hn{};
+        if (kAhead) hn = *reinterpret_cast<const QkU4*>(cur + kOpWords);
         for (int o = 1; o <= ngates; ++o) {
           const uint32_t* g0 = cur + o * kOpWords;
-          const uint32_t oh = __builtin_amdgcn_readfirstlane(g0[0]);
+          QkU4 hc;
+          if (kAhead) {
+            hc = hn;
+            if (o < ngates) hn = *reinterpret_cast<const QkU4*>(g0 + kOpWords);
+          } else {
+            hc = *reinterpret_cast<const QkU4*>(g0);
+          }
+          const uint32_t oh = __builtin_amdgcn_readfirstlane(hc.x);
           const int okind = oh & 0xff, ncond = oh >> 24;
           const uint32_t a = (oh >> 8) & 0xff, b = (oh >> 16) & 0xff;
           if (ncond > 0) {
-            const uint32_t cw = __builtin_amdgcn_readfirstlane(g0[2]);
+            const uint32_t cw = __builtin_amdgcn_readfirstlane(hc.z);
             if ((uint32_t)__builtin_amdgcn_readfirstlane(cb[cw & 0xff]) != ((cw >> 8) & 0xff)) continue;
             if (ncond > 1 && (uint32_t)__builtin_amdgcn_readfirstlane(cb[(cw >> 16) & 0xff]) != (cw >> 24)) continue;
           }
@@ -391,8 +407,8 @@ __device__ __forceinline__ void run_items(typename EVb<R>::T* st, uint32_t dim, 
           // (rmask: the member bits they need, a uniform test per member)
           // and the rest (cout: the same for the whole group, one test per
           // lane); with neither, no tests at all
-          const uint32_t cout = __builtin_amdgcn_readfirstlane(g0[1]);
-          const uint32_t aux = __builtin_amdgcn_readfirstlane(g0[3]);
+          const uint32_t cout = __builtin_amdgcn_readfirstlane(hc.y);
+          const uint32_t aux = __builtin_amdgcn_readfirstlane(hc.w);
           const int rmask = (int)((aux >> 16) & 7u);
           const bool plain = cout == 0u && rmask == 0;
           const bool gact = (base & cout) == cout;

@@ -58,6 +58,47 @@ def test_batch_matches_oracle(dtype):
     b.close()
 
 
+def _tiny_jobs():
+    """Jobs of one to three qubits with every builtin gate kind, controls on
+    and off the pass's targets, classical conditions and measurements: their
+    passes have slots above the job's qubits (LDS padding)."""
+    one = W.Circuit([W.add_qubits(1), W.add_cbits(1)]
+                    + [W.gate(g, [0]) for g in ("H", "S", "T", "X", "Y", "Z", "SDG", "TDG")]
+                    + [W.gate("RX", [0], params=(0.3,)), W.gate("RY", [0], params=(1.1,)),
+                       W.gate("RZ", [0], params=(0.7,)), W.gate("PHASE", [0], params=(0.4,)),
+                       W.measure(0, cbit=0, u=0.37), W.gate("RX", [0], conds=[(0, 1)], params=(0.9,)),
+                       W.gate("RZ", [0], conds=[(0, 0)], params=(1.3,)), W.gate("H", [0])])
+    two = W.Circuit([W.add_qubits(2), W.add_cbits(2), W.gate("H", [0]), W.gate("RY", [1], params=(0.8,)),
+                     W.gate("X", [1], controls=[0]), W.gate("CPHASE", [0, 1], params=(0.9,)),
+                     W.gate("RZZ", [0, 1], params=(0.5,)), W.gate("RZ", [1], controls=[0], params=(1.7,)),
+                     W.gate("H", [0], controls=[1]), W.gate("Y", [1], controls=[0]), W.gate("SWAP", [0, 1]),
+                     W.gate("RX", [0], params=(2.1,)), W.measure(1, cbit=1, u=0.61),
+                     W.gate("PHASE", [0], controls=[1], params=(0.6,)), W.gate("X", [0], conds=[(1, 1)]),
+                     W.gate("RZZ", [0, 1], conds=[(1, 0)], params=(1.9,)), W.gate("T", [1])])
+    three = W.Circuit([W.add_qubits(3), W.gate("H", [0]), W.gate("H", [1]), W.gate("RX", [2], params=(0.4,)),
+                       W.gate("X", [2], controls=[0, 1]), W.gate("RZ", [0], controls=[2], params=(0.3,)),
+                       W.gate("CPHASE", [1, 2], controls=[0], params=(1.2,)),
+                       W.gate("RZZ", [0, 2], controls=[1], params=(0.8,)), W.gate("RY", [1], controls=[2], params=(2.2,))])
+    return [one, two, three]
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_tiny_jobs_every_gate_kind(dtype):
+    import paper_1908_07187_amd as qk
+    jobs = _tiny_jobs()
+    b = qk.Batch(dtype)
+    ids = [qk.add_circuit(b, c) for c in jobs]
+    b.run()
+    b.sync()
+    for c, j in zip(jobs, ids):
+        print(f"[gpu-batch] tiny job n={c.n_qubits} ops={len(c.ops)} dtype={dtype}", flush=True)
+        ref, rcb, recs = oracle.run(c)
+        assert all(abs(r.u - r.P0) > 1e-9 for r in recs)
+        assert list(b.cbits(j)) == list(rcb)
+        _check(ref, b.state(j), dtype, circ=c)
+    b.close()
+
+
 def test_batch_result_independent_of_company():
     """A job's result is bit-identical alone and in a mixed batch (fixed-order reductions)."""
     import paper_1908_07187_amd as qk
