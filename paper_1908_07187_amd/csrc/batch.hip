@@ -5,7 +5,7 @@
 // builtin gates with their FP64 matrices, controls as a bit mask, up to two
 // classical conditions, measurements with their pre-drawn uniform.  One-qubit,
 // diagonal and phase gates are packed into passes: a pass names three target
-// qubits and carries up to eight gates whose dense targets are among them
+// qubits and carries up to eleven gates whose dense targets are among them
 // (diagonal and phase gates may act on any qubits).  One persistent grid
 // runs all jobs: every workgroup takes the next job from a device counter
 // (largest jobs first), builds |0...0> in LDS and runs the job's items one
@@ -90,9 +90,9 @@ struct BOp {
 };
 static_assert(sizeof(BOp) == 80, "op record layout");
 constexpr int kOpWords = (int)(sizeof(BOp) / 4);
-constexpr int kPassGates = 8;                  // gates per pass at most
+constexpr int kPassGates = 11;                 // gates per pass at most
 constexpr int kPassSlots = 3;                  // target qubits of every pass (8 amplitudes per group)
-constexpr int kItemWords = 3 * 64;             // dwords an item read brings in (>= (1 + kPassGates) * kOpWords)
+constexpr int kItemWords = 4 * 64;             // dwords an item read brings in (>= (1 + kPassGates) * kOpWords)
 static_assert((1 + kPassGates) * kOpWords <= kItemWords, "an item fits one read");
 constexpr int kPadRecords = kItemWords / kOpWords + 1;   // zero records after the last job, so item reads stay in bounds
 
@@ -114,27 +114,26 @@ __device__ __forceinline__ double bwave_sum(double v) {
 }
 
 // An item's records (at most kItemWords dwords) are read from global memory
-// one item ahead, lane l of every wave holding dwords l, 64 + l and 128 + l;
+// one item ahead, lane l of every wave holding dwords l, 64 + l, 128 + l and
+// 192 + l;
 // wave 0 copies them into one of two LDS buffers before the barrier that
 // ends the current item, and the next item reads its fields from there as
 // broadcast LDS loads (all lanes read the same address).
 struct ItemRegs {
-  uint32_t w0, w1, w2;
+  uint32_t w[kItemWords / 64];
 };
 
 __device__ __forceinline__ ItemRegs load_item(const uint32_t* __restrict__ opw, uint32_t rec, int lane) {
   const uint32_t* p = opw + (size_t)rec * kOpWords;
   ItemRegs it;
-  it.w0 = p[lane];
-  it.w1 = p[64 + lane];
-  it.w2 = p[128 + lane];
+#pragma unroll
+  for (int j = 0; j < kItemWords / 64; ++j) it.w[j] = p[64 * j + lane];
   return it;
 }
 
 __device__ __forceinline__ void stage_item(uint32_t* buf, const ItemRegs& it, int lane) {
-  buf[lane] = it.w0;
-  buf[64 + lane] = it.w1;
-  buf[128 + lane] = it.w2;
+#pragma unroll
+  for (int j = 0; j < kItemWords / 64; ++j) buf[64 * j + lane] = it.w[j];
 }
 
 __device__ __forceinline__ double ldbl(const uint32_t* buf, int d) {
@@ -837,7 +836,12 @@ __global__ __launch_bounds__(kBatchThreads, kStageWavesPerSimd) void k_stage(
 // Packs a job's gate records into items: one-qubit, diagonal and phase gates
 // into passes over three target qubits (the targets of its one-qubit gates,
 // filled up with the lowest other qubits) and at most kPassGates gates; swaps
-// and measurements stay single records.  Order is kept.
+// and measurements stay single records.  Gates keep their order except where
+// a later gate commutes with the ones it passes.
+uint32_t op_mask(const BOp& o);
+bool op_diag(const BOp& o);
+constexpr int kPassWindow = 64;   // gates a pass looks at past its first
+
 // The LDS swizzle of the pass kernel (swz), for the host.
 uint32_t swz_host(uint32_t i, bool c64) {
   const uint32_t b = c64 ? 4 : 3, m = (1u << b) - 1;
@@ -900,23 +904,51 @@ std::vector<BOp> build_items(const std::vector<BOp>& ops, bool c64) {
     cur.clear();
     T.clear();
   };
-  for (const BOp& o : ops) {
-    const int kind = o.head & 0xff;
-    if (kind == BK_SWAP || kind == BK_MEAS) {
-      close();
-      out.push_back(o);
+  // A pass starts at the first unplaced gate and takes every later gate (up
+  // to kPassWindow looked at) that fits its slots and may move up to it: a
+  // gate passes the skipped ones only where they commute (no shared qubit,
+  // or both diagonal).  Swaps and measurements end the look-ahead.
+  std::vector<char> used(ops.size(), 0);
+  size_t first = 0;
+  while (first < ops.size()) {
+    if (used[first]) {
+      ++first;
       continue;
     }
-    if ((int)cur.size() == kPassGates) close();
-    if (is_one_qubit_dense(kind)) {
-      const int t = (o.head >> 8) & 0xff;
-      const bool in = std::find(T.begin(), T.end(), t) != T.end();
-      if (!in && (int)T.size() == K) close();
-      if (!in) T.push_back(t);
+    const int kind0 = ops[first].head & 0xff;
+    if (kind0 == BK_SWAP || kind0 == BK_MEAS) {
+      out.push_back(ops[first]);
+      used[first++] = 1;
+      continue;
     }
-    cur.push_back(o);
+    uint32_t blocked = 0, blocked_diag = 0;   // qubits of skipped gates (non-diagonal / diagonal)
+    int seen = 0;
+    for (size_t i = first; i < ops.size() && (int)cur.size() < kPassGates && seen < kPassWindow; ++i) {
+      if (used[i]) continue;
+      ++seen;
+      const BOp& o = ops[i];
+      const int kind = o.head & 0xff;
+      if (kind == BK_SWAP || kind == BK_MEAS) break;
+      const uint32_t m = op_mask(o);
+      const bool dg = op_diag(o);
+      bool ok = (m & blocked) == 0 && (dg || (m & blocked_diag) == 0);
+      if (ok && is_one_qubit_dense(kind)) {
+        const int t = (o.head >> 8) & 0xff;
+        const bool in = std::find(T.begin(), T.end(), t) != T.end();
+        if (!in && (int)T.size() == K) ok = false;
+        else if (!in) T.push_back(t);
+      }
+      if (ok) {
+        cur.push_back(o);
+        used[i] = 1;
+      } else if (dg) {
+        blocked_diag |= m;
+      } else {
+        blocked |= m;
+      }
+    }
+    close();
   }
-  close();
   return out;
 }
 
