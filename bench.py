@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--serve-mid-max", type=int, default=0,
                     help="batch serving jobs up to this many qubits by stages (0: only jobs that fit LDS)")
     ap.add_argument("--serve-slots", type=int, default=4, help="serving: stream slots for jobs above the batch size")
+    ap.add_argument("--serve-short-first", type=int, default=0,
+                    help="serving: stream jobs of at most this many qubits are admitted before larger ones (0: arrival order)")
     ap.add_argument("--serve-stages", action="store_true",
                     help="serving: run stream-slot jobs in the LDS-tile mode instead of autotuned fusion")
     ap.add_argument("--serve-capacity", type=float, default=0.0,

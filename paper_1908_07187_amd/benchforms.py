@@ -131,7 +131,8 @@ def serve(args, qk, torch):
     mid = {"c128": args.serve_mid_max, "c64": args.serve_mid_max} if args.serve_mid_max > 0 else None
     warm = W.c4_job_stream(20, seed=args.seed + 1, rate=1.0)
     sg = bool(args.serve_stages)
-    Server(slots=args.serve_slots, autotuned=True, mid_max=mid, stages=sg).serve(warm, realtime=False)
+    Server(slots=args.serve_slots, autotuned=True, mid_max=mid, stages=sg,
+           short_first=args.serve_short_first).serve(warm, realtime=False)
     rep0 = None
     if args.serve_capacity > 0:
         cap = args.serve_capacity
@@ -140,8 +141,8 @@ def serve(args, qk, torch):
         _say(f"serve: closed loop over {nj} jobs")
         jobs = W.c4_job_stream(nj, seed=args.seed, rate=1.0)
         c0 = time.perf_counter_ns()
-        rep0 = Server(slots=args.serve_slots, autotuned=True, mid_max=mid, stages=sg).serve(jobs, realtime=False,
-                                                                                         progress_every=prog)
+        rep0 = Server(slots=args.serve_slots, autotuned=True, mid_max=mid, stages=sg,
+                      short_first=args.serve_short_first).serve(jobs, realtime=False, progress_every=prog)
         spans["closed_loop"] = (c0, time.perf_counter_ns())
         cap = rep0.circuits_per_s
         _say(f"serve closed-loop capacity {cap:.1f} circuits/s, wall {rep0.wall_s:.1f} s")
@@ -153,7 +154,7 @@ def serve(args, qk, torch):
         jobs_p = W.c4_job_stream(nj, seed=args.seed, rate=rate)
         c0 = time.perf_counter_ns()
         rep = Server(slots=args.serve_slots, keep_states=sample if fi == 0 else set(), autotuned=True, mid_max=mid,
-                     stages=sg).serve(
+                     stages=sg, short_first=args.serve_short_first).serve(
             jobs_p, realtime=True, progress_every=prog)
         spans[f"{frac:.2f}"] = (c0, time.perf_counter_ns())
         _say(f"serve at {frac:.2f} x capacity = {rate:.1f}/s: {rep.circuits_per_s:.1f} circuits/s "
@@ -207,6 +208,7 @@ def serve(args, qk, torch):
     out["mid_batched_max_qubits"] = args.serve_mid_max if mid else None
     out["stream_jobs"] = "stages" if sg else "autotuned fusion"
     out["stream_slots"] = args.serve_slots
+    out["stream_short_first_qubits"] = args.serve_short_first
     return out
 
 

@@ -27,7 +27,10 @@ Jobs (a circuit and a dtype) arrive over time.  The loop, run on the host:
   circuit there (fused into matrix-core blocks as configured, or as the
   autotuner chose for that qubit count and dtype, or with ``stages`` in the
   LDS-tile mode); slots run concurrently, so their sweeps overlap on the
-  device;
+  device; with ``short_first`` > 0 a free slot takes the oldest waiting job
+  of at most that many qubits before any larger one (shorter waits for
+  short jobs up to about 0.8 of capacity, a longer tail for long jobs near
+  saturation; off by default);
 * polls completion events and, for each finished job, takes its cbits and a
   digest (norm; for small jobs the whole state) on the host, frees its memory
   and records its latency (arrival -> result on the host).  A stream-slot job
@@ -123,7 +126,8 @@ class Server:
     def __init__(self, hbm_budget: Optional[int] = None, slots: int = 4,
                  fusion: Optional[Dict[str, int]] = None, keep_states: Sequence[int] = (),
                  small_max: Optional[Dict[str, int]] = None, poll_sleep: float = 20e-6,
-                 autotuned: bool = False, mid_max: Optional[Dict[str, int]] = None, stages: bool = False):
+                 autotuned: bool = False, mid_max: Optional[Dict[str, int]] = None, stages: bool = False,
+                 short_first: int = 0):
         import torch
         self.torch = torch
         if hbm_budget is None:
@@ -138,6 +142,9 @@ class Server:
         # stream-slot jobs in the LDS-tile mode (gates grouped into stages, no
         # block matrices to compose) instead of fused blocks
         self.stages = stages
+        # stream-slot jobs of at most this many qubits are admitted before
+        # larger ones (each class in arrival order); 0: one arrival-order queue
+        self.short_first = short_first
         self.poll_sleep = poll_sleep
         # large jobs take the autotuner's fusion width and tile shape for their size
         self.tuning_cache = _autotune.load_cache() if autotuned else None
@@ -202,9 +209,11 @@ class Server:
         route = []
         for j, (_, circ, dt) in enumerate(jobs):
             batched = res[j].n <= self.mid_max[dt] and recs[j] is not None
-            q = (dt if res[j].n <= self.small_max[dt] else "mid-" + dt) if batched else "stream"
+            q = (dt if res[j].n <= self.small_max[dt] else "mid-" + dt) if batched else \
+                ("stream-short" if res[j].n <= self.short_first else "stream")
             route.append((q, footprint(res[j].n, dt, circ, batched=batched)))
-        waiting = {q: deque() for q in pools + ("stream",)}   # arrived, not yet admitted, in arrival order
+        # arrived, not yet admitted, in arrival order
+        waiting = {q: deque() for q in pools + ("stream-short", "stream")}
         inflight_stream = []   # (slot, sim, event, job index, norm partial sums)
         inflight_batch = []    # (dtype, pool index, event, [(job index, batch job id)])
         used = 0
@@ -308,8 +317,16 @@ class Server:
                     small[p].append(j)
                     used += route[j][1]
                     res[j].admitted = now()
-            wq = waiting["stream"]
-            while free_slots and wq and used + route[wq[0]][1] <= self.budget:
+            while free_slots:
+                # the short-job queue first, then the others
+                wq = None
+                for qn in ("stream-short", "stream"):
+                    cand = waiting[qn]
+                    if cand and used + route[cand[0]][1] <= self.budget:
+                        wq = cand
+                        break
+                if wq is None:
+                    break
                 j = wq.popleft()
                 _, circ, dt = jobs[j]
                 r = res[j]

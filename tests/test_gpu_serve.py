@@ -14,11 +14,13 @@ def _stream(count, seed, n_range=(6, 20), depth_range=(4, 14), rate=300.0):
     return W.c4_job_stream(count, seed=seed, rate=rate, n_range=n_range, depth_range=depth_range)
 
 
-def test_results_identical_alone_and_in_the_mix():
+@pytest.mark.parametrize("short_first", [0, 16])
+def test_results_identical_alone_and_in_the_mix(short_first):
+    """Also with short stream jobs admitted before longer ones (short_first)."""
     from paper_1908_07187_amd.serve import Server
     jobs = _stream(24, seed=11)
-    print(f"[gpu-serve] mix of {len(jobs)} jobs", flush=True)
-    rep = Server(keep_states=range(len(jobs)), slots=4).serve(jobs)
+    print(f"[gpu-serve] mix of {len(jobs)} jobs, short_first={short_first}", flush=True)
+    rep = Server(keep_states=range(len(jobs)), slots=4, short_first=short_first).serve(jobs)
     assert rep.completed == len(jobs) and rep.failed == 0 and rep.refused == 0
     assert rep.batches >= 1 and rep.max_concurrent_streams >= 2
     for i, (_, circ, dt) in enumerate(jobs):
