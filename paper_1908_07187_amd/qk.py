@@ -129,6 +129,11 @@ def load(build_if_missing: bool = True):
             raise ImportError(f"{LIB_PATH} is not built")
         from .build import build
         build()
+    # torch first: the library must bind to the HIP runtime torch already
+    # holds (its device memory and streams are passed in).  Loaded before
+    # torch, the library pulled in a second runtime, which then found no
+    # device once torch's had initialised the GPU.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
