@@ -57,7 +57,7 @@ def parse():
     ap.add_argument("--cpu-gates", type=int, default=16, help="gates of the circuit the oracle sample runs")
     ap.add_argument("--workload", default="random30",
                     choices=["random30", "batch12", "batch_mid", "serve", "qft26", "ipe21", "shor", "sample30", "shor39",
-                             "kernels30", "cpu_oracle", "stages30"],
+                             "kernels30", "cpu_oracle", "stages30", "stage_sizes"],
                     help="random30 (default): the 30-qubit depth-40 circuit; the others are the batching, "
                          "serving, QFT, phase-estimation, Shor (dense and sparse) and deferred-measurement forms")
     ap.add_argument("--serve-jobs", type=int, default=400)

@@ -702,6 +702,50 @@ def stages30(args, qk, torch):
     return out
 
 
+def stage_sizes(args, qk, torch):
+    """Stage kernel time against the gates in the stage: one stage of g gates
+    (H and RZ alternating on qubits 0..g-1 mod 12, so every stage covers the
+    same 12 qubits) on a 30-qubit state, g = 1..24, complex128 and complex64;
+    HIP events on the simulator's stream bracket the flush that runs the
+    stage.  Separates the gather/scatter part of a stage from the per-gate
+    part."""
+    n = args.qubits
+    stream = torch.cuda.current_stream()
+    res = {}
+    for dt in ("c128", "c64"):
+        s = qk.Sim(dt)
+        s.set_tuning("stages", 1)
+        s.add_qubits(n)
+        s.sync()
+        rows = []
+        for g in (1, 2, 4, 8, 12, 16, 24):
+            ms = []
+            for rep in range(max(2, args.steps) + 1):
+                for i in range(g):
+                    if i % 2:
+                        s.apply("RZ", [i % 12], params=(0.3,))
+                    else:
+                        s.apply("H", [i % 12])
+                torch.cuda.synchronize()   # the gates stay held back until the flush
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                s.flush()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                if rep:
+                    ms.append(e0.elapsed_time(e1))
+            t = min(ms)
+            gbps = 2 * (1 << n) * (16 if dt == "c128" else 8) / (t * 1e-3) / 1e9
+            rows.append({"gates": g, "ms_per_stage": t, "state_gbps": gbps})
+            _say(f"stage_sizes {dt}: {g} gates {t:.3f} ms per stage ({gbps:.0f} GB/s on the state traffic)")
+        s.close()
+        res[dt] = rows
+    out = _base(args, res["c128"][0]["state_gbps"], "GB/s",
+                {"workload": f"one stage of 1..24 gates on a {n}-qubit state in the LDS-tile mode"}, "f64")
+    out["forms"] = res
+    return out
+
+
 def cpu_oracle(args, qk, torch):
     """The CPU baseline plan: the FP64 oracle (as it stands) on the host's
     cores, single thread and OpenMP over all threads, each case bounded to
@@ -756,5 +800,5 @@ def cpu_oracle(args, qk, torch):
 
 def run(name, args, qk, torch):
     return {"batch12": batch12, "serve": serve, "qft26": qft26, "ipe21": ipe21, "shor": shor,
-            "sample30": sample30, "shor39": shor39, "kernels30": kernels30,
+            "sample30": sample30, "shor39": shor39, "kernels30": kernels30, "stage_sizes": stage_sizes,
             "cpu_oracle": cpu_oracle, "batch_mid": batch_mid, "stages30": stages30}[name](args, qk, torch)
