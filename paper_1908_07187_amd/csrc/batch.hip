@@ -354,8 +354,10 @@ __device__ __forceinline__ void run_items(typename EVb<R>::T* st, uint32_t dim, 
     const int kind = head & 0xff;
     const int ngates = kind == BK_PASS ? (int)((head >> 16) & 0xff) : 0;
     const uint32_t next = rec + 1 + (uint32_t)ngates;
-    ItemRegs nxt{};
-    if (!LREC && w == 0) nxt = load_item(opw, next, lane);   // the record array ends with padding
+    ItemRegs nxt;   // (unused when the records are in LDS: no registers to clear)
+    if constexpr (!LREC) {
+      if (w == 0) nxt = load_item(opw, next, lane);   // the record array ends with padding
+    }
     if (kind == BK_PASS) {
       // every pass has three slots (the host fills them with qubits above
       // the job's own for jobs of one or two qubits, whose groups then run
@@ -481,7 +483,9 @@ __device__ __forceinline__ void run_items(typename EVb<R>::T* st, uint32_t dim, 
     }
     // the next item's records into the other buffer (its last readers
     // finished before the barrier that ended the previous item)
-    if (!LREC && w == 0) stage_item(items[buf ^ 1], nxt, lane);
+    if constexpr (!LREC) {
+      if (w == 0) stage_item(items[buf ^ 1], nxt, lane);
+    }
     __syncthreads();
     buf ^= 1;
     rec = next;
@@ -825,8 +829,43 @@ __global__ __launch_bounds__(kBatchThreads, kStageWavesPerSimd) void k_stage(
     uint32_t* lrec = reinterpret_cast<uint32_t*>(smem_raw + (sizeof(typename EVb<R>::T) << LQ));
     for (uint32_t i = tid; i < nwords; i += blockDim.x) lrec[i] = opw[(size_t)cm.it_begin * kOpWords + i];
     __syncthreads();
-    for (uint32_t i = blockIdx.x; i < nchunks; i += gridDim.x)
-      stage_chunk<R, REC_LDS>(st, psi, cm, xcd_chunk(i, nchunks), false, opw, cb, items, red, meas, lrec);
+    if constexpr (sizeof(R) == 4) {
+      // complex64: the next chunk's amplitudes are loaded into registers
+      // while this chunk's passes run (16 per thread; complex128 has no
+      // registers to spare for its 8)
+      using C = typename EVb<R>::T;
+      constexpr int PT = stage_per_thread<R>();
+      const uint32_t bd = blockDim.x;
+      C pre[PT];
+      uint32_t i = blockIdx.x;
+      if (i < nchunks) {
+        const uint32_t cpart = deposit(xcd_chunk(i, nchunks), cm.cmask);
+#pragma unroll
+        for (int k = 0; k < PT; ++k) pre[k] = psi[cm.base | deposit((uint32_t)k, cm.shigh) | cpart];
+      }
+      for (; i < nchunks; i += gridDim.x) {
+        const uint32_t cpart = deposit(xcd_chunk(i, nchunks), cm.cmask);
+#pragma unroll
+        for (int k = 0; k < PT; ++k) st[swz<R>(tid + (uint32_t)k * bd)] = pre[k];
+        __syncthreads();
+        const uint32_t inext = i + gridDim.x;
+        if (inext < nchunks) {
+          const uint32_t npart = deposit(xcd_chunk(inext, nchunks), cm.cmask);
+#pragma unroll
+          for (int k = 0; k < PT; ++k) pre[k] = psi[cm.base | deposit((uint32_t)k, cm.shigh) | npart];
+        }
+        run_items<R, REC_LDS>(st, 1u << LQ, cm.it_begin, cm.it_end, opw, cb, items, red, meas, lrec, cm.it_begin);
+#pragma unroll 1
+        for (int k0 = 0; k0 < PT; k0 += 8)
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            psi[cm.base | deposit((uint32_t)(k0 + k), cm.shigh) | cpart] = st[swz<R>(tid + (uint32_t)(k0 + k) * bd)];
+        __syncthreads();   // the next chunk's amplitudes overwrite LDS
+      }
+    } else {
+      for (uint32_t i = blockIdx.x; i < nchunks; i += gridDim.x)
+        stage_chunk<R, REC_LDS>(st, psi, cm, xcd_chunk(i, nchunks), false, opw, cb, items, red, meas, lrec);
+    }
   } else {
     for (uint32_t i = blockIdx.x; i < nchunks; i += gridDim.x)
       stage_chunk<R>(st, psi, cm, xcd_chunk(i, nchunks), false, opw, cb, items, red, meas);
