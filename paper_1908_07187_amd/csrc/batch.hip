@@ -76,11 +76,12 @@ struct BJob {
 // header followed by its gate records.  BK_PASS header: head = kind | K << 8 |
 // ngates << 16, cmask = target qubits of slots 0..K-1 (8 bits each), conds =
 // the same qubits in ascending order, dwords 4..11 = the LDS byte offset of
-// each of the 8 group members relative to the group base.  A gate inside a pass names its dense
-// target by slot (head bits 8..15), other qubits by position; its cmask
-// keeps only the controls off the pass's targets, and cbit holds the member
-// bits the others need (bits 16..18) and, for a diagonal gate, each
-// member's factor bits from pass targets (2 bits per member, bits 0..15).
+// each of the 8 group members relative to the group base.  A gate inside a
+// pass names its dense target by slot (head bits 8..15), other qubits by
+// position; its cmask keeps only the controls off the pass's targets, and
+// cbit holds the member bits the others need (bits 16..18) and, for a
+// diagonal gate, each member's factor bits from pass targets (2 bits per
+// member, bits 0..15).
 struct BOp {
   uint32_t head;    // kind | t0 << 8 | t1 << 16 | ncond << 24
   uint32_t cmask;   // control mask (BK_PHASE: the all-ones mask of targets and controls)
@@ -115,10 +116,9 @@ __device__ __forceinline__ double bwave_sum(double v) {
 
 // An item's records (at most kItemWords dwords) are read from global memory
 // one item ahead, lane l of every wave holding dwords l, 64 + l, 128 + l and
-// 192 + l;
-// wave 0 copies them into one of two LDS buffers before the barrier that
-// ends the current item, and the next item reads its fields from there as
-// broadcast LDS loads (all lanes read the same address).
+// 192 + l; wave 0 copies them into one of two LDS buffers before the barrier
+// that ends the current item, and the next item reads its fields from there
+// as broadcast LDS loads (all lanes read the same address).
 struct ItemRegs {
   uint32_t w[kItemWords / 64];
 };
@@ -198,9 +198,10 @@ __device__ __forceinline__ void bfly(typename EVb<R>::T& p, typename EVb<R>::T& 
 // The pairs of a group that differ in slot `a` (the gate's target), updated
 // by bfly<R, KIND> when the pair's member number has the bits of rmask set
 // (its controls among the pass's targets: a uniform test) and ACT holds (the
-// lane's controls outside them).  Expanded in the kernel body on the kernel's own register
-// array with constant indices: passing the array to a function (by
-// reference) made the compiler keep part of it in scratch memory.
+// lane's controls outside them).  Expanded in the kernel body on the
+// kernel's own register array with constant indices: passing the array to a
+// function (by reference) made the compiler keep part of it in scratch
+// memory.
 #define QK_PASS_GATE(KIND, U, ACT, RMASK)                                               \
   do {                                                                                  \
     if (a == 0) {                                                                       \
